@@ -1,0 +1,476 @@
+/*
+ * lgsr_ref.c -- plain FP64 CPU oracle of the spherical surfel range-image renderer.
+ *
+ * TEST INFRASTRUCTURE ONLY (see lgsr_ref.h).  Deliberately simple: every ray is tested
+ * against every surfel, in float64, with no tiles, no culling and no reformulation.
+ * It shares no code with the GPU path.
+ *
+ * Paper: "Real-Time LiDAR Gaussian Splatting SLAM via Geometry-Aware Covariance
+ * Coupling" (arXiv 2607.04127).  Readings taken where the paper is silent:
+ *   R1 primitive: a planar Gaussian with density G = exp(-(u^2 + v^2) / 2), (u, v) the
+ *      ray/plane hit in the primitive's tangent axes measured in units of its two scales
+ *      (2DGS, cited in Sec. 1), cut off at u^2 + v^2 <= k^2 (k = 3).
+ *   R2 intersection: exact ray/plane intersection along each beam direction.
+ *   R3 order: surfels composited front to back by ascending sensor-frame centre range,
+ *      equal ranges by ascending index.
+ *   R4 stabilisers: alpha_hat = min(alpha_max, alpha G); hits with alpha_hat < alpha_thr
+ *      skipped; stop after the hit that takes the transmittance below T_min.
+ *   R5 outputs (Sec. 3.1, Sec. 3.4 "predicted depth, opacity, and normals"): opacity
+ *      A = sum of weights; depth = opacity-normalised expected range; normal = opacity-
+ *      normalised sum of surfel normals turned to face the sensor, sensor frame, not
+ *      renormalised.  Rendered ray drop = [A < drop_tau].  No hit: all zero, drop = 1.
+ *   R6 parameters: s = exp(s~) (Sec. 3.3), alpha = sigmoid(o), q = (w, x, y, z) normalised
+ *      inside, rotation columns (a, b, n) with a the major tangent axis (Sec. 3.5 uses
+ *      a = R(q) e_0).
+ *   R7 pose: T_ws maps sensor to world; the pose gradient is taken in the tangent of the
+ *      right perturbation T_ws * Exp(xi), xi = (rho, omega).
+ *   R8 beams: a pixel is one ray with direction (cos phi cos th, cos phi sin th, sin phi)
+ *      built from the beam tables.
+ */
+#include "lgsr_ref.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+typedef struct {
+    double mu[3], a[3], b[3], n[3]; /* centre and axes in the sensor frame */
+    double nt[3];                   /* normal turned to face the sensor */
+    double sigma;                   /* +1 or -1: nt = sigma * n */
+    double s0, s1, alpha, r;
+    double qhat[4], qnorm;
+    int valid;
+} surf_t;
+
+typedef struct {
+    int64_t i;
+    double t, u, v, G, aG, ahat, T, den, delta[3];
+} hit_t;
+
+typedef struct {
+    double A, SD, SN[3], T, margin, order_gap;
+    int32_t K, n_hits;
+} ray_t;
+
+static double dot3(const double *x, const double *y) { return x[0] * y[0] + x[1] * y[1] + x[2] * y[2]; }
+
+static void cross3(const double *x, const double *y, double *o)
+{
+    o[0] = x[1] * y[2] - x[2] * y[1];
+    o[1] = x[2] * y[0] - x[0] * y[2];
+    o[2] = x[0] * y[1] - x[1] * y[0];
+}
+
+/* Rotation of a unit quaternion (w, x, y, z); columns returned as a, b, n (R6). */
+static void quat_axes(const double *q, double *a, double *b, double *n)
+{
+    double w = q[0], x = q[1], y = q[2], z = q[3];
+    a[0] = 1 - 2 * (y * y + z * z); a[1] = 2 * (x * y + w * z);     a[2] = 2 * (x * z - w * y);
+    b[0] = 2 * (x * y - w * z);     b[1] = 1 - 2 * (x * x + z * z); b[2] = 2 * (y * z + w * x);
+    n[0] = 2 * (x * z + w * y);     n[1] = 2 * (y * z - w * x);     n[2] = 1 - 2 * (x * x + y * y);
+}
+
+/* v_sensor = R_p^T v_world, with pose rows R_p[i][j] = pose[4 i + j]. */
+static void world_to_sensor_dir(const double *pose, const double *v, double *o)
+{
+    for (int j = 0; j < 3; ++j) o[j] = pose[j] * v[0] + pose[4 + j] * v[1] + pose[8 + j] * v[2];
+}
+
+static void sensor_to_world_dir(const double *pose, const double *v, double *o)
+{
+    for (int i = 0; i < 3; ++i) o[i] = pose[4 * i] * v[0] + pose[4 * i + 1] * v[1] + pose[4 * i + 2] * v[2];
+}
+
+/* Per-surfel quantities of the map Theta (Sec. 3.1) under the pose. */
+static void setup_surfels(const lgsr_ref_map *map, const double *pose, const lgsr_ref_params *p, surf_t *S)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < map->n; ++i) {
+        surf_t *s = &S[i];
+        const double *q = map->quats + 4 * i;
+        double qn = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+        s->qnorm = qn;
+        s->valid = 0;
+        if (!(qn > 0)) continue;
+        for (int c = 0; c < 4; ++c) s->qhat[c] = q[c] / qn;
+        double aw[3], bw[3], nw[3], dm[3];
+        quat_axes(s->qhat, aw, bw, nw);
+        for (int c = 0; c < 3; ++c) dm[c] = map->means[3 * i + c] - pose[4 * c + 3];
+        world_to_sensor_dir(pose, dm, s->mu);
+        world_to_sensor_dir(pose, aw, s->a);
+        world_to_sensor_dir(pose, bw, s->b);
+        world_to_sensor_dir(pose, nw, s->n);
+        s->s0 = exp(map->log_scales[2 * i]);
+        s->s1 = exp(map->log_scales[2 * i + 1]);
+        s->alpha = 1.0 / (1.0 + exp(-map->opacity_logits[i]));
+        s->r = sqrt(dot3(s->mu, s->mu));
+        s->sigma = dot3(s->n, s->mu) <= 0 ? 1.0 : -1.0;
+        for (int c = 0; c < 3; ++c) s->nt[c] = s->sigma * s->n[c];
+        s->valid = s->r >= p->near;
+    }
+}
+
+static const surf_t *g_sort_S; /* comparator context (sorting is single threaded) */
+
+static int cmp_range(const void *x, const void *y)
+{
+    int64_t i = *(const int64_t *)x, j = *(const int64_t *)y;
+    double ri = g_sort_S[i].r, rj = g_sort_S[j].r;
+    if (ri < rj) return -1;
+    if (ri > rj) return 1;
+    return (i > j) - (i < j);
+}
+
+/* Valid surfels in compositing order (R3); returns their count. */
+static int64_t sort_surfels(const surf_t *S, int64_t n, int64_t *order)
+{
+    int64_t m = 0;
+    for (int64_t i = 0; i < n; ++i)
+        if (S[i].valid) order[m++] = i;
+    g_sort_S = S;
+    qsort(order, (size_t)m, sizeof(int64_t), cmp_range);
+    return m;
+}
+
+static void ray_dir(const lgsr_ref_beams *B, int64_t rid, double *d)
+{
+    int64_t k = rid / B->W, j = rid % B->W;
+    double sp = B->row_sincos[2 * k], cp = B->row_sincos[2 * k + 1];
+    double st = B->col_sincos[2 * j], ct = B->col_sincos[2 * j + 1];
+    d[0] = cp * ct;
+    d[1] = cp * st;
+    d[2] = sp;
+}
+
+static double rel_gap(double x, double thr) { return fabs(x - thr) / fabs(thr); }
+
+/* Front-to-back compositing of one ray over every surfel (R1-R5).  When hits != NULL the
+ * composited hits are recorded in order (capacity: the number of valid surfels).
+ * margin: the smallest relative gap between a quantity and the threshold it was tested
+ * against (|n'.d| vs den_eps, t vs near, q2 vs k^2, alpha G vs alpha_thr and alpha_max,
+ * transmittance vs T_min); order_gap: the smallest relative gap between the centre ranges
+ * of consecutive composited surfels.  A small value flags a ray whose result may
+ * legitimately differ when computed in lower precision. */
+static void render_ray(const surf_t *S, const int64_t *order, int64_t m, const double *d,
+                       const lgsr_ref_params *p, int want_extra, ray_t *out, hit_t *hits)
+{
+    double T = 1, A = 0, SD = 0, SN[3] = {0, 0, 0}, margin = INFINITY, order_gap = INFINITY;
+    int32_t K = 0, nh = 0;
+    int stopped = 0;
+    double k2 = p->cutoff_sigma * p->cutoff_sigma, prev_r = -1;
+    for (int64_t oi = 0; oi < m; ++oi) {
+        const surf_t *s = &S[order[oi]];
+        double den = dot3(s->n, d);
+        if (want_extra && !stopped) margin = fmin(margin, rel_gap(fabs(den), p->den_eps));
+        if (fabs(den) < p->den_eps) continue;
+        double t = dot3(s->n, s->mu) / den;
+        if (want_extra && !stopped) margin = fmin(margin, rel_gap(t, p->near));
+        if (t < p->near) continue;
+        double delta[3];
+        for (int c = 0; c < 3; ++c) delta[c] = t * d[c] - s->mu[c];
+        double u = dot3(s->a, delta) / s->s0;
+        double v = dot3(s->b, delta) / s->s1;
+        double q2 = u * u + v * v;
+        if (want_extra && !stopped) margin = fmin(margin, rel_gap(q2, k2));
+        if (q2 > k2) continue;
+        double G = exp(-0.5 * q2);
+        double aG = s->alpha * G;
+        if (want_extra && !stopped) {
+            margin = fmin(margin, rel_gap(aG, p->alpha_thr));
+            margin = fmin(margin, rel_gap(aG, p->alpha_max));
+        }
+        double ahat = aG < p->alpha_max ? aG : p->alpha_max;
+        if (ahat < p->alpha_thr) continue;
+        nh++;
+        if (stopped) {
+            if (!want_extra) break;
+            continue;
+        }
+        if (hits) {
+            hit_t *h = &hits[K];
+            h->i = order[oi];
+            h->t = t; h->u = u; h->v = v; h->G = G; h->aG = aG; h->ahat = ahat; h->T = T; h->den = den;
+            for (int c = 0; c < 3; ++c) h->delta[c] = delta[c];
+        }
+        if (want_extra && prev_r >= 0) order_gap = fmin(order_gap, rel_gap(s->r, prev_r));
+        prev_r = s->r;
+        double w = T * ahat;
+        A += w;
+        SD += w * t;
+        for (int c = 0; c < 3; ++c) SN[c] += w * s->nt[c];
+        T *= (1 - ahat);
+        K++;
+        if (want_extra) margin = fmin(margin, rel_gap(T, p->T_min));
+        if (T < p->T_min) {
+            stopped = 1;
+            if (!want_extra) break;
+        }
+    }
+    out->A = A; out->SD = SD; out->T = T; out->K = K; out->n_hits = nh; out->margin = margin;
+    out->order_gap = order_gap;
+    for (int c = 0; c < 3; ++c) out->SN[c] = SN[c];
+}
+
+static int check_args(const lgsr_ref_map *map, const double *pose, const lgsr_ref_beams *beams,
+                      const lgsr_ref_params *prm, int64_t n_rays, const int64_t *ray_ids)
+{
+    if (!map || !pose || !beams || !prm || map->n < 0 || n_rays < 0) return -1;
+    if (map->n > 0 && (!map->means || !map->quats || !map->log_scales || !map->opacity_logits)) return -1;
+    if (beams->H <= 0 || beams->W <= 0 || !beams->row_sincos || !beams->col_sincos) return -1;
+    int64_t total = (int64_t)beams->H * beams->W;
+    if (!ray_ids && n_rays != total) return -1;
+    if (ray_ids)
+        for (int64_t i = 0; i < n_rays; ++i)
+            if (ray_ids[i] < 0 || ray_ids[i] >= total) return -1;
+    return 0;
+}
+
+int lgsr_ref_forward(const lgsr_ref_map *map, const double pose[12], const lgsr_ref_beams *beams,
+                     const lgsr_ref_params *prm, int64_t n_rays, const int64_t *ray_ids,
+                     double *depth, double *opacity, double *normal, uint8_t *drop,
+                     double *t_final, int32_t *n_contrib, double *margin, double *order_gap,
+                     int32_t *n_hits)
+{
+    if (check_args(map, pose, beams, prm, n_rays, ray_ids)) return -1;
+    if (n_rays > 0 && (!depth || !opacity || !normal || !drop)) return -1;
+    surf_t *S = (surf_t *)calloc((size_t)(map->n > 0 ? map->n : 1), sizeof(surf_t));
+    int64_t *order = (int64_t *)malloc(sizeof(int64_t) * (size_t)(map->n > 0 ? map->n : 1));
+    if (!S || !order) { free(S); free(order); return -1; }
+    setup_surfels(map, pose, prm, S);
+    int64_t m = sort_surfels(S, map->n, order);
+    int want_extra = (margin != NULL) || (n_hits != NULL) || (order_gap != NULL);
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t i = 0; i < n_rays; ++i) {
+        int64_t rid = ray_ids ? ray_ids[i] : i;
+        double d[3];
+        ray_dir(beams, rid, d);
+        ray_t r;
+        render_ray(S, order, m, d, prm, want_extra, &r, NULL);
+        if (r.K == 0) {
+            depth[i] = 0; opacity[i] = 0;
+            normal[3 * i] = normal[3 * i + 1] = normal[3 * i + 2] = 0;
+            drop[i] = 1;
+        } else {
+            opacity[i] = r.A;
+            depth[i] = r.SD / r.A;
+            for (int c = 0; c < 3; ++c) normal[3 * i + c] = r.SN[c] / r.A;
+            drop[i] = r.A < prm->drop_tau;
+        }
+        if (t_final) t_final[i] = r.T;
+        if (n_contrib) n_contrib[i] = r.K;
+        if (margin) margin[i] = r.margin;
+        if (order_gap) order_gap[i] = r.order_gap;
+        if (n_hits) n_hits[i] = r.n_hits;
+    }
+    free(S);
+    free(order);
+    return 0;
+}
+
+/* Sec. 3.4: masked depth L1 (Eq. 8, left) and G-ICP normal cosine term (Eq. 9, first term),
+ * L = w_depth * L_depth + lambda_n * lambda_ng * mean_{Omega_N}(1 - Nhat^T N / |Nhat|).
+ * Empty masks give a zero term; sign(0) = 0; a zero rendered normal costs 1 with no gradient. */
+int lgsr_ref_loss(int64_t n_rays, const double *depth, const double *opacity, const double *normal,
+                  const double *target_depth, const double *target_normal, const double *ray_weight,
+                  double w_depth, double lambda_n, double lambda_ng, double loss[5],
+                  double *g_depth, double *g_opacity, double *g_normal)
+{
+    if (n_rays < 0 || !loss) return -1;
+    if (n_rays > 0 && (!depth || !opacity || !normal || !target_depth || !target_normal)) return -1;
+    (void)opacity;
+    double cntD = 0, cntN = 0, sumD = 0, sumN = 0;
+    for (int64_t i = 0; i < n_rays; ++i) {
+        double wgt = ray_weight ? ray_weight[i] : 1.0;
+        double mD = (target_depth[i] > 0) ? wgt : 0.0;
+        const double *N = target_normal + 3 * i, *Nh = normal + 3 * i;
+        double mN = (dot3(N, N) > 0) ? mD : 0.0;
+        cntD += mD;
+        cntN += mN;
+        sumD += mD * fabs(depth[i] - target_depth[i]);
+        double nn = sqrt(dot3(Nh, Nh));
+        sumN += mN * (nn > 0 ? 1.0 - dot3(Nh, N) / nn : 1.0);
+    }
+    double termD = cntD > 0 ? w_depth * sumD / cntD : 0.0;
+    double termN = cntN > 0 ? lambda_n * lambda_ng * sumN / cntN : 0.0;
+    loss[0] = termD + termN;
+    loss[1] = termD;
+    loss[2] = termN;
+    loss[3] = cntD;
+    loss[4] = cntN;
+    for (int64_t i = 0; i < n_rays; ++i) {
+        double wgt = ray_weight ? ray_weight[i] : 1.0;
+        double mD = (target_depth[i] > 0) ? wgt : 0.0;
+        const double *N = target_normal + 3 * i, *Nh = normal + 3 * i;
+        double mN = (dot3(N, N) > 0) ? mD : 0.0;
+        double diff = depth[i] - target_depth[i];
+        double sgn = diff > 0 ? 1.0 : (diff < 0 ? -1.0 : 0.0);
+        if (g_depth) g_depth[i] = cntD > 0 ? w_depth * mD * sgn / cntD : 0.0;
+        if (g_opacity) g_opacity[i] = 0.0;
+        if (g_normal) {
+            double nn = sqrt(dot3(Nh, Nh));
+            for (int c = 0; c < 3; ++c) g_normal[3 * i + c] = 0.0;
+            if (nn > 0 && cntN > 0 && mN != 0) {
+                double cosv = dot3(Nh, N) / nn;
+                double f = -lambda_n * lambda_ng * mN / (cntN * nn);
+                for (int c = 0; c < 3; ++c) g_normal[3 * i + c] = f * (N[c] - cosv * Nh[c] / nn);
+            }
+        }
+    }
+    return 0;
+}
+
+/* Per-surfel gradient accumulators in the sensor frame. */
+typedef struct {
+    double mu[3], a[3], b[3], n[3], s0, s1, alpha;
+} sgrad_t;
+
+static void atomic_add(double *x, double v)
+{
+#pragma omp atomic
+    *x += v;
+}
+
+int lgsr_ref_backward(const lgsr_ref_map *map, const double pose[12], const lgsr_ref_beams *beams,
+                      const lgsr_ref_params *prm, int64_t n_rays, const int64_t *ray_ids,
+                      const double *g_depth, const double *g_opacity, const double *g_normal,
+                      double *d_means, double *d_quats, double *d_log_scales,
+                      double *d_opacity_logits, double d_pose[6])
+{
+    if (check_args(map, pose, beams, prm, n_rays, ray_ids)) return -1;
+    if (n_rays > 0 && (!g_depth || !g_opacity || !g_normal)) return -1;
+    if (map->n > 0 && (!d_means || !d_quats || !d_log_scales || !d_opacity_logits)) return -1;
+    if (!d_pose) return -1;
+    int64_t n = map->n;
+    size_t nn = (size_t)(n > 0 ? n : 1);
+    surf_t *S = (surf_t *)calloc(nn, sizeof(surf_t));
+    int64_t *order = (int64_t *)malloc(sizeof(int64_t) * nn);
+    sgrad_t *Gs = (sgrad_t *)calloc(nn, sizeof(sgrad_t));
+    if (!S || !order || !Gs) { free(S); free(order); free(Gs); return -1; }
+    setup_surfels(map, pose, prm, S);
+    int64_t m = sort_surfels(S, n, order);
+
+#pragma omp parallel
+    {
+        hit_t *hits = (hit_t *)malloc(sizeof(hit_t) * (size_t)(m > 0 ? m : 1));
+#pragma omp for schedule(dynamic, 16)
+        for (int64_t i = 0; i < n_rays; ++i) {
+            int64_t rid = ray_ids ? ray_ids[i] : i;
+            double d[3];
+            ray_dir(beams, rid, d);
+            ray_t r;
+            render_ray(S, order, m, d, prm, 0, &r, hits);
+            if (r.K == 0) continue;
+            /* dL = gD dDhat + gA dA + gN.dNhat with Dhat = SD/A, Nhat = SN/A:
+             * dL = (gD/A) dSD + (gN/A).dSN + (gA - (gD Dhat + gN.Nhat)/A) dA. */
+            double A = r.A, Dh = r.SD / A, Nh[3];
+            for (int c = 0; c < 3; ++c) Nh[c] = r.SN[c] / A;
+            const double *gN = g_normal + 3 * i;
+            double gbD = g_depth[i] / A, gbN[3];
+            for (int c = 0; c < 3; ++c) gbN[c] = gN[c] / A;
+            double gbA = g_opacity[i] - (g_depth[i] * Dh + dot3(gN, Nh)) / A;
+            double B = 0; /* sum over later hits of w_i c_i */
+            for (int j = r.K - 1; j >= 0; --j) {
+                const hit_t *h = &hits[j];
+                const surf_t *s = &S[h->i];
+                double cj = gbD * h->t + dot3(gbN, s->nt) + gbA;
+                double w = h->T * h->ahat;
+                /* w_j = T_j ahat_j and every later weight carries the factor (1 - ahat_j) */
+                double d_ahat = h->T * cj - B / (1 - h->ahat);
+                B += w * cj;
+                double d_t = gbD * w, d_nt[3];
+                for (int c = 0; c < 3; ++c) d_nt[c] = gbN[c] * w;
+                double d_alpha = 0, d_G = 0;
+                if (h->aG < prm->alpha_max) { d_alpha = d_ahat * h->G; d_G = d_ahat * s->alpha; }
+                double d_q2 = -0.5 * h->G * d_G;
+                double d_u = 2 * h->u * d_q2, d_v = 2 * h->v * d_q2;
+                /* u = a'.Delta / s0, v = b'.Delta / s1, Delta = t d - mu', t = n'.mu' / n'.d */
+                double gDelta[3], g_mu[3], g_a[3], g_b[3], g_n[3];
+                for (int c = 0; c < 3; ++c) {
+                    gDelta[c] = d_u * s->a[c] / s->s0 + d_v * s->b[c] / s->s1;
+                    g_a[c] = d_u * h->delta[c] / s->s0;
+                    g_b[c] = d_v * h->delta[c] / s->s1;
+                }
+                double g_t = d_t + dot3(gDelta, d);
+                for (int c = 0; c < 3; ++c) {
+                    g_mu[c] = -gDelta[c] + g_t * s->n[c] / h->den;
+                    g_n[c] = -g_t * h->delta[c] / h->den + s->sigma * d_nt[c];
+                }
+                sgrad_t *g = &Gs[h->i];
+                for (int c = 0; c < 3; ++c) {
+                    atomic_add(&g->mu[c], g_mu[c]);
+                    atomic_add(&g->a[c], g_a[c]);
+                    atomic_add(&g->b[c], g_b[c]);
+                    atomic_add(&g->n[c], g_n[c]);
+                }
+                atomic_add(&g->s0, -d_u * h->u / s->s0);
+                atomic_add(&g->s1, -d_v * h->v / s->s1);
+                atomic_add(&g->alpha, d_alpha);
+            }
+        }
+        free(hits);
+    }
+
+    /* Chain rule to the raw parameters and the pose. */
+    double pr[3] = {0, 0, 0}, pw[3] = {0, 0, 0};
+    for (int64_t i = 0; i < n; ++i) {
+        const surf_t *s = &S[i];
+        const sgrad_t *g = &Gs[i];
+        double *dm = d_means + 3 * i, *dq = d_quats + 4 * i, *dl = d_log_scales + 2 * i;
+        if (!s->valid) {
+            dm[0] = dm[1] = dm[2] = 0;
+            dq[0] = dq[1] = dq[2] = dq[3] = 0;
+            dl[0] = dl[1] = 0;
+            d_opacity_logits[i] = 0;
+            continue;
+        }
+        /* mu' = R_p^T (mu - t_p), a' = R_p^T a, ...: world gradient = R_p times sensor gradient */
+        double Ga[3], Gb[3], Gn[3];
+        sensor_to_world_dir(pose, g->mu, dm);
+        sensor_to_world_dir(pose, g->a, Ga);
+        sensor_to_world_dir(pose, g->b, Gb);
+        sensor_to_world_dir(pose, g->n, Gn);
+        /* (a, b, n) = columns of R(qhat): d/dqhat, then project out the radial part of q */
+        double w = s->qhat[0], x = s->qhat[1], y = s->qhat[2], z = s->qhat[3];
+        double dw = Ga[1] * 2 * z - Ga[2] * 2 * y - Gb[0] * 2 * z + Gb[2] * 2 * x + Gn[0] * 2 * y - Gn[1] * 2 * x;
+        double dx = Ga[1] * 2 * y + Ga[2] * 2 * z + Gb[0] * 2 * y - Gb[1] * 4 * x + Gb[2] * 2 * w
+                  + Gn[0] * 2 * z - Gn[1] * 2 * w - Gn[2] * 4 * x;
+        double dy = -Ga[0] * 4 * y + Ga[1] * 2 * x - Ga[2] * 2 * w + Gb[0] * 2 * x + Gb[2] * 2 * z
+                  + Gn[0] * 2 * w + Gn[1] * 2 * z - Gn[2] * 4 * y;
+        double dz = -Ga[0] * 4 * z + Ga[1] * 2 * w + Ga[2] * 2 * x - Gb[0] * 2 * w - Gb[1] * 4 * z
+                  + Gb[2] * 2 * y + Gn[0] * 2 * x + Gn[1] * 2 * y;
+        double dqh[4] = {dw, dx, dy, dz};
+        double radial = dqh[0] * s->qhat[0] + dqh[1] * s->qhat[1] + dqh[2] * s->qhat[2] + dqh[3] * s->qhat[3];
+        for (int c = 0; c < 4; ++c) dq[c] = (dqh[c] - radial * s->qhat[c]) / s->qnorm;
+        dl[0] = s->s0 * g->s0;
+        dl[1] = s->s1 * g->s1;
+        d_opacity_logits[i] = s->alpha * (1 - s->alpha) * g->alpha;
+        /* right perturbation: mu' -> mu' - rho + mu' x omega, a' -> a' + a' x omega, ... */
+        double c1[3], c2[3], c3[3], c4[3];
+        cross3(s->mu, g->mu, c1);
+        cross3(s->a, g->a, c2);
+        cross3(s->b, g->b, c3);
+        cross3(s->n, g->n, c4);
+        for (int c = 0; c < 3; ++c) {
+            pr[c] -= g->mu[c];
+            pw[c] -= c1[c] + c2[c] + c3[c] + c4[c];
+        }
+    }
+    for (int c = 0; c < 3; ++c) { d_pose[c] = pr[c]; d_pose[3 + c] = pw[c]; }
+    free(S);
+    free(order);
+    free(Gs);
+    return 0;
+}
+
+int lgsr_ref_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

@@ -1,0 +1,91 @@
+/*
+ * lgsr_ref.h -- plain FP64 CPU oracle of the spherical surfel range-image renderer.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library defines what the GPU renderer must compute and
+ * is used by the test-suite, the smoke check and the benchmark's CPU-baseline leg.  The
+ * product path never links, loads or calls it, and it shares no code with the GPU path.
+ *
+ * What it follows (arXiv 2607.04127):
+ *   - map representation Theta = {mu, q, s~, alpha} of 2D Gaussian primitives (Sec. 3.1);
+ *   - rendering under the spherical projection into predicted depth, opacity and normals
+ *     on the scan's grid (Sec. 3.1, Sec. 3.4), with the surfel (2D Gaussian) ray
+ *     intersection of the cited 2DGS work;
+ *   - log-scale parameterisation s = exp(s~) (Sec. 3.3, range-adaptive scale init);
+ *   - valid-depth mask M_D = [D > 0], masked depth L1 and the cosine normal loss with
+ *     mask M_N = M_D * [|N| > 0] (Sec. 3.4, Eq. 8 left and Eq. 9 first term);
+ *   - weights lambda_n = 1 and lambda_{n,g} = 0.05 (Sec. 4.1, implementation details).
+ * Readings where the paper is silent (compositing order, stabilisers, beam model, pose
+ * convention) are stated beside each function in lgsr_ref.c.
+ *
+ * All arrays are HOST memory in float64.  Inputs that the GPU receives as float32 are
+ * promoted exactly by the caller.  Functions return 0 on success and -1 on bad arguments.
+ */
+#ifndef LGSR_REF_H
+#define LGSR_REF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+    double cutoff_sigma; /* a hit counts while u^2 + v^2 <= cutoff_sigma^2 */
+    double alpha_thr;    /* a hit with alpha_hat < alpha_thr is skipped */
+    double alpha_max;    /* alpha_hat = min(alpha_max, alpha * G) */
+    double T_min;        /* stop once the transmittance drops below T_min (that hit included) */
+    double near;         /* surfels whose centre is nearer than this are dropped; hits with t < near skipped */
+    double den_eps;      /* |n'.d| < den_eps: ray parallel to the surfel plane, skipped */
+    double drop_tau;     /* rendered ray drop = [A < drop_tau] */
+} lgsr_ref_params;
+
+typedef struct {
+    int64_t n;
+    const double *means;          /* n x 3, world frame */
+    const double *quats;          /* n x 4, (w, x, y, z), any nonzero norm */
+    const double *log_scales;     /* n x 2 */
+    const double *opacity_logits; /* n */
+} lgsr_ref_map;
+
+typedef struct {
+    int32_t H, W;
+    const double *row_sincos; /* H x 2: (sin phi_k, cos phi_k), row 0 = top beam */
+    const double *col_sincos; /* W x 2: (sin th_j, cos th_j) */
+} lgsr_ref_beams;
+
+/* Render n_rays rays (ray_ids[i] = k * W + j, or all H*W rays in order when ray_ids is NULL).
+ * Outputs per ray: depth, opacity, normal (x3, sensor frame), drop; optional (NULL to skip):
+ * t_final (transmittance after the last hit), n_contrib (hits composited), margin (smallest
+ * relative distance of any threshold decision to its threshold, see lgsr_ref.c), order_gap
+ * (smallest relative centre-range gap between consecutive composited surfels), n_hits
+ * (hits passing every test when early termination is ignored). */
+int lgsr_ref_forward(const lgsr_ref_map *map, const double pose[12], const lgsr_ref_beams *beams,
+                     const lgsr_ref_params *prm, int64_t n_rays, const int64_t *ray_ids,
+                     double *depth, double *opacity, double *normal, uint8_t *drop,
+                     double *t_final, int32_t *n_contrib, double *margin, double *order_gap,
+                     int32_t *n_hits);
+
+/* Loss over n_rays rays and its gradient with respect to the rendered depth, opacity and
+ * normal.  ray_weight (NULL = all ones) multiplies the valid masks; it restricts the loss to
+ * a ray subset.  loss[5] = {total, depth term, normal term, |Omega_D|, |Omega_N|}. */
+int lgsr_ref_loss(int64_t n_rays, const double *depth, const double *opacity, const double *normal,
+                  const double *target_depth, const double *target_normal, const double *ray_weight,
+                  double w_depth, double lambda_n, double lambda_ng, double loss[5],
+                  double *g_depth, double *g_opacity, double *g_normal);
+
+/* Backward of lgsr_ref_forward: given dL/d(depth, opacity, normal) per ray, accumulate the
+ * gradient with respect to every surfel parameter (outputs are overwritten) and the pose in
+ * the right-perturbation tangent (rho, omega) of T_ws * Exp(xi). */
+int lgsr_ref_backward(const lgsr_ref_map *map, const double pose[12], const lgsr_ref_beams *beams,
+                      const lgsr_ref_params *prm, int64_t n_rays, const int64_t *ray_ids,
+                      const double *g_depth, const double *g_opacity, const double *g_normal,
+                      double *d_means, double *d_quats, double *d_log_scales,
+                      double *d_opacity_logits, double d_pose[6]);
+
+/* Number of OpenMP threads the oracle runs with. */
+int lgsr_ref_threads(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

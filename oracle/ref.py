@@ -1,0 +1,180 @@
+"""numpy front end of the FP64 oracle library (test infrastructure; see lgsr_ref.h).
+
+Inputs may be float32 or float64; they are promoted exactly to float64.  Threshold
+parameters are rounded to float32 first so that the oracle tests exactly the threshold
+values the float32 renderer receives.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+from . import build as _build
+
+_lib = None
+
+DEFAULT_PARAMS = dict(cutoff_sigma=3.0, alpha_thr=1.0 / 255.0, alpha_max=0.99, T_min=1e-4,
+                      near=0.2, den_eps=1e-6, drop_tau=0.5)
+DEFAULT_WEIGHTS = dict(w_depth=1.0, lambda_n=1.0, lambda_ng=0.05)
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_double) for k in
+                ("cutoff_sigma", "alpha_thr", "alpha_max", "T_min", "near", "den_eps", "drop_tau")]
+
+
+class _Map(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("means", ctypes.c_void_p), ("quats", ctypes.c_void_p),
+                ("log_scales", ctypes.c_void_p), ("opacity_logits", ctypes.c_void_p)]
+
+
+class _Beams(ctypes.Structure):
+    _fields_ = [("H", ctypes.c_int32), ("W", ctypes.c_int32), ("row_sincos", ctypes.c_void_p),
+                ("col_sincos", ctypes.c_void_p)]
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        path = _build.LIB
+        src = os.path.join(_build.HERE, "lgsr_ref.c")
+        if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(src):
+            _build.build()
+        L = ctypes.CDLL(path)
+        vp, i64 = ctypes.c_void_p, ctypes.c_int64
+        L.lgsr_ref_forward.argtypes = [vp, vp, vp, vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.lgsr_ref_forward.restype = ctypes.c_int
+        L.lgsr_ref_loss.argtypes = [i64, vp, vp, vp, vp, vp, vp, ctypes.c_double, ctypes.c_double,
+                                    ctypes.c_double, vp, vp, vp, vp]
+        L.lgsr_ref_loss.restype = ctypes.c_int
+        L.lgsr_ref_backward.argtypes = [vp, vp, vp, vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.lgsr_ref_backward.restype = ctypes.c_int
+        L.lgsr_ref_threads.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def threads() -> int:
+    return int(lib().lgsr_ref_threads())
+
+
+def params(**kw) -> dict:
+    p = dict(DEFAULT_PARAMS)
+    p.update(kw)
+    return {k: float(np.float32(v)) for k, v in p.items()}
+
+
+def _f64(x):
+    return np.ascontiguousarray(np.asarray(x, dtype=np.float64))
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+class _Inputs:
+    """Keeps the float64 copies alive for the duration of a call."""
+
+    def __init__(self, surfels, pose, row_sincos, col_sincos, prm):
+        self.means = _f64(surfels["means"]).reshape(-1, 3)
+        self.quats = _f64(surfels["quats"]).reshape(-1, 4)
+        self.log_scales = _f64(surfels["log_scales"]).reshape(-1, 2)
+        self.logits = _f64(surfels["opacity_logits"]).reshape(-1)
+        n = self.means.shape[0]
+        assert self.quats.shape[0] == n and self.log_scales.shape[0] == n and self.logits.shape[0] == n
+        self.pose = _f64(pose).reshape(12)
+        self.rows = _f64(row_sincos).reshape(-1, 2)
+        self.cols = _f64(col_sincos).reshape(-1, 2)
+        self.H, self.W = self.rows.shape[0], self.cols.shape[0]
+        self.map = _Map(n, _ptr(self.means), _ptr(self.quats), _ptr(self.log_scales), _ptr(self.logits))
+        self.beams = _Beams(self.H, self.W, _ptr(self.rows), _ptr(self.cols))
+        self.prm = _Params(**params(**(prm or {})))
+        self.n = n
+
+
+def _rays(inp, ray_ids):
+    if ray_ids is None:
+        return inp.H * inp.W, None
+    ids = np.ascontiguousarray(np.asarray(ray_ids, dtype=np.int64).reshape(-1))
+    return ids.shape[0], ids
+
+
+def forward(surfels, pose, row_sincos, col_sincos, prm=None, ray_ids=None, extra=False):
+    """Render (all rays, or ``ray_ids`` = k * W + j).  Returns float64 arrays: depth, opacity,
+    normal (n,3), drop (uint8), t_final, K; with ``extra`` also margin, order_gap and n_hits."""
+    inp = _Inputs(surfels, pose, row_sincos, col_sincos, prm)
+    n_rays, ids = _rays(inp, ray_ids)
+    out = dict(depth=np.zeros(n_rays), opacity=np.zeros(n_rays), normal=np.zeros((n_rays, 3)),
+               drop=np.zeros(n_rays, np.uint8), t_final=np.zeros(n_rays), K=np.zeros(n_rays, np.int32))
+    if extra:
+        out["margin"] = np.zeros(n_rays)
+        out["order_gap"] = np.zeros(n_rays)
+        out["n_hits"] = np.zeros(n_rays, np.int32)
+    rc = lib().lgsr_ref_forward(ctypes.byref(inp.map), _ptr(inp.pose), ctypes.byref(inp.beams),
+                                ctypes.byref(inp.prm), n_rays, _ptr(ids), _ptr(out["depth"]),
+                                _ptr(out["opacity"]), _ptr(out["normal"]), _ptr(out["drop"]),
+                                _ptr(out["t_final"]), _ptr(out["K"]), _ptr(out.get("margin")),
+                                _ptr(out.get("order_gap")), _ptr(out.get("n_hits")))
+    if rc != 0:
+        raise ValueError("lgsr_ref_forward rejected its arguments")
+    return out
+
+
+def loss(pred, target_depth, target_normal, weights=None, ray_weight=None):
+    """Loss and its gradient w.r.t. the rendered (depth, opacity, normal).  Returns
+    (loss[5] = total, depth term, normal term, |Omega_D|, |Omega_N|; g_depth, g_opacity, g_normal)."""
+    w = dict(DEFAULT_WEIGHTS)
+    w.update(weights or {})
+    w = {k: float(np.float32(v)) for k, v in w.items()}
+    depth = _f64(pred["depth"]).reshape(-1)
+    n = depth.shape[0]
+    opacity = _f64(pred["opacity"]).reshape(-1)
+    normal = _f64(pred["normal"]).reshape(-1, 3)
+    td = _f64(target_depth).reshape(-1)
+    tn = _f64(target_normal).reshape(-1, 3)
+    rw = None if ray_weight is None else _f64(ray_weight).reshape(-1)
+    out = np.zeros(5)
+    gd, go, gn = np.zeros(n), np.zeros(n), np.zeros((n, 3))
+    rc = lib().lgsr_ref_loss(n, _ptr(depth), _ptr(opacity), _ptr(normal), _ptr(td), _ptr(tn), _ptr(rw),
+                             w["w_depth"], w["lambda_n"], w["lambda_ng"], _ptr(out), _ptr(gd), _ptr(go),
+                             _ptr(gn))
+    if rc != 0:
+        raise ValueError("lgsr_ref_loss rejected its arguments")
+    return out, gd, go, gn
+
+
+def backward(surfels, pose, row_sincos, col_sincos, g_depth, g_opacity, g_normal, prm=None,
+             ray_ids=None):
+    """Gradients of sum(g . rendered) w.r.t. means, quats, log_scales, opacity_logits and the
+    pose tangent (rho, omega) of the right perturbation."""
+    inp = _Inputs(surfels, pose, row_sincos, col_sincos, prm)
+    n_rays, ids = _rays(inp, ray_ids)
+    gd = _f64(g_depth).reshape(-1)
+    go = _f64(g_opacity).reshape(-1)
+    gn = _f64(g_normal).reshape(-1, 3)
+    assert gd.shape[0] == n_rays and go.shape[0] == n_rays and gn.shape[0] == n_rays
+    n = inp.n
+    out = dict(means=np.zeros((n, 3)), quats=np.zeros((n, 4)), log_scales=np.zeros((n, 2)),
+               opacity_logits=np.zeros(n), pose=np.zeros(6))
+    rc = lib().lgsr_ref_backward(ctypes.byref(inp.map), _ptr(inp.pose), ctypes.byref(inp.beams),
+                                 ctypes.byref(inp.prm), n_rays, _ptr(ids), _ptr(gd), _ptr(go), _ptr(gn),
+                                 _ptr(out["means"]), _ptr(out["quats"]), _ptr(out["log_scales"]),
+                                 _ptr(out["opacity_logits"]), _ptr(out["pose"]))
+    if rc != 0:
+        raise ValueError("lgsr_ref_backward rejected its arguments")
+    return out
+
+
+def loss_and_grad(surfels, pose, row_sincos, col_sincos, target_depth, target_normal, prm=None,
+                  weights=None, ray_ids=None, ray_weight=None):
+    """Forward + loss + backward in one call (float64 throughout)."""
+    fw = forward(surfels, pose, row_sincos, col_sincos, prm, ray_ids)
+    td = np.asarray(target_depth).reshape(-1)
+    tn = np.asarray(target_normal).reshape(-1, 3)
+    if ray_ids is not None:
+        td, tn = td[np.asarray(ray_ids)], tn[np.asarray(ray_ids)]
+    L, gd, go, gn = loss(fw, td, tn, weights, ray_weight)
+    g = backward(surfels, pose, row_sincos, col_sincos, gd, go, gn, prm, ray_ids)
+    return L, fw, g
