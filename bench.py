@@ -1,0 +1,208 @@
+"""Benchmark: forward + loss + backward of the spherical surfel renderer on one MI355X.
+
+    python bench.py [--steps K] [--warmup W] [--workload NAME] [--no-cpu]
+
+One step = lgsr_forward (projection, culling, both sorts, compositing) + lgsr_loss +
+lgsr_backward (raster backward, chain rule to every surfel parameter and the pose) over the
+64 x 1024-beam, 300,000-surfel synthetic street-block scene; inputs are resident in HBM
+before the timed region.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "rendered rays/s fwd+bwd @64×1024, 300k surfels; p50/p99 batched render latency"
+
+# Algorithmic float32 operations of the backward raster (FMA = 2): per ray-surfel test
+# (ray direction offsets, plane denominator, two homogeneous tangent coordinates,
+# reciprocal, range, squared radius, Gaussian, opacity clamp and the four threshold tests)
+# and per composited hit (transmittance recovery, dL/dalpha_hat, the clamp, and the
+# gradients w.r.t. the 11 record quantities).
+FLOPS_TEST = 37
+FLOPS_COMPOSITE_BWD = 55
+FLOPS_COMPOSITE_FWD = 13
+# MI355X float32 vector peak without packed (dual) float32 math: 256 CUs x 64 lanes x
+# 2 flops (FMA) x 2.4 GHz.  The published 157.3 TFLOP/s counts packed float32, which this
+# build does not emit.
+PEAK_FP32_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
+PEAK_FP32_PUBLISHED = 157.3
+PEAK_HBM_GBS = 8000.0
+
+
+def _bytes_model(n, P, rays):
+    """Bytes a tile-binned forward + backward must move (record and gradient layouts of
+    this implementation): per surfel the parameters (40 B) read twice, the 64 B record
+    written once, the 48 B record gradient zeroed, added and read, 40 B of parameter
+    gradients written; per (surfel, tile) pair the 8 B pair written by emission, one read +
+    write per sort pass (counted once), the record and id read by both rasters; per ray the
+    beam tables, 21 B of frame output, 32 B per-ray state written and read, 16 B of targets
+    and 20 B of loss gradient written and read."""
+    per_surfel = 40 + 64 + 40 + 3 * 48 + 40
+    per_pair = 8 + 16 + 2 * (64 + 4 + 8)
+    per_ray = 21 + 2 * 32 + 16 + 2 * 20 + 8
+    return n * per_surfel + P * per_pair + rays * per_ray
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="block64x1024_300k")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU oracle sample time")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this build measures one GPU only; run with --gpus 1 (one process)",
+                          "n_gpus": args.gpus}), flush=True)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import scenegen
+    from paper_2607_04127_amd import lgsr
+
+    dev = torch.device("cuda:0")
+    t_gen = time.perf_counter()
+    w = scenegen.make_workload(args.workload)
+    print(f"# workload {args.workload}: N={w['means'].shape[0]} H={w['H']} W={w['W']} "
+          f"(generated in {time.perf_counter() - t_gen:.1f} s)", file=sys.stderr, flush=True)
+    H, W = w["H"], w["W"]
+    rays = H * W
+    n = w["means"].shape[0]
+    S = {k: torch.from_numpy(w[k]).to(dev) for k in ("means", "quats", "log_scales", "opacity_logits")}
+    rows = torch.from_numpy(w["row_sincos"]).to(dev)
+    cols = torch.from_numpy(w["col_sincos"]).to(dev)
+    pose = torch.from_numpy(w["pose"])
+    td = torch.from_numpy(w["target_depth"]).to(dev)
+    tn = torch.from_numpy(w["target_normal"]).to(dev)
+    frame = dict(depth=torch.empty((H, W), device=dev), opacity=torch.empty((H, W), device=dev),
+                 normal=torch.empty((H, W, 3), device=dev), drop=torch.empty((H, W), device=dev, dtype=torch.uint8))
+    fgrad = dict(depth=torch.empty((H, W), device=dev), opacity=torch.empty((H, W), device=dev),
+                 normal=torch.empty((H, W, 3), device=dev))
+    sgrad = dict(means=torch.empty((n, 3), device=dev), quats=torch.empty((n, 4), device=dev),
+                 log_scales=torch.empty((n, 2), device=dev), opacity_logits=torch.empty((n,), device=dev))
+    loss = torch.empty(5, device=dev)
+    gpose = torch.empty(6, device=dev)
+    ctx = lgsr.Context(0)
+
+    def step():
+        _, st = lgsr.lgsr_forward(ctx, S, pose, rows, cols, out=frame)
+        lgsr.lgsr_loss(ctx, frame, td, tn, loss_out=loss, grad_out=fgrad)
+        lgsr.lgsr_backward(ctx, st, fgrad, out=sgrad, grad_pose=gpose)
+        st.free()
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    print(f"# warmup done ({args.warmup} steps)", file=sys.stderr, flush=True)
+
+    lgsr.lgsr_profile(ctx, True)
+    lgsr.lgsr_profile_read(ctx)  # reset
+    step_ms = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        a = time.perf_counter()
+        step()
+        torch.cuda.synchronize()
+        step_ms.append((time.perf_counter() - a) * 1e3)
+    t1 = time.perf_counter()
+    prof = lgsr.lgsr_profile_read(ctx)
+    lgsr.lgsr_profile(ctx, False)
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    value = rays / (ms_per_step / 1e3)
+    print(f"# timed {args.steps} steps: {ms_per_step:.3f} ms/step", file=sys.stderr, flush=True)
+
+    # work counters of one forward (same inputs, deterministic lists)
+    _, st = lgsr.lgsr_forward(ctx, S, pose, rows, cols, out=frame)
+    q = lgsr.lgsr_query(ctx, st)
+    st.free()
+    stages = {k: dict(ms_per_call=(v[0] / v[1] if v[1] else 0.0), calls=v[1]) for k, v in prof.items()}
+    bwd_ms = stages["raster_bwd"]["ms_per_call"]
+    fwd_ms = stages["raster_fwd"]["ms_per_call"]
+    flops_bwd = q["ray_tests"] * FLOPS_TEST + q["composites"] * FLOPS_COMPOSITE_BWD
+    flops_fwd = q["ray_tests"] * FLOPS_TEST + q["composites"] * FLOPS_COMPOSITE_FWD
+    achieved = flops_bwd / (bwd_ms * 1e-3) / 1e12 if bwd_ms > 0 else 0.0
+    bytes_step = _bytes_model(n, q["pairs"], rays)
+    p50 = float(np.percentile(step_ms, 50))
+    p99 = float(np.percentile(step_ms, 99))
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(w, args.cpu_seconds)
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "rays/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded street-block scene, virtual-scan surfels, exact raycast targets)",
+        "config": {"workload": args.workload, "rays": rays, "H": H, "W": W, "surfels": n,
+                   "pairs": q["pairs"], "visible_surfels": q["visible"], "max_tile_list": q["max_list"],
+                   "ray_tests": q["ray_tests"], "composites": q["composites"], "rays_hit": q["rays_hit"],
+                   "loss": "depth L1 + G-ICP normal cosine", "step_latency_ms_p50": round(p50, 4),
+                   "step_latency_ms_p99": round(p99, 4)},
+        "roofline": {"kernel": "raster_bwd", "bound": "alu", "achieved": round(achieved, 3),
+                     "peak": round(PEAK_FP32_TFLOPS, 1), "unit": "TFLOP/s",
+                     "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None,
+                     "flops_per_launch": flops_bwd, "ms_per_launch": round(bwd_ms, 5),
+                     "peak_published_packed": PEAK_FP32_PUBLISHED},
+        "stages_ms": {k: round(v["ms_per_call"], 5) for k, v in stages.items() if v["calls"]},
+        "raster_fwd": {"ms_per_launch": round(fwd_ms, 5), "flops_per_launch": flops_fwd,
+                       "achieved_tflops": round(flops_fwd / (fwd_ms * 1e-3) / 1e12, 3) if fwd_ms > 0 else 0.0},
+        "hbm_model": {"bytes_per_step": bytes_step, "achieved_GBps": round(bytes_step / (ms_per_step * 1e-3) / 1e9, 1),
+                      "frac_of_8TBps": round(bytes_step / (ms_per_step * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+def cpu_baseline(w, target_s):
+    """The FP64 oracle (forward + loss + backward over every surfel per ray) on a seeded
+    ray subset of the same workload, sized to take about target_s seconds."""
+    import numpy as np
+
+    from oracle import ref
+
+    H, W = w["H"], w["W"]
+    rng = np.random.Generator(np.random.PCG64(1234))
+    order = rng.permutation(H * W)
+
+    def run(m):
+        ids = np.sort(order[:m])
+        t = time.perf_counter()
+        ref.loss_and_grad(w, w["pose"], w["row_sincos"], w["col_sincos"], w["target_depth"], w["target_normal"],
+                          ray_ids=ids)
+        return time.perf_counter() - t
+
+    m = 256
+    dt = run(m)
+    m2 = int(min(H * W, max(m, m * target_s / max(dt, 1e-3))))
+    dt2 = run(m2)
+    print(f"# cpu oracle: {m2} rays in {dt2:.1f} s", file=sys.stderr, flush=True)
+    return {"value": round(m2 / dt2, 1), "unit": "rays/s", "cores": ref.threads(), "kind": "oracle",
+            "sample": f"{m2} seeded random rays of the {H}x{W} image against all {w['means'].shape[0]} surfels, "
+                      f"forward + loss + backward in float64 ({dt2:.1f} s)"}
+
+
+if __name__ == "__main__":
+    main()

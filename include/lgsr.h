@@ -1,0 +1,219 @@
+/*
+ * lgsr.h -- C ABI of the MI355X (gfx950) spherical surfel range-image renderer.
+ *
+ * The library renders a map of surface-oriented 2D anisotropic Gaussians (surfels) into
+ * a spinning-LiDAR range image -- per-ray depth, opacity, normal and ray-drop mask -- and
+ * back-propagates a range-image loss to every surfel parameter and to the 6-DoF sensor
+ * pose.  It follows arXiv 2607.04127 ("Real-Time LiDAR Gaussian Splatting SLAM via
+ * Geometry-Aware Covariance Coupling"):
+ *   Sec. 3.1  map Theta = {(mu_i, q_i, s~_i, alpha_i)} rendered under the spherical
+ *             projection pi_s into (D^, A^, N^) on the scan's grid;
+ *   Sec. 3.3  log-scale parameterisation s~ = log s;
+ *   Sec. 3.4  mapping: rasterise, compare with the observations on valid pixels
+ *             M_D = [D > 0] (masked depth L1, Eq. 8 left; G-ICP normal cosine term with
+ *             M_N = M_D [|N| > 0], Eq. 9 first term), optimise Theta;
+ *   Sec. 4.1  loss weights lambda_n = 1, lambda_{n,g} = 0.05.
+ * The primitive is the 2DGS surfel cited in Sec. 1: a planar Gaussian
+ * G = exp(-(u^2 + v^2) / 2) at the exact ray/plane hit (u, v) in units of its two scales,
+ * composited front to back by ascending sensor-frame centre range (ties: lower index),
+ * with alpha_hat = min(alpha_max, alpha G), hits below alpha_thr skipped and traversal
+ * stopped after the hit that takes the transmittance below T_min.  Outputs: opacity
+ * A = sum of weights, depth = opacity-normalised expected range, normal = opacity-
+ * normalised sum of sensor-facing surfel normals (sensor frame), drop = [A < drop_tau];
+ * a ray with no hit renders all zeros and drop = 1.
+ *
+ * Conventions
+ *   - float32 everywhere; sizes int64 / int32.  Pointers are DEVICE pointers unless marked
+ *     HOST.  The caller owns every input and output buffer; the library owns its context
+ *     workspace and the lgsr_state objects it returns.
+ *   - surfel layout (structure of arrays, row-major, contiguous): means n x 3 (world),
+ *     quats n x 4 as (w, x, y, z) of any nonzero norm whose rotation's columns are
+ *     (major tangent a, minor tangent b, normal n), log_scales n x 2, opacity_logits n
+ *     (opacity = sigmoid(logit)).  A surfel with a zero quaternion or whose centre lies
+ *     nearer than `near` renders nothing and gets zero gradient.
+ *   - pose: 3 x 4 row-major [R | t] mapping sensor coordinates to world coordinates.
+ *     Pose gradients are in the tangent (rho, omega) of the right perturbation
+ *     T * Exp(xi): mu' -> mu' - rho + mu' x omega to first order.
+ *   - beams: row_sincos H x 2 holds (sin phi_k, cos phi_k), row 0 the highest beam, rows
+ *     strictly decreasing in elevation within (-90, 90) degrees; col_sincos W x 2 holds
+ *     (sin th_j, cos th_j) with th_j = 2 pi j / W (uniform azimuth, counter-clockwise from
+ *     +x).  Pixel (k, j), ray index k * W + j, is one ray of direction
+ *     (cos phi_k cos th_j, cos phi_k sin th_j, sin phi_k).  The library relies on this
+ *     layout for culling; other tables give undefined images.  1 <= H, W <= 32768.
+ *   - per-ray images are row-major H x W (normals H x W x 3).
+ *   - all calls are asynchronous on the context's HIP stream unless stated; errors are
+ *     status codes (no exception crosses the ABI) with a message from lgsr_last_error.
+ *     Arguments are validated before anything is launched.  A kernel fault surfaces as
+ *     LGSR_EDEVICE at a later synchronising call.
+ *   - one context may be used by one host thread at a time; calls on one context are
+ *     ordered on its stream.
+ */
+#ifndef LGSR_H
+#define LGSR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    LGSR_OK = 0,
+    LGSR_EINVAL = -1,     /* invalid argument (null pointer, size out of range, bad option) */
+    LGSR_ENOMEM = -2,     /* device or pinned-host allocation failed */
+    LGSR_EDEVICE = -3,    /* HIP runtime error: no device, launch failure, earlier kernel fault */
+    LGSR_ECAPACITY = -4,  /* the (surfel, tile) pair list would exceed the configured limit */
+    LGSR_ESTATE = -5,     /* state from another context, or used after its context changed device */
+    LGSR_EINTERNAL = -6
+} lgsr_status;
+
+typedef struct {
+    int64_t n;
+    const float *means;          /* n x 3 */
+    const float *quats;          /* n x 4 */
+    const float *log_scales;     /* n x 2 */
+    const float *opacity_logits; /* n */
+} lgsr_surfels;
+
+typedef struct {
+    int32_t H, W;
+    const float *row_sincos; /* H x 2 */
+    const float *col_sincos; /* W x 2 */
+} lgsr_beams;
+
+typedef struct {
+    float cutoff_sigma; /* hits count while u^2 + v^2 <= cutoff_sigma^2      (default 3)      */
+    float alpha_thr;    /* hits with alpha_hat < alpha_thr are skipped         (default 1/255)  */
+    float alpha_max;    /* alpha_hat = min(alpha_max, alpha G)                 (default 0.99)   */
+    float T_min;        /* stop after the hit taking transmittance below T_min (default 1e-4)   */
+    float near;         /* centres nearer than this are dropped; hits at t < near skipped (0.2) */
+    float den_eps;      /* |n . d| < den_eps: ray parallel to the surfel, skipped (1e-6)        */
+    float drop_tau;     /* rendered drop = [A < drop_tau]                      (default 0.5)    */
+    int32_t flags;      /* reserved, must be 0 */
+} lgsr_raster_opts;
+
+typedef struct {
+    float *depth;   /* H x W   */
+    float *opacity; /* H x W   */
+    float *normal;  /* H x W x 3, sensor frame */
+    uint8_t *drop;  /* H x W   */
+} lgsr_frame;
+
+typedef struct {
+    float w_depth;   /* weight of the masked depth L1 term            (default 1)    */
+    float lambda_n;  /* weight of the normal loss                     (default 1)    */
+    float lambda_ng; /* weight of the G-ICP normal cosine term inside (default 0.05) */
+} lgsr_loss_weights;
+
+typedef struct {
+    float *d_depth;   /* H x W     dL/d depth   */
+    float *d_opacity; /* H x W     dL/d opacity */
+    float *d_normal;  /* H x W x 3 dL/d normal  */
+} lgsr_frame_grad;
+
+typedef struct {
+    float *means;          /* n x 3 */
+    float *quats;          /* n x 4 */
+    float *log_scales;     /* n x 2 */
+    float *opacity_logits; /* n     */
+} lgsr_surfel_grads;
+
+typedef struct lgsr_ctx lgsr_ctx;     /* library-owned, opaque */
+typedef struct lgsr_state lgsr_state; /* library-owned, opaque */
+
+/* Fill *opts / *w with the defaults listed above. */
+void lgsr_default_opts(lgsr_raster_opts *opts);
+void lgsr_default_loss_weights(lgsr_loss_weights *w);
+
+/* Create a context on HIP device `device` issuing all work on `hip_stream` (a hipStream_t;
+ * NULL = the device's null stream).  Allocates a small workspace; later calls grow it.
+ * Errors: EINVAL (out == NULL), EDEVICE (no such device), ENOMEM. */
+lgsr_status lgsr_create(lgsr_ctx **out, int device, void *hip_stream);
+
+/* Wait for the context's stream, then free the context and its workspace.  States created
+ * from it must be freed first.  NULL is a no-op. */
+void lgsr_destroy(lgsr_ctx *ctx);
+
+/* Switch the stream later calls are issued on (NULL = null stream). */
+lgsr_status lgsr_set_stream(lgsr_ctx *ctx, void *hip_stream);
+
+/* Message of the last failed call on ctx; valid until the next call on ctx. */
+const char *lgsr_last_error(const lgsr_ctx *ctx);
+
+/* Render the surfels seen from pose_ws (Sec. 3.1, Sec. 3.4 rasterisation).
+ *   pose_ws: 12 floats, HOST memory when pose_on_device == 0, DEVICE memory otherwise.
+ *   out: caller-owned frame buffers, fully overwritten.
+ *   state: if not NULL, receives a new state holding what lgsr_backward needs (sorted
+ *          (surfel, tile) lists, per-surfel records, per-ray transmittance); it refers to
+ *          the surfel buffers and the beam tables, which must stay unchanged until the
+ *          backward has been issued.  Free it with lgsr_state_free.
+ * The call reads back one integer (the number of (surfel, tile) pairs) to size the pair
+ * list, so it waits for the projection kernels of this call; everything else is async.
+ * Errors: EINVAL, ENOMEM, ECAPACITY (more than 2^31 - 1 pairs), EDEVICE. */
+lgsr_status lgsr_forward(lgsr_ctx *ctx, const lgsr_surfels *surfels, const float *pose_ws,
+                         int32_t pose_on_device, const lgsr_beams *beams,
+                         const lgsr_raster_opts *opts, lgsr_frame *out, lgsr_state **state);
+
+/* Loss of a rendered frame against targets (Sec. 3.4, Eq. 8 left and Eq. 9 first term):
+ *   L = w_depth / |Omega_D| sum M_D |D^ - D|
+ *     + lambda_n lambda_ng / |Omega_N| sum M_N (1 - N^ . N / |N^|),
+ * M_D = [D > 0], M_N = M_D [|N| > 0]; an empty mask gives a zero term; |0| has zero
+ * slope; a ray rendering a zero normal costs 1 with zero gradient.
+ *   n_rays: number of rays (H * W), >= 0.
+ *   target_depth: n_rays (0 = no return); target_normal: n_rays x 3, unit, sensor frame.
+ *   loss_out: DEVICE float[5] = {total, depth term, normal term, |Omega_D|, |Omega_N|}.
+ *   grad_out: caller-owned dL/d(depth, opacity, normal); d_opacity is zero for this loss.
+ * Errors: EINVAL, EDEVICE. */
+lgsr_status lgsr_loss(lgsr_ctx *ctx, int64_t n_rays, const lgsr_frame *pred,
+                      const float *target_depth, const float *target_normal,
+                      const lgsr_loss_weights *weights, float *loss_out, lgsr_frame_grad *grad_out);
+
+/* Backward of the forward that produced `state`: given dL/d(depth, opacity, normal) per
+ * ray, write dL/d every surfel parameter into `out` (overwritten; zero for surfels that
+ * render nothing) and dL/d(rho, omega) into grad_pose (DEVICE float[6], overwritten).
+ * Per-surfel gradients are summed with float atomics, so the last bits can vary from run
+ * to run.  Errors: EINVAL, ESTATE, ENOMEM, EDEVICE. */
+lgsr_status lgsr_backward(lgsr_ctx *ctx, lgsr_state *state, const lgsr_frame_grad *grad_in,
+                          lgsr_surfel_grads *out, float *grad_pose);
+
+/* Release a state (its buffers return to the context's pool).  NULL is a no-op. */
+void lgsr_state_free(lgsr_state *state);
+
+/* Counters of the forward that produced `state` (waits for it), HOST int64[8]:
+ *   out[0] (surfel, tile) pairs            out[1] surfels that survived culling
+ *   out[2] bytes of device workspace held by the context and the state
+ *   out[3] longest per-tile list           out[4] ray-surfel tests the raster performs
+ *          (64 per pair and overlapping 8 x 8 wave sub-tile)
+ *   out[5] composited hits (sum over rays of the hit count)
+ *   out[6] rays with at least one hit      out[7] reserved (0). */
+lgsr_status lgsr_query(lgsr_ctx *ctx, const lgsr_state *state, int64_t out[8]);
+
+/* Stage timers.  While enabled, every stage below is bracketed by HIP events on the
+ * context's stream (a stage may span several kernel launches); lgsr_profile_read waits for
+ * the stream, adds up the elapsed times per stage since the last read (HOST double[12],
+ * milliseconds) and the number of times each stage ran (HOST int64[12]), then resets them. */
+enum {
+    LGSR_STAGE_PROJECT = 0,    /* projection, records, rectangles, tile counts */
+    LGSR_STAGE_DEPTH_SORT = 1, /* surfels by (range, index) */
+    LGSR_STAGE_SCAN = 2,       /* pair offsets and counters */
+    LGSR_STAGE_EMIT = 3,       /* (tile, surfel) pairs */
+    LGSR_STAGE_TILE_SORT = 4,  /* pairs by tile */
+    LGSR_STAGE_RANGES = 5,     /* per-tile list bounds */
+    LGSR_STAGE_RASTER_FWD = 6, /* forward compositing */
+    LGSR_STAGE_LOSS = 7,       /* loss and its per-ray gradient */
+    LGSR_STAGE_BWD_ZERO = 8,   /* clearing the record gradients */
+    LGSR_STAGE_RASTER_BWD = 9, /* backward compositing */
+    LGSR_STAGE_CHAIN = 10,     /* parameter and pose gradients */
+    LGSR_STAGE_READBACK = 11,  /* the one device-to-host read of the pair count */
+    LGSR_NUM_STAGES = 12
+};
+lgsr_status lgsr_profile(lgsr_ctx *ctx, int32_t enable);
+lgsr_status lgsr_profile_read(lgsr_ctx *ctx, double ms[12], int64_t calls[12]);
+
+/* Wait for all work issued on the context's stream; reports an earlier kernel fault. */
+lgsr_status lgsr_sync(lgsr_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,161 @@
+// chain.hip -- record-space gradients -> surfel parameters and the 6-DoF pose.
+//
+// The backward raster leaves, per surfel, dL/d(nt, c, U, V, alpha) summed over rays.  With
+//   nt = sigma n',  c = nt . mu',  U = sigma (b' x mu') / s0,  V = sigma (mu' x a') / s1
+// (sigma piecewise constant), the sensor-frame gradients are
+//   dmu' = gc nt + (sigma/s0) gU x b' + (sigma/s1) a' x gV
+//   da'  = (sigma/s1) gV x mu',   db' = (sigma/s0) mu' x gU,   dn' = sigma (gnt + gc mu')
+//   ds0  = -gU.U / s0,   ds1 = -gV.V / s1
+// then world frame (multiply by R), the rotation columns (a, b, n) of the normalised
+// quaternion and its normalisation, s~ = log s (Sec. 3.3) and alpha = sigmoid(o).
+// Pose, right perturbation T Exp(xi): drho = -sum dmu', domega = -sum(mu' x dmu' + a' x da'
+// + b' x db' + n' x dn'); per-block partials are folded by one block in a fixed order with
+// compensated sums, so the pose gradient is deterministic given the record gradients.
+#include "lgsr_internal.h"
+#include "lgsr_kernels.h"
+
+namespace lgsr {
+
+constexpr int kChainThreads = 256;
+
+__device__ __forceinline__ void cross(const float *x, const float *y, float *o)
+{
+    o[0] = x[1] * y[2] - x[2] * y[1];
+    o[1] = x[2] * y[0] - x[0] * y[2];
+    o[2] = x[0] * y[1] - x[1] * y[0];
+}
+
+__device__ __forceinline__ Pose load_pose(const float *__restrict__ pd)
+{
+    Pose P;
+    for (int c = 0; c < 9; ++c) P.r[c] = pd[(c / 3) * 4 + (c % 3)];
+    for (int c = 0; c < 3; ++c) P.t[c] = pd[4 * c + 3];
+    return P;
+}
+
+__global__ __launch_bounds__(kChainThreads) void chain_kernel(SurfelPtrs S, const float *__restrict__ pose_dev,
+                                                              RasterParams p, const float *__restrict__ recgrad,
+                                                              float *__restrict__ dm, float *__restrict__ dq,
+                                                              float *__restrict__ dls, float *__restrict__ dlog,
+                                                              float *__restrict__ partials)
+{
+    const Pose P = load_pose(pose_dev);
+    const int64_t i = (int64_t)blockIdx.x * kChainThreads + threadIdx.x;
+    float pr[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    if (i < S.n) {
+        Geom g = project_geom(S.means, S.quats, S.log_scales, S.logits, i, P, p.near);
+        float out_m[3] = {0.f, 0.f, 0.f}, out_q[4] = {0.f, 0.f, 0.f, 0.f}, out_s[2] = {0.f, 0.f}, out_o = 0.f;
+        if (g.valid) {
+            const float4 *G4 = reinterpret_cast<const float4 *>(recgrad + (size_t)i * kGrad);
+            float4 x = G4[0], y = G4[1], z = G4[2];
+            float gnt[3] = {x.x, x.y, x.z}, gc = x.w;
+            float gU[3] = {y.x, y.y, y.z}, gV[3] = {y.w, z.x, z.y};
+            float ga = z.z;
+            float mu[3] = {g.mh[0] + g.ml[0], g.mh[1] + g.ml[1], g.mh[2] + g.ml[2]};
+            float nt[3] = {g.sigma * g.n[0], g.sigma * g.n[1], g.sigma * g.n[2]};
+            float k0 = g.sigma / g.s0, k1 = g.sigma / g.s1;
+            float bxm[3], mxa[3];
+            cross(g.b, mu, bxm);
+            cross(mu, g.a, mxa);
+            float U[3] = {bxm[0] * k0, bxm[1] * k0, bxm[2] * k0};
+            float V[3] = {mxa[0] * k1, mxa[1] * k1, mxa[2] * k1};
+            float t1[3], t2[3];
+            cross(gU, g.b, t1);
+            cross(g.a, gV, t2);
+            float gmu[3], gav[3], gbv[3], gnv[3];
+            for (int c = 0; c < 3; ++c) gmu[c] = gc * nt[c] + k0 * t1[c] + k1 * t2[c];
+            cross(gV, mu, t1);
+            cross(mu, gU, t2);
+            for (int c = 0; c < 3; ++c) {
+                gav[c] = k1 * t1[c];
+                gbv[c] = k0 * t2[c];
+                gnv[c] = g.sigma * (gnt[c] + gc * mu[c]);
+            }
+            float gs0 = -(gU[0] * U[0] + gU[1] * U[1] + gU[2] * U[2]) / g.s0;
+            float gs1 = -(gV[0] * V[0] + gV[1] * V[1] + gV[2] * V[2]) / g.s1;
+            // world frame
+            float Ga[3], Gb[3], Gn[3];
+            rot(P, gmu, out_m);
+            rot(P, gav, Ga);
+            rot(P, gbv, Gb);
+            rot(P, gnv, Gn);
+            // columns of R(qhat): a = (1-2(y2+z2), 2(xy+wz), 2(xz-wy)), b = (2(xy-wz), 1-2(x2+z2),
+            // 2(yz+wx)), n = (2(xz+wy), 2(yz-wx), 1-2(x2+y2))
+            float w = g.qh[0], qx = g.qh[1], qy = g.qh[2], qz = g.qh[3];
+            float dw = 2.f * (Ga[1] * qz - Ga[2] * qy - Gb[0] * qz + Gb[2] * qx + Gn[0] * qy - Gn[1] * qx);
+            float dx = 2.f * (Ga[1] * qy + Ga[2] * qz + Gb[0] * qy + Gb[2] * w + Gn[0] * qz - Gn[1] * w)
+                     - 4.f * (Gb[1] * qx + Gn[2] * qx);
+            float dy = 2.f * (Ga[1] * qx - Ga[2] * w + Gb[0] * qx + Gb[2] * qz + Gn[0] * w + Gn[1] * qz)
+                     - 4.f * (Ga[0] * qy + Gn[2] * qy);
+            float dz = 2.f * (Ga[1] * w + Ga[2] * qx - Gb[0] * w + Gb[2] * qy + Gn[0] * qx + Gn[1] * qy)
+                     - 4.f * (Ga[0] * qz + Gb[1] * qz);
+            float radial = dw * w + dx * qx + dy * qy + dz * qz;
+            float iq = 1.f / g.qn;
+            out_q[0] = (dw - radial * w) * iq;
+            out_q[1] = (dx - radial * qx) * iq;
+            out_q[2] = (dy - radial * qy) * iq;
+            out_q[3] = (dz - radial * qz) * iq;
+            out_s[0] = g.s0 * gs0;
+            out_s[1] = g.s1 * gs1;
+            out_o = g.alpha * (1.f - g.alpha) * ga;
+            float c1[3], c2[3], c3[3], c4[3];
+            cross(mu, gmu, c1);
+            cross(g.a, gav, c2);
+            cross(g.b, gbv, c3);
+            cross(g.n, gnv, c4);
+            for (int c = 0; c < 3; ++c) {
+                pr[c] = -gmu[c];
+                pr[3 + c] = -(c1[c] + c2[c] + c3[c] + c4[c]);
+            }
+        }
+        for (int c = 0; c < 3; ++c) dm[3 * i + c] = out_m[c];
+        for (int c = 0; c < 4; ++c) dq[4 * i + c] = out_q[c];
+        dls[2 * i] = out_s[0];
+        dls[2 * i + 1] = out_s[1];
+        dlog[i] = out_o;
+    }
+    // block reduction of the pose terms: wave butterfly, then the 4 wave sums in order
+    __shared__ float ws[4][6];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+        float v = pr[c];
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+        if (lane == 0) ws[wv][c] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < 6) {
+        int c = threadIdx.x;
+        partials[(size_t)blockIdx.x * 6 + c] = ((ws[0][c] + ws[1][c]) + ws[2][c]) + ws[3][c];
+    }
+}
+
+__global__ void pose_finalize(int nb, const float *__restrict__ partials, float *__restrict__ grad_pose)
+{
+    int c = threadIdx.x;
+    if (c >= 6) return;
+    float s = 0.f, comp = 0.f;  // Kahan-Babuska (Neumaier) summation
+    for (int b = 0; b < nb; ++b) {
+        float x = partials[(size_t)b * 6 + c];
+        float t = s + x;
+        comp += fabsf(s) >= fabsf(x) ? (s - t) + x : (x - t) + s;
+        s = t;
+    }
+    grad_pose[c] = s + comp;
+}
+
+int chain_blocks(int64_t n) { return n > 0 ? (int)((n + kChainThreads - 1) / kChainThreads) : 1; }
+
+hipError_t launch_chain(const SurfelPtrs &S, const float *pose_dev, const RasterParams &p, const float *recgrad,
+                        float *d_means, float *d_quats, float *d_log_scales, float *d_logits, float *pose_partials,
+                        float *grad_pose, hipStream_t s)
+{
+    int nb = chain_blocks(S.n);
+    chain_kernel<<<nb, kChainThreads, 0, s>>>(S, pose_dev, p, recgrad, d_means, d_quats, d_log_scales, d_logits,
+                                             pose_partials);
+    pose_finalize<<<1, 64, 0, s>>>(nb, pose_partials, grad_pose);
+    return hipGetLastError();
+}
+
+}  // namespace lgsr

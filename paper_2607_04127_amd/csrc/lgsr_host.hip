@@ -1,0 +1,632 @@
+// lgsr_host.hip -- the C ABI of include/lgsr.h: argument validation, contexts, pooled
+// states and the ordering of the stages on one HIP stream.
+//
+// Forward stages (all on the context's stream):
+//   project      per-surfel record, conservative ray rectangle, tile count, range key
+//   sort         surfels by (range, index): stable LSD radix sort of the 31-bit range keys
+//   scan         tile counts gathered in range order -> pair offsets, total P
+//   (P is read back once to size the pair list)
+//   emit         (tile, surfel) pairs in range order
+//   sort         pairs by tile (stable, so each tile's list stays in range order)
+//   ranges       [start, end) of every tile's list
+//   raster_fwd   compositing, frame outputs and per-ray backward state
+// Backward: zero record gradients, raster_bwd, chain (parameters + pose).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "lgsr.h"
+#include "lgsr_internal.h"
+#include "lgsr_kernels.h"
+
+using namespace lgsr;
+
+namespace {
+
+struct DevBuf {
+    void *p = nullptr;
+    size_t cap = 0;
+};
+
+hipError_t ensure(DevBuf &b, size_t bytes)
+{
+    if (bytes == 0) bytes = 256;
+    if (bytes <= b.cap) return hipSuccess;
+    if (b.p) {
+        hipError_t e = hipFree(b.p);
+        b.p = nullptr;
+        b.cap = 0;
+        if (e != hipSuccess) return e;
+    }
+    size_t want = bytes + bytes / 4;
+    want = (want + 4095) & ~(size_t)4095;
+    hipError_t e = hipMalloc(&b.p, want);
+    if (e != hipSuccess) {
+        b.p = nullptr;
+        (void)hipGetLastError();
+        return e;
+    }
+    b.cap = want;
+    return hipSuccess;
+}
+
+void release(DevBuf &b)
+{
+    if (b.p) (void)hipFree(b.p);
+    b.p = nullptr;
+    b.cap = 0;
+}
+
+template <class T>
+T *as(DevBuf &b)
+{
+    return static_cast<T *>(b.p);
+}
+
+}  // namespace
+
+struct lgsr_state {
+    lgsr_ctx *ctx = nullptr;
+    bool live = false;
+    // forward products kept for the backward
+    DevBuf recs, rects, pk, pv, pk2, pv2, ranges, st0, st1, pose;
+    uint32_t *ids = nullptr;        // sorted pair surfel ids (pv or pv2)
+    uint32_t *tile_keys = nullptr;  // sorted pair tile ids (pk or pk2)
+    SurfelPtrs S{};
+    const float *rows = nullptr, *cols = nullptr;
+    Grid g{};
+    RasterParams prm{};
+    int64_t P = 0;
+    uint32_t n_visible = 0;  // filled by lgsr_query
+};
+
+struct lgsr_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+    // scratch
+    DevBuf keys, vals, keys2, vals2, cnt, offs, hist, scan_tmp, counters, recgrad, partials, pose_partials;
+    uint32_t *pinned = nullptr;  // host-pinned readback slots
+    std::vector<lgsr_state *> pool;
+    lgsr_state scratch_state;  // used when the caller asks for no state
+    int live_states = 0;
+    // stage timers
+    bool prof = false;
+    std::vector<hipEvent_t> ev_free;
+    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_pending;
+    double prof_ms[LGSR_NUM_STAGES] = {};
+    int64_t prof_calls[LGSR_NUM_STAGES] = {};
+};
+
+namespace {
+
+lgsr_status fail(lgsr_ctx *ctx, lgsr_status st, const char *fmt, ...)
+{
+    if (ctx) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        ctx->err = buf;
+    }
+    return st;
+}
+
+lgsr_status hip_fail(lgsr_ctx *ctx, hipError_t e, const char *where)
+{
+    lgsr_status st = (e == hipErrorOutOfMemory) ? LGSR_ENOMEM : LGSR_EDEVICE;
+    return fail(ctx, st, "%s: %s", where, hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr, where)                                   \
+    do {                                                       \
+        hipError_t e_ = (expr);                                \
+        if (e_ != hipSuccess) return hip_fail(ctx, e_, where); \
+    } while (0)
+
+bool finite_pos(float x) { return std::isfinite(x) && x > 0.f; }
+
+lgsr_status check_opts(lgsr_ctx *ctx, const lgsr_raster_opts *o)
+{
+    if (!o) return fail(ctx, LGSR_EINVAL, "opts is NULL");
+    if (!finite_pos(o->cutoff_sigma)) return fail(ctx, LGSR_EINVAL, "cutoff_sigma must be finite and > 0");
+    if (!finite_pos(o->alpha_thr) || !finite_pos(o->alpha_max) || o->alpha_max >= 1.f || o->alpha_thr > o->alpha_max)
+        return fail(ctx, LGSR_EINVAL, "need 0 < alpha_thr <= alpha_max < 1");
+    if (!std::isfinite(o->T_min) || o->T_min < 0.f || o->T_min >= 1.f)
+        return fail(ctx, LGSR_EINVAL, "T_min must lie in [0, 1)");
+    if (!finite_pos(o->near)) return fail(ctx, LGSR_EINVAL, "near must be finite and > 0");
+    if (!std::isfinite(o->den_eps) || o->den_eps < 0.f) return fail(ctx, LGSR_EINVAL, "den_eps must be >= 0");
+    if (!std::isfinite(o->drop_tau)) return fail(ctx, LGSR_EINVAL, "drop_tau must be finite");
+    if (o->flags != 0) return fail(ctx, LGSR_EINVAL, "flags must be 0");
+    return LGSR_OK;
+}
+
+RasterParams to_params(const lgsr_raster_opts *o)
+{
+    RasterParams p;
+    p.cutoff = o->cutoff_sigma;
+    p.k2 = o->cutoff_sigma * o->cutoff_sigma;
+    p.alpha_thr = o->alpha_thr;
+    p.alpha_max = o->alpha_max;
+    p.T_min = o->T_min;
+    p.near = o->near;
+    p.den_eps = o->den_eps;
+    p.drop_tau = o->drop_tau;
+    return p;
+}
+
+int bits_for(int T)
+{
+    int b = 0;
+    while ((1 << b) < T) ++b;
+    return b;
+}
+
+lgsr_state *take_state(lgsr_ctx *ctx)
+{
+    if (!ctx->pool.empty()) {
+        lgsr_state *s = ctx->pool.back();
+        ctx->pool.pop_back();
+        return s;
+    }
+    lgsr_state *s = new (std::nothrow) lgsr_state;
+    if (s) s->ctx = ctx;
+    return s;
+}
+
+void free_state_buffers(lgsr_state *s)
+{
+    release(s->recs); release(s->rects); release(s->pk); release(s->pv); release(s->pk2); release(s->pv2);
+    release(s->ranges); release(s->st0); release(s->st1); release(s->pose);
+}
+
+hipEvent_t take_event(lgsr_ctx *ctx)
+{
+    if (!ctx->ev_free.empty()) {
+        hipEvent_t e = ctx->ev_free.back();
+        ctx->ev_free.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    return e;
+}
+
+// Brackets one stage with events on the context's stream while profiling is on.
+struct Stage {
+    lgsr_ctx *ctx;
+    int id;
+    hipEvent_t a = nullptr;
+    Stage(lgsr_ctx *c, int stage) : ctx(c), id(stage)
+    {
+        if (!ctx->prof) return;
+        a = take_event(ctx);
+        if (a) (void)hipEventRecord(a, ctx->stream);
+    }
+    ~Stage()
+    {
+        if (!a) return;
+        hipEvent_t b = take_event(ctx);
+        if (!b) {
+            ctx->ev_free.push_back(a);
+            return;
+        }
+        (void)hipEventRecord(b, ctx->stream);
+        ctx->ev_pending.push_back({id, {a, b}});
+    }
+};
+
+size_t state_bytes(const lgsr_state *s)
+{
+    return s->recs.cap + s->rects.cap + s->pk.cap + s->pv.cap + s->pk2.cap + s->pv2.cap + s->ranges.cap +
+           s->st0.cap + s->st1.cap + s->pose.cap;
+}
+
+size_t ctx_bytes(const lgsr_ctx *c)
+{
+    return c->keys.cap + c->vals.cap + c->keys2.cap + c->vals2.cap + c->cnt.cap + c->offs.cap + c->hist.cap +
+           c->scan_tmp.cap + c->counters.cap + c->recgrad.cap + c->partials.cap + c->pose_partials.cap +
+           state_bytes(&c->scratch_state);
+}
+
+}  // namespace
+
+extern "C" {
+
+void lgsr_default_opts(lgsr_raster_opts *o)
+{
+    if (!o) return;
+    o->cutoff_sigma = 3.f;
+    o->alpha_thr = 1.f / 255.f;
+    o->alpha_max = 0.99f;
+    o->T_min = 1e-4f;
+    o->near = 0.2f;
+    o->den_eps = 1e-6f;
+    o->drop_tau = 0.5f;
+    o->flags = 0;
+}
+
+void lgsr_default_loss_weights(lgsr_loss_weights *w)
+{
+    if (!w) return;
+    w->w_depth = 1.f;
+    w->lambda_n = 1.f;
+    w->lambda_ng = 0.05f;
+}
+
+lgsr_status lgsr_create(lgsr_ctx **out, int device, void *hip_stream)
+{
+    if (!out) return LGSR_EINVAL;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) {
+        (void)hipGetLastError();
+        return LGSR_EDEVICE;
+    }
+    if (device < 0 || device >= ndev) return LGSR_EDEVICE;
+    if (hipSetDevice(device) != hipSuccess) return LGSR_EDEVICE;
+    lgsr_ctx *ctx = new (std::nothrow) lgsr_ctx;
+    if (!ctx) return LGSR_ENOMEM;
+    ctx->device = device;
+    ctx->stream = static_cast<hipStream_t>(hip_stream);
+    ctx->scratch_state.ctx = ctx;
+    if (hipHostMalloc(reinterpret_cast<void **>(&ctx->pinned), 256, hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        delete ctx;
+        return LGSR_ENOMEM;
+    }
+    if (ensure(ctx->counters, 256) != hipSuccess) {
+        (void)hipHostFree(ctx->pinned);
+        delete ctx;
+        return LGSR_ENOMEM;
+    }
+    *out = ctx;
+    return LGSR_OK;
+}
+
+void lgsr_destroy(lgsr_ctx *ctx)
+{
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    for (lgsr_state *s : ctx->pool) {
+        free_state_buffers(s);
+        delete s;
+    }
+    free_state_buffers(&ctx->scratch_state);
+    DevBuf *bufs[] = {&ctx->keys, &ctx->vals, &ctx->keys2, &ctx->vals2, &ctx->cnt, &ctx->offs, &ctx->hist,
+                      &ctx->scan_tmp, &ctx->counters, &ctx->recgrad, &ctx->partials, &ctx->pose_partials};
+    for (DevBuf *b : bufs) release(*b);
+    for (auto &pe : ctx->ev_pending) {
+        (void)hipEventDestroy(pe.second.first);
+        (void)hipEventDestroy(pe.second.second);
+    }
+    for (hipEvent_t e : ctx->ev_free) (void)hipEventDestroy(e);
+    if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+    delete ctx;
+}
+
+lgsr_status lgsr_set_stream(lgsr_ctx *ctx, void *hip_stream)
+{
+    if (!ctx) return LGSR_EINVAL;
+    ctx->stream = static_cast<hipStream_t>(hip_stream);
+    return LGSR_OK;
+}
+
+const char *lgsr_last_error(const lgsr_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+lgsr_status lgsr_forward(lgsr_ctx *ctx, const lgsr_surfels *surfels, const float *pose_ws, int32_t pose_on_device,
+                         const lgsr_beams *beams, const lgsr_raster_opts *opts, lgsr_frame *out,
+                         lgsr_state **state)
+{
+    if (!ctx) return LGSR_EINVAL;
+    if (state) *state = nullptr;
+    if (!surfels) return fail(ctx, LGSR_EINVAL, "surfels is NULL");
+    const int64_t n = surfels->n;
+    if (n < 0 || n > (int64_t)0x7FFFFFFF) return fail(ctx, LGSR_EINVAL, "surfel count %lld out of range", (long long)n);
+    if (n > 0 && (!surfels->means || !surfels->quats || !surfels->log_scales || !surfels->opacity_logits))
+        return fail(ctx, LGSR_EINVAL, "surfel arrays must not be NULL");
+    if (!pose_ws) return fail(ctx, LGSR_EINVAL, "pose is NULL");
+    if (!beams) return fail(ctx, LGSR_EINVAL, "beams is NULL");
+    if (beams->H < 1 || beams->W < 1 || beams->H > 32768 || beams->W > 32768)
+        return fail(ctx, LGSR_EINVAL, "beam grid %d x %d out of range [1, 32768]", beams->H, beams->W);
+    if (!beams->row_sincos || !beams->col_sincos) return fail(ctx, LGSR_EINVAL, "beam tables must not be NULL");
+    lgsr_status st = check_opts(ctx, opts);
+    if (st != LGSR_OK) return st;
+    if (!out || !out->depth || !out->opacity || !out->normal || !out->drop)
+        return fail(ctx, LGSR_EINVAL, "frame outputs must not be NULL");
+    Pose pose_val{};
+    if (!pose_on_device) {
+        for (int c = 0; c < 9; ++c) pose_val.r[c] = pose_ws[(c / 3) * 4 + (c % 3)];
+        for (int c = 0; c < 3; ++c) pose_val.t[c] = pose_ws[4 * c + 3];
+        for (int c = 0; c < 12; ++c)
+            if (!std::isfinite(pose_ws[c])) return fail(ctx, LGSR_EINVAL, "pose has a non-finite entry");
+    }
+    HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
+    hipStream_t s = ctx->stream;
+
+    lgsr_state *S = state ? take_state(ctx) : &ctx->scratch_state;
+    if (!S) return fail(ctx, LGSR_ENOMEM, "out of host memory");
+    // on any error below a taken state goes back to the pool
+    struct Guard {
+        lgsr_ctx *c;
+        lgsr_state *s;
+        bool keep = false;
+        ~Guard()
+        {
+            if (!keep && s != &c->scratch_state) c->pool.push_back(s);
+        }
+    } guard{ctx, S};
+
+    Grid g;
+    g.H = beams->H;
+    g.W = beams->W;
+    g.TH = (g.H + kTile - 1) / kTile;
+    g.TW = (g.W + kTile - 1) / kTile;
+    g.T = g.TH * g.TW;
+    const int64_t rays = (int64_t)g.H * g.W;
+    const RasterParams prm = to_params(opts);
+    const size_t nn = (size_t)(n > 0 ? n : 1);
+
+    HIP_TRY(ensure(S->recs, nn * kRec * sizeof(float)), "alloc records");
+    HIP_TRY(ensure(S->rects, nn * sizeof(uint2)), "alloc rects");
+    HIP_TRY(ensure(S->ranges, (size_t)g.T * sizeof(uint2)), "alloc ranges");
+    HIP_TRY(ensure(S->st0, (size_t)rays * sizeof(float4)), "alloc ray state");
+    HIP_TRY(ensure(S->st1, (size_t)rays * sizeof(float4)), "alloc ray state");
+    HIP_TRY(ensure(S->pose, 16 * sizeof(float)), "alloc pose");
+    HIP_TRY(ensure(ctx->keys, nn * 4), "alloc keys");
+    HIP_TRY(ensure(ctx->vals, nn * 4), "alloc vals");
+    HIP_TRY(ensure(ctx->keys2, nn * 4), "alloc keys");
+    HIP_TRY(ensure(ctx->vals2, nn * 4), "alloc vals");
+    HIP_TRY(ensure(ctx->cnt, nn * 4), "alloc counts");
+    HIP_TRY(ensure(ctx->offs, nn * 4), "alloc offsets");
+    HIP_TRY(ensure(ctx->hist, radix_hist_words(n) * 4), "alloc histogram");
+    HIP_TRY(ensure(ctx->scan_tmp, (scan_tmp_words(n) + scan_tmp_words(radix_hist_words(n))) * 4), "alloc scan");
+
+    SurfelPtrs SP{surfels->means, surfels->quats, surfels->log_scales, surfels->opacity_logits, n};
+    uint32_t *counters = as<uint32_t>(ctx->counters);
+    {
+    Stage st_(ctx, LGSR_STAGE_PROJECT);
+    HIP_TRY(launch_project(SP, pose_val, pose_on_device ? pose_ws : nullptr, as<float>(S->pose), beams->row_sincos, g,
+                           prm, as<float>(S->recs), as<uint2>(S->rects), as<uint32_t>(ctx->keys),
+                           as<uint32_t>(ctx->vals), as<uint32_t>(ctx->cnt), s),
+            "project");
+    }
+    int64_t P = 0;
+    const uint32_t *sorted_ids = as<uint32_t>(ctx->vals);
+    if (n > 0) {
+        bool alt = false;
+        {
+        Stage st_(ctx, LGSR_STAGE_DEPTH_SORT);
+        HIP_TRY(radix_sort_pairs(as<uint32_t>(ctx->keys), as<uint32_t>(ctx->vals), as<uint32_t>(ctx->keys2),
+                                 as<uint32_t>(ctx->vals2), n, 31, as<uint32_t>(ctx->hist),
+                                 as<uint32_t>(ctx->scan_tmp), s, &alt),
+                "depth sort");
+        }
+        sorted_ids = alt ? as<uint32_t>(ctx->vals2) : as<uint32_t>(ctx->vals);
+        {
+        Stage st_(ctx, LGSR_STAGE_SCAN);
+        HIP_TRY(scan_u32(as<uint32_t>(ctx->cnt), sorted_ids, as<uint32_t>(ctx->offs), counters, n,
+                         as<uint32_t>(ctx->scan_tmp), s),
+                "count scan");
+        HIP_TRY(launch_count_visible(as<uint32_t>(ctx->cnt), n, counters + 2, s), "count visible");
+        }
+        Stage st_(ctx, LGSR_STAGE_READBACK);
+        HIP_TRY(hipMemcpyAsync(ctx->pinned, counters, 3 * sizeof(uint32_t), hipMemcpyDeviceToHost, s), "readback");
+        HIP_TRY(hipStreamSynchronize(s), "readback sync");
+        P = (int64_t)ctx->pinned[0];
+    }
+    const uint32_t n_visible = n > 0 ? ctx->pinned[2] : 0u;
+    // the scan is 32-bit: the count must stay below 2^31 (lists are addressed as int)
+    if (P < 0 || P > (int64_t)0x7FFFFFFF) return fail(ctx, LGSR_ECAPACITY, "too many (surfel, tile) pairs");
+    const size_t pp = (size_t)(P > 0 ? P : 1);
+    HIP_TRY(ensure(S->pk, pp * 4), "alloc pairs");
+    HIP_TRY(ensure(S->pv, pp * 4), "alloc pairs");
+    HIP_TRY(ensure(S->pk2, pp * 4), "alloc pairs");
+    HIP_TRY(ensure(S->pv2, pp * 4), "alloc pairs");
+    HIP_TRY(ensure(ctx->hist, (radix_hist_words(n) > radix_hist_words(P) ? radix_hist_words(n) : radix_hist_words(P)) * 4),
+            "alloc histogram");
+    HIP_TRY(ensure(ctx->scan_tmp, (scan_tmp_words(radix_hist_words(P)) + scan_tmp_words(radix_hist_words(n)) +
+                                   scan_tmp_words(n)) * 4),
+            "alloc scan");
+    S->ids = as<uint32_t>(S->pv);
+    const uint32_t *tile_keys = as<uint32_t>(S->pk);
+    if (P > 0) {
+        {
+        Stage st_(ctx, LGSR_STAGE_EMIT);
+        HIP_TRY(launch_emit(sorted_ids, as<uint32_t>(ctx->cnt), as<uint32_t>(ctx->offs), as<uint2>(S->rects), n, g,
+                            as<uint32_t>(S->pk), as<uint32_t>(S->pv), s),
+                "emit");
+        }
+        bool alt = false;
+        Stage st_(ctx, LGSR_STAGE_TILE_SORT);
+        HIP_TRY(radix_sort_pairs(as<uint32_t>(S->pk), as<uint32_t>(S->pv), as<uint32_t>(S->pk2),
+                                 as<uint32_t>(S->pv2), P, bits_for(g.T), as<uint32_t>(ctx->hist),
+                                 as<uint32_t>(ctx->scan_tmp), s, &alt),
+                "tile sort");
+        if (alt) {
+            S->ids = as<uint32_t>(S->pv2);
+            tile_keys = as<uint32_t>(S->pk2);
+        }
+    }
+    {
+    Stage st_(ctx, LGSR_STAGE_RANGES);
+    HIP_TRY(launch_ranges(tile_keys, P, g.T, as<uint2>(S->ranges), s), "ranges");
+    }
+    {
+    Stage st_(ctx, LGSR_STAGE_RASTER_FWD);
+    HIP_TRY(launch_raster_fwd(S->ids, as<uint2>(S->ranges), as<float>(S->recs), as<uint2>(S->rects),
+                              beams->row_sincos, beams->col_sincos, g, prm, out->depth, out->opacity, out->normal,
+                              out->drop, as<float4>(S->st0), as<float4>(S->st1), s),
+            "raster forward");
+    }
+    S->tile_keys = const_cast<uint32_t *>(tile_keys);
+    S->S = SP;
+    S->rows = beams->row_sincos;
+    S->cols = beams->col_sincos;
+    S->g = g;
+    S->prm = prm;
+    S->P = P;
+    S->n_visible = n_visible;
+    if (state) {
+        S->live = true;
+        ctx->live_states++;
+        guard.keep = true;
+        *state = S;
+    }
+    return LGSR_OK;
+}
+
+lgsr_status lgsr_loss(lgsr_ctx *ctx, int64_t n_rays, const lgsr_frame *pred, const float *target_depth,
+                      const float *target_normal, const lgsr_loss_weights *w, float *loss_out,
+                      lgsr_frame_grad *grad_out)
+{
+    if (!ctx) return LGSR_EINVAL;
+    if (n_rays < 0) return fail(ctx, LGSR_EINVAL, "n_rays must be >= 0");
+    if (!w) return fail(ctx, LGSR_EINVAL, "weights is NULL");
+    if (!std::isfinite(w->w_depth) || !std::isfinite(w->lambda_n) || !std::isfinite(w->lambda_ng))
+        return fail(ctx, LGSR_EINVAL, "weights must be finite");
+    if (!loss_out) return fail(ctx, LGSR_EINVAL, "loss_out is NULL");
+    if (n_rays > 0) {
+        if (!pred || !pred->depth || !pred->normal) return fail(ctx, LGSR_EINVAL, "prediction is NULL");
+        if (!target_depth || !target_normal) return fail(ctx, LGSR_EINVAL, "targets are NULL");
+        if (!grad_out || !grad_out->d_depth || !grad_out->d_opacity || !grad_out->d_normal)
+            return fail(ctx, LGSR_EINVAL, "gradient outputs are NULL");
+    }
+    HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
+    HIP_TRY(ensure(ctx->partials, (size_t)loss_blocks(n_rays) * 4 * sizeof(float)), "alloc partials");
+    Stage st_(ctx, LGSR_STAGE_LOSS);
+    HIP_TRY(launch_loss(n_rays, pred ? pred->depth : nullptr, pred ? pred->normal : nullptr, target_depth,
+                        target_normal, w->w_depth, w->lambda_n, w->lambda_ng, as<float>(ctx->partials), loss_out,
+                        grad_out ? grad_out->d_depth : nullptr, grad_out ? grad_out->d_opacity : nullptr,
+                        grad_out ? grad_out->d_normal : nullptr, ctx->stream),
+            "loss");
+    return LGSR_OK;
+}
+
+lgsr_status lgsr_backward(lgsr_ctx *ctx, lgsr_state *S, const lgsr_frame_grad *gin, lgsr_surfel_grads *out,
+                          float *grad_pose)
+{
+    if (!ctx) return LGSR_EINVAL;
+    if (!S) return fail(ctx, LGSR_EINVAL, "state is NULL");
+    if (S->ctx != ctx || !S->live) return fail(ctx, LGSR_ESTATE, "state does not belong to this context");
+    if (!gin || !gin->d_depth || !gin->d_opacity || !gin->d_normal)
+        return fail(ctx, LGSR_EINVAL, "frame gradients are NULL");
+    if (!out || (S->S.n > 0 && (!out->means || !out->quats || !out->log_scales || !out->opacity_logits)))
+        return fail(ctx, LGSR_EINVAL, "surfel gradient outputs are NULL");
+    if (!grad_pose) return fail(ctx, LGSR_EINVAL, "grad_pose is NULL");
+    HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
+    hipStream_t s = ctx->stream;
+    const size_t nn = (size_t)(S->S.n > 0 ? S->S.n : 1);
+    HIP_TRY(ensure(ctx->recgrad, nn * kGrad * sizeof(float)), "alloc record gradients");
+    HIP_TRY(ensure(ctx->pose_partials, (size_t)chain_blocks(S->S.n) * 6 * sizeof(float)), "alloc pose partials");
+    {
+    Stage st_(ctx, LGSR_STAGE_BWD_ZERO);
+    HIP_TRY(launch_fill_u32(as<uint32_t>(ctx->recgrad), 0u, (int64_t)nn * kGrad, s), "zero record gradients");
+    }
+    {
+    Stage st_(ctx, LGSR_STAGE_RASTER_BWD);
+    HIP_TRY(launch_raster_bwd(S->ids, as<uint2>(S->ranges), as<float>(S->recs), as<uint2>(S->rects), S->rows, S->cols,
+                              S->g, S->prm, as<float4>(S->st0), as<float4>(S->st1), gin->d_depth, gin->d_opacity,
+                              gin->d_normal, as<float>(ctx->recgrad), s),
+            "raster backward");
+    }
+    Stage st_(ctx, LGSR_STAGE_CHAIN);
+    HIP_TRY(launch_chain(S->S, as<float>(S->pose), S->prm, as<float>(ctx->recgrad), out->means, out->quats,
+                         out->log_scales, out->opacity_logits, as<float>(ctx->pose_partials), grad_pose, s),
+            "chain");
+    return LGSR_OK;
+}
+
+void lgsr_state_free(lgsr_state *S)
+{
+    if (!S || !S->ctx) return;
+    lgsr_ctx *ctx = S->ctx;
+    if (S == &ctx->scratch_state || !S->live) return;
+    S->live = false;
+    ctx->live_states--;
+    ctx->pool.push_back(S);
+}
+
+lgsr_status lgsr_query(lgsr_ctx *ctx, const lgsr_state *S, int64_t out[8])
+{
+    if (!ctx) return LGSR_EINVAL;
+    if (!S || !out) return fail(ctx, LGSR_EINVAL, "state or out is NULL");
+    if (S->ctx != ctx || !S->live) return fail(ctx, LGSR_ESTATE, "state does not belong to this context");
+    HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
+    hipStream_t s = ctx->stream;
+    uint32_t *counters = as<uint32_t>(ctx->counters);
+    lgsr_state *W = const_cast<lgsr_state *>(S);
+    unsigned long long *wc = reinterpret_cast<unsigned long long *>(counters + 8);
+    HIP_TRY(launch_max_range(as<uint2>(W->ranges), S->g.T, counters + 1, s), "query");
+    HIP_TRY(launch_work_counts(W->tile_keys, W->ids, as<uint2>(W->rects), S->P, as<float4>(W->st1), S->g, wc, s),
+            "query");
+    HIP_TRY(hipMemcpyAsync(ctx->pinned + 1, counters + 1, sizeof(uint32_t), hipMemcpyDeviceToHost, s), "readback");
+    HIP_TRY(hipMemcpyAsync(ctx->pinned + 4, wc, 3 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s),
+            "readback");
+    HIP_TRY(hipStreamSynchronize(s), "query sync");
+    const unsigned long long *hw = reinterpret_cast<const unsigned long long *>(ctx->pinned + 4);
+    out[0] = S->P;
+    out[1] = (int64_t)S->n_visible;
+    out[2] = (int64_t)(ctx_bytes(ctx) + state_bytes(S));
+    out[3] = (int64_t)ctx->pinned[1];
+    out[4] = (int64_t)hw[0];
+    out[5] = (int64_t)hw[1];
+    out[6] = (int64_t)hw[2];
+    out[7] = 0;
+    return LGSR_OK;
+}
+
+lgsr_status lgsr_profile(lgsr_ctx *ctx, int32_t enable)
+{
+    if (!ctx) return LGSR_EINVAL;
+    ctx->prof = enable != 0;
+    return LGSR_OK;
+}
+
+lgsr_status lgsr_profile_read(lgsr_ctx *ctx, double ms[LGSR_NUM_STAGES], int64_t calls[LGSR_NUM_STAGES])
+{
+    if (!ctx) return LGSR_EINVAL;
+    if (!ms || !calls) return fail(ctx, LGSR_EINVAL, "ms or calls is NULL");
+    HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
+    HIP_TRY(hipStreamSynchronize(ctx->stream), "profile sync");
+    for (auto &pe : ctx->ev_pending) {
+        float t = 0.f;
+        if (hipEventElapsedTime(&t, pe.second.first, pe.second.second) == hipSuccess) {
+            ctx->prof_ms[pe.first] += t;
+            ctx->prof_calls[pe.first] += 1;
+        } else {
+            (void)hipGetLastError();
+        }
+        ctx->ev_free.push_back(pe.second.first);
+        ctx->ev_free.push_back(pe.second.second);
+    }
+    ctx->ev_pending.clear();
+    for (int k = 0; k < LGSR_NUM_STAGES; ++k) {
+        ms[k] = ctx->prof_ms[k];
+        calls[k] = ctx->prof_calls[k];
+        ctx->prof_ms[k] = 0.0;
+        ctx->prof_calls[k] = 0;
+    }
+    return LGSR_OK;
+}
+
+lgsr_status lgsr_sync(lgsr_ctx *ctx)
+{
+    if (!ctx) return LGSR_EINVAL;
+    HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
+    HIP_TRY(hipStreamSynchronize(ctx->stream), "sync");
+    return LGSR_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,286 @@
+// lgsr_internal.h -- device-side building blocks of the gfx950 surfel renderer.
+//
+// Formulation used on the GPU (equal in exact arithmetic to the plain definition of
+// arXiv 2607.04127 Sec. 3.1 / Sec. 3.4 with the 2DGS surfel of Sec. 1):
+//   sensor frame: mu' = R^T (mu - t), a' = R^T a, b' = R^T b, n' = R^T n, r = |mu'|;
+//   sigma = +1 if n'.mu' <= 0 else -1, nt = sigma n' (the normal facing the sensor);
+//   ray d: den = nt.d, hit range t = c / den with c = nt.mu' (<= 0),
+//          u = nu / den, v = nv / den  with nu = U.d, nv = V.d,
+//          U = sigma (b' x mu') / s0,  V = sigma (mu' x a') / s1
+//   (homogeneous form of the ray/plane hit: (t d - mu') . a' / s0 = U.d / den).
+// U.d nearly cancels for rays near the surfel centre (|U| ~ r / s), so it is evaluated as
+//   nu = cu + U . ((d_hi - m) + d_lo),   cu = U . m computed from an error-compensated mu',
+// where m is the float32 unit direction of the centre and d = d_hi + d_lo the exact ray
+// direction (cos phi cos th is a product of two float32 values, split exactly by an FMA).
+// The float32 rounding of U then only multiplies the small vector d - m.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lgsr {
+
+constexpr int kTile = 16;      // tile edge in rays: a tile is 16 x 16 rays, one workgroup
+constexpr int kSub = 8;        // wave sub-tile edge: 8 x 8 rays, one wavefront of 64 lanes
+constexpr int kRec = 16;       // floats per surfel record
+constexpr int kGrad = 12;      // floats per surfel record-gradient slot (11 used)
+constexpr uint32_t kCulledKey = 0x7FFFFFFFu;  // depth key of a surfel that renders nothing
+
+// Record layout (float index).
+enum : int {
+    R_NT = 0,   // 0..2 sensor-facing normal nt
+    R_C = 3,    // c = nt . mu'
+    R_U = 4,    // 4..6 U
+    R_CU = 7,   // cu = U . m (compensated)
+    R_V = 8,    // 8..10 V
+    R_CV = 11,  // cv = V . m (compensated)
+    R_M = 12,   // 12..14 m = mu' / r
+    R_ALPHA = 15
+};
+
+// Record-gradient layout (float index): dL/d(nt, c, U, V, alpha) summed over rays.
+enum : int { G_NT = 0, G_C = 3, G_U = 4, G_V = 7, G_ALPHA = 10 };
+
+struct Pose {
+    float r[9];  // row-major rotation sensor -> world
+    float t[3];
+};
+
+struct RasterParams {
+    float k2;  // cutoff_sigma^2
+    float alpha_thr, alpha_max, T_min, near, den_eps, drop_tau;
+    float cutoff;
+};
+
+struct Grid {
+    int H, W;    // rays
+    int TH, TW;  // tiles
+    int T;       // TH * TW
+};
+
+// Tile numbering is column-major so that consecutive tiles form azimuth sectors.
+__host__ __device__ inline int tile_id(int tr, int tc, int TH) { return tc * TH + tr; }
+
+// ----------------------------------------------------------------------------------------
+// error-free transformations (float32)
+// ----------------------------------------------------------------------------------------
+
+__device__ __forceinline__ void two_sum(float a, float b, float &s, float &e)
+{
+    s = a + b;
+    float bb = s - a;
+    e = (a - (s - bb)) + (b - bb);
+}
+
+__device__ __forceinline__ void two_prod(float a, float b, float &p, float &e)
+{
+    p = a * b;
+    e = fmaf(a, b, -p);
+}
+
+// a*b - c*d with about one rounding (Kahan's FMA difference of products)
+__device__ __forceinline__ float diff_prod(float a, float b, float c, float d)
+{
+    float w = c * d;
+    float e = fmaf(-c, d, w);
+    float f = fmaf(a, b, -w);
+    return f + e;
+}
+
+// ----------------------------------------------------------------------------------------
+// per-surfel projection (shared by the projection and the chain-rule kernels)
+// ----------------------------------------------------------------------------------------
+
+struct Geom {
+    float mh[3], ml[3];  // mu' = mh + ml (compensated)
+    float a[3], b[3], n[3];
+    float qh[4], qn;
+    float s0, s1, alpha, r, sigma;
+    bool valid;
+};
+
+__device__ __forceinline__ void quat_columns(const float *q, float *a, float *b, float *n)
+{
+    float w = q[0], x = q[1], y = q[2], z = q[3];
+    a[0] = 1.f - 2.f * (y * y + z * z); a[1] = 2.f * (x * y + w * z);       a[2] = 2.f * (x * z - w * y);
+    b[0] = 2.f * (x * y - w * z);       b[1] = 1.f - 2.f * (x * x + z * z); b[2] = 2.f * (y * z + w * x);
+    n[0] = 2.f * (x * z + w * y);       n[1] = 2.f * (y * z - w * x);       n[2] = 1.f - 2.f * (x * x + y * y);
+}
+
+// v' = R^T v
+__device__ __forceinline__ void rot_t(const Pose &P, const float *v, float *o)
+{
+    for (int j = 0; j < 3; ++j) o[j] = fmaf(P.r[j], v[0], fmaf(P.r[3 + j], v[1], P.r[6 + j] * v[2]));
+}
+
+// v = R v'
+__device__ __forceinline__ void rot(const Pose &P, const float *v, float *o)
+{
+    for (int i = 0; i < 3; ++i) o[i] = fmaf(P.r[3 * i], v[0], fmaf(P.r[3 * i + 1], v[1], P.r[3 * i + 2] * v[2]));
+}
+
+__device__ __forceinline__ Geom project_geom(const float *__restrict__ means, const float *__restrict__ quats,
+                                             const float *__restrict__ log_scales,
+                                             const float *__restrict__ logits, int64_t i, const Pose &P,
+                                             float near)
+{
+    Geom g;
+    float q[4] = {quats[4 * i], quats[4 * i + 1], quats[4 * i + 2], quats[4 * i + 3]};
+    float qq = fmaf(q[0], q[0], fmaf(q[1], q[1], fmaf(q[2], q[2], q[3] * q[3])));
+    g.qn = sqrtf(qq);
+    g.valid = g.qn > 0.f && isfinite(g.qn);
+    float inv = g.valid ? 1.f / g.qn : 0.f;
+    for (int c = 0; c < 4; ++c) g.qh[c] = q[c] * inv;
+    float aw[3], bw[3], nw[3];
+    quat_columns(g.qh, aw, bw, nw);
+    rot_t(P, aw, g.a);
+    rot_t(P, bw, g.b);
+    rot_t(P, nw, g.n);
+    // mu - t exactly as a float pair, then R^T (.) with compensated sums
+    float dh[3], dl[3];
+    for (int c = 0; c < 3; ++c) two_sum(means[3 * i + c], -P.t[c], dh[c], dl[c]);
+    for (int j = 0; j < 3; ++j) {
+        float s = 0.f, comp = 0.f;
+        for (int k = 0; k < 3; ++k) {
+            float p, pe, se;
+            two_prod(P.r[3 * k + j], dh[k], p, pe);
+            two_sum(s, p, s, se);
+            comp += pe + se + P.r[3 * k + j] * dl[k];
+        }
+        float hi, lo;
+        two_sum(s, comp, hi, lo);
+        g.mh[j] = hi;
+        g.ml[j] = lo;
+    }
+    g.s0 = expf(log_scales[2 * i]);
+    g.s1 = expf(log_scales[2 * i + 1]);
+    g.alpha = 1.f / (1.f + expf(-logits[i]));
+    g.r = sqrtf(fmaf(g.mh[0], g.mh[0], fmaf(g.mh[1], g.mh[1], g.mh[2] * g.mh[2])));
+    float nm = fmaf(g.n[0], g.mh[0], fmaf(g.n[1], g.mh[1], g.n[2] * g.mh[2]))
+             + fmaf(g.n[0], g.ml[0], fmaf(g.n[1], g.ml[1], g.n[2] * g.ml[2]));
+    g.sigma = nm <= 0.f ? 1.f : -1.f;
+    g.valid = g.valid && g.r >= near && isfinite(g.r) && isfinite(g.s0) && isfinite(g.s1) && g.s0 > 0.f &&
+              g.s1 > 0.f && isfinite(g.alpha);
+    return g;
+}
+
+// Record of a projected surfel (layout above).
+__device__ __forceinline__ void make_record(const Geom &g, float *rec)
+{
+    float nt[3] = {g.sigma * g.n[0], g.sigma * g.n[1], g.sigma * g.n[2]};
+    float c = fmaf(nt[0], g.mh[0], fmaf(nt[1], g.mh[1], nt[2] * g.mh[2]))
+            + fmaf(nt[0], g.ml[0], fmaf(nt[1], g.ml[1], nt[2] * g.ml[2]));
+    float ir = 1.f / g.r;
+    float m[3] = {g.mh[0] * ir, g.mh[1] * ir, g.mh[2] * ir};
+    // w = mu' x m, small: accurate difference of products on the high part + low part
+    float w[3];
+    w[0] = diff_prod(g.mh[1], m[2], g.mh[2], m[1]) + (g.ml[1] * m[2] - g.ml[2] * m[1]);
+    w[1] = diff_prod(g.mh[2], m[0], g.mh[0], m[2]) + (g.ml[2] * m[0] - g.ml[0] * m[2]);
+    w[2] = diff_prod(g.mh[0], m[1], g.mh[1], m[0]) + (g.ml[0] * m[1] - g.ml[1] * m[0]);
+    float i0 = g.sigma / g.s0, i1 = g.sigma / g.s1;
+    // U = sigma (b' x mu') / s0, V = sigma (mu' x a') / s1
+    float U[3] = {(g.b[1] * g.mh[2] - g.b[2] * g.mh[1]) * i0, (g.b[2] * g.mh[0] - g.b[0] * g.mh[2]) * i0,
+                  (g.b[0] * g.mh[1] - g.b[1] * g.mh[0]) * i0};
+    float V[3] = {(g.mh[1] * g.a[2] - g.mh[2] * g.a[1]) * i1, (g.mh[2] * g.a[0] - g.mh[0] * g.a[2]) * i1,
+                  (g.mh[0] * g.a[1] - g.mh[1] * g.a[0]) * i1};
+    // U . m = sigma b'.(mu' x m) / s0,   V . m = -sigma a'.(mu' x m) / s1
+    float cu = fmaf(g.b[0], w[0], fmaf(g.b[1], w[1], g.b[2] * w[2])) * i0;
+    float cv = -fmaf(g.a[0], w[0], fmaf(g.a[1], w[1], g.a[2] * w[2])) * i1;
+    rec[R_NT + 0] = nt[0]; rec[R_NT + 1] = nt[1]; rec[R_NT + 2] = nt[2];
+    rec[R_C] = c;
+    rec[R_U + 0] = U[0]; rec[R_U + 1] = U[1]; rec[R_U + 2] = U[2];
+    rec[R_CU] = cu;
+    rec[R_V + 0] = V[0]; rec[R_V + 1] = V[1]; rec[R_V + 2] = V[2];
+    rec[R_CV] = cv;
+    rec[R_M + 0] = m[0]; rec[R_M + 1] = m[1]; rec[R_M + 2] = m[2];
+    rec[R_ALPHA] = g.alpha;
+}
+
+// ----------------------------------------------------------------------------------------
+// rays and the per-(ray, surfel) hit test (shared bit-for-bit by forward and backward)
+// ----------------------------------------------------------------------------------------
+
+struct Ray {
+    float dh[3];  // float32 direction
+    float dl[2];  // exact residuals of the two products (the z component is exact)
+};
+
+__device__ __forceinline__ Ray make_ray(const float *__restrict__ rows, const float *__restrict__ cols, int k, int j)
+{
+    Ray r;
+    float sp = rows[2 * k], cp = rows[2 * k + 1];
+    float st = cols[2 * j], ct = cols[2 * j + 1];
+    r.dh[0] = cp * ct;
+    r.dh[1] = cp * st;
+    r.dh[2] = sp;
+    r.dl[0] = fmaf(cp, ct, -r.dh[0]);
+    r.dl[1] = fmaf(cp, st, -r.dh[1]);
+    return r;
+}
+
+struct Hit {
+    float den, inv, nu, nv, t, G, aG, ah;
+    bool pass;
+};
+
+// Record fields are passed by value so that wave-uniform loads stay in scalar registers.
+struct Rec {
+    float nt0, nt1, nt2, c, U0, U1, U2, cu, V0, V1, V2, cv, m0, m1, m2, alpha;
+};
+
+__device__ __forceinline__ Rec load_rec(const float *__restrict__ recs, uint32_t id)
+{
+    const float4 *p = reinterpret_cast<const float4 *>(recs + (size_t)id * kRec);
+    float4 x = p[0], y = p[1], z = p[2], w = p[3];
+    return Rec{x.x, x.y, x.z, x.w, y.x, y.y, y.z, y.w, z.x, z.y, z.z, z.w, w.x, w.y, w.z, w.w};
+}
+
+// -log2(e) / 2: G = exp(-q2 / 2) = exp2(q2 * kNegHalfLog2e)
+constexpr float kNegHalfLog2e = -0.72134752044448170f;
+
+__device__ __forceinline__ Hit hit_test(const Rec &s, const Ray &ray, const RasterParams &p)
+{
+    Hit h;
+    float ex = (ray.dh[0] - s.m0) + ray.dl[0];
+    float ey = (ray.dh[1] - s.m1) + ray.dl[1];
+    float ez = ray.dh[2] - s.m2;
+    h.den = fmaf(s.nt0, ray.dh[0], fmaf(s.nt1, ray.dh[1], s.nt2 * ray.dh[2]));
+    h.nu = fmaf(s.U0, ex, fmaf(s.U1, ey, fmaf(s.U2, ez, s.cu)));
+    h.nv = fmaf(s.V0, ex, fmaf(s.V1, ey, fmaf(s.V2, ez, s.cv)));
+    h.inv = __builtin_amdgcn_rcpf(h.den);
+    h.t = s.c * h.inv;
+    float u = h.nu * h.inv, v = h.nv * h.inv;
+    float q2 = fmaf(u, u, v * v);
+    h.G = __builtin_amdgcn_exp2f(q2 * kNegHalfLog2e);
+    h.aG = s.alpha * h.G;
+    h.ah = fminf(h.aG, p.alpha_max);
+    // |den| >= den_eps, t >= near, q2 <= k^2, alpha_hat >= alpha_thr
+    h.pass = (fabsf(h.den) >= p.den_eps) && (h.t >= p.near) && (q2 <= p.k2) && (h.ah >= p.alpha_thr);
+    return h;
+}
+
+// Wave sub-tile vs a surfel's conservative ray rectangle (rows r0..r1, columns c0..c0+cw-1
+// modulo W).  Two arcs of a circle meet iff one contains the other's first element.
+__device__ __forceinline__ bool sub_overlap(uint2 rc, int sr0, int sc0, int W)
+{
+    int r0 = (int)(rc.x & 0xFFFFu), r1 = (int)(rc.x >> 16);
+    int c0 = (int)(rc.y & 0xFFFFu), cw = (int)(rc.y >> 16);
+    if (cw == 0 || r0 >= sr0 + kSub || r1 < sr0) return false;
+    int d1 = sc0 - c0;
+    if (d1 < 0) d1 += W;
+    int d2 = c0 - sc0;
+    if (d2 < 0) d2 += W;
+    return d1 < cw || d2 < kSub;
+}
+
+// XCD-aware block -> tile map: workgroups are dealt to the 8 XCDs round-robin, so give
+// each XCD a contiguous run of tiles (an azimuth sector that shares surfels in its L2).
+__device__ __forceinline__ int xcd_tile(int b, int T)
+{
+    int x = b & 7, i = b >> 3;
+    int per = T >> 3, rem = T & 7;
+    int start = x * per + (x < rem ? x : rem);
+    return start + i;
+}
+
+}  // namespace lgsr

@@ -1,0 +1,326 @@
+// project.hip -- per-surfel projection and culling, pair emission and tile ranges.
+//
+// Projection (one thread per surfel): activations (normalised q, s = exp(s~) per Sec. 3.3,
+// alpha = sigmoid), world -> sensor transform, the 64-byte record of lgsr_internal.h, and
+// a conservative ray rectangle: every hit with u^2 + v^2 <= k^2 lies within
+// rho = k max(s0, s1) of the centre, so its direction lies in the cone of half-angle
+// asin(rho / r) around the centre direction.  The cone maps to an elevation interval
+// (rows, by binary search of the monotone row table) and an azimuth interval of half
+// width asin(sin beta / cos phi_c) (columns, uniform, wrapping at 360 degrees), or to
+// whole rows of azimuth when a pole lies inside the cone.
+#include "lgsr_internal.h"
+#include "lgsr_kernels.h"
+
+namespace lgsr {
+
+// Angular safety margin of the culling cone (radians): far above float32 rounding of
+// the angles involved, far below one beam spacing.
+constexpr float kAngMargin = 2e-4f;
+constexpr float kHalfPi = 1.57079632679489662f;
+constexpr float kTwoPi = 6.28318530717958648f;
+
+// Tile-column segments [a0, a1] and [b0, b1] (b1 < b0: empty) covered by columns
+// c0 .. c0 + cw - 1 modulo W.
+__device__ __forceinline__ void col_segments(int c0, int cw, int W, int TW, int &a0, int &a1, int &b0, int &b1)
+{
+    b0 = 1;
+    b1 = 0;
+    if (cw >= W) {
+        a0 = 0;
+        a1 = TW - 1;
+        return;
+    }
+    int end = c0 + cw - 1;
+    if (end < W) {
+        a0 = c0 / kTile;
+        a1 = end / kTile;
+        return;
+    }
+    a0 = c0 / kTile;
+    a1 = TW - 1;
+    int bh = (end - W) / kTile;
+    if (bh >= a0) {
+        a0 = 0;
+        a1 = TW - 1;
+    } else {
+        b0 = 0;
+        b1 = bh;
+    }
+}
+
+// first k in [0, H) with rows_sin[k] <= x (rows strictly decreasing); H if none
+__device__ __forceinline__ int first_row_le(const float *__restrict__ rows, int H, float x)
+{
+    int lo = 0, hi = H;
+    while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if (rows[2 * mid] <= x) hi = mid;
+        else lo = mid + 1;
+    }
+    return lo;
+}
+
+// first k in [0, H) with rows_sin[k] < x; H if none
+__device__ __forceinline__ int first_row_lt(const float *__restrict__ rows, int H, float x)
+{
+    int lo = 0, hi = H;
+    while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if (rows[2 * mid] < x) hi = mid;
+        else lo = mid + 1;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(256) void project_kernel(SurfelPtrs S, Pose pose_val, const float *__restrict__ pose_dev,
+                                                      float *__restrict__ pose_out,
+                                                      const float *__restrict__ rows, Grid g, RasterParams p,
+                                                      float *__restrict__ recs, uint2 *__restrict__ rects,
+                                                      uint32_t *__restrict__ keys, uint32_t *__restrict__ vals,
+                                                      uint32_t *__restrict__ cnt)
+{
+    Pose P = pose_val;
+    if (pose_dev) {
+        for (int c = 0; c < 9; ++c) P.r[c] = pose_dev[(c / 3) * 4 + (c % 3)];
+        for (int c = 0; c < 3; ++c) P.t[c] = pose_dev[4 * c + 3];
+    }
+    if (blockIdx.x == 0 && threadIdx.x < 12) {
+        int c = threadIdx.x, row = c >> 2, col = c & 3;
+        pose_out[c] = col < 3 ? P.r[3 * row + col] : P.t[row];
+    }
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= S.n) return;
+    vals[i] = (uint32_t)i;
+    Geom gm = project_geom(S.means, S.quats, S.log_scales, S.logits, i, P, p.near);
+    if (!gm.valid) {
+        keys[i] = kCulledKey;
+        cnt[i] = 0;
+        rects[i] = make_uint2(0u, 0u);
+        return;
+    }
+    float rec[kRec];
+    make_record(gm, rec);
+    float4 *dst = reinterpret_cast<float4 *>(recs + (size_t)i * kRec);
+    dst[0] = make_float4(rec[0], rec[1], rec[2], rec[3]);
+    dst[1] = make_float4(rec[4], rec[5], rec[6], rec[7]);
+    dst[2] = make_float4(rec[8], rec[9], rec[10], rec[11]);
+    dst[3] = make_float4(rec[12], rec[13], rec[14], rec[15]);
+    keys[i] = __float_as_uint(gm.r);
+
+    // conservative ray rectangle
+    const int H = g.H, W = g.W;
+    int r0, r1, c0, cw;
+    float rho = p.cutoff * fmaxf(gm.s0, gm.s1);
+    if (rho >= gm.r * 0.999f) {
+        r0 = 0; r1 = H - 1; c0 = 0; cw = W;
+    } else {
+        float beta = asinf(rho / gm.r) + kAngMargin;
+        float mz = fminf(1.f, fmaxf(-1.f, rec[R_M + 2]));
+        float phic = asinf(mz);
+        float s_hi = (phic + beta >= kHalfPi) ? 2.f : sinf(phic + beta);
+        float s_lo = (phic - beta <= -kHalfPi) ? -2.f : sinf(phic - beta);
+        r0 = first_row_le(rows, H, s_hi);
+        r1 = first_row_lt(rows, H, s_lo) - 1;
+        if (fabsf(phic) + beta >= kHalfPi) {
+            c0 = 0; cw = W;
+        } else {
+            float thc = atan2f(rec[R_M + 1], rec[R_M + 0]);
+            float dth = asinf(fminf(1.f, sinf(beta) / cosf(phic))) + kAngMargin;
+            float scale = (float)W / kTwoPi;
+            int jlo = (int)ceilf((thc - dth) * scale);
+            int jhi = (int)floorf((thc + dth) * scale);
+            int w = jhi - jlo + 1;
+            if (w >= W) {
+                c0 = 0; cw = W;
+            } else if (w <= 0) {
+                cw = 0; c0 = 0;
+            } else {
+                c0 = jlo % W;
+                if (c0 < 0) c0 += W;
+                cw = w;
+            }
+        }
+    }
+    if (r0 > r1 || cw <= 0) {
+        cnt[i] = 0;
+        rects[i] = make_uint2(0u, 0u);
+        return;
+    }
+    rects[i] = make_uint2((uint32_t)r0 | ((uint32_t)r1 << 16), (uint32_t)c0 | ((uint32_t)cw << 16));
+    int a0, a1, b0, b1;
+    col_segments(c0, cw, W, g.TW, a0, a1, b0, b1);
+    int ncol = (a1 - a0 + 1) + (b1 >= b0 ? b1 - b0 + 1 : 0);
+    int nrow = r1 / kTile - r0 / kTile + 1;
+    cnt[i] = (uint32_t)(ncol * nrow);
+}
+
+__global__ __launch_bounds__(256) void emit_kernel(const uint32_t *__restrict__ sorted_ids,
+                                                   const uint32_t *__restrict__ cnt,
+                                                   const uint32_t *__restrict__ offs,
+                                                   const uint2 *__restrict__ rects, int64_t n, Grid g,
+                                                   uint32_t *__restrict__ pk, uint32_t *__restrict__ pv)
+{
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    uint32_t id = sorted_ids[k];
+    uint32_t c = cnt[id];
+    if (c == 0) return;
+    uint32_t o = offs[k];
+    uint2 rc = rects[id];
+    int r0 = (int)(rc.x & 0xFFFFu), r1 = (int)(rc.x >> 16);
+    int c0 = (int)(rc.y & 0xFFFFu), cw = (int)(rc.y >> 16);
+    int a0, a1, b0, b1;
+    col_segments(c0, cw, g.W, g.TW, a0, a1, b0, b1);
+    for (int tr = r0 / kTile; tr <= r1 / kTile; ++tr) {
+        for (int tc = a0; tc <= a1; ++tc) {
+            pk[o] = (uint32_t)tile_id(tr, tc, g.TH);
+            pv[o] = id;
+            ++o;
+        }
+        for (int tc = b0; tc <= b1; ++tc) {
+            pk[o] = (uint32_t)tile_id(tr, tc, g.TH);
+            pv[o] = id;
+            ++o;
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void ranges_kernel(const uint32_t *__restrict__ keys, int64_t P,
+                                                     uint2 *__restrict__ ranges)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= P) return;
+    uint32_t t = keys[i];
+    if (i == 0 || keys[i - 1] != t) ranges[t].x = (uint32_t)i;
+    if (i == P - 1 || keys[i + 1] != t) ranges[t].y = (uint32_t)(i + 1);
+}
+
+__global__ __launch_bounds__(256) void fill_u32_kernel(uint32_t *__restrict__ p, uint32_t v, int64_t n)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// out[0] += number of surfels with a nonzero tile count (out zeroed by the caller)
+__global__ __launch_bounds__(256) void count_visible_kernel(const uint32_t *__restrict__ cnt, int64_t n,
+                                                            uint32_t *__restrict__ out)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint64_t m = __ballot(i < n && cnt[i] > 0);
+    if ((threadIdx.x & 63) == 0 && m) atomicAdd(out, (uint32_t)__popcll(m));
+}
+
+__global__ __launch_bounds__(256) void max_range_kernel(const uint2 *__restrict__ ranges, int T,
+                                                        uint32_t *__restrict__ out)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < T) {
+        uint2 r = ranges[i];
+        atomicMax(out, r.y - r.x);
+    }
+}
+
+// out[0] += ray-surfel tests of the raster (64 per pair and overlapping wave sub-tile)
+__global__ __launch_bounds__(256) void work_tests_kernel(const uint32_t *__restrict__ tile_keys,
+                                                         const uint32_t *__restrict__ ids,
+                                                         const uint2 *__restrict__ rects, int64_t P, Grid g,
+                                                         unsigned long long *__restrict__ out)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    unsigned long long c = 0;
+    if (i < P) {
+        int t = (int)tile_keys[i];
+        int tc = t / g.TH, tr = t - tc * g.TH;
+        uint2 rc = rects[ids[i]];
+        for (int w = 0; w < 4; ++w) {
+            int sr0 = tr * kTile + (w >> 1) * kSub, sc0 = tc * kTile + (w & 1) * kSub;
+            if (sr0 < g.H && sc0 < g.W && sub_overlap(rc, sr0, sc0, g.W)) c += 64;
+        }
+    }
+    for (int o = 32; o >= 1; o >>= 1) c += __shfl_xor(c, o, 64);
+    if ((threadIdx.x & 63) == 0 && c) atomicAdd(out, c);
+}
+
+// out[1] += composited hits, out[2] += rays with a hit (from the per-ray state)
+__global__ __launch_bounds__(256) void work_hits_kernel(const float4 *__restrict__ st1, int64_t rays,
+                                                        unsigned long long *__restrict__ out)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    unsigned long long k = 0, h = 0;
+    if (i < rays) {
+        int K = __float_as_int(st1[i].w);
+        k = (unsigned long long)K;
+        h = K > 0;
+    }
+    for (int o = 32; o >= 1; o >>= 1) {
+        k += __shfl_xor(k, o, 64);
+        h += __shfl_xor(h, o, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        if (k) atomicAdd(out + 1, k);
+        if (h) atomicAdd(out + 2, h);
+    }
+}
+
+static inline unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+hipError_t launch_work_counts(const uint32_t *tile_keys, const uint32_t *ids, const uint2 *rects, int64_t P,
+                              const float4 *st1, const Grid &g, unsigned long long *out, hipStream_t s)
+{
+    hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t *>(out), 0u, 6, s);
+    if (e != hipSuccess) return e;
+    if (P > 0) work_tests_kernel<<<blocks_for(P, 256), 256, 0, s>>>(tile_keys, ids, rects, P, g, out);
+    int64_t rays = (int64_t)g.H * g.W;
+    work_hits_kernel<<<blocks_for(rays, 256), 256, 0, s>>>(st1, rays, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_project(const SurfelPtrs &S, const Pose &pose_val, const float *pose_dev, float *pose_out,
+                          const float *rows, const Grid &g, const RasterParams &p, float *recs, uint2 *rects,
+                          uint32_t *keys, uint32_t *vals, uint32_t *cnt, hipStream_t s)
+{
+    unsigned nb = S.n > 0 ? blocks_for(S.n, 256) : 1u;  // one block still writes the pose
+    project_kernel<<<nb, 256, 0, s>>>(S, pose_val, pose_dev, pose_out, rows, g, p, recs, rects, keys, vals, cnt);
+    return hipGetLastError();
+}
+
+hipError_t launch_emit(const uint32_t *sorted_ids, const uint32_t *cnt, const uint32_t *offs, const uint2 *rects,
+                       int64_t n, const Grid &g, uint32_t *pk, uint32_t *pv, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    emit_kernel<<<blocks_for(n, 256), 256, 0, s>>>(sorted_ids, cnt, offs, rects, n, g, pk, pv);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    fill_u32_kernel<<<blocks_for(n, 256), 256, 0, s>>>(p, v, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_ranges(const uint32_t *sorted_keys, int64_t P, int T, uint2 *ranges, hipStream_t s)
+{
+    hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t *>(ranges), 0u, 2 * (int64_t)T, s);
+    if (e != hipSuccess || P <= 0) return e;
+    ranges_kernel<<<blocks_for(P, 256), 256, 0, s>>>(sorted_keys, P, ranges);
+    return hipGetLastError();
+}
+
+hipError_t launch_count_visible(const uint32_t *cnt, int64_t n, uint32_t *out, hipStream_t s)
+{
+    hipError_t e = launch_fill_u32(out, 0u, 1, s);
+    if (e != hipSuccess || n <= 0) return e;
+    count_visible_kernel<<<blocks_for(n, 256), 256, 0, s>>>(cnt, n, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_max_range(const uint2 *ranges, int T, uint32_t *out, hipStream_t s)
+{
+    hipError_t e = launch_fill_u32(out, 0u, 1, s);
+    if (e != hipSuccess) return e;
+    max_range_kernel<<<blocks_for(T, 256), 256, 0, s>>>(ranges, T, out);
+    return hipGetLastError();
+}
+
+}  // namespace lgsr

@@ -1,0 +1,308 @@
+"""ctypes binding of the gfx950 renderer library (include/lgsr.h), same entry-point names.
+
+Argument marshalling only: tensors are checked (device, dtype, shape, contiguity), their
+device pointers and torch's current HIP stream are handed to the C ABI, and outputs are
+allocated with torch.  Every step of the rendering path runs in the library's kernels;
+there is no fallback.  If the library is not built, loading fails with an error.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblgsr.so")
+
+LGSR_OK, LGSR_EINVAL, LGSR_ENOMEM, LGSR_EDEVICE, LGSR_ECAPACITY, LGSR_ESTATE, LGSR_EINTERNAL = 0, -1, -2, -3, -4, -5, -6
+_STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ECAPACITY", -5: "ESTATE", -6: "EINTERNAL"}
+
+EXPORTS = ("lgsr_default_opts", "lgsr_default_loss_weights", "lgsr_create", "lgsr_destroy", "lgsr_set_stream",
+           "lgsr_last_error", "lgsr_forward", "lgsr_loss", "lgsr_backward", "lgsr_state_free", "lgsr_query",
+           "lgsr_profile", "lgsr_profile_read", "lgsr_sync")
+STAGES = ("project", "depth_sort", "scan", "emit", "tile_sort", "ranges", "raster_fwd", "loss", "bwd_zero",
+          "raster_bwd", "chain", "readback")
+
+
+class LgsrError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+vp = ctypes.c_void_p
+
+
+class Surfels(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("means", vp), ("quats", vp), ("log_scales", vp), ("opacity_logits", vp)]
+
+
+class Beams(ctypes.Structure):
+    _fields_ = [("H", ctypes.c_int32), ("W", ctypes.c_int32), ("row_sincos", vp), ("col_sincos", vp)]
+
+
+class RasterOpts(ctypes.Structure):
+    _fields_ = [("cutoff_sigma", ctypes.c_float), ("alpha_thr", ctypes.c_float), ("alpha_max", ctypes.c_float),
+                ("T_min", ctypes.c_float), ("near", ctypes.c_float), ("den_eps", ctypes.c_float),
+                ("drop_tau", ctypes.c_float), ("flags", ctypes.c_int32)]
+
+
+class Frame(ctypes.Structure):
+    _fields_ = [("depth", vp), ("opacity", vp), ("normal", vp), ("drop", vp)]
+
+
+class LossWeights(ctypes.Structure):
+    _fields_ = [("w_depth", ctypes.c_float), ("lambda_n", ctypes.c_float), ("lambda_ng", ctypes.c_float)]
+
+
+class FrameGrad(ctypes.Structure):
+    _fields_ = [("d_depth", vp), ("d_opacity", vp), ("d_normal", vp)]
+
+
+class SurfelGrads(ctypes.Structure):
+    _fields_ = [("means", vp), ("quats", vp), ("log_scales", vp), ("opacity_logits", vp)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2607_04127_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        P = ctypes.POINTER
+        L.lgsr_default_opts.argtypes = [P(RasterOpts)]
+        L.lgsr_default_opts.restype = None
+        L.lgsr_default_loss_weights.argtypes = [P(LossWeights)]
+        L.lgsr_default_loss_weights.restype = None
+        L.lgsr_create.argtypes = [P(vp), ctypes.c_int, vp]
+        L.lgsr_destroy.argtypes = [vp]
+        L.lgsr_destroy.restype = None
+        L.lgsr_set_stream.argtypes = [vp, vp]
+        L.lgsr_last_error.argtypes = [vp]
+        L.lgsr_last_error.restype = ctypes.c_char_p
+        L.lgsr_forward.argtypes = [vp, P(Surfels), vp, ctypes.c_int32, P(Beams), P(RasterOpts), P(Frame), P(vp)]
+        L.lgsr_loss.argtypes = [vp, ctypes.c_int64, P(Frame), vp, vp, P(LossWeights), vp, P(FrameGrad)]
+        L.lgsr_backward.argtypes = [vp, vp, P(FrameGrad), P(SurfelGrads), vp]
+        L.lgsr_state_free.argtypes = [vp]
+        L.lgsr_state_free.restype = None
+        L.lgsr_query.argtypes = [vp, vp, P(ctypes.c_int64)]
+        L.lgsr_sync.argtypes = [vp]
+        L.lgsr_profile.argtypes = [vp, ctypes.c_int32]
+        L.lgsr_profile_read.argtypes = [vp, P(ctypes.c_double), P(ctypes.c_int64)]
+        for name in ("lgsr_create", "lgsr_set_stream", "lgsr_forward", "lgsr_loss", "lgsr_backward", "lgsr_query",
+                     "lgsr_profile", "lgsr_profile_read", "lgsr_sync"):
+            getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def default_opts(**kw) -> RasterOpts:
+    o = RasterOpts()
+    lib().lgsr_default_opts(ctypes.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def default_loss_weights(**kw) -> LossWeights:
+    w = LossWeights()
+    lib().lgsr_default_loss_weights(ctypes.byref(w))
+    for k, v in kw.items():
+        setattr(w, k, v)
+    return w
+
+
+def _ptr(t: torch.Tensor | None):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _dev(t: torch.Tensor, name: str, shape, device, dtype=torch.float32):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if t.device != device:
+        raise ValueError(f"{name} must be on {device}, got {t.device}")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t
+
+
+class Context:
+    """Owns an lgsr_ctx on one device; calls follow torch's current stream."""
+
+    def __init__(self, device: int | torch.device = 0):
+        dev = torch.device("cuda", device) if isinstance(device, int) else torch.device(device)
+        self.device = dev
+        h = vp()
+        with torch.cuda.device(dev):
+            st = lib().lgsr_create(ctypes.byref(h), dev.index or 0, vp(torch.cuda.current_stream(dev).cuda_stream))
+        if st != LGSR_OK:
+            raise LgsrError(st, "lgsr_create failed")
+        self.handle = h
+
+    def _check(self, st: int):
+        if st != LGSR_OK:
+            raise LgsrError(st, lib().lgsr_last_error(self.handle).decode())
+
+    def _stream(self):
+        self._check(lib().lgsr_set_stream(self.handle, vp(torch.cuda.current_stream(self.device).cuda_stream)))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().lgsr_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class State:
+    def __init__(self, ctx: Context, handle, keep):
+        self.ctx, self.handle, self._keep = ctx, handle, keep
+
+    def free(self):
+        if self.handle:
+            lib().lgsr_state_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def _surfels(ctx, S):
+    n = S["means"].shape[0]
+    d = ctx.device
+    m = _dev(S["means"], "means", (n, 3), d)
+    q = _dev(S["quats"], "quats", (n, 4), d)
+    ls = _dev(S["log_scales"], "log_scales", (n, 2), d)
+    lo = _dev(S["opacity_logits"], "opacity_logits", (n,), d)
+    return Surfels(n, _ptr(m), _ptr(q), _ptr(ls), _ptr(lo)), (m, q, ls, lo)
+
+
+def lgsr_forward(ctx: Context, surfels: dict, pose: torch.Tensor, row_sincos: torch.Tensor, col_sincos: torch.Tensor,
+                 opts: RasterOpts | None = None, want_state: bool = True, out: dict | None = None):
+    """Render.  ``pose`` is a float32 (3, 4) tensor on the CPU (host) or on the context's device.
+    Returns (frame dict: depth (H,W), opacity (H,W), normal (H,W,3), drop (H,W) uint8; State or None)."""
+    d = ctx.device
+    H, W = row_sincos.shape[0], col_sincos.shape[0]
+    _dev(row_sincos, "row_sincos", (H, 2), d)
+    _dev(col_sincos, "col_sincos", (W, 2), d)
+    if pose.dtype != torch.float32 or tuple(pose.shape) != (3, 4) or not pose.is_contiguous():
+        raise ValueError("pose must be a contiguous float32 (3, 4) tensor")
+    if pose.device.type == "cpu":
+        on_dev = 0
+    elif pose.device == d:
+        on_dev = 1
+    else:
+        raise ValueError(f"pose must be on the CPU or on {d}")
+    s, keep = _surfels(ctx, surfels)
+    if out is None:
+        out = dict(depth=torch.empty((H, W), device=d), opacity=torch.empty((H, W), device=d),
+                   normal=torch.empty((H, W, 3), device=d), drop=torch.empty((H, W), device=d, dtype=torch.uint8))
+    else:
+        _dev(out["depth"], "depth", (H, W), d)
+        _dev(out["opacity"], "opacity", (H, W), d)
+        _dev(out["normal"], "normal", (H, W, 3), d)
+        _dev(out["drop"], "drop", (H, W), d, torch.uint8)
+    fr = Frame(_ptr(out["depth"]), _ptr(out["opacity"]), _ptr(out["normal"]), _ptr(out["drop"]))
+    bm = Beams(H, W, _ptr(row_sincos), _ptr(col_sincos))
+    o = opts if opts is not None else default_opts()
+    h = vp()
+    ctx._stream()
+    ctx._check(lib().lgsr_forward(ctx.handle, ctypes.byref(s), _ptr(pose), on_dev, ctypes.byref(bm), ctypes.byref(o),
+                                  ctypes.byref(fr), ctypes.byref(h) if want_state else None))
+    state = State(ctx, h, (keep, row_sincos, col_sincos, pose)) if want_state else None
+    return out, state
+
+
+def lgsr_loss(ctx: Context, frame: dict, target_depth: torch.Tensor, target_normal: torch.Tensor,
+              weights: LossWeights | None = None, loss_out: torch.Tensor | None = None, grad_out: dict | None = None):
+    """Loss (float32[5] on the device: total, depth term, normal term, |Omega_D|, |Omega_N|)
+    and dL/d(depth, opacity, normal)."""
+    d = ctx.device
+    H, W = frame["depth"].shape
+    n = H * W
+    _dev(frame["depth"], "depth", (H, W), d)
+    _dev(frame["normal"], "normal", (H, W, 3), d)
+    _dev(target_depth, "target_depth", (H, W), d)
+    _dev(target_normal, "target_normal", (H, W, 3), d)
+    if loss_out is None:
+        loss_out = torch.empty(5, device=d)
+    _dev(loss_out, "loss_out", (5,), d)
+    if grad_out is None:
+        grad_out = dict(depth=torch.empty((H, W), device=d), opacity=torch.empty((H, W), device=d),
+                        normal=torch.empty((H, W, 3), device=d))
+    fr = Frame(_ptr(frame["depth"]), _ptr(frame.get("opacity")), _ptr(frame["normal"]), None)
+    fg = FrameGrad(_ptr(grad_out["depth"]), _ptr(grad_out["opacity"]), _ptr(grad_out["normal"]))
+    w = weights if weights is not None else default_loss_weights()
+    ctx._stream()
+    ctx._check(lib().lgsr_loss(ctx.handle, n, ctypes.byref(fr), _ptr(target_depth), _ptr(target_normal),
+                               ctypes.byref(w), _ptr(loss_out), ctypes.byref(fg)))
+    return loss_out, grad_out
+
+
+def lgsr_backward(ctx: Context, state: State, grad: dict, out: dict | None = None,
+                  grad_pose: torch.Tensor | None = None):
+    """Gradients w.r.t. means (n,3), quats (n,4), log_scales (n,2), opacity_logits (n,) and the
+    pose tangent (rho, omega) (6,) of the right perturbation."""
+    d = ctx.device
+    if state is None or not state.handle:
+        raise ValueError("a live State from lgsr_forward is required")
+    H, W = grad["depth"].shape
+    _dev(grad["depth"], "d_depth", (H, W), d)
+    _dev(grad["opacity"], "d_opacity", (H, W), d)
+    _dev(grad["normal"], "d_normal", (H, W, 3), d)
+    n = state._keep[0][0].shape[0]
+    if out is None:
+        out = dict(means=torch.empty((n, 3), device=d), quats=torch.empty((n, 4), device=d),
+                   log_scales=torch.empty((n, 2), device=d), opacity_logits=torch.empty((n,), device=d))
+    if grad_pose is None:
+        grad_pose = torch.empty(6, device=d)
+    fg = FrameGrad(_ptr(grad["depth"]), _ptr(grad["opacity"]), _ptr(grad["normal"]))
+    sg = SurfelGrads(_ptr(out["means"]), _ptr(out["quats"]), _ptr(out["log_scales"]), _ptr(out["opacity_logits"]))
+    ctx._stream()
+    ctx._check(lib().lgsr_backward(ctx.handle, state.handle, ctypes.byref(fg), ctypes.byref(sg), _ptr(grad_pose)))
+    return out, grad_pose
+
+
+def lgsr_state_free(state: State):
+    state.free()
+
+
+def lgsr_query(ctx: Context, state: State) -> dict:
+    o = (ctypes.c_int64 * 8)()
+    ctx._stream()
+    ctx._check(lib().lgsr_query(ctx.handle, state.handle, o))
+    return dict(pairs=o[0], visible=o[1], workspace_bytes=o[2], max_list=o[3], ray_tests=o[4], composites=o[5],
+                rays_hit=o[6])
+
+
+def lgsr_profile(ctx: Context, enable: bool):
+    ctx._check(lib().lgsr_profile(ctx.handle, 1 if enable else 0))
+
+
+def lgsr_profile_read(ctx: Context) -> dict:
+    """{stage: (milliseconds, calls)} accumulated since the last read (waits for the stream)."""
+    ms = (ctypes.c_double * len(STAGES))()
+    calls = (ctypes.c_int64 * len(STAGES))()
+    ctx._stream()
+    ctx._check(lib().lgsr_profile_read(ctx.handle, ms, calls))
+    return {name: (ms[i], calls[i]) for i, name in enumerate(STAGES)}
+
+
+def lgsr_sync(ctx: Context):
+    ctx._check(lib().lgsr_sync(ctx.handle))

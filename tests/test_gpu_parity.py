@@ -1,0 +1,279 @@
+"""GPU parity: the gfx950 renderer, called through its C ABI, against the FP64 oracle on the
+same seeded inputs (tolerances and the tie-ray rule in tests/_gpu.py)."""
+import math
+
+import numpy as np
+import pytest
+
+import scenegen
+from oracle import ref
+from tests import _gpu as G
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2607_04127_amd import lgsr
+    c = lgsr.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def room():
+    return scenegen.make_workload("room32x256_1k")
+
+
+@pytest.fixture(scope="module")
+def block():
+    return scenegen.make_workload("block64x1024_300k")
+
+
+def _print(name, stats):
+    print(f"\n[{name}] " + " ".join(f"{k}={v}" for k, v in stats.items()), flush=True)
+
+
+def _loss_upstream(w, of, ray_ids=None, mask=None):
+    """Oracle loss gradients of the oracle frame, float32-rounded, zero on masked-out rays."""
+    td = np.asarray(w["target_depth"]).reshape(-1)
+    tn = np.asarray(w["target_normal"]).reshape(-1, 3)
+    if ray_ids is not None:
+        td, tn = td[ray_ids], tn[ray_ids]
+    _, gd, go, gn = ref.loss(of, td, tn)
+    if mask is not None:
+        gd, go, gn = gd * mask, go * mask, gn * mask[:, None]
+    return gd.astype(np.float32), go.astype(np.float32), gn.astype(np.float32)
+
+
+def _gpu_backward(ctx, dw, state, H, W, gd, go, gn, ray_ids=None):
+    from paper_2607_04127_amd import lgsr
+    full = np.zeros(H * W, np.float32), np.zeros(H * W, np.float32), np.zeros((H * W, 3), np.float32)
+    if ray_ids is None:
+        full = (gd, go, gn)
+    else:
+        full[0][ray_ids], full[1][ray_ids], full[2][ray_ids] = gd, go, gn
+    grad = dict(depth=torch.from_numpy(full[0].reshape(H, W)).cuda(),
+                opacity=torch.from_numpy(full[1].reshape(H, W)).cuda(),
+                normal=torch.from_numpy(full[2].reshape(H, W, 3)).cuda())
+    out, gp = lgsr.lgsr_backward(ctx, state, grad)
+    torch.cuda.synchronize()
+    return {k: v.cpu().numpy() for k, v in out.items()}, gp.cpu().numpy()
+
+
+def _check_grads(name, g_gpu, gp_gpu, g_ref):
+    report = {}
+    for key in G.SURF_KEYS:
+        nbad, cos, worst = G.grad_check(g_gpu[key], g_ref[key])
+        report[key] = (nbad, round(cos, 9), round(worst, 3))
+    nbad_p, cos_p, worst_p = G.grad_check(gp_gpu, g_ref["pose"], floor=0.0)
+    report["pose"] = (nbad_p, round(cos_p, 9), round(worst_p, 3))
+    _print(name, report)
+    for key, (nbad, cos, _) in report.items():
+        assert nbad == 0, (key, report[key])
+        assert cos > 0.99999, (key, report[key])
+
+
+# ------------------------------------------------------------------------------------------
+# 32 x 256 beams, 1,000 surfels (full image)
+# ------------------------------------------------------------------------------------------
+
+def test_forward_room(ctx, room):
+    dw = G.to_dev(room)
+    fr, st = G.gpu_forward(ctx, dw)
+    torch.cuda.synchronize()
+    of = G.oracle_forward(room)
+    stats = G.compare_forward(fr, of)
+    from paper_2607_04127_amd import lgsr
+    q = lgsr.lgsr_query(ctx, st)
+    stats.update(pairs=q["pairs"], visible=q["visible"], max_list=q["max_list"])
+    _print("forward room32x256_1k", stats)
+    assert stats["tie"] < 0.01 * stats["rays"]
+    st.free()
+
+
+def test_forward_is_deterministic(ctx, room):
+    dw = G.to_dev(room)
+    a, _ = G.gpu_forward(ctx, dw, want_state=False)
+    a = {k: v.clone() for k, v in a.items()}
+    b, _ = G.gpu_forward(ctx, dw, want_state=False)
+    for k in a:
+        assert torch.equal(a[k], b[k]), k
+
+
+def test_loss_kernel(ctx, room):
+    """The loss kernel on the renderer's own frame against the oracle loss of that frame."""
+    from paper_2607_04127_amd import lgsr
+    dw = G.to_dev(room)
+    fr, _ = G.gpu_forward(ctx, dw, want_state=False)
+    L, g = lgsr.lgsr_loss(ctx, fr, dw["target_depth"], dw["target_normal"])
+    torch.cuda.synchronize()
+    pred = {k: fr[k].cpu().numpy().astype(np.float64).reshape(-1, *(fr[k].shape[2:])) for k in ("depth", "opacity",
+                                                                                                "normal")}
+    L_ref, gd, go, gn = ref.loss(pred, room["target_depth"], room["target_normal"])
+    L = L.cpu().numpy().astype(np.float64)
+    np.testing.assert_allclose(L[:3], L_ref[:3], rtol=1e-5)
+    assert tuple(L[3:]) == tuple(L_ref[3:])
+    np.testing.assert_allclose(g["depth"].cpu().numpy().reshape(-1), gd, rtol=1e-6, atol=0)
+    assert np.all(g["opacity"].cpu().numpy() == 0)
+    np.testing.assert_allclose(g["normal"].cpu().numpy().reshape(-1, 3), gn, rtol=1e-4, atol=1e-9)
+
+
+def test_backward_room(ctx, room):
+    H, W = room["H"], room["W"]
+    dw = G.to_dev(room)
+    _, st = G.gpu_forward(ctx, dw)
+    of = G.oracle_forward(room)
+    mask = (~G.tie_mask(of)).astype(np.float64)
+    gd, go, gn = _loss_upstream(room, of, mask=mask)
+    # an opacity upstream as well, so the g_A path (used by the opacity BCE) is covered
+    rng = np.random.default_rng(4)
+    go = (rng.normal(size=go.shape) * 1e-4 * mask).astype(np.float32)
+    g_gpu, gp = _gpu_backward(ctx, dw, st, H, W, gd, go, gn)
+    g_ref = ref.backward(room, room["pose"], room["row_sincos"], room["col_sincos"], gd, go, gn)
+    _check_grads("backward room32x256_1k", g_gpu, gp, g_ref)
+    st.free()
+
+
+def test_end_to_end_loss_and_grad(ctx, room):
+    """forward -> loss -> backward entirely on the GPU vs the oracle's loss_and_grad."""
+    from paper_2607_04127_amd import lgsr
+    dw = G.to_dev(room)
+    fr, st = G.gpu_forward(ctx, dw)
+    L, g = lgsr.lgsr_loss(ctx, fr, dw["target_depth"], dw["target_normal"])
+    out, gp = lgsr.lgsr_backward(ctx, st, g)
+    torch.cuda.synchronize()
+    L_ref, of, g_ref = ref.loss_and_grad(room, room["pose"], room["row_sincos"], room["col_sincos"],
+                                         room["target_depth"], room["target_normal"])
+    np.testing.assert_allclose(L.cpu().numpy()[:3], L_ref[:3], rtol=1e-4)
+    for key in G.SURF_KEYS:
+        _, cos, _ = G.grad_check(out[key].cpu().numpy(), g_ref[key])
+        assert cos > 0.999, (key, cos)
+    _, cos, _ = G.grad_check(gp.cpu().numpy(), g_ref["pose"])
+    assert cos > 0.999
+    st.free()
+
+
+# ------------------------------------------------------------------------------------------
+# 64 x 1024 beams, 300,000 surfels: the benchmark configuration, sampled rays
+# ------------------------------------------------------------------------------------------
+
+def test_forward_block_sampled(ctx, block):
+    H, W = block["H"], block["W"]
+    dw = G.to_dev(block)
+    fr, st = G.gpu_forward(ctx, dw)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(2024)
+    ids = np.sort(rng.choice(H * W, size=4096, replace=False))
+    of = G.oracle_forward(block, ray_ids=ids)
+    stats = G.compare_forward(fr, of, ray_ids=ids)
+    from paper_2607_04127_amd import lgsr
+    q = lgsr.lgsr_query(ctx, st)
+    stats.update(pairs=q["pairs"], visible=q["visible"], max_list=q["max_list"], mean_K=float(of["K"].mean()))
+    _print("forward block64x1024_300k (4096 sampled rays)", stats)
+    assert stats["tie"] < 0.02 * stats["rays"]
+    st.free()
+
+
+def test_backward_block_sampled(ctx, block):
+    """Upstream gradient nonzero on 2048 sampled rays only: the renderer's full backward
+    then equals the oracle's backward restricted to those rays, for every surfel."""
+    H, W = block["H"], block["W"]
+    dw = G.to_dev(block)
+    _, st = G.gpu_forward(ctx, dw)
+    rng = np.random.default_rng(77)
+    ids = np.sort(rng.choice(H * W, size=2048, replace=False))
+    of = G.oracle_forward(block, ray_ids=ids)
+    mask = (~G.tie_mask(of)).astype(np.float64)
+    gd, go, gn = _loss_upstream(block, of, ray_ids=ids, mask=mask)
+    g_gpu, gp = _gpu_backward(ctx, dw, st, H, W, gd, go, gn, ray_ids=ids)
+    g_ref = ref.backward(block, block["pose"], block["row_sincos"], block["col_sincos"], gd, go, gn, ray_ids=ids)
+    _check_grads("backward block64x1024_300k (2048 sampled rays)", g_gpu, gp, g_ref)
+    st.free()
+
+
+# ------------------------------------------------------------------------------------------
+# edge cases
+# ------------------------------------------------------------------------------------------
+
+def _small_map(n, seed=0, scale=1.0):
+    w = scenegen.make_workload("room32x256_1k")
+    idx = np.random.default_rng(seed).choice(1000, size=n, replace=False)
+    S = {k: np.ascontiguousarray(w[k][idx]) for k in G.SURF_KEYS}
+    S["log_scales"] = (S["log_scales"] + np.float32(math.log(scale))).astype(np.float32)
+    return S, w
+
+
+def test_empty_map(ctx):
+    row, col = scenegen.beam_tables(32, 256, -15, 15)
+    w = dict(means=np.zeros((0, 3), np.float32), quats=np.zeros((0, 4), np.float32),
+             log_scales=np.zeros((0, 2), np.float32), opacity_logits=np.zeros(0, np.float32),
+             row_sincos=row, col_sincos=col, pose=np.hstack([np.eye(3), np.zeros((3, 1))]).astype(np.float32))
+    fr, st = G.gpu_forward(ctx, G.to_dev(w))
+    torch.cuda.synchronize()
+    assert torch.all(fr["depth"] == 0) and torch.all(fr["drop"] == 1)
+    g = dict(depth=torch.ones_like(fr["depth"]), opacity=torch.ones_like(fr["depth"]),
+             normal=torch.ones_like(fr["normal"]))
+    from paper_2607_04127_amd import lgsr
+    out, gp = lgsr.lgsr_backward(ctx, st, g)
+    torch.cuda.synchronize()
+    assert torch.all(gp == 0)
+    st.free()
+
+
+@pytest.mark.parametrize("H,W", [(37, 250), (1, 64), (16, 17), (70, 1030)])
+def test_ragged_grids(ctx, H, W):
+    """Image sizes that are not multiples of the 16 x 16 tile or the 8 x 8 wave sub-tile."""
+    S, w = _small_map(200, seed=H * 1000 + W, scale=3.0)
+    row, col = scenegen.beam_tables(H, W, -15, 15)
+    wl = dict(S, row_sincos=row, col_sincos=col, pose=w["pose"])
+    fr, st = G.gpu_forward(ctx, G.to_dev(wl))
+    torch.cuda.synchronize()
+    of = G.oracle_forward(wl)
+    stats = G.compare_forward(fr, of)
+    assert stats["hit"] > 0
+    st.free()
+
+
+def test_wrap_and_near_surfels(ctx):
+    """Surfels straddling azimuth 0, one near the sensor whose footprint covers every tile,
+    one nearer than `near` (dropped), a zero quaternion (dropped) and an edge-on surfel."""
+    from tests import _util as U
+    row, col = scenegen.beam_tables(32, 256, -15, 15)
+    D = scenegen.ray_dirs_f64(row, col).reshape(-1, 3)
+    cen, frames, sc, al = [], [], [], []
+    rng = np.random.default_rng(8)
+    for k in range(40):  # around azimuth 0 at various ranges and sizes
+        d = D[(k % 32) * 256 + (0 if k % 2 else 255)]
+        r = rng.uniform(3, 30)
+        cen.append(r * d)
+        frames.append(U.frame_facing(-d + rng.normal(scale=0.2, size=3), spin=rng.uniform(0, 6.28)))
+        sc.append(rng.uniform(0.02, 0.1, 2) * r)
+        al.append(rng.uniform(0.3, 0.95))
+    cen.append([0.0, 0.0, -1.0])  # 1 m below the sensor, 2 m wide: every ray in the lower half
+    frames.append(U.frame_facing([0.0, 0.0, 1.0]))
+    sc.append([2.0, 2.0])
+    al.append(0.6)
+    cen.append(0.1 * D[5000])  # nearer than 0.2 m
+    frames.append(U.frame_facing(-D[5000]))
+    sc.append([1.0, 1.0])
+    al.append(0.9)
+    cen.append(10 * D[3000])  # edge-on
+    frames.append(U.frame_facing(np.cross(D[3000], [0.0, 0.0, 1.0])))
+    sc.append([1.0, 1.0])
+    al.append(0.9)
+    S = {k: v.astype(np.float32) for k, v in U.surfels(cen, frames, sc, al).items()}
+    S["quats"][3] = 0.0  # zero quaternion: renders nothing
+    wl = dict(S, row_sincos=row, col_sincos=col, pose=np.hstack([np.eye(3), np.zeros((3, 1))]).astype(np.float32))
+    fr, st = G.gpu_forward(ctx, G.to_dev(wl))
+    torch.cuda.synchronize()
+    of = G.oracle_forward(wl)
+    stats = G.compare_forward(fr, of)
+    _print("wrap/near", stats)
+    seam = of["K"].reshape(32, 256)
+    assert seam[:, 0].sum() > 0 and seam[:, 255].sum() > 0
+    st.free()
