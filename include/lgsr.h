@@ -130,8 +130,9 @@ void lgsr_default_loss_weights(lgsr_loss_weights *w);
  * Errors: EINVAL (out == NULL), EDEVICE (no such device), ENOMEM. */
 lgsr_status lgsr_create(lgsr_ctx **out, int device, void *hip_stream);
 
-/* Wait for the context's stream, then free the context and its workspace.  States created
- * from it must be freed first.  NULL is a no-op. */
+/* Wait for the context's stream, then free the context, its workspace and every state it
+ * created (live or freed); handles of those states must not be used afterwards.  NULL is a
+ * no-op. */
 void lgsr_destroy(lgsr_ctx *ctx);
 
 /* Switch the stream later calls are issued on (NULL = null stream). */

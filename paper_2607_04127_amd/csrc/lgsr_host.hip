@@ -93,8 +93,9 @@ struct lgsr_ctx {
     // scratch
     DevBuf keys, vals, keys2, vals2, cnt, offs, hist, scan_tmp, counters, recgrad, partials, pose_partials;
     uint32_t *pinned = nullptr;  // host-pinned readback slots
-    std::vector<lgsr_state *> pool;
-    lgsr_state scratch_state;  // used when the caller asks for no state
+    std::vector<lgsr_state *> pool;  // freed states kept for reuse
+    std::vector<lgsr_state *> all;   // every state allocated by this context
+    lgsr_state scratch_state;        // used when the caller asks for no state
     int live_states = 0;
     // stage timers
     bool prof = false;
@@ -177,7 +178,10 @@ lgsr_state *take_state(lgsr_ctx *ctx)
         return s;
     }
     lgsr_state *s = new (std::nothrow) lgsr_state;
-    if (s) s->ctx = ctx;
+    if (s) {
+        s->ctx = ctx;
+        ctx->all.push_back(s);
+    }
     return s;
 }
 
@@ -299,7 +303,8 @@ void lgsr_destroy(lgsr_ctx *ctx)
     if (!ctx) return;
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
-    for (lgsr_state *s : ctx->pool) {
+    // every state, freed or not: handles of states still live become invalid here
+    for (lgsr_state *s : ctx->all) {
         free_state_buffers(s);
         delete s;
     }

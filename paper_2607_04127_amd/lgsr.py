@@ -9,6 +9,7 @@ from __future__ import annotations
 
 import ctypes
 import os
+import weakref
 
 import torch
 
@@ -147,6 +148,7 @@ class Context:
         if st != LGSR_OK:
             raise LgsrError(st, "lgsr_create failed")
         self.handle = h
+        self._states = weakref.WeakSet()
 
     def _check(self, st: int):
         if st != LGSR_OK:
@@ -157,6 +159,8 @@ class Context:
 
     def close(self):
         if getattr(self, "handle", None):
+            for st in list(self._states):  # destroying the context invalidates its states
+                st.handle = None
             lib().lgsr_destroy(self.handle)
             self.handle = None
 
@@ -170,11 +174,12 @@ class Context:
 class State:
     def __init__(self, ctx: Context, handle, keep):
         self.ctx, self.handle, self._keep = ctx, handle, keep
+        ctx._states.add(self)
 
     def free(self):
-        if self.handle:
+        if self.handle and self.ctx.handle:
             lib().lgsr_state_free(self.handle)
-            self.handle = None
+        self.handle = None
 
     def __del__(self):
         try:

@@ -4,11 +4,17 @@ ABI, run the FP64 oracle on the same inputs and compare with the stated toleranc
 Tolerances (float32 renderer against the float64 oracle):
   depth, opacity  |x - x_ref| <= 1e-5 |x_ref|
   normal          max-abs component error <= 1e-4
-  gradients       |g - g_ref| <= 1e-3 max(|g_ref|, 1e-3 rms(g_ref of that parameter))
+  gradients       per surfel, max_c |g_c - g_ref,c| <= 1e-3 max(|g_ref|_2, 3e-2 rms(g_ref of that
+                  parameter)), |.|_2 the norm of the surfel's vector for that parameter (3 for
+                  means, 4 quats, 2 log-scales, 1 opacity logit).  The absolute floor covers
+                  gradients that vanish in exact arithmetic (coplanar contributors render
+                  depth = t exactly, so moving one along the plane changes nothing) and carry
+                  float32 noise of about eps32 t |dL/ddepth| per ray.
 Tie rays -- a threshold decision within 1e-4 relative of its threshold, or two
-consecutive contributors whose centre ranges differ by less than 2e-6 relative, where a
-float32 evaluation may legitimately decide differently -- are excluded from value parity
-and reported; their upstream gradient is zeroed on both sides in gradient parity.
+consecutive contributors whose centre ranges differ by less than 5e-7 relative (about four
+float32 rounding errors of the range, which decides the compositing order), where a float32
+evaluation may legitimately decide differently -- are excluded from value parity and
+reported; their upstream gradient is zeroed on both sides in gradient parity.
 """
 from __future__ import annotations
 
@@ -18,7 +24,7 @@ import torch
 from oracle import ref
 
 TIE_MARGIN = 1e-4
-TIE_ORDER = 2e-6
+TIE_ORDER = 5e-7
 SURF_KEYS = ("means", "quats", "log_scales", "opacity_logits")
 
 
@@ -67,6 +73,7 @@ def compare_forward(fr, of, ray_ids=None, rel=1e-5, natol=1e-4):
     e_a = np.abs(opa[m] - of["opacity"][m]) / np.abs(of["opacity"][m])
     e_n = np.abs(nrm[m] - of["normal"][m]).max(axis=1) if m.any() else np.zeros(0)
     stats = dict(rays=int(dep.shape[0]), hit=int(hit.sum()), tie=int(tie.sum()),
+                 tie_threshold=int((of["margin"] < TIE_MARGIN).sum()), tie_order=int((of["order_gap"] < TIE_ORDER).sum()),
                  max_rel_depth=float(e_d.max(initial=0)), max_rel_opacity=float(e_a.max(initial=0)),
                  max_abs_normal=float(e_n.max(initial=0)))
     bad_d, bad_a, bad_n = (e_d > rel).sum(), (e_a > rel).sum(), (e_n > natol).sum()
@@ -76,12 +83,17 @@ def compare_forward(fr, of, ray_ids=None, rel=1e-5, natol=1e-4):
     return stats
 
 
-def grad_check(g, g_ref, rel=1e-3, floor=1e-3):
-    g = np.asarray(g, np.float64).reshape(-1)
-    g_ref = np.asarray(g_ref, np.float64).reshape(-1)
+def grad_check(g, g_ref, rel=1e-3, floor=3e-2, per_row=True):
+    """(failures, cosine, worst error / bound).  per_row: rows of a 2-D array are one
+    surfel's vector; otherwise every element is judged on its own."""
+    g = np.asarray(g, np.float64)
+    g_ref = np.asarray(g_ref, np.float64)
+    if not per_row or g_ref.ndim == 1:
+        g, g_ref = g.reshape(-1, 1), g_ref.reshape(-1, 1)
     rms = float(np.sqrt(np.mean(g_ref ** 2))) if g_ref.size else 0.0
-    err = np.abs(g - g_ref)
-    bound = rel * np.maximum(np.abs(g_ref), floor * rms)
+    err = np.abs(g - g_ref).max(axis=1)
+    bound = rel * np.maximum(np.linalg.norm(g_ref, axis=1), floor * rms)
     bad = err > bound + 1e-30
-    cos = float(g @ g_ref / (np.linalg.norm(g) * np.linalg.norm(g_ref) + 1e-300))
+    gf, rf = g.reshape(-1), g_ref.reshape(-1)
+    cos = float(gf @ rf / (np.linalg.norm(gf) * np.linalg.norm(rf) + 1e-300))
     return int(bad.sum()), cos, float((err / np.maximum(bound, 1e-300)).max(initial=0))

@@ -70,7 +70,7 @@ def _check_grads(name, g_gpu, gp_gpu, g_ref):
     for key in G.SURF_KEYS:
         nbad, cos, worst = G.grad_check(g_gpu[key], g_ref[key])
         report[key] = (nbad, round(cos, 9), round(worst, 3))
-    nbad_p, cos_p, worst_p = G.grad_check(gp_gpu, g_ref["pose"], floor=0.0)
+    nbad_p, cos_p, worst_p = G.grad_check(gp_gpu, g_ref["pose"], floor=0.0, per_row=False)
     report["pose"] = (nbad_p, round(cos_p, 9), round(worst_p, 3))
     _print(name, report)
     for key, (nbad, cos, _) in report.items():
@@ -140,15 +140,21 @@ def test_backward_room(ctx, room):
 
 
 def test_end_to_end_loss_and_grad(ctx, room):
-    """forward -> loss -> backward entirely on the GPU vs the oracle's loss_and_grad."""
+    """forward -> loss -> backward entirely on the GPU vs the oracle's loss_and_grad.  The
+    surfels sit on the raycast surfaces, so many rendered depths equal their targets
+    exactly, at the corner of |x| where the sign is arbitrary; targets are moved off it."""
     from paper_2607_04127_amd import lgsr
-    dw = G.to_dev(room)
+    rng = np.random.default_rng(12)
+    td = room["target_depth"]
+    td = np.where(td > 0, td + rng.choice([-1, 1], td.shape) * rng.uniform(0.05, 0.3, td.shape), 0).astype(np.float32)
+    w = dict(room, target_depth=td)
+    dw = G.to_dev(w)
     fr, st = G.gpu_forward(ctx, dw)
     L, g = lgsr.lgsr_loss(ctx, fr, dw["target_depth"], dw["target_normal"])
     out, gp = lgsr.lgsr_backward(ctx, st, g)
     torch.cuda.synchronize()
-    L_ref, of, g_ref = ref.loss_and_grad(room, room["pose"], room["row_sincos"], room["col_sincos"],
-                                         room["target_depth"], room["target_normal"])
+    L_ref, of, g_ref = ref.loss_and_grad(w, w["pose"], w["row_sincos"], w["col_sincos"], w["target_depth"],
+                                         w["target_normal"])
     np.testing.assert_allclose(L.cpu().numpy()[:3], L_ref[:3], rtol=1e-4)
     for key in G.SURF_KEYS:
         _, cos, _ = G.grad_check(out[key].cpu().numpy(), g_ref[key])
