@@ -89,6 +89,8 @@ typedef struct {
     float near;         /* centres nearer than this are dropped; hits at t < near skipped (0.2) */
     float den_eps;      /* |n . d| < den_eps: ray parallel to the surfel, skipped (1e-6)        */
     float drop_tau;     /* rendered drop = [A < drop_tau]                      (default 0.5)    */
+    int32_t chunk;      /* list entries per parallel chunk; 0 = chosen from the pair count, else
+                           16..65536.  Results do not depend on it beyond float32 rounding.     */
     int32_t flags;      /* reserved, must be 0 */
 } lgsr_raster_opts;
 
@@ -189,10 +191,12 @@ void lgsr_state_free(lgsr_state *state);
  *   out[6] rays with at least one hit      out[7] reserved (0). */
 lgsr_status lgsr_query(lgsr_ctx *ctx, const lgsr_state *state, int64_t out[8]);
 
-/* Stage timers.  While enabled, every stage below is bracketed by HIP events on the
- * context's stream (a stage may span several kernel launches); lgsr_profile_read waits for
- * the stream, adds up the elapsed times per stage since the last read (HOST double[12],
- * milliseconds) and the number of times each stage ran (HOST int64[12]), then resets them. */
+/* Stage timers.  lgsr_profile selects stages by bit mask (bit k = stage k, 0 = off, -1 =
+ * all); each selected stage is then bracketed by HIP events on the context's stream (a
+ * stage may span several kernel launches; every event costs a little stream time).
+ * lgsr_profile_read waits for the stream, adds up the elapsed times per stage since the
+ * last read (HOST double[12], milliseconds) and the number of times each stage ran (HOST
+ * int64[12]), then resets them. */
 enum {
     LGSR_STAGE_PROJECT = 0,    /* projection, records, rectangles, tile counts */
     LGSR_STAGE_DEPTH_SORT = 1, /* surfels by (range, index) */
@@ -200,15 +204,15 @@ enum {
     LGSR_STAGE_EMIT = 3,       /* (tile, surfel) pairs */
     LGSR_STAGE_TILE_SORT = 4,  /* pairs by tile */
     LGSR_STAGE_RANGES = 5,     /* per-tile list bounds */
-    LGSR_STAGE_RASTER_FWD = 6, /* forward compositing */
+    LGSR_STAGE_RASTER_FWD = 6, /* forward compositing: chunk list, chunks, merge, fix-up */
     LGSR_STAGE_LOSS = 7,       /* loss and its per-ray gradient */
-    LGSR_STAGE_BWD_ZERO = 8,   /* clearing the record gradients */
+    LGSR_STAGE_BWD_PREP = 8,   /* clearing the record gradients, per-ray backward set-up */
     LGSR_STAGE_RASTER_BWD = 9, /* backward compositing */
     LGSR_STAGE_CHAIN = 10,     /* parameter and pose gradients */
     LGSR_STAGE_READBACK = 11,  /* the one device-to-host read of the pair count */
     LGSR_NUM_STAGES = 12
 };
-lgsr_status lgsr_profile(lgsr_ctx *ctx, int32_t enable);
+lgsr_status lgsr_profile(lgsr_ctx *ctx, int32_t stage_mask);
 lgsr_status lgsr_profile_read(lgsr_ctx *ctx, double ms[12], int64_t calls[12]);
 
 /* Wait for all work issued on the context's stream; reports an earlier kernel fault. */

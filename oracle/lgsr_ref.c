@@ -334,11 +334,56 @@ static void atomic_add(double *x, double v)
     *x += v;
 }
 
+/* Chain rule from sensor-frame gradients g of one surfel to its raw parameters and to the
+ * pose tangent (rho, omega) of the right perturbation (R6, R7):
+ *   mu' = R_p^T (mu - t_p), a' = R_p^T a, ...: world gradient = R_p times sensor gradient;
+ *   (a, b, n) = columns of R(qhat); q -> qhat = q / |q|; s = exp(s~); alpha = sigmoid(o);
+ *   mu' -> mu' - rho + mu' x omega, a' -> a' + a' x omega, ... to first order. */
+static void chain_params(const surf_t *s, const double *pose, const sgrad_t *g, double *dm, double *dq,
+                         double *dl, double *dlog, double *dpose)
+{
+    double Ga[3], Gb[3], Gn[3];
+    sensor_to_world_dir(pose, g->mu, dm);
+    sensor_to_world_dir(pose, g->a, Ga);
+    sensor_to_world_dir(pose, g->b, Gb);
+    sensor_to_world_dir(pose, g->n, Gn);
+    double w = s->qhat[0], x = s->qhat[1], y = s->qhat[2], z = s->qhat[3];
+    double dw = Ga[1] * 2 * z - Ga[2] * 2 * y - Gb[0] * 2 * z + Gb[2] * 2 * x + Gn[0] * 2 * y - Gn[1] * 2 * x;
+    double dx = Ga[1] * 2 * y + Ga[2] * 2 * z + Gb[0] * 2 * y - Gb[1] * 4 * x + Gb[2] * 2 * w
+              + Gn[0] * 2 * z - Gn[1] * 2 * w - Gn[2] * 4 * x;
+    double dy = -Ga[0] * 4 * y + Ga[1] * 2 * x - Ga[2] * 2 * w + Gb[0] * 2 * x + Gb[2] * 2 * z
+              + Gn[0] * 2 * w + Gn[1] * 2 * z - Gn[2] * 4 * y;
+    double dz = -Ga[0] * 4 * z + Ga[1] * 2 * w + Ga[2] * 2 * x - Gb[0] * 2 * w - Gb[1] * 4 * z
+              + Gb[2] * 2 * y + Gn[0] * 2 * x + Gn[1] * 2 * y;
+    double dqh[4] = {dw, dx, dy, dz};
+    double radial = dqh[0] * s->qhat[0] + dqh[1] * s->qhat[1] + dqh[2] * s->qhat[2] + dqh[3] * s->qhat[3];
+    for (int c = 0; c < 4; ++c) dq[c] = (dqh[c] - radial * s->qhat[c]) / s->qnorm;
+    dl[0] = s->s0 * g->s0;
+    dl[1] = s->s1 * g->s1;
+    *dlog = s->alpha * (1 - s->alpha) * g->alpha;
+    double c1[3], c2[3], c3[3], c4[3];
+    cross3(s->mu, g->mu, c1);
+    cross3(s->a, g->a, c2);
+    cross3(s->b, g->b, c3);
+    cross3(s->n, g->n, c4);
+    for (int c = 0; c < 3; ++c) {
+        dpose[c] = -g->mu[c];
+        dpose[3 + c] = -(c1[c] + c2[c] + c3[c] + c4[c]);
+    }
+}
+
+static double norm_n(const double *v, int n)
+{
+    double q = 0;
+    for (int c = 0; c < n; ++c) q += v[c] * v[c];
+    return sqrt(q);
+}
+
 int lgsr_ref_backward(const lgsr_ref_map *map, const double pose[12], const lgsr_ref_beams *beams,
                       const lgsr_ref_params *prm, int64_t n_rays, const int64_t *ray_ids,
                       const double *g_depth, const double *g_opacity, const double *g_normal,
                       double *d_means, double *d_quats, double *d_log_scales,
-                      double *d_opacity_logits, double d_pose[6])
+                      double *d_opacity_logits, double d_pose[6], double *mass, double *pose_mass)
 {
     if (check_args(map, pose, beams, prm, n_rays, ray_ids)) return -1;
     if (n_rays > 0 && (!g_depth || !g_opacity || !g_normal)) return -1;
@@ -350,6 +395,10 @@ int lgsr_ref_backward(const lgsr_ref_map *map, const double pose[12], const lgsr
     int64_t *order = (int64_t *)malloc(sizeof(int64_t) * nn);
     sgrad_t *Gs = (sgrad_t *)calloc(nn, sizeof(sgrad_t));
     if (!S || !order || !Gs) { free(S); free(order); free(Gs); return -1; }
+    if (mass)
+        for (int64_t i = 0; i < 4 * n; ++i) mass[i] = 0;
+    if (pose_mass)
+        for (int c = 0; c < 6; ++c) pose_mass[c] = 0;
     setup_surfels(map, pose, prm, S);
     int64_t m = sort_surfels(S, n, order);
 
@@ -409,6 +458,26 @@ int lgsr_ref_backward(const lgsr_ref_map *map, const double pose[12], const lgsr
                 atomic_add(&g->s0, -d_u * h->u / s->s0);
                 atomic_add(&g->s1, -d_v * h->v / s->s1);
                 atomic_add(&g->alpha, d_alpha);
+                if (mass || pose_mass) {
+                    /* size of this one contribution in parameter space (test tolerances) */
+                    sgrad_t one;
+                    for (int c = 0; c < 3; ++c) {
+                        one.mu[c] = g_mu[c]; one.a[c] = g_a[c]; one.b[c] = g_b[c]; one.n[c] = g_n[c];
+                    }
+                    one.s0 = -d_u * h->u / s->s0;
+                    one.s1 = -d_v * h->v / s->s1;
+                    one.alpha = d_alpha;
+                    double dm[3], dq[4], dl[2], dlog, dp[6];
+                    chain_params(s, pose, &one, dm, dq, dl, &dlog, dp);
+                    if (mass) {
+                        atomic_add(&mass[4 * h->i + 0], norm_n(dm, 3));
+                        atomic_add(&mass[4 * h->i + 1], norm_n(dq, 4));
+                        atomic_add(&mass[4 * h->i + 2], norm_n(dl, 2));
+                        atomic_add(&mass[4 * h->i + 3], fabs(dlog));
+                    }
+                    if (pose_mass)
+                        for (int c = 0; c < 6; ++c) atomic_add(&pose_mass[c], fabs(dp[c]));
+                }
             }
         }
         free(hits);
@@ -418,7 +487,6 @@ int lgsr_ref_backward(const lgsr_ref_map *map, const double pose[12], const lgsr
     double pr[3] = {0, 0, 0}, pw[3] = {0, 0, 0};
     for (int64_t i = 0; i < n; ++i) {
         const surf_t *s = &S[i];
-        const sgrad_t *g = &Gs[i];
         double *dm = d_means + 3 * i, *dq = d_quats + 4 * i, *dl = d_log_scales + 2 * i;
         if (!s->valid) {
             dm[0] = dm[1] = dm[2] = 0;
@@ -427,36 +495,11 @@ int lgsr_ref_backward(const lgsr_ref_map *map, const double pose[12], const lgsr
             d_opacity_logits[i] = 0;
             continue;
         }
-        /* mu' = R_p^T (mu - t_p), a' = R_p^T a, ...: world gradient = R_p times sensor gradient */
-        double Ga[3], Gb[3], Gn[3];
-        sensor_to_world_dir(pose, g->mu, dm);
-        sensor_to_world_dir(pose, g->a, Ga);
-        sensor_to_world_dir(pose, g->b, Gb);
-        sensor_to_world_dir(pose, g->n, Gn);
-        /* (a, b, n) = columns of R(qhat): d/dqhat, then project out the radial part of q */
-        double w = s->qhat[0], x = s->qhat[1], y = s->qhat[2], z = s->qhat[3];
-        double dw = Ga[1] * 2 * z - Ga[2] * 2 * y - Gb[0] * 2 * z + Gb[2] * 2 * x + Gn[0] * 2 * y - Gn[1] * 2 * x;
-        double dx = Ga[1] * 2 * y + Ga[2] * 2 * z + Gb[0] * 2 * y - Gb[1] * 4 * x + Gb[2] * 2 * w
-                  + Gn[0] * 2 * z - Gn[1] * 2 * w - Gn[2] * 4 * x;
-        double dy = -Ga[0] * 4 * y + Ga[1] * 2 * x - Ga[2] * 2 * w + Gb[0] * 2 * x + Gb[2] * 2 * z
-                  + Gn[0] * 2 * w + Gn[1] * 2 * z - Gn[2] * 4 * y;
-        double dz = -Ga[0] * 4 * z + Ga[1] * 2 * w + Ga[2] * 2 * x - Gb[0] * 2 * w - Gb[1] * 4 * z
-                  + Gb[2] * 2 * y + Gn[0] * 2 * x + Gn[1] * 2 * y;
-        double dqh[4] = {dw, dx, dy, dz};
-        double radial = dqh[0] * s->qhat[0] + dqh[1] * s->qhat[1] + dqh[2] * s->qhat[2] + dqh[3] * s->qhat[3];
-        for (int c = 0; c < 4; ++c) dq[c] = (dqh[c] - radial * s->qhat[c]) / s->qnorm;
-        dl[0] = s->s0 * g->s0;
-        dl[1] = s->s1 * g->s1;
-        d_opacity_logits[i] = s->alpha * (1 - s->alpha) * g->alpha;
-        /* right perturbation: mu' -> mu' - rho + mu' x omega, a' -> a' + a' x omega, ... */
-        double c1[3], c2[3], c3[3], c4[3];
-        cross3(s->mu, g->mu, c1);
-        cross3(s->a, g->a, c2);
-        cross3(s->b, g->b, c3);
-        cross3(s->n, g->n, c4);
+        double dp[6];
+        chain_params(s, pose, &Gs[i], dm, dq, dl, &d_opacity_logits[i], dp);
         for (int c = 0; c < 3; ++c) {
-            pr[c] -= g->mu[c];
-            pw[c] -= c1[c] + c2[c] + c3[c] + c4[c];
+            pr[c] += dp[c];
+            pw[c] += dp[3 + c];
         }
     }
     for (int c = 0; c < 3; ++c) { d_pose[c] = pr[c]; d_pose[3 + c] = pw[c]; }

@@ -49,7 +49,7 @@ def lib():
         L.lgsr_ref_loss.argtypes = [i64, vp, vp, vp, vp, vp, vp, ctypes.c_double, ctypes.c_double,
                                     ctypes.c_double, vp, vp, vp, vp]
         L.lgsr_ref_loss.restype = ctypes.c_int
-        L.lgsr_ref_backward.argtypes = [vp, vp, vp, vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.lgsr_ref_backward.argtypes = [vp, vp, vp, vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
         L.lgsr_ref_backward.restype = ctypes.c_int
         L.lgsr_ref_threads.restype = ctypes.c_int
         _lib = L
@@ -146,9 +146,11 @@ def loss(pred, target_depth, target_normal, weights=None, ray_weight=None):
 
 
 def backward(surfels, pose, row_sincos, col_sincos, g_depth, g_opacity, g_normal, prm=None,
-             ray_ids=None):
+             ray_ids=None, with_mass=False):
     """Gradients of sum(g . rendered) w.r.t. means, quats, log_scales, opacity_logits and the
-    pose tangent (rho, omega) of the right perturbation."""
+    pose tangent (rho, omega) of the right perturbation.  With ``with_mass`` also ``mass``
+    (n, 4): per surfel the sum over rays of the norm of each ray's contribution to the
+    means / quats / log_scales / opacity_logit gradient, and ``pose_mass`` (6,)."""
     inp = _Inputs(surfels, pose, row_sincos, col_sincos, prm)
     n_rays, ids = _rays(inp, ray_ids)
     gd = _f64(g_depth).reshape(-1)
@@ -158,10 +160,14 @@ def backward(surfels, pose, row_sincos, col_sincos, g_depth, g_opacity, g_normal
     n = inp.n
     out = dict(means=np.zeros((n, 3)), quats=np.zeros((n, 4)), log_scales=np.zeros((n, 2)),
                opacity_logits=np.zeros(n), pose=np.zeros(6))
+    if with_mass:
+        out["mass"] = np.zeros((n, 4))
+        out["pose_mass"] = np.zeros(6)
     rc = lib().lgsr_ref_backward(ctypes.byref(inp.map), _ptr(inp.pose), ctypes.byref(inp.beams),
                                  ctypes.byref(inp.prm), n_rays, _ptr(ids), _ptr(gd), _ptr(go), _ptr(gn),
                                  _ptr(out["means"]), _ptr(out["quats"]), _ptr(out["log_scales"]),
-                                 _ptr(out["opacity_logits"]), _ptr(out["pose"]))
+                                 _ptr(out["opacity_logits"]), _ptr(out["pose"]), _ptr(out.get("mass")),
+                                 _ptr(out.get("pose_mass")))
     if rc != 0:
         raise ValueError("lgsr_ref_backward rejected its arguments")
     return out

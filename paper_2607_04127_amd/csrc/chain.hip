@@ -131,18 +131,33 @@ __global__ __launch_bounds__(kChainThreads) void chain_kernel(SurfelPtrs S, cons
     }
 }
 
-__global__ void pose_finalize(int nb, const float *__restrict__ partials, float *__restrict__ grad_pose)
+// 6 x 256 threads: thread (c, t) sums partials t, t + 256, ... of component c with
+// Neumaier compensation; the 256 (sum, compensation) pairs are then folded in a fixed tree.
+__global__ __launch_bounds__(256) void pose_finalize(int nb, const float *__restrict__ partials,
+                                                     float *__restrict__ grad_pose)
 {
-    int c = threadIdx.x;
-    if (c >= 6) return;
-    float s = 0.f, comp = 0.f;  // Kahan-Babuska (Neumaier) summation
-    for (int b = 0; b < nb; ++b) {
-        float x = partials[(size_t)b * 6 + c];
-        float t = s + x;
-        comp += fabsf(s) >= fabsf(x) ? (s - t) + x : (x - t) + s;
-        s = t;
+    __shared__ float ss[256], cc[256];
+    const int c = blockIdx.x, t = threadIdx.x;
+    float s = 0.f, comp = 0.f;
+    for (int b = t; b < nb; b += 256) {
+        const float x = partials[(size_t)b * 6 + c];
+        const float y = s + x;
+        comp += fabsf(s) >= fabsf(x) ? (s - y) + x : (x - y) + s;
+        s = y;
     }
-    grad_pose[c] = s + comp;
+    ss[t] = s;
+    cc[t] = comp;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (t < o) {
+            const float a = ss[t], x = ss[t + o];
+            const float y = a + x;
+            cc[t] += cc[t + o] + (fabsf(a) >= fabsf(x) ? (a - y) + x : (x - y) + a);
+            ss[t] = y;
+        }
+        __syncthreads();
+    }
+    if (t == 0) grad_pose[c] = ss[0] + cc[0];
 }
 
 int chain_blocks(int64_t n) { return n > 0 ? (int)((n + kChainThreads - 1) / kChainThreads) : 1; }
@@ -154,7 +169,7 @@ hipError_t launch_chain(const SurfelPtrs &S, const float *pose_dev, const Raster
     int nb = chain_blocks(S.n);
     chain_kernel<<<nb, kChainThreads, 0, s>>>(S, pose_dev, p, recgrad, d_means, d_quats, d_log_scales, d_logits,
                                              pose_partials);
-    pose_finalize<<<1, 64, 0, s>>>(nb, pose_partials, grad_pose);
+    pose_finalize<<<6, 256, 0, s>>>(nb, pose_partials, grad_pose);
     return hipGetLastError();
 }
 

@@ -75,15 +75,15 @@ struct lgsr_state {
     lgsr_ctx *ctx = nullptr;
     bool live = false;
     // forward products kept for the backward
-    DevBuf recs, rects, pk, pv, pk2, pv2, ranges, st0, st1, pose;
+    DevBuf recs, rects, pk, pv, pk2, pv2, ranges, st0, st1, pose, chunks, chunk_base, slots, fixA, fixB;
     uint32_t *ids = nullptr;        // sorted pair surfel ids (pv or pv2)
     uint32_t *tile_keys = nullptr;  // sorted pair tile ids (pk or pk2)
     SurfelPtrs S{};
     const float *rows = nullptr, *cols = nullptr;
     Grid g{};
     RasterParams prm{};
+    RasterBufs R{};
     int64_t P = 0;
-    uint32_t n_visible = 0;  // filled by lgsr_query
 };
 
 struct lgsr_ctx {
@@ -91,14 +91,14 @@ struct lgsr_ctx {
     hipStream_t stream = nullptr;
     std::string err;
     // scratch
-    DevBuf keys, vals, keys2, vals2, cnt, offs, hist, scan_tmp, counters, recgrad, partials, pose_partials;
+    DevBuf keys, vals, keys2, vals2, cnt, offs, hist, scan_tmp, counters, recgrad, partials, pose_partials, gb0, gb1;
     uint32_t *pinned = nullptr;  // host-pinned readback slots
     std::vector<lgsr_state *> pool;  // freed states kept for reuse
     std::vector<lgsr_state *> all;   // every state allocated by this context
     lgsr_state scratch_state;        // used when the caller asks for no state
     int live_states = 0;
     // stage timers
-    bool prof = false;
+    uint32_t prof_mask = 0;  // bit k: time stage k
     std::vector<hipEvent_t> ev_free;
     std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_pending;
     double prof_ms[LGSR_NUM_STAGES] = {};
@@ -145,6 +145,8 @@ lgsr_status check_opts(lgsr_ctx *ctx, const lgsr_raster_opts *o)
     if (!finite_pos(o->near)) return fail(ctx, LGSR_EINVAL, "near must be finite and > 0");
     if (!std::isfinite(o->den_eps) || o->den_eps < 0.f) return fail(ctx, LGSR_EINVAL, "den_eps must be >= 0");
     if (!std::isfinite(o->drop_tau)) return fail(ctx, LGSR_EINVAL, "drop_tau must be finite");
+    if (o->chunk != 0 && (o->chunk < 16 || o->chunk > 65536))
+        return fail(ctx, LGSR_EINVAL, "chunk must be 0 or lie in [16, 65536]");
     if (o->flags != 0) return fail(ctx, LGSR_EINVAL, "flags must be 0");
     return LGSR_OK;
 }
@@ -189,6 +191,7 @@ void free_state_buffers(lgsr_state *s)
 {
     release(s->recs); release(s->rects); release(s->pk); release(s->pv); release(s->pk2); release(s->pv2);
     release(s->ranges); release(s->st0); release(s->st1); release(s->pose);
+    release(s->chunks); release(s->chunk_base); release(s->slots); release(s->fixA); release(s->fixB);
 }
 
 hipEvent_t take_event(lgsr_ctx *ctx)
@@ -213,7 +216,7 @@ struct Stage {
     hipEvent_t a = nullptr;
     Stage(lgsr_ctx *c, int stage) : ctx(c), id(stage)
     {
-        if (!ctx->prof) return;
+        if (!((ctx->prof_mask >> id) & 1u)) return;
         a = take_event(ctx);
         if (a) (void)hipEventRecord(a, ctx->stream);
     }
@@ -233,13 +236,15 @@ struct Stage {
 size_t state_bytes(const lgsr_state *s)
 {
     return s->recs.cap + s->rects.cap + s->pk.cap + s->pv.cap + s->pk2.cap + s->pv2.cap + s->ranges.cap +
-           s->st0.cap + s->st1.cap + s->pose.cap;
+           s->st0.cap + s->st1.cap + s->pose.cap + s->chunks.cap + s->chunk_base.cap + s->slots.cap + s->fixA.cap +
+           s->fixB.cap;
 }
 
 size_t ctx_bytes(const lgsr_ctx *c)
 {
     return c->keys.cap + c->vals.cap + c->keys2.cap + c->vals2.cap + c->cnt.cap + c->offs.cap + c->hist.cap +
-           c->scan_tmp.cap + c->counters.cap + c->recgrad.cap + c->partials.cap + c->pose_partials.cap +
+           c->scan_tmp.cap + c->counters.cap + c->recgrad.cap + c->partials.cap + c->pose_partials.cap + c->gb0.cap +
+           c->gb1.cap +
            state_bytes(&c->scratch_state);
 }
 
@@ -257,6 +262,7 @@ void lgsr_default_opts(lgsr_raster_opts *o)
     o->near = 0.2f;
     o->den_eps = 1e-6f;
     o->drop_tau = 0.5f;
+    o->chunk = 0;
     o->flags = 0;
 }
 
@@ -310,7 +316,8 @@ void lgsr_destroy(lgsr_ctx *ctx)
     }
     free_state_buffers(&ctx->scratch_state);
     DevBuf *bufs[] = {&ctx->keys, &ctx->vals, &ctx->keys2, &ctx->vals2, &ctx->cnt, &ctx->offs, &ctx->hist,
-                      &ctx->scan_tmp, &ctx->counters, &ctx->recgrad, &ctx->partials, &ctx->pose_partials};
+                      &ctx->scan_tmp, &ctx->counters, &ctx->recgrad, &ctx->partials, &ctx->pose_partials,
+                      &ctx->gb0, &ctx->gb1};
     for (DevBuf *b : bufs) release(*b);
     for (auto &pe : ctx->ev_pending) {
         (void)hipEventDestroy(pe.second.first);
@@ -424,14 +431,12 @@ lgsr_status lgsr_forward(lgsr_ctx *ctx, const lgsr_surfels *surfels, const float
         HIP_TRY(scan_u32(as<uint32_t>(ctx->cnt), sorted_ids, as<uint32_t>(ctx->offs), counters, n,
                          as<uint32_t>(ctx->scan_tmp), s),
                 "count scan");
-        HIP_TRY(launch_count_visible(as<uint32_t>(ctx->cnt), n, counters + 2, s), "count visible");
         }
         Stage st_(ctx, LGSR_STAGE_READBACK);
-        HIP_TRY(hipMemcpyAsync(ctx->pinned, counters, 3 * sizeof(uint32_t), hipMemcpyDeviceToHost, s), "readback");
+        HIP_TRY(hipMemcpyAsync(ctx->pinned, counters, sizeof(uint32_t), hipMemcpyDeviceToHost, s), "readback");
         HIP_TRY(hipStreamSynchronize(s), "readback sync");
         P = (int64_t)ctx->pinned[0];
     }
-    const uint32_t n_visible = n > 0 ? ctx->pinned[2] : 0u;
     // the scan is 32-bit: the count must stay below 2^31 (lists are addressed as int)
     if (P < 0 || P > (int64_t)0x7FFFFFFF) return fail(ctx, LGSR_ECAPACITY, "too many (surfel, tile) pairs");
     const size_t pp = (size_t)(P > 0 ? P : 1);
@@ -469,11 +474,33 @@ lgsr_status lgsr_forward(lgsr_ctx *ctx, const lgsr_surfels *surfels, const float
     HIP_TRY(launch_ranges(tile_keys, P, g.T, as<uint2>(S->ranges), s), "ranges");
     }
     {
+    const int seg = chunk_size(P, opts->chunk);
+    const int64_t items_max = chunk_items_max(P, g.T, seg);
+    if (items_max > 0x7FFFFFFF) return fail(ctx, LGSR_ECAPACITY, "too many list chunks");
+    HIP_TRY(ensure(S->chunks, (size_t)(items_max > 0 ? items_max : 1) * sizeof(uint4)), "alloc chunks");
+    HIP_TRY(ensure(S->chunk_base, (size_t)(g.T + 1) * sizeof(uint32_t)), "alloc chunks");
+    HIP_TRY(ensure(S->slots, chunk_slot_floats(items_max > 0 ? items_max : 1) * sizeof(float)), "alloc slots");
+    HIP_TRY(ensure(S->fixA, (size_t)rays * sizeof(float4)), "alloc ray state");
+    HIP_TRY(ensure(S->fixB, (size_t)rays * sizeof(float4)), "alloc ray state");
+    RasterBufs &R = S->R;
+    R.ids = S->ids;
+    R.recs = as<float>(S->recs);
+    R.rects = as<uint2>(S->rects);
+    R.ranges = as<uint2>(S->ranges);
+    R.rows = beams->row_sincos;
+    R.cols = beams->col_sincos;
+    R.chunks = as<uint4>(S->chunks);
+    R.chunk_base = as<uint32_t>(S->chunk_base);
+    R.n_items = as<uint32_t>(S->pose) + 12;
+    R.slots = as<float>(S->slots);
+    R.st0 = as<float4>(S->st0);
+    R.st1 = as<float4>(S->st1);
+    R.fixA = as<float4>(S->fixA);
+    R.fixB = as<float4>(S->fixB);
+    R.seg = seg;
+    R.items_max = items_max;
     Stage st_(ctx, LGSR_STAGE_RASTER_FWD);
-    HIP_TRY(launch_raster_fwd(S->ids, as<uint2>(S->ranges), as<float>(S->recs), as<uint2>(S->rects),
-                              beams->row_sincos, beams->col_sincos, g, prm, out->depth, out->opacity, out->normal,
-                              out->drop, as<float4>(S->st0), as<float4>(S->st1), s),
-            "raster forward");
+    HIP_TRY(launch_raster_fwd(R, g, prm, out->depth, out->opacity, out->normal, out->drop, s), "raster forward");
     }
     S->tile_keys = const_cast<uint32_t *>(tile_keys);
     S->S = SP;
@@ -482,7 +509,6 @@ lgsr_status lgsr_forward(lgsr_ctx *ctx, const lgsr_surfels *surfels, const float
     S->g = g;
     S->prm = prm;
     S->P = P;
-    S->n_visible = n_visible;
     if (state) {
         S->live = true;
         ctx->live_states++;
@@ -535,15 +561,20 @@ lgsr_status lgsr_backward(lgsr_ctx *ctx, lgsr_state *S, const lgsr_frame_grad *g
     const size_t nn = (size_t)(S->S.n > 0 ? S->S.n : 1);
     HIP_TRY(ensure(ctx->recgrad, nn * kGrad * sizeof(float)), "alloc record gradients");
     HIP_TRY(ensure(ctx->pose_partials, (size_t)chain_blocks(S->S.n) * 6 * sizeof(float)), "alloc pose partials");
+    const int64_t rays = (int64_t)S->g.H * S->g.W;
+    HIP_TRY(ensure(ctx->gb0, (size_t)rays * sizeof(float4)), "alloc backward state");
+    HIP_TRY(ensure(ctx->gb1, (size_t)rays * sizeof(float)), "alloc backward state");
     {
-    Stage st_(ctx, LGSR_STAGE_BWD_ZERO);
+    Stage st_(ctx, LGSR_STAGE_BWD_PREP);
     HIP_TRY(launch_fill_u32(as<uint32_t>(ctx->recgrad), 0u, (int64_t)nn * kGrad, s), "zero record gradients");
+    HIP_TRY(launch_raster_bwd_prep(S->R, S->g, gin->d_depth, gin->d_opacity, gin->d_normal, as<float4>(ctx->gb0),
+                                   as<float>(ctx->gb1), s),
+            "backward set-up");
     }
     {
     Stage st_(ctx, LGSR_STAGE_RASTER_BWD);
-    HIP_TRY(launch_raster_bwd(S->ids, as<uint2>(S->ranges), as<float>(S->recs), as<uint2>(S->rects), S->rows, S->cols,
-                              S->g, S->prm, as<float4>(S->st0), as<float4>(S->st1), gin->d_depth, gin->d_opacity,
-                              gin->d_normal, as<float>(ctx->recgrad), s),
+    HIP_TRY(launch_raster_bwd(S->R, S->g, S->prm, as<float4>(ctx->gb0), as<float>(ctx->gb1), as<float>(ctx->recgrad),
+                              s),
             "raster backward");
     }
     Stage st_(ctx, LGSR_STAGE_CHAIN);
@@ -574,15 +605,17 @@ lgsr_status lgsr_query(lgsr_ctx *ctx, const lgsr_state *S, int64_t out[8])
     lgsr_state *W = const_cast<lgsr_state *>(S);
     unsigned long long *wc = reinterpret_cast<unsigned long long *>(counters + 8);
     HIP_TRY(launch_max_range(as<uint2>(W->ranges), S->g.T, counters + 1, s), "query");
+    HIP_TRY(launch_count_visible(as<uint2>(W->rects), S->S.n, counters + 2, s), "query");
     HIP_TRY(launch_work_counts(W->tile_keys, W->ids, as<uint2>(W->rects), S->P, as<float4>(W->st1), S->g, wc, s),
             "query");
-    HIP_TRY(hipMemcpyAsync(ctx->pinned + 1, counters + 1, sizeof(uint32_t), hipMemcpyDeviceToHost, s), "readback");
+    HIP_TRY(hipMemcpyAsync(ctx->pinned + 1, counters + 1, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, s),
+            "readback");
     HIP_TRY(hipMemcpyAsync(ctx->pinned + 4, wc, 3 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s),
             "readback");
     HIP_TRY(hipStreamSynchronize(s), "query sync");
     const unsigned long long *hw = reinterpret_cast<const unsigned long long *>(ctx->pinned + 4);
     out[0] = S->P;
-    out[1] = (int64_t)S->n_visible;
+    out[1] = (int64_t)ctx->pinned[2];
     out[2] = (int64_t)(ctx_bytes(ctx) + state_bytes(S));
     out[3] = (int64_t)ctx->pinned[1];
     out[4] = (int64_t)hw[0];
@@ -592,10 +625,10 @@ lgsr_status lgsr_query(lgsr_ctx *ctx, const lgsr_state *S, int64_t out[8])
     return LGSR_OK;
 }
 
-lgsr_status lgsr_profile(lgsr_ctx *ctx, int32_t enable)
+lgsr_status lgsr_profile(lgsr_ctx *ctx, int32_t stage_mask)
 {
     if (!ctx) return LGSR_EINVAL;
-    ctx->prof = enable != 0;
+    ctx->prof_mask = (uint32_t)stage_mask;
     return LGSR_OK;
 }
 

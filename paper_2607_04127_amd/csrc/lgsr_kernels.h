@@ -34,21 +34,36 @@ hipError_t launch_emit(const uint32_t *sorted_ids, const uint32_t *cnt, const ui
                        int64_t n, const Grid &g, uint32_t *pair_keys, uint32_t *pair_vals, hipStream_t s);
 hipError_t launch_ranges(const uint32_t *sorted_keys, int64_t P, int T, uint2 *ranges, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
-hipError_t launch_count_visible(const uint32_t *cnt, int64_t n, uint32_t *out, hipStream_t s);
+hipError_t launch_count_visible(const uint2 *rects, int64_t n, uint32_t *out, hipStream_t s);
 hipError_t launch_max_range(const uint2 *ranges, int T, uint32_t *out, hipStream_t s);
 // out[0] ray-surfel tests, out[1] composited hits, out[2] rays with a hit (u64, zeroed here)
 hipError_t launch_work_counts(const uint32_t *tile_keys, const uint32_t *ids, const uint2 *rects, int64_t P,
                               const float4 *st1, const Grid &g, unsigned long long *out, hipStream_t s);
 
 // ---- raster.hip ----
-hipError_t launch_raster_fwd(const uint32_t *ids, const uint2 *ranges, const float *recs, const uint2 *rects,
-                             const float *rows, const float *cols, const Grid &g, const RasterParams &p,
-                             float *depth, float *opacity, float *normal, uint8_t *drop, float4 *st0, float4 *st1,
-                             hipStream_t s);
-hipError_t launch_raster_bwd(const uint32_t *ids, const uint2 *ranges, const float *recs, const uint2 *rects,
-                             const float *rows, const float *cols, const Grid &g, const RasterParams &p,
-                             const float4 *st0, const float4 *st1, const float *gD, const float *gA,
-                             const float *gN, float *recgrad, hipStream_t s);
+struct RasterBufs {
+    const uint32_t *ids;  // sorted pair surfel ids
+    const float *recs;
+    const uint2 *rects, *ranges;
+    const float *rows, *cols;
+    uint4 *chunks;         // items_max x (tile, first, end, 0)
+    uint32_t *chunk_base;  // T + 1
+    uint32_t *n_items;     // device counter
+    float *slots;          // chunk_slot_floats(items_max)
+    float4 *st0, *st1;     // per ray
+    float4 *fixA, *fixB;   // per ray
+    int seg;
+    int64_t items_max;
+};
+int chunk_size(int64_t P, int requested);
+int64_t chunk_items_max(int64_t P, int T, int seg);
+size_t chunk_slot_floats(int64_t items_max);
+hipError_t launch_raster_fwd(const RasterBufs &R, const Grid &g, const RasterParams &p, float *depth,
+                             float *opacity, float *normal, uint8_t *drop, hipStream_t s);
+hipError_t launch_raster_bwd_prep(const RasterBufs &R, const Grid &g, const float *gD, const float *gA,
+                                  const float *gN, float4 *gb0, float *gb1, hipStream_t s);
+hipError_t launch_raster_bwd(const RasterBufs &R, const Grid &g, const RasterParams &p, const float4 *gb0,
+                             const float *gb1, float *recgrad, hipStream_t s);
 
 // ---- loss.hip ----
 int loss_blocks(int64_t n_rays);

@@ -201,13 +201,19 @@ __global__ __launch_bounds__(256) void fill_u32_kernel(uint32_t *__restrict__ p,
     if (i < n) p[i] = v;
 }
 
-// out[0] += number of surfels with a nonzero tile count (out zeroed by the caller)
-__global__ __launch_bounds__(256) void count_visible_kernel(const uint32_t *__restrict__ cnt, int64_t n,
+// out[0] += number of surfels whose ray rectangle is not empty (one atomic per workgroup)
+__global__ __launch_bounds__(256) void count_visible_kernel(const uint2 *__restrict__ rects, int64_t n,
                                                             uint32_t *__restrict__ out)
 {
+    __shared__ uint32_t ws[4];
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    uint64_t m = __ballot(i < n && cnt[i] > 0);
-    if ((threadIdx.x & 63) == 0 && m) atomicAdd(out, (uint32_t)__popcll(m));
+    uint64_t m = __ballot(i < n && (rects[i].y >> 16) > 0);
+    if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = (uint32_t)__popcll(m);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t c = ws[0] + ws[1] + ws[2] + ws[3];
+        if (c) atomicAdd(out, c);
+    }
 }
 
 __global__ __launch_bounds__(256) void max_range_kernel(const uint2 *__restrict__ ranges, int T,
@@ -307,11 +313,11 @@ hipError_t launch_ranges(const uint32_t *sorted_keys, int64_t P, int T, uint2 *r
     return hipGetLastError();
 }
 
-hipError_t launch_count_visible(const uint32_t *cnt, int64_t n, uint32_t *out, hipStream_t s)
+hipError_t launch_count_visible(const uint2 *rects, int64_t n, uint32_t *out, hipStream_t s)
 {
     hipError_t e = launch_fill_u32(out, 0u, 1, s);
     if (e != hipSuccess || n <= 0) return e;
-    count_visible_kernel<<<blocks_for(n, 256), 256, 0, s>>>(cnt, n, out);
+    count_visible_kernel<<<blocks_for(n, 256), 256, 0, s>>>(rects, n, out);
     return hipGetLastError();
 }
 

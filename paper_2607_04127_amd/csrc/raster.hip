@@ -1,72 +1,245 @@
-// raster.hip -- per-tile front-to-back compositing (forward) and its reverse-order backward.
+// raster.hip -- chunk-parallel front-to-back compositing and its reverse-order backward.
 //
-// A workgroup renders one 16 x 16 tile; each of its four wavefronts owns an 8 x 8 sub-tile,
-// one ray per lane, and walks the tile's range-sorted surfel list on its own (no barriers).
-// A list entry is wave-uniform, so its surfel id, ray rectangle and 64-byte record are
-// read with scalar loads into SGPRs; an entry whose rectangle misses the wave's sub-tile is
-// skipped by a scalar branch before the record is touched.
+// Each tile (16 x 16 rays) owns a range-sorted list of surfels.  The lists are cut into
+// chunks of `seg` entries; a chunk is one workgroup whose four wavefronts own the tile's
+// four 8 x 8 sub-tiles (one ray per lane).  The workgroup first stages the chunk's surfel
+// ids, ray rectangles and 64-byte records in LDS with coalesced vector loads; each wave
+// then walks the staged entries on its own, skipping (scalar branch) entries whose
+// rectangle misses its sub-tile and broadcasting the others' records from LDS.  Chunking
+// spreads long lists over many workgroups (load balance) and keeps several waves per SIMD
+// resident (latency hiding).
 //
-// Forward per ray (Sec. 3.1 / 3.4 rendering, 2DGS surfel):
-//   w = T alpha_hat, A += w, S_D += w t, S_N += w nt, T *= 1 - alpha_hat, stop once T < T_min;
-//   depth = S_D / A, opacity = A, normal = S_N / A, drop = [A < drop_tau].
-// It stores per ray (A, depth, T_final, last list position) and (normal, K).
+// Compositing (Sec. 3.1 / 3.4 rendering with the 2DGS surfel), per ray and hit:
+//   w = T alpha_hat, A += w, S_D += w t, S_N += w nt, T *= 1 - alpha_hat, stop once T < T_min.
+// Segments compose associatively: with the transmittance T_pre in front of a chunk, its
+// local sums (from T = 1) enter as (T_pre T_loc, A + T_pre A_loc, ...).  Every chunk stops
+// locally at T_loc < T_min, which is exact for the first chunk of a tile (T_pre = 1).  The
+// merge walks a ray's chunks in order; if T_pre T_loc drops below T_min inside a later
+// chunk, the ray terminated there and that one chunk is re-walked sequentially from T_pre
+// (fix-up) while later chunks are dropped.
 //
-// Backward per ray, list walked from the wave's last contributor down (lanes aligned on
-// list position, each lane acting only on its own contributors), with
+// Backward, per ray and chunk (list walked from the wave's last contributor down, lanes
+// aligned on list position, each lane acting only on its own contributors):
 //   gD~ = gD / A, gN~ = gN / A, gA~ = gA - (gD depth + gN . normal) / A,
-//   c_j = gD~ t_j + gN~ . nt_j + gA~,  B_j = sum_{i > j} w_i c_i,
+//   c_j = gD~ t_j + gN~ . nt_j + gA~,  B_j = sum_{i > j} w_i c_i (global weights),
 //   dL/dalpha_hat_j = T_j c_j - B_j / (1 - alpha_hat_j),
-// T_j recovered as T_{j+1} / (1 - alpha_hat_j) from the bit-identical recomputed
-// alpha_hat_j.  The per-(ray, surfel) gradient w.r.t. the record quantities
-// (nt, c, U, V, alpha) is summed over the wave by a butterfly and added with one vector
-// atomic (11 lanes) per surfel and wave into the record-gradient buffer.
+// with the chunk's end transmittance and its B (the later chunks' sums gD~ S_D + gN~ . S_N
+// + gA~ S_A) set up per ray beforehand, and T_j recovered as T_{j+1} / (1 - alpha_hat_j)
+// from the bit-identical recomputed alpha_hat_j.  The per-(ray, surfel) gradient w.r.t.
+// the record quantities (nt, c, U, V, alpha) is summed over the wave and added with one
+// vector atomic (11 lanes) per surfel and wave.
 #include "lgsr_internal.h"
 #include "lgsr_kernels.h"
 
 namespace lgsr {
 
-__global__ __launch_bounds__(256) void raster_fwd_kernel(
-    const uint32_t *__restrict__ ids, const uint2 *__restrict__ ranges, const float *__restrict__ recs,
-    const uint2 *__restrict__ rects, const float *__restrict__ rows, const float *__restrict__ cols, Grid g,
-    RasterParams p, float *__restrict__ depth, float *__restrict__ opacity, float *__restrict__ normal,
-    uint8_t *__restrict__ drop, float4 *__restrict__ st0, float4 *__restrict__ st1)
-{
-    const int tile = xcd_tile(blockIdx.x, g.T);
-    const int tc = tile / g.TH, tr = tile - tc * g.TH;
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
-    const int sr0 = tr * kTile + (wave >> 1) * kSub, sc0 = tc * kTile + (wave & 1) * kSub;
-    const int k = sr0 + (lane >> 3), j = sc0 + (lane & 7);
-    const bool valid = k < g.H && j < g.W;
-    Ray ray = make_ray(rows, cols, valid ? k : 0, valid ? j : 0);
+// Per (chunk, ray) slot fields; slot(item, f, rt) with rt = wave * 64 + lane.
+enum : int { F_TEND = 0, F_SA, F_SD, F_SN0, F_SN1, F_SN2, F_LAST, F_K, F_B, kSlotFields };
 
-    float T = 1.f, A = 0.f, SD = 0.f, SN0 = 0.f, SN1 = 0.f, SN2 = 0.f;
-    int K = 0, last = -1;
-    bool done = !valid;
-    const uint2 rg = ranges[tile];
-    if (sr0 < g.H && sc0 < g.W) {
-        for (uint32_t pos = rg.x; pos < rg.y; ++pos) {
-            const uint32_t id = ids[pos];
-            if (sub_overlap(rects[id], sr0, sc0, g.W)) {
-                const Rec s = load_rec(recs, id);
-                const Hit h = hit_test(s, ray, p);
-                if (h.pass && !done) {
-                    float w = T * h.ah;
-                    A += w;
-                    SD = fmaf(w, h.t, SD);
-                    SN0 = fmaf(w, s.nt0, SN0);
-                    SN1 = fmaf(w, s.nt1, SN1);
-                    SN2 = fmaf(w, s.nt2, SN2);
-                    T = T * (1.f - h.ah);
-                    ++K;
-                    last = (int)pos;
-                    done = T < p.T_min;
-                }
-                if (__all(done)) break;
+__device__ __forceinline__ size_t slot(uint32_t item, int f, int rt)
+{
+    return ((size_t)item * kSlotFields + f) * 256 + rt;
+}
+
+struct Lane {
+    int wave, lane, rt, sr0, sc0, k, j;
+    bool valid, wave_in;
+};
+
+__device__ __forceinline__ Lane lane_of(int tile, const Grid &g)
+{
+    Lane L;
+    const int tc = tile / g.TH, tr = tile - tc * g.TH;
+    L.wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    L.lane = threadIdx.x & 63;
+    L.rt = threadIdx.x;
+    L.sr0 = tr * kTile + (L.wave >> 1) * kSub;
+    L.sc0 = tc * kTile + (L.wave & 1) * kSub;
+    L.k = L.sr0 + (L.lane >> 3);
+    L.j = L.sc0 + (L.lane & 7);
+    L.valid = L.k < g.H && L.j < g.W;
+    L.wave_in = L.sr0 < g.H && L.sc0 < g.W;
+    return L;
+}
+
+// ---------------------------------------------------------------------------------------
+// chunk list
+// ---------------------------------------------------------------------------------------
+
+__global__ __launch_bounds__(1024) void build_chunks_kernel(const uint2 *__restrict__ ranges, int T, int seg,
+                                                            uint4 *__restrict__ chunks,
+                                                            uint32_t *__restrict__ chunk_base,
+                                                            uint32_t *__restrict__ n_items)
+{
+    __shared__ uint32_t wsum[16];
+    const int t0 = threadIdx.x, w = t0 >> 6, l = t0 & 63;
+    uint32_t carry = 0;
+    for (int base = 0; base < T; base += 1024) {
+        const int t = base + t0;
+        uint2 r = make_uint2(0u, 0u);
+        uint32_t c = 0;
+        if (t < T) {
+            r = ranges[t];
+            c = (r.y - r.x + (uint32_t)seg - 1u) / (uint32_t)seg;
+        }
+        uint32_t inc = c;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            uint32_t y = __shfl_up(inc, o, 64);
+            if (l >= o) inc += y;
+        }
+        if (l == 63) wsum[w] = inc;
+        __syncthreads();
+        uint32_t off = 0, tot = 0;
+        for (int q = 0; q < 16; ++q) {
+            uint32_t s = wsum[q];
+            if (q < w) off += s;
+            tot += s;
+        }
+        const uint32_t first = carry + off + inc - c;
+        if (t < T) {
+            chunk_base[t] = first;
+            for (uint32_t q = 0; q < c; ++q) {
+                uint32_t a = r.x + q * (uint32_t)seg;
+                uint32_t b = min(r.y, a + (uint32_t)seg);
+                chunks[first + q] = make_uint4((uint32_t)t, a, b, 0u);
             }
         }
+        carry += tot;
+        __syncthreads();
     }
-    if (!valid) return;
-    const int r = k * g.W + j;
+    if (t0 == 0) {
+        chunk_base[T] = carry;
+        *n_items = carry;
+    }
+}
+
+// ---------------------------------------------------------------------------------------
+// forward
+// ---------------------------------------------------------------------------------------
+
+struct Acc {
+    float T, A, SD, SN0, SN1, SN2;
+    int K, last;
+};
+
+// A chunk's (tile, first, end) as scalar values (all lanes read the same entry).
+__device__ __forceinline__ uint4 uniform_chunk(const uint4 *__restrict__ chunks, uint32_t item)
+{
+    const uint4 c = chunks[item];
+    return make_uint4(__builtin_amdgcn_readfirstlane(c.x), __builtin_amdgcn_readfirstlane(c.y),
+                      __builtin_amdgcn_readfirstlane(c.z), 0u);
+}
+
+// A chunk's list entries staged in LDS: ids, ray rectangles and 64-byte records, loaded
+// by the whole workgroup with coalesced vector loads (one memory latency per stage instead
+// of a dependent id -> rectangle -> record chain per entry).
+constexpr int kStage = 256;
+struct Staged {
+    float4 rec[kStage][4];
+    uint2 rect[kStage];
+    uint32_t id[kStage];
+};
+
+// All 256 threads; n <= kStage entries from list position a.  Ends with a barrier.
+__device__ __forceinline__ void stage_entries(Staged &sm, const uint32_t *__restrict__ ids,
+                                              const float *__restrict__ recs, const uint2 *__restrict__ rects,
+                                              uint32_t a, uint32_t n)
+{
+    const int t = threadIdx.x;
+    if ((uint32_t)t < n) {
+        const uint32_t id = ids[a + t];
+        sm.id[t] = id;
+        sm.rect[t] = rects[id];
+    }
+    __syncthreads();
+    const float4 *r4 = reinterpret_cast<const float4 *>(recs);
+    for (uint32_t k = t; k < 4u * n; k += 256u) {
+        const uint32_t e = k >> 2, q = k & 3u;
+        sm.rec[e][q] = r4[(size_t)sm.id[e] * 4 + q];
+    }
+    __syncthreads();
+}
+
+__device__ __forceinline__ bool staged_overlap(const Staged &sm, uint32_t e, const Lane &L, int W)
+{
+    const uint2 rc = sm.rect[e];
+    const uint2 su = make_uint2(__builtin_amdgcn_readfirstlane(rc.x), __builtin_amdgcn_readfirstlane(rc.y));
+    return sub_overlap(su, L.sr0, L.sc0, W);
+}
+
+__device__ __forceinline__ Rec staged_rec(const Staged &sm, uint32_t e)
+{
+    const float4 x = sm.rec[e][0], y = sm.rec[e][1], z = sm.rec[e][2], w = sm.rec[e][3];
+    return Rec{x.x, x.y, x.z, x.w, y.x, y.y, y.z, y.w, z.x, z.y, z.z, z.w, w.x, w.y, w.z, w.w};
+}
+
+// Composite list entries [a, b) for this wave's rays, starting from acc (transmittance
+// acc.T); lanes with `active` false only follow along.  A lane stops once T < T_min.
+// Every thread of the workgroup must call this (it stages through LDS with barriers).
+__device__ __forceinline__ void composite(Staged &sm, const uint32_t *__restrict__ ids,
+                                          const float *__restrict__ recs, const uint2 *__restrict__ rects,
+                                          uint32_t a, uint32_t b, const Lane &L, const Ray &ray,
+                                          const RasterParams &p, int W, bool active, Acc &acc)
+{
+    bool done = !active || !L.wave_in;
+    for (uint32_t base = a; base < b; base += kStage) {
+        const uint32_t n = min((uint32_t)kStage, b - base);
+        if (base != a) __syncthreads();  // the previous stage is no longer read
+        stage_entries(sm, ids, recs, rects, base, n);
+        if (__all(done)) continue;
+        for (uint32_t e = 0; e < n; ++e) {
+            if (!staged_overlap(sm, e, L, W)) continue;
+            const Rec s = staged_rec(sm, e);
+            const Hit h = hit_test(s, ray, p);
+            if (h.pass && !done) {
+                float w = acc.T * h.ah;
+                acc.A += w;
+                acc.SD = fmaf(w, h.t, acc.SD);
+                acc.SN0 = fmaf(w, s.nt0, acc.SN0);
+                acc.SN1 = fmaf(w, s.nt1, acc.SN1);
+                acc.SN2 = fmaf(w, s.nt2, acc.SN2);
+                acc.T = acc.T * (1.f - h.ah);
+                ++acc.K;
+                acc.last = (int)(base + e);
+                done = acc.T < p.T_min;
+            }
+            if (__all(done)) break;
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void raster_fwd_chunk_kernel(
+    const uint4 *__restrict__ chunks, const uint32_t *__restrict__ n_items, int items_max,
+    const uint32_t *__restrict__ ids, const float *__restrict__ recs, const uint2 *__restrict__ rects,
+    const float *__restrict__ rows, const float *__restrict__ cols, Grid g, RasterParams p, float *__restrict__ slots)
+{
+    __shared__ Staged sm;
+    const uint32_t item = (uint32_t)xcd_tile(blockIdx.x, items_max);
+    if (item >= *n_items) return;  // whole workgroup
+    const uint4 ch = uniform_chunk(chunks, item);
+    const Lane L = lane_of((int)ch.x, g);
+    Ray ray = make_ray(rows, cols, L.valid ? L.k : 0, L.valid ? L.j : 0);
+    Acc acc{1.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0, -1};
+    composite(sm, ids, recs, rects, ch.y, ch.z, L, ray, p, g.W, L.valid, acc);
+    if (!L.valid) return;
+    slots[slot(item, F_TEND, L.rt)] = acc.T;
+    slots[slot(item, F_SA, L.rt)] = acc.A;
+    slots[slot(item, F_SD, L.rt)] = acc.SD;
+    slots[slot(item, F_SN0, L.rt)] = acc.SN0;
+    slots[slot(item, F_SN1, L.rt)] = acc.SN1;
+    slots[slot(item, F_SN2, L.rt)] = acc.SN2;
+    slots[slot(item, F_LAST, L.rt)] = __int_as_float(acc.last);
+    slots[slot(item, F_K, L.rt)] = __int_as_float(acc.K);
+}
+
+__device__ __forceinline__ void write_ray(const Lane &L, const Grid &g, const RasterParams &p, float A, float SD,
+                                          float SN0, float SN1, float SN2, float T, int K, float *__restrict__ depth,
+                                          float *__restrict__ opacity, float *__restrict__ normal,
+                                          uint8_t *__restrict__ drop, float4 *__restrict__ st0,
+                                          float4 *__restrict__ st1)
+{
+    const int r = L.k * g.W + L.j;
     float D = 0.f, N0 = 0.f, N1 = 0.f, N2 = 0.f;
     if (K > 0) {
         D = SD / A;
@@ -80,15 +253,192 @@ __global__ __launch_bounds__(256) void raster_fwd_kernel(
     normal[3 * r + 1] = N1;
     normal[3 * r + 2] = N2;
     drop[r] = (K == 0 || A < p.drop_tau) ? 1 : 0;
-    st0[r] = make_float4(A, D, T, __int_as_float(last));
+    st0[r] = make_float4(A, D, T, 0.f);
     st1[r] = make_float4(N0, N1, N2, __int_as_float(K));
 }
 
-__device__ __forceinline__ float wave_sum(float v)
+// One workgroup per tile: combine the chunks of every ray in list order (slots become
+// global: end transmittance and sums in global weights), detect termination in a later
+// chunk (-> fix-up record) and write the frame for rays that need no fix-up.
+__global__ __launch_bounds__(256) void raster_merge_kernel(const uint32_t *__restrict__ chunk_base, Grid g,
+                                                           RasterParams p, float *__restrict__ slots,
+                                                           float *__restrict__ depth, float *__restrict__ opacity,
+                                                           float *__restrict__ normal, uint8_t *__restrict__ drop,
+                                                           float4 *__restrict__ st0, float4 *__restrict__ st1,
+                                                           float4 *__restrict__ fixA, float4 *__restrict__ fixB)
 {
+    const int tile = blockIdx.x;
+    const Lane L = lane_of(tile, g);
+    if (!L.valid) return;
+    const uint32_t c0 = chunk_base[tile], c1 = chunk_base[tile + 1];
+    float T = 1.f, A = 0.f, SD = 0.f, SN0 = 0.f, SN1 = 0.f, SN2 = 0.f;
+    int K = 0, fix = -1;
+    float4 fa = make_float4(0.f, 0.f, 0.f, 0.f), fb = make_float4(0.f, 0.f, 0.f, __int_as_float(-1));
+    for (uint32_t it = c0; it < c1; ++it) {
+        if (fix >= 0 || T < p.T_min) {  // after termination: the chunk contributes nothing
+            slots[slot(it, F_LAST, L.rt)] = __int_as_float(-1);
+            continue;
+        }
+        const int Kl = __float_as_int(slots[slot(it, F_K, L.rt)]);
+        if (Kl == 0) {
+            slots[slot(it, F_TEND, L.rt)] = T;
+            continue;
+        }
+        const float Tl = slots[slot(it, F_TEND, L.rt)];
+        const float Tn = T * Tl;
+        if (it > c0 && Tn < p.T_min) {  // the ray terminates inside this chunk: re-walk it
+            fix = (int)it;
+            fa = make_float4(T, A, SD, __int_as_float(K));
+            fb = make_float4(SN0, SN1, SN2, __int_as_float(fix));
+            slots[slot(it, F_LAST, L.rt)] = __int_as_float(-1);
+            continue;
+        }
+        const float Al = slots[slot(it, F_SA, L.rt)], SDl = slots[slot(it, F_SD, L.rt)];
+        const float S0 = slots[slot(it, F_SN0, L.rt)], S1 = slots[slot(it, F_SN1, L.rt)];
+        const float S2 = slots[slot(it, F_SN2, L.rt)];
+        const float gA = T * Al, gD = T * SDl, g0 = T * S0, g1 = T * S1, g2 = T * S2;
+        slots[slot(it, F_TEND, L.rt)] = Tn;
+        slots[slot(it, F_SA, L.rt)] = gA;
+        slots[slot(it, F_SD, L.rt)] = gD;
+        slots[slot(it, F_SN0, L.rt)] = g0;
+        slots[slot(it, F_SN1, L.rt)] = g1;
+        slots[slot(it, F_SN2, L.rt)] = g2;
+        A += gA;
+        SD += gD;
+        SN0 += g0;
+        SN1 += g1;
+        SN2 += g2;
+        K += Kl;
+        T = Tn;
+    }
+    const int r = L.k * g.W + L.j;
+    fixA[r] = fa;
+    fixB[r] = fb;
+    if (fix < 0) write_ray(L, g, p, A, SD, SN0, SN1, SN2, T, K, depth, opacity, normal, drop, st0, st1);
+}
+
+// Re-walk the chunk in which a ray terminates, from its true transmittance, and finish it.
+__global__ __launch_bounds__(256) void raster_fixup_kernel(
+    const uint4 *__restrict__ chunks, const uint32_t *__restrict__ n_items, int items_max,
+    const uint32_t *__restrict__ ids, const float *__restrict__ recs, const uint2 *__restrict__ rects,
+    const float *__restrict__ rows, const float *__restrict__ cols, Grid g, RasterParams p,
+    const float4 *__restrict__ fixA, const float4 *__restrict__ fixB, float *__restrict__ slots,
+    float *__restrict__ depth, float *__restrict__ opacity, float *__restrict__ normal, uint8_t *__restrict__ drop,
+    float4 *__restrict__ st0, float4 *__restrict__ st1)
+{
+    __shared__ Staged sm;
+    const uint32_t item = (uint32_t)xcd_tile(blockIdx.x, items_max);
+    if (item >= *n_items) return;  // whole workgroup
+    const uint4 ch = uniform_chunk(chunks, item);
+    const Lane L = lane_of((int)ch.x, g);
+    const int r = L.valid ? L.k * g.W + L.j : 0;
+    float4 fa = make_float4(0.f, 0.f, 0.f, 0.f), fb = make_float4(0.f, 0.f, 0.f, __int_as_float(-1));
+    if (L.valid) {
+        fb = fixB[r];
+        fa = fixA[r];
+    }
+    const bool pend = L.valid && __float_as_int(fb.w) == (int)item;
+    if (!__syncthreads_or(pend)) return;  // whole workgroup
+    Ray ray = make_ray(rows, cols, L.valid ? L.k : 0, L.valid ? L.j : 0);
+    Acc acc{pend ? fa.x : 1.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0, -1};
+    composite(sm, ids, recs, rects, ch.y, ch.z, L, ray, p, g.W, pend, acc);
+    if (!pend) return;
+    slots[slot(item, F_TEND, L.rt)] = acc.T;
+    slots[slot(item, F_SA, L.rt)] = acc.A;
+    slots[slot(item, F_SD, L.rt)] = acc.SD;
+    slots[slot(item, F_SN0, L.rt)] = acc.SN0;
+    slots[slot(item, F_SN1, L.rt)] = acc.SN1;
+    slots[slot(item, F_SN2, L.rt)] = acc.SN2;
+    slots[slot(item, F_LAST, L.rt)] = __int_as_float(acc.last);
+    slots[slot(item, F_K, L.rt)] = __int_as_float(acc.K);
+    write_ray(L, g, p, fa.y + acc.A, fa.z + acc.SD, fb.x + acc.SN0, fb.y + acc.SN1, fb.z + acc.SN2, acc.T,
+              __float_as_int(fa.w) + acc.K, depth, opacity, normal, drop, st0, st1);
+}
+
+// ---------------------------------------------------------------------------------------
+// backward
+// ---------------------------------------------------------------------------------------
+
+// Per ray: effective upstream gradients and, per chunk, the suffix sum B of later chunks.
+__global__ __launch_bounds__(256) void raster_bwd_prep_kernel(const uint32_t *__restrict__ chunk_base, Grid g,
+                                                              const float4 *__restrict__ st0,
+                                                              const float4 *__restrict__ st1,
+                                                              const float *__restrict__ gDp,
+                                                              const float *__restrict__ gAp,
+                                                              const float *__restrict__ gNp,
+                                                              float *__restrict__ slots, float4 *__restrict__ gb0,
+                                                              float *__restrict__ gb1)
+{
+    const int tile = blockIdx.x;
+    const Lane L = lane_of(tile, g);
+    if (!L.valid) return;
+    const int r = L.k * g.W + L.j;
+    const float4 a = st0[r], b = st1[r];
+    const int K = __float_as_int(b.w);
+    float gbD = 0.f, gbN0 = 0.f, gbN1 = 0.f, gbN2 = 0.f, gbA = 0.f;
+    if (K > 0) {
+        const float iA = 1.f / a.x, D = a.y;
+        const float gd = gDp[r], ga = gAp[r];
+        const float gn0 = gNp[3 * r], gn1 = gNp[3 * r + 1], gn2 = gNp[3 * r + 2];
+        gbD = gd * iA;
+        gbN0 = gn0 * iA;
+        gbN1 = gn1 * iA;
+        gbN2 = gn2 * iA;
+        gbA = ga - (gd * D + gn0 * b.x + gn1 * b.y + gn2 * b.z) * iA;
+    }
+    gb0[r] = make_float4(gbD, gbN0, gbN1, gbN2);
+    gb1[r] = gbA;
+    const uint32_t c0 = chunk_base[tile], c1 = chunk_base[tile + 1];
+    float B = 0.f;
+    for (uint32_t it = c1; it-- > c0;) {
+        slots[slot(it, F_B, L.rt)] = B;
+        if (K == 0 || __float_as_int(slots[slot(it, F_LAST, L.rt)]) < 0) continue;
+        const float SA = slots[slot(it, F_SA, L.rt)], SD = slots[slot(it, F_SD, L.rt)];
+        const float S0 = slots[slot(it, F_SN0, L.rt)], S1 = slots[slot(it, F_SN1, L.rt)];
+        const float S2 = slots[slot(it, F_SN2, L.rt)];
+        B = fmaf(gbD, SD, fmaf(gbN0, S0, fmaf(gbN1, S1, fmaf(gbN2, S2, fmaf(gbA, SA, B)))));
+    }
+}
+
+// Wave-wide sums of 12 per-lane values by transposition: v_permlane32_swap folds lanes
+// 32-63 onto 0-31 for six pairs (i, i + 6), v_permlane16_swap folds odd rows onto even rows
+// for three pairs, and four DPP steps (xor 1, xor 2, half-row mirror, row mirror) finish
+// each 16-lane row.  Afterwards lane 16 r + k (k < 3) holds the total of value 3 r + k.
+// Needs all 64 lanes active.
+template <int CTRL>
+__device__ __forceinline__ float dpp_add(float v)
+{
+    return v + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, true));
+}
+
+__device__ __forceinline__ float swap32_add(float x, float y)
+{
+    auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(y), false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
+__device__ __forceinline__ float swap16_add(float x, float y)
+{
+    auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(x), __float_as_uint(y), false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
+__device__ __forceinline__ float wave_sum12(const float (&g)[12], int lane)
+{
+    float a[6], b[3];
 #pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
+    for (int i = 0; i < 6; ++i) a[i] = swap32_add(g[i], g[i + 6]);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        float v = swap16_add(a[i], a[i + 3]);
+        v = dpp_add<0xB1>(v);   // quad_perm [1,0,3,2]
+        v = dpp_add<0x4E>(v);   // quad_perm [2,3,0,1]
+        v = dpp_add<0x141>(v);  // row_half_mirror
+        v = dpp_add<0x140>(v);  // row_mirror
+        b[i] = v;
+    }
+    const int k = lane & 15;
+    return k == 0 ? b[0] : (k == 1 ? b[1] : b[2]);
 }
 
 __device__ __forceinline__ int wave_max_i(int v)
@@ -98,121 +448,150 @@ __device__ __forceinline__ int wave_max_i(int v)
     return v;
 }
 
-__global__ __launch_bounds__(256) void raster_bwd_kernel(
-    const uint32_t *__restrict__ ids, const uint2 *__restrict__ ranges, const float *__restrict__ recs,
-    const uint2 *__restrict__ rects, const float *__restrict__ rows, const float *__restrict__ cols, Grid g,
-    RasterParams p, const float4 *__restrict__ st0, const float4 *__restrict__ st1, const float *__restrict__ gDp,
-    const float *__restrict__ gAp, const float *__restrict__ gNp, float *__restrict__ recgrad)
+__global__ __launch_bounds__(256) void raster_bwd_chunk_kernel(
+    const uint4 *__restrict__ chunks, const uint32_t *__restrict__ n_items, int items_max,
+    const uint32_t *__restrict__ ids, const float *__restrict__ recs, const uint2 *__restrict__ rects,
+    const float *__restrict__ rows, const float *__restrict__ cols, Grid g, RasterParams p,
+    const float *__restrict__ slots, const float4 *__restrict__ gb0, const float *__restrict__ gb1,
+    float *__restrict__ recgrad)
 {
-    const int tile = xcd_tile(blockIdx.x, g.T);
-    const int tc = tile / g.TH, tr = tile - tc * g.TH;
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
-    const int sr0 = tr * kTile + (wave >> 1) * kSub, sc0 = tc * kTile + (wave & 1) * kSub;
-    if (sr0 >= g.H || sc0 >= g.W) return;  // whole wave outside the image
-    const int k = sr0 + (lane >> 3), j = sc0 + (lane & 7);
-    const bool valid = k < g.H && j < g.W;
-    Ray ray = make_ray(rows, cols, valid ? k : 0, valid ? j : 0);
-
+    __shared__ Staged sm;
+    const uint32_t item = (uint32_t)xcd_tile(blockIdx.x, items_max);
+    if (item >= *n_items) return;  // whole workgroup
+    const uint4 ch = uniform_chunk(chunks, item);
+    const Lane L = lane_of((int)ch.x, g);
+    Ray ray = make_ray(rows, cols, L.valid ? L.k : 0, L.valid ? L.j : 0);
     int last = -1;
-    float T = 1.f, gbD = 0.f, gbN0 = 0.f, gbN1 = 0.f, gbN2 = 0.f, gbA = 0.f;
-    if (valid) {
-        const int r = k * g.W + j;
-        float4 a = st0[r], b = st1[r];
-        last = __float_as_int(a.w);
+    float T = 1.f, B = 0.f, gbD = 0.f, gbN0 = 0.f, gbN1 = 0.f, gbN2 = 0.f, gbA = 0.f;
+    if (L.valid) {
+        last = __float_as_int(slots[slot(item, F_LAST, L.rt)]);
         if (last >= 0) {
-            float A = a.x, D = a.y;
-            T = a.z;
-            float iA = 1.f / A;
-            float gd = gDp[r], ga = gAp[r];
-            float gn0 = gNp[3 * r], gn1 = gNp[3 * r + 1], gn2 = gNp[3 * r + 2];
-            gbD = gd * iA;
-            gbN0 = gn0 * iA;
-            gbN1 = gn1 * iA;
-            gbN2 = gn2 * iA;
-            gbA = ga - (gd * D + gn0 * b.x + gn1 * b.y + gn2 * b.z) * iA;
+            const int r = L.k * g.W + L.j;
+            T = slots[slot(item, F_TEND, L.rt)];
+            B = slots[slot(item, F_B, L.rt)];
+            const float4 q = gb0[r];
+            gbD = q.x;
+            gbN0 = q.y;
+            gbN1 = q.z;
+            gbN2 = q.w;
+            gbA = gb1[r];
         }
     }
-    const int pmax = wave_max_i(last);
-    const uint2 rg = ranges[tile];
-    float B = 0.f;
-    for (int pos = pmax; pos >= (int)rg.x; --pos) {
-        const uint32_t id = ids[pos];
-        if (!sub_overlap(rects[id], sr0, sc0, g.W)) continue;
-        const Rec s = load_rec(recs, id);
-        float gv[11];
+    const int wmax = wave_max_i(last);
+    if (!__syncthreads_or(last >= 0)) return;  // whole workgroup: nothing to propagate
+    const uint32_t a = ch.y, b = ch.z;
+    const uint32_t nstages = (b - a + kStage - 1) / kStage;
+    for (uint32_t sidx = nstages; sidx-- > 0;) {
+        const uint32_t base = a + sidx * kStage;
+        const uint32_t n = min((uint32_t)kStage, b - base);
+        if (sidx + 1 != nstages) __syncthreads();  // the previous stage is no longer read
+        stage_entries(sm, ids, recs, rects, base, n);
+        if (wmax < (int)base) continue;
+        const uint32_t e_hi = min(n, (uint32_t)(wmax - (int)base) + 1u);
+        for (uint32_t e = e_hi; e-- > 0;) {
+            if (!staged_overlap(sm, e, L, g.W)) continue;
+            const int pos = (int)(base + e);
+            const Rec s = staged_rec(sm, e);
+            float gv[12];
 #pragma unroll
-        for (int c = 0; c < 11; ++c) gv[c] = 0.f;
-        bool contrib = false;
-        if (pos <= last) {
-            Hit h = hit_test(s, ray, p);
-            if (h.pass) {
-                contrib = true;
-                float one_m = 1.f - h.ah;
-                float r1m = __builtin_amdgcn_rcpf(one_m);
-                float Tj = T * r1m;
-                float w = Tj * h.ah;
-                float cj = fmaf(gbD, h.t, fmaf(gbN0, s.nt0, fmaf(gbN1, s.nt1, fmaf(gbN2, s.nt2, gbA))));
-                float dah = fmaf(Tj, cj, -B * r1m);
-                B = fmaf(w, cj, B);
-                T = Tj;
-                float dt = gbD * w;
-                float dalpha = 0.f, dG = 0.f;
-                if (h.aG < p.alpha_max) {
-                    dalpha = dah * h.G;
-                    dG = dah * s.alpha;
+            for (int c = 0; c < 12; ++c) gv[c] = 0.f;
+            bool contrib = false;
+            if (pos <= last) {
+                const Hit h = hit_test(s, ray, p);
+                if (h.pass) {
+                    contrib = true;
+                    const float one_m = 1.f - h.ah;
+                    const float r1m = __builtin_amdgcn_rcpf(one_m);
+                    const float Tj = T * r1m;
+                    const float w = Tj * h.ah;
+                    const float cj = fmaf(gbD, h.t, fmaf(gbN0, s.nt0, fmaf(gbN1, s.nt1, fmaf(gbN2, s.nt2, gbA))));
+                    const float dah = fmaf(Tj, cj, -B * r1m);
+                    B = fmaf(w, cj, B);
+                    T = Tj;
+                    const float dt = gbD * w;
+                    float dalpha = 0.f, dG = 0.f;
+                    if (h.aG < p.alpha_max) {
+                        dalpha = dah * h.G;
+                        dG = dah * s.alpha;
+                    }
+                    const float dq2 = -0.5f * h.G * dG;
+                    const float u = h.nu * h.inv, v = h.nv * h.inv;
+                    const float du = 2.f * u * dq2, dv = 2.f * v * dq2;
+                    const float dnu = du * h.inv, dnv = dv * h.inv;
+                    const float dden = -fmaf(du, u, fmaf(dv, v, dt * h.t)) * h.inv;
+                    gv[G_NT + 0] = fmaf(gbN0, w, dden * ray.dh[0]);
+                    gv[G_NT + 1] = fmaf(gbN1, w, dden * ray.dh[1]);
+                    gv[G_NT + 2] = fmaf(gbN2, w, dden * ray.dh[2]);
+                    gv[G_C] = dt * h.inv;
+                    gv[G_U + 0] = dnu * ray.dh[0];
+                    gv[G_U + 1] = dnu * ray.dh[1];
+                    gv[G_U + 2] = dnu * ray.dh[2];
+                    gv[G_V + 0] = dnv * ray.dh[0];
+                    gv[G_V + 1] = dnv * ray.dh[1];
+                    gv[G_V + 2] = dnv * ray.dh[2];
+                    gv[G_ALPHA] = dalpha;
                 }
-                float dq2 = -0.5f * h.G * dG;
-                float u = h.nu * h.inv, v = h.nv * h.inv;
-                float du = 2.f * u * dq2, dv = 2.f * v * dq2;
-                float dnu = du * h.inv, dnv = dv * h.inv;
-                float dden = -fmaf(du, u, fmaf(dv, v, dt * h.t)) * h.inv;
-                float dc = dt * h.inv;
-                gv[G_NT + 0] = fmaf(gbN0, w, dden * ray.dh[0]);
-                gv[G_NT + 1] = fmaf(gbN1, w, dden * ray.dh[1]);
-                gv[G_NT + 2] = fmaf(gbN2, w, dden * ray.dh[2]);
-                gv[G_C] = dc;
-                gv[G_U + 0] = dnu * ray.dh[0];
-                gv[G_U + 1] = dnu * ray.dh[1];
-                gv[G_U + 2] = dnu * ray.dh[2];
-                gv[G_V + 0] = dnv * ray.dh[0];
-                gv[G_V + 1] = dnv * ray.dh[1];
-                gv[G_V + 2] = dnv * ray.dh[2];
-                gv[G_ALPHA] = dalpha;
             }
-        }
-        if (__any(contrib)) {
-            float mine = 0.f;
-#pragma unroll
-            for (int c = 0; c < 11; ++c) {
-                float sum = wave_sum(gv[c]);
-                mine = (lane == c) ? sum : mine;
+            if (__any(contrib)) {
+                const float mine = wave_sum12(gv, L.lane);
+                const int k = L.lane & 15, c = 3 * (L.lane >> 4) + k;
+                if (k < 3 && c < 11) unsafeAtomicAdd(recgrad + (size_t)sm.id[e] * kGrad + c, mine);
             }
-            if (lane < 11) unsafeAtomicAdd(recgrad + (size_t)id * kGrad + lane, mine);
         }
     }
 }
 
-static inline unsigned grid_tiles(const Grid &g) { return (unsigned)g.T; }
+// ---------------------------------------------------------------------------------------
+// host launchers
+// ---------------------------------------------------------------------------------------
 
-hipError_t launch_raster_fwd(const uint32_t *ids, const uint2 *ranges, const float *recs, const uint2 *rects,
-                             const float *rows, const float *cols, const Grid &g, const RasterParams &p,
-                             float *depth, float *opacity, float *normal, uint8_t *drop, float4 *st0, float4 *st1,
-                             hipStream_t s)
+int chunk_size(int64_t P, int requested)
+{
+    if (requested > 0) return requested;
+    // about 2048 chunks (8 resident waves on each of 1024 SIMDs), at most one LDS stage each
+    int64_t s = (P + 2047) / 2048;
+    s = (s + 15) / 16 * 16;
+    if (s < 32) s = 32;
+    if (s > kStage) s = kStage;
+    return (int)s;
+}
+
+int64_t chunk_items_max(int64_t P, int T, int seg) { return (int64_t)T + (P + seg - 1) / seg; }
+
+size_t chunk_slot_floats(int64_t items_max) { return (size_t)items_max * kSlotFields * 256; }
+
+hipError_t launch_raster_fwd(const RasterBufs &R, const Grid &g, const RasterParams &p, float *depth,
+                             float *opacity, float *normal, uint8_t *drop, hipStream_t s)
 {
     if (g.T <= 0) return hipSuccess;
-    raster_fwd_kernel<<<grid_tiles(g), 256, 0, s>>>(ids, ranges, recs, rects, rows, cols, g, p, depth, opacity,
-                                                    normal, drop, st0, st1);
+    build_chunks_kernel<<<1, 1024, 0, s>>>(R.ranges, g.T, R.seg, R.chunks, R.chunk_base, R.n_items);
+    const int im = (int)R.items_max;
+    if (im > 0)
+        raster_fwd_chunk_kernel<<<im, 256, 0, s>>>(R.chunks, R.n_items, im, R.ids, R.recs, R.rects, R.rows, R.cols, g,
+                                                   p, R.slots);
+    raster_merge_kernel<<<g.T, 256, 0, s>>>(R.chunk_base, g, p, R.slots, depth, opacity, normal, drop, R.st0, R.st1,
+                                           R.fixA, R.fixB);
+    if (im > 0)
+        raster_fixup_kernel<<<im, 256, 0, s>>>(R.chunks, R.n_items, im, R.ids, R.recs, R.rects, R.rows, R.cols, g, p,
+                                               R.fixA, R.fixB, R.slots, depth, opacity, normal, drop, R.st0, R.st1);
     return hipGetLastError();
 }
 
-hipError_t launch_raster_bwd(const uint32_t *ids, const uint2 *ranges, const float *recs, const uint2 *rects,
-                             const float *rows, const float *cols, const Grid &g, const RasterParams &p,
-                             const float4 *st0, const float4 *st1, const float *gD, const float *gA,
-                             const float *gN, float *recgrad, hipStream_t s)
+hipError_t launch_raster_bwd_prep(const RasterBufs &R, const Grid &g, const float *gD, const float *gA,
+                                  const float *gN, float4 *gb0, float *gb1, hipStream_t s)
 {
     if (g.T <= 0) return hipSuccess;
-    raster_bwd_kernel<<<grid_tiles(g), 256, 0, s>>>(ids, ranges, recs, rects, rows, cols, g, p, st0, st1, gD, gA,
-                                                    gN, recgrad);
+    raster_bwd_prep_kernel<<<g.T, 256, 0, s>>>(R.chunk_base, g, R.st0, R.st1, gD, gA, gN, R.slots, gb0, gb1);
+    return hipGetLastError();
+}
+
+hipError_t launch_raster_bwd(const RasterBufs &R, const Grid &g, const RasterParams &p, const float4 *gb0,
+                             const float *gb1, float *recgrad, hipStream_t s)
+{
+    const int im = (int)R.items_max;
+    if (g.T <= 0 || im <= 0) return hipSuccess;
+    raster_bwd_chunk_kernel<<<im, 256, 0, s>>>(R.chunks, R.n_items, im, R.ids, R.recs, R.rects, R.rows, R.cols, g, p,
+                                               R.slots, gb0, gb1, recgrad);
     return hipGetLastError();
 }
 

@@ -40,17 +40,52 @@ __global__ __launch_bounds__(kSortThreads) void radix_upsweep(const uint32_t *__
 {
     __shared__ uint32_t h[256];
     h[threadIdx.x] = 0;
-    __syncthreads();
-    int64_t base = (int64_t)blockIdx.x * kSortTile;
+    const int64_t base = (int64_t)blockIdx.x * kSortTile + threadIdx.x;
+    uint32_t x[kSortItems];
+#pragma unroll
     for (int rd = 0; rd < kSortItems; ++rd) {
-        int64_t i = base + rd * kSortThreads + threadIdx.x;
-        bool valid = i < n;
-        uint32_t d = valid ? (keys[i] >> shift) & 255u : 0u;
-        uint64_t peers = match_digit(d, valid);
+        const int64_t i = base + rd * kSortThreads;
+        x[rd] = i < n ? keys[i] : 0u;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int rd = 0; rd < kSortItems; ++rd) {
+        const bool valid = base + rd * kSortThreads < n;
+        const uint32_t d = (x[rd] >> shift) & 255u;
+        const uint64_t peers = match_digit(d, valid);
         if (valid && (peers & lanemask_lt()) == 0) atomicAdd(&h[d], (uint32_t)__popcll(peers));
     }
     __syncthreads();
     hist[(size_t)threadIdx.x * nb + blockIdx.x] = h[threadIdx.x];
+}
+
+// Exclusive offset of (digit t, this workgroup) straight from the digit-major histogram:
+// sum of all counts of lower digits plus this digit's counts in lower workgroups.  Used
+// when the matrix is small (nb <= kSelfOffsetBlocks), saving the separate scan.
+constexpr int kSelfOffsetBlocks = 256;
+
+__device__ __forceinline__ uint32_t self_offset(const uint32_t *__restrict__ hist, int nb)
+{
+    __shared__ uint32_t wsum[4];
+    const int t = threadIdx.x, w = t >> 6, l = t & 63;
+    const uint32_t *row = hist + (size_t)t * nb;
+    uint32_t before = 0, total = 0;
+    for (int b = 0; b < nb; ++b) {
+        const uint32_t c = row[b];
+        before += b < (int)blockIdx.x ? c : 0u;
+        total += c;
+    }
+    uint32_t inc = total;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(inc, o, 64);
+        if (l >= o) inc += y;
+    }
+    if (l == 63) wsum[w] = inc;
+    __syncthreads();
+    uint32_t off = 0;
+    for (int k = 0; k < w; ++k) off += wsum[k];
+    return off + inc - total + before;
 }
 
 __global__ __launch_bounds__(kSortThreads) void radix_downsweep(const uint32_t *__restrict__ keys_in,
@@ -58,30 +93,36 @@ __global__ __launch_bounds__(kSortThreads) void radix_downsweep(const uint32_t *
                                                                 uint32_t *__restrict__ keys_out,
                                                                 uint32_t *__restrict__ vals_out, int64_t n,
                                                                 int shift, const uint32_t *__restrict__ offs,
-                                                                int nb)
+                                                                int nb, int scanned)
 {
     __shared__ uint32_t base_off[256];
     __shared__ uint32_t run[256];
     __shared__ uint32_t wcnt[4][256];
     const int t = threadIdx.x, w = t >> 6;
-    base_off[t] = offs[(size_t)t * nb + blockIdx.x];
-    run[t] = 0;
-    int64_t base = (int64_t)blockIdx.x * kSortTile;
+    const int64_t base = (int64_t)blockIdx.x * kSortTile + t;
+    uint32_t kx[kSortItems], vx[kSortItems];
+#pragma unroll
     for (int rd = 0; rd < kSortItems; ++rd) {
-        int64_t i = base + rd * kSortThreads + t;
-        bool valid = i < n;
-        uint32_t key = valid ? keys_in[i] : 0u;
-        uint32_t val = valid ? vals_in[i] : 0u;
-        uint32_t d = (key >> shift) & 255u;
+        const int64_t i = base + rd * kSortThreads;
+        kx[rd] = i < n ? keys_in[i] : 0u;
+        vx[rd] = i < n ? vals_in[i] : 0u;
+    }
+    base_off[t] = scanned ? offs[(size_t)t * nb + blockIdx.x] : self_offset(offs, nb);
+    run[t] = 0;
+#pragma unroll
+    for (int rd = 0; rd < kSortItems; ++rd) {
+        const bool valid = base + rd * kSortThreads < n;
+        const uint32_t key = kx[rd], val = vx[rd];
+        const uint32_t d = (key >> shift) & 255u;
         for (int c = 0; c < 4; ++c) wcnt[c][t] = 0;
         __syncthreads();
-        uint64_t peers = match_digit(d, valid);
-        uint32_t rank = (uint32_t)__popcll(peers & lanemask_lt());
+        const uint64_t peers = match_digit(d, valid);
+        const uint32_t rank = (uint32_t)__popcll(peers & lanemask_lt());
         if (valid && rank == 0) wcnt[w][d] = (uint32_t)__popcll(peers);
         __syncthreads();
         {   // thread t owns digit t: prefix over waves, advance the running count
-            uint32_t r = run[t];
-            uint32_t c0 = wcnt[0][t], c1 = wcnt[1][t], c2 = wcnt[2][t], c3 = wcnt[3][t];
+            const uint32_t r = run[t];
+            const uint32_t c0 = wcnt[0][t], c1 = wcnt[1][t], c2 = wcnt[2][t], c3 = wcnt[3][t];
             wcnt[0][t] = r;
             wcnt[1][t] = r + c0;
             wcnt[2][t] = r + c0 + c1;
@@ -90,7 +131,7 @@ __global__ __launch_bounds__(kSortThreads) void radix_downsweep(const uint32_t *
         }
         __syncthreads();
         if (valid) {
-            uint32_t dst = base_off[d] + wcnt[w][d] + rank;
+            const uint32_t dst = base_off[d] + wcnt[w][d] + rank;
             keys_out[dst] = key;
             vals_out[dst] = val;
         }
@@ -191,6 +232,30 @@ __global__ __launch_bounds__(256) void scan_down(const uint32_t *__restrict__ in
     }
 }
 
+// One workgroup scans n <= 16 * 4096 elements in rounds of 4096 with a running carry.
+__global__ __launch_bounds__(256) void scan_single(const uint32_t *__restrict__ in,
+                                                   const uint32_t *__restrict__ gather, int64_t n,
+                                                   uint32_t *__restrict__ out, uint32_t *__restrict__ total)
+{
+    uint32_t carry = 0;
+    for (int64_t first_tile = 0; first_tile < n; first_tile += kScanTile) {
+        uint32_t x[16];
+        const int64_t first = first_tile + threadIdx.x * 16;
+        load16(in, gather, n, first, x);
+        uint32_t s = 0;
+        for (int k = 0; k < 16; ++k) s += x[k];
+        uint32_t tot;
+        uint32_t off = block_excl_scan(s, &tot) + carry;
+        for (int k = 0; k < 16; ++k) {
+            const int64_t i = first + k;
+            if (i < n) out[i] = off;
+            off += x[k];
+        }
+        carry += tot;
+    }
+    if (threadIdx.x == 0 && total) *total = carry;
+}
+
 // ---------------------------------------------------------------------------------------
 // host launchers
 // ---------------------------------------------------------------------------------------
@@ -203,6 +268,10 @@ hipError_t scan_u32(const uint32_t *in, const uint32_t *gather, uint32_t *out, u
     if (n <= 0) return hipSuccess;
     int64_t nb = (n + kScanTile - 1) / kScanTile;
     if (nb > kScanTile) return hipErrorInvalidValue;
+    if (nb <= 1) {  // one tile: one launch
+        scan_single<<<1, 256, 0, s>>>(in, gather, n, out, total);
+        return hipGetLastError();
+    }
     scan_reduce<<<(unsigned)nb, 256, 0, s>>>(in, gather, n, tmp);
     scan_top<<<1, 256, 0, s>>>(tmp, (int)nb, total);
     scan_down<<<(unsigned)nb, 256, 0, s>>>(in, gather, n, tmp, out);
@@ -218,11 +287,14 @@ hipError_t radix_sort_pairs(uint32_t *keys, uint32_t *vals, uint32_t *keys_alt, 
     if (n <= 0 || bits <= 0) return hipSuccess;
     int nb = (int)((n + kSortTile - 1) / kSortTile);
     uint32_t *ki = keys, *vi = vals, *ko = keys_alt, *vo = vals_alt;
+    const int scanned = nb > kSelfOffsetBlocks;
     for (int shift = 0; shift < bits; shift += 8) {
         radix_upsweep<<<nb, kSortThreads, 0, s>>>(ki, n, shift, hist, nb);
-        hipError_t e = scan_u32(hist, nullptr, hist, nullptr, (int64_t)256 * nb, scan_tmp, s);
-        if (e != hipSuccess) return e;
-        radix_downsweep<<<nb, kSortThreads, 0, s>>>(ki, vi, ko, vo, n, shift, hist, nb);
+        if (scanned) {
+            hipError_t e = scan_u32(hist, nullptr, hist, nullptr, (int64_t)256 * nb, scan_tmp, s);
+            if (e != hipSuccess) return e;
+        }
+        radix_downsweep<<<nb, kSortThreads, 0, s>>>(ki, vi, ko, vo, n, shift, hist, nb, scanned);
         uint32_t *tk = ki, *tv = vi;
         ki = ko;
         vi = vo;

@@ -22,7 +22,7 @@ _STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ECAPACITY", 
 EXPORTS = ("lgsr_default_opts", "lgsr_default_loss_weights", "lgsr_create", "lgsr_destroy", "lgsr_set_stream",
            "lgsr_last_error", "lgsr_forward", "lgsr_loss", "lgsr_backward", "lgsr_state_free", "lgsr_query",
            "lgsr_profile", "lgsr_profile_read", "lgsr_sync")
-STAGES = ("project", "depth_sort", "scan", "emit", "tile_sort", "ranges", "raster_fwd", "loss", "bwd_zero",
+STAGES = ("project", "depth_sort", "scan", "emit", "tile_sort", "ranges", "raster_fwd", "loss", "bwd_prep",
           "raster_bwd", "chain", "readback")
 
 
@@ -46,7 +46,7 @@ class Beams(ctypes.Structure):
 class RasterOpts(ctypes.Structure):
     _fields_ = [("cutoff_sigma", ctypes.c_float), ("alpha_thr", ctypes.c_float), ("alpha_max", ctypes.c_float),
                 ("T_min", ctypes.c_float), ("near", ctypes.c_float), ("den_eps", ctypes.c_float),
-                ("drop_tau", ctypes.c_float), ("flags", ctypes.c_int32)]
+                ("drop_tau", ctypes.c_float), ("chunk", ctypes.c_int32), ("flags", ctypes.c_int32)]
 
 
 class Frame(ctypes.Structure):
@@ -296,8 +296,17 @@ def lgsr_query(ctx: Context, state: State) -> dict:
                 rays_hit=o[6])
 
 
-def lgsr_profile(ctx: Context, enable: bool):
-    ctx._check(lib().lgsr_profile(ctx.handle, 1 if enable else 0))
+def lgsr_profile(ctx: Context, stages=True):
+    """Enable stage timers: True = all stages, False = off, or an iterable of stage names."""
+    if stages is True:
+        mask = -1
+    elif not stages:
+        mask = 0
+    else:
+        mask = 0
+        for name in stages:
+            mask |= 1 << STAGES.index(name)
+    ctx._check(lib().lgsr_profile(ctx.handle, mask))
 
 
 def lgsr_profile_read(ctx: Context) -> dict:

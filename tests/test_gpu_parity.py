@@ -67,10 +67,10 @@ def _gpu_backward(ctx, dw, state, H, W, gd, go, gn, ray_ids=None):
 
 def _check_grads(name, g_gpu, gp_gpu, g_ref):
     report = {}
-    for key in G.SURF_KEYS:
-        nbad, cos, worst = G.grad_check(g_gpu[key], g_ref[key])
+    for k, key in enumerate(G.SURF_KEYS):
+        nbad, cos, worst = G.grad_check(g_gpu[key], g_ref[key], mass=g_ref["mass"][:, k])
         report[key] = (nbad, round(cos, 9), round(worst, 3))
-    nbad_p, cos_p, worst_p = G.grad_check(gp_gpu, g_ref["pose"], floor=0.0, per_row=False)
+    nbad_p, cos_p, worst_p = G.grad_check(gp_gpu, g_ref["pose"], mass=g_ref["pose_mass"], per_row=False)
     report["pose"] = (nbad_p, round(cos_p, 9), round(worst_p, 3))
     _print(name, report)
     for key, (nbad, cos, _) in report.items():
@@ -82,16 +82,19 @@ def _check_grads(name, g_gpu, gp_gpu, g_ref):
 # 32 x 256 beams, 1,000 surfels (full image)
 # ------------------------------------------------------------------------------------------
 
-def test_forward_room(ctx, room):
+@pytest.mark.parametrize("chunk", [0, 16, 4096])
+def test_forward_room(ctx, room, chunk):
+    """Full image; chunk 16 splits every tile list into many parallel chunks (merge and
+    fix-up paths), 4096 keeps each list in one chunk."""
     dw = G.to_dev(room)
-    fr, st = G.gpu_forward(ctx, dw)
+    fr, st = G.gpu_forward(ctx, dw, chunk=chunk)
     torch.cuda.synchronize()
     of = G.oracle_forward(room)
     stats = G.compare_forward(fr, of)
     from paper_2607_04127_amd import lgsr
     q = lgsr.lgsr_query(ctx, st)
     stats.update(pairs=q["pairs"], visible=q["visible"], max_list=q["max_list"])
-    _print("forward room32x256_1k", stats)
+    _print(f"forward room32x256_1k chunk={chunk}", stats)
     assert stats["tie"] < 0.01 * stats["rays"]
     st.free()
 
@@ -123,10 +126,11 @@ def test_loss_kernel(ctx, room):
     np.testing.assert_allclose(g["normal"].cpu().numpy().reshape(-1, 3), gn, rtol=1e-4, atol=1e-9)
 
 
-def test_backward_room(ctx, room):
+@pytest.mark.parametrize("chunk", [0, 16, 4096])
+def test_backward_room(ctx, room, chunk):
     H, W = room["H"], room["W"]
     dw = G.to_dev(room)
-    _, st = G.gpu_forward(ctx, dw)
+    _, st = G.gpu_forward(ctx, dw, chunk=chunk)
     of = G.oracle_forward(room)
     mask = (~G.tie_mask(of)).astype(np.float64)
     gd, go, gn = _loss_upstream(room, of, mask=mask)
@@ -134,8 +138,8 @@ def test_backward_room(ctx, room):
     rng = np.random.default_rng(4)
     go = (rng.normal(size=go.shape) * 1e-4 * mask).astype(np.float32)
     g_gpu, gp = _gpu_backward(ctx, dw, st, H, W, gd, go, gn)
-    g_ref = ref.backward(room, room["pose"], room["row_sincos"], room["col_sincos"], gd, go, gn)
-    _check_grads("backward room32x256_1k", g_gpu, gp, g_ref)
+    g_ref = ref.backward(room, room["pose"], room["row_sincos"], room["col_sincos"], gd, go, gn, with_mass=True)
+    _check_grads(f"backward room32x256_1k chunk={chunk}", g_gpu, gp, g_ref)
     st.free()
 
 
@@ -168,10 +172,11 @@ def test_end_to_end_loss_and_grad(ctx, room):
 # 64 x 1024 beams, 300,000 surfels: the benchmark configuration, sampled rays
 # ------------------------------------------------------------------------------------------
 
-def test_forward_block_sampled(ctx, block):
+@pytest.mark.parametrize("chunk", [0, 64])
+def test_forward_block_sampled(ctx, block, chunk):
     H, W = block["H"], block["W"]
     dw = G.to_dev(block)
-    fr, st = G.gpu_forward(ctx, dw)
+    fr, st = G.gpu_forward(ctx, dw, chunk=chunk)
     torch.cuda.synchronize()
     rng = np.random.default_rng(2024)
     ids = np.sort(rng.choice(H * W, size=4096, replace=False))
@@ -180,25 +185,27 @@ def test_forward_block_sampled(ctx, block):
     from paper_2607_04127_amd import lgsr
     q = lgsr.lgsr_query(ctx, st)
     stats.update(pairs=q["pairs"], visible=q["visible"], max_list=q["max_list"], mean_K=float(of["K"].mean()))
-    _print("forward block64x1024_300k (4096 sampled rays)", stats)
+    _print(f"forward block64x1024_300k (4096 sampled rays) chunk={chunk}", stats)
     assert stats["tie"] < 0.02 * stats["rays"]
     st.free()
 
 
-def test_backward_block_sampled(ctx, block):
+@pytest.mark.parametrize("chunk", [0, 64])
+def test_backward_block_sampled(ctx, block, chunk):
     """Upstream gradient nonzero on 2048 sampled rays only: the renderer's full backward
     then equals the oracle's backward restricted to those rays, for every surfel."""
     H, W = block["H"], block["W"]
     dw = G.to_dev(block)
-    _, st = G.gpu_forward(ctx, dw)
+    _, st = G.gpu_forward(ctx, dw, chunk=chunk)
     rng = np.random.default_rng(77)
     ids = np.sort(rng.choice(H * W, size=2048, replace=False))
     of = G.oracle_forward(block, ray_ids=ids)
     mask = (~G.tie_mask(of)).astype(np.float64)
     gd, go, gn = _loss_upstream(block, of, ray_ids=ids, mask=mask)
     g_gpu, gp = _gpu_backward(ctx, dw, st, H, W, gd, go, gn, ray_ids=ids)
-    g_ref = ref.backward(block, block["pose"], block["row_sincos"], block["col_sincos"], gd, go, gn, ray_ids=ids)
-    _check_grads("backward block64x1024_300k (2048 sampled rays)", g_gpu, gp, g_ref)
+    g_ref = ref.backward(block, block["pose"], block["row_sincos"], block["col_sincos"], gd, go, gn, ray_ids=ids,
+                         with_mass=True)
+    _check_grads(f"backward block64x1024_300k (2048 sampled rays) chunk={chunk}", g_gpu, gp, g_ref)
     st.free()
 
 

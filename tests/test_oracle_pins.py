@@ -434,3 +434,29 @@ def test_tiny_restatement_agrees(ref):
     np.testing.assert_allclose(out["opacity"], [x[1] for x in lit], rtol=1e-12)
     np.testing.assert_allclose(out["normal"], [x[2] for x in lit], atol=1e-12)
     np.testing.assert_array_equal(out["K"], [x[4] for x in lit])
+
+
+# ------------------------------------------------------------------------------------------
+# Gradient mass (used by the GPU tolerances): it bounds the gradient (triangle inequality)
+# and equals its norm when a single ray contributes
+# ------------------------------------------------------------------------------------------
+
+def test_gradient_mass_bounds_gradient(ref):
+    S, pose, rows, cols, td, tn = _fd_scene()
+    n = rows.shape[0] * cols.shape[0]
+    rng = np.random.default_rng(21)
+    gD, gA, gN = rng.normal(size=n), rng.normal(size=n), rng.normal(size=(n, 3))
+    g = ref.backward(S, pose, rows, cols, gD, gA, gN, PRM, with_mass=True)
+    m = g["mass"]
+    assert np.all(m >= 0) and m[:, 3].max() > 0
+    for k, key in enumerate(("means", "quats", "log_scales")):
+        assert np.all(np.linalg.norm(g[key], axis=1) <= m[:, k] * (1 + 1e-12) + 1e-300)
+    assert np.all(np.abs(g["opacity_logits"]) <= m[:, 3] * (1 + 1e-12) + 1e-300)
+    assert np.all(np.abs(g["pose"]) <= g["pose_mass"] * (1 + 1e-12))
+    # one ray: mass equals the gradient's norm
+    one = np.zeros(n)
+    i0 = int(np.nonzero(ref.forward(S, pose, rows, cols, PRM)["K"] > 0)[0][0])
+    one[i0] = 1.0
+    g1 = ref.backward(S, pose, rows, cols, one, np.zeros(n), np.zeros((n, 3)), PRM, with_mass=True)
+    np.testing.assert_allclose(np.linalg.norm(g1["means"], axis=1), g1["mass"][:, 0], rtol=1e-12, atol=1e-300)
+    np.testing.assert_allclose(np.abs(g1["opacity_logits"]), g1["mass"][:, 3], rtol=1e-12, atol=1e-300)
