@@ -372,6 +372,40 @@ static void chain_params(const surf_t *s, const double *pose, const sgrad_t *g, 
     }
 }
 
+/* chain_params on magnitudes: every coefficient and input taken by absolute value, so the
+ * result bounds the size of the terms that the signed chain adds up (running error bound). */
+static void chain_params_abs(const surf_t *s, const double *pose, const sgrad_t *g, double *dm, double *dq,
+                             double *dl, double *dlog, double *dpose)
+{
+    double P[12];
+    for (int c = 0; c < 12; ++c) P[c] = fabs(pose[c]);
+    double Ga[3], Gb[3], Gn[3];
+    sensor_to_world_dir(P, g->mu, dm);
+    sensor_to_world_dir(P, g->a, Ga);
+    sensor_to_world_dir(P, g->b, Gb);
+    sensor_to_world_dir(P, g->n, Gn);
+    double w = fabs(s->qhat[0]), x = fabs(s->qhat[1]), y = fabs(s->qhat[2]), z = fabs(s->qhat[3]);
+    double dw = 2 * (Ga[1] * z + Ga[2] * y + Gb[0] * z + Gb[2] * x + Gn[0] * y + Gn[1] * x);
+    double dx = 2 * (Ga[1] * y + Ga[2] * z + Gb[0] * y + Gb[2] * w + Gn[0] * z + Gn[1] * w) + 4 * x * (Gb[1] + Gn[2]);
+    double dy = 2 * (Ga[1] * x + Ga[2] * w + Gb[0] * x + Gb[2] * z + Gn[0] * w + Gn[1] * z) + 4 * y * (Ga[0] + Gn[2]);
+    double dz = 2 * (Ga[1] * w + Ga[2] * x + Gb[0] * w + Gb[2] * y + Gn[0] * x + Gn[1] * y) + 4 * z * (Ga[0] + Gb[1]);
+    double dqh[4] = {dw, dx, dy, dz}, qa[4] = {w, x, y, z};
+    double radial = dqh[0] * w + dqh[1] * x + dqh[2] * y + dqh[3] * z;
+    for (int c = 0; c < 4; ++c) dq[c] = (dqh[c] + radial * qa[c]) / s->qnorm;
+    dl[0] = s->s0 * g->s0;
+    dl[1] = s->s1 * g->s1;
+    *dlog = s->alpha * (1 - s->alpha) * g->alpha;
+    const double *vec[4] = {s->mu, s->a, s->b, s->n};
+    const double *gv[4] = {g->mu, g->a, g->b, g->n};
+    for (int c = 0; c < 3; ++c) {
+        dpose[c] = g->mu[c];
+        double acc = 0;
+        int c1 = (c + 1) % 3, c2 = (c + 2) % 3;
+        for (int k = 0; k < 4; ++k) acc += fabs(vec[k][c1]) * gv[k][c2] + fabs(vec[k][c2]) * gv[k][c1];
+        dpose[3 + c] = acc;
+    }
+}
+
 static double norm_n(const double *v, int n)
 {
     double q = 0;
@@ -422,6 +456,11 @@ int lgsr_ref_backward(const lgsr_ref_map *map, const double pose[12], const lgsr
             for (int c = 0; c < 3; ++c) gbN[c] = gN[c] / A;
             double gbA = g_opacity[i] - (g_depth[i] * Dh + dot3(gN, Nh)) / A;
             double B = 0; /* sum over later hits of w_i c_i */
+            /* magnitudes of the same quantities before any cancellation (test tolerances) */
+            double abD = fabs(g_depth[i]) / A, abN[3], abA, Babs = 0;
+            for (int c = 0; c < 3; ++c) abN[c] = fabs(gN[c]) / A;
+            abA = fabs(g_opacity[i]) + (fabs(g_depth[i]) * fabs(Dh) + fabs(gN[0] * Nh[0]) + fabs(gN[1] * Nh[1])
+                                         + fabs(gN[2] * Nh[2])) / A;
             for (int j = r.K - 1; j >= 0; --j) {
                 const hit_t *h = &hits[j];
                 const surf_t *s = &S[h->i];
@@ -459,16 +498,32 @@ int lgsr_ref_backward(const lgsr_ref_map *map, const double pose[12], const lgsr
                 atomic_add(&g->s1, -d_v * h->v / s->s1);
                 atomic_add(&g->alpha, d_alpha);
                 if (mass || pose_mass) {
-                    /* size of this one contribution in parameter space (test tolerances) */
+                    /* the same contribution evaluated on magnitudes: a running error bound of
+                     * the terms a finite-precision evaluation adds up (test tolerances) */
+                    double ca = abD * fabs(h->t) + fabs(abN[0] * s->nt[0]) + fabs(abN[1] * s->nt[1])
+                              + fabs(abN[2] * s->nt[2]) + abA;
+                    double ahA = h->T * ca + Babs / (1 - h->ahat);
+                    Babs += w * ca;
+                    double aA = 0, aG = 0;
+                    if (h->aG < prm->alpha_max) { aA = ahA * h->G; aG = ahA * s->alpha; }
+                    double aq2 = 0.5 * h->G * aG, au = 2 * fabs(h->u) * aq2, av = 2 * fabs(h->v) * aq2;
+                    double aT = abD * w, aDel[3], aTt, ad = fabs(h->den);
                     sgrad_t one;
                     for (int c = 0; c < 3; ++c) {
-                        one.mu[c] = g_mu[c]; one.a[c] = g_a[c]; one.b[c] = g_b[c]; one.n[c] = g_n[c];
+                        aDel[c] = au * fabs(s->a[c]) / s->s0 + av * fabs(s->b[c]) / s->s1;
+                        one.a[c] = au * fabs(h->delta[c]) / s->s0;
+                        one.b[c] = av * fabs(h->delta[c]) / s->s1;
                     }
-                    one.s0 = -d_u * h->u / s->s0;
-                    one.s1 = -d_v * h->v / s->s1;
-                    one.alpha = d_alpha;
+                    aTt = aT + aDel[0] * fabs(d[0]) + aDel[1] * fabs(d[1]) + aDel[2] * fabs(d[2]);
+                    for (int c = 0; c < 3; ++c) {
+                        one.mu[c] = aDel[c] + aTt * fabs(s->n[c]) / ad;
+                        one.n[c] = aTt * fabs(h->delta[c]) / ad + abN[c] * w;
+                    }
+                    one.s0 = au * fabs(h->u) / s->s0;
+                    one.s1 = av * fabs(h->v) / s->s1;
+                    one.alpha = aA;
                     double dm[3], dq[4], dl[2], dlog, dp[6];
-                    chain_params(s, pose, &one, dm, dq, dl, &dlog, dp);
+                    chain_params_abs(s, pose, &one, dm, dq, dl, &dlog, dp);
                     if (mass) {
                         atomic_add(&mass[4 * h->i + 0], norm_n(dm, 3));
                         atomic_add(&mass[4 * h->i + 1], norm_n(dq, 4));

@@ -76,9 +76,11 @@ int lgsr_ref_loss(int64_t n_rays, const double *depth, const double *opacity, co
 /* Backward of lgsr_ref_forward: given dL/d(depth, opacity, normal) per ray, accumulate the
  * gradient with respect to every surfel parameter (outputs are overwritten) and the pose in
  * the right-perturbation tangent (rho, omega) of T_ws * Exp(xi).
- * Optional (NULL to skip), for test tolerances: mass (n x 4) receives per surfel the sum
- * over rays of the norm of each ray's contribution to the gradient of means, quats,
- * log_scales and opacity_logit; pose_mass[6] the sum of |contribution| per pose component. */
+ * Optional (NULL to skip), for test tolerances: mass (n x 4) receives per surfel, for the
+ * gradient of means, quats, log_scales and opacity_logit, the sum over rays of the norm of
+ * each ray's contribution evaluated on magnitudes (every term and coefficient by absolute
+ * value, before any cancellation: a running error bound); pose_mass[6] likewise per pose
+ * component. */
 int lgsr_ref_backward(const lgsr_ref_map *map, const double pose[12], const lgsr_ref_beams *beams,
                       const lgsr_ref_params *prm, int64_t n_rays, const int64_t *ray_ids,
                       const double *g_depth, const double *g_opacity, const double *g_normal,
