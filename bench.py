@@ -59,6 +59,9 @@ def main():
     ap.add_argument("--workload", default="block64x1024_300k")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU oracle sample time")
+    ap.add_argument("--chunk", type=int, default=0, help="list entries per raster chunk (0 = automatic)")
+    ap.add_argument("--calib-copy", type=int, default=0,
+                    help="bytes of one plain device copy issued before the steps (calibrates counters)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -95,9 +98,16 @@ def main():
     loss = torch.empty(5, device=dev)
     gpose = torch.empty(6, device=dev)
     ctx = lgsr.Context(0)
+    opts = lgsr.default_opts(chunk=args.chunk)
+    if args.calib_copy:
+        src = torch.empty(args.calib_copy // 4, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     def step():
-        _, st = lgsr.lgsr_forward(ctx, S, pose, rows, cols, out=frame)
+        _, st = lgsr.lgsr_forward(ctx, S, pose, rows, cols, opts=opts, out=frame)
         lgsr.lgsr_loss(ctx, frame, td, tn, loss_out=loss, grad_out=fgrad)
         lgsr.lgsr_backward(ctx, st, fgrad, out=sgrad, grad_pose=gpose)
         st.free()
@@ -138,7 +148,7 @@ def main():
     lgsr.lgsr_profile(ctx, False)
 
     # work counters of one forward (same inputs, deterministic lists)
-    _, st = lgsr.lgsr_forward(ctx, S, pose, rows, cols, out=frame)
+    _, st = lgsr.lgsr_forward(ctx, S, pose, rows, cols, opts=opts, out=frame)
     q = lgsr.lgsr_query(ctx, st)
     st.free()
     stages = {k: dict(ms_per_call=(v[0] / v[1] if v[1] else 0.0), calls=v[1]) for k, v in prof.items()}
@@ -168,7 +178,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic (seeded street-block scene, virtual-scan surfels, exact raycast targets)",
-        "config": {"workload": args.workload, "rays": rays, "H": H, "W": W, "surfels": n,
+        "config": {"workload": args.workload, "rays": rays, "H": H, "W": W, "surfels": n, "chunk": args.chunk,
                    "pairs": q["pairs"], "visible_surfels": q["visible"], "max_tile_list": q["max_list"],
                    "ray_tests": q["ray_tests"], "composites": q["composites"], "rays_hit": q["rays_hit"],
                    "loss": "depth L1 + G-ICP normal cosine", "step_latency_ms_p50": round(p50, 4),

@@ -131,41 +131,70 @@ __device__ __forceinline__ uint4 uniform_chunk(const uint4 *__restrict__ chunks,
                       __builtin_amdgcn_readfirstlane(c.z), 0u);
 }
 
-// A chunk's list entries staged in LDS: ids, ray rectangles and 64-byte records, loaded
-// by the whole workgroup with coalesced vector loads (one memory latency per stage instead
-// of a dependent id -> rectangle -> record chain per entry).
+// A chunk's list entries staged in LDS by the whole workgroup: surfel ids, the 64-byte
+// records (coalesced vector loads, one memory latency per stage) and, for each of the four
+// waves, the compacted in-order list of entries whose ray rectangle meets the wave's
+// sub-tile (one packed block-wide prefix count), so that a wave walks only its own entries
+// with no per-entry test and records no wave needs are never loaded.
 constexpr int kStage = 256;
 struct Staged {
     float4 rec[kStage][4];
-    uint2 rect[kStage];
     uint32_t id[kStage];
+    uint16_t list[4][kStage];
+    uint8_t mask[kStage];
+    uint64_t wtot[4];
+    uint32_t cnt[4];
 };
 
-// All 256 threads; n <= kStage entries from list position a.  Ends with a barrier.
+// All 256 threads; n <= kStage entries from list position a; (r16, c16) is the tile origin.
+// Ends with a barrier.
 __device__ __forceinline__ void stage_entries(Staged &sm, const uint32_t *__restrict__ ids,
                                               const float *__restrict__ recs, const uint2 *__restrict__ rects,
-                                              uint32_t a, uint32_t n)
+                                              uint32_t a, uint32_t n, int r16, int c16, int H, int W)
 {
-    const int t = threadIdx.x;
+    const int t = threadIdx.x, wv = t >> 6, l = t & 63;
+    uint32_t m = 0;
     if ((uint32_t)t < n) {
         const uint32_t id = ids[a + t];
+        const uint2 rc = rects[id];
         sm.id[t] = id;
-        sm.rect[t] = rects[id];
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+            const int sr = r16 + (w >> 1) * kSub, sc = c16 + (w & 1) * kSub;
+            if (sr < H && sc < W && sub_overlap(rc, sr, sc, W)) m |= 1u << w;
+        }
     }
+    sm.mask[t] = (uint8_t)m;
+    // exclusive prefix counts of the four membership flags, 16-bit fields of one u64
+    const uint64_t packed = (uint64_t)(m & 1u) | ((uint64_t)((m >> 1) & 1u) << 16) |
+                            ((uint64_t)((m >> 2) & 1u) << 32) | ((uint64_t)((m >> 3) & 1u) << 48);
+    uint64_t inc = packed;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint64_t y = __shfl_up(inc, o, 64);
+        if (l >= o) inc += y;
+    }
+    if (l == 63) sm.wtot[wv] = inc;
+    __syncthreads();
+    uint64_t off = 0, tot = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const uint64_t s = sm.wtot[k];
+        off += k < wv ? s : 0ull;
+        tot += s;
+    }
+    const uint64_t excl = off + inc - packed;
+#pragma unroll
+    for (int w = 0; w < 4; ++w)
+        if ((m >> w) & 1u) sm.list[w][(excl >> (16 * w)) & 0xFFFFu] = (uint16_t)t;
+    if (t < 4) sm.cnt[t] = (uint32_t)((tot >> (16 * t)) & 0xFFFFu);
     __syncthreads();
     const float4 *r4 = reinterpret_cast<const float4 *>(recs);
     for (uint32_t k = t; k < 4u * n; k += 256u) {
         const uint32_t e = k >> 2, q = k & 3u;
-        sm.rec[e][q] = r4[(size_t)sm.id[e] * 4 + q];
+        if (sm.mask[e]) sm.rec[e][q] = r4[(size_t)sm.id[e] * 4 + q];
     }
     __syncthreads();
-}
-
-__device__ __forceinline__ bool staged_overlap(const Staged &sm, uint32_t e, const Lane &L, int W)
-{
-    const uint2 rc = sm.rect[e];
-    const uint2 su = make_uint2(__builtin_amdgcn_readfirstlane(rc.x), __builtin_amdgcn_readfirstlane(rc.y));
-    return sub_overlap(su, L.sr0, L.sc0, W);
 }
 
 __device__ __forceinline__ Rec staged_rec(const Staged &sm, uint32_t e)
@@ -180,16 +209,18 @@ __device__ __forceinline__ Rec staged_rec(const Staged &sm, uint32_t e)
 __device__ __forceinline__ void composite(Staged &sm, const uint32_t *__restrict__ ids,
                                           const float *__restrict__ recs, const uint2 *__restrict__ rects,
                                           uint32_t a, uint32_t b, const Lane &L, const Ray &ray,
-                                          const RasterParams &p, int W, bool active, Acc &acc)
+                                          const RasterParams &p, int H, int W, bool active, Acc &acc)
 {
     bool done = !active || !L.wave_in;
+    const int r16 = L.sr0 - (L.wave >> 1) * kSub, c16 = L.sc0 - (L.wave & 1) * kSub;
     for (uint32_t base = a; base < b; base += kStage) {
         const uint32_t n = min((uint32_t)kStage, b - base);
         if (base != a) __syncthreads();  // the previous stage is no longer read
-        stage_entries(sm, ids, recs, rects, base, n);
+        stage_entries(sm, ids, recs, rects, base, n, r16, c16, H, W);
         if (__all(done)) continue;
-        for (uint32_t e = 0; e < n; ++e) {
-            if (!staged_overlap(sm, e, L, W)) continue;
+        const uint32_t cnt = __builtin_amdgcn_readfirstlane(sm.cnt[L.wave]);
+        for (uint32_t i = 0; i < cnt; ++i) {
+            const uint32_t e = __builtin_amdgcn_readfirstlane(sm.list[L.wave][i]);
             const Rec s = staged_rec(sm, e);
             const Hit h = hit_test(s, ray, p);
             if (h.pass && !done) {
@@ -221,7 +252,7 @@ __global__ __launch_bounds__(256) void raster_fwd_chunk_kernel(
     const Lane L = lane_of((int)ch.x, g);
     Ray ray = make_ray(rows, cols, L.valid ? L.k : 0, L.valid ? L.j : 0);
     Acc acc{1.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0, -1};
-    composite(sm, ids, recs, rects, ch.y, ch.z, L, ray, p, g.W, L.valid, acc);
+    composite(sm, ids, recs, rects, ch.y, ch.z, L, ray, p, g.H, g.W, L.valid, acc);
     if (!L.valid) return;
     slots[slot(item, F_TEND, L.rt)] = acc.T;
     slots[slot(item, F_SA, L.rt)] = acc.A;
@@ -274,42 +305,58 @@ __global__ __launch_bounds__(256) void raster_merge_kernel(const uint32_t *__res
     float T = 1.f, A = 0.f, SD = 0.f, SN0 = 0.f, SN1 = 0.f, SN2 = 0.f;
     int K = 0, fix = -1;
     float4 fa = make_float4(0.f, 0.f, 0.f, 0.f), fb = make_float4(0.f, 0.f, 0.f, __int_as_float(-1));
-    for (uint32_t it = c0; it < c1; ++it) {
-        if (fix >= 0 || T < p.T_min) {  // after termination: the chunk contributes nothing
-            slots[slot(it, F_LAST, L.rt)] = __int_as_float(-1);
-            continue;
+    constexpr int kB = 8;  // chunks whose slots are loaded together (one memory latency per batch)
+    for (uint32_t it0 = c0; it0 < c1; it0 += kB) {
+        float v[kB][7];
+#pragma unroll
+        for (int q = 0; q < kB; ++q) {
+            const uint32_t it = it0 + q;
+            if (it < c1) {
+                v[q][0] = slots[slot(it, F_K, L.rt)];
+                v[q][1] = slots[slot(it, F_TEND, L.rt)];
+                v[q][2] = slots[slot(it, F_SA, L.rt)];
+                v[q][3] = slots[slot(it, F_SD, L.rt)];
+                v[q][4] = slots[slot(it, F_SN0, L.rt)];
+                v[q][5] = slots[slot(it, F_SN1, L.rt)];
+                v[q][6] = slots[slot(it, F_SN2, L.rt)];
+            }
         }
-        const int Kl = __float_as_int(slots[slot(it, F_K, L.rt)]);
-        if (Kl == 0) {
-            slots[slot(it, F_TEND, L.rt)] = T;
-            continue;
+#pragma unroll
+        for (int q = 0; q < kB; ++q) {
+            const uint32_t it = it0 + q;
+            if (it >= c1) break;
+            if (fix >= 0 || T < p.T_min) {  // after termination: the chunk contributes nothing
+                slots[slot(it, F_LAST, L.rt)] = __int_as_float(-1);
+                continue;
+            }
+            const int Kl = __float_as_int(v[q][0]);
+            if (Kl == 0) {
+                slots[slot(it, F_TEND, L.rt)] = T;
+                continue;
+            }
+            const float Tn = T * v[q][1];
+            if (it > c0 && Tn < p.T_min) {  // the ray terminates inside this chunk: re-walk it
+                fix = (int)it;
+                fa = make_float4(T, A, SD, __int_as_float(K));
+                fb = make_float4(SN0, SN1, SN2, __int_as_float(fix));
+                slots[slot(it, F_LAST, L.rt)] = __int_as_float(-1);
+                continue;
+            }
+            const float gA = T * v[q][2], gD = T * v[q][3], g0 = T * v[q][4], g1 = T * v[q][5], g2 = T * v[q][6];
+            slots[slot(it, F_TEND, L.rt)] = Tn;
+            slots[slot(it, F_SA, L.rt)] = gA;
+            slots[slot(it, F_SD, L.rt)] = gD;
+            slots[slot(it, F_SN0, L.rt)] = g0;
+            slots[slot(it, F_SN1, L.rt)] = g1;
+            slots[slot(it, F_SN2, L.rt)] = g2;
+            A += gA;
+            SD += gD;
+            SN0 += g0;
+            SN1 += g1;
+            SN2 += g2;
+            K += Kl;
+            T = Tn;
         }
-        const float Tl = slots[slot(it, F_TEND, L.rt)];
-        const float Tn = T * Tl;
-        if (it > c0 && Tn < p.T_min) {  // the ray terminates inside this chunk: re-walk it
-            fix = (int)it;
-            fa = make_float4(T, A, SD, __int_as_float(K));
-            fb = make_float4(SN0, SN1, SN2, __int_as_float(fix));
-            slots[slot(it, F_LAST, L.rt)] = __int_as_float(-1);
-            continue;
-        }
-        const float Al = slots[slot(it, F_SA, L.rt)], SDl = slots[slot(it, F_SD, L.rt)];
-        const float S0 = slots[slot(it, F_SN0, L.rt)], S1 = slots[slot(it, F_SN1, L.rt)];
-        const float S2 = slots[slot(it, F_SN2, L.rt)];
-        const float gA = T * Al, gD = T * SDl, g0 = T * S0, g1 = T * S1, g2 = T * S2;
-        slots[slot(it, F_TEND, L.rt)] = Tn;
-        slots[slot(it, F_SA, L.rt)] = gA;
-        slots[slot(it, F_SD, L.rt)] = gD;
-        slots[slot(it, F_SN0, L.rt)] = g0;
-        slots[slot(it, F_SN1, L.rt)] = g1;
-        slots[slot(it, F_SN2, L.rt)] = g2;
-        A += gA;
-        SD += gD;
-        SN0 += g0;
-        SN1 += g1;
-        SN2 += g2;
-        K += Kl;
-        T = Tn;
     }
     const int r = L.k * g.W + L.j;
     fixA[r] = fa;
@@ -341,7 +388,7 @@ __global__ __launch_bounds__(256) void raster_fixup_kernel(
     if (!__syncthreads_or(pend)) return;  // whole workgroup
     Ray ray = make_ray(rows, cols, L.valid ? L.k : 0, L.valid ? L.j : 0);
     Acc acc{pend ? fa.x : 1.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0, -1};
-    composite(sm, ids, recs, rects, ch.y, ch.z, L, ray, p, g.W, pend, acc);
+    composite(sm, ids, recs, rects, ch.y, ch.z, L, ray, p, g.H, g.W, pend, acc);
     if (!pend) return;
     slots[slot(item, F_TEND, L.rt)] = acc.T;
     slots[slot(item, F_SA, L.rt)] = acc.A;
@@ -390,13 +437,35 @@ __global__ __launch_bounds__(256) void raster_bwd_prep_kernel(const uint32_t *__
     gb1[r] = gbA;
     const uint32_t c0 = chunk_base[tile], c1 = chunk_base[tile + 1];
     float B = 0.f;
-    for (uint32_t it = c1; it-- > c0;) {
-        slots[slot(it, F_B, L.rt)] = B;
-        if (K == 0 || __float_as_int(slots[slot(it, F_LAST, L.rt)]) < 0) continue;
-        const float SA = slots[slot(it, F_SA, L.rt)], SD = slots[slot(it, F_SD, L.rt)];
-        const float S0 = slots[slot(it, F_SN0, L.rt)], S1 = slots[slot(it, F_SN1, L.rt)];
-        const float S2 = slots[slot(it, F_SN2, L.rt)];
-        B = fmaf(gbD, SD, fmaf(gbN0, S0, fmaf(gbN1, S1, fmaf(gbN2, S2, fmaf(gbA, SA, B)))));
+    if (K == 0) {
+        for (uint32_t it = c0; it < c1; ++it) slots[slot(it, F_B, L.rt)] = 0.f;
+        return;
+    }
+    constexpr int kB = 8;  // chunks whose slots are loaded together (one memory latency per batch)
+    for (uint32_t top = c1; top > c0;) {
+        const uint32_t lo = top - c0 > (uint32_t)kB ? top - kB : c0;
+        float v[kB][6];
+#pragma unroll
+        for (int q = 0; q < kB; ++q) {
+            const uint32_t it = top - 1 - q;
+            if (it >= lo && it < top) {
+                v[q][0] = slots[slot(it, F_LAST, L.rt)];
+                v[q][1] = slots[slot(it, F_SA, L.rt)];
+                v[q][2] = slots[slot(it, F_SD, L.rt)];
+                v[q][3] = slots[slot(it, F_SN0, L.rt)];
+                v[q][4] = slots[slot(it, F_SN1, L.rt)];
+                v[q][5] = slots[slot(it, F_SN2, L.rt)];
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < kB; ++q) {
+            const uint32_t it = top - 1 - q;
+            if (it < lo || it >= top) break;
+            slots[slot(it, F_B, L.rt)] = B;
+            if (__float_as_int(v[q][0]) < 0) continue;
+            B = fmaf(gbD, v[q][2], fmaf(gbN0, v[q][3], fmaf(gbN1, v[q][4], fmaf(gbN2, v[q][5], fmaf(gbA, v[q][1], B)))));
+        }
+        top = lo;
     }
 }
 
@@ -480,17 +549,19 @@ __global__ __launch_bounds__(256) void raster_bwd_chunk_kernel(
     const int wmax = wave_max_i(last);
     if (!__syncthreads_or(last >= 0)) return;  // whole workgroup: nothing to propagate
     const uint32_t a = ch.y, b = ch.z;
+    const int r16 = L.sr0 - (L.wave >> 1) * kSub, c16 = L.sc0 - (L.wave & 1) * kSub;
     const uint32_t nstages = (b - a + kStage - 1) / kStage;
     for (uint32_t sidx = nstages; sidx-- > 0;) {
         const uint32_t base = a + sidx * kStage;
         const uint32_t n = min((uint32_t)kStage, b - base);
         if (sidx + 1 != nstages) __syncthreads();  // the previous stage is no longer read
-        stage_entries(sm, ids, recs, rects, base, n);
+        stage_entries(sm, ids, recs, rects, base, n, r16, c16, g.H, g.W);
         if (wmax < (int)base) continue;
-        const uint32_t e_hi = min(n, (uint32_t)(wmax - (int)base) + 1u);
-        for (uint32_t e = e_hi; e-- > 0;) {
-            if (!staged_overlap(sm, e, L, g.W)) continue;
+        const uint32_t cnt = __builtin_amdgcn_readfirstlane(sm.cnt[L.wave]);
+        for (uint32_t i = cnt; i-- > 0;) {
+            const uint32_t e = __builtin_amdgcn_readfirstlane(sm.list[L.wave][i]);
             const int pos = (int)(base + e);
+            if (pos > wmax) continue;
             const Rec s = staged_rec(sm, e);
             float gv[12];
 #pragma unroll
@@ -548,8 +619,9 @@ __global__ __launch_bounds__(256) void raster_bwd_chunk_kernel(
 int chunk_size(int64_t P, int requested)
 {
     if (requested > 0) return requested;
-    // about 2048 chunks (8 resident waves on each of 1024 SIMDs), at most one LDS stage each
-    int64_t s = (P + 2047) / 2048;
+    // about 4096 chunks (several rounds of 8 resident waves on each of 1024 SIMDs; short
+    // chunks also keep the re-walk of a terminating ray short), at most one LDS stage each
+    int64_t s = (P + 4095) / 4096;
     s = (s + 15) / 16 * 16;
     if (s < 32) s = 32;
     if (s > kStage) s = kStage;
