@@ -2,6 +2,8 @@
 
     python -m oracle.build        # writes oracle/liblgsr_ref.so
 """
+from __future__ import annotations
+
 import os
 import subprocess
 import sys
@@ -10,17 +12,19 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB = os.path.join(HERE, "liblgsr_ref.so")
 
 
-def build(verbose: bool = False) -> str:
-    src = os.path.join(HERE, "lgsr_ref.c")
-    tmp = LIB + ".tmp"
+def build(verbose: bool = False, src: str | None = None, out: str | None = None) -> str:
+    """Compile lgsr_ref.c (or the copy at `src`) into LIB (or `out`)."""
+    src = src or os.path.join(HERE, "lgsr_ref.c")
+    out = out or LIB
+    tmp = out + ".tmp"
     # strict IEEE float64: no fast-math, no contraction into FMA
     cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
            "-Wall", "-Wextra", "-o", tmp, src, "-lm"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":

@@ -271,7 +271,7 @@ int lgsr_ref_forward(const lgsr_ref_map *map, const double pose[12], const lgsr_
     return 0;
 }
 
-/* Sec. 3.4: masked depth L1 (Eq. 8, left) and G-ICP normal cosine term (Eq. 9, first term),
+/* Sec. 3.4: masked depth L1 (Eq. 10, left) and G-ICP normal cosine term (Eq. 11, first term),
  * L = w_depth * L_depth + lambda_n * lambda_ng * mean_{Omega_N}(1 - Nhat^T N / |Nhat|).
  * Empty masks give a zero term; sign(0) = 0; a zero rendered normal costs 1 with no gradient. */
 int lgsr_ref_loss(int64_t n_rays, const double *depth, const double *opacity, const double *normal,

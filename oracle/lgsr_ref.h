@@ -12,7 +12,7 @@
  *     intersection of the cited 2DGS work;
  *   - log-scale parameterisation s = exp(s~) (Sec. 3.3, range-adaptive scale init);
  *   - valid-depth mask M_D = [D > 0], masked depth L1 and the cosine normal loss with
- *     mask M_N = M_D * [|N| > 0] (Sec. 3.4, Eq. 8 left and Eq. 9 first term);
+ *     mask M_N = M_D * [|N| > 0] (Sec. 3.4, Eq. 10 left and Eq. 11 first term);
  *   - weights lambda_n = 1 and lambda_{n,g} = 0.05 (Sec. 4.1, implementation details).
  * Readings where the paper is silent (compositing order, stabilisers, beam model, pose
  * convention) are stated beside each function in lgsr_ref.c.

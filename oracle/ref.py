@@ -38,9 +38,10 @@ class _Beams(ctypes.Structure):
 def lib():
     global _lib
     if _lib is None:
-        path = _build.LIB
+        # LGSR_REF_LIB names another build of the oracle (the mutation tests use it)
+        path = os.environ.get("LGSR_REF_LIB") or _build.LIB
         src = os.path.join(_build.HERE, "lgsr_ref.c")
-        if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(src):
+        if path == _build.LIB and (not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(src)):
             _build.build()
         L = ctypes.CDLL(path)
         vp, i64 = ctypes.c_void_p, ctypes.c_int64

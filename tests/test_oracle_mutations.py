@@ -1,0 +1,79 @@
+"""The oracle's pins must catch plausible mistakes.  Each case plants one slip (a dropped
+term, a wrong sign, a wrong index or scale, a transposed operand) in a temporary copy of
+oracle/lgsr_ref.c, compiles the copy on the CPU and runs the pin tests against it in a
+subprocess (LGSR_REF_LIB); at least one pin must fail.  The oracle itself is not touched."""
+import concurrent.futures
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "lgsr_ref.c")
+
+# name -> (text in lgsr_ref.c, replacement)
+MUTATIONS = {
+    # forward
+    "u_uses_minor_scale": ("double u = dot3(s->a, delta) / s->s0;", "double u = dot3(s->a, delta) / s->s1;"),
+    "transmittance_half_step": ("T *= (1 - ahat);", "T *= (1 - 0.5 * ahat);"),
+    "depth_weight_is_T": ("SD += w * t;", "SD += T * t;"),
+    "normal_not_normalised": ("for (int c = 0; c < 3; ++c) normal[3 * i + c] = r.SN[c] / r.A;",
+                              "for (int c = 0; c < 3; ++c) normal[3 * i + c] = r.SN[c];"),
+    "orientation_flipped": ("s->sigma = dot3(s->n, s->mu) <= 0 ? 1.0 : -1.0;",
+                            "s->sigma = dot3(s->n, s->mu) <= 0 ? -1.0 : 1.0;"),
+    "order_ignores_range": ("if (ri < rj) return -1;\n    if (ri > rj) return 1;", "if (0) return -1;"),
+    "quaternion_sign": ("a[1] = 2 * (x * y + w * z);", "a[1] = 2 * (x * y - w * z);"),
+    "pose_transposed": ("o[j] = pose[j] * v[0] + pose[4 + j] * v[1] + pose[8 + j] * v[2];",
+                        "o[j] = pose[4 * j] * v[0] + pose[4 * j + 1] * v[1] + pose[4 * j + 2] * v[2];"),
+    # loss
+    "normal_loss_gradient_unprojected": (
+        "for (int c = 0; c < 3; ++c) g_normal[3 * i + c] = f * (N[c] - cosv * Nh[c] / nn);",
+        "for (int c = 0; c < 3; ++c) g_normal[3 * i + c] = f * N[c];"),
+    # backward
+    "backward_drops_later_hits": ("double d_ahat = h->T * cj - B / (1 - h->ahat);", "double d_ahat = h->T * cj;"),
+    "clamp_passes_gradient": ("if (h->aG < prm->alpha_max) { d_alpha = d_ahat * h->G; d_G = d_ahat * s->alpha; }",
+                              "{ d_alpha = d_ahat * h->G; d_G = d_ahat * s->alpha; }"),
+    "scale_gradient_sign": ("atomic_add(&g->s0, -d_u * h->u / s->s0);", "atomic_add(&g->s0, d_u * h->u / s->s0);"),
+    "normal_gradient_sign": ("g_n[c] = -g_t * h->delta[c] / h->den + s->sigma * d_nt[c];",
+                             "g_n[c] = g_t * h->delta[c] / h->den + s->sigma * d_nt[c];"),
+    "quaternion_gradient_unprojected": (
+        "for (int c = 0; c < 4; ++c) dq[c] = (dqh[c] - radial * s->qhat[c]) / s->qnorm;",
+        "for (int c = 0; c < 4; ++c) dq[c] = dqh[c] / s->qnorm;"),
+    "pose_rotation_sign": ("dpose[3 + c] = -(c1[c] + c2[c] + c3[c] + c4[c]);",
+                           "dpose[3 + c] = (c1[c] + c2[c] + c3[c] + c4[c]);"),
+}
+
+
+def _run_case(name, tmp):
+    from oracle import build as oracle_build
+    orig = open(SRC).read()
+    a, b = MUTATIONS[name]
+    src = os.path.join(tmp, f"{name}.c")
+    with open(src, "w") as f:
+        f.write(orig.replace(a, b, 1))
+    # the copy includes its header from the oracle directory
+    lib = oracle_build.build(src=src, out=os.path.join(tmp, f"lib_{name}.so"))
+    env = dict(os.environ, LGSR_REF_LIB=lib, OMP_NUM_THREADS="1")
+    r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider",
+                        os.path.join(ROOT, "tests", "test_oracle_pins.py")],
+                       cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+    return name, r.returncode, r.stdout.strip().splitlines()[-1] if r.stdout.strip() else r.stderr[-300:]
+
+
+def test_mutations_apply():
+    orig = open(SRC).read()
+    for name, (a, _) in MUTATIONS.items():
+        assert orig.count(a) == 1, f"{name}: the planted text must occur once in lgsr_ref.c"
+
+
+def test_every_mutation_fails_a_pin(tmp_path):
+    import shutil
+    shutil.copy(os.path.join(ROOT, "oracle", "lgsr_ref.h"), tmp_path / "lgsr_ref.h")
+    workers = min(8, os.cpu_count() or 1)
+    with concurrent.futures.ThreadPoolExecutor(workers) as ex:
+        results = list(ex.map(lambda n: _run_case(n, str(tmp_path)), MUTATIONS))
+    survivors = [(n, last) for n, rc, last in results if rc == 0]
+    for n, rc, last in results:
+        print(f"{n:36s} rc={rc} {last}")
+    assert not survivors, f"mutations that no pin caught: {survivors}"
