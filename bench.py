@@ -21,13 +21,13 @@ if ROOT not in sys.path:
 
 METRIC = "rendered rays/s fwd+bwd @64×1024, 300k surfels; p50/p99 batched render latency"
 
-# Algorithmic float32 operations of the backward raster (FMA = 2): per ray-surfel test
-# (ray direction offsets, plane denominator, two homogeneous tangent coordinates,
-# reciprocal, range, squared radius, Gaussian, opacity clamp and the four threshold tests)
-# and per composited hit (transmittance recovery, dL/dalpha_hat, the clamp, and the
-# gradients w.r.t. the 11 record quantities).
+# Algorithmic float32 operations of the raster (FMA = 2): per ray-surfel test (ray direction
+# offsets, plane denominator, two homogeneous tangent coordinates, reciprocal, range,
+# squared radius, Gaussian, opacity clamp and the four threshold tests), per composited hit
+# forward (weight, the four sums, transmittance, stop test) and backward (transmittance
+# recovery, dL/dalpha_hat, the clamp, and the gradients w.r.t. the 13 record quantities).
 FLOPS_TEST = 37
-FLOPS_COMPOSITE_BWD = 55
+FLOPS_COMPOSITE_BWD = 53
 FLOPS_COMPOSITE_FWD = 13
 # MI355X float32 vector peak without packed (dual) float32 math: 256 CUs x 64 lanes x
 # 2 flops (FMA) x 2.4 GHz.  The published 157.3 TFLOP/s counts packed float32, which this
@@ -40,13 +40,14 @@ PEAK_HBM_GBS = 8000.0
 def _bytes_model(n, P, rays):
     """Bytes a tile-binned forward + backward must move (record and gradient layouts of
     this implementation): per surfel the parameters (40 B) read twice, the 64 B record
-    written once, the 48 B record gradient zeroed, added and read, 40 B of parameter
-    gradients written; per (surfel, tile) pair the 8 B pair written by emission, one read +
-    write per sort pass (counted once), the record and id read by both rasters; per ray the
-    beam tables, 21 B of frame output, 32 B per-ray state written and read, 16 B of targets
-    and 20 B of loss gradient written and read."""
-    per_surfel = 40 + 64 + 40 + 3 * 48 + 40
-    per_pair = 8 + 16 + 2 * (64 + 4 + 8)
+    written once, the range key written once, the 52 B record gradient zeroed, added and
+    read, 40 B of parameter gradients written; per (surfel, tile) pair the 4 B id written by
+    emission, read, its range key gathered and written back by the per-tile sort, the
+    record, id and ray rectangle read by both rasters; per ray the beam tables, 21 B of
+    frame output, 32 B per-ray state written and read, 16 B of targets and 20 B of loss
+    gradient written and read."""
+    per_surfel = 40 + 64 + 4 + 40 + 3 * 52 + 40
+    per_pair = 4 + 12 + 2 * (64 + 4 + 8)
     per_ray = 21 + 2 * 32 + 16 + 2 * 20 + 8
     return n * per_surfel + P * per_pair + rays * per_ray
 
@@ -180,7 +181,8 @@ def main():
         "data": "synthetic (seeded street-block scene, virtual-scan surfels, exact raycast targets)",
         "config": {"workload": args.workload, "rays": rays, "H": H, "W": W, "surfels": n, "chunk": args.chunk,
                    "pairs": q["pairs"], "visible_surfels": q["visible"], "max_tile_list": q["max_list"],
-                   "ray_tests": q["ray_tests"], "composites": q["composites"], "rays_hit": q["rays_hit"],
+                   "ray_tests": q["ray_tests"], "ray_tests_needed": q["ray_tests_needed"],
+                   "composites": q["composites"], "rays_hit": q["rays_hit"],
                    "loss": "depth L1 + G-ICP normal cosine", "step_latency_ms_p50": round(p50, 4),
                    "step_latency_ms_p99": round(p99, 4)},
         "roofline": {"kernel": "raster_bwd", "bound": "alu", "achieved": round(achieved, 3),

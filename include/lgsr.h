@@ -10,8 +10,8 @@
  *             projection pi_s into (D^, A^, N^) on the scan's grid;
  *   Sec. 3.3  log-scale parameterisation s~ = log s;
  *   Sec. 3.4  mapping: rasterise, compare with the observations on valid pixels
- *             M_D = [D > 0] (masked depth L1, Eq. 8 left; G-ICP normal cosine term with
- *             M_N = M_D [|N| > 0], Eq. 9 first term), optimise Theta;
+ *             M_D = [D > 0] (masked depth L1, Eq. 10 left; G-ICP normal cosine term with
+ *             M_N = M_D [|N| > 0], Eq. 11 first term), optimise Theta;
  *   Sec. 4.1  loss weights lambda_n = 1, lambda_{n,g} = 0.05.
  * The primitive is the 2DGS surfel cited in Sec. 1: a planar Gaussian
  * G = exp(-(u^2 + v^2) / 2) at the exact ray/plane hit (u, v) in units of its two scales,
@@ -157,7 +157,7 @@ lgsr_status lgsr_forward(lgsr_ctx *ctx, const lgsr_surfels *surfels, const float
                          int32_t pose_on_device, const lgsr_beams *beams,
                          const lgsr_raster_opts *opts, lgsr_frame *out, lgsr_state **state);
 
-/* Loss of a rendered frame against targets (Sec. 3.4, Eq. 8 left and Eq. 9 first term):
+/* Loss of a rendered frame against targets (Sec. 3.4, Eq. 10 left and Eq. 11 first term):
  *   L = w_depth / |Omega_D| sum M_D |D^ - D|
  *     + lambda_n lambda_ng / |Omega_N| sum M_N (1 - N^ . N / |N^|),
  * M_D = [D > 0], M_N = M_D [|N| > 0]; an empty mask gives a zero term; |0| has zero
@@ -188,35 +188,60 @@ void lgsr_state_free(lgsr_state *state);
  *   out[3] longest per-tile list           out[4] ray-surfel tests the raster performs
  *          (64 per pair and overlapping 8 x 8 wave sub-tile)
  *   out[5] composited hits (sum over rays of the hit count)
- *   out[6] rays with at least one hit      out[7] reserved (0). */
+ *   out[6] rays with at least one hit
+ *   out[7] ray tests a front-to-back walk needs: as out[4], but per wave sub-tile only up to
+ *          the last contributor of its slowest ray (the whole list if a ray never drops
+ *          below T_min). */
 lgsr_status lgsr_query(lgsr_ctx *ctx, const lgsr_state *state, int64_t out[8]);
 
 /* Stage timers.  lgsr_profile selects stages by bit mask (bit k = stage k, 0 = off, -1 =
  * all); each selected stage is then bracketed by HIP events on the context's stream (a
  * stage may span several kernel launches; every event costs a little stream time).
  * lgsr_profile_read waits for the stream, adds up the elapsed times per stage since the
- * last read (HOST double[12], milliseconds) and the number of times each stage ran (HOST
- * int64[12]), then resets them. */
+ * last read (HOST double[10], milliseconds) and the number of times each stage ran (HOST
+ * int64[10]), then resets them. */
 enum {
-    LGSR_STAGE_PROJECT = 0,    /* projection, records, rectangles, tile counts */
-    LGSR_STAGE_DEPTH_SORT = 1, /* surfels by (range, index) */
-    LGSR_STAGE_SCAN = 2,       /* pair offsets and counters */
-    LGSR_STAGE_EMIT = 3,       /* (tile, surfel) pairs */
-    LGSR_STAGE_TILE_SORT = 4,  /* pairs by tile */
-    LGSR_STAGE_RANGES = 5,     /* per-tile list bounds */
-    LGSR_STAGE_RASTER_FWD = 6, /* forward compositing: chunk list, chunks, merge, fix-up */
-    LGSR_STAGE_LOSS = 7,       /* loss and its per-ray gradient */
-    LGSR_STAGE_BWD_PREP = 8,   /* clearing the record gradients, per-ray backward set-up */
-    LGSR_STAGE_RASTER_BWD = 9, /* backward compositing */
-    LGSR_STAGE_CHAIN = 10,     /* parameter and pose gradients */
-    LGSR_STAGE_READBACK = 11,  /* the one device-to-host read of the pair count */
-    LGSR_NUM_STAGES = 12
+    LGSR_STAGE_PROJECT = 0,    /* projection, records, rectangles, per-tile pair counts */
+    LGSR_STAGE_SCAN = 1,       /* tile offsets, list bounds and the pair count */
+    LGSR_STAGE_READBACK = 2,   /* the one device-to-host read (pair count, longest list) */
+    LGSR_STAGE_EMIT = 3,       /* surfel ids into the tile lists */
+    LGSR_STAGE_TILE_SORT = 4,  /* each tile list by (range, index) */
+    LGSR_STAGE_RASTER_FWD = 5, /* forward compositing: chunk list, chunks, merge, fix-up */
+    LGSR_STAGE_LOSS = 6,       /* loss and its per-ray gradient */
+    LGSR_STAGE_BWD_PREP = 7,   /* clearing the record gradients, per-ray backward set-up */
+    LGSR_STAGE_RASTER_BWD = 8, /* backward compositing */
+    LGSR_STAGE_CHAIN = 9,      /* parameter and pose gradients */
+    LGSR_NUM_STAGES = 10
 };
 lgsr_status lgsr_profile(lgsr_ctx *ctx, int32_t stage_mask);
-lgsr_status lgsr_profile_read(lgsr_ctx *ctx, double ms[12], int64_t calls[12]);
+lgsr_status lgsr_profile_read(lgsr_ctx *ctx, double ms[10], int64_t calls[10]);
 
 /* Wait for all work issued on the context's stream; reports an earlier kernel fault. */
 lgsr_status lgsr_sync(lgsr_ctx *ctx);
+
+/* Device bytes held by `state` (HOST int64 out); no GPU work, no wait.  A caller that keeps
+ * states from forward to backward can budget HBM with it, and recompute (run the forward
+ * again, which is deterministic) instead of keeping a state when the budget is spent. */
+lgsr_status lgsr_state_bytes(lgsr_ctx *ctx, const lgsr_state *state, int64_t *bytes);
+
+/* One Adam step (Kingma and Ba; the map optimisation of Sec. 3.4 does not name its
+ * optimiser, this is the usual choice for Gaussian maps) over up to 8 groups of float32
+ * arrays in one launch.  Per element, with t = step >= 1:
+ *   m = beta1 m + (1 - beta1) g,  v = beta2 v + (1 - beta2) g^2,
+ *   p -= lr * (m / (1 - beta1^t)) / (sqrt(v / (1 - beta2^t)) + eps).
+ * All pointers DEVICE, n elements each; param, m and v are updated in place (m, v start at
+ * zero).  Arrays of different groups must not overlap.  LGSR_EINVAL for n_groups outside
+ * [0, 8], a NULL array with n > 0, step < 1, or beta outside [0, 1). */
+typedef struct {
+    int64_t n;
+    float *param;
+    const float *grad;
+    float *m;
+    float *v;
+    float lr;
+} lgsr_adam_group;
+lgsr_status lgsr_adam_step(lgsr_ctx *ctx, int32_t n_groups, const lgsr_adam_group *groups /* HOST */, float beta1,
+                           float beta2, float eps, int32_t step);
 
 #ifdef __cplusplus
 }

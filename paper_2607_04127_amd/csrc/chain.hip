@@ -1,16 +1,20 @@
 // chain.hip -- record-space gradients -> surfel parameters and the 6-DoF pose.
 //
-// The backward raster leaves, per surfel, dL/d(nt, c, U, V, alpha) summed over rays.  With
+// The backward raster leaves, per surfel, dL/d(nt, c, cu, U, cv, V, alpha) summed over rays,
+// where the hit test evaluates u = (cu + U.(d - m)) / den with cu = U.m (likewise v).  With
 //   nt = sigma n',  c = nt . mu',  U = sigma (b' x mu') / s0,  V = sigma (mu' x a') / s1
-// (sigma piecewise constant), the sensor-frame gradients are
-//   dmu' = gc nt + (sigma/s0) gU x b' + (sigma/s1) a' x gV
-//   da'  = (sigma/s1) gV x mu',   db' = (sigma/s0) mu' x gU,   dn' = sigma (gnt + gc mu')
-//   ds0  = -gU.U / s0,   ds1 = -gV.V / s1
-// then world frame (multiply by R), the rotation columns (a, b, n) of the normalised
-// quaternion and its normalisation, s~ = log s (Sec. 3.3) and alpha = sigmoid(o).
-// Pose, right perturbation T Exp(xi): drho = -sum dmu', domega = -sum(mu' x dmu' + a' x da'
-// + b' x db' + n' x dn'); per-block partials are folded by one block in a fixed order with
-// compensated sums, so the pose gradient is deterministic given the record gradients.
+// (sigma piecewise constant) the total U gradient is gU + gcu m, and with w = mu' x m
+//   dmu' = gc nt + (sigma/s0) (gU + gcu m) x b' + (sigma/s1) a' x (gV + gcv m)
+//   da'  = (sigma/s1) (gV x mu' - gcv w),   db' = (sigma/s0) (mu' x gU + gcu w)
+//   dn'  = sigma (gnt + gc mu')
+//   ds0  = -(gU.U + gcu cu) / s0,   ds1 = -(gV.V + gcv cv) / s1
+// (U is nearly perpendicular to m, so these forms avoid the cancellation that products with
+// the unsplit gradient would suffer), then world frame (multiply by R), the rotation columns
+// (a, b, n) of the normalised quaternion and its normalisation, s~ = log s (Sec. 3.3) and
+// alpha = sigmoid(o).  Pose, right perturbation T Exp(xi): drho = -sum dmu', domega =
+// -sum(mu' x dmu' + a' x da' + b' x db' + n' x dn'); per-block partials are folded by one
+// block in a fixed order with compensated sums, so the pose gradient is deterministic given
+// the record gradients.
 #include "lgsr_internal.h"
 #include "lgsr_kernels.h"
 
@@ -46,33 +50,34 @@ __global__ __launch_bounds__(kChainThreads) void chain_kernel(SurfelPtrs S, cons
         Geom g = project_geom(S.means, S.quats, S.log_scales, S.logits, i, P, p.near);
         float out_m[3] = {0.f, 0.f, 0.f}, out_q[4] = {0.f, 0.f, 0.f, 0.f}, out_s[2] = {0.f, 0.f}, out_o = 0.f;
         if (g.valid) {
+            const RecParts q = record_parts(g);
             const float4 *G4 = reinterpret_cast<const float4 *>(recgrad + (size_t)i * kGrad);
-            float4 x = G4[0], y = G4[1], z = G4[2];
-            float gnt[3] = {x.x, x.y, x.z}, gc = x.w;
-            float gU[3] = {y.x, y.y, y.z}, gV[3] = {y.w, z.x, z.y};
-            float ga = z.z;
+            const float4 x = G4[0], y = G4[1], z = G4[2], zz = G4[3];
+            const float gnt[3] = {x.x, x.y, x.z}, gc = x.w;
+            const float gcu = y.x, gU[3] = {y.y, y.z, y.w};
+            const float gcv = z.x, gV[3] = {z.y, z.z, z.w};
+            const float ga = zz.x;
             float mu[3] = {g.mh[0] + g.ml[0], g.mh[1] + g.ml[1], g.mh[2] + g.ml[2]};
-            float nt[3] = {g.sigma * g.n[0], g.sigma * g.n[1], g.sigma * g.n[2]};
-            float k0 = g.sigma / g.s0, k1 = g.sigma / g.s1;
-            float bxm[3], mxa[3];
-            cross(g.b, mu, bxm);
-            cross(mu, g.a, mxa);
-            float U[3] = {bxm[0] * k0, bxm[1] * k0, bxm[2] * k0};
-            float V[3] = {mxa[0] * k1, mxa[1] * k1, mxa[2] * k1};
+            const float k0 = g.sigma / g.s0, k1 = g.sigma / g.s1;
+            float gUt[3], gVt[3];
+            for (int c = 0; c < 3; ++c) {
+                gUt[c] = fmaf(gcu, q.m[c], gU[c]);
+                gVt[c] = fmaf(gcv, q.m[c], gV[c]);
+            }
             float t1[3], t2[3];
-            cross(gU, g.b, t1);
-            cross(g.a, gV, t2);
+            cross(gUt, g.b, t1);
+            cross(g.a, gVt, t2);
             float gmu[3], gav[3], gbv[3], gnv[3];
-            for (int c = 0; c < 3; ++c) gmu[c] = gc * nt[c] + k0 * t1[c] + k1 * t2[c];
+            for (int c = 0; c < 3; ++c) gmu[c] = gc * q.nt[c] + k0 * t1[c] + k1 * t2[c];
             cross(gV, mu, t1);
             cross(mu, gU, t2);
             for (int c = 0; c < 3; ++c) {
-                gav[c] = k1 * t1[c];
-                gbv[c] = k0 * t2[c];
+                gav[c] = k1 * fmaf(-gcv, q.w[c], t1[c]);
+                gbv[c] = k0 * fmaf(gcu, q.w[c], t2[c]);
                 gnv[c] = g.sigma * (gnt[c] + gc * mu[c]);
             }
-            float gs0 = -(gU[0] * U[0] + gU[1] * U[1] + gU[2] * U[2]) / g.s0;
-            float gs1 = -(gV[0] * V[0] + gV[1] * V[1] + gV[2] * V[2]) / g.s1;
+            const float gs0 = -fmaf(gcu, q.cu, gU[0] * q.U[0] + gU[1] * q.U[1] + gU[2] * q.U[2]) / g.s0;
+            const float gs1 = -fmaf(gcv, q.cv, gV[0] * q.V[0] + gV[1] * q.V[1] + gV[2] * q.V[2]) / g.s1;
             // world frame
             float Ga[3], Gb[3], Gn[3];
             rot(P, gmu, out_m);

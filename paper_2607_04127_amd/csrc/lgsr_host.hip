@@ -2,13 +2,11 @@
 // states and the ordering of the stages on one HIP stream.
 //
 // Forward stages (all on the context's stream):
-//   project      per-surfel record, conservative ray rectangle, tile count, range key
-//   sort         surfels by (range, index): stable LSD radix sort of the 31-bit range keys
-//   scan         tile counts gathered in range order -> pair offsets, total P
-//   (P is read back once to size the pair list)
-//   emit         (tile, surfel) pairs in range order
-//   sort         pairs by tile (stable, so each tile's list stays in range order)
-//   ranges       [start, end) of every tile's list
+//   project      per-surfel record, conservative ray rectangle, range key, per-tile counts
+//   scan         tile counts -> [start, end) of every tile's list, total P, longest list
+//   (P and the longest list are read back once to size the pair buffers)
+//   emit         surfel ids into their tiles' lists (unordered)
+//   tile_sort    every list by (range, index), one workgroup per tile
 //   raster_fwd   compositing, frame outputs and per-ray backward state
 // Backward: zero record gradients, raster_bwd, chain (parameters + pose).
 #include <hip/hip_runtime.h>
@@ -76,8 +74,7 @@ struct lgsr_state {
     bool live = false;
     // forward products kept for the backward
     DevBuf recs, rects, pk, pv, pk2, pv2, ranges, st0, st1, pose, chunks, chunk_base, slots, fixA, fixB;
-    uint32_t *ids = nullptr;        // sorted pair surfel ids (pv or pv2)
-    uint32_t *tile_keys = nullptr;  // sorted pair tile ids (pk or pk2)
+    uint32_t *ids = nullptr;  // per-tile lists of surfel ids, front to back (pv)
     SurfelPtrs S{};
     const float *rows = nullptr, *cols = nullptr;
     Grid g{};
@@ -91,7 +88,7 @@ struct lgsr_ctx {
     hipStream_t stream = nullptr;
     std::string err;
     // scratch
-    DevBuf keys, vals, keys2, vals2, cnt, offs, hist, scan_tmp, counters, recgrad, partials, pose_partials, gb0, gb1;
+    DevBuf keys, cnt, offs, counters, recgrad, partials, pose_partials, gb0, gb1;
     uint32_t *pinned = nullptr;  // host-pinned readback slots
     std::vector<lgsr_state *> pool;  // freed states kept for reuse
     std::vector<lgsr_state *> all;   // every state allocated by this context
@@ -165,13 +162,6 @@ RasterParams to_params(const lgsr_raster_opts *o)
     return p;
 }
 
-int bits_for(int T)
-{
-    int b = 0;
-    while ((1 << b) < T) ++b;
-    return b;
-}
-
 lgsr_state *take_state(lgsr_ctx *ctx)
 {
     if (!ctx->pool.empty()) {
@@ -242,10 +232,8 @@ size_t state_bytes(const lgsr_state *s)
 
 size_t ctx_bytes(const lgsr_ctx *c)
 {
-    return c->keys.cap + c->vals.cap + c->keys2.cap + c->vals2.cap + c->cnt.cap + c->offs.cap + c->hist.cap +
-           c->scan_tmp.cap + c->counters.cap + c->recgrad.cap + c->partials.cap + c->pose_partials.cap + c->gb0.cap +
-           c->gb1.cap +
-           state_bytes(&c->scratch_state);
+    return c->keys.cap + c->cnt.cap + c->offs.cap + c->counters.cap + c->recgrad.cap + c->partials.cap +
+           c->pose_partials.cap + c->gb0.cap + c->gb1.cap + state_bytes(&c->scratch_state);
 }
 
 }  // namespace
@@ -315,9 +303,8 @@ void lgsr_destroy(lgsr_ctx *ctx)
         delete s;
     }
     free_state_buffers(&ctx->scratch_state);
-    DevBuf *bufs[] = {&ctx->keys, &ctx->vals, &ctx->keys2, &ctx->vals2, &ctx->cnt, &ctx->offs, &ctx->hist,
-                      &ctx->scan_tmp, &ctx->counters, &ctx->recgrad, &ctx->partials, &ctx->pose_partials,
-                      &ctx->gb0, &ctx->gb1};
+    DevBuf *bufs[] = {&ctx->keys, &ctx->cnt, &ctx->offs, &ctx->counters, &ctx->recgrad, &ctx->partials,
+                      &ctx->pose_partials, &ctx->gb0, &ctx->gb1};
     for (DevBuf *b : bufs) release(*b);
     for (auto &pe : ctx->ev_pending) {
         (void)hipEventDestroy(pe.second.first);
@@ -397,81 +384,53 @@ lgsr_status lgsr_forward(lgsr_ctx *ctx, const lgsr_surfels *surfels, const float
     HIP_TRY(ensure(S->st1, (size_t)rays * sizeof(float4)), "alloc ray state");
     HIP_TRY(ensure(S->pose, 16 * sizeof(float)), "alloc pose");
     HIP_TRY(ensure(ctx->keys, nn * 4), "alloc keys");
-    HIP_TRY(ensure(ctx->vals, nn * 4), "alloc vals");
-    HIP_TRY(ensure(ctx->keys2, nn * 4), "alloc keys");
-    HIP_TRY(ensure(ctx->vals2, nn * 4), "alloc vals");
-    HIP_TRY(ensure(ctx->cnt, nn * 4), "alloc counts");
-    HIP_TRY(ensure(ctx->offs, nn * 4), "alloc offsets");
-    HIP_TRY(ensure(ctx->hist, radix_hist_words(n) * 4), "alloc histogram");
-    HIP_TRY(ensure(ctx->scan_tmp, (scan_tmp_words(n) + scan_tmp_words(radix_hist_words(n))) * 4), "alloc scan");
+    HIP_TRY(ensure(ctx->cnt, (size_t)g.T * kShards * 4), "alloc tile counts");
+    HIP_TRY(ensure(ctx->offs, (size_t)g.T * kShards * 4), "alloc tile cursors");
 
     SurfelPtrs SP{surfels->means, surfels->quats, surfels->log_scales, surfels->opacity_logits, n};
     uint32_t *counters = as<uint32_t>(ctx->counters);
     {
     Stage st_(ctx, LGSR_STAGE_PROJECT);
+    HIP_TRY(launch_fill_u32(as<uint32_t>(ctx->cnt), 0u, (int64_t)g.T * kShards, s), "clear tile counts");
     HIP_TRY(launch_project(SP, pose_val, pose_on_device ? pose_ws : nullptr, as<float>(S->pose), beams->row_sincos, g,
                            prm, as<float>(S->recs), as<uint2>(S->rects), as<uint32_t>(ctx->keys),
-                           as<uint32_t>(ctx->vals), as<uint32_t>(ctx->cnt), s),
+                           as<uint32_t>(ctx->cnt), s),
             "project");
     }
-    int64_t P = 0;
-    const uint32_t *sorted_ids = as<uint32_t>(ctx->vals);
-    if (n > 0) {
-        bool alt = false;
-        {
-        Stage st_(ctx, LGSR_STAGE_DEPTH_SORT);
-        HIP_TRY(radix_sort_pairs(as<uint32_t>(ctx->keys), as<uint32_t>(ctx->vals), as<uint32_t>(ctx->keys2),
-                                 as<uint32_t>(ctx->vals2), n, 31, as<uint32_t>(ctx->hist),
-                                 as<uint32_t>(ctx->scan_tmp), s, &alt),
-                "depth sort");
-        }
-        sorted_ids = alt ? as<uint32_t>(ctx->vals2) : as<uint32_t>(ctx->vals);
-        {
-        Stage st_(ctx, LGSR_STAGE_SCAN);
-        HIP_TRY(scan_u32(as<uint32_t>(ctx->cnt), sorted_ids, as<uint32_t>(ctx->offs), counters, n,
-                         as<uint32_t>(ctx->scan_tmp), s),
-                "count scan");
-        }
-        Stage st_(ctx, LGSR_STAGE_READBACK);
-        HIP_TRY(hipMemcpyAsync(ctx->pinned, counters, sizeof(uint32_t), hipMemcpyDeviceToHost, s), "readback");
-        HIP_TRY(hipStreamSynchronize(s), "readback sync");
-        P = (int64_t)ctx->pinned[0];
+    {
+    Stage st_(ctx, LGSR_STAGE_SCAN);
+    HIP_TRY(launch_tile_scan(as<uint32_t>(ctx->cnt), g.T, as<uint2>(S->ranges), as<uint32_t>(ctx->offs), counters, s),
+            "tile scan");
     }
-    // the scan is 32-bit: the count must stay below 2^31 (lists are addressed as int)
-    if (P < 0 || P > (int64_t)0x7FFFFFFF) return fail(ctx, LGSR_ECAPACITY, "too many (surfel, tile) pairs");
+    int64_t P = 0, longest = 0;
+    {
+    Stage st_(ctx, LGSR_STAGE_READBACK);
+    HIP_TRY(hipMemcpyAsync(ctx->pinned, counters, 3 * sizeof(uint32_t), hipMemcpyDeviceToHost, s), "readback");
+    HIP_TRY(hipStreamSynchronize(s), "readback sync");
+    P = (int64_t)((uint64_t)ctx->pinned[0] | ((uint64_t)ctx->pinned[1] << 32));
+    longest = (int64_t)ctx->pinned[2];
+    }
+    // lists are addressed with 32-bit offsets
+    if (P > (int64_t)0x7FFFFFFF) return fail(ctx, LGSR_ECAPACITY, "too many (surfel, tile) pairs");
     const size_t pp = (size_t)(P > 0 ? P : 1);
-    HIP_TRY(ensure(S->pk, pp * 4), "alloc pairs");
     HIP_TRY(ensure(S->pv, pp * 4), "alloc pairs");
-    HIP_TRY(ensure(S->pk2, pp * 4), "alloc pairs");
-    HIP_TRY(ensure(S->pv2, pp * 4), "alloc pairs");
-    HIP_TRY(ensure(ctx->hist, (radix_hist_words(n) > radix_hist_words(P) ? radix_hist_words(n) : radix_hist_words(P)) * 4),
-            "alloc histogram");
-    HIP_TRY(ensure(ctx->scan_tmp, (scan_tmp_words(radix_hist_words(P)) + scan_tmp_words(radix_hist_words(n)) +
-                                   scan_tmp_words(n)) * 4),
-            "alloc scan");
+    const bool streamed = longest > tile_sort_capacity();
+    if (streamed) {
+        HIP_TRY(ensure(S->pk, pp * 4), "alloc pairs");
+        HIP_TRY(ensure(S->pk2, pp * 4), "alloc pairs");
+        HIP_TRY(ensure(S->pv2, pp * 4), "alloc pairs");
+    }
     S->ids = as<uint32_t>(S->pv);
-    const uint32_t *tile_keys = as<uint32_t>(S->pk);
     if (P > 0) {
         {
         Stage st_(ctx, LGSR_STAGE_EMIT);
-        HIP_TRY(launch_emit(sorted_ids, as<uint32_t>(ctx->cnt), as<uint32_t>(ctx->offs), as<uint2>(S->rects), n, g,
-                            as<uint32_t>(S->pk), as<uint32_t>(S->pv), s),
-                "emit");
+        HIP_TRY(launch_emit(as<uint2>(S->rects), n, g, as<uint32_t>(ctx->offs), S->ids, P, s), "emit");
         }
-        bool alt = false;
         Stage st_(ctx, LGSR_STAGE_TILE_SORT);
-        HIP_TRY(radix_sort_pairs(as<uint32_t>(S->pk), as<uint32_t>(S->pv), as<uint32_t>(S->pk2),
-                                 as<uint32_t>(S->pv2), P, bits_for(g.T), as<uint32_t>(ctx->hist),
-                                 as<uint32_t>(ctx->scan_tmp), s, &alt),
+        HIP_TRY(launch_tile_sort(as<uint2>(S->ranges), g.T, as<uint32_t>(ctx->keys), n, S->ids,
+                                 streamed ? as<uint32_t>(S->pk) : nullptr, streamed ? as<uint32_t>(S->pk2) : nullptr,
+                                 streamed ? as<uint32_t>(S->pv2) : nullptr, s),
                 "tile sort");
-        if (alt) {
-            S->ids = as<uint32_t>(S->pv2);
-            tile_keys = as<uint32_t>(S->pk2);
-        }
-    }
-    {
-    Stage st_(ctx, LGSR_STAGE_RANGES);
-    HIP_TRY(launch_ranges(tile_keys, P, g.T, as<uint2>(S->ranges), s), "ranges");
     }
     {
     const int seg = chunk_size(P, opts->chunk);
@@ -502,7 +461,6 @@ lgsr_status lgsr_forward(lgsr_ctx *ctx, const lgsr_surfels *surfels, const float
     Stage st_(ctx, LGSR_STAGE_RASTER_FWD);
     HIP_TRY(launch_raster_fwd(R, g, prm, out->depth, out->opacity, out->normal, out->drop, s), "raster forward");
     }
-    S->tile_keys = const_cast<uint32_t *>(tile_keys);
     S->S = SP;
     S->rows = beams->row_sincos;
     S->cols = beams->col_sincos;
@@ -606,11 +564,12 @@ lgsr_status lgsr_query(lgsr_ctx *ctx, const lgsr_state *S, int64_t out[8])
     unsigned long long *wc = reinterpret_cast<unsigned long long *>(counters + 8);
     HIP_TRY(launch_max_range(as<uint2>(W->ranges), S->g.T, counters + 1, s), "query");
     HIP_TRY(launch_count_visible(as<uint2>(W->rects), S->S.n, counters + 2, s), "query");
-    HIP_TRY(launch_work_counts(W->tile_keys, W->ids, as<uint2>(W->rects), S->P, as<float4>(W->st1), S->g, wc, s),
+    HIP_TRY(launch_work_counts(as<uint2>(W->ranges), W->ids, as<uint2>(W->rects), S->P, as<float4>(W->st1), S->g, wc, s),
             "query");
+    if (S->P > 0) HIP_TRY(launch_work_needed(W->R, S->g, S->prm, wc + 3, s), "query");
     HIP_TRY(hipMemcpyAsync(ctx->pinned + 1, counters + 1, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, s),
             "readback");
-    HIP_TRY(hipMemcpyAsync(ctx->pinned + 4, wc, 3 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s),
+    HIP_TRY(hipMemcpyAsync(ctx->pinned + 4, wc, 4 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s),
             "readback");
     HIP_TRY(hipStreamSynchronize(s), "query sync");
     const unsigned long long *hw = reinterpret_cast<const unsigned long long *>(ctx->pinned + 4);
@@ -621,7 +580,7 @@ lgsr_status lgsr_query(lgsr_ctx *ctx, const lgsr_state *S, int64_t out[8])
     out[4] = (int64_t)hw[0];
     out[5] = (int64_t)hw[1];
     out[6] = (int64_t)hw[2];
-    out[7] = 0;
+    out[7] = (int64_t)hw[3];
     return LGSR_OK;
 }
 
@@ -664,6 +623,39 @@ lgsr_status lgsr_sync(lgsr_ctx *ctx)
     if (!ctx) return LGSR_EINVAL;
     HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
     HIP_TRY(hipStreamSynchronize(ctx->stream), "sync");
+    return LGSR_OK;
+}
+
+lgsr_status lgsr_state_bytes(lgsr_ctx *ctx, const lgsr_state *S, int64_t *bytes)
+{
+    if (!ctx) return LGSR_EINVAL;
+    if (!S || !bytes) return fail(ctx, LGSR_EINVAL, "state or bytes is NULL");
+    if (S->ctx != ctx || !S->live) return fail(ctx, LGSR_ESTATE, "state does not belong to this context");
+    *bytes = (int64_t)state_bytes(S);
+    return LGSR_OK;
+}
+
+lgsr_status lgsr_adam_step(lgsr_ctx *ctx, int32_t n_groups, const lgsr_adam_group *groups, float beta1, float beta2,
+                           float eps, int32_t step)
+{
+    if (!ctx) return LGSR_EINVAL;
+    if (n_groups < 0 || n_groups > 8) return fail(ctx, LGSR_EINVAL, "n_groups must lie in [0, 8]");
+    if (n_groups > 0 && !groups) return fail(ctx, LGSR_EINVAL, "groups is NULL");
+    if (step < 1) return fail(ctx, LGSR_EINVAL, "step must be >= 1");
+    if (!(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f))
+        return fail(ctx, LGSR_EINVAL, "beta1 and beta2 must lie in [0, 1)");
+    if (!std::isfinite(eps) || eps < 0.f) return fail(ctx, LGSR_EINVAL, "eps must be finite and >= 0");
+    AdamBatch B{};
+    B.count = n_groups;
+    for (int k = 0; k < n_groups; ++k) {
+        const lgsr_adam_group &G = groups[k];
+        if (G.n < 0) return fail(ctx, LGSR_EINVAL, "group %d: n < 0", k);
+        if (G.n > 0 && (!G.param || !G.grad || !G.m || !G.v)) return fail(ctx, LGSR_EINVAL, "group %d: NULL array", k);
+        if (!std::isfinite(G.lr)) return fail(ctx, LGSR_EINVAL, "group %d: lr must be finite", k);
+        B.g[k] = AdamGroup{G.n, G.param, G.grad, G.m, G.v, G.lr};
+    }
+    HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
+    HIP_TRY(launch_adam(B, beta1, beta2, eps, step, ctx->stream), "adam");
     return LGSR_OK;
 }
 

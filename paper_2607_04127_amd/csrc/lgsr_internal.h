@@ -23,7 +23,13 @@ namespace lgsr {
 constexpr int kTile = 16;      // tile edge in rays: a tile is 16 x 16 rays, one workgroup
 constexpr int kSub = 8;        // wave sub-tile edge: 8 x 8 rays, one wavefront of 64 lanes
 constexpr int kRec = 16;       // floats per surfel record
-constexpr int kGrad = 12;      // floats per surfel record-gradient slot (11 used)
+// Per-tile pair counters are split into kShards by surfel index ((i >> 8) mod kShards) so
+// that no single counter takes an atomic from every workgroup; a tile's list is the
+// concatenation of its shards.
+constexpr int kShards = 8;
+__host__ __device__ __forceinline__ int shard_of(int64_t i) { return (int)((i >> 8) & (kShards - 1)); }
+constexpr int kGrad = 16;      // floats per surfel record-gradient slot (kGradUsed used)
+constexpr int kGradUsed = 13;
 constexpr uint32_t kCulledKey = 0x7FFFFFFFu;  // depth key of a surfel that renders nothing
 
 // Record layout (float index).
@@ -39,7 +45,10 @@ enum : int {
 };
 
 // Record-gradient layout (float index): dL/d(nt, c, U, V, alpha) summed over rays.
-enum : int { G_NT = 0, G_C = 3, G_U = 4, G_V = 7, G_ALPHA = 10 };
+// Record gradients.  u = (cu + U.(d - m)) / den is differentiated in that split: G_CU
+// accumulates dL/dnu and G_U the vector dL/dnu (d - m), so that the chain rule meets U only
+// through products that do not cancel (U is nearly perpendicular to m, and the rays near m).
+enum : int { G_NT = 0, G_C = 3, G_CU = 4, G_U = 5, G_CV = 8, G_V = 9, G_ALPHA = 12 };
 
 struct Pose {
     float r[9];  // row-major rotation sensor -> world
@@ -165,34 +174,48 @@ __device__ __forceinline__ Geom project_geom(const float *__restrict__ means, co
 }
 
 // Record of a projected surfel (layout above).
-__device__ __forceinline__ void make_record(const Geom &g, float *rec)
+// The record quantities of a projected surfel.  The chain rule calls this too, so both see
+// bit-identical values.
+struct RecParts {
+    float nt[3], c, m[3], w[3], U[3], cu, V[3], cv;
+};
+
+__device__ __forceinline__ RecParts record_parts(const Geom &g)
 {
-    float nt[3] = {g.sigma * g.n[0], g.sigma * g.n[1], g.sigma * g.n[2]};
-    float c = fmaf(nt[0], g.mh[0], fmaf(nt[1], g.mh[1], nt[2] * g.mh[2]))
-            + fmaf(nt[0], g.ml[0], fmaf(nt[1], g.ml[1], nt[2] * g.ml[2]));
+    RecParts q;
+    for (int k = 0; k < 3; ++k) q.nt[k] = g.sigma * g.n[k];
+    q.c = fmaf(q.nt[0], g.mh[0], fmaf(q.nt[1], g.mh[1], q.nt[2] * g.mh[2]))
+        + fmaf(q.nt[0], g.ml[0], fmaf(q.nt[1], g.ml[1], q.nt[2] * g.ml[2]));
     float ir = 1.f / g.r;
-    float m[3] = {g.mh[0] * ir, g.mh[1] * ir, g.mh[2] * ir};
+    for (int k = 0; k < 3; ++k) q.m[k] = g.mh[k] * ir;
     // w = mu' x m, small: accurate difference of products on the high part + low part
-    float w[3];
-    w[0] = diff_prod(g.mh[1], m[2], g.mh[2], m[1]) + (g.ml[1] * m[2] - g.ml[2] * m[1]);
-    w[1] = diff_prod(g.mh[2], m[0], g.mh[0], m[2]) + (g.ml[2] * m[0] - g.ml[0] * m[2]);
-    w[2] = diff_prod(g.mh[0], m[1], g.mh[1], m[0]) + (g.ml[0] * m[1] - g.ml[1] * m[0]);
+    q.w[0] = diff_prod(g.mh[1], q.m[2], g.mh[2], q.m[1]) + (g.ml[1] * q.m[2] - g.ml[2] * q.m[1]);
+    q.w[1] = diff_prod(g.mh[2], q.m[0], g.mh[0], q.m[2]) + (g.ml[2] * q.m[0] - g.ml[0] * q.m[2]);
+    q.w[2] = diff_prod(g.mh[0], q.m[1], g.mh[1], q.m[0]) + (g.ml[0] * q.m[1] - g.ml[1] * q.m[0]);
     float i0 = g.sigma / g.s0, i1 = g.sigma / g.s1;
     // U = sigma (b' x mu') / s0, V = sigma (mu' x a') / s1
-    float U[3] = {(g.b[1] * g.mh[2] - g.b[2] * g.mh[1]) * i0, (g.b[2] * g.mh[0] - g.b[0] * g.mh[2]) * i0,
-                  (g.b[0] * g.mh[1] - g.b[1] * g.mh[0]) * i0};
-    float V[3] = {(g.mh[1] * g.a[2] - g.mh[2] * g.a[1]) * i1, (g.mh[2] * g.a[0] - g.mh[0] * g.a[2]) * i1,
-                  (g.mh[0] * g.a[1] - g.mh[1] * g.a[0]) * i1};
+    q.U[0] = (g.b[1] * g.mh[2] - g.b[2] * g.mh[1]) * i0;
+    q.U[1] = (g.b[2] * g.mh[0] - g.b[0] * g.mh[2]) * i0;
+    q.U[2] = (g.b[0] * g.mh[1] - g.b[1] * g.mh[0]) * i0;
+    q.V[0] = (g.mh[1] * g.a[2] - g.mh[2] * g.a[1]) * i1;
+    q.V[1] = (g.mh[2] * g.a[0] - g.mh[0] * g.a[2]) * i1;
+    q.V[2] = (g.mh[0] * g.a[1] - g.mh[1] * g.a[0]) * i1;
     // U . m = sigma b'.(mu' x m) / s0,   V . m = -sigma a'.(mu' x m) / s1
-    float cu = fmaf(g.b[0], w[0], fmaf(g.b[1], w[1], g.b[2] * w[2])) * i0;
-    float cv = -fmaf(g.a[0], w[0], fmaf(g.a[1], w[1], g.a[2] * w[2])) * i1;
-    rec[R_NT + 0] = nt[0]; rec[R_NT + 1] = nt[1]; rec[R_NT + 2] = nt[2];
-    rec[R_C] = c;
-    rec[R_U + 0] = U[0]; rec[R_U + 1] = U[1]; rec[R_U + 2] = U[2];
-    rec[R_CU] = cu;
-    rec[R_V + 0] = V[0]; rec[R_V + 1] = V[1]; rec[R_V + 2] = V[2];
-    rec[R_CV] = cv;
-    rec[R_M + 0] = m[0]; rec[R_M + 1] = m[1]; rec[R_M + 2] = m[2];
+    q.cu = fmaf(g.b[0], q.w[0], fmaf(g.b[1], q.w[1], g.b[2] * q.w[2])) * i0;
+    q.cv = -fmaf(g.a[0], q.w[0], fmaf(g.a[1], q.w[1], g.a[2] * q.w[2])) * i1;
+    return q;
+}
+
+__device__ __forceinline__ void make_record(const Geom &g, float *rec)
+{
+    const RecParts q = record_parts(g);
+    rec[R_NT + 0] = q.nt[0]; rec[R_NT + 1] = q.nt[1]; rec[R_NT + 2] = q.nt[2];
+    rec[R_C] = q.c;
+    rec[R_U + 0] = q.U[0]; rec[R_U + 1] = q.U[1]; rec[R_U + 2] = q.U[2];
+    rec[R_CU] = q.cu;
+    rec[R_V + 0] = q.V[0]; rec[R_V + 1] = q.V[1]; rec[R_V + 2] = q.V[2];
+    rec[R_CV] = q.cv;
+    rec[R_M + 0] = q.m[0]; rec[R_M + 1] = q.m[1]; rec[R_M + 2] = q.m[2];
     rec[R_ALPHA] = g.alpha;
 }
 
@@ -219,6 +242,7 @@ __device__ __forceinline__ Ray make_ray(const float *__restrict__ rows, const fl
 }
 
 struct Hit {
+    float e[3];  // d - m
     float den, inv, nu, nv, t, G, aG, ah;
     bool pass;
 };
@@ -241,12 +265,12 @@ constexpr float kNegHalfLog2e = -0.72134752044448170f;
 __device__ __forceinline__ Hit hit_test(const Rec &s, const Ray &ray, const RasterParams &p)
 {
     Hit h;
-    float ex = (ray.dh[0] - s.m0) + ray.dl[0];
-    float ey = (ray.dh[1] - s.m1) + ray.dl[1];
-    float ez = ray.dh[2] - s.m2;
+    h.e[0] = (ray.dh[0] - s.m0) + ray.dl[0];
+    h.e[1] = (ray.dh[1] - s.m1) + ray.dl[1];
+    h.e[2] = ray.dh[2] - s.m2;
     h.den = fmaf(s.nt0, ray.dh[0], fmaf(s.nt1, ray.dh[1], s.nt2 * ray.dh[2]));
-    h.nu = fmaf(s.U0, ex, fmaf(s.U1, ey, fmaf(s.U2, ez, s.cu)));
-    h.nv = fmaf(s.V0, ex, fmaf(s.V1, ey, fmaf(s.V2, ez, s.cv)));
+    h.nu = fmaf(s.U0, h.e[0], fmaf(s.U1, h.e[1], fmaf(s.U2, h.e[2], s.cu)));
+    h.nv = fmaf(s.V0, h.e[0], fmaf(s.V1, h.e[1], fmaf(s.V2, h.e[2], s.cv)));
     h.inv = __builtin_amdgcn_rcpf(h.den);
     h.t = s.c * h.inv;
     float u = h.nu * h.inv, v = h.nv * h.inv;

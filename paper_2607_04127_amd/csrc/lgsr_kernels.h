@@ -10,16 +10,19 @@
 namespace lgsr {
 
 // ---- sort.hip ----
-size_t scan_tmp_words(int64_t n);
-// out[i] = sum_{k<i} x_k with x_k = in[k] (or in[gather[k]]); *total (device, may be null)
-// receives the sum of all n.  n <= 4096 * 4096.  In-place (out == in) is allowed.
-hipError_t scan_u32(const uint32_t *in, const uint32_t *gather, uint32_t *out, uint32_t *total, int64_t n,
-                    uint32_t *tmp, hipStream_t s);
-size_t radix_hist_words(int64_t n);
-// Stable sort by the low `bits` bits of keys; on return *in_alt tells whether the sorted
-// data ended in (keys_alt, vals_alt).
-hipError_t radix_sort_pairs(uint32_t *keys, uint32_t *vals, uint32_t *keys_alt, uint32_t *vals_alt, int64_t n,
-                            int bits, uint32_t *hist, uint32_t *scan_tmp, hipStream_t s, bool *in_alt);
+// Lists longer than this are sorted through the spare pair buffers (k0, k1, v1).
+int tile_sort_capacity();
+// cnt, cursor: T x kShards.  ranges[t] = [first, end) of tile t's list and cursor[t kShards
+// + s] = first slot of its shard s, from the exclusive prefix sum of cnt in (tile, shard)
+// order; out (device) receives the total as two 32-bit words (low, high) and the largest
+// tile count.
+hipError_t launch_tile_scan(const uint32_t *cnt, int T, uint2 *ranges, uint32_t *cursor, uint32_t *out,
+                            hipStream_t s);
+// Orders every tile's list ids[ranges[t].x .. ranges[t].y) by (keys[id], id) ascending
+// (keys has n entries).  k0, k1, v1 (P words each) are needed only when some list is longer
+// than tile_sort_capacity(); otherwise they may be null.
+hipError_t launch_tile_sort(const uint2 *ranges, int T, const uint32_t *keys, int64_t n, uint32_t *ids,
+                            uint32_t *k0, uint32_t *k1, uint32_t *v1, hipStream_t s);
 
 // ---- project.hip ----
 struct SurfelPtrs {
@@ -27,17 +30,19 @@ struct SurfelPtrs {
     int64_t n;
 };
 
+// records, range keys (float bits of the sensor range), ray rectangles, and per-(tile,
+// shard) pair counts added to tile_cnt (T x kShards, zero it first)
 hipError_t launch_project(const SurfelPtrs &S, const Pose &pose_val, const float *pose_dev, float *pose_out,
                           const float *rows, const Grid &g, const RasterParams &p, float *recs, uint2 *rects,
-                          uint32_t *keys, uint32_t *vals, uint32_t *cnt, hipStream_t s);
-hipError_t launch_emit(const uint32_t *sorted_ids, const uint32_t *cnt, const uint32_t *offs, const uint2 *rects,
-                       int64_t n, const Grid &g, uint32_t *pair_keys, uint32_t *pair_vals, hipStream_t s);
-hipError_t launch_ranges(const uint32_t *sorted_keys, int64_t P, int T, uint2 *ranges, hipStream_t s);
+                          uint32_t *keys, uint32_t *tile_cnt, hipStream_t s);
+// surfel ids into the tile lists; cursor (T x kShards) from launch_tile_scan, pv holds P words
+hipError_t launch_emit(const uint2 *rects, int64_t n, const Grid &g, uint32_t *cursor, uint32_t *pv, int64_t P,
+                       hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
 hipError_t launch_count_visible(const uint2 *rects, int64_t n, uint32_t *out, hipStream_t s);
 hipError_t launch_max_range(const uint2 *ranges, int T, uint32_t *out, hipStream_t s);
-// out[0] ray-surfel tests, out[1] composited hits, out[2] rays with a hit (u64, zeroed here)
-hipError_t launch_work_counts(const uint32_t *tile_keys, const uint32_t *ids, const uint2 *rects, int64_t P,
+// out[0] ray-surfel tests, out[1] composited hits, out[2] rays with a hit (u64; out[0..3] zeroed here)
+hipError_t launch_work_counts(const uint2 *ranges, const uint32_t *ids, const uint2 *rects, int64_t P,
                               const float4 *st1, const Grid &g, unsigned long long *out, hipStream_t s);
 
 // ---- raster.hip ----
@@ -62,6 +67,9 @@ hipError_t launch_raster_fwd(const RasterBufs &R, const Grid &g, const RasterPar
                              float *opacity, float *normal, uint8_t *drop, hipStream_t s);
 hipError_t launch_raster_bwd_prep(const RasterBufs &R, const Grid &g, const float *gD, const float *gA,
                                   const float *gN, float4 *gb0, float *gb1, hipStream_t s);
+// out (u64, device) += ray tests needed up to each wave's last contributor (query only)
+hipError_t launch_work_needed(const RasterBufs &R, const Grid &g, const RasterParams &p, unsigned long long *out,
+                              hipStream_t s);
 hipError_t launch_raster_bwd(const RasterBufs &R, const Grid &g, const RasterParams &p, const float4 *gb0,
                              const float *gb1, float *recgrad, hipStream_t s);
 
@@ -76,5 +84,20 @@ int chain_blocks(int64_t n);
 hipError_t launch_chain(const SurfelPtrs &S, const float *pose_dev, const RasterParams &p, const float *recgrad,
                         float *d_means, float *d_quats, float *d_log_scales, float *d_logits, float *pose_partials,
                         float *grad_pose, hipStream_t s);
+
+// ---- adam.hip ----
+struct AdamGroup {
+    int64_t n;
+    float *param;
+    const float *grad;
+    float *m, *v;
+    float lr;
+};
+struct AdamBatch {
+    AdamGroup g[8];
+    int64_t first_block[8];  // filled by launch_adam
+    int count;
+};
+hipError_t launch_adam(AdamBatch B, float beta1, float beta2, float eps, int step, hipStream_t s);
 
 }  // namespace lgsr

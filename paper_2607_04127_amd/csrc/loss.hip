@@ -1,5 +1,5 @@
 // loss.hip -- masked depth L1 + G-ICP normal cosine loss and its per-ray gradient
-// (arXiv 2607.04127 Sec. 3.4, Eq. 8 left and Eq. 9 first term; weights of Sec. 4.1).
+// (arXiv 2607.04127 Sec. 3.4, Eq. 10 left and Eq. 11 first term; weights of Sec. 4.1).
 //
 //   L = w_depth / |Omega_D| sum M_D |D^ - D| + lambda_n lambda_ng / |Omega_N| sum M_N (1 - N^.N / |N^|)
 //   M_D = [D > 0], M_N = M_D [|N| > 0]

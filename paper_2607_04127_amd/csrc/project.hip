@@ -1,4 +1,4 @@
-// project.hip -- per-surfel projection and culling, pair emission and tile ranges.
+// project.hip -- per-surfel projection and culling, per-tile pair counts and emission.
 //
 // Projection (one thread per surfel): activations (normalised q, s = exp(s~) per Sec. 3.3,
 // alpha = sigmoid), world -> sensor transform, the 64-byte record of lgsr_internal.h, and
@@ -72,31 +72,34 @@ __device__ __forceinline__ int first_row_lt(const float *__restrict__ rows, int 
     return lo;
 }
 
-__global__ __launch_bounds__(256) void project_kernel(SurfelPtrs S, Pose pose_val, const float *__restrict__ pose_dev,
-                                                      float *__restrict__ pose_out,
-                                                      const float *__restrict__ rows, Grid g, RasterParams p,
-                                                      float *__restrict__ recs, uint2 *__restrict__ rects,
-                                                      uint32_t *__restrict__ keys, uint32_t *__restrict__ vals,
-                                                      uint32_t *__restrict__ cnt)
+// Calls f(tile) for every tile met by the ray rectangle rc (rows r0..r1, columns c0 ..
+// c0 + cw - 1 modulo W); projection (counting) and emission (writing) both enumerate with it.
+template <class F>
+__device__ __forceinline__ void for_each_tile(uint2 rc, const Grid &g, F &&f)
 {
-    Pose P = pose_val;
-    if (pose_dev) {
-        for (int c = 0; c < 9; ++c) P.r[c] = pose_dev[(c / 3) * 4 + (c % 3)];
-        for (int c = 0; c < 3; ++c) P.t[c] = pose_dev[4 * c + 3];
+    const int r0 = (int)(rc.x & 0xFFFFu), r1 = (int)(rc.x >> 16);
+    const int c0 = (int)(rc.y & 0xFFFFu), cw = (int)(rc.y >> 16);
+    if (cw <= 0) return;
+    int a0, a1, b0, b1;
+    col_segments(c0, cw, g.W, g.TW, a0, a1, b0, b1);
+    for (int tr = r0 / kTile; tr <= r1 / kTile; ++tr) {
+        for (int tc = a0; tc <= a1; ++tc) f(tile_id(tr, tc, g.TH));
+        for (int tc = b0; tc <= b1; ++tc) f(tile_id(tr, tc, g.TH));
     }
-    if (blockIdx.x == 0 && threadIdx.x < 12) {
-        int c = threadIdx.x, row = c >> 2, col = c & 3;
-        pose_out[c] = col < 3 ? P.r[3 * row + col] : P.t[row];
-    }
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= S.n) return;
-    vals[i] = (uint32_t)i;
+}
+
+// Grids with at most this many tiles count and reserve pairs in LDS per workgroup.
+constexpr int kLdsBins = 4096;
+
+// Record, range key and ray rectangle of surfel i; (0, 0) when it cannot be hit.
+__device__ __forceinline__ uint2 project_one(const SurfelPtrs &S, const Pose &P, const float *__restrict__ rows,
+                                             const Grid &g, const RasterParams &p, float *__restrict__ recs,
+                                             uint32_t *__restrict__ keys, int64_t i)
+{
     Geom gm = project_geom(S.means, S.quats, S.log_scales, S.logits, i, P, p.near);
     if (!gm.valid) {
         keys[i] = kCulledKey;
-        cnt[i] = 0;
-        rects[i] = make_uint2(0u, 0u);
-        return;
+        return make_uint2(0u, 0u);
     }
     float rec[kRec];
     make_record(gm, rec);
@@ -141,58 +144,88 @@ __global__ __launch_bounds__(256) void project_kernel(SurfelPtrs S, Pose pose_va
             }
         }
     }
-    if (r0 > r1 || cw <= 0) {
-        cnt[i] = 0;
-        rects[i] = make_uint2(0u, 0u);
+    if (r0 > r1 || cw <= 0) return make_uint2(0u, 0u);
+    return make_uint2((uint32_t)r0 | ((uint32_t)r1 << 16), (uint32_t)c0 | ((uint32_t)cw << 16));
+}
+
+// Projection plus the per-tile pair counts, tile_cnt[t * kShards + shard_of(i)] (zero on
+// entry).  A workgroup's surfels share one shard.  Dynamic LDS: T words when T <= kLdsBins,
+// else none (counts then go straight to tile_cnt).
+__global__ __launch_bounds__(256) void project_kernel(SurfelPtrs S, Pose pose_val, const float *__restrict__ pose_dev,
+                                                      float *__restrict__ pose_out,
+                                                      const float *__restrict__ rows, Grid g, RasterParams p,
+                                                      float *__restrict__ recs, uint2 *__restrict__ rects,
+                                                      uint32_t *__restrict__ keys, uint32_t *__restrict__ tile_cnt)
+{
+    extern __shared__ uint32_t bins[];
+    const bool lds_bins = g.T <= kLdsBins;
+    if (lds_bins)
+        for (int b = threadIdx.x; b < g.T; b += 256) bins[b] = 0u;
+    Pose P = pose_val;
+    if (pose_dev) {
+        for (int c = 0; c < 9; ++c) P.r[c] = pose_dev[(c / 3) * 4 + (c % 3)];
+        for (int c = 0; c < 3; ++c) P.t[c] = pose_dev[4 * c + 3];
+    }
+    if (blockIdx.x == 0 && threadIdx.x < 12) {
+        int c = threadIdx.x, row = c >> 2, col = c & 3;
+        pose_out[c] = col < 3 ? P.r[3 * row + col] : P.t[row];
+    }
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint2 rc = make_uint2(0u, 0u);
+    if (i < S.n) {
+        rc = project_one(S, P, rows, g, p, recs, keys, i);
+        rects[i] = rc;
+    }
+    const int sh = shard_of((int64_t)blockIdx.x * blockDim.x);
+    if (lds_bins) {
+        __syncthreads();
+        for_each_tile(rc, g, [&](int t) { atomicAdd(&bins[t], 1u); });
+        __syncthreads();
+        for (int b = threadIdx.x; b < g.T; b += 256) {
+            const uint32_t c = bins[b];
+            if (c) atomicAdd(&tile_cnt[b * kShards + sh], c);
+        }
+    } else {
+        for_each_tile(rc, g, [&](int t) { atomicAdd(&tile_cnt[t * kShards + sh], 1u); });
+    }
+}
+
+// Writes surfel ids into their tiles' buckets: cursor[t * kShards + s] starts at the first
+// slot of shard s of tile t.
+// Per workgroup, pairs are counted per tile in LDS, one range per tile is reserved with a
+// single atomic, and the workgroup's pairs fill it.  Positions at or beyond P are dropped
+// (they cannot occur when the counts came from project_kernel over the same rectangles).
+__global__ __launch_bounds__(256) void emit_kernel(const uint2 *__restrict__ rects, int64_t n, Grid g,
+                                                   uint32_t *__restrict__ cursor, uint32_t *__restrict__ pv,
+                                                   int64_t P)
+{
+    extern __shared__ uint32_t bins[];  // count, then reserved base, per tile
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint2 rc = i < n ? rects[i] : make_uint2(0u, 0u);
+    const uint32_t id = (uint32_t)i;
+    const int sh = shard_of((int64_t)blockIdx.x * blockDim.x);
+    if (g.T > kLdsBins) {
+        for_each_tile(rc, g, [&](int t) {
+            const uint32_t pos = atomicAdd(&cursor[t * kShards + sh], 1u);
+            if ((int64_t)pos < P) pv[pos] = id;
+        });
         return;
     }
-    rects[i] = make_uint2((uint32_t)r0 | ((uint32_t)r1 << 16), (uint32_t)c0 | ((uint32_t)cw << 16));
-    int a0, a1, b0, b1;
-    col_segments(c0, cw, W, g.TW, a0, a1, b0, b1);
-    int ncol = (a1 - a0 + 1) + (b1 >= b0 ? b1 - b0 + 1 : 0);
-    int nrow = r1 / kTile - r0 / kTile + 1;
-    cnt[i] = (uint32_t)(ncol * nrow);
-}
-
-__global__ __launch_bounds__(256) void emit_kernel(const uint32_t *__restrict__ sorted_ids,
-                                                   const uint32_t *__restrict__ cnt,
-                                                   const uint32_t *__restrict__ offs,
-                                                   const uint2 *__restrict__ rects, int64_t n, Grid g,
-                                                   uint32_t *__restrict__ pk, uint32_t *__restrict__ pv)
-{
-    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= n) return;
-    uint32_t id = sorted_ids[k];
-    uint32_t c = cnt[id];
-    if (c == 0) return;
-    uint32_t o = offs[k];
-    uint2 rc = rects[id];
-    int r0 = (int)(rc.x & 0xFFFFu), r1 = (int)(rc.x >> 16);
-    int c0 = (int)(rc.y & 0xFFFFu), cw = (int)(rc.y >> 16);
-    int a0, a1, b0, b1;
-    col_segments(c0, cw, g.W, g.TW, a0, a1, b0, b1);
-    for (int tr = r0 / kTile; tr <= r1 / kTile; ++tr) {
-        for (int tc = a0; tc <= a1; ++tc) {
-            pk[o] = (uint32_t)tile_id(tr, tc, g.TH);
-            pv[o] = id;
-            ++o;
-        }
-        for (int tc = b0; tc <= b1; ++tc) {
-            pk[o] = (uint32_t)tile_id(tr, tc, g.TH);
-            pv[o] = id;
-            ++o;
-        }
+    uint32_t *cnt = bins, *base = bins + g.T;
+    for (int b = threadIdx.x; b < g.T; b += 256) cnt[b] = 0u;
+    __syncthreads();
+    for_each_tile(rc, g, [&](int t) { atomicAdd(&cnt[t], 1u); });
+    __syncthreads();
+    for (int b = threadIdx.x; b < g.T; b += 256) {
+        const uint32_t c = cnt[b];
+        if (c) base[b] = atomicAdd(&cursor[b * kShards + sh], c);
+        cnt[b] = 0u;
     }
-}
-
-__global__ __launch_bounds__(256) void ranges_kernel(const uint32_t *__restrict__ keys, int64_t P,
-                                                     uint2 *__restrict__ ranges)
-{
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= P) return;
-    uint32_t t = keys[i];
-    if (i == 0 || keys[i - 1] != t) ranges[t].x = (uint32_t)i;
-    if (i == P - 1 || keys[i + 1] != t) ranges[t].y = (uint32_t)(i + 1);
+    __syncthreads();
+    for_each_tile(rc, g, [&](int t) {
+        const uint32_t pos = base[t] + atomicAdd(&cnt[t], 1u);
+        if ((int64_t)pos < P) pv[pos] = id;
+    });
 }
 
 __global__ __launch_bounds__(256) void fill_u32_kernel(uint32_t *__restrict__ p, uint32_t v, int64_t n)
@@ -226,8 +259,10 @@ __global__ __launch_bounds__(256) void max_range_kernel(const uint2 *__restrict_
     }
 }
 
-// out[0] += ray-surfel tests of the raster (64 per pair and overlapping wave sub-tile)
-__global__ __launch_bounds__(256) void work_tests_kernel(const uint32_t *__restrict__ tile_keys,
+// out[0] += ray-surfel tests of the raster (64 per pair and overlapping wave sub-tile).  The
+// tile of pair i is the last tile whose list starts at or before i (lists are laid out in
+// tile order, empty ones included).
+__global__ __launch_bounds__(256) void work_tests_kernel(const uint2 *__restrict__ ranges,
                                                          const uint32_t *__restrict__ ids,
                                                          const uint2 *__restrict__ rects, int64_t P, Grid g,
                                                          unsigned long long *__restrict__ out)
@@ -235,7 +270,13 @@ __global__ __launch_bounds__(256) void work_tests_kernel(const uint32_t *__restr
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     unsigned long long c = 0;
     if (i < P) {
-        int t = (int)tile_keys[i];
+        int lo = 0, hi = g.T - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if ((int64_t)ranges[mid].x <= i) lo = mid;
+            else hi = mid - 1;
+        }
+        int t = lo;
         int tc = t / g.TH, tr = t - tc * g.TH;
         uint2 rc = rects[ids[i]];
         for (int w = 0; w < 4; ++w) {
@@ -270,12 +311,12 @@ __global__ __launch_bounds__(256) void work_hits_kernel(const float4 *__restrict
 
 static inline unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
-hipError_t launch_work_counts(const uint32_t *tile_keys, const uint32_t *ids, const uint2 *rects, int64_t P,
+hipError_t launch_work_counts(const uint2 *ranges, const uint32_t *ids, const uint2 *rects, int64_t P,
                               const float4 *st1, const Grid &g, unsigned long long *out, hipStream_t s)
 {
-    hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t *>(out), 0u, 6, s);
+    hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t *>(out), 0u, 8, s);
     if (e != hipSuccess) return e;
-    if (P > 0) work_tests_kernel<<<blocks_for(P, 256), 256, 0, s>>>(tile_keys, ids, rects, P, g, out);
+    if (P > 0) work_tests_kernel<<<blocks_for(P, 256), 256, 0, s>>>(ranges, ids, rects, P, g, out);
     int64_t rays = (int64_t)g.H * g.W;
     work_hits_kernel<<<blocks_for(rays, 256), 256, 0, s>>>(st1, rays, out);
     return hipGetLastError();
@@ -283,18 +324,20 @@ hipError_t launch_work_counts(const uint32_t *tile_keys, const uint32_t *ids, co
 
 hipError_t launch_project(const SurfelPtrs &S, const Pose &pose_val, const float *pose_dev, float *pose_out,
                           const float *rows, const Grid &g, const RasterParams &p, float *recs, uint2 *rects,
-                          uint32_t *keys, uint32_t *vals, uint32_t *cnt, hipStream_t s)
+                          uint32_t *keys, uint32_t *tile_cnt, hipStream_t s)
 {
     unsigned nb = S.n > 0 ? blocks_for(S.n, 256) : 1u;  // one block still writes the pose
-    project_kernel<<<nb, 256, 0, s>>>(S, pose_val, pose_dev, pose_out, rows, g, p, recs, rects, keys, vals, cnt);
+    size_t lds = g.T <= kLdsBins ? (size_t)g.T * sizeof(uint32_t) : 0;
+    project_kernel<<<nb, 256, lds, s>>>(S, pose_val, pose_dev, pose_out, rows, g, p, recs, rects, keys, tile_cnt);
     return hipGetLastError();
 }
 
-hipError_t launch_emit(const uint32_t *sorted_ids, const uint32_t *cnt, const uint32_t *offs, const uint2 *rects,
-                       int64_t n, const Grid &g, uint32_t *pk, uint32_t *pv, hipStream_t s)
+hipError_t launch_emit(const uint2 *rects, int64_t n, const Grid &g, uint32_t *cursor, uint32_t *pv, int64_t P,
+                       hipStream_t s)
 {
-    if (n <= 0) return hipSuccess;
-    emit_kernel<<<blocks_for(n, 256), 256, 0, s>>>(sorted_ids, cnt, offs, rects, n, g, pk, pv);
+    if (n <= 0 || P <= 0) return hipSuccess;
+    size_t lds = g.T <= kLdsBins ? 2 * (size_t)g.T * sizeof(uint32_t) : 0;
+    emit_kernel<<<blocks_for(n, 256), 256, lds, s>>>(rects, n, g, cursor, pv, P);
     return hipGetLastError();
 }
 
@@ -302,14 +345,6 @@ hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
     fill_u32_kernel<<<blocks_for(n, 256), 256, 0, s>>>(p, v, n);
-    return hipGetLastError();
-}
-
-hipError_t launch_ranges(const uint32_t *sorted_keys, int64_t P, int T, uint2 *ranges, hipStream_t s)
-{
-    hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t *>(ranges), 0u, 2 * (int64_t)T, s);
-    if (e != hipSuccess || P <= 0) return e;
-    ranges_kernel<<<blocks_for(P, 256), 256, 0, s>>>(sorted_keys, P, ranges);
     return hipGetLastError();
 }
 

@@ -26,8 +26,9 @@
 // with the chunk's end transmittance and its B (the later chunks' sums gD~ S_D + gN~ . S_N
 // + gA~ S_A) set up per ray beforehand, and T_j recovered as T_{j+1} / (1 - alpha_hat_j)
 // from the bit-identical recomputed alpha_hat_j.  The per-(ray, surfel) gradient w.r.t.
-// the record quantities (nt, c, U, V, alpha) is summed over the wave and added with one
-// vector atomic (11 lanes) per surfel and wave.
+// the record quantities (nt, c, cu, U, cv, V, alpha; U and V split along m as the record
+// splits them) is summed over the wave and added with one vector atomic (13 lanes) per
+// surfel and wave.
 #include "lgsr_internal.h"
 #include "lgsr_kernels.h"
 
@@ -469,10 +470,10 @@ __global__ __launch_bounds__(256) void raster_bwd_prep_kernel(const uint32_t *__
     }
 }
 
-// Wave-wide sums of 12 per-lane values by transposition: v_permlane32_swap folds lanes
-// 32-63 onto 0-31 for six pairs (i, i + 6), v_permlane16_swap folds odd rows onto even rows
-// for three pairs, and four DPP steps (xor 1, xor 2, half-row mirror, row mirror) finish
-// each 16-lane row.  Afterwards lane 16 r + k (k < 3) holds the total of value 3 r + k.
+// Wave-wide sums of 16 per-lane values by transposition: v_permlane32_swap folds lanes
+// 32-63 onto 0-31 for eight pairs (i, i + 8), v_permlane16_swap folds odd rows onto even rows
+// for four pairs, and four DPP steps (xor 1, xor 2, half-row mirror, row mirror) finish
+// each 16-lane row.  Afterwards lane 16 r + k (k < 4) holds the total of value 4 r + k.
 // Needs all 64 lanes active.
 template <int CTRL>
 __device__ __forceinline__ float dpp_add(float v)
@@ -492,14 +493,14 @@ __device__ __forceinline__ float swap16_add(float x, float y)
     return __uint_as_float(r[0]) + __uint_as_float(r[1]);
 }
 
-__device__ __forceinline__ float wave_sum12(const float (&g)[12], int lane)
+__device__ __forceinline__ float wave_sum16(const float (&g)[16], int lane)
 {
-    float a[6], b[3];
+    float a[8], b[4];
 #pragma unroll
-    for (int i = 0; i < 6; ++i) a[i] = swap32_add(g[i], g[i + 6]);
+    for (int i = 0; i < 8; ++i) a[i] = swap32_add(g[i], g[i + 8]);
 #pragma unroll
-    for (int i = 0; i < 3; ++i) {
-        float v = swap16_add(a[i], a[i + 3]);
+    for (int i = 0; i < 4; ++i) {
+        float v = swap16_add(a[i], a[i + 4]);
         v = dpp_add<0xB1>(v);   // quad_perm [1,0,3,2]
         v = dpp_add<0x4E>(v);   // quad_perm [2,3,0,1]
         v = dpp_add<0x141>(v);  // row_half_mirror
@@ -507,7 +508,7 @@ __device__ __forceinline__ float wave_sum12(const float (&g)[12], int lane)
         b[i] = v;
     }
     const int k = lane & 15;
-    return k == 0 ? b[0] : (k == 1 ? b[1] : b[2]);
+    return k == 0 ? b[0] : (k == 1 ? b[1] : (k == 2 ? b[2] : b[3]));
 }
 
 __device__ __forceinline__ int wave_max_i(int v)
@@ -563,9 +564,9 @@ __global__ __launch_bounds__(256) void raster_bwd_chunk_kernel(
             const int pos = (int)(base + e);
             if (pos > wmax) continue;
             const Rec s = staged_rec(sm, e);
-            float gv[12];
+            float gv[16];
 #pragma unroll
-            for (int c = 0; c < 12; ++c) gv[c] = 0.f;
+            for (int c = 0; c < 16; ++c) gv[c] = 0.f;
             bool contrib = false;
             if (pos <= last) {
                 const Hit h = hit_test(s, ray, p);
@@ -594,22 +595,62 @@ __global__ __launch_bounds__(256) void raster_bwd_chunk_kernel(
                     gv[G_NT + 1] = fmaf(gbN1, w, dden * ray.dh[1]);
                     gv[G_NT + 2] = fmaf(gbN2, w, dden * ray.dh[2]);
                     gv[G_C] = dt * h.inv;
-                    gv[G_U + 0] = dnu * ray.dh[0];
-                    gv[G_U + 1] = dnu * ray.dh[1];
-                    gv[G_U + 2] = dnu * ray.dh[2];
-                    gv[G_V + 0] = dnv * ray.dh[0];
-                    gv[G_V + 1] = dnv * ray.dh[1];
-                    gv[G_V + 2] = dnv * ray.dh[2];
+                    gv[G_CU] = dnu;
+                    gv[G_U + 0] = dnu * h.e[0];
+                    gv[G_U + 1] = dnu * h.e[1];
+                    gv[G_U + 2] = dnu * h.e[2];
+                    gv[G_CV] = dnv;
+                    gv[G_V + 0] = dnv * h.e[0];
+                    gv[G_V + 1] = dnv * h.e[1];
+                    gv[G_V + 2] = dnv * h.e[2];
                     gv[G_ALPHA] = dalpha;
                 }
             }
             if (__any(contrib)) {
-                const float mine = wave_sum12(gv, L.lane);
-                const int k = L.lane & 15, c = 3 * (L.lane >> 4) + k;
-                if (k < 3 && c < 11) unsafeAtomicAdd(recgrad + (size_t)sm.id[e] * kGrad + c, mine);
+                const float mine = wave_sum16(gv, L.lane);
+                const int k = L.lane & 15, c = 4 * (L.lane >> 4) + k;
+                if (k < 4 && c < kGradUsed) unsafeAtomicAdd(recgrad + (size_t)sm.id[e] * kGrad + c, mine);
             }
         }
     }
+}
+
+// ---------------------------------------------------------------------------------------
+// work counter (query only)
+// ---------------------------------------------------------------------------------------
+
+// out += ray tests a front-to-back walk needs: per wave sub-tile, 64 per list entry that
+// overlaps it, up to the last contributor of its slowest ray (the whole list when a ray
+// never falls below T_min).  One workgroup per tile, after the forward.
+__global__ __launch_bounds__(256) void work_needed_kernel(const uint32_t *__restrict__ chunk_base,
+                                                          const uint32_t *__restrict__ ids,
+                                                          const uint2 *__restrict__ rects,
+                                                          const uint2 *__restrict__ ranges, Grid g, RasterParams p,
+                                                          const float *__restrict__ slots,
+                                                          const float4 *__restrict__ st0,
+                                                          unsigned long long *__restrict__ out)
+{
+    const int tile = blockIdx.x;
+    const Lane L = lane_of(tile, g);
+    const uint2 rg = ranges[tile];
+    int need = -1;
+    if (L.valid) {
+        const uint32_t c0 = chunk_base[tile], c1 = chunk_base[tile + 1];
+        int last = -1;
+        for (uint32_t it = c0; it < c1; ++it) last = max(last, __float_as_int(slots[slot(it, F_LAST, L.rt)]));
+        const bool dead = st0[L.k * g.W + L.j].z < p.T_min;
+        need = dead ? last : (int)rg.y - 1;
+    }
+    need = wave_max_i(need);
+    unsigned long long c = 0;
+    if (need >= 0) {
+        const int r16 = L.sr0, c16 = L.sc0;
+        const uint32_t end = min((uint32_t)need + 1u, rg.y);
+        for (uint32_t pos = rg.x + (uint32_t)L.lane; pos < end; pos += 64u)
+            c += sub_overlap(rects[ids[pos]], r16, c16, g.W) ? 64ull : 0ull;
+    }
+    for (int o = 32; o >= 1; o >>= 1) c += __shfl_xor(c, o, 64);
+    if (L.lane == 0 && c) atomicAdd(out, c);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -654,6 +695,13 @@ hipError_t launch_raster_bwd_prep(const RasterBufs &R, const Grid &g, const floa
 {
     if (g.T <= 0) return hipSuccess;
     raster_bwd_prep_kernel<<<g.T, 256, 0, s>>>(R.chunk_base, g, R.st0, R.st1, gD, gA, gN, R.slots, gb0, gb1);
+    return hipGetLastError();
+}
+
+hipError_t launch_work_needed(const RasterBufs &R, const Grid &g, const RasterParams &p, unsigned long long *out,
+                              hipStream_t s)
+{
+    work_needed_kernel<<<g.T, 256, 0, s>>>(R.chunk_base, R.ids, R.rects, R.ranges, g, p, R.slots, R.st0, out);
     return hipGetLastError();
 }
 

@@ -21,9 +21,9 @@ _STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ECAPACITY", 
 
 EXPORTS = ("lgsr_default_opts", "lgsr_default_loss_weights", "lgsr_create", "lgsr_destroy", "lgsr_set_stream",
            "lgsr_last_error", "lgsr_forward", "lgsr_loss", "lgsr_backward", "lgsr_state_free", "lgsr_query",
-           "lgsr_profile", "lgsr_profile_read", "lgsr_sync")
-STAGES = ("project", "depth_sort", "scan", "emit", "tile_sort", "ranges", "raster_fwd", "loss", "bwd_prep",
-          "raster_bwd", "chain", "readback")
+           "lgsr_profile", "lgsr_profile_read", "lgsr_sync", "lgsr_state_bytes", "lgsr_adam_step")
+STAGES = ("project", "scan", "readback", "emit", "tile_sort", "raster_fwd", "loss", "bwd_prep", "raster_bwd",
+          "chain")
 
 
 class LgsrError(RuntimeError):
@@ -65,6 +65,10 @@ class SurfelGrads(ctypes.Structure):
     _fields_ = [("means", vp), ("quats", vp), ("log_scales", vp), ("opacity_logits", vp)]
 
 
+class AdamGroup(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("param", vp), ("grad", vp), ("m", vp), ("v", vp), ("lr", ctypes.c_float)]
+
+
 _lib = None
 
 
@@ -95,8 +99,11 @@ def lib():
         L.lgsr_sync.argtypes = [vp]
         L.lgsr_profile.argtypes = [vp, ctypes.c_int32]
         L.lgsr_profile_read.argtypes = [vp, P(ctypes.c_double), P(ctypes.c_int64)]
+        L.lgsr_state_bytes.argtypes = [vp, vp, P(ctypes.c_int64)]
+        L.lgsr_adam_step.argtypes = [vp, ctypes.c_int32, P(AdamGroup), ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                     ctypes.c_int32]
         for name in ("lgsr_create", "lgsr_set_stream", "lgsr_forward", "lgsr_loss", "lgsr_backward", "lgsr_query",
-                     "lgsr_profile", "lgsr_profile_read", "lgsr_sync"):
+                     "lgsr_profile", "lgsr_profile_read", "lgsr_sync", "lgsr_state_bytes", "lgsr_adam_step"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -293,7 +300,31 @@ def lgsr_query(ctx: Context, state: State) -> dict:
     ctx._stream()
     ctx._check(lib().lgsr_query(ctx.handle, state.handle, o))
     return dict(pairs=o[0], visible=o[1], workspace_bytes=o[2], max_list=o[3], ray_tests=o[4], composites=o[5],
-                rays_hit=o[6])
+                rays_hit=o[6], ray_tests_needed=o[7])
+
+
+def lgsr_state_bytes(ctx: Context, state: State) -> int:
+    """Device bytes held by a state (host-side bookkeeping, no GPU work)."""
+    b = ctypes.c_int64()
+    ctx._check(lib().lgsr_state_bytes(ctx.handle, state.handle, ctypes.byref(b)))
+    return int(b.value)
+
+
+def lgsr_adam_step(ctx: Context, groups, step: int, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8):
+    """One fused Adam step.  groups: iterable of (param, grad, m, v, lr) with float32
+    contiguous tensors of equal shape on the context's device (param, m, v updated in place)."""
+    d = ctx.device
+    arr = (AdamGroup * 8)()
+    k = 0
+    for param, grad, m, v, lr in groups:
+        if k == 8:
+            raise ValueError("at most 8 groups per step")
+        for name, t in (("param", param), ("grad", grad), ("m", m), ("v", v)):
+            _dev(t, name, tuple(param.shape), d)
+        arr[k] = AdamGroup(param.numel(), _ptr(param), _ptr(grad), _ptr(m), _ptr(v), float(lr))
+        k += 1
+    ctx._stream()
+    ctx._check(lib().lgsr_adam_step(ctx.handle, k, arr, beta1, beta2, eps, int(step)))
 
 
 def lgsr_profile(ctx: Context, stages=True):

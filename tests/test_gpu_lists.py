@@ -1,0 +1,135 @@
+"""GPU parity of the per-tile list construction: a tile holding more entries than one
+workgroup sorts in registers (the streaming sort), surfels at exactly equal ranges (ordered
+by index on both sides), and a grid with more tiles than the per-workgroup LDS bins."""
+import numpy as np
+import pytest
+
+import scenegen
+from oracle import ref
+from tests import _gpu as G
+from tests import _util as U
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2607_04127_amd import lgsr
+    c = lgsr.Context(0)
+    yield c
+    c.close()
+
+
+def _crowded_tile(m, seed, dup_frac=0.1):
+    """m small surfels in front of the rays of one 16 x 16 tile (rows 16-31, columns
+    128-143 of 32 x 256 beams), at distinct ranges on a 1 mm grid, each centred near one
+    ray; the last dup_frac of them repeat an earlier centre exactly (equal ranges)."""
+    row, col = scenegen.beam_tables(32, 256, -15, 15)
+    D = scenegen.ray_dirs_f64(row, col).reshape(32, 256, 3)
+    rng = np.random.default_rng(seed)
+    n_dup = int(m * dup_frac)
+    n0 = m - n_dup
+    ranges = 2.0 + 1e-3 * rng.choice(23000, size=n0, replace=False)
+    rr = rng.integers(17, 31, size=n0)
+    cc = rng.integers(129, 143, size=n0)
+    d = D[rr, cc]
+    frames, cen = [], []
+    for k in range(n0):
+        f = U.frame_facing(-d[k] + rng.normal(scale=0.25, size=3), spin=rng.uniform(0, 6.28))
+        off = (f[:, 0] * rng.normal() + f[:, 1] * rng.normal()) * 3e-4 * ranges[k]
+        cen.append(ranges[k] * d[k] + off)
+        frames.append(f)
+    src = rng.integers(0, n0, size=n_dup)
+    for k in src:
+        frames.append(U.frame_facing(-d[k] + rng.normal(scale=0.25, size=3), spin=rng.uniform(0, 6.28)))
+        cen.append(cen[k])
+    cen = np.asarray(cen)
+    r = np.linalg.norm(cen, axis=1)
+    sc = r[:, None] * rng.uniform(1e-3, 4e-3, size=(m, 2))
+    al = rng.uniform(0.02, 0.2, size=m)
+    S = {k: v.astype(np.float32) for k, v in U.surfels(cen, frames, sc, al).items()}
+    # equal centres must stay bit-identical after the float32 rounding
+    S["means"][n0:] = S["means"][src]
+    return dict(S, row_sincos=row, col_sincos=col, pose=U.identity_pose().astype(np.float32))
+
+
+def _compare_all_rays(fr, of):
+    """Value parity on every ray except threshold ties: the only order ties here are exact
+    (equal centres), which both sides break by surfel index."""
+    of = dict(of, order_gap=np.full_like(of["order_gap"], np.inf))
+    return G.compare_forward(fr, of)
+
+
+@pytest.mark.parametrize("m", [3000, 12000])
+def test_crowded_tile_and_equal_ranges(ctx, m):
+    """m = 3000 sorts the tile in registers, m = 12000 exceeds one workgroup's capacity
+    (8192) and takes the streaming sort; both with 10% exact range ties."""
+    from paper_2607_04127_amd import lgsr
+    wl = _crowded_tile(m, seed=m)
+    dw = G.to_dev(wl)
+    fr, st = G.gpu_forward(ctx, dw)
+    torch.cuda.synchronize()
+    of = G.oracle_forward(wl)
+    stats = _compare_all_rays(fr, of)
+    q = lgsr.lgsr_query(ctx, st)
+    stats.update(pairs=q["pairs"], max_list=q["max_list"], mean_K=float(of["K"][of["K"] > 0].mean()))
+    print(f"\n[crowded tile m={m}] " + " ".join(f"{k}={v}" for k, v in stats.items()), flush=True)
+    assert q["max_list"] >= m
+    assert stats["hit"] > 150
+    # gradients through the same lists
+    H, W = 32, 256
+    td = np.where(of["K"] > 0, of["depth"] + 0.1, 0.0)
+    tn = np.tile(np.array([0.0, 0.0, 1.0]), (H * W, 1))
+    _, gd, go, gn = ref.loss(of, td, tn)
+    keep = (of["margin"] >= G.TIE_MARGIN).astype(np.float64)
+    gd, gn = (gd * keep).astype(np.float32), (gn * keep[:, None]).astype(np.float32)
+    go = np.zeros_like(gd)
+    grad = dict(depth=torch.from_numpy(gd.reshape(H, W)).cuda(), opacity=torch.from_numpy(go.reshape(H, W)).cuda(),
+                normal=torch.from_numpy(gn.reshape(H, W, 3)).cuda())
+    out, gp = lgsr.lgsr_backward(ctx, st, grad)
+    torch.cuda.synchronize()
+    g_ref = ref.backward(wl, wl["pose"], wl["row_sincos"], wl["col_sincos"], gd, go, gn, with_mass=True)
+    for k, key in enumerate(G.SURF_KEYS):
+        nbad, cos, worst = G.grad_check(out[key].cpu().numpy(), g_ref[key], mass=g_ref["mass"][:, k])
+        assert nbad == 0 and cos > 0.99999, (key, nbad, cos, worst)
+    nbad, cos, worst = G.grad_check(gp.cpu().numpy(), g_ref["pose"], mass=g_ref["pose_mass"], per_row=False)
+    assert nbad == 0 and cos > 0.99999, ("pose", nbad, cos, worst)
+    st.free()
+
+
+def test_equal_ranges_deterministic(ctx):
+    """Entries arrive in each tile list in whatever order the emission atomics give; the
+    sorted lists, and so the frame, must not depend on it."""
+    wl = _crowded_tile(3000, seed=5, dup_frac=0.3)
+    dw = G.to_dev(wl)
+    a, _ = G.gpu_forward(ctx, dw, want_state=False)
+    a = {k: v.clone() for k, v in a.items()}
+    for _ in range(3):
+        b, _ = G.gpu_forward(ctx, dw, want_state=False)
+        for k in a:
+            assert torch.equal(a[k], b[k]), k
+
+
+def test_grid_beyond_lds_bins(ctx):
+    """80 x 13120 beams = 5 x 820 = 4100 tiles, more than the 4096 per-workgroup LDS bins:
+    counting and emission go through global atomics."""
+    w = scenegen.make_workload("room32x256_1k")
+    idx = np.random.default_rng(3).choice(1000, size=300, replace=False)
+    S = {k: np.ascontiguousarray(w[k][idx]) for k in G.SURF_KEYS}
+    S["log_scales"] = (S["log_scales"] + np.float32(np.log(2.0))).astype(np.float32)
+    H, W = 80, 13120
+    row, col = scenegen.beam_tables(H, W, -15, 15)
+    wl = dict(S, row_sincos=row, col_sincos=col, pose=w["pose"])
+    fr, st = G.gpu_forward(ctx, G.to_dev(wl))
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(11)
+    ids = np.sort(rng.choice(H * W, size=16384, replace=False))
+    of = G.oracle_forward(wl, ray_ids=ids)
+    stats = G.compare_forward(fr, of, ray_ids=ids)
+    print("\n[grid 80x13120] " + " ".join(f"{k}={v}" for k, v in stats.items()), flush=True)
+    assert stats["hit"] > 1000
+    st.free()
