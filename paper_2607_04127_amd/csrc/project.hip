@@ -2,12 +2,10 @@
 //
 // Projection (one thread per surfel): activations (normalised q, s = exp(s~) per Sec. 3.3,
 // alpha = sigmoid), world -> sensor transform, the 64-byte record of lgsr_internal.h, and
-// a conservative ray rectangle: every hit with u^2 + v^2 <= k^2 lies within
-// rho = k max(s0, s1) of the centre, so its direction lies in the cone of half-angle
-// asin(rho / r) around the centre direction.  The cone maps to an elevation interval
-// (rows, by binary search of the monotone row table) and an azimuth interval of half
-// width asin(sin beta / cos phi_c) (columns, uniform, wrapping at 360 degrees), or to
-// whole rows of azimuth when a pole lies inside the cone.
+// a conservative ray rectangle of the hit disk u^2 + v^2 <= k^2 (bounds along the centre,
+// elevation and azimuth directions; see project_one): an elevation interval (rows, by
+// binary search of the monotone row table) and an azimuth interval (columns, uniform,
+// wrapping at 360 degrees), or whole rows of azimuth when a pole may lie inside.
 #include "lgsr_internal.h"
 #include "lgsr_kernels.h"
 
@@ -16,6 +14,8 @@ namespace lgsr {
 // Angular safety margin of the culling cone (radians): far above float32 rounding of
 // the angles involved, far below one beam spacing.
 constexpr float kAngMargin = 2e-4f;
+// Relative inflation of the disk's extents: covers float32 rounding of the frame and scales.
+constexpr float kExtSlack = 1e-4f;
 constexpr float kHalfPi = 1.57079632679489662f;
 constexpr float kTwoPi = 6.28318530717958648f;
 
@@ -110,29 +110,60 @@ __device__ __forceinline__ uint2 project_one(const SurfelPtrs &S, const Pose &P,
     dst[3] = make_float4(rec[12], rec[13], rec[14], rec[15]);
     keys[i] = __float_as_uint(gm.r);
 
-    // conservative ray rectangle
+    // Conservative ray rectangle of the hit region: the disk u^2 + v^2 <= k^2, i.e. the
+    // points p = mu' + delta, delta = x a' + y b' with (x / s0)^2 + (y / s1)^2 <= k^2.  Along
+    // a unit vector e, |delta . e| <= ext(e) = k sqrt((s0 a'.e)^2 + (s1 b'.e)^2); the bound
+    // is taken along the centre direction m and the elevation and azimuth directions
+    // e_el, e_az there.  With p = (r + d_m) m + d_el e_el + d_az e_az:
+    //   elevation of the vertical-plane part: phi_c + atan2(d_el, r + d_m), within
+    //   +- A = atan(ext_el / (r - ext_m)); the horizontal offset d_az only moves the
+    //   elevation toward the equator, by at most the factor c = 1/sqrt(1 + (ext_az / (r -
+    //   ext_m))^2) on its sine;
+    //   azimuth: atan2(d_az, h) with h >= (r - ext_m) cos phi_c - ext_el |sin phi_c|.
+    // Tilted (foreshortened) and elongated surfels get a footprint much tighter than the
+    // bounding cone of radius k max(s0, s1).
     const int H = g.H, W = g.W;
     int r0, r1, c0, cw;
-    float rho = p.cutoff * fmaxf(gm.s0, gm.s1);
-    if (rho >= gm.r * 0.999f) {
+    const float mx = rec[R_M + 0], my = rec[R_M + 1], mz = fminf(1.f, fmaxf(-1.f, rec[R_M + 2]));
+    const float ch = sqrtf(mx * mx + my * my);
+    const float ct = ch > 0.f ? mx / ch : 1.f, st = ch > 0.f ? my / ch : 0.f;
+    const float eel[3] = {-mz * ct, -mz * st, ch};
+    const float eaz[3] = {-st, ct, 0.f};
+    const float mm[3] = {mx, my, mz};
+    auto ext = [&](const float *e) {
+        const float pa = gm.s0 * (gm.a[0] * e[0] + gm.a[1] * e[1] + gm.a[2] * e[2]);
+        const float pb = gm.s1 * (gm.b[0] * e[0] + gm.b[1] * e[1] + gm.b[2] * e[2]);
+        return p.cutoff * sqrtf(pa * pa + pb * pb) * (1.f + kExtSlack);
+    };
+    const float ext_m = ext(mm), ext_el = ext(eel), ext_az = ext(eaz);
+    const float rmin = gm.r - ext_m;
+    if (rmin <= 0.05f * gm.r) {  // the disk reaches around the sensor: every ray
         r0 = 0; r1 = H - 1; c0 = 0; cw = W;
     } else {
-        float beta = asinf(rho / gm.r) + kAngMargin;
-        float mz = fminf(1.f, fmaxf(-1.f, rec[R_M + 2]));
-        float phic = asinf(mz);
-        float s_hi = (phic + beta >= kHalfPi) ? 2.f : sinf(phic + beta);
-        float s_lo = (phic - beta <= -kHalfPi) ? -2.f : sinf(phic - beta);
+        const float phic = asinf(mz);
+        const float A = atanf(ext_el / rmin);
+        const float q = ext_az / rmin;
+        const float c = 1.f / sqrtf(1.f + q * q);
+        float hi = phic + A, lo = phic - A;
+        if (hi < 0.f) hi = asinf(sinf(hi) * c);
+        if (lo > 0.f) lo = asinf(sinf(lo) * c);
+        hi += kAngMargin;
+        lo -= kAngMargin;
+        const bool pole = hi >= kHalfPi || lo <= -kHalfPi;
+        const float s_hi = hi >= kHalfPi ? 2.f : sinf(hi);
+        const float s_lo = lo <= -kHalfPi ? -2.f : sinf(lo);
         r0 = first_row_le(rows, H, s_hi);
         r1 = first_row_lt(rows, H, s_lo) - 1;
-        if (fabsf(phic) + beta >= kHalfPi) {
+        const float hmin = rmin * ch - ext_el * fabsf(mz);
+        if (pole || hmin <= 0.f) {
             c0 = 0; cw = W;
         } else {
-            float thc = atan2f(rec[R_M + 1], rec[R_M + 0]);
-            float dth = asinf(fminf(1.f, sinf(beta) / cosf(phic))) + kAngMargin;
-            float scale = (float)W / kTwoPi;
-            int jlo = (int)ceilf((thc - dth) * scale);
-            int jhi = (int)floorf((thc + dth) * scale);
-            int w = jhi - jlo + 1;
+            const float thc = atan2f(my, mx);
+            const float dth = atanf(ext_az / hmin) + kAngMargin;
+            const float scale = (float)W / kTwoPi;
+            const int jlo = (int)ceilf((thc - dth) * scale);
+            const int jhi = (int)floorf((thc + dth) * scale);
+            const int w = jhi - jlo + 1;
             if (w >= W) {
                 c0 = 0; cw = W;
             } else if (w <= 0) {
