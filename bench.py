@@ -36,6 +36,24 @@ PEAK_FP32_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
 PEAK_FP32_PUBLISHED = 157.3
 PEAK_HBM_GBS = 8000.0
 
+# HBM bytes of one raster_bwd launch on the benchmark workload: rocprofv3 FETCH_SIZE and
+# WRITE_SIZE per dispatch, each scaled by what the counter reads for a plain 256 MiB device
+# copy (profiles/pmc_traffic_raster_bwd_block64x1024_300k.md).  Valid only for the kernel
+# sources they were taken with (digest below); reported as null once those change.
+TRAFFIC_RASTER_BWD = dict(bytes=38259330,
+                          sources_sha256="2223136e58d47cf7d18d911aee730a3956bf1395255dd913fff8b4e1bd08edbe")
+
+
+def _sources_digest() -> str:
+    import hashlib
+    d = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2607_04127_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".h")):
+            with open(os.path.join(csrc, name), "rb") as f:
+                d.update(name.encode() + b"\0" + f.read())
+    return d.hexdigest()
+
 
 def _bytes_model(n, P, rays):
     """Bytes a tile-binned forward + backward must move (record and gradient layouts of
@@ -187,7 +205,9 @@ def main():
                    "step_latency_ms_p99": round(p99, 4)},
         "roofline": {"kernel": "raster_bwd", "bound": "alu", "achieved": round(achieved, 3),
                      "peak": round(PEAK_FP32_TFLOPS, 1), "unit": "TFLOP/s",
-                     "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None,
+                     "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
+                     "traffic": (TRAFFIC_RASTER_BWD["bytes"]
+                                 if TRAFFIC_RASTER_BWD["sources_sha256"] == _sources_digest() else None),
                      "flops_per_launch": flops_bwd, "ms_per_launch": round(bwd_ms, 5),
                      "peak_published_packed": PEAK_FP32_PUBLISHED},
         "stages_ms": {k: round(v["ms_per_call"], 5) for k, v in stages.items() if v["calls"]},
