@@ -1,6 +1,8 @@
 // chain.hip -- record-space gradients -> surfel parameters and the 6-DoF pose.
 //
-// The backward raster leaves, per surfel, dL/d(nt, c, cu, U, cv, V, alpha) summed over rays,
+// The backward raster leaves, per surfel, dL/d(nt, c, cu, U, cv, V, alpha) summed over rays
+// (the slots of surfels with a ray rectangle, the only ones the raster writes, are cleared
+// here after they are read, so the next backward finds every slot zero),
 // where the hit test evaluates u = (cu + U.(d - m)) / den with cu = U.m (likewise v).  With
 //   nt = sigma n',  c = nt . mu',  U = sigma (b' x mu') / s0,  V = sigma (mu' x a') / s1
 // (sigma piecewise constant) the total U gradient is gU + gcu m, and with w = mu' x m
@@ -38,7 +40,8 @@ __device__ __forceinline__ Pose load_pose(const float *__restrict__ pd)
 }
 
 __global__ __launch_bounds__(kChainThreads) void chain_kernel(SurfelPtrs S, const float *__restrict__ pose_dev,
-                                                              RasterParams p, const float *__restrict__ recgrad,
+                                                              RasterParams p, const uint2 *__restrict__ rects,
+                                                              float *__restrict__ recgrad,
                                                               float *__restrict__ dm, float *__restrict__ dq,
                                                               float *__restrict__ dls, float *__restrict__ dlog,
                                                               float *__restrict__ partials)
@@ -49,10 +52,24 @@ __global__ __launch_bounds__(kChainThreads) void chain_kernel(SurfelPtrs S, cons
     if (i < S.n) {
         Geom g = project_geom(S.means, S.quats, S.log_scales, S.logits, i, P, p.near);
         float out_m[3] = {0.f, 0.f, 0.f}, out_q[4] = {0.f, 0.f, 0.f, 0.f}, out_s[2] = {0.f, 0.f}, out_o = 0.f;
-        if (g.valid) {
+        // only surfels with a ray rectangle (from the forward) can have a written slot
+        const bool listed = (rects[i].y >> 16) > 0u;
+        float4 x = make_float4(0.f, 0.f, 0.f, 0.f), y = x, z = x, zz = x;
+        if (listed) {
+            float4 *G4 = reinterpret_cast<float4 *>(recgrad + (size_t)i * kGrad);
+            x = G4[0];
+            y = G4[1];
+            z = G4[2];
+            zz = G4[3];
+            // leave the slot zero for the next backward
+            const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
+            G4[0] = z4;
+            G4[1] = z4;
+            G4[2] = z4;
+            G4[3] = z4;
+        }
+        if (g.valid && listed) {
             const RecParts q = record_parts(g);
-            const float4 *G4 = reinterpret_cast<const float4 *>(recgrad + (size_t)i * kGrad);
-            const float4 x = G4[0], y = G4[1], z = G4[2], zz = G4[3];
             const float gnt[3] = {x.x, x.y, x.z}, gc = x.w;
             const float gcu = y.x, gU[3] = {y.y, y.z, y.w};
             const float gcv = z.x, gV[3] = {z.y, z.z, z.w};
@@ -167,13 +184,14 @@ __global__ __launch_bounds__(256) void pose_finalize(int nb, const float *__rest
 
 int chain_blocks(int64_t n) { return n > 0 ? (int)((n + kChainThreads - 1) / kChainThreads) : 1; }
 
-hipError_t launch_chain(const SurfelPtrs &S, const float *pose_dev, const RasterParams &p, const float *recgrad,
+hipError_t launch_chain(const SurfelPtrs &S, const float *pose_dev, const RasterParams &p, const uint2 *rects,
+                        float *recgrad,
                         float *d_means, float *d_quats, float *d_log_scales, float *d_logits, float *pose_partials,
                         float *grad_pose, hipStream_t s)
 {
     int nb = chain_blocks(S.n);
-    chain_kernel<<<nb, kChainThreads, 0, s>>>(S, pose_dev, p, recgrad, d_means, d_quats, d_log_scales, d_logits,
-                                             pose_partials);
+    chain_kernel<<<nb, kChainThreads, 0, s>>>(S, pose_dev, p, rects, recgrad, d_means, d_quats, d_log_scales,
+                                             d_logits, pose_partials);
     pose_finalize<<<6, 256, 0, s>>>(nb, pose_partials, grad_pose);
     return hipGetLastError();
 }

@@ -89,6 +89,7 @@ struct lgsr_ctx {
     std::string err;
     // scratch
     DevBuf keys, cnt, offs, counters, recgrad, partials, pose_partials, gb0, gb1;
+    bool recgrad_zero = false;  // every record-gradient slot is zero (the chain clears what it reads)
     uint32_t *pinned = nullptr;  // host-pinned readback slots
     std::vector<lgsr_state *> pool;  // freed states kept for reuse
     std::vector<lgsr_state *> all;   // every state allocated by this context
@@ -517,6 +518,7 @@ lgsr_status lgsr_backward(lgsr_ctx *ctx, lgsr_state *S, const lgsr_frame_grad *g
     HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
     hipStream_t s = ctx->stream;
     const size_t nn = (size_t)(S->S.n > 0 ? S->S.n : 1);
+    if (ctx->recgrad.cap < nn * kGrad * sizeof(float)) ctx->recgrad_zero = false;
     HIP_TRY(ensure(ctx->recgrad, nn * kGrad * sizeof(float)), "alloc record gradients");
     HIP_TRY(ensure(ctx->pose_partials, (size_t)chain_blocks(S->S.n) * 6 * sizeof(float)), "alloc pose partials");
     const int64_t rays = (int64_t)S->g.H * S->g.W;
@@ -524,7 +526,10 @@ lgsr_status lgsr_backward(lgsr_ctx *ctx, lgsr_state *S, const lgsr_frame_grad *g
     HIP_TRY(ensure(ctx->gb1, (size_t)rays * sizeof(float)), "alloc backward state");
     {
     Stage st_(ctx, LGSR_STAGE_BWD_PREP);
-    HIP_TRY(launch_fill_u32(as<uint32_t>(ctx->recgrad), 0u, (int64_t)nn * kGrad, s), "zero record gradients");
+    if (!ctx->recgrad_zero)
+        HIP_TRY(launch_fill_u32(as<uint32_t>(ctx->recgrad), 0u, (int64_t)(ctx->recgrad.cap / sizeof(uint32_t)), s),
+                "zero record gradients");
+    ctx->recgrad_zero = false;
     HIP_TRY(launch_raster_bwd_prep(S->R, S->g, gin->d_depth, gin->d_opacity, gin->d_normal, as<float4>(ctx->gb0),
                                    as<float>(ctx->gb1), s),
             "backward set-up");
@@ -536,9 +541,11 @@ lgsr_status lgsr_backward(lgsr_ctx *ctx, lgsr_state *S, const lgsr_frame_grad *g
             "raster backward");
     }
     Stage st_(ctx, LGSR_STAGE_CHAIN);
-    HIP_TRY(launch_chain(S->S, as<float>(S->pose), S->prm, as<float>(ctx->recgrad), out->means, out->quats,
+    HIP_TRY(launch_chain(S->S, as<float>(S->pose), S->prm, as<uint2>(S->rects), as<float>(ctx->recgrad), out->means,
+                         out->quats,
                          out->log_scales, out->opacity_logits, as<float>(ctx->pose_partials), grad_pose, s),
             "chain");
+    ctx->recgrad_zero = true;
     return LGSR_OK;
 }
 

@@ -81,7 +81,9 @@ hipError_t launch_loss(int64_t n_rays, const float *depth, const float *normal, 
 
 // ---- chain.hip ----
 int chain_blocks(int64_t n);
-hipError_t launch_chain(const SurfelPtrs &S, const float *pose_dev, const RasterParams &p, const float *recgrad,
+// reads the record-gradient slots of surfels with a non-empty ray rectangle and clears them
+hipError_t launch_chain(const SurfelPtrs &S, const float *pose_dev, const RasterParams &p, const uint2 *rects,
+                        float *recgrad,
                         float *d_means, float *d_quats, float *d_log_scales, float *d_logits, float *pose_partials,
                         float *grad_pose, hipStream_t s);
 

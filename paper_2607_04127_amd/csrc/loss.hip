@@ -81,19 +81,42 @@ __global__ __launch_bounds__(kLossThreads) void loss_partials(int64_t n, const f
     }
 }
 
+// One workgroup: thread t adds partials t, t + 256, ... in order, then a fixed tree folds
+// the 256 sums (deterministic); counts are exact integers.
 __global__ __launch_bounds__(kLossThreads) void loss_finalize(int nb, const float *__restrict__ partials,
                                                               float w_depth, float lambda_n, float lambda_ng,
                                                               float *__restrict__ loss_out)
 {
-    if (threadIdx.x != 0) return;
+    __shared__ float s1[kLossThreads], s2[kLossThreads];
+    __shared__ uint32_t k1[kLossThreads], k2[kLossThreads];
+    const int t = threadIdx.x;
     float l1 = 0.f, cs = 0.f;
     uint32_t cD = 0, cN = 0;
-    for (int b = 0; b < nb; ++b) {
+    for (int b = t; b < nb; b += kLossThreads) {
         l1 += partials[4 * b];
         cs += partials[4 * b + 1];
         cD += __float_as_uint(partials[4 * b + 2]);
         cN += __float_as_uint(partials[4 * b + 3]);
     }
+    s1[t] = l1;
+    s2[t] = cs;
+    k1[t] = cD;
+    k2[t] = cN;
+    __syncthreads();
+    for (int o = kLossThreads / 2; o > 0; o >>= 1) {
+        if (t < o) {
+            s1[t] += s1[t + o];
+            s2[t] += s2[t + o];
+            k1[t] += k1[t + o];
+            k2[t] += k2[t + o];
+        }
+        __syncthreads();
+    }
+    if (t != 0) return;
+    l1 = s1[0];
+    cs = s2[0];
+    cD = k1[0];
+    cN = k2[0];
     float td = cD ? w_depth * l1 / (float)cD : 0.f;
     float tn = cN ? lambda_n * lambda_ng * cs / (float)cN : 0.f;
     loss_out[0] = td + tn;

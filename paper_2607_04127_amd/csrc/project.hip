@@ -179,6 +179,12 @@ __device__ __forceinline__ uint2 project_one(const SurfelPtrs &S, const Pose &P,
     return make_uint2((uint32_t)r0 | ((uint32_t)r1 << 16), (uint32_t)c0 | ((uint32_t)cw << 16));
 }
 
+// Surfels per projection / emission workgroup (kPerThread per thread, strided by 256): one
+// reservation per (workgroup, tile) then covers four times as many pairs.
+constexpr int kPerThread = 4;
+constexpr int kPerBlock = 256 * kPerThread;
+static_assert(kPerBlock == 1 << kShardShift, "the shard of a surfel is its workgroup's");
+
 // Projection plus the per-tile pair counts, tile_cnt[t * kShards + shard_of(i)] (zero on
 // entry).  A workgroup's surfels share one shard.  Dynamic LDS: T words when T <= kLdsBins,
 // else none (counts then go straight to tile_cnt).
@@ -201,23 +207,23 @@ __global__ __launch_bounds__(256) void project_kernel(SurfelPtrs S, Pose pose_va
         int c = threadIdx.x, row = c >> 2, col = c & 3;
         pose_out[c] = col < 3 ? P.r[3 * row + col] : P.t[row];
     }
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    uint2 rc = make_uint2(0u, 0u);
-    if (i < S.n) {
-        rc = project_one(S, P, rows, g, p, recs, keys, i);
+    const int64_t first = (int64_t)blockIdx.x * kPerBlock;
+    const int sh = shard_of(first);
+    if (lds_bins) __syncthreads();
+    for (int k = 0; k < kPerThread; ++k) {
+        const int64_t i = first + k * 256 + threadIdx.x;
+        if (i >= S.n) break;
+        const uint2 rc = project_one(S, P, rows, g, p, recs, keys, i);
         rects[i] = rc;
+        if (lds_bins) for_each_tile(rc, g, [&](int t) { atomicAdd(&bins[t], 1u); });
+        else for_each_tile(rc, g, [&](int t) { atomicAdd(&tile_cnt[t * kShards + sh], 1u); });
     }
-    const int sh = shard_of((int64_t)blockIdx.x * blockDim.x);
     if (lds_bins) {
-        __syncthreads();
-        for_each_tile(rc, g, [&](int t) { atomicAdd(&bins[t], 1u); });
         __syncthreads();
         for (int b = threadIdx.x; b < g.T; b += 256) {
             const uint32_t c = bins[b];
             if (c) atomicAdd(&tile_cnt[b * kShards + sh], c);
         }
-    } else {
-        for_each_tile(rc, g, [&](int t) { atomicAdd(&tile_cnt[t * kShards + sh], 1u); });
     }
 }
 
@@ -231,21 +237,28 @@ __global__ __launch_bounds__(256) void emit_kernel(const uint2 *__restrict__ rec
                                                    int64_t P)
 {
     extern __shared__ uint32_t bins[];  // count, then reserved base, per tile
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const uint2 rc = i < n ? rects[i] : make_uint2(0u, 0u);
-    const uint32_t id = (uint32_t)i;
-    const int sh = shard_of((int64_t)blockIdx.x * blockDim.x);
+    const int64_t first = (int64_t)blockIdx.x * kPerBlock;
+    const int sh = shard_of(first);
+    uint2 rc[kPerThread];
+#pragma unroll
+    for (int k = 0; k < kPerThread; ++k) {
+        const int64_t i = first + k * 256 + threadIdx.x;
+        rc[k] = i < n ? rects[i] : make_uint2(0u, 0u);
+    }
     if (g.T > kLdsBins) {
-        for_each_tile(rc, g, [&](int t) {
-            const uint32_t pos = atomicAdd(&cursor[t * kShards + sh], 1u);
-            if ((int64_t)pos < P) pv[pos] = id;
-        });
+        for (int k = 0; k < kPerThread; ++k) {
+            const uint32_t id = (uint32_t)(first + k * 256 + threadIdx.x);
+            for_each_tile(rc[k], g, [&](int t) {
+                const uint32_t pos = atomicAdd(&cursor[t * kShards + sh], 1u);
+                if ((int64_t)pos < P) pv[pos] = id;
+            });
+        }
         return;
     }
     uint32_t *cnt = bins, *base = bins + g.T;
     for (int b = threadIdx.x; b < g.T; b += 256) cnt[b] = 0u;
     __syncthreads();
-    for_each_tile(rc, g, [&](int t) { atomicAdd(&cnt[t], 1u); });
+    for (int k = 0; k < kPerThread; ++k) for_each_tile(rc[k], g, [&](int t) { atomicAdd(&cnt[t], 1u); });
     __syncthreads();
     for (int b = threadIdx.x; b < g.T; b += 256) {
         const uint32_t c = cnt[b];
@@ -253,10 +266,13 @@ __global__ __launch_bounds__(256) void emit_kernel(const uint2 *__restrict__ rec
         cnt[b] = 0u;
     }
     __syncthreads();
-    for_each_tile(rc, g, [&](int t) {
-        const uint32_t pos = base[t] + atomicAdd(&cnt[t], 1u);
-        if ((int64_t)pos < P) pv[pos] = id;
-    });
+    for (int k = 0; k < kPerThread; ++k) {
+        const uint32_t id = (uint32_t)(first + k * 256 + threadIdx.x);
+        for_each_tile(rc[k], g, [&](int t) {
+            const uint32_t pos = base[t] + atomicAdd(&cnt[t], 1u);
+            if ((int64_t)pos < P) pv[pos] = id;
+        });
+    }
 }
 
 __global__ __launch_bounds__(256) void fill_u32_kernel(uint32_t *__restrict__ p, uint32_t v, int64_t n)
@@ -357,7 +373,7 @@ hipError_t launch_project(const SurfelPtrs &S, const Pose &pose_val, const float
                           const float *rows, const Grid &g, const RasterParams &p, float *recs, uint2 *rects,
                           uint32_t *keys, uint32_t *tile_cnt, hipStream_t s)
 {
-    unsigned nb = S.n > 0 ? blocks_for(S.n, 256) : 1u;  // one block still writes the pose
+    unsigned nb = S.n > 0 ? blocks_for(S.n, kPerBlock) : 1u;  // one block still writes the pose
     size_t lds = g.T <= kLdsBins ? (size_t)g.T * sizeof(uint32_t) : 0;
     project_kernel<<<nb, 256, lds, s>>>(S, pose_val, pose_dev, pose_out, rows, g, p, recs, rects, keys, tile_cnt);
     return hipGetLastError();
@@ -368,7 +384,7 @@ hipError_t launch_emit(const uint2 *rects, int64_t n, const Grid &g, uint32_t *c
 {
     if (n <= 0 || P <= 0) return hipSuccess;
     size_t lds = g.T <= kLdsBins ? 2 * (size_t)g.T * sizeof(uint32_t) : 0;
-    emit_kernel<<<blocks_for(n, 256), 256, lds, s>>>(rects, n, g, cursor, pv, P);
+    emit_kernel<<<blocks_for(n, kPerBlock), 256, lds, s>>>(rects, n, g, cursor, pv, P);
     return hipGetLastError();
 }
 
