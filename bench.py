@@ -77,6 +77,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="block64x1024_300k")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--service-requests", type=int, default=2000,
+                    help="requests of the batched-service latency phase (0 = skip)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU oracle sample time")
     ap.add_argument("--chunk", type=int, default=0, help="list entries per raster chunk (0 = automatic)")
     ap.add_argument("--calib-copy", type=int, default=0,
@@ -180,6 +182,10 @@ def main():
     p50 = float(np.percentile(step_ms, 50))
     p99 = float(np.percentile(step_ms, 99))
 
+    svc = None
+    if args.service_requests > 0:
+        svc = service_phase(ctx, w, S, rows, cols, args.service_requests)
+
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(w, args.cpu_seconds)
@@ -202,7 +208,10 @@ def main():
                    "ray_tests": q["ray_tests"], "ray_tests_needed": q["ray_tests_needed"],
                    "composites": q["composites"], "rays_hit": q["rays_hit"],
                    "loss": "depth L1 + G-ICP normal cosine", "step_latency_ms_p50": round(p50, 4),
-                   "step_latency_ms_p99": round(p99, 4)},
+                   "step_latency_ms_p99": round(p99, 4),
+                   "batched_latency_ms_p50": svc["batched"]["p50_ms"] if svc else None,
+                   "batched_latency_ms_p99": svc["batched"]["p99_ms"] if svc else None},
+        "service": svc,
         "roofline": {"kernel": "raster_bwd", "bound": "alu", "achieved": round(achieved, 3),
                      "peak": round(PEAK_FP32_TFLOPS, 1), "unit": "TFLOP/s",
                      "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
@@ -219,6 +228,40 @@ def main():
     }
     print(json.dumps(out), flush=True)
     ctx.close()
+
+
+def service_phase(ctx, w, S, rows, cols, n_requests, n_poses=4, seed=45):
+    """Batched render latency on the benchmark map: n_requests Poisson arrivals (70% render,
+    30% render + gradient) over n_poses poses (random yaw, +-5 m), at 0.7 times the measured
+    one-request-per-call capacity, served batched (up to 16 per call) and one by one."""
+    import numpy as np
+    import torch
+
+    import scenegen
+    from paper_2607_04127_amd import service as SV
+
+    rng = np.random.Generator(np.random.PCG64(seed))
+    rows_np, cols_np = w["row_sincos"], w["col_sincos"]
+    pool = []
+    for k in range(n_poses):
+        pose = scenegen.make_pose(rng.uniform(0, 2 * np.pi), *rng.uniform(-5, 5, 2))
+        td, tn = scenegen.targets_for_pose(w["scene"], pose, rows_np, cols_np, 0.1, 300 + k)
+        pool.append(SV.template(S, w["means"].shape[0], rows, cols, pose, torch.from_numpy(td).to(rows.device),
+                                torch.from_numpy(tn).to(rows.device)))
+    cap = SV.capacity(ctx, pool, n=200)
+    rate = 0.7 * cap
+    stream = SV.poisson_stream(pool, n_requests, rate, grad_fraction=0.3, seed=seed)
+    out = dict(requests=n_requests, rate_rps=round(rate, 1), single_capacity_rps=round(cap, 1),
+               grad_fraction=0.3, max_batch=16)
+    for mode in ("batched", "single"):
+        SV.Service(ctx, pool, mode, max_batch=16).run(stream[:50])  # warm the per-request states
+        rep = SV.Service(ctx, pool, mode, max_batch=16).run(stream)
+        out[mode] = dict(p50_ms=round(rep["p50_ms"], 4), p99_ms=round(rep["p99_ms"], 4),
+                         rays_per_s=round(rep["rays_per_s"], 1), mean_batch=round(rep["mean_batch"], 2))
+        print(f"# service {mode}: p50 {rep['p50_ms']:.3f} ms p99 {rep['p99_ms']:.3f} ms "
+              f"({rep['rays_per_s'] / 1e6:.1f} Mrays/s, mean batch {rep['mean_batch']:.1f})",
+              file=sys.stderr, flush=True)
+    return out
 
 
 def cpu_baseline(w, target_s):

@@ -219,6 +219,36 @@ lgsr_status lgsr_profile_read(lgsr_ctx *ctx, double ms[10], int64_t calls[10]);
 /* Wait for all work issued on the context's stream; reports an earlier kernel fault. */
 lgsr_status lgsr_sync(lgsr_ctx *ctx);
 
+/* A batch of render or render + gradient requests (the rendering-service path).  Each
+ * request names its own map, pose, beam model and outputs; requests of one batch may mix
+ * maps and resolutions.  Every request's projection and tile offsets are issued first,
+ * spread over four streams, then the library waits once per request for its pair count
+ * and issues the rest (lists, compositing and, for a request with targets, lgsr_loss and
+ * lgsr_backward) on the same streams.  One host wait per request instead of one per stage
+ * chain, and kernels of different requests overlap on the GPU.  Sec. 3.4's mapping step
+ * renders and differentiates many keyframes this way.
+ * All pointers in a request are DEVICE pointers except pose_ws (by value) and the request
+ * array itself (HOST).  target_depth == NULL: render only (the gradient fields are then
+ * ignored).  With targets, loss_out (float[5]), frame_grad (H x W scratch that receives
+ * dL/d(frame)), grads (n) and grad_pose (6) must be set.  Outputs of different requests
+ * must not overlap.  The call returns once everything is issued; the context's stream
+ * orders after all of it (lgsr_sync waits for it).  Arguments of every request are
+ * validated before anything is issued (LGSR_EINVAL, naming the request). */
+typedef struct {
+    lgsr_surfels surfels;
+    float pose_ws[12]; /* 3 x 4 row-major [R | t], sensor to world */
+    lgsr_beams beams;
+    lgsr_frame out;
+    const float *target_depth;  /* H x W or NULL */
+    const float *target_normal; /* H x W x 3 */
+    float *loss_out;            /* device float[5] */
+    lgsr_frame_grad frame_grad; /* H x W scratch */
+    lgsr_surfel_grads grads;    /* n, overwritten */
+    float *grad_pose;           /* device float[6] */
+} lgsr_request;
+lgsr_status lgsr_render_batch(lgsr_ctx *ctx, int32_t n, const lgsr_request *requests /* HOST */,
+                              const lgsr_raster_opts *opts, const lgsr_loss_weights *weights);
+
 /* Device bytes held by `state` (HOST int64 out); no GPU work, no wait.  A caller that keeps
  * states from forward to backward can budget HBM with it, and recompute (run the forward
  * again, which is deterministic) instead of keeping a state when the budget is spent. */

@@ -1,7 +1,7 @@
 // lgsr_host.hip -- the C ABI of include/lgsr.h: argument validation, contexts, pooled
-// states and the ordering of the stages on one HIP stream.
+// states and the ordering of the stages on HIP streams.
 //
-// Forward stages (all on the context's stream):
+// Forward stages (on the context's stream, or on a lane stream within a batch):
 //   project      per-surfel record, conservative ray rectangle, range key, per-tile counts
 //   scan         tile counts -> [start, end) of every tile's list, total P, longest list
 //   (P and the longest list are read back once to size the pair buffers)
@@ -9,6 +9,10 @@
 //   tile_sort    every list by (range, index), one workgroup per tile
 //   raster_fwd   compositing, frame outputs and per-ray backward state
 // Backward: zero record gradients, raster_bwd, chain (parameters + pose).
+// A forward is split in two: begin (everything up to the read-back of the pair count) and
+// end (the rest).  A batch runs every request's begin first, spread over kLanes streams,
+// then waits once per request for its count and issues the ends (with loss and backward
+// for gradient requests) on the same lanes.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -74,6 +78,11 @@ struct lgsr_state {
     bool live = false;
     // forward products kept for the backward
     DevBuf recs, rects, pk, pv, pk2, pv2, ranges, st0, st1, pose, chunks, chunk_base, slots, fixA, fixB;
+    // per-forward scratch: range keys, per-(tile, shard) counts and cursors, read-back words
+    DevBuf keys, cnt, offs, counters;
+    uint32_t *pinned = nullptr;  // host-pinned copy of counters[0..2]
+    hipEvent_t rb = nullptr;     // recorded after the read-back copy
+    int chunk_req = 0;           // requested chunk size (0: automatic)
     uint32_t *ids = nullptr;  // per-tile lists of surfel ids, front to back (pv)
     SurfelPtrs S{};
     const float *rows = nullptr, *cols = nullptr;
@@ -83,14 +92,26 @@ struct lgsr_state {
     int64_t P = 0;
 };
 
+// A stream with the scratch of the loss and the backward; calls on one lane run in order.
+struct Lane {
+    hipStream_t stream = nullptr;  // lane 0: the context's stream
+    bool own = false;              // created by the context (lanes 1..)
+    DevBuf recgrad, partials, pose_partials, gb0, gb1;
+    bool recgrad_zero = false;  // every record-gradient slot is zero (the chain clears what it reads)
+    hipEvent_t done = nullptr;  // joins a batch back into the context's stream
+    std::vector<lgsr_state *> batch_states;  // per-request states of batches on this lane
+};
+
+constexpr int kLanes = 4;
+
 struct lgsr_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
     std::string err;
-    // scratch
-    DevBuf keys, cnt, offs, counters, recgrad, partials, pose_partials, gb0, gb1;
-    bool recgrad_zero = false;  // every record-gradient slot is zero (the chain clears what it reads)
-    uint32_t *pinned = nullptr;  // host-pinned readback slots
+    Lane lanes[kLanes];
+    hipEvent_t batch_start = nullptr;
+    DevBuf counters;             // lgsr_query's counters
+    uint32_t *pinned = nullptr;  // host-pinned read-back of lgsr_query
     std::vector<lgsr_state *> pool;  // freed states kept for reuse
     std::vector<lgsr_state *> all;   // every state allocated by this context
     lgsr_state scratch_state;        // used when the caller asks for no state
@@ -183,6 +204,21 @@ void free_state_buffers(lgsr_state *s)
     release(s->recs); release(s->rects); release(s->pk); release(s->pv); release(s->pk2); release(s->pv2);
     release(s->ranges); release(s->st0); release(s->st1); release(s->pose);
     release(s->chunks); release(s->chunk_base); release(s->slots); release(s->fixA); release(s->fixB);
+    release(s->keys); release(s->cnt); release(s->offs); release(s->counters);
+    if (s->pinned) (void)hipHostFree(s->pinned);
+    s->pinned = nullptr;
+    if (s->rb) (void)hipEventDestroy(s->rb);
+    s->rb = nullptr;
+}
+
+void free_lane(Lane &L)
+{
+    release(L.recgrad); release(L.partials); release(L.pose_partials); release(L.gb0); release(L.gb1);
+    if (L.done) (void)hipEventDestroy(L.done);
+    L.done = nullptr;
+    if (L.own && L.stream) (void)hipStreamDestroy(L.stream);
+    L.stream = nullptr;
+    L.own = false;
 }
 
 hipEvent_t take_event(lgsr_ctx *ctx)
@@ -200,16 +236,17 @@ hipEvent_t take_event(lgsr_ctx *ctx)
     return e;
 }
 
-// Brackets one stage with events on the context's stream while profiling is on.
+// Brackets one stage with events on a stream while profiling is on.
 struct Stage {
     lgsr_ctx *ctx;
     int id;
+    hipStream_t s;
     hipEvent_t a = nullptr;
-    Stage(lgsr_ctx *c, int stage) : ctx(c), id(stage)
+    Stage(lgsr_ctx *c, int stage, hipStream_t stream) : ctx(c), id(stage), s(stream)
     {
         if (!((ctx->prof_mask >> id) & 1u)) return;
         a = take_event(ctx);
-        if (a) (void)hipEventRecord(a, ctx->stream);
+        if (a) (void)hipEventRecord(a, s);
     }
     ~Stage()
     {
@@ -219,7 +256,7 @@ struct Stage {
             ctx->ev_free.push_back(a);
             return;
         }
-        (void)hipEventRecord(b, ctx->stream);
+        (void)hipEventRecord(b, s);
         ctx->ev_pending.push_back({id, {a, b}});
     }
 };
@@ -228,13 +265,237 @@ size_t state_bytes(const lgsr_state *s)
 {
     return s->recs.cap + s->rects.cap + s->pk.cap + s->pv.cap + s->pk2.cap + s->pv2.cap + s->ranges.cap +
            s->st0.cap + s->st1.cap + s->pose.cap + s->chunks.cap + s->chunk_base.cap + s->slots.cap + s->fixA.cap +
-           s->fixB.cap;
+           s->fixB.cap + s->keys.cap + s->cnt.cap + s->offs.cap + s->counters.cap;
 }
 
 size_t ctx_bytes(const lgsr_ctx *c)
 {
-    return c->keys.cap + c->cnt.cap + c->offs.cap + c->counters.cap + c->recgrad.cap + c->partials.cap +
-           c->pose_partials.cap + c->gb0.cap + c->gb1.cap + state_bytes(&c->scratch_state);
+    size_t b = c->counters.cap + state_bytes(&c->scratch_state);
+    for (const Lane &L : c->lanes) {
+        b += L.recgrad.cap + L.partials.cap + L.pose_partials.cap + L.gb0.cap + L.gb1.cap;
+        for (const lgsr_state *st : L.batch_states) b += state_bytes(st);
+    }
+    return b;
+}
+
+// ---- validation shared by the single-request and batch entry points ----
+
+lgsr_status check_surfels(lgsr_ctx *ctx, const lgsr_surfels *surfels)
+{
+    if (!surfels) return fail(ctx, LGSR_EINVAL, "surfels is NULL");
+    const int64_t n = surfels->n;
+    if (n < 0 || n > (int64_t)0x7FFFFFFF) return fail(ctx, LGSR_EINVAL, "surfel count %lld out of range", (long long)n);
+    if (n > 0 && (!surfels->means || !surfels->quats || !surfels->log_scales || !surfels->opacity_logits))
+        return fail(ctx, LGSR_EINVAL, "surfel arrays must not be NULL");
+    return LGSR_OK;
+}
+
+lgsr_status check_beams(lgsr_ctx *ctx, const lgsr_beams *beams)
+{
+    if (!beams) return fail(ctx, LGSR_EINVAL, "beams is NULL");
+    if (beams->H < 1 || beams->W < 1 || beams->H > 32768 || beams->W > 32768)
+        return fail(ctx, LGSR_EINVAL, "beam grid %d x %d out of range [1, 32768]", beams->H, beams->W);
+    if (!beams->row_sincos || !beams->col_sincos) return fail(ctx, LGSR_EINVAL, "beam tables must not be NULL");
+    return LGSR_OK;
+}
+
+lgsr_status check_frame(lgsr_ctx *ctx, const lgsr_frame *out)
+{
+    if (!out || !out->depth || !out->opacity || !out->normal || !out->drop)
+        return fail(ctx, LGSR_EINVAL, "frame outputs must not be NULL");
+    return LGSR_OK;
+}
+
+lgsr_status host_pose(lgsr_ctx *ctx, const float *pose_ws, Pose &P)
+{
+    for (int c = 0; c < 12; ++c)
+        if (!std::isfinite(pose_ws[c])) return fail(ctx, LGSR_EINVAL, "pose has a non-finite entry");
+    for (int c = 0; c < 9; ++c) P.r[c] = pose_ws[(c / 3) * 4 + (c % 3)];
+    for (int c = 0; c < 3; ++c) P.t[c] = pose_ws[4 * c + 3];
+    return LGSR_OK;
+}
+
+lgsr_status check_weights(lgsr_ctx *ctx, const lgsr_loss_weights *w)
+{
+    if (!w) return fail(ctx, LGSR_EINVAL, "weights is NULL");
+    if (!std::isfinite(w->w_depth) || !std::isfinite(w->lambda_n) || !std::isfinite(w->lambda_ng))
+        return fail(ctx, LGSR_EINVAL, "weights must be finite");
+    return LGSR_OK;
+}
+
+lgsr_status check_surfel_grads(lgsr_ctx *ctx, int64_t n, const lgsr_surfel_grads *out, const float *grad_pose)
+{
+    if (!out || (n > 0 && (!out->means || !out->quats || !out->log_scales || !out->opacity_logits)))
+        return fail(ctx, LGSR_EINVAL, "surfel gradient outputs are NULL");
+    if (!grad_pose) return fail(ctx, LGSR_EINVAL, "grad_pose is NULL");
+    return LGSR_OK;
+}
+
+// ---- forward, loss and backward on a given stream / lane ----
+
+// Forward, first half: records, rectangles, counts, tile offsets and the asynchronous
+// read-back of (P, longest list), after which S->rb is recorded.  pose_dev (device 3 x 4)
+// replaces pose_val when not null.
+lgsr_status forward_begin(lgsr_ctx *ctx, lgsr_state *S, const lgsr_surfels *surfels, const Pose &pose_val,
+                          const float *pose_dev, const lgsr_beams *beams, const lgsr_raster_opts *opts,
+                          hipStream_t s)
+{
+    const int64_t n = surfels->n;
+    Grid g;
+    g.H = beams->H;
+    g.W = beams->W;
+    g.TH = (g.H + kTile - 1) / kTile;
+    g.TW = (g.W + kTile - 1) / kTile;
+    g.T = g.TH * g.TW;
+    const int64_t rays = (int64_t)g.H * g.W;
+    const size_t nn = (size_t)(n > 0 ? n : 1);
+    S->g = g;
+    S->prm = to_params(opts);
+    S->chunk_req = opts->chunk;
+    S->S = SurfelPtrs{surfels->means, surfels->quats, surfels->log_scales, surfels->opacity_logits, n};
+    S->rows = beams->row_sincos;
+    S->cols = beams->col_sincos;
+    S->P = 0;
+    HIP_TRY(ensure(S->recs, nn * kRec * sizeof(float)), "alloc records");
+    HIP_TRY(ensure(S->rects, nn * sizeof(uint2)), "alloc rects");
+    HIP_TRY(ensure(S->ranges, (size_t)g.T * sizeof(uint2)), "alloc ranges");
+    HIP_TRY(ensure(S->st0, (size_t)rays * sizeof(float4)), "alloc ray state");
+    HIP_TRY(ensure(S->st1, (size_t)rays * sizeof(float4)), "alloc ray state");
+    HIP_TRY(ensure(S->pose, 16 * sizeof(float)), "alloc pose");
+    HIP_TRY(ensure(S->keys, nn * 4), "alloc keys");
+    HIP_TRY(ensure(S->cnt, (size_t)g.T * kShards * 4), "alloc tile counts");
+    HIP_TRY(ensure(S->offs, (size_t)g.T * kShards * 4), "alloc tile cursors");
+    HIP_TRY(ensure(S->counters, 16), "alloc counters");
+    if (!S->pinned) HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&S->pinned), 16, hipHostMallocDefault), "pinned");
+    if (!S->rb) HIP_TRY(hipEventCreateWithFlags(&S->rb, hipEventDisableTiming), "event");
+    uint32_t *counters = as<uint32_t>(S->counters);
+    {
+    Stage st_(ctx, LGSR_STAGE_PROJECT, s);
+    HIP_TRY(launch_fill_u32(as<uint32_t>(S->cnt), 0u, (int64_t)g.T * kShards, s), "clear tile counts");
+    HIP_TRY(launch_project(S->S, pose_val, pose_dev, as<float>(S->pose), beams->row_sincos, g, S->prm,
+                           as<float>(S->recs), as<uint2>(S->rects), as<uint32_t>(S->keys), as<uint32_t>(S->cnt), s),
+            "project");
+    }
+    {
+    Stage st_(ctx, LGSR_STAGE_SCAN, s);
+    HIP_TRY(launch_tile_scan(as<uint32_t>(S->cnt), g.T, as<uint2>(S->ranges), as<uint32_t>(S->offs), counters, s),
+            "tile scan");
+    }
+    Stage st_(ctx, LGSR_STAGE_READBACK, s);
+    HIP_TRY(hipMemcpyAsync(S->pinned, counters, 3 * sizeof(uint32_t), hipMemcpyDeviceToHost, s), "readback");
+    HIP_TRY(hipEventRecord(S->rb, s), "readback event");
+    return LGSR_OK;
+}
+
+// Forward, second half: waits for the read-back, then emission, per-tile order and
+// compositing into `out`.
+lgsr_status forward_end(lgsr_ctx *ctx, lgsr_state *S, const lgsr_frame *out, hipStream_t s)
+{
+    HIP_TRY(hipEventSynchronize(S->rb), "readback wait");
+    const int64_t P = (int64_t)((uint64_t)S->pinned[0] | ((uint64_t)S->pinned[1] << 32));
+    const int64_t longest = (int64_t)S->pinned[2];
+    const Grid g = S->g;
+    const int64_t n = S->S.n;
+    const int64_t rays = (int64_t)g.H * g.W;
+    // lists are addressed with 32-bit offsets
+    if (P > (int64_t)0x7FFFFFFF) return fail(ctx, LGSR_ECAPACITY, "too many (surfel, tile) pairs");
+    const size_t pp = (size_t)(P > 0 ? P : 1);
+    HIP_TRY(ensure(S->pv, pp * 4), "alloc pairs");
+    const bool streamed = longest > tile_sort_capacity();
+    if (streamed) {
+        HIP_TRY(ensure(S->pk, pp * 4), "alloc pairs");
+        HIP_TRY(ensure(S->pk2, pp * 4), "alloc pairs");
+        HIP_TRY(ensure(S->pv2, pp * 4), "alloc pairs");
+    }
+    S->ids = as<uint32_t>(S->pv);
+    if (P > 0) {
+        {
+        Stage st_(ctx, LGSR_STAGE_EMIT, s);
+        HIP_TRY(launch_emit(as<uint2>(S->rects), n, g, as<uint32_t>(S->offs), S->ids, P, s), "emit");
+        }
+        Stage st_(ctx, LGSR_STAGE_TILE_SORT, s);
+        HIP_TRY(launch_tile_sort(as<uint2>(S->ranges), g.T, as<uint32_t>(S->keys), n, S->ids,
+                                 streamed ? as<uint32_t>(S->pk) : nullptr, streamed ? as<uint32_t>(S->pk2) : nullptr,
+                                 streamed ? as<uint32_t>(S->pv2) : nullptr, s),
+                "tile sort");
+    }
+    const int seg = chunk_size(P, S->chunk_req);
+    const int64_t items_max = chunk_items_max(P, g.T, seg);
+    if (items_max > 0x7FFFFFFF) return fail(ctx, LGSR_ECAPACITY, "too many list chunks");
+    HIP_TRY(ensure(S->chunks, (size_t)(items_max > 0 ? items_max : 1) * sizeof(uint4)), "alloc chunks");
+    HIP_TRY(ensure(S->chunk_base, (size_t)(g.T + 1) * sizeof(uint32_t)), "alloc chunks");
+    HIP_TRY(ensure(S->slots, chunk_slot_floats(items_max > 0 ? items_max : 1) * sizeof(float)), "alloc slots");
+    HIP_TRY(ensure(S->fixA, (size_t)rays * sizeof(float4)), "alloc ray state");
+    HIP_TRY(ensure(S->fixB, (size_t)rays * sizeof(float4)), "alloc ray state");
+    RasterBufs &R = S->R;
+    R.ids = S->ids;
+    R.recs = as<float>(S->recs);
+    R.rects = as<uint2>(S->rects);
+    R.ranges = as<uint2>(S->ranges);
+    R.rows = S->rows;
+    R.cols = S->cols;
+    R.chunks = as<uint4>(S->chunks);
+    R.chunk_base = as<uint32_t>(S->chunk_base);
+    R.n_items = as<uint32_t>(S->pose) + 12;
+    R.slots = as<float>(S->slots);
+    R.st0 = as<float4>(S->st0);
+    R.st1 = as<float4>(S->st1);
+    R.fixA = as<float4>(S->fixA);
+    R.fixB = as<float4>(S->fixB);
+    R.seg = seg;
+    R.items_max = items_max;
+    Stage st_(ctx, LGSR_STAGE_RASTER_FWD, s);
+    HIP_TRY(launch_raster_fwd(R, g, S->prm, out->depth, out->opacity, out->normal, out->drop, s), "raster forward");
+    S->P = P;
+    return LGSR_OK;
+}
+
+lgsr_status loss_impl(lgsr_ctx *ctx, Lane &L, int64_t n_rays, const lgsr_frame *pred, const float *target_depth,
+                      const float *target_normal, const lgsr_loss_weights *w, float *loss_out,
+                      const lgsr_frame_grad *grad_out)
+{
+    HIP_TRY(ensure(L.partials, (size_t)loss_blocks(n_rays) * 4 * sizeof(float)), "alloc partials");
+    Stage st_(ctx, LGSR_STAGE_LOSS, L.stream);
+    HIP_TRY(launch_loss(n_rays, pred ? pred->depth : nullptr, pred ? pred->normal : nullptr, target_depth,
+                        target_normal, w->w_depth, w->lambda_n, w->lambda_ng, as<float>(L.partials), loss_out,
+                        grad_out ? grad_out->d_depth : nullptr, grad_out ? grad_out->d_opacity : nullptr,
+                        grad_out ? grad_out->d_normal : nullptr, L.stream),
+            "loss");
+    return LGSR_OK;
+}
+
+lgsr_status backward_impl(lgsr_ctx *ctx, Lane &L, lgsr_state *S, const lgsr_frame_grad *gin,
+                          const lgsr_surfel_grads *out, float *grad_pose)
+{
+    hipStream_t s = L.stream;
+    const size_t nn = (size_t)(S->S.n > 0 ? S->S.n : 1);
+    if (L.recgrad.cap < nn * kGrad * sizeof(float)) L.recgrad_zero = false;
+    HIP_TRY(ensure(L.recgrad, nn * kGrad * sizeof(float)), "alloc record gradients");
+    HIP_TRY(ensure(L.pose_partials, (size_t)chain_blocks(S->S.n) * 6 * sizeof(float)), "alloc pose partials");
+    const int64_t rays = (int64_t)S->g.H * S->g.W;
+    HIP_TRY(ensure(L.gb0, (size_t)rays * sizeof(float4)), "alloc backward state");
+    HIP_TRY(ensure(L.gb1, (size_t)rays * sizeof(float)), "alloc backward state");
+    {
+    Stage st_(ctx, LGSR_STAGE_BWD_PREP, s);
+    if (!L.recgrad_zero)
+        HIP_TRY(launch_fill_u32(as<uint32_t>(L.recgrad), 0u, (int64_t)(L.recgrad.cap / sizeof(uint32_t)), s),
+                "zero record gradients");
+    L.recgrad_zero = false;
+    HIP_TRY(launch_raster_bwd_prep(S->R, S->g, gin->d_depth, gin->d_opacity, gin->d_normal, as<float4>(L.gb0),
+                                   as<float>(L.gb1), s),
+            "backward set-up");
+    }
+    {
+    Stage st_(ctx, LGSR_STAGE_RASTER_BWD, s);
+    HIP_TRY(launch_raster_bwd(S->R, S->g, S->prm, as<float4>(L.gb0), as<float>(L.gb1), as<float>(L.recgrad), s),
+            "raster backward");
+    }
+    Stage st_(ctx, LGSR_STAGE_CHAIN, s);
+    HIP_TRY(launch_chain(S->S, as<float>(S->pose), S->prm, as<uint2>(S->rects), as<float>(L.recgrad), out->means,
+                         out->quats, out->log_scales, out->opacity_logits, as<float>(L.pose_partials), grad_pose, s),
+            "chain");
+    L.recgrad_zero = true;
+    return LGSR_OK;
 }
 
 }  // namespace
@@ -278,6 +539,7 @@ lgsr_status lgsr_create(lgsr_ctx **out, int device, void *hip_stream)
     if (!ctx) return LGSR_ENOMEM;
     ctx->device = device;
     ctx->stream = static_cast<hipStream_t>(hip_stream);
+    ctx->lanes[0].stream = ctx->stream;
     ctx->scratch_state.ctx = ctx;
     if (hipHostMalloc(reinterpret_cast<void **>(&ctx->pinned), 256, hipHostMallocDefault) != hipSuccess) {
         (void)hipGetLastError();
@@ -298,15 +560,17 @@ void lgsr_destroy(lgsr_ctx *ctx)
     if (!ctx) return;
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
-    // every state, freed or not: handles of states still live become invalid here
+    for (Lane &L : ctx->lanes)
+        if (L.own && L.stream) (void)hipStreamSynchronize(L.stream);
+    // every state, freed or not (batch states included): handles of live states become invalid
     for (lgsr_state *s : ctx->all) {
         free_state_buffers(s);
         delete s;
     }
     free_state_buffers(&ctx->scratch_state);
-    DevBuf *bufs[] = {&ctx->keys, &ctx->cnt, &ctx->offs, &ctx->counters, &ctx->recgrad, &ctx->partials,
-                      &ctx->pose_partials, &ctx->gb0, &ctx->gb1};
-    for (DevBuf *b : bufs) release(*b);
+    for (Lane &L : ctx->lanes) free_lane(L);
+    release(ctx->counters);
+    if (ctx->batch_start) (void)hipEventDestroy(ctx->batch_start);
     for (auto &pe : ctx->ev_pending) {
         (void)hipEventDestroy(pe.second.first);
         (void)hipEventDestroy(pe.second.second);
@@ -320,6 +584,7 @@ lgsr_status lgsr_set_stream(lgsr_ctx *ctx, void *hip_stream)
 {
     if (!ctx) return LGSR_EINVAL;
     ctx->stream = static_cast<hipStream_t>(hip_stream);
+    ctx->lanes[0].stream = ctx->stream;
     return LGSR_OK;
 }
 
@@ -331,30 +596,15 @@ lgsr_status lgsr_forward(lgsr_ctx *ctx, const lgsr_surfels *surfels, const float
 {
     if (!ctx) return LGSR_EINVAL;
     if (state) *state = nullptr;
-    if (!surfels) return fail(ctx, LGSR_EINVAL, "surfels is NULL");
-    const int64_t n = surfels->n;
-    if (n < 0 || n > (int64_t)0x7FFFFFFF) return fail(ctx, LGSR_EINVAL, "surfel count %lld out of range", (long long)n);
-    if (n > 0 && (!surfels->means || !surfels->quats || !surfels->log_scales || !surfels->opacity_logits))
-        return fail(ctx, LGSR_EINVAL, "surfel arrays must not be NULL");
-    if (!pose_ws) return fail(ctx, LGSR_EINVAL, "pose is NULL");
-    if (!beams) return fail(ctx, LGSR_EINVAL, "beams is NULL");
-    if (beams->H < 1 || beams->W < 1 || beams->H > 32768 || beams->W > 32768)
-        return fail(ctx, LGSR_EINVAL, "beam grid %d x %d out of range [1, 32768]", beams->H, beams->W);
-    if (!beams->row_sincos || !beams->col_sincos) return fail(ctx, LGSR_EINVAL, "beam tables must not be NULL");
-    lgsr_status st = check_opts(ctx, opts);
+    lgsr_status st = check_surfels(ctx, surfels);
     if (st != LGSR_OK) return st;
-    if (!out || !out->depth || !out->opacity || !out->normal || !out->drop)
-        return fail(ctx, LGSR_EINVAL, "frame outputs must not be NULL");
+    if (!pose_ws) return fail(ctx, LGSR_EINVAL, "pose is NULL");
+    if ((st = check_beams(ctx, beams)) != LGSR_OK) return st;
+    if ((st = check_opts(ctx, opts)) != LGSR_OK) return st;
+    if ((st = check_frame(ctx, out)) != LGSR_OK) return st;
     Pose pose_val{};
-    if (!pose_on_device) {
-        for (int c = 0; c < 9; ++c) pose_val.r[c] = pose_ws[(c / 3) * 4 + (c % 3)];
-        for (int c = 0; c < 3; ++c) pose_val.t[c] = pose_ws[4 * c + 3];
-        for (int c = 0; c < 12; ++c)
-            if (!std::isfinite(pose_ws[c])) return fail(ctx, LGSR_EINVAL, "pose has a non-finite entry");
-    }
+    if (!pose_on_device && (st = host_pose(ctx, pose_ws, pose_val)) != LGSR_OK) return st;
     HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
-    hipStream_t s = ctx->stream;
-
     lgsr_state *S = state ? take_state(ctx) : &ctx->scratch_state;
     if (!S) return fail(ctx, LGSR_ENOMEM, "out of host memory");
     // on any error below a taken state goes back to the pool
@@ -367,107 +617,10 @@ lgsr_status lgsr_forward(lgsr_ctx *ctx, const lgsr_surfels *surfels, const float
             if (!keep && s != &c->scratch_state) c->pool.push_back(s);
         }
     } guard{ctx, S};
-
-    Grid g;
-    g.H = beams->H;
-    g.W = beams->W;
-    g.TH = (g.H + kTile - 1) / kTile;
-    g.TW = (g.W + kTile - 1) / kTile;
-    g.T = g.TH * g.TW;
-    const int64_t rays = (int64_t)g.H * g.W;
-    const RasterParams prm = to_params(opts);
-    const size_t nn = (size_t)(n > 0 ? n : 1);
-
-    HIP_TRY(ensure(S->recs, nn * kRec * sizeof(float)), "alloc records");
-    HIP_TRY(ensure(S->rects, nn * sizeof(uint2)), "alloc rects");
-    HIP_TRY(ensure(S->ranges, (size_t)g.T * sizeof(uint2)), "alloc ranges");
-    HIP_TRY(ensure(S->st0, (size_t)rays * sizeof(float4)), "alloc ray state");
-    HIP_TRY(ensure(S->st1, (size_t)rays * sizeof(float4)), "alloc ray state");
-    HIP_TRY(ensure(S->pose, 16 * sizeof(float)), "alloc pose");
-    HIP_TRY(ensure(ctx->keys, nn * 4), "alloc keys");
-    HIP_TRY(ensure(ctx->cnt, (size_t)g.T * kShards * 4), "alloc tile counts");
-    HIP_TRY(ensure(ctx->offs, (size_t)g.T * kShards * 4), "alloc tile cursors");
-
-    SurfelPtrs SP{surfels->means, surfels->quats, surfels->log_scales, surfels->opacity_logits, n};
-    uint32_t *counters = as<uint32_t>(ctx->counters);
-    {
-    Stage st_(ctx, LGSR_STAGE_PROJECT);
-    HIP_TRY(launch_fill_u32(as<uint32_t>(ctx->cnt), 0u, (int64_t)g.T * kShards, s), "clear tile counts");
-    HIP_TRY(launch_project(SP, pose_val, pose_on_device ? pose_ws : nullptr, as<float>(S->pose), beams->row_sincos, g,
-                           prm, as<float>(S->recs), as<uint2>(S->rects), as<uint32_t>(ctx->keys),
-                           as<uint32_t>(ctx->cnt), s),
-            "project");
-    }
-    {
-    Stage st_(ctx, LGSR_STAGE_SCAN);
-    HIP_TRY(launch_tile_scan(as<uint32_t>(ctx->cnt), g.T, as<uint2>(S->ranges), as<uint32_t>(ctx->offs), counters, s),
-            "tile scan");
-    }
-    int64_t P = 0, longest = 0;
-    {
-    Stage st_(ctx, LGSR_STAGE_READBACK);
-    HIP_TRY(hipMemcpyAsync(ctx->pinned, counters, 3 * sizeof(uint32_t), hipMemcpyDeviceToHost, s), "readback");
-    HIP_TRY(hipStreamSynchronize(s), "readback sync");
-    P = (int64_t)((uint64_t)ctx->pinned[0] | ((uint64_t)ctx->pinned[1] << 32));
-    longest = (int64_t)ctx->pinned[2];
-    }
-    // lists are addressed with 32-bit offsets
-    if (P > (int64_t)0x7FFFFFFF) return fail(ctx, LGSR_ECAPACITY, "too many (surfel, tile) pairs");
-    const size_t pp = (size_t)(P > 0 ? P : 1);
-    HIP_TRY(ensure(S->pv, pp * 4), "alloc pairs");
-    const bool streamed = longest > tile_sort_capacity();
-    if (streamed) {
-        HIP_TRY(ensure(S->pk, pp * 4), "alloc pairs");
-        HIP_TRY(ensure(S->pk2, pp * 4), "alloc pairs");
-        HIP_TRY(ensure(S->pv2, pp * 4), "alloc pairs");
-    }
-    S->ids = as<uint32_t>(S->pv);
-    if (P > 0) {
-        {
-        Stage st_(ctx, LGSR_STAGE_EMIT);
-        HIP_TRY(launch_emit(as<uint2>(S->rects), n, g, as<uint32_t>(ctx->offs), S->ids, P, s), "emit");
-        }
-        Stage st_(ctx, LGSR_STAGE_TILE_SORT);
-        HIP_TRY(launch_tile_sort(as<uint2>(S->ranges), g.T, as<uint32_t>(ctx->keys), n, S->ids,
-                                 streamed ? as<uint32_t>(S->pk) : nullptr, streamed ? as<uint32_t>(S->pk2) : nullptr,
-                                 streamed ? as<uint32_t>(S->pv2) : nullptr, s),
-                "tile sort");
-    }
-    {
-    const int seg = chunk_size(P, opts->chunk);
-    const int64_t items_max = chunk_items_max(P, g.T, seg);
-    if (items_max > 0x7FFFFFFF) return fail(ctx, LGSR_ECAPACITY, "too many list chunks");
-    HIP_TRY(ensure(S->chunks, (size_t)(items_max > 0 ? items_max : 1) * sizeof(uint4)), "alloc chunks");
-    HIP_TRY(ensure(S->chunk_base, (size_t)(g.T + 1) * sizeof(uint32_t)), "alloc chunks");
-    HIP_TRY(ensure(S->slots, chunk_slot_floats(items_max > 0 ? items_max : 1) * sizeof(float)), "alloc slots");
-    HIP_TRY(ensure(S->fixA, (size_t)rays * sizeof(float4)), "alloc ray state");
-    HIP_TRY(ensure(S->fixB, (size_t)rays * sizeof(float4)), "alloc ray state");
-    RasterBufs &R = S->R;
-    R.ids = S->ids;
-    R.recs = as<float>(S->recs);
-    R.rects = as<uint2>(S->rects);
-    R.ranges = as<uint2>(S->ranges);
-    R.rows = beams->row_sincos;
-    R.cols = beams->col_sincos;
-    R.chunks = as<uint4>(S->chunks);
-    R.chunk_base = as<uint32_t>(S->chunk_base);
-    R.n_items = as<uint32_t>(S->pose) + 12;
-    R.slots = as<float>(S->slots);
-    R.st0 = as<float4>(S->st0);
-    R.st1 = as<float4>(S->st1);
-    R.fixA = as<float4>(S->fixA);
-    R.fixB = as<float4>(S->fixB);
-    R.seg = seg;
-    R.items_max = items_max;
-    Stage st_(ctx, LGSR_STAGE_RASTER_FWD);
-    HIP_TRY(launch_raster_fwd(R, g, prm, out->depth, out->opacity, out->normal, out->drop, s), "raster forward");
-    }
-    S->S = SP;
-    S->rows = beams->row_sincos;
-    S->cols = beams->col_sincos;
-    S->g = g;
-    S->prm = prm;
-    S->P = P;
+    st = forward_begin(ctx, S, surfels, pose_val, pose_on_device ? pose_ws : nullptr, beams, opts, ctx->stream);
+    if (st != LGSR_OK) return st;
+    st = forward_end(ctx, S, out, ctx->stream);
+    if (st != LGSR_OK) return st;
     if (state) {
         S->live = true;
         ctx->live_states++;
@@ -483,9 +636,8 @@ lgsr_status lgsr_loss(lgsr_ctx *ctx, int64_t n_rays, const lgsr_frame *pred, con
 {
     if (!ctx) return LGSR_EINVAL;
     if (n_rays < 0) return fail(ctx, LGSR_EINVAL, "n_rays must be >= 0");
-    if (!w) return fail(ctx, LGSR_EINVAL, "weights is NULL");
-    if (!std::isfinite(w->w_depth) || !std::isfinite(w->lambda_n) || !std::isfinite(w->lambda_ng))
-        return fail(ctx, LGSR_EINVAL, "weights must be finite");
+    lgsr_status st = check_weights(ctx, w);
+    if (st != LGSR_OK) return st;
     if (!loss_out) return fail(ctx, LGSR_EINVAL, "loss_out is NULL");
     if (n_rays > 0) {
         if (!pred || !pred->depth || !pred->normal) return fail(ctx, LGSR_EINVAL, "prediction is NULL");
@@ -494,14 +646,7 @@ lgsr_status lgsr_loss(lgsr_ctx *ctx, int64_t n_rays, const lgsr_frame *pred, con
             return fail(ctx, LGSR_EINVAL, "gradient outputs are NULL");
     }
     HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
-    HIP_TRY(ensure(ctx->partials, (size_t)loss_blocks(n_rays) * 4 * sizeof(float)), "alloc partials");
-    Stage st_(ctx, LGSR_STAGE_LOSS);
-    HIP_TRY(launch_loss(n_rays, pred ? pred->depth : nullptr, pred ? pred->normal : nullptr, target_depth,
-                        target_normal, w->w_depth, w->lambda_n, w->lambda_ng, as<float>(ctx->partials), loss_out,
-                        grad_out ? grad_out->d_depth : nullptr, grad_out ? grad_out->d_opacity : nullptr,
-                        grad_out ? grad_out->d_normal : nullptr, ctx->stream),
-            "loss");
-    return LGSR_OK;
+    return loss_impl(ctx, ctx->lanes[0], n_rays, pred, target_depth, target_normal, w, loss_out, grad_out);
 }
 
 lgsr_status lgsr_backward(lgsr_ctx *ctx, lgsr_state *S, const lgsr_frame_grad *gin, lgsr_surfel_grads *out,
@@ -512,40 +657,99 @@ lgsr_status lgsr_backward(lgsr_ctx *ctx, lgsr_state *S, const lgsr_frame_grad *g
     if (S->ctx != ctx || !S->live) return fail(ctx, LGSR_ESTATE, "state does not belong to this context");
     if (!gin || !gin->d_depth || !gin->d_opacity || !gin->d_normal)
         return fail(ctx, LGSR_EINVAL, "frame gradients are NULL");
-    if (!out || (S->S.n > 0 && (!out->means || !out->quats || !out->log_scales || !out->opacity_logits)))
-        return fail(ctx, LGSR_EINVAL, "surfel gradient outputs are NULL");
-    if (!grad_pose) return fail(ctx, LGSR_EINVAL, "grad_pose is NULL");
+    lgsr_status st = check_surfel_grads(ctx, S->S.n, out, grad_pose);
+    if (st != LGSR_OK) return st;
     HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
-    hipStream_t s = ctx->stream;
-    const size_t nn = (size_t)(S->S.n > 0 ? S->S.n : 1);
-    if (ctx->recgrad.cap < nn * kGrad * sizeof(float)) ctx->recgrad_zero = false;
-    HIP_TRY(ensure(ctx->recgrad, nn * kGrad * sizeof(float)), "alloc record gradients");
-    HIP_TRY(ensure(ctx->pose_partials, (size_t)chain_blocks(S->S.n) * 6 * sizeof(float)), "alloc pose partials");
-    const int64_t rays = (int64_t)S->g.H * S->g.W;
-    HIP_TRY(ensure(ctx->gb0, (size_t)rays * sizeof(float4)), "alloc backward state");
-    HIP_TRY(ensure(ctx->gb1, (size_t)rays * sizeof(float)), "alloc backward state");
-    {
-    Stage st_(ctx, LGSR_STAGE_BWD_PREP);
-    if (!ctx->recgrad_zero)
-        HIP_TRY(launch_fill_u32(as<uint32_t>(ctx->recgrad), 0u, (int64_t)(ctx->recgrad.cap / sizeof(uint32_t)), s),
-                "zero record gradients");
-    ctx->recgrad_zero = false;
-    HIP_TRY(launch_raster_bwd_prep(S->R, S->g, gin->d_depth, gin->d_opacity, gin->d_normal, as<float4>(ctx->gb0),
-                                   as<float>(ctx->gb1), s),
-            "backward set-up");
+    return backward_impl(ctx, ctx->lanes[0], S, gin, out, grad_pose);
+}
+
+lgsr_status lgsr_render_batch(lgsr_ctx *ctx, int32_t n, const lgsr_request *reqs, const lgsr_raster_opts *opts,
+                              const lgsr_loss_weights *w)
+{
+    if (!ctx) return LGSR_EINVAL;
+    if (n < 0 || (n > 0 && !reqs)) return fail(ctx, LGSR_EINVAL, "n < 0 or requests is NULL");
+    lgsr_status st = check_opts(ctx, opts);
+    if (st != LGSR_OK) return st;
+    std::vector<Pose> poses((size_t)n);
+    for (int32_t i = 0; i < n; ++i) {
+        const lgsr_request &q = reqs[i];
+        if ((st = check_surfels(ctx, &q.surfels)) != LGSR_OK ||
+            (st = check_beams(ctx, &q.beams)) != LGSR_OK || (st = check_frame(ctx, &q.out)) != LGSR_OK ||
+            (st = host_pose(ctx, q.pose_ws, poses[(size_t)i])) != LGSR_OK) {
+            const std::string e = ctx->err;
+            return fail(ctx, st, "request %d: %s", i, e.c_str());
+        }
+        if (q.target_depth || q.target_normal) {
+            if (!q.target_depth || !q.target_normal) return fail(ctx, LGSR_EINVAL, "request %d: one target is NULL", i);
+            if ((st = check_weights(ctx, w)) != LGSR_OK) return st;
+            if (!q.loss_out || !q.frame_grad.d_depth || !q.frame_grad.d_opacity || !q.frame_grad.d_normal)
+                return fail(ctx, LGSR_EINVAL, "request %d: loss_out or frame_grad is NULL", i);
+            if ((st = check_surfel_grads(ctx, q.surfels.n, &q.grads, q.grad_pose)) != LGSR_OK) {
+                const std::string e = ctx->err;
+                return fail(ctx, st, "request %d: %s", i, e.c_str());
+            }
+        }
     }
-    {
-    Stage st_(ctx, LGSR_STAGE_RASTER_BWD);
-    HIP_TRY(launch_raster_bwd(S->R, S->g, S->prm, as<float4>(ctx->gb0), as<float>(ctx->gb1), as<float>(ctx->recgrad),
-                              s),
-            "raster backward");
+    HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
+    for (int k = 1; k < kLanes; ++k) {
+        Lane &L = ctx->lanes[k];
+        if (!L.stream) {
+            HIP_TRY(hipStreamCreateWithFlags(&L.stream, hipStreamNonBlocking), "lane stream");
+            L.own = true;
+        }
     }
-    Stage st_(ctx, LGSR_STAGE_CHAIN);
-    HIP_TRY(launch_chain(S->S, as<float>(S->pose), S->prm, as<uint2>(S->rects), as<float>(ctx->recgrad), out->means,
-                         out->quats,
-                         out->log_scales, out->opacity_logits, as<float>(ctx->pose_partials), grad_pose, s),
-            "chain");
-    ctx->recgrad_zero = true;
+    for (Lane &L : ctx->lanes)
+        if (!L.done) HIP_TRY(hipEventCreateWithFlags(&L.done, hipEventDisableTiming), "lane event");
+    if (!ctx->batch_start) HIP_TRY(hipEventCreateWithFlags(&ctx->batch_start, hipEventDisableTiming), "event");
+    // The lanes start after the work already on the context's stream, and the context's
+    // stream continues after the lanes (also when returning early with an error).
+    HIP_TRY(hipEventRecord(ctx->batch_start, ctx->stream), "batch start");
+    for (int k = 1; k < kLanes; ++k) HIP_TRY(hipStreamWaitEvent(ctx->lanes[k].stream, ctx->batch_start, 0), "join");
+    struct Join {
+        lgsr_ctx *c;
+        uint32_t mask;
+        ~Join()
+        {
+            for (int k = 1; k < kLanes; ++k) {
+                Lane &L = c->lanes[k];
+                if (hipEventRecord(L.done, L.stream) == hipSuccess) (void)hipStreamWaitEvent(c->stream, L.done, 0);
+            }
+            c->prof_mask = mask;
+        }
+    } join{ctx, ctx->prof_mask};
+    ctx->prof_mask = 0;  // stage timers describe single calls, not overlapping lanes
+    std::vector<lgsr_state *> states((size_t)n);
+    int used[kLanes] = {};
+    for (int32_t i = 0; i < n; ++i) {
+        Lane &L = ctx->lanes[i % kLanes];
+        const int r = used[i % kLanes]++;
+        if ((int)L.batch_states.size() <= r) {
+            lgsr_state *S = new (std::nothrow) lgsr_state;
+            if (!S) return fail(ctx, LGSR_ENOMEM, "out of host memory");
+            S->ctx = ctx;
+            ctx->all.push_back(S);
+            L.batch_states.push_back(S);
+        }
+        states[(size_t)i] = L.batch_states[(size_t)r];
+    }
+    for (int32_t i = 0; i < n; ++i) {
+        const lgsr_request &q = reqs[i];
+        st = forward_begin(ctx, states[(size_t)i], &q.surfels, poses[(size_t)i], nullptr, &q.beams, opts,
+                           ctx->lanes[i % kLanes].stream);
+        if (st != LGSR_OK) return st;
+    }
+    for (int32_t i = 0; i < n; ++i) {
+        const lgsr_request &q = reqs[i];
+        Lane &L = ctx->lanes[i % kLanes];
+        lgsr_state *S = states[(size_t)i];
+        if ((st = forward_end(ctx, S, &q.out, L.stream)) != LGSR_OK) return st;
+        if (!q.target_depth) continue;
+        const int64_t rays = (int64_t)q.beams.H * q.beams.W;
+        if ((st = loss_impl(ctx, L, rays, &q.out, q.target_depth, q.target_normal, w, q.loss_out, &q.frame_grad)) !=
+            LGSR_OK)
+            return st;
+        if ((st = backward_impl(ctx, L, S, &q.frame_grad, &q.grads, q.grad_pose)) != LGSR_OK) return st;
+    }
     return LGSR_OK;
 }
 

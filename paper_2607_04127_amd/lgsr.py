@@ -21,7 +21,8 @@ _STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ECAPACITY", 
 
 EXPORTS = ("lgsr_default_opts", "lgsr_default_loss_weights", "lgsr_create", "lgsr_destroy", "lgsr_set_stream",
            "lgsr_last_error", "lgsr_forward", "lgsr_loss", "lgsr_backward", "lgsr_state_free", "lgsr_query",
-           "lgsr_profile", "lgsr_profile_read", "lgsr_sync", "lgsr_state_bytes", "lgsr_adam_step")
+           "lgsr_profile", "lgsr_profile_read", "lgsr_sync", "lgsr_state_bytes", "lgsr_adam_step",
+           "lgsr_render_batch")
 STAGES = ("project", "scan", "readback", "emit", "tile_sort", "raster_fwd", "loss", "bwd_prep", "raster_bwd",
           "chain")
 
@@ -65,6 +66,12 @@ class SurfelGrads(ctypes.Structure):
     _fields_ = [("means", vp), ("quats", vp), ("log_scales", vp), ("opacity_logits", vp)]
 
 
+class Request(ctypes.Structure):
+    _fields_ = [("surfels", Surfels), ("pose_ws", ctypes.c_float * 12), ("beams", Beams), ("out", Frame),
+                ("target_depth", vp), ("target_normal", vp), ("loss_out", vp), ("frame_grad", FrameGrad),
+                ("grads", SurfelGrads), ("grad_pose", vp)]
+
+
 class AdamGroup(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("param", vp), ("grad", vp), ("m", vp), ("v", vp), ("lr", ctypes.c_float)]
 
@@ -100,10 +107,12 @@ def lib():
         L.lgsr_profile.argtypes = [vp, ctypes.c_int32]
         L.lgsr_profile_read.argtypes = [vp, P(ctypes.c_double), P(ctypes.c_int64)]
         L.lgsr_state_bytes.argtypes = [vp, vp, P(ctypes.c_int64)]
+        L.lgsr_render_batch.argtypes = [vp, ctypes.c_int32, P(Request), P(RasterOpts), P(LossWeights)]
         L.lgsr_adam_step.argtypes = [vp, ctypes.c_int32, P(AdamGroup), ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                      ctypes.c_int32]
         for name in ("lgsr_create", "lgsr_set_stream", "lgsr_forward", "lgsr_loss", "lgsr_backward", "lgsr_query",
-                     "lgsr_profile", "lgsr_profile_read", "lgsr_sync", "lgsr_state_bytes", "lgsr_adam_step"):
+                     "lgsr_profile", "lgsr_profile_read", "lgsr_sync", "lgsr_state_bytes", "lgsr_adam_step",
+           "lgsr_render_batch"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -301,6 +310,66 @@ def lgsr_query(ctx: Context, state: State) -> dict:
     ctx._check(lib().lgsr_query(ctx.handle, state.handle, o))
     return dict(pairs=o[0], visible=o[1], workspace_bytes=o[2], max_list=o[3], ray_tests=o[4], composites=o[5],
                 rays_hit=o[6], ray_tests_needed=o[7])
+
+
+def lgsr_render_batch(ctx: Context, requests, opts: RasterOpts | None = None, weights: LossWeights | None = None):
+    """Render a batch of requests in one call (mixed maps, poses and resolutions).
+
+    Each request is a dict with ``surfels`` (dict of device tensors), ``pose`` (3 x 4, host
+    array-like), ``row_sincos`` and ``col_sincos`` (device tensors) and optionally
+    ``target_depth`` / ``target_normal`` (device tensors: render + gradient) and ``out``
+    (preallocated frame dict).  Returns one dict per request: the frame (depth, opacity,
+    normal, drop) and, for gradient requests, ``loss`` (5,), ``grads`` (means, quats,
+    log_scales, opacity_logits) and ``grad_pose`` (6,).  Asynchronous on torch's current
+    stream."""
+    d = ctx.device
+    arr = (Request * max(1, len(requests)))()
+    results, keep = [], []
+    for k, q in enumerate(requests):
+        rows, cols = q["row_sincos"], q["col_sincos"]
+        H, W = rows.shape[0], cols.shape[0]
+        _dev(rows, "row_sincos", (H, 2), d)
+        _dev(cols, "col_sincos", (W, 2), d)
+        s_, tens = _surfels(ctx, q["surfels"])
+        out = q.get("out") or dict(depth=torch.empty((H, W), device=d), opacity=torch.empty((H, W), device=d),
+                                   normal=torch.empty((H, W, 3), device=d),
+                                   drop=torch.empty((H, W), device=d, dtype=torch.uint8))
+        _dev(out["depth"], "depth", (H, W), d)
+        _dev(out["opacity"], "opacity", (H, W), d)
+        _dev(out["normal"], "normal", (H, W, 3), d)
+        _dev(out["drop"], "drop", (H, W), d, torch.uint8)
+        pose = torch.as_tensor(q["pose"], dtype=torch.float32).reshape(12)
+        r = arr[k]
+        r.surfels = s_
+        for c in range(12):
+            r.pose_ws[c] = float(pose[c])
+        r.beams = Beams(H, W, _ptr(rows), _ptr(cols))
+        r.out = Frame(_ptr(out["depth"]), _ptr(out["opacity"]), _ptr(out["normal"]), _ptr(out["drop"]))
+        res = dict(frame=out)
+        if q.get("target_depth") is not None:
+            td, tn = q["target_depth"], q["target_normal"]
+            _dev(td, "target_depth", (H, W), d)
+            _dev(tn, "target_normal", (H, W, 3), d)
+            n = s_.n
+            fg = dict(depth=torch.empty((H, W), device=d), opacity=torch.empty((H, W), device=d),
+                      normal=torch.empty((H, W, 3), device=d))
+            gr = dict(means=torch.empty((n, 3), device=d), quats=torch.empty((n, 4), device=d),
+                      log_scales=torch.empty((n, 2), device=d), opacity_logits=torch.empty((n,), device=d))
+            res.update(loss=torch.empty(5, device=d), grads=gr, grad_pose=torch.empty(6, device=d), frame_grad=fg)
+            r.target_depth, r.target_normal = _ptr(td), _ptr(tn)
+            r.loss_out = _ptr(res["loss"])
+            r.frame_grad = FrameGrad(_ptr(fg["depth"]), _ptr(fg["opacity"]), _ptr(fg["normal"]))
+            r.grads = SurfelGrads(_ptr(gr["means"]), _ptr(gr["quats"]), _ptr(gr["log_scales"]),
+                                  _ptr(gr["opacity_logits"]))
+            r.grad_pose = _ptr(res["grad_pose"])
+            keep.append((td, tn))
+        keep.append((tens, rows, cols))
+        results.append(res)
+    o = opts if opts is not None else default_opts()
+    w = weights if weights is not None else default_loss_weights()
+    ctx._stream()
+    ctx._check(lib().lgsr_render_batch(ctx.handle, len(requests), arr, ctypes.byref(o), ctypes.byref(w)))
+    return results
 
 
 def lgsr_state_bytes(ctx: Context, state: State) -> int:
