@@ -564,6 +564,191 @@ int lgsr_ref_backward(const lgsr_ref_map *map, const double pose[12], const lgsr
     return 0;
 }
 
+/* ---- full mapping objective (Sec. 3.4, Eq. 10-13) -------------------------------------- */
+
+/* The four neighbours of pixel (k, j) used by N_surf: right/left columns (azimuth wraps over
+ * the full turn) and the rows above/below (index k + 1 / k - 1, no wrap). */
+typedef struct {
+    int64_t r, l, u, d;
+} nbr_t;
+
+/* R12 (Sec. 3.4, normal loss, N_surf): the normal of the rendered surface at pixel (k, j),
+ * from the points P = D^ d of the rendered range image at the four neighbours:
+ * v = (P_r - P_l) x (P_u - P_d), N_surf = v / |v| turned to face the sensor (v.d_p > 0 flips
+ * it).  Defined for 1 <= k <= H - 2 when the four neighbours rendered a range (D^ > 0) and
+ * v != 0.  Returns 1 when defined; a, b, v receive the two differences and their cross
+ * product, *sgn the turn (+1 or -1), *flip_margin |v.d_p| / |v| (how close the turn is to a
+ * tie). */
+static int surf_normal(const lgsr_ref_beams *B, const double *depth, int64_t k, int64_t j, nbr_t *nb,
+                       double a[3], double b[3], double v[3], double *sgn, double *flip_margin)
+{
+    const int64_t H = B->H, W = B->W;
+    if (k < 1 || k > H - 2) return 0;
+    nb->r = k * W + (j + 1) % W;
+    nb->l = k * W + (j + W - 1) % W;
+    nb->u = (k + 1) * W + j;
+    nb->d = (k - 1) * W + j;
+    if (!(depth[nb->r] > 0) || !(depth[nb->l] > 0) || !(depth[nb->u] > 0) || !(depth[nb->d] > 0)) return 0;
+    double dr[3], dl[3], du[3], dd[3], dp[3];
+    ray_dir(B, nb->r, dr);
+    ray_dir(B, nb->l, dl);
+    ray_dir(B, nb->u, du);
+    ray_dir(B, nb->d, dd);
+    ray_dir(B, k * W + j, dp);
+    for (int c = 0; c < 3; ++c) {
+        a[c] = depth[nb->r] * dr[c] - depth[nb->l] * dl[c];
+        b[c] = depth[nb->u] * du[c] - depth[nb->d] * dd[c];
+    }
+    cross3(a, b, v);
+    double vn = sqrt(dot3(v, v));
+    if (!(vn > 0)) return 0;
+    double vd = dot3(v, dp);
+    *sgn = vd > 0 ? -1.0 : 1.0;
+    *flip_margin = fabs(vd) / vn;
+    return 1;
+}
+
+int lgsr_ref_surf_normal(const lgsr_ref_beams *B, const double *depth, double *n_surf, uint8_t *defined,
+                         double *flip_margin)
+{
+    if (!B || !depth || !n_surf || B->H < 0 || B->W < 0) return -1;
+    const int64_t H = B->H, W = B->W;
+    for (int64_t k = 0; k < H; ++k)
+        for (int64_t j = 0; j < W; ++j) {
+            int64_t i = k * W + j;
+            nbr_t nb;
+            double a[3], b[3], v[3], sgn = 1, fm = INFINITY;
+            int ok = surf_normal(B, depth, k, j, &nb, a, b, v, &sgn, &fm);
+            double vn = ok ? sqrt(dot3(v, v)) : 1.0;
+            for (int c = 0; c < 3; ++c) n_surf[3 * i + c] = ok ? sgn * v[c] / vn : 0.0;
+            if (defined) defined[i] = (uint8_t)ok;
+            if (flip_margin) flip_margin[i] = ok ? fm : INFINITY;
+        }
+    return 0;
+}
+
+/* Eq. 10 (depth L1 and positive-only opacity BCE), Eq. 11 (both normal terms) and their
+ * weights in Eq. 13:
+ *   L = w_depth / |Omega_D| sum_{Omega_D} |D^ - D|
+ *     - lambda_alpha / |Omega_D| sum_{Omega_D} log(A^ + eps)
+ *     + lambda_n lambda_ng / |Omega_N| sum_{Omega_N} (1 - N^ . N_gicp / |N^|)
+ *     + lambda_n lambda_ns / |Omega_D| sum_{Omega_D, N_surf defined} (1 - N^ . N_surf / |N^|).
+ * The gradient is the full derivative: through N^ and, inside N_surf, through the rendered
+ * depth of the four neighbours. */
+int lgsr_ref_objective(const lgsr_ref_beams *B, const double *depth, const double *opacity, const double *normal,
+                       const double *target_depth, const double *target_normal, double w_depth,
+                       double lambda_alpha, double eps, double lambda_n, double lambda_ng, double lambda_ns,
+                       double loss[8], double *g_depth, double *g_opacity, double *g_normal)
+{
+    if (!B || !loss || B->H < 0 || B->W < 0) return -1;
+    const int64_t n = (int64_t)B->H * B->W;
+    if (n > 0 && (!depth || !opacity || !normal || !target_depth || !target_normal)) return -1;
+    double cntD = 0, cntN = 0, cntS = 0, sumD = 0, sumA = 0, sumNg = 0, sumNs = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        if (!(target_depth[i] > 0)) continue;
+        const double *Nt = target_normal + 3 * i, *Nh = normal + 3 * i;
+        double nh = sqrt(dot3(Nh, Nh));
+        cntD += 1;
+        sumD += fabs(depth[i] - target_depth[i]);
+        sumA += log(opacity[i] + eps);
+        if (dot3(Nt, Nt) > 0) {
+            cntN += 1;
+            sumNg += nh > 0 ? 1.0 - dot3(Nh, Nt) / nh : 1.0;
+        }
+        nbr_t nb;
+        double a[3], b[3], v[3], sgn, fm;
+        if (surf_normal(B, depth, i / B->W, i % B->W, &nb, a, b, v, &sgn, &fm)) {
+            double vn = sqrt(dot3(v, v));
+            double Ns[3] = {sgn * v[0] / vn, sgn * v[1] / vn, sgn * v[2] / vn};
+            cntS += 1;
+            sumNs += nh > 0 ? 1.0 - dot3(Nh, Ns) / nh : 1.0;
+        }
+    }
+    double tD = cntD > 0 ? w_depth * sumD / cntD : 0.0;
+    double tA = cntD > 0 ? -lambda_alpha * sumA / cntD : 0.0;
+    double tNg = cntN > 0 ? lambda_n * lambda_ng * sumNg / cntN : 0.0;
+    double tNs = cntD > 0 ? lambda_n * lambda_ns * sumNs / cntD : 0.0;
+    loss[0] = tD + tA + tNg + tNs;
+    loss[1] = tD;
+    loss[2] = tA;
+    loss[3] = tNg;
+    loss[4] = tNs;
+    loss[5] = cntD;
+    loss[6] = cntN;
+    loss[7] = cntS;
+    if (!g_depth && !g_opacity && !g_normal) return 0;
+    if (!g_depth || !g_opacity || !g_normal) return -1;
+    for (int64_t i = 0; i < n; ++i) {
+        g_depth[i] = 0;
+        g_opacity[i] = 0;
+        g_normal[3 * i] = g_normal[3 * i + 1] = g_normal[3 * i + 2] = 0;
+    }
+    if (!(cntD > 0)) return 0;
+    for (int64_t i = 0; i < n; ++i) {
+        if (!(target_depth[i] > 0)) continue;
+        const double *Nt = target_normal + 3 * i, *Nh = normal + 3 * i;
+        double nh = sqrt(dot3(Nh, Nh));
+        double diff = depth[i] - target_depth[i];
+        g_depth[i] += w_depth * (diff > 0 ? 1.0 : (diff < 0 ? -1.0 : 0.0)) / cntD;
+        g_opacity[i] = -lambda_alpha / (cntD * (opacity[i] + eps));
+        if (dot3(Nt, Nt) > 0 && nh > 0) {
+            double cosv = dot3(Nh, Nt) / nh;
+            double f = -lambda_n * lambda_ng / (cntN * nh);
+            for (int c = 0; c < 3; ++c) g_normal[3 * i + c] += f * (Nt[c] - cosv * Nh[c] / nh);
+        }
+        nbr_t nb;
+        double a[3], b[3], v[3], sgn, fm;
+        if (nh > 0 && surf_normal(B, depth, i / B->W, i % B->W, &nb, a, b, v, &sgn, &fm)) {
+            double vn = sqrt(dot3(v, v));
+            double u[3] = {v[0] / vn, v[1] / vn, v[2] / vn};
+            double Ns[3] = {sgn * u[0], sgn * u[1], sgn * u[2]};
+            double cosv = dot3(Nh, Ns) / nh;
+            double c0 = lambda_n * lambda_ns / cntD;
+            for (int c = 0; c < 3; ++c) g_normal[3 * i + c] += -c0 * (Ns[c] - cosv * Nh[c] / nh) / nh;
+            /* dl/dN_surf = -c0 N^/|N^|; through N_surf = sgn v/|v| to v, then to a and b */
+            double gN[3] = {-c0 * Nh[0] / nh, -c0 * Nh[1] / nh, -c0 * Nh[2] / nh};
+            double gu = dot3(gN, u);
+            double gv[3], ga[3], gb[3];
+            for (int c = 0; c < 3; ++c) gv[c] = sgn * (gN[c] - gu * u[c]) / vn;
+            cross3(b, gv, ga); /* d(a x b) . gv = da . (b x gv) */
+            cross3(gv, a, gb); /* (a x db) . gv = db . (gv x a) */
+            double dr[3], dl[3], du[3], dd[3];
+            ray_dir(B, nb.r, dr);
+            ray_dir(B, nb.l, dl);
+            ray_dir(B, nb.u, du);
+            ray_dir(B, nb.d, dd);
+            g_depth[nb.r] += dot3(dr, ga);
+            g_depth[nb.l] -= dot3(dl, ga);
+            g_depth[nb.u] += dot3(du, gb);
+            g_depth[nb.d] -= dot3(dd, gb);
+        }
+    }
+    return 0;
+}
+
+/* Eq. 12 with its weight from Eq. 13: lambda_s sum_i max(0, max(s_x, s_y) - s_max), s =
+ * exp(log_scales).  The gradient goes to the larger scale (the first on a tie): lambda_s s_k
+ * when it exceeds s_max.  margin (NULL to skip): |max(s) - s_max| / s_max per surfel. */
+int lgsr_ref_scale_reg(int64_t n, const double *log_scales, double lambda_s, double s_max, double *loss,
+                       double *g_log_scales, double *margin)
+{
+    if (n < 0 || !loss || (n > 0 && !log_scales) || !(s_max > 0)) return -1;
+    double sum = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        double sx = exp(log_scales[2 * i]), sy = exp(log_scales[2 * i + 1]);
+        int k = sy > sx ? 1 : 0;
+        double smax = k ? sy : sx;
+        if (smax > s_max) sum += smax - s_max;
+        if (g_log_scales) {
+            g_log_scales[2 * i] = g_log_scales[2 * i + 1] = 0;
+            if (smax > s_max) g_log_scales[2 * i + k] = lambda_s * smax;
+        }
+        if (margin) margin[i] = fabs(smax - s_max) / s_max;
+    }
+    *loss = lambda_s * sum;
+    return 0;
+}
+
 int lgsr_ref_threads(void)
 {
 #ifdef _OPENMP

@@ -87,6 +87,27 @@ int lgsr_ref_backward(const lgsr_ref_map *map, const double pose[12], const lgsr
                       double *d_means, double *d_quats, double *d_log_scales,
                       double *d_opacity_logits, double d_pose[6], double *mass, double *pose_mass);
 
+/* Normals of the rendered surface (Sec. 3.4, N_surf) for every pixel of an H x W range
+ * image: n_surf (H*W x 3, zero where undefined), defined (H*W, may be NULL), flip_margin
+ * (H*W, may be NULL: |v.d| / |v| of the orientation decision, +inf where undefined). */
+int lgsr_ref_surf_normal(const lgsr_ref_beams *beams, const double *depth, double *n_surf, uint8_t *defined,
+                         double *flip_margin);
+
+/* Frame terms of the mapping objective (Eq. 10, Eq. 11, weighted as in Eq. 13) over the full
+ * H x W image of `beams`, and their gradient with respect to the rendered depth, opacity and
+ * normal (all three NULL to skip; overwritten).  loss[8] = {total, depth term, opacity term,
+ * G-ICP normal term, rendered-surface normal term, |Omega_D|, |Omega_N|, |Omega_S|} with
+ * Omega_S the rays of Omega_D whose N_surf is defined. */
+int lgsr_ref_objective(const lgsr_ref_beams *beams, const double *depth, const double *opacity,
+                       const double *normal, const double *target_depth, const double *target_normal,
+                       double w_depth, double lambda_alpha, double eps, double lambda_n, double lambda_ng,
+                       double lambda_ns, double loss[8], double *g_depth, double *g_opacity, double *g_normal);
+
+/* Scale regulariser (Eq. 12, times lambda_s): *loss, and g_log_scales (n x 2, NULL to skip,
+ * overwritten); margin (n, NULL to skip) = |max(s) - s_max| / s_max. */
+int lgsr_ref_scale_reg(int64_t n, const double *log_scales, double lambda_s, double s_max, double *loss,
+                       double *g_log_scales, double *margin);
+
 /* Number of OpenMP threads the oracle runs with. */
 int lgsr_ref_threads(void);
 

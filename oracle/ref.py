@@ -18,6 +18,9 @@ _lib = None
 DEFAULT_PARAMS = dict(cutoff_sigma=3.0, alpha_thr=1.0 / 255.0, alpha_max=0.99, T_min=1e-4,
                       near=0.2, den_eps=1e-6, drop_tau=0.5)
 DEFAULT_WEIGHTS = dict(w_depth=1.0, lambda_n=1.0, lambda_ng=0.05)
+# Eq. 13 weights of Sec. 4.1; eps (Eq. 10) and s_max (Eq. 12) are not given numerically
+DEFAULT_OBJECTIVE = dict(w_depth=1.0, lambda_alpha=0.1, eps=1e-6, lambda_n=1.0, lambda_ng=0.05, lambda_ns=0.01)
+DEFAULT_SCALE_REG = dict(lambda_s=10.0, s_max=1.0)
 
 
 class _Params(ctypes.Structure):
@@ -53,6 +56,13 @@ def lib():
         L.lgsr_ref_backward.argtypes = [vp, vp, vp, vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
         L.lgsr_ref_backward.restype = ctypes.c_int
         L.lgsr_ref_threads.restype = ctypes.c_int
+        L.lgsr_ref_surf_normal.argtypes = [vp, vp, vp, vp, vp]
+        L.lgsr_ref_surf_normal.restype = ctypes.c_int
+        d = ctypes.c_double
+        L.lgsr_ref_objective.argtypes = [vp, vp, vp, vp, vp, vp, d, d, d, d, d, d, vp, vp, vp, vp]
+        L.lgsr_ref_objective.restype = ctypes.c_int
+        L.lgsr_ref_scale_reg.argtypes = [i64, vp, d, d, vp, vp, vp]
+        L.lgsr_ref_scale_reg.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -185,3 +195,61 @@ def loss_and_grad(surfels, pose, row_sincos, col_sincos, target_depth, target_no
     L, gd, go, gn = loss(fw, td, tn, weights, ray_weight)
     g = backward(surfels, pose, row_sincos, col_sincos, gd, go, gn, prm, ray_ids)
     return L, fw, g
+
+
+def _beams(row_sincos, col_sincos):
+    rows = _f64(row_sincos).reshape(-1, 2)
+    cols = _f64(col_sincos).reshape(-1, 2)
+    return rows, cols, _Beams(rows.shape[0], cols.shape[0], _ptr(rows), _ptr(cols))
+
+
+def surf_normal(row_sincos, col_sincos, depth):
+    """N_surf of a rendered H x W range image: (normals (H*W, 3), defined (H*W,) uint8,
+    flip_margin (H*W,))."""
+    rows, cols, B = _beams(row_sincos, col_sincos)
+    n = rows.shape[0] * cols.shape[0]
+    d = _f64(depth).reshape(-1)
+    assert d.shape[0] == n
+    ns, ok, fm = np.zeros((n, 3)), np.zeros(n, np.uint8), np.zeros(n)
+    if lib().lgsr_ref_surf_normal(ctypes.byref(B), _ptr(d), _ptr(ns), _ptr(ok), _ptr(fm)) != 0:
+        raise ValueError("lgsr_ref_surf_normal rejected its arguments")
+    return ns, ok, fm
+
+
+def objective(row_sincos, col_sincos, pred, target_depth, target_normal, weights=None, grad=True):
+    """Frame terms of the full objective over the H x W image.  Returns (loss[8] = total,
+    depth, opacity, G-ICP normal and surface normal terms, |Omega_D|, |Omega_N|, |Omega_S|;
+    g_depth, g_opacity, g_normal) (gradients None when grad is False).  Weights are rounded
+    to float32 like the ones the renderer receives."""
+    w = dict(DEFAULT_OBJECTIVE)
+    w.update(weights or {})
+    w = {k: float(np.float32(v)) for k, v in w.items()}
+    rows, cols, B = _beams(row_sincos, col_sincos)
+    n = rows.shape[0] * cols.shape[0]
+    depth = _f64(pred["depth"]).reshape(-1)
+    opacity = _f64(pred["opacity"]).reshape(-1)
+    normal = _f64(pred["normal"]).reshape(-1, 3)
+    td = _f64(target_depth).reshape(-1)
+    tn = _f64(target_normal).reshape(-1, 3)
+    assert depth.shape[0] == n and opacity.shape[0] == n and normal.shape[0] == n and td.shape[0] == n
+    out = np.zeros(8)
+    g = (np.zeros(n), np.zeros(n), np.zeros((n, 3))) if grad else (None, None, None)
+    rc = lib().lgsr_ref_objective(ctypes.byref(B), _ptr(depth), _ptr(opacity), _ptr(normal), _ptr(td), _ptr(tn),
+                                  w["w_depth"], w["lambda_alpha"], w["eps"], w["lambda_n"], w["lambda_ng"],
+                                  w["lambda_ns"], _ptr(out), *(_ptr(x) for x in g))
+    if rc != 0:
+        raise ValueError("lgsr_ref_objective rejected its arguments")
+    return (out,) + g
+
+
+def scale_reg(log_scales, lambda_s=None, s_max=None):
+    """Scale regulariser: (loss, g_log_scales (n, 2), margin (n,))."""
+    ls = _f64(log_scales).reshape(-1, 2)
+    lam = float(np.float32(DEFAULT_SCALE_REG["lambda_s"] if lambda_s is None else lambda_s))
+    smax = float(np.float32(DEFAULT_SCALE_REG["s_max"] if s_max is None else s_max))
+    n = ls.shape[0]
+    loss = np.zeros(1)
+    g, m = np.zeros((n, 2)), np.zeros(n)
+    if lib().lgsr_ref_scale_reg(n, _ptr(ls), lam, smax, _ptr(loss), _ptr(g), _ptr(m)) != 0:
+        raise ValueError("lgsr_ref_scale_reg rejected its arguments")
+    return float(loss[0]), g, m

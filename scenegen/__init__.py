@@ -16,5 +16,6 @@ from .scene import (  # noqa: F401
     ray_dirs_f64,
     raycast,
     sample_surfels,
+    synthetic_frame,
     targets_for_pose,
 )

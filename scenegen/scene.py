@@ -404,6 +404,23 @@ def targets_for_pose(scene: Scene, pose: np.ndarray, row_sincos, col_sincos,
     return depth.astype(np.float32), normal.astype(np.float32)
 
 
+def synthetic_frame(scene: Scene, pose: np.ndarray, row_sincos, col_sincos, seed: int,
+                    range_noise: float = 0.01, hole_rate: float = 0.05):
+    """A frame shaped like a renderer's output, for tests of the loss: depth = exact raycast
+    times (1 + N(0, range_noise)) with a Bernoulli hole_rate of rays and every no-return ray
+    zero; opacity U(0.3, 1) on rays with a depth, else 0; normal = the raycast normal
+    (sensor frame) plus N(0, 0.05) noise, scaled by the opacity.  float32 arrays (H,W),
+    (H,W), (H,W,3)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    depth, normal = targets_for_pose(scene, pose, row_sincos, col_sincos)
+    H, W = depth.shape
+    d = depth.astype(np.float64) * (1.0 + rng.normal(0.0, range_noise, size=(H, W)))
+    d[(rng.uniform(size=(H, W)) < hole_rate) | ~(depth > 0)] = 0.0
+    op = np.where(d > 0, rng.uniform(0.3, 1.0, size=(H, W)), 0.0)
+    nrm = (normal.astype(np.float64) + rng.normal(0.0, 0.05, size=(H, W, 3))) * op[..., None]
+    return d.astype(np.float32), op.astype(np.float32), nrm.astype(np.float32)
+
+
 # --------------------------------------------------------------------------------------
 # named workloads
 # --------------------------------------------------------------------------------------

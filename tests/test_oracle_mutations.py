@@ -42,6 +42,18 @@ MUTATIONS = {
         "for (int c = 0; c < 4; ++c) dq[c] = dqh[c] / s->qnorm;"),
     "pose_rotation_sign": ("dpose[3 + c] = -(c1[c] + c2[c] + c3[c] + c4[c]);",
                            "dpose[3 + c] = (c1[c] + c2[c] + c3[c] + c4[c]);"),
+    # full objective
+    "surf_normal_seam_not_wrapped": ("nb->r = k * W + (j + 1) % W;", "nb->r = k * W + (j + 1 < W ? j + 1 : j);"),
+    "surf_normal_one_sided": ("a[c] = depth[nb->r] * dr[c] - depth[nb->l] * dl[c];",
+                              "a[c] = depth[nb->r] * dr[c] - depth[k * W + j] * dp[c];"),
+    "surf_normal_not_turned": ("*sgn = vd > 0 ? -1.0 : 1.0;", "*sgn = 1.0;"),
+    "surf_term_over_omega_s": ("double tNs = cntD > 0 ? lambda_n * lambda_ns * sumNs / cntD : 0.0;",
+                               "double tNs = cntS > 0 ? lambda_n * lambda_ns * sumNs / cntS : 0.0;"),
+    "bce_without_eps": ("sumA += log(opacity[i] + eps);", "sumA += log(opacity[i]);"),
+    "stencil_row_sign": ("g_depth[nb.u] += dot3(du, gb);", "g_depth[nb.u] -= dot3(du, gb);"),
+    "stencil_cross_transposed": ("cross3(b, gv, ga);", "cross3(gv, b, ga);"),
+    "surf_gradient_unprojected": ("gv[c] = sgn * (gN[c] - gu * u[c]) / vn;", "gv[c] = sgn * gN[c] / vn;"),
+    "scale_reg_first_axis_only": ("int k = sy > sx ? 1 : 0;", "int k = 0;"),
 }
 
 
@@ -56,7 +68,8 @@ def _run_case(name, tmp):
     lib = oracle_build.build(src=src, out=os.path.join(tmp, f"lib_{name}.so"))
     env = dict(os.environ, LGSR_REF_LIB=lib, OMP_NUM_THREADS="1")
     r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider",
-                        os.path.join(ROOT, "tests", "test_oracle_pins.py")],
+                        os.path.join(ROOT, "tests", "test_oracle_pins.py"),
+                        os.path.join(ROOT, "tests", "test_oracle_objective_pins.py")],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     return name, r.returncode, r.stdout.strip().splitlines()[-1] if r.stdout.strip() else r.stderr[-300:]
 
