@@ -107,6 +107,18 @@ typedef struct {
     float lambda_ng; /* weight of the G-ICP normal cosine term inside (default 0.05) */
 } lgsr_loss_weights;
 
+/* Weights of the full mapping objective (Eq. 13 with Eq. 10-11; values of Sec. 4.1).  eps
+ * is not given numerically in the paper; lambda_ns is zero until densification starts
+ * (Sec. 3.4), which is the caller's schedule. */
+typedef struct {
+    float w_depth;      /* masked depth L1 (Eq. 10 left)                      (default 1)    */
+    float lambda_alpha; /* positive-only opacity BCE (Eq. 10 right)           (default 0.1)  */
+    float eps;          /* inside log(A^ + eps)                               (default 1e-6) */
+    float lambda_n;     /* normal loss (Eq. 13)                               (default 1)    */
+    float lambda_ng;    /* G-ICP normal cosine term (Eq. 11)                  (default 0.05) */
+    float lambda_ns;    /* rendered-surface normal cosine term (Eq. 11)       (default 0.01) */
+} lgsr_objective_weights;
+
 typedef struct {
     float *d_depth;   /* H x W     dL/d depth   */
     float *d_opacity; /* H x W     dL/d opacity */
@@ -126,6 +138,7 @@ typedef struct lgsr_state lgsr_state; /* library-owned, opaque */
 /* Fill *opts / *w with the defaults listed above. */
 void lgsr_default_opts(lgsr_raster_opts *opts);
 void lgsr_default_loss_weights(lgsr_loss_weights *w);
+void lgsr_default_objective_weights(lgsr_objective_weights *w);
 
 /* Create a context on HIP device `device` issuing all work on `hip_stream` (a hipStream_t;
  * NULL = the device's null stream).  Allocates a small workspace; later calls grow it.
@@ -170,6 +183,41 @@ lgsr_status lgsr_forward(lgsr_ctx *ctx, const lgsr_surfels *surfels, const float
 lgsr_status lgsr_loss(lgsr_ctx *ctx, int64_t n_rays, const lgsr_frame *pred,
                       const float *target_depth, const float *target_normal,
                       const lgsr_loss_weights *weights, float *loss_out, lgsr_frame_grad *grad_out);
+
+/* Frame terms of the full mapping objective (Sec. 3.4: Eq. 10, Eq. 11, weighted as in
+ * Eq. 13) and their gradient:
+ *   L = w_depth / |Omega_D| sum_{Omega_D} |D^ - D|
+ *     - lambda_alpha / |Omega_D| sum_{Omega_D} log(A^ + eps)
+ *     + lambda_n lambda_ng / |Omega_N| sum_{Omega_N} (1 - N^ . N / |N^|)
+ *     + lambda_n lambda_ns / |Omega_D| sum_{Omega_D, N_surf defined} (1 - N^ . N_surf / |N^|)
+ * N_surf (Sec. 3.4 (ii)) at pixel (k, j) is the unit normal of the rendered surface:
+ * v = (P(k, j+1) - P(k, j-1)) x (P(k+1, j) - P(k-1, j)), P = D^ d (d from the beam tables;
+ * columns wrap around the full turn), turned to face the sensor; defined on rows 1..H-2
+ * when the four neighbours rendered a range (D^ > 0) and v != 0.  The gradient is the full
+ * derivative, through N^ and through the neighbours' D^ inside N_surf.
+ *   beams: the H x W beam model the frame was rendered with (device tables).
+ *   pred: the rendered frame (depth, opacity, normal read; drop unused).
+ *   target_depth: H x W (0 = no return); target_normal: H x W x 3 (zero = none), sensor frame.
+ *   loss_out: DEVICE float[8] = {total, depth term, opacity term, G-ICP normal term,
+ *             surface normal term, |Omega_D|, |Omega_N|, |Omega_S|} (Omega_S: rays of Omega_D
+ *             whose N_surf is defined).
+ *   grad_out: caller-owned dL/d(depth, opacity, normal), overwritten; NULL = loss only.
+ * Errors: EINVAL (NULL or inconsistent arguments, eps < 0), EDEVICE. */
+lgsr_status lgsr_objective(lgsr_ctx *ctx, const lgsr_beams *beams, const lgsr_frame *pred,
+                           const float *target_depth, const float *target_normal,
+                           const lgsr_objective_weights *weights, float *loss_out,
+                           lgsr_frame_grad *grad_out);
+
+/* Scale regulariser (Sec. 3.4, Eq. 12, times lambda_s of Eq. 13):
+ *   L = lambda_s sum_i max(0, max(s_x, s_y) - s_max),  s = exp(log_scales).
+ *   log_scales: DEVICE n x 2, 8-byte aligned.  s_max > 0 (not given numerically in the paper).
+ *   loss_out: DEVICE float[1].
+ *   grad_log_scales: DEVICE n x 2, 8-byte aligned, ACCUMULATED into (dL/dlog s_k = lambda_s s_k
+ *     for the larger scale when it exceeds s_max, the first one on a tie); NULL = loss only.
+ *     Issue it after lgsr_backward to add the regulariser to the rendering gradient.
+ * Errors: EINVAL, EDEVICE. */
+lgsr_status lgsr_scale_reg(lgsr_ctx *ctx, int64_t n, const float *log_scales, float lambda_s, float s_max,
+                           float *loss_out, float *grad_log_scales);
 
 /* Backward of the forward that produced `state`: given dL/d(depth, opacity, normal) per
  * ray, write dL/d every surfel parameter into `out` (overwritten; zero for surfels that

@@ -211,6 +211,52 @@ def loss(renderer: Renderer, frame: dict, target_depth: torch.Tensor, target_nor
     return _Loss.apply(renderer, frame["depth"], frame["opacity"], frame["normal"], target_depth, target_normal)
 
 
+class _Objective(torch.autograd.Function):
+    @staticmethod
+    def forward(fctx, renderer: Renderer, weights, depth, opacity, normal, target_depth, target_normal):
+        frame = dict(depth=depth.detach().contiguous(), opacity=opacity.detach().contiguous(),
+                     normal=normal.detach().contiguous())
+        L, g = lgsr.lgsr_objective(renderer.ctx, frame, renderer.rows, renderer.cols, target_depth, target_normal,
+                                   weights)
+        fctx.grads = g
+        terms = L[1:].clone()
+        fctx.mark_non_differentiable(terms)
+        return L[0].clone(), terms
+
+    @staticmethod
+    def backward(fctx, gL, _gterms):
+        g = fctx.grads
+        return None, None, g["depth"] * gL, g["opacity"] * gL, g["normal"] * gL, None, None
+
+
+def objective(renderer: Renderer, frame: dict, target_depth: torch.Tensor, target_normal: torch.Tensor,
+              weights: lgsr.ObjectiveWeights | None = None):
+    """Frame terms of the full objective (Eq. 10-11 weighted as in Eq. 13): (total, tensor(
+    [depth, opacity, G-ICP normal, surface normal terms, |Omega_D|, |Omega_N|, |Omega_S|]));
+    the total is differentiable with respect to the rendered depth, opacity and normal."""
+    w = weights if weights is not None else lgsr.default_objective_weights()
+    return _Objective.apply(renderer, w, frame["depth"], frame["opacity"], frame["normal"], target_depth,
+                            target_normal)
+
+
+class _ScaleReg(torch.autograd.Function):
+    @staticmethod
+    def forward(fctx, ctx: lgsr.Context, lambda_s: float, s_max: float, log_scales):
+        g = torch.zeros_like(log_scales)
+        L = lgsr.lgsr_scale_reg(ctx, log_scales.detach().contiguous(), lambda_s, s_max, grad_log_scales=g)
+        fctx.g = g
+        return L[0].clone()
+
+    @staticmethod
+    def backward(fctx, gL):
+        return None, None, None, fctx.g * gL
+
+
+def scale_reg(ctx: lgsr.Context, log_scales: torch.Tensor, lambda_s: float = 10.0, s_max: float = 1.0):
+    """lambda_s sum_i max(0, max(s_i) - s_max) (Eq. 12), differentiable in log_scales."""
+    return _ScaleReg.apply(ctx, float(lambda_s), float(s_max), log_scales)
+
+
 # ------------------------------------------------------------------------------------------
 # optimisers
 # ------------------------------------------------------------------------------------------

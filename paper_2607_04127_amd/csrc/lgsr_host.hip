@@ -649,6 +649,72 @@ lgsr_status lgsr_loss(lgsr_ctx *ctx, int64_t n_rays, const lgsr_frame *pred, con
     return loss_impl(ctx, ctx->lanes[0], n_rays, pred, target_depth, target_normal, w, loss_out, grad_out);
 }
 
+void lgsr_default_objective_weights(lgsr_objective_weights *w)
+{
+    if (!w) return;
+    w->w_depth = 1.f;
+    w->lambda_alpha = 0.1f;
+    w->eps = 1e-6f;
+    w->lambda_n = 1.f;
+    w->lambda_ng = 0.05f;
+    w->lambda_ns = 0.01f;
+}
+
+lgsr_status lgsr_objective(lgsr_ctx *ctx, const lgsr_beams *beams, const lgsr_frame *pred,
+                           const float *target_depth, const float *target_normal, const lgsr_objective_weights *w,
+                           float *loss_out, lgsr_frame_grad *grad_out)
+{
+    if (!ctx) return LGSR_EINVAL;
+    lgsr_status st = check_beams(ctx, beams);
+    if (st != LGSR_OK) return st;
+    if (!w) return fail(ctx, LGSR_EINVAL, "weights are NULL");
+    const float ws[6] = {w->w_depth, w->lambda_alpha, w->eps, w->lambda_n, w->lambda_ng, w->lambda_ns};
+    for (float x : ws)
+        if (!std::isfinite(x)) return fail(ctx, LGSR_EINVAL, "weights must be finite");
+    if (w->eps < 0.f) return fail(ctx, LGSR_EINVAL, "eps must be >= 0");
+    if (!loss_out) return fail(ctx, LGSR_EINVAL, "loss_out is NULL");
+    const int64_t n_rays = (int64_t)beams->H * beams->W;
+    if (n_rays > 0) {
+        if (!pred || !pred->depth || !pred->opacity || !pred->normal) return fail(ctx, LGSR_EINVAL, "prediction is NULL");
+        if (!target_depth || !target_normal) return fail(ctx, LGSR_EINVAL, "targets are NULL");
+        if (grad_out && (!grad_out->d_depth || !grad_out->d_opacity || !grad_out->d_normal))
+            return fail(ctx, LGSR_EINVAL, "a gradient output is NULL");
+    }
+    HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
+    Lane &L = ctx->lanes[0];
+    HIP_TRY(ensure(L.partials, (size_t)objective_partial_floats(n_rays) * sizeof(float)), "alloc partials");
+    const ObjectiveWeights ow{w->w_depth, w->lambda_alpha, w->eps, w->lambda_n, w->lambda_ng, w->lambda_ns};
+    Stage st_(ctx, LGSR_STAGE_LOSS, L.stream);
+    HIP_TRY(launch_objective(beams->H, beams->W, beams->row_sincos, beams->col_sincos, pred ? pred->depth : nullptr,
+                             pred ? pred->opacity : nullptr, pred ? pred->normal : nullptr, target_depth,
+                             target_normal, ow, as<float>(L.partials), loss_out,
+                             grad_out ? grad_out->d_depth : nullptr, grad_out ? grad_out->d_opacity : nullptr,
+                             grad_out ? grad_out->d_normal : nullptr, L.stream),
+            "objective");
+    return LGSR_OK;
+}
+
+lgsr_status lgsr_scale_reg(lgsr_ctx *ctx, int64_t n, const float *log_scales, float lambda_s, float s_max,
+                           float *loss_out, float *grad_log_scales)
+{
+    if (!ctx) return LGSR_EINVAL;
+    if (n < 0) return fail(ctx, LGSR_EINVAL, "n must be >= 0");
+    if (!loss_out) return fail(ctx, LGSR_EINVAL, "loss_out is NULL");
+    if (n > 0 && !log_scales) return fail(ctx, LGSR_EINVAL, "log_scales is NULL");
+    if (!std::isfinite(lambda_s) || !(s_max > 0.f) || !std::isfinite(s_max))
+        return fail(ctx, LGSR_EINVAL, "lambda_s must be finite and s_max finite and > 0");
+    if ((reinterpret_cast<uintptr_t>(log_scales) | reinterpret_cast<uintptr_t>(grad_log_scales)) & 7u)
+        return fail(ctx, LGSR_EINVAL, "log_scales and grad_log_scales must be 8-byte aligned");
+    HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
+    Lane &L = ctx->lanes[0];
+    HIP_TRY(ensure(L.partials, (size_t)scale_reg_blocks(n) * sizeof(float)), "alloc partials");
+    Stage st_(ctx, LGSR_STAGE_LOSS, L.stream);
+    HIP_TRY(launch_scale_reg(n, log_scales, lambda_s, s_max, as<float>(L.partials), loss_out, grad_log_scales,
+                             L.stream),
+            "scale regulariser");
+    return LGSR_OK;
+}
+
 lgsr_status lgsr_backward(lgsr_ctx *ctx, lgsr_state *S, const lgsr_frame_grad *gin, lgsr_surfel_grads *out,
                           float *grad_pose)
 {

@@ -79,6 +79,19 @@ hipError_t launch_loss(int64_t n_rays, const float *depth, const float *normal, 
                        float w_depth, float lambda_n, float lambda_ng, float *partials, float *loss_out,
                        float *gD, float *gA, float *gN, hipStream_t s);
 
+// ---- objective.hip ----
+struct ObjectiveWeights {
+    float w_depth, lambda_alpha, eps, lambda_n, lambda_ng, lambda_ns;
+};
+int objective_partial_floats(int64_t n_rays);
+hipError_t launch_objective(int H, int W, const float *rows, const float *cols, const float *depth,
+                            const float *opacity, const float *normal, const float *td, const float *tn,
+                            const ObjectiveWeights &w, float *partials, float *loss_out, float *gD, float *gA,
+                            float *gN, hipStream_t s);
+int scale_reg_blocks(int64_t n);
+hipError_t launch_scale_reg(int64_t n, const float *log_scales, float lambda_s, float s_max, float *partials,
+                            float *loss_out, float *grad_log_scales, hipStream_t s);
+
 // ---- chain.hip ----
 int chain_blocks(int64_t n);
 // reads the record-gradient slots of surfels with a non-empty ray rectangle and clears them

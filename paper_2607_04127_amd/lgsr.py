@@ -22,7 +22,7 @@ _STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ECAPACITY", 
 EXPORTS = ("lgsr_default_opts", "lgsr_default_loss_weights", "lgsr_create", "lgsr_destroy", "lgsr_set_stream",
            "lgsr_last_error", "lgsr_forward", "lgsr_loss", "lgsr_backward", "lgsr_state_free", "lgsr_query",
            "lgsr_profile", "lgsr_profile_read", "lgsr_sync", "lgsr_state_bytes", "lgsr_adam_step",
-           "lgsr_render_batch")
+           "lgsr_render_batch", "lgsr_default_objective_weights", "lgsr_objective", "lgsr_scale_reg")
 STAGES = ("project", "scan", "readback", "emit", "tile_sort", "raster_fwd", "loss", "bwd_prep", "raster_bwd",
           "chain")
 
@@ -56,6 +56,10 @@ class Frame(ctypes.Structure):
 
 class LossWeights(ctypes.Structure):
     _fields_ = [("w_depth", ctypes.c_float), ("lambda_n", ctypes.c_float), ("lambda_ng", ctypes.c_float)]
+
+
+class ObjectiveWeights(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_float) for k in ("w_depth", "lambda_alpha", "eps", "lambda_n", "lambda_ng", "lambda_ns")]
 
 
 class FrameGrad(ctypes.Structure):
@@ -110,9 +114,13 @@ def lib():
         L.lgsr_render_batch.argtypes = [vp, ctypes.c_int32, P(Request), P(RasterOpts), P(LossWeights)]
         L.lgsr_adam_step.argtypes = [vp, ctypes.c_int32, P(AdamGroup), ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                      ctypes.c_int32]
+        L.lgsr_default_objective_weights.argtypes = [P(ObjectiveWeights)]
+        L.lgsr_default_objective_weights.restype = None
+        L.lgsr_objective.argtypes = [vp, P(Beams), P(Frame), vp, vp, P(ObjectiveWeights), vp, P(FrameGrad)]
+        L.lgsr_scale_reg.argtypes = [vp, ctypes.c_int64, vp, ctypes.c_float, ctypes.c_float, vp, vp]
         for name in ("lgsr_create", "lgsr_set_stream", "lgsr_forward", "lgsr_loss", "lgsr_backward", "lgsr_query",
                      "lgsr_profile", "lgsr_profile_read", "lgsr_sync", "lgsr_state_bytes", "lgsr_adam_step",
-           "lgsr_render_batch"):
+                     "lgsr_render_batch", "lgsr_objective", "lgsr_scale_reg"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -129,6 +137,14 @@ def default_opts(**kw) -> RasterOpts:
 def default_loss_weights(**kw) -> LossWeights:
     w = LossWeights()
     lib().lgsr_default_loss_weights(ctypes.byref(w))
+    for k, v in kw.items():
+        setattr(w, k, v)
+    return w
+
+
+def default_objective_weights(**kw) -> ObjectiveWeights:
+    w = ObjectiveWeights()
+    lib().lgsr_default_objective_weights(ctypes.byref(w))
     for k, v in kw.items():
         setattr(w, k, v)
     return w
@@ -274,6 +290,63 @@ def lgsr_loss(ctx: Context, frame: dict, target_depth: torch.Tensor, target_norm
     ctx._check(lib().lgsr_loss(ctx.handle, n, ctypes.byref(fr), _ptr(target_depth), _ptr(target_normal),
                                ctypes.byref(w), _ptr(loss_out), ctypes.byref(fg)))
     return loss_out, grad_out
+
+
+def lgsr_objective(ctx: Context, frame: dict, row_sincos: torch.Tensor, col_sincos: torch.Tensor,
+                   target_depth: torch.Tensor, target_normal: torch.Tensor, weights: ObjectiveWeights | None = None,
+                   loss_out: torch.Tensor | None = None, grad_out: dict | None = None, want_grad: bool = True):
+    """Frame terms of the full objective (float32[8] on the device: total, depth, opacity,
+    G-ICP normal and surface normal terms, |Omega_D|, |Omega_N|, |Omega_S|) and, when
+    want_grad, dL/d(depth, opacity, normal) (else None)."""
+    d = ctx.device
+    H, W = row_sincos.shape[0], col_sincos.shape[0]
+    _dev(row_sincos, "row_sincos", (H, 2), d)
+    _dev(col_sincos, "col_sincos", (W, 2), d)
+    _dev(frame["depth"], "depth", (H, W), d)
+    _dev(frame["opacity"], "opacity", (H, W), d)
+    _dev(frame["normal"], "normal", (H, W, 3), d)
+    _dev(target_depth, "target_depth", (H, W), d)
+    _dev(target_normal, "target_normal", (H, W, 3), d)
+    if loss_out is None:
+        loss_out = torch.empty(8, device=d)
+    _dev(loss_out, "loss_out", (8,), d)
+    fg = None
+    if want_grad:
+        if grad_out is None:
+            grad_out = dict(depth=torch.empty((H, W), device=d), opacity=torch.empty((H, W), device=d),
+                            normal=torch.empty((H, W, 3), device=d))
+        _dev(grad_out["depth"], "grad depth", (H, W), d)
+        _dev(grad_out["opacity"], "grad opacity", (H, W), d)
+        _dev(grad_out["normal"], "grad normal", (H, W, 3), d)
+        fg = FrameGrad(_ptr(grad_out["depth"]), _ptr(grad_out["opacity"]), _ptr(grad_out["normal"]))
+    else:
+        grad_out = None
+    bm = Beams(H, W, _ptr(row_sincos), _ptr(col_sincos))
+    fr = Frame(_ptr(frame["depth"]), _ptr(frame["opacity"]), _ptr(frame["normal"]), None)
+    w = weights if weights is not None else default_objective_weights()
+    ctx._stream()
+    ctx._check(lib().lgsr_objective(ctx.handle, ctypes.byref(bm), ctypes.byref(fr), _ptr(target_depth),
+                                    _ptr(target_normal), ctypes.byref(w), _ptr(loss_out),
+                                    ctypes.byref(fg) if fg is not None else None))
+    return loss_out, grad_out
+
+
+def lgsr_scale_reg(ctx: Context, log_scales: torch.Tensor, lambda_s: float = 10.0, s_max: float = 1.0,
+                   loss_out: torch.Tensor | None = None, grad_log_scales: torch.Tensor | None = None):
+    """Scale regulariser lambda_s sum max(0, max(s) - s_max) (float32[1] on the device); its
+    gradient is ADDED into grad_log_scales (n, 2) when given."""
+    d = ctx.device
+    n = log_scales.shape[0]
+    _dev(log_scales, "log_scales", (n, 2), d)
+    if loss_out is None:
+        loss_out = torch.empty(1, device=d)
+    _dev(loss_out, "loss_out", (1,), d)
+    if grad_log_scales is not None:
+        _dev(grad_log_scales, "grad_log_scales", (n, 2), d)
+    ctx._stream()
+    ctx._check(lib().lgsr_scale_reg(ctx.handle, n, _ptr(log_scales), float(lambda_s), float(s_max), _ptr(loss_out),
+                                    _ptr(grad_log_scales)))
+    return loss_out
 
 
 def lgsr_backward(ctx: Context, state: State, grad: dict, out: dict | None = None,

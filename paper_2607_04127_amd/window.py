@@ -57,7 +57,13 @@ class Window:
     """Device-resident map parameters, per-keyframe targets and both optimisers."""
 
     def __init__(self, ctx: lgsr.Context, w: dict, poses, means=None, keep_lists="auto", lr=None,
-                 pose_lr=(1e-3, 2e-4), hbm_budget=16 << 30):
+                 pose_lr=(1e-3, 2e-4), hbm_budget=16 << 30, objective="basic", ns_start=0, s_max=1.0):
+        """objective: "basic" (depth L1 + G-ICP normal term) or "full" (Eq. 13: also the
+        opacity BCE, the rendered-surface normal term from iteration ns_start on, and the
+        scale regulariser with threshold s_max)."""
+        if objective not in ("basic", "full"):
+            raise ValueError("objective must be 'basic' or 'full'")
+        self.objective, self.ns_start, self.s_max, self.iter = objective, int(ns_start), float(s_max), 0
         dev = ctx.device
         self.ctx = ctx
         self.rows = torch.from_numpy(w["row_sincos"]).to(dev)
@@ -76,9 +82,18 @@ class Window:
         alive until then, kept or dropped for recomputation against the HBM budget);
         gradients land in .grad of the map parameters and of the pose tangents."""
         losses = []
+        if self.objective == "full":
+            wts = lgsr.default_objective_weights()
+            if self.iter < self.ns_start:
+                wts.lambda_ns = 0.0
         for k, (td, tn) in enumerate(self.targets):
             fr = AG.render(self.renderer, self.params, self.pose_opt.T0[k], self.pose_opt.xi[k])
-            losses.append(AG.loss(self.renderer, fr, td, tn)[0])
+            if self.objective == "full":
+                losses.append(AG.objective(self.renderer, fr, td, tn, wts)[0])
+            else:
+                losses.append(AG.loss(self.renderer, fr, td, tn)[0])
+        if self.objective == "full":
+            losses.append(AG.scale_reg(self.ctx, self.params["log_scales"], 10.0, self.s_max))
         total = torch.stack(losses).sum()
         total.backward()
         return float(total.detach())
@@ -89,6 +104,7 @@ class Window:
         total = self.loss_and_backward()
         self.map_opt.step()
         self.pose_opt.step()
+        self.iter += 1
         return total
 
 
@@ -97,6 +113,8 @@ def main():
     ap.add_argument("--iters", type=int, default=10)
     ap.add_argument("--surfels", type=int, default=None)
     ap.add_argument("--keep", default="auto", choices=("auto", "store", "recompute"))
+    ap.add_argument("--objective", default="basic", choices=("basic", "full"))
+    ap.add_argument("--ns-start", type=int, default=5, help="iteration that enables the surface-normal term")
     args = ap.parse_args()
     import scenegen
 
@@ -106,7 +124,7 @@ def main():
           f"({time.perf_counter() - t0:.1f} s)", file=sys.stderr, flush=True)
     poses, means = perturb(w)
     ctx = lgsr.Context(0)
-    win = Window(ctx, w, poses, means=means, keep_lists=args.keep)
+    win = Window(ctx, w, poses, means=means, keep_lists=args.keep, objective=args.objective, ns_start=args.ns_start)
     err0 = pose_errors(win.pose_opt.T0, w["poses"])
     curve, times = [], []
     for it in range(args.iters):
@@ -119,7 +137,7 @@ def main():
     err1 = pose_errors(win.pose_opt.T0, w["poses"])
     rays = w["H"] * w["W"] * len(w["poses"])
     out = dict(workload="window64x2048_1m", surfels=int(w["means"].shape[0]), poses=len(w["poses"]),
-               iters=args.iters, keep_lists=args.keep, s_per_iter=float(np.median(times)),
+               iters=args.iters, keep_lists=args.keep, objective=args.objective, s_per_iter=float(np.median(times)),
                rays_per_s=float(rays / np.median(times)), loss=curve,
                recomputed_backwards=win.renderer.recomputed,
                pose_err_before=dict(t_m=float(np.mean([e[0] for e in err0])),
