@@ -749,6 +749,93 @@ int lgsr_ref_scale_reg(int64_t n, const double *log_scales, double lambda_s, dou
     return 0;
 }
 
+/* ---- scan to range image (Sec. 3.1) and target covariance (Sec. 3.2) ------------------ */
+
+/* R15: the spherical projection pi_s of a scan onto the H x W grid of a spinning LiDAR:
+ * rows uniform in elevation from el_max (row 0) down to el_min (row H - 1), columns uniform
+ * over the full turn (column j at azimuth 2 pi j / W).  A point goes to the nearest row and
+ * column (f = (el_max - el) / step, k = floor(f + 1/2); g = az W / (2 pi), j = floor(g +
+ * 1/2) mod W), is kept when 0 <= k < H and r_min <= r <= r_max, and the nearest return wins
+ * each pixel (equal ranges: the lower point index).  The pixel takes that point's range and
+ * its normal turned to face the sensor (n.p > 0 flips it).  bin_margin (per point, NULL to
+ * skip) is the distance of f and g to their rounding boundaries in bins and of r to the
+ * range gates relative to r: how close the point is to landing elsewhere. */
+int lgsr_ref_scan_to_range(int64_t n, const double *points, const double *normals, int32_t H, int32_t W,
+                           double el_min, double el_max, double r_min, double r_max, double *depth,
+                           double *normal, int64_t *index, double *bin_margin)
+{
+    if (n < 0 || H < 2 || W < 1 || !(el_max > el_min) || !depth || !index || (n > 0 && !points)) return -1;
+    const int64_t P = (int64_t)H * W;
+    for (int64_t i = 0; i < P; ++i) {
+        depth[i] = 0;
+        index[i] = -1;
+        if (normal) normal[3 * i] = normal[3 * i + 1] = normal[3 * i + 2] = 0;
+    }
+    const double step = (el_max - el_min) / (H - 1);
+    const double two_pi = 6.283185307179586476925286766559;
+    for (int64_t i = 0; i < n; ++i) {
+        const double *p = points + 3 * i;
+        double rxy = sqrt(p[0] * p[0] + p[1] * p[1]);
+        double r = sqrt(p[0] * p[0] + p[1] * p[1] + p[2] * p[2]);
+        double el = atan2(p[2], rxy);
+        double az = atan2(p[1], p[0]);
+        double f = (el_max - el) / step;
+        double g = az * W / two_pi;
+        double kf = floor(f + 0.5), jf = floor(g + 0.5);
+        if (bin_margin) {
+            double m = fmin(fabs(f + 0.5 - kf), fabs(kf + 0.5 - f));
+            m = fmin(m, fmin(fabs(g + 0.5 - jf), fabs(jf + 0.5 - g)));
+            if (r > 0) m = fmin(m, fmin(fabs(r - r_min), fabs(r - r_max)) / r);
+            bin_margin[i] = m;
+        }
+        if (!(r >= r_min && r <= r_max) || kf < 0 || kf > H - 1) continue;
+        int64_t j = (int64_t)jf % W;
+        if (j < 0) j += W;
+        int64_t pix = (int64_t)kf * W + j;
+        if (index[pix] < 0 || r < depth[pix]) {
+            depth[pix] = r;
+            index[pix] = i;
+        }
+    }
+    if (normal && normals)
+        for (int64_t q = 0; q < P; ++q) {
+            if (index[q] < 0) continue;
+            const double *nv = normals + 3 * index[q], *p = points + 3 * index[q];
+            double sgn = dot3(nv, p) > 0 ? -1.0 : 1.0;
+            for (int c = 0; c < 3; ++c) normal[3 * q + c] = sgn * nv[c];
+        }
+    return 0;
+}
+
+/* Sec. 3.2, target covariance: Sigma = R diag(s_x^2, s_y^2, eps^2) R^T with R = [a b n]
+ * the rotation of the normalised quaternion (w, x, y, z) and s = exp(log_scales).
+ * cov: n x 6 = (xx, xy, xz, yy, yz, zz). */
+int lgsr_ref_target_cov(int64_t n, const double *quats, const double *log_scales, double eps, double *cov)
+{
+    if (n < 0 || !(eps >= 0) || (n > 0 && (!quats || !log_scales || !cov))) return -1;
+    for (int64_t i = 0; i < n; ++i) {
+        const double *q = quats + 4 * i;
+        double qn = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+        if (!(qn > 0)) return -1;
+        double w = q[0] / qn, x = q[1] / qn, y = q[2] / qn, z = q[3] / qn;
+        double R[3][3] = {{1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)},
+                          {2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)},
+                          {2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)}};
+        double d[3] = {exp(2 * log_scales[2 * i]), exp(2 * log_scales[2 * i + 1]), eps * eps};
+        double S[3][3];
+        for (int r = 0; r < 3; ++r)
+            for (int c = 0; c < 3; ++c) S[r][c] = R[r][0] * d[0] * R[c][0] + R[r][1] * d[1] * R[c][1] + R[r][2] * d[2] * R[c][2];
+        double *o = cov + 6 * i;
+        o[0] = S[0][0];
+        o[1] = S[0][1];
+        o[2] = S[0][2];
+        o[3] = S[1][1];
+        o[4] = S[1][2];
+        o[5] = S[2][2];
+    }
+    return 0;
+}
+
 int lgsr_ref_threads(void)
 {
 #ifdef _OPENMP

@@ -108,6 +108,18 @@ int lgsr_ref_objective(const lgsr_ref_beams *beams, const double *depth, const d
 int lgsr_ref_scale_reg(int64_t n, const double *log_scales, double lambda_s, double s_max, double *loss,
                        double *g_log_scales, double *margin);
 
+/* Spherical projection of a scan (n points, sensor frame, n x 3; normals n x 3 or NULL) onto
+ * the H x W grid with rows from el_max (row 0) to el_min and columns over the full turn:
+ * nearest return per pixel.  depth (H*W, 0 = none), normal (H*W x 3, may be NULL: the
+ * winner's normal turned to face the sensor, zero if none), index (H*W, the winning point,
+ * -1 if none), bin_margin (n, may be NULL). */
+int lgsr_ref_scan_to_range(int64_t n, const double *points, const double *normals, int32_t H, int32_t W,
+                           double el_min, double el_max, double r_min, double r_max, double *depth,
+                           double *normal, int64_t *index, double *bin_margin);
+
+/* Target covariances of surfels (n x 6: xx, xy, xz, yy, yz, zz), thickness eps. */
+int lgsr_ref_target_cov(int64_t n, const double *quats, const double *log_scales, double eps, double *cov);
+
 /* Number of OpenMP threads the oracle runs with. */
 int lgsr_ref_threads(void);
 

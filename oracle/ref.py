@@ -63,6 +63,10 @@ def lib():
         L.lgsr_ref_objective.restype = ctypes.c_int
         L.lgsr_ref_scale_reg.argtypes = [i64, vp, d, d, vp, vp, vp]
         L.lgsr_ref_scale_reg.restype = ctypes.c_int
+        L.lgsr_ref_scan_to_range.argtypes = [i64, vp, vp, ctypes.c_int32, ctypes.c_int32, d, d, d, d, vp, vp, vp, vp]
+        L.lgsr_ref_scan_to_range.restype = ctypes.c_int
+        L.lgsr_ref_target_cov.argtypes = [i64, vp, vp, d, vp]
+        L.lgsr_ref_target_cov.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -253,3 +257,31 @@ def scale_reg(log_scales, lambda_s=None, s_max=None):
     if lib().lgsr_ref_scale_reg(n, _ptr(ls), lam, smax, _ptr(loss), _ptr(g), _ptr(m)) != 0:
         raise ValueError("lgsr_ref_scale_reg rejected its arguments")
     return float(loss[0]), g, m
+
+
+def scan_to_range(points, H, W, el_min, el_max, r_min=0.0, r_max=float("inf"), normals=None):
+    """Spherical range image of a scan (angles in radians): dict(depth (H*W,), normal (H*W,3),
+    index (H*W,) int64, bin_margin (n,)).  Grid parameters are rounded to float32 like the
+    ones the GPU receives."""
+    pts = _f64(points).reshape(-1, 3)
+    n = pts.shape[0]
+    nrm = None if normals is None else _f64(normals).reshape(-1, 3)
+    f32 = lambda x: float(np.float32(x))  # noqa: E731
+    out = dict(depth=np.zeros(H * W), normal=np.zeros((H * W, 3)), index=np.zeros(H * W, np.int64),
+               bin_margin=np.zeros(n))
+    rc = lib().lgsr_ref_scan_to_range(n, _ptr(pts), _ptr(nrm), H, W, f32(el_min), f32(el_max), f32(r_min),
+                                      f32(r_max), _ptr(out["depth"]), _ptr(out["normal"]), _ptr(out["index"]),
+                                      _ptr(out["bin_margin"]))
+    if rc != 0:
+        raise ValueError("lgsr_ref_scan_to_range rejected its arguments")
+    return out
+
+
+def target_cov(quats, log_scales, eps=0.01):
+    """Surfel target covariances (n, 6): xx, xy, xz, yy, yz, zz."""
+    q = _f64(quats).reshape(-1, 4)
+    ls = _f64(log_scales).reshape(-1, 2)
+    cov = np.zeros((q.shape[0], 6))
+    if lib().lgsr_ref_target_cov(q.shape[0], _ptr(q), _ptr(ls), float(np.float32(eps)), _ptr(cov)) != 0:
+        raise ValueError("lgsr_ref_target_cov rejected its arguments")
+    return cov

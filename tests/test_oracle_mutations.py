@@ -54,6 +54,16 @@ MUTATIONS = {
     "stencil_cross_transposed": ("cross3(b, gv, ga);", "cross3(gv, b, ga);"),
     "surf_gradient_unprojected": ("gv[c] = sgn * (gN[c] - gu * u[c]) / vn;", "gv[c] = sgn * gN[c] / vn;"),
     "scale_reg_first_axis_only": ("int k = sy > sx ? 1 : 0;", "int k = 0;"),
+    # scan projection and target covariance
+    "scan_rows_bottom_up": ("double f = (el_max - el) / step;", "double f = (el - el_min) / step;"),
+    "scan_farthest_wins": ("if (index[pix] < 0 || r < depth[pix]) {", "if (index[pix] < 0 || r > depth[pix]) {"),
+    "scan_seam_clamped": ("if (j < 0) j += W;", "if (j < 0) j = 0;"),
+    "scan_normal_not_turned": ("double sgn = dot3(nv, p) > 0 ? -1.0 : 1.0;", "double sgn = 1.0;"),
+    "cov_axes_transposed": (
+        "S[r][c] = R[r][0] * d[0] * R[c][0] + R[r][1] * d[1] * R[c][1] + R[r][2] * d[2] * R[c][2];",
+        "S[r][c] = R[0][r] * d[0] * R[0][c] + R[1][r] * d[1] * R[1][c] + R[2][r] * d[2] * R[2][c];"),
+    "cov_scales_swapped": ("double d[3] = {exp(2 * log_scales[2 * i]), exp(2 * log_scales[2 * i + 1]), eps * eps};",
+                           "double d[3] = {exp(2 * log_scales[2 * i + 1]), exp(2 * log_scales[2 * i]), eps * eps};"),
 }
 
 
@@ -69,7 +79,8 @@ def _run_case(name, tmp):
     env = dict(os.environ, LGSR_REF_LIB=lib, OMP_NUM_THREADS="1")
     r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider",
                         os.path.join(ROOT, "tests", "test_oracle_pins.py"),
-                        os.path.join(ROOT, "tests", "test_oracle_objective_pins.py")],
+                        os.path.join(ROOT, "tests", "test_oracle_objective_pins.py"),
+                        os.path.join(ROOT, "tests", "test_oracle_scan_pins.py")],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     return name, r.returncode, r.stdout.strip().splitlines()[-1] if r.stdout.strip() else r.stderr[-300:]
 
