@@ -219,6 +219,38 @@ lgsr_status lgsr_objective(lgsr_ctx *ctx, const lgsr_beams *beams, const lgsr_fr
 lgsr_status lgsr_scale_reg(lgsr_ctx *ctx, int64_t n, const float *log_scales, float lambda_s, float s_max,
                            float *loss_out, float *grad_log_scales);
 
+/* The spherical grid a scan is projected onto (Sec. 3.1): H rows uniform in elevation from
+ * el_max (row 0) down to el_min (row H - 1), W columns uniform over the full turn (column j
+ * at azimuth 2 pi j / W, azimuth measured from +x towards +y), the grid the renderer's beam
+ * tables describe.  Angles in radians; returns with range outside [r_min, r_max] are dropped. */
+typedef struct {
+    int32_t H, W;  /* H >= 2, W >= 1 */
+    float el_min, el_max;  /* el_max > el_min */
+    float r_min, r_max;    /* 0 <= r_min <= r_max (r_max may be +inf) */
+} lgsr_scan_grid;
+
+/* Scan to range image (Sec. 3.1; the target image D and G-ICP normal image of Sec. 3.4): each
+ * point (sensor frame) goes to the nearest row and column of `grid`, is kept inside the rows
+ * and the range gates, and the nearest return wins each pixel (equal ranges: the lower point
+ * index).  A pixel takes the winner's range and its normal turned to face the sensor.
+ *   points: DEVICE n x 3 float; normals: DEVICE n x 3 (e.g. the smallest principal axes of
+ *     the tracker's point covariances) or NULL (normal image zero).
+ *   depth: DEVICE H x W (0 = no return); normal: DEVICE H x W x 3 or NULL;
+ *   index: DEVICE H x W int32 (winning point, -1 = none) or NULL.
+ * n < 2^31.  Uses 8 bytes of workspace per pixel.  Errors: EINVAL, ENOMEM, EDEVICE. */
+lgsr_status lgsr_scan_to_range(lgsr_ctx *ctx, int64_t n, const float *points, const float *normals,
+                               const lgsr_scan_grid *grid, float *depth, float *normal, int32_t *index);
+
+/* Target covariances for covariance-weighted G-ICP (Sec. 3.2): per surfel
+ * Sigma = R diag(s_x^2, s_y^2, eps^2) R^T, R = [a b n] the rotation of the normalised
+ * quaternion, s = exp(log_scales), eps the thickness along the normal (not given numerically
+ * in the paper); a zero quaternion gives a zero covariance.
+ *   quats: DEVICE n x 4 (w, x, y, z), 16-byte aligned; log_scales: DEVICE n x 2, 8-byte aligned.
+ *   cov: DEVICE n x 6 = (xx, xy, xz, yy, yz, zz), world frame, 8-byte aligned.
+ * Errors: EINVAL, EDEVICE. */
+lgsr_status lgsr_target_cov(lgsr_ctx *ctx, int64_t n, const float *quats, const float *log_scales, float eps,
+                            float *cov);
+
 /* Backward of the forward that produced `state`: given dL/d(depth, opacity, normal) per
  * ray, write dL/d every surfel parameter into `out` (overwritten; zero for surfels that
  * render nothing) and dL/d(rho, omega) into grad_pose (DEVICE float[6], overwritten).

@@ -808,15 +808,18 @@ int lgsr_ref_scan_to_range(int64_t n, const double *points, const double *normal
 }
 
 /* Sec. 3.2, target covariance: Sigma = R diag(s_x^2, s_y^2, eps^2) R^T with R = [a b n]
- * the rotation of the normalised quaternion (w, x, y, z) and s = exp(log_scales).
- * cov: n x 6 = (xx, xy, xz, yy, yz, zz). */
+ * the rotation of the normalised quaternion (w, x, y, z) and s = exp(log_scales); a zero
+ * quaternion (no orientation) gives a zero covariance.  cov: n x 6 = (xx, xy, xz, yy, yz, zz). */
 int lgsr_ref_target_cov(int64_t n, const double *quats, const double *log_scales, double eps, double *cov)
 {
     if (n < 0 || !(eps >= 0) || (n > 0 && (!quats || !log_scales || !cov))) return -1;
     for (int64_t i = 0; i < n; ++i) {
         const double *q = quats + 4 * i;
         double qn = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
-        if (!(qn > 0)) return -1;
+        if (!(qn > 0)) { /* no orientation: no target */
+            for (int c = 0; c < 6; ++c) cov[6 * i + c] = 0;
+            continue;
+        }
         double w = q[0] / qn, x = q[1] / qn, y = q[2] / qn, z = q[3] / qn;
         double R[3][3] = {{1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)},
                           {2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)},

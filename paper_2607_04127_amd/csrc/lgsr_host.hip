@@ -111,6 +111,7 @@ struct lgsr_ctx {
     Lane lanes[kLanes];
     hipEvent_t batch_start = nullptr;
     DevBuf counters;             // lgsr_query's counters
+    DevBuf scan_slots;           // lgsr_scan_to_range's per-pixel keys
     uint32_t *pinned = nullptr;  // host-pinned read-back of lgsr_query
     std::vector<lgsr_state *> pool;  // freed states kept for reuse
     std::vector<lgsr_state *> all;   // every state allocated by this context
@@ -270,7 +271,7 @@ size_t state_bytes(const lgsr_state *s)
 
 size_t ctx_bytes(const lgsr_ctx *c)
 {
-    size_t b = c->counters.cap + state_bytes(&c->scratch_state);
+    size_t b = c->counters.cap + c->scan_slots.cap + state_bytes(&c->scratch_state);
     for (const Lane &L : c->lanes) {
         b += L.recgrad.cap + L.partials.cap + L.pose_partials.cap + L.gb0.cap + L.gb1.cap;
         for (const lgsr_state *st : L.batch_states) b += state_bytes(st);
@@ -570,6 +571,7 @@ void lgsr_destroy(lgsr_ctx *ctx)
     free_state_buffers(&ctx->scratch_state);
     for (Lane &L : ctx->lanes) free_lane(L);
     release(ctx->counters);
+    release(ctx->scan_slots);
     if (ctx->batch_start) (void)hipEventDestroy(ctx->batch_start);
     for (auto &pe : ctx->ev_pending) {
         (void)hipEventDestroy(pe.second.first);
@@ -712,6 +714,54 @@ lgsr_status lgsr_scale_reg(lgsr_ctx *ctx, int64_t n, const float *log_scales, fl
     HIP_TRY(launch_scale_reg(n, log_scales, lambda_s, s_max, as<float>(L.partials), loss_out, grad_log_scales,
                              L.stream),
             "scale regulariser");
+    return LGSR_OK;
+}
+
+lgsr_status lgsr_scan_to_range(lgsr_ctx *ctx, int64_t n, const float *points, const float *normals,
+                               const lgsr_scan_grid *grid, float *depth, float *normal, int32_t *index)
+{
+    if (!ctx) return LGSR_EINVAL;
+    if (n < 0 || n > (int64_t)0x7FFFFFFF) return fail(ctx, LGSR_EINVAL, "point count %lld out of range", (long long)n);
+    if (n > 0 && !points) return fail(ctx, LGSR_EINVAL, "points is NULL");
+    if (!grid) return fail(ctx, LGSR_EINVAL, "grid is NULL");
+    if (grid->H < 2 || grid->W < 1 || grid->H > 32768 || grid->W > 32768)
+        return fail(ctx, LGSR_EINVAL, "grid %d x %d out of range (H in [2, 32768], W in [1, 32768])", grid->H,
+                    grid->W);
+    if (!std::isfinite(grid->el_min) || !std::isfinite(grid->el_max) || !(grid->el_max > grid->el_min))
+        return fail(ctx, LGSR_EINVAL, "need finite el_min < el_max");
+    if (!(grid->r_min >= 0.f) || std::isnan(grid->r_max) || !(grid->r_max >= grid->r_min))
+        return fail(ctx, LGSR_EINVAL, "need 0 <= r_min <= r_max");
+    if (!depth) return fail(ctx, LGSR_EINVAL, "depth is NULL");
+    HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
+    Lane &L = ctx->lanes[0];
+    const int64_t P = (int64_t)grid->H * grid->W;
+    HIP_TRY(ensure(ctx->scan_slots, (size_t)P * sizeof(unsigned long long)), "alloc scan workspace");
+    ScanGridF g;
+    g.H = grid->H;
+    g.W = grid->W;
+    g.el_max = grid->el_max;
+    g.rows_per_rad = (float)((double)(grid->H - 1) / ((double)grid->el_max - (double)grid->el_min));
+    g.cols_per_rad = (float)((double)grid->W / 6.283185307179586476925286766559);
+    g.r_min = grid->r_min;
+    g.r_max = grid->r_max;
+    HIP_TRY(launch_scan_to_range(n, points, normals, g, as<unsigned long long>(ctx->scan_slots), depth, normal, index,
+                                 L.stream),
+            "scan to range image");
+    return LGSR_OK;
+}
+
+lgsr_status lgsr_target_cov(lgsr_ctx *ctx, int64_t n, const float *quats, const float *log_scales, float eps,
+                            float *cov)
+{
+    if (!ctx) return LGSR_EINVAL;
+    if (n < 0) return fail(ctx, LGSR_EINVAL, "n must be >= 0");
+    if (n > 0 && (!quats || !log_scales || !cov)) return fail(ctx, LGSR_EINVAL, "an array is NULL");
+    if (!(eps >= 0.f) || !std::isfinite(eps)) return fail(ctx, LGSR_EINVAL, "eps must be finite and >= 0");
+    if ((reinterpret_cast<uintptr_t>(quats) & 15u) || (reinterpret_cast<uintptr_t>(log_scales) & 7u) ||
+        (reinterpret_cast<uintptr_t>(cov) & 7u))
+        return fail(ctx, LGSR_EINVAL, "quats must be 16-byte, log_scales and cov 8-byte aligned");
+    HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
+    HIP_TRY(launch_target_cov(n, quats, log_scales, eps, cov, ctx->lanes[0].stream), "target covariance");
     return LGSR_OK;
 }
 

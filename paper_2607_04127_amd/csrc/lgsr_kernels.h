@@ -92,6 +92,16 @@ int scale_reg_blocks(int64_t n);
 hipError_t launch_scale_reg(int64_t n, const float *log_scales, float lambda_s, float s_max, float *partials,
                             float *loss_out, float *grad_log_scales, hipStream_t s);
 
+// ---- scan.hip ----
+struct ScanGridF {
+    int H, W;
+    float el_max, rows_per_rad, cols_per_rad, r_min, r_max;
+};
+hipError_t launch_scan_to_range(int64_t n, const float *pts, const float *nrm, const ScanGridF &g,
+                                unsigned long long *slots, float *depth, float *normal, int32_t *index, hipStream_t s);
+hipError_t launch_target_cov(int64_t n, const float *quats, const float *log_scales, float eps, float *cov,
+                             hipStream_t s);
+
 // ---- chain.hip ----
 int chain_blocks(int64_t n);
 // reads the record-gradient slots of surfels with a non-empty ray rectangle and clears them

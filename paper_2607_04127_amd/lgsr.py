@@ -22,7 +22,8 @@ _STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ECAPACITY", 
 EXPORTS = ("lgsr_default_opts", "lgsr_default_loss_weights", "lgsr_create", "lgsr_destroy", "lgsr_set_stream",
            "lgsr_last_error", "lgsr_forward", "lgsr_loss", "lgsr_backward", "lgsr_state_free", "lgsr_query",
            "lgsr_profile", "lgsr_profile_read", "lgsr_sync", "lgsr_state_bytes", "lgsr_adam_step",
-           "lgsr_render_batch", "lgsr_default_objective_weights", "lgsr_objective", "lgsr_scale_reg")
+           "lgsr_render_batch", "lgsr_default_objective_weights", "lgsr_objective", "lgsr_scale_reg",
+           "lgsr_scan_to_range", "lgsr_target_cov")
 STAGES = ("project", "scan", "readback", "emit", "tile_sort", "raster_fwd", "loss", "bwd_prep", "raster_bwd",
           "chain")
 
@@ -60,6 +61,11 @@ class LossWeights(ctypes.Structure):
 
 class ObjectiveWeights(ctypes.Structure):
     _fields_ = [(k, ctypes.c_float) for k in ("w_depth", "lambda_alpha", "eps", "lambda_n", "lambda_ng", "lambda_ns")]
+
+
+class ScanGrid(ctypes.Structure):
+    _fields_ = [("H", ctypes.c_int32), ("W", ctypes.c_int32), ("el_min", ctypes.c_float), ("el_max", ctypes.c_float),
+                ("r_min", ctypes.c_float), ("r_max", ctypes.c_float)]
 
 
 class FrameGrad(ctypes.Structure):
@@ -118,9 +124,12 @@ def lib():
         L.lgsr_default_objective_weights.restype = None
         L.lgsr_objective.argtypes = [vp, P(Beams), P(Frame), vp, vp, P(ObjectiveWeights), vp, P(FrameGrad)]
         L.lgsr_scale_reg.argtypes = [vp, ctypes.c_int64, vp, ctypes.c_float, ctypes.c_float, vp, vp]
+        L.lgsr_scan_to_range.argtypes = [vp, ctypes.c_int64, vp, vp, P(ScanGrid), vp, vp, vp]
+        L.lgsr_target_cov.argtypes = [vp, ctypes.c_int64, vp, vp, ctypes.c_float, vp]
         for name in ("lgsr_create", "lgsr_set_stream", "lgsr_forward", "lgsr_loss", "lgsr_backward", "lgsr_query",
                      "lgsr_profile", "lgsr_profile_read", "lgsr_sync", "lgsr_state_bytes", "lgsr_adam_step",
-                     "lgsr_render_batch", "lgsr_objective", "lgsr_scale_reg"):
+                     "lgsr_render_batch", "lgsr_objective", "lgsr_scale_reg", "lgsr_scan_to_range",
+                     "lgsr_target_cov"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -347,6 +356,44 @@ def lgsr_scale_reg(ctx: Context, log_scales: torch.Tensor, lambda_s: float = 10.
     ctx._check(lib().lgsr_scale_reg(ctx.handle, n, _ptr(log_scales), float(lambda_s), float(s_max), _ptr(loss_out),
                                     _ptr(grad_log_scales)))
     return loss_out
+
+
+def lgsr_scan_to_range(ctx: Context, points: torch.Tensor, H: int, W: int, el_min: float, el_max: float,
+                       r_min: float = 0.0, r_max: float = float("inf"), normals: torch.Tensor | None = None,
+                       out: dict | None = None):
+    """Spherical range image of a scan (angles in radians): dict(depth (H,W), normal (H,W,3),
+    index (H,W) int32: the winning point or -1)."""
+    d = ctx.device
+    n = points.shape[0]
+    _dev(points, "points", (n, 3), d)
+    if normals is not None:
+        _dev(normals, "normals", (n, 3), d)
+    if out is None:
+        out = dict(depth=torch.empty((H, W), device=d), normal=torch.empty((H, W, 3), device=d),
+                   index=torch.empty((H, W), device=d, dtype=torch.int32))
+    _dev(out["depth"], "depth", (H, W), d)
+    _dev(out["normal"], "normal", (H, W, 3), d)
+    _dev(out["index"], "index", (H, W), d, torch.int32)
+    g = ScanGrid(H, W, el_min, el_max, r_min, r_max)
+    ctx._stream()
+    ctx._check(lib().lgsr_scan_to_range(ctx.handle, n, _ptr(points), _ptr(normals), ctypes.byref(g),
+                                        _ptr(out["depth"]), _ptr(out["normal"]), _ptr(out["index"])))
+    return out
+
+
+def lgsr_target_cov(ctx: Context, quats: torch.Tensor, log_scales: torch.Tensor, eps: float = 0.01,
+                    out: torch.Tensor | None = None):
+    """Surfel target covariances (n, 6): xx, xy, xz, yy, yz, zz."""
+    d = ctx.device
+    n = quats.shape[0]
+    _dev(quats, "quats", (n, 4), d)
+    _dev(log_scales, "log_scales", (n, 2), d)
+    if out is None:
+        out = torch.empty((n, 6), device=d)
+    _dev(out, "cov", (n, 6), d)
+    ctx._stream()
+    ctx._check(lib().lgsr_target_cov(ctx.handle, n, _ptr(quats), _ptr(log_scales), float(eps), _ptr(out)))
+    return out
 
 
 def lgsr_backward(ctx: Context, state: State, grad: dict, out: dict | None = None,

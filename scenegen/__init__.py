@@ -17,5 +17,6 @@ from .scene import (  # noqa: F401
     raycast,
     sample_surfels,
     synthetic_frame,
+    synthetic_scan,
     targets_for_pose,
 )

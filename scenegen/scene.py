@@ -421,6 +421,40 @@ def synthetic_frame(scene: Scene, pose: np.ndarray, row_sincos, col_sincos, seed
     return d.astype(np.float32), op.astype(np.float32), nrm.astype(np.float32)
 
 
+def synthetic_scan(scene: Scene, pose: np.ndarray, H: int, W: int, el_min_deg: float, el_max_deg: float,
+                   seed: int, az_jitter: float = 0.3, el_jitter: float = 0.05, extra_fraction: float = 0.2,
+                   range_noise: float = 0.01):
+    """A spinning-LiDAR scan of the scene in the sensor frame: one ray per beam and column,
+    azimuth jittered by U(-az_jitter, az_jitter) of a column and elevation by
+    U(-el_jitter, el_jitter) of a row, range = exact raycast times (1 + N(0, range_noise)),
+    returns beyond the scene dropped; plus extra_fraction more points as second returns in
+    front of the first along random rays (a partial occluder between 20% and 95% of the
+    range).  Normals: the surface normals at the hits with random signs (the orientation a
+    covariance's principal axis has).  float32 (n, 3) points and normals, shuffled."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    P = np.asarray(pose, np.float64)
+    R, t = P[:, :3], P[:, 3]
+    phi_max, phi_min = math.radians(el_max_deg), math.radians(el_min_deg)
+    k = np.repeat(np.arange(H), W).astype(np.float64)
+    j = np.tile(np.arange(W), H).astype(np.float64)
+    el = phi_max - (k + rng.uniform(-el_jitter, el_jitter, k.size)) * (phi_max - phi_min) / max(H - 1, 1)
+    az = 2.0 * np.pi * (j + rng.uniform(-az_jitter, az_jitter, j.size)) / W
+    d = np.stack([np.cos(el) * np.cos(az), np.cos(el) * np.sin(az), np.sin(el)], 1)
+    tt, nw = raycast(scene, np.broadcast_to(t, d.shape), d @ R.T)
+    keep = np.isfinite(tt) & (tt > 0)
+    r = tt[keep] * (1.0 + rng.normal(0.0, range_noise, keep.sum()))
+    pts = r[:, None] * d[keep]
+    nrm = (nw[keep] @ R) * rng.choice([-1.0, 1.0], size=(keep.sum(), 1))
+    m = int(round(extra_fraction * pts.shape[0]))
+    if m:
+        src = rng.integers(0, pts.shape[0], m)
+        pts = np.concatenate([pts, pts[src] * rng.uniform(0.2, 0.95, (m, 1))])
+        v = rng.normal(size=(m, 3))
+        nrm = np.concatenate([nrm, v / np.linalg.norm(v, axis=1, keepdims=True)])
+    perm = rng.permutation(pts.shape[0])
+    return pts[perm].astype(np.float32), nrm[perm].astype(np.float32)
+
+
 # --------------------------------------------------------------------------------------
 # named workloads
 # --------------------------------------------------------------------------------------
