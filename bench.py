@@ -40,18 +40,18 @@ PEAK_HBM_GBS = 8000.0
 # WRITE_SIZE per dispatch, each scaled by what the counter reads for a plain 256 MiB device
 # copy (profiles/pmc_traffic_raster_bwd_block64x1024_300k.md).  Valid only for the kernel
 # sources they were taken with (digest below); reported as null once those change.
-TRAFFIC_RASTER_BWD = dict(bytes=38259330,
-                          sources_sha256="2223136e58d47cf7d18d911aee730a3956bf1395255dd913fff8b4e1bd08edbe")
+TRAFFIC_RASTER_BWD = dict(bytes=38258365,
+                          sources_sha256="385573ddeb1526b3ad5adb0f6fa3014189673255d9a032b0190f4098e8769505")
 
 
 def _sources_digest() -> str:
+    """Digest of the sources raster_bwd is compiled from."""
     import hashlib
     d = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2607_04127_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
-        if name.endswith((".hip", ".h")):
-            with open(os.path.join(csrc, name), "rb") as f:
-                d.update(name.encode() + b"\0" + f.read())
+    for name in ("raster.hip", "lgsr_internal.h"):
+        with open(os.path.join(csrc, name), "rb") as f:
+            d.update(name.encode() + b"\0" + f.read())
     return d.hexdigest()
 
 
@@ -182,6 +182,8 @@ def main():
     p50 = float(np.percentile(step_ms, 50))
     p99 = float(np.percentile(step_ms, 99))
 
+    aux = aux_kernels(ctx, w, S, rows, cols, pose, frame, td, tn, args.steps)
+
     svc = None
     if args.service_requests > 0:
         svc = service_phase(ctx, w, S, rows, cols, args.service_requests)
@@ -212,6 +214,7 @@ def main():
                    "batched_latency_ms_p50": svc["batched"]["p50_ms"] if svc else None,
                    "batched_latency_ms_p99": svc["batched"]["p99_ms"] if svc else None},
         "service": svc,
+        "aux_kernels": aux,
         "roofline": {"kernel": "raster_bwd", "bound": "alu", "achieved": round(achieved, 3),
                      "peak": round(PEAK_FP32_TFLOPS, 1), "unit": "TFLOP/s",
                      "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
@@ -228,6 +231,73 @@ def main():
     }
     print(json.dumps(out), flush=True)
     ctx.close()
+
+
+def _time_us(fn, reps):
+    """Mean microseconds per call of fn over reps calls, HIP events on torch's current stream
+    (the stream the library issues on)."""
+    import torch
+    fn()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    a.record()
+    for _ in range(reps):
+        fn()
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) * 1e3 / reps
+
+
+def aux_kernels(ctx, w, S, rows, cols, pose, frame, td, tn, reps):
+    """The kernels beside the rendering path on the benchmark's shapes, each against the HBM
+    roofline with its algorithmic bytes: the full objective of Eq. 13 on the 64 x 1024 frame,
+    the scale regulariser and the target covariances over the 300k surfels, and the
+    projection of a 64 x 1024 scan of the same street block."""
+    import numpy as np
+    import torch
+
+    import scenegen
+    from paper_2607_04127_amd import lgsr
+
+    dev = rows.device
+    H, W = rows.shape[0], cols.shape[0]
+    rays, n = H * W, S["means"].shape[0]
+    reps = max(reps, 20)
+    out = {}
+
+    def entry(us, nbytes, note):
+        gbs = nbytes / (us * 1e-6) / 1e9
+        return dict(us_per_call=round(us, 3), bytes=int(nbytes), GBps=round(gbs, 1),
+                    frac_of_8TBps=round(gbs / PEAK_HBM_GBS, 4), bytes_model=note)
+
+    lgsr.lgsr_forward(ctx, S, pose, rows, cols, out=frame, want_state=False)
+    Lo = torch.empty(8, device=dev)
+    go = dict(depth=torch.empty((H, W), device=dev), opacity=torch.empty((H, W), device=dev),
+              normal=torch.empty((H, W, 3), device=dev))
+    wts = lgsr.default_objective_weights()
+    us = _time_us(lambda: lgsr.lgsr_objective(ctx, frame, rows, cols, td, tn, wts, loss_out=Lo, grad_out=go), reps)
+    out["objective"] = entry(us, rays * (2 * 36 + 20), "per ray: depth, opacity, normal, targets (36 B) read "
+                                                       "by both passes, 20 B of gradient written")
+    ls = S["log_scales"]
+    gls = torch.zeros_like(ls)
+    Ls = torch.empty(1, device=dev)
+    us = _time_us(lambda: lgsr.lgsr_scale_reg(ctx, ls, 10.0, 1.0, loss_out=Ls, grad_log_scales=gls), reps)
+    out["scale_reg"] = entry(us, n * 24, "per surfel: 8 B log-scales read, 16 B gradient read and written")
+    cov = torch.empty((n, 6), device=dev)
+    us = _time_us(lambda: lgsr.lgsr_target_cov(ctx, S["quats"], ls, 0.01, out=cov), reps)
+    out["target_cov"] = entry(us, n * 48, "per surfel: 16 B quaternion and 8 B log-scales read, 24 B written")
+    pts, nrm = scenegen.synthetic_scan(w["scene"], w["pose"], H, W, -22.5, 22.5, seed=7)
+    pts_d, nrm_d = torch.from_numpy(pts).to(dev), torch.from_numpy(nrm).to(dev)
+    so = dict(depth=torch.empty((H, W), device=dev), normal=torch.empty((H, W, 3), device=dev),
+              index=torch.empty((H, W), device=dev, dtype=torch.int32))
+    el = (np.radians(-22.5), np.radians(22.5))
+    us = _time_us(lambda: lgsr.lgsr_scan_to_range(ctx, pts_d, H, W, el[0], el[1], 0.5, 80.0, normals=nrm_d, out=so),
+                  reps)
+    hits = int((so["index"] >= 0).sum())
+    out["scan_to_range"] = entry(us, pts.shape[0] * 20 + rays * 44 + hits * 24,
+                                 f"{pts.shape[0]} points: 12 B read, one 8 B atomic; per pixel 8 B key "
+                                 f"filled and read, 20 B written; per return 24 B of the winner gathered")
+    return out
 
 
 def service_phase(ctx, w, S, rows, cols, n_requests, n_poses=4, seed=45):
