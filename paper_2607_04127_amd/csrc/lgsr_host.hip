@@ -77,7 +77,7 @@ struct lgsr_state {
     lgsr_ctx *ctx = nullptr;
     bool live = false;
     // forward products kept for the backward
-    DevBuf recs, rects, pk, pv, pk2, pv2, ranges, st0, st1, pose, chunks, chunk_base, slots, fixA, fixB;
+    DevBuf recs, rects, pk, pv, ranges, long_tiles, st0, st1, pose, chunks, chunk_base, slots, fixA, fixB;
     // per-forward scratch: range keys, per-(tile, shard) counts and cursors, read-back words
     DevBuf keys, cnt, offs, counters;
     uint32_t *pinned = nullptr;  // host-pinned copy of counters[0..2]
@@ -202,7 +202,7 @@ lgsr_state *take_state(lgsr_ctx *ctx)
 
 void free_state_buffers(lgsr_state *s)
 {
-    release(s->recs); release(s->rects); release(s->pk); release(s->pv); release(s->pk2); release(s->pv2);
+    release(s->recs); release(s->rects); release(s->pk); release(s->pv); release(s->long_tiles);
     release(s->ranges); release(s->st0); release(s->st1); release(s->pose);
     release(s->chunks); release(s->chunk_base); release(s->slots); release(s->fixA); release(s->fixB);
     release(s->keys); release(s->cnt); release(s->offs); release(s->counters);
@@ -264,7 +264,7 @@ struct Stage {
 
 size_t state_bytes(const lgsr_state *s)
 {
-    return s->recs.cap + s->rects.cap + s->pk.cap + s->pv.cap + s->pk2.cap + s->pv2.cap + s->ranges.cap +
+    return s->recs.cap + s->rects.cap + s->pk.cap + s->pv.cap + s->long_tiles.cap + s->ranges.cap +
            s->st0.cap + s->st1.cap + s->pose.cap + s->chunks.cap + s->chunk_base.cap + s->slots.cap + s->fixA.cap +
            s->fixB.cap + s->keys.cap + s->cnt.cap + s->offs.cap + s->counters.cap;
 }
@@ -366,6 +366,7 @@ lgsr_status forward_begin(lgsr_ctx *ctx, lgsr_state *S, const lgsr_surfels *surf
     HIP_TRY(ensure(S->keys, nn * 4), "alloc keys");
     HIP_TRY(ensure(S->cnt, (size_t)g.T * kShards * 4), "alloc tile counts");
     HIP_TRY(ensure(S->offs, (size_t)g.T * kShards * 4), "alloc tile cursors");
+    HIP_TRY(ensure(S->long_tiles, (size_t)g.T * 4), "alloc long tile list");
     HIP_TRY(ensure(S->counters, 16), "alloc counters");
     if (!S->pinned) HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&S->pinned), 16, hipHostMallocDefault), "pinned");
     if (!S->rb) HIP_TRY(hipEventCreateWithFlags(&S->rb, hipEventDisableTiming), "event");
@@ -379,11 +380,12 @@ lgsr_status forward_begin(lgsr_ctx *ctx, lgsr_state *S, const lgsr_surfels *surf
     }
     {
     Stage st_(ctx, LGSR_STAGE_SCAN, s);
-    HIP_TRY(launch_tile_scan(as<uint32_t>(S->cnt), g.T, as<uint2>(S->ranges), as<uint32_t>(S->offs), counters, s),
+    HIP_TRY(launch_tile_scan(as<uint32_t>(S->cnt), g.T, as<uint2>(S->ranges), as<uint32_t>(S->offs), counters,
+                             as<uint32_t>(S->long_tiles), s),
             "tile scan");
     }
     Stage st_(ctx, LGSR_STAGE_READBACK, s);
-    HIP_TRY(hipMemcpyAsync(S->pinned, counters, 3 * sizeof(uint32_t), hipMemcpyDeviceToHost, s), "readback");
+    HIP_TRY(hipMemcpyAsync(S->pinned, counters, 4 * sizeof(uint32_t), hipMemcpyDeviceToHost, s), "readback");
     HIP_TRY(hipEventRecord(S->rb, s), "readback event");
     return LGSR_OK;
 }
@@ -402,11 +404,11 @@ lgsr_status forward_end(lgsr_ctx *ctx, lgsr_state *S, const lgsr_frame *out, hip
     if (P > (int64_t)0x7FFFFFFF) return fail(ctx, LGSR_ECAPACITY, "too many (surfel, tile) pairs");
     const size_t pp = (size_t)(P > 0 ? P : 1);
     HIP_TRY(ensure(S->pv, pp * 4), "alloc pairs");
-    const bool streamed = longest > tile_sort_capacity();
-    if (streamed) {
-        HIP_TRY(ensure(S->pk, pp * 4), "alloc pairs");
-        HIP_TRY(ensure(S->pk2, pp * 4), "alloc pairs");
-        HIP_TRY(ensure(S->pv2, pp * 4), "alloc pairs");
+    const int n_long = (int)S->pinned[3];
+    const int nch = tile_sort_chunks(longest);
+    if (n_long > 0) {
+        if ((int64_t)n_long * nch > (int64_t)0x7FFFFFFF) return fail(ctx, LGSR_ECAPACITY, "tile lists too long");
+        HIP_TRY(ensure(S->pk, pp * 8), "alloc sort workspace");
     }
     S->ids = as<uint32_t>(S->pv);
     if (P > 0) {
@@ -416,8 +418,8 @@ lgsr_status forward_end(lgsr_ctx *ctx, lgsr_state *S, const lgsr_frame *out, hip
         }
         Stage st_(ctx, LGSR_STAGE_TILE_SORT, s);
         HIP_TRY(launch_tile_sort(as<uint2>(S->ranges), g.T, as<uint32_t>(S->keys), n, S->ids,
-                                 streamed ? as<uint32_t>(S->pk) : nullptr, streamed ? as<uint32_t>(S->pk2) : nullptr,
-                                 streamed ? as<uint32_t>(S->pv2) : nullptr, s),
+                                 as<uint32_t>(S->long_tiles), n_long, nch,
+                                 n_long > 0 ? as<unsigned long long>(S->pk) : nullptr, s),
                 "tile sort");
     }
     const int seg = chunk_size(P, S->chunk_req);

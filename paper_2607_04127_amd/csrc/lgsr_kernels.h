@@ -10,19 +10,23 @@
 namespace lgsr {
 
 // ---- sort.hip ----
-// Lists longer than this are sorted through the spare pair buffers (k0, k1, v1).
+// Lists longer than this are sorted in chunks of this size and merged.
 int tile_sort_capacity();
+// Chunks of a list of `longest` entries.
+int tile_sort_chunks(int64_t longest);
 // cnt, cursor: T x kShards.  ranges[t] = [first, end) of tile t's list and cursor[t kShards
 // + s] = first slot of its shard s, from the exclusive prefix sum of cnt in (tile, shard)
-// order; out (device) receives the total as two 32-bit words (low, high) and the largest
-// tile count.
+// order; out (device, 4 words) receives the total as two 32-bit words (low, high), the
+// largest tile count and the number of tiles longer than tile_sort_capacity(), whose ids go
+// to long_tiles (T words).
 hipError_t launch_tile_scan(const uint32_t *cnt, int T, uint2 *ranges, uint32_t *cursor, uint32_t *out,
-                            hipStream_t s);
+                            uint32_t *long_tiles, hipStream_t s);
 // Orders every tile's list ids[ranges[t].x .. ranges[t].y) by (keys[id], id) ascending
-// (keys has n entries).  k0, k1, v1 (P words each) are needed only when some list is longer
-// than tile_sort_capacity(); otherwise they may be null.
+// (keys has n entries).  Tiles longer than tile_sort_capacity(): the n_long of them in
+// long_tiles, nch = tile_sort_chunks(longest), tmp (P x 8 bytes); tmp may be null when
+// n_long is 0.
 hipError_t launch_tile_sort(const uint2 *ranges, int T, const uint32_t *keys, int64_t n, uint32_t *ids,
-                            uint32_t *k0, uint32_t *k1, uint32_t *v1, hipStream_t s);
+                            const uint32_t *long_tiles, int n_long, int nch, unsigned long long *tmp, hipStream_t s);
 
 // ---- project.hip ----
 struct SurfelPtrs {

@@ -4,10 +4,13 @@
 // The compositing order of Sec. 3.4 (ascending sensor range, ties by surfel index) is then
 // established per tile by one workgroup: a least-significant-digit radix sort with 9-bit
 // digits on (range bits - tile minimum), stable within the workgroup, kept in registers and
-// LDS when the list fits (kTsCap entries) and streamed through the two spare pair buffers
-// otherwise.  Equal range keys are put in index order by sorting on the index first and
-// then again on the range (both passes stable), which happens only for tiles that hold
-// exactly equal ranges.
+// LDS (up to kTsCap entries).  Equal range keys are put in index order by sorting on the
+// index first and then again on the range (both passes stable), which happens only for tiles
+// that hold exactly equal ranges.  A longer list is cut into kTsCap-entry chunks, each sorted
+// the same way by a workgroup of its own into packed (range << 32 | index) keys; every entry
+// then finds its place as its position in its chunk plus, for each other chunk, the number of
+// keys below it there (a binary search).  Packed keys are unique within a tile, so the
+// merged order is exactly (range, index).
 #include "lgsr_internal.h"
 #include "lgsr_kernels.h"
 
@@ -210,8 +213,11 @@ __device__ __forceinline__ bool resident_has_ties(TileSortSmem &sm, const uint32
     return __syncthreads_or(tie) != 0;
 }
 
+// Sorts the m entries of ids (m <= kTsCap) and writes the sorted ids back into ids, or, with
+// kPacked, the sorted (range << 32 | index) keys into packed instead.
+template <bool kPacked>
 __device__ void sort_resident(TileSortSmem &sm, const uint32_t *__restrict__ keys, int64_t n,
-                              uint32_t *__restrict__ ids, int m)
+                              uint32_t *__restrict__ ids, int m, unsigned long long *__restrict__ packed)
 {
     const int w = threadIdx.x >> 6;
     const int R = (m + kTsThreads - 1) / kTsThreads;
@@ -247,100 +253,16 @@ __device__ void sort_resident(TileSortSmem &sm, const uint32_t *__restrict__ key
 #pragma unroll
     for (int r = 0; r < kTsItems; ++r) {
         const int j = j0 + r * 64;
-        if (r < R && j < m) ids[j] = vx[r];
-    }
-}
-
-// ---- streaming path: lists longer than kTsCap, one workgroup, chunks through LDS ----
-
-// Global writes of one phase become visible to the workgroup's reads of the next.
-__device__ __forceinline__ void phase_barrier()
-{
-    __threadfence();
-    __syncthreads();
-    __threadfence();
-}
-
-__device__ void stream_pass(TileSortSmem &sm, const uint32_t *sk, const uint32_t *sv, uint32_t *dk, uint32_t *dv,
-                            int m, bool by_val, uint32_t base, int shift)
-{
-    const int t = threadIdx.x, w = t >> 6;
-    for (int i = t; i < kDigits; i += kTsThreads) sm.dbase[i] = 0u;
-    __syncthreads();
-    for (int j = t; j < m; j += kTsThreads) atomicAdd(&sm.dbase[digit_of(by_val ? sv[j] : sk[j], base, shift)], 1u);
-    __syncthreads();
-    uint32_t run = t < kDigits ? sm.dbase[t] : 0u;
-    run = block_excl_scan(sm, run);
-    for (int c0 = 0; c0 < m; c0 += kTsCap) {
-        const int mc = min(kTsCap, m - c0);
-        const int R = (mc + kTsThreads - 1) / kTsThreads;
-        const int j0 = w * R * 64 + lane_id();
-        uint32_t kx[kTsItems], vx[kTsItems], off[kTsItems];
-#pragma unroll
-        for (int r = 0; r < kTsItems; ++r) {
-            const int j = j0 + r * 64;
-            const bool ok = r < R && j < mc;
-            kx[r] = ok ? sk[c0 + j] : 0u;
-            vx[r] = ok ? sv[c0 + j] : 0u;
+        if (r < R && j < m) {
+            if constexpr (kPacked)
+                packed[j] = ((unsigned long long)kx[r] << 32) | vx[r];
+            else
+                ids[j] = vx[r];
         }
-        const uint32_t total = rank_chunk(sm, kx, vx, off, mc, R, by_val, base, shift);
-        if (t < kDigits) sm.dbase[t] = run;
-        __syncthreads();
-#pragma unroll
-        for (int r = 0; r < kTsItems; ++r) {
-            if (r < R && j0 + r * 64 < mc) {
-                const uint32_t d = digit_of(by_val ? vx[r] : kx[r], base, shift);
-                const uint32_t dst = min(sm.dbase[d] + (uint32_t)sm.wcnt[w][d] + off[r], (uint32_t)(m - 1));
-                dk[dst] = kx[r];
-                dv[dst] = vx[r];
-            }
-        }
-        if (t < kDigits) run += total;
-        __syncthreads();
-    }
-    phase_barrier();
-}
-
-__device__ void sort_streaming(TileSortSmem &sm, const uint32_t *__restrict__ keys, int64_t n, uint32_t *ids,
-                               uint32_t *k0, uint32_t *k1, uint32_t *v1, int m)
-{
-    const int t = threadIdx.x;
-    uint32_t kmin = 0xFFFFFFFFu, kmax = 0u, vmin = 0xFFFFFFFFu, vmax = 0u;
-    for (int j = t; j < m; j += kTsThreads) {
-        const uint32_t v = ids[j], k = (int64_t)v < n ? keys[v] : 0xFFFFFFFFu;
-        k0[j] = k;
-        kmin = min(kmin, k);
-        kmax = max(kmax, k);
-        vmin = min(vmin, v);
-        vmax = max(vmax, v);
-    }
-    block_minmax(sm, kmin, kmax, vmin, vmax);
-    phase_barrier();
-    // (k0, ids) and (k1, v1) alternate as source and destination
-    uint32_t *sk = k0, *sv = ids, *dk = k1, *dv = v1;
-    auto pass = [&](bool by_val, uint32_t base, int shift) {
-        stream_pass(sm, sk, sv, dk, dv, m, by_val, base, shift);
-        uint32_t *a = sk, *b = sv;
-        sk = dk;
-        sv = dv;
-        dk = a;
-        dv = b;
-    };
-    const int kp = passes_for(kmin, kmax);
-    for (int q = 0; q < kp; ++q) pass(false, kmin, q * kDigitBits);
-    bool tie = false;
-    for (int j = t + 1; j < m; j += kTsThreads) tie |= sk[j - 1] == sk[j];
-    if (__syncthreads_or(tie)) {
-        const int vp = passes_for(vmin, vmax);
-        for (int q = 0; q < vp; ++q) pass(true, vmin, q * kDigitBits);
-        for (int q = 0; q < kp; ++q) pass(false, kmin, q * kDigitBits);
-    }
-    if (sv != ids) {
-        for (int j = t; j < m; j += kTsThreads) ids[j] = sv[j];
     }
 }
 
-// One workgroup per tile; lists longer than kTsCap are left to tile_sort_stream_kernel.
+// One workgroup per tile; lists longer than kTsCap are left to the chunk kernels below.
 __global__ __launch_bounds__(kTsThreads) void tile_sort_kernel(const uint2 *__restrict__ ranges, int T,
                                                                const uint32_t *__restrict__ keys, int64_t n,
                                                                uint32_t *ids)
@@ -351,36 +273,93 @@ __global__ __launch_bounds__(kTsThreads) void tile_sort_kernel(const uint2 *__re
     const uint2 rg = ranges[tile];
     const int m = (int)(rg.y - rg.x);
     if (m <= 1 || m > kTsCap) return;
-    sort_resident(sm, keys, n, ids + rg.x, m);
+    sort_resident<false>(sm, keys, n, ids + rg.x, m, nullptr);
 }
 
-__global__ __launch_bounds__(kTsThreads) void tile_sort_stream_kernel(const uint2 *__restrict__ ranges, int T,
-                                                                      const uint32_t *__restrict__ keys, int64_t n,
-                                                                      uint32_t *ids, uint32_t *k0, uint32_t *k1,
-                                                                      uint32_t *v1)
+// ---- lists longer than kTsCap: chunk sorts, then a merge by rank ----
+
+// Workgroup b sorts chunk b % nch of long tile b / nch (if the list has that many chunks)
+// into packed keys at the chunk's own positions of tmp.
+__global__ __launch_bounds__(kTsThreads) void tile_chunk_sort_kernel(const uint2 *__restrict__ ranges,
+                                                                     const uint32_t *__restrict__ long_tiles, int nch,
+                                                                     const uint32_t *__restrict__ keys, int64_t n,
+                                                                     uint32_t *ids, unsigned long long *tmp)
 {
     __shared__ TileSortSmem sm;
-    const int tile = blockIdx.x;
-    if (tile >= T) return;
+    const uint32_t tile = long_tiles[blockIdx.x / nch];
+    const int c0 = (int)(blockIdx.x % nch) * kTsCap;
     const uint2 rg = ranges[tile];
     const int m = (int)(rg.y - rg.x);
-    if (m <= kTsCap) return;
-    sort_streaming(sm, keys, n, ids + rg.x, k0 + rg.x, k1 + rg.x, v1 + rg.x, m);
+    if (c0 >= m) return;
+    sort_resident<true>(sm, keys, n, ids + rg.x + c0, min(kTsCap, m - c0), tmp + rg.x + c0);
+}
+
+// Number of the len sorted keys of a below x.
+__device__ __forceinline__ int lower_bound_u64(const unsigned long long *__restrict__ a, int len,
+                                               unsigned long long x)
+{
+    int lo = 0;
+    for (int step = 1 << (31 - __clz(max(len, 1))); step > 0; step >>= 1)
+        if (lo + step <= len && a[lo + step - 1] < x) lo += step;
+    return lo;
+}
+
+// Workgroup b places the entries of chunk b % nch of long tile b / nch: final position =
+// position in the chunk + keys below it in every other chunk.  kItems entries per thread
+// search side by side.
+__global__ __launch_bounds__(kTsThreads) void tile_chunk_merge_kernel(const uint2 *__restrict__ ranges,
+                                                                      const uint32_t *__restrict__ long_tiles, int nch,
+                                                                      const unsigned long long *__restrict__ tmp,
+                                                                      uint32_t *__restrict__ ids)
+{
+    const uint32_t tile = long_tiles[blockIdx.x / nch];
+    const int c = (int)(blockIdx.x % nch);
+    const uint2 rg = ranges[tile];
+    const int m = (int)(rg.y - rg.x);
+    const int c0 = c * kTsCap;
+    if (c0 >= m) return;
+    const int mc = min(kTsCap, m - c0);
+    const unsigned long long *list = tmp + rg.x;
+    unsigned long long x[kTsItems];
+    int pos[kTsItems];
+#pragma unroll
+    for (int r = 0; r < kTsItems; ++r) {
+        const int j = (int)threadIdx.x + r * kTsThreads;
+        x[r] = j < mc ? list[c0 + j] : 0ull;
+        pos[r] = j;
+    }
+    const int chunks = (m + kTsCap - 1) / kTsCap;
+    for (int o = 0; o < chunks; ++o) {
+        if (o == c) continue;
+        const int len = min(kTsCap, m - o * kTsCap);
+#pragma unroll
+        for (int r = 0; r < kTsItems; ++r) pos[r] += lower_bound_u64(list + o * kTsCap, len, x[r]);
+    }
+#pragma unroll
+    for (int r = 0; r < kTsItems; ++r) {
+        const int j = (int)threadIdx.x + r * kTsThreads;
+        if (j < mc) ids[rg.x + pos[r]] = (uint32_t)x[r];
+    }
 }
 
 // ---- tile offsets ----
 
 // One workgroup.  cnt holds kShards counts per tile; with o the exclusive prefix sum of all
 // counts in (tile, shard) order: cursor[t kShards + s] = o at that entry, ranges[t] = (o at
-// (t, 0), o at (t + 1, 0)); out[0..1] = total (64-bit), out[2] = largest tile count.
+// (t, 0), o at (t + 1, 0)); out[0..1] = total (64-bit), out[2] = largest tile count, out[3] =
+// number of tiles with more than kTsCap entries, listed (in no particular order) in
+// long_tiles.
 __global__ __launch_bounds__(1024) void tile_scan_kernel(const uint32_t *__restrict__ cnt, int T,
                                                          uint2 *__restrict__ ranges, uint32_t *__restrict__ cursor,
-                                                         uint32_t *__restrict__ out)
+                                                         uint32_t *__restrict__ out, uint32_t *__restrict__ long_tiles)
 {
     static_assert(kShards == 8, "two uint4 loads per tile");
     __shared__ uint64_t wsum[16];
     __shared__ uint32_t wmax[16];
+    __shared__ uint32_t nlong;
     const int t = threadIdx.x, w = t >> 6, l = t & 63;
+    if (t == 0) nlong = 0u;
+    __syncthreads();
     uint64_t carry = 0;
     uint32_t mx = 0;
     for (int first = 0; first < T; first += 1024) {
@@ -396,6 +375,7 @@ __global__ __launch_bounds__(1024) void tile_scan_kernel(const uint32_t *__restr
 #pragma unroll
         for (int k = 0; k < 8; ++k) s += x[k];
         mx = max(mx, (uint32_t)min(s, (uint64_t)0xFFFFFFFFu));
+        if (tile < T && s > (uint64_t)kTsCap) long_tiles[atomicAdd(&nlong, 1u)] = (uint32_t)tile;
         uint64_t inc = s;
 #pragma unroll
         for (int o = 1; o < 64; o <<= 1) {
@@ -437,6 +417,7 @@ __global__ __launch_bounds__(1024) void tile_scan_kernel(const uint32_t *__restr
         out[0] = (uint32_t)carry;
         out[1] = (uint32_t)(carry >> 32);
         out[2] = mx;
+        out[3] = nlong;
     }
 }
 
@@ -447,18 +428,24 @@ __global__ __launch_bounds__(1024) void tile_scan_kernel(const uint32_t *__restr
 int tile_sort_capacity() { return kTsCap; }
 
 hipError_t launch_tile_scan(const uint32_t *cnt, int T, uint2 *ranges, uint32_t *cursor, uint32_t *out,
-                            hipStream_t s)
+                            uint32_t *long_tiles, hipStream_t s)
 {
-    tile_scan_kernel<<<1, 1024, 0, s>>>(cnt, T, ranges, cursor, out);
+    tile_scan_kernel<<<1, 1024, 0, s>>>(cnt, T, ranges, cursor, out, long_tiles);
     return hipGetLastError();
 }
 
-hipError_t launch_tile_sort(const uint2 *ranges, int T, const uint32_t *keys, int64_t n, uint32_t *ids, uint32_t *k0,
-                            uint32_t *k1, uint32_t *v1, hipStream_t s)
+int tile_sort_chunks(int64_t longest) { return (int)((longest + kTsCap - 1) / kTsCap); }
+
+hipError_t launch_tile_sort(const uint2 *ranges, int T, const uint32_t *keys, int64_t n, uint32_t *ids,
+                            const uint32_t *long_tiles, int n_long, int nch, unsigned long long *tmp, hipStream_t s)
 {
     if (T <= 0) return hipSuccess;
     tile_sort_kernel<<<T, kTsThreads, 0, s>>>(ranges, T, keys, n, ids);
-    if (k0 && k1 && v1) tile_sort_stream_kernel<<<T, kTsThreads, 0, s>>>(ranges, T, keys, n, ids, k0, k1, v1);
+    if (n_long > 0 && nch > 1) {
+        const unsigned grid = (unsigned)((int64_t)n_long * nch);
+        tile_chunk_sort_kernel<<<grid, kTsThreads, 0, s>>>(ranges, long_tiles, nch, keys, n, ids, tmp);
+        tile_chunk_merge_kernel<<<grid, kTsThreads, 0, s>>>(ranges, long_tiles, nch, tmp, ids);
+    }
     return hipGetLastError();
 }
 

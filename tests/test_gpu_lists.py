@@ -1,6 +1,6 @@
 """GPU parity of the per-tile list construction: a tile holding more entries than one
-workgroup sorts in registers (the streaming sort), surfels at exactly equal ranges (ordered
-by index on both sides), and a grid with more tiles than the per-workgroup LDS bins."""
+workgroup sorts in registers (sorted in chunks, then merged), surfels at exactly equal ranges
+(ordered by index on both sides), and a grid with more tiles than the per-workgroup LDS bins."""
 import numpy as np
 import pytest
 
@@ -33,7 +33,8 @@ def _crowded_tile(m, seed, dup_frac=0.1):
     rng = np.random.default_rng(seed)
     n_dup = int(m * dup_frac)
     n0 = m - n_dup
-    ranges = 2.0 + 1e-3 * rng.choice(23000, size=n0, replace=False)
+    ranges = 2.0 + 1e-3 * rng.choice(23000, size=n0, replace=False) if n0 <= 23000 else \
+        2.0 + 1e-4 * rng.choice(230000, size=n0, replace=False)
     rr = rng.integers(17, 31, size=n0)
     cc = rng.integers(129, 143, size=n0)
     d = D[rr, cc]
@@ -64,10 +65,10 @@ def _compare_all_rays(fr, of):
     return G.compare_forward(fr, of)
 
 
-@pytest.mark.parametrize("m", [3000, 12000])
+@pytest.mark.parametrize("m", [3000, 12000, 30000])
 def test_crowded_tile_and_equal_ranges(ctx, m):
-    """m = 3000 sorts the tile in registers, m = 12000 exceeds one workgroup's capacity
-    (8192) and takes the streaming sort; both with 10% exact range ties."""
+    """m = 3000 sorts the tile in registers; m = 12000 and 30000 exceed one workgroup's
+    capacity (8192): 2 and 4 chunks sorted apart and merged; all with 10% exact range ties."""
     from paper_2607_04127_amd import lgsr
     wl = _crowded_tile(m, seed=m)
     dw = G.to_dev(wl)
