@@ -306,7 +306,7 @@ __global__ __launch_bounds__(256) void raster_merge_kernel(const uint32_t *__res
     float T = 1.f, A = 0.f, SD = 0.f, SN0 = 0.f, SN1 = 0.f, SN2 = 0.f;
     int K = 0, fix = -1;
     float4 fa = make_float4(0.f, 0.f, 0.f, 0.f), fb = make_float4(0.f, 0.f, 0.f, __int_as_float(-1));
-    constexpr int kB = 8;  // chunks whose slots are loaded together (one memory latency per batch)
+    constexpr int kB = 16;  // chunks whose slots are loaded together (one memory latency per batch)
     for (uint32_t it0 = c0; it0 < c1; it0 += kB) {
         float v[kB][7];
 #pragma unroll
@@ -442,7 +442,7 @@ __global__ __launch_bounds__(256) void raster_bwd_prep_kernel(const uint32_t *__
         for (uint32_t it = c0; it < c1; ++it) slots[slot(it, F_B, L.rt)] = 0.f;
         return;
     }
-    constexpr int kB = 8;  // chunks whose slots are loaded together (one memory latency per batch)
+    constexpr int kB = 16;  // chunks whose slots are loaded together (one memory latency per batch)
     for (uint32_t top = c1; top > c0;) {
         const uint32_t lo = top - c0 > (uint32_t)kB ? top - kB : c0;
         float v[kB][6];
