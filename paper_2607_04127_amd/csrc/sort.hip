@@ -22,6 +22,7 @@ constexpr int kTsItems = 8;
 constexpr int kTsCap = kTsThreads * kTsItems;  // entries sorted without leaving the CU
 constexpr int kDigitBits = 9;
 constexpr int kDigits = 1 << kDigitBits;
+constexpr int kRunMax = 16;  // longest run of equal range keys ordered in place
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
 
@@ -246,9 +247,43 @@ __device__ void sort_resident(TileSortSmem &sm, const uint32_t *__restrict__ key
     const int kp = passes_for(kmin, kmax);
     for (int q = 0; q < kp; ++q) resident_pass(sm, kx, vx, m, R, false, kmin, q * kDigitBits);
     if (resident_has_ties(sm, kx, m, R)) {
-        const int vp = passes_for(vmin, vmax);
-        for (int q = 0; q < vp; ++q) resident_pass(sm, kx, vx, m, R, true, vmin, q * kDigitBits);
-        for (int q = 0; q < kp; ++q) resident_pass(sm, kx, vx, m, R, false, kmin, q * kDigitBits);
+        // Runs of equal keys are adjacent now (sm.key, sm.val hold the sorted list after a
+        // pass).  Short runs are put in index order in place; a run longer than kRunMax (or a
+        // list that needed no pass) takes two more sorts: by index, then again by key.
+        bool long_run = kp == 0;
+        for (int j = threadIdx.x; j < m && kp > 0; j += kTsThreads) {
+            const uint32_t kj = sm.key[j];
+            if ((j > 0 && sm.key[j - 1] == kj) || j + 1 >= m || sm.key[j + 1] != kj) continue;  // not a run start
+            int len = 2;
+            while (len <= kRunMax && j + len < m && sm.key[j + len] == kj) ++len;
+            long_run |= len > kRunMax;
+        }
+        if (__syncthreads_or(long_run)) {
+            const int vp = passes_for(vmin, vmax);
+            for (int q = 0; q < vp; ++q) resident_pass(sm, kx, vx, m, R, true, vmin, q * kDigitBits);
+            for (int q = 0; q < kp; ++q) resident_pass(sm, kx, vx, m, R, false, kmin, q * kDigitBits);
+        } else {
+            for (int j = threadIdx.x; j < m; j += kTsThreads) {
+                const uint32_t kj = sm.key[j];
+                if ((j > 0 && sm.key[j - 1] == kj) || j + 1 >= m || sm.key[j + 1] != kj) continue;
+                int len = 2;
+                while (j + len < m && sm.key[j + len] == kj) ++len;
+                // insertion sort of the run's indices (distinct), len <= kRunMax
+                for (int a = j + 1; a < j + len; ++a) {
+                    const uint32_t v = sm.val[a];
+                    int b = a - 1;
+                    while (b >= j && sm.val[b] > v) {
+                        sm.val[b + 1] = sm.val[b];
+                        --b;
+                    }
+                    sm.val[b + 1] = v;
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int r = 0; r < kTsItems; ++r)
+                if (r < R) vx[r] = sm.val[min(j0 + r * 64, m - 1)];
+        }
     }
 #pragma unroll
     for (int r = 0; r < kTsItems; ++r) {

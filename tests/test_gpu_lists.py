@@ -24,10 +24,11 @@ def ctx():
     c.close()
 
 
-def _crowded_tile(m, seed, dup_frac=0.1):
+def _crowded_tile(m, seed, dup_frac=0.1, dup_one=0):
     """m small surfels in front of the rays of one 16 x 16 tile (rows 16-31, columns
     128-143 of 32 x 256 beams), at distinct ranges on a 1 mm grid, each centred near one
-    ray; the last dup_frac of them repeat an earlier centre exactly (equal ranges)."""
+    ray; the last dup_frac of them repeat an earlier centre exactly (equal ranges), and
+    dup_one of those all repeat the same centre (one long run of equal ranges)."""
     row, col = scenegen.beam_tables(32, 256, -15, 15)
     D = scenegen.ray_dirs_f64(row, col).reshape(32, 256, 3)
     rng = np.random.default_rng(seed)
@@ -45,6 +46,7 @@ def _crowded_tile(m, seed, dup_frac=0.1):
         cen.append(ranges[k] * d[k] + off)
         frames.append(f)
     src = rng.integers(0, n0, size=n_dup)
+    src[:dup_one] = src[0]
     for k in src:
         frames.append(U.frame_facing(-d[k] + rng.normal(scale=0.25, size=3), spin=rng.uniform(0, 6.28)))
         cen.append(cen[k])
@@ -99,6 +101,18 @@ def test_crowded_tile_and_equal_ranges(ctx, m):
         assert nbad == 0 and cos > 0.99999, (key, nbad, cos, worst)
     nbad, cos, worst = G.grad_check(gp.cpu().numpy(), g_ref["pose"], mass=g_ref["pose_mass"], per_row=False)
     assert nbad == 0 and cos > 0.99999, ("pose", nbad, cos, worst)
+    st.free()
+
+
+def test_long_run_of_equal_ranges(ctx):
+    """40 surfels at one exact range in a crowded tile: a run of equal keys too long to put
+    in index order in place, ordered by the extra index and key sorts instead."""
+    wl = _crowded_tile(2000, seed=17, dup_frac=0.05, dup_one=40)
+    fr, st = G.gpu_forward(ctx, G.to_dev(wl))
+    torch.cuda.synchronize()
+    stats = _compare_all_rays(fr, G.oracle_forward(wl))
+    print("\n[long equal run] " + " ".join(f"{k}={v}" for k, v in stats.items()), flush=True)
+    assert stats["hit"] > 150
     st.free()
 
 
