@@ -47,13 +47,14 @@ struct Lane {
     bool valid, wave_in;
 };
 
-__device__ __forceinline__ Lane lane_of(int tile, const Grid &g)
+// Ray t (0..255) of tile `tile`: wave t / 64 owns one 8 x 8 sub-tile.
+__device__ __forceinline__ Lane lane_of(int tile, const Grid &g, int t = (int)threadIdx.x)
 {
     Lane L;
     const int tc = tile / g.TH, tr = tile - tc * g.TH;
-    L.wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    L.lane = threadIdx.x & 63;
-    L.rt = threadIdx.x;
+    L.wave = __builtin_amdgcn_readfirstlane(t >> 6);
+    L.lane = t & 63;
+    L.rt = t;
     L.sr0 = tr * kTile + (L.wave >> 1) * kSub;
     L.sc0 = tc * kTile + (L.wave & 1) * kSub;
     L.k = L.sr0 + (L.lane >> 3);
@@ -291,28 +292,72 @@ __device__ __forceinline__ void write_ray(const Lane &L, const Grid &g, const Ra
 
 // One workgroup per tile: combine the chunks of every ray in list order (slots become
 // global: end transmittance and sums in global weights), detect termination in a later
-// chunk (-> fix-up record) and write the frame for rays that need no fix-up.
-__global__ __launch_bounds__(256) void raster_merge_kernel(const uint32_t *__restrict__ chunk_base, Grid g,
-                                                           RasterParams p, float *__restrict__ slots,
-                                                           float *__restrict__ depth, float *__restrict__ opacity,
-                                                           float *__restrict__ normal, uint8_t *__restrict__ drop,
-                                                           float4 *__restrict__ st0, float4 *__restrict__ st1,
-                                                           float4 *__restrict__ fixA, float4 *__restrict__ fixB)
+// chunk (-> fix-up record) and write the frame for rays that need no fix-up.  The tile's
+// chunks are split into kMergeGroups runs handled side by side, 256 threads (one per ray)
+// each: first the product of each run's chunk transmittances (a chunk's transmittance is
+// exactly 1 for a ray it does not touch), which gives every run its exact incoming
+// transmittance; then each run walks its chunks from there; then one pass per ray joins
+// the runs' sums in order up to the first run in which the ray terminates.
+constexpr int kMergeGroups = 4;  // at most; the launch picks 1 or 4 (blockDim.x / 256)
+constexpr int kMergeThreads = 256 * kMergeGroups;
+
+// LDS floats per run: the product of its chunk transmittances, then its end T, A, SD, SN0,
+// SN1, SN2, K and fix chunk, each for 256 rays.
+constexpr int kMergeRunFloats = 9 * 256;
+
+__device__ __forceinline__ void run_bounds(uint32_t c0, uint32_t c1, int grp, int ng, uint32_t &r0, uint32_t &r1)
 {
+    const uint32_t q = (c1 - c0 + ng - 1) / ng;
+    r0 = min(c1, c0 + grp * q);
+    r1 = min(c1, r0 + q);
+}
+
+// Runs per tile: enough workgroups to fill the machine first, then shorter chains.
+int merge_groups(int T) { return T <= 512 ? 4 : 1; }
+
+__global__ __launch_bounds__(kMergeThreads) void raster_merge_kernel(const uint32_t *__restrict__ chunk_base, Grid g,
+                                                                     RasterParams p, float *__restrict__ slots,
+                                                                     float *__restrict__ depth,
+                                                                     float *__restrict__ opacity,
+                                                                     float *__restrict__ normal,
+                                                                     uint8_t *__restrict__ drop,
+                                                                     float4 *__restrict__ st0, float4 *__restrict__ st1,
+                                                                     float4 *__restrict__ fixA, float4 *__restrict__ fixB)
+{
+    extern __shared__ float msm[];  // ng runs x kMergeRunFloats
+    const int ng = (int)(blockDim.x >> 8);
     const int tile = blockIdx.x;
-    const Lane L = lane_of(tile, g);
-    if (!L.valid) return;
+    const int t = (int)(threadIdx.x & 255u), grp = (int)(threadIdx.x >> 8);
+    const Lane L = lane_of(tile, g, t);
     const uint32_t c0 = chunk_base[tile], c1 = chunk_base[tile + 1];
+    uint32_t r0, r1;
+    run_bounds(c0, c1, grp, ng, r0, r1);
+    auto P_of = [&](int q) -> float & { return msm[q * kMergeRunFloats + t]; };
+    auto S_of = [&](int q, int f) -> float & { return msm[q * kMergeRunFloats + (1 + f) * 256 + t]; };
+    constexpr int kB = 8;  // chunks whose slots are loaded together (one memory latency per batch)
+    // 1. the run's transmittance product (read by the later runs only)
+    if (grp + 1 < ng) {
+        float P = 1.f;
+        for (uint32_t it0 = r0; it0 < r1 && L.valid; it0 += kB) {
+            float v[kB];
+#pragma unroll
+            for (int q = 0; q < kB; ++q) v[q] = it0 + q < r1 ? slots[slot(it0 + q, F_TEND, L.rt)] : 1.f;
+#pragma unroll
+            for (int q = 0; q < kB; ++q) P *= v[q];
+        }
+        P_of(grp) = P;
+    }
+    __syncthreads();
+    // 2. the run from its incoming transmittance
     float T = 1.f, A = 0.f, SD = 0.f, SN0 = 0.f, SN1 = 0.f, SN2 = 0.f;
     int K = 0, fix = -1;
-    float4 fa = make_float4(0.f, 0.f, 0.f, 0.f), fb = make_float4(0.f, 0.f, 0.f, __int_as_float(-1));
-    constexpr int kB = 16;  // chunks whose slots are loaded together (one memory latency per batch)
-    for (uint32_t it0 = c0; it0 < c1; it0 += kB) {
+    for (int q = 0; q < grp; ++q) T *= P_of(q);
+    for (uint32_t it0 = r0; it0 < r1 && L.valid; it0 += kB) {
         float v[kB][7];
 #pragma unroll
         for (int q = 0; q < kB; ++q) {
             const uint32_t it = it0 + q;
-            if (it < c1) {
+            if (it < r1) {
                 v[q][0] = slots[slot(it, F_K, L.rt)];
                 v[q][1] = slots[slot(it, F_TEND, L.rt)];
                 v[q][2] = slots[slot(it, F_SA, L.rt)];
@@ -325,7 +370,7 @@ __global__ __launch_bounds__(256) void raster_merge_kernel(const uint32_t *__res
 #pragma unroll
         for (int q = 0; q < kB; ++q) {
             const uint32_t it = it0 + q;
-            if (it >= c1) break;
+            if (it >= r1) break;
             if (fix >= 0 || T < p.T_min) {  // after termination: the chunk contributes nothing
                 slots[slot(it, F_LAST, L.rt)] = __int_as_float(-1);
                 continue;
@@ -337,9 +382,7 @@ __global__ __launch_bounds__(256) void raster_merge_kernel(const uint32_t *__res
             }
             const float Tn = T * v[q][1];
             if (it > c0 && Tn < p.T_min) {  // the ray terminates inside this chunk: re-walk it
-                fix = (int)it;
-                fa = make_float4(T, A, SD, __int_as_float(K));
-                fb = make_float4(SN0, SN1, SN2, __int_as_float(fix));
+                fix = (int)it;              // the run's end state is then the state before it
                 slots[slot(it, F_LAST, L.rt)] = __int_as_float(-1);
                 continue;
             }
@@ -359,10 +402,39 @@ __global__ __launch_bounds__(256) void raster_merge_kernel(const uint32_t *__res
             T = Tn;
         }
     }
+    S_of(grp, 0) = T;
+    S_of(grp, 1) = A;
+    S_of(grp, 2) = SD;
+    S_of(grp, 3) = SN0;
+    S_of(grp, 4) = SN1;
+    S_of(grp, 5) = SN2;
+    S_of(grp, 6) = __int_as_float(K);
+    S_of(grp, 7) = __int_as_float(fix);
+    __syncthreads();
+    // 3. join the runs in order
+    if (grp != 0 || !L.valid) return;
+    float aA = 0.f, aD = 0.f, a0 = 0.f, a1 = 0.f, a2 = 0.f, Tf = 1.f;
+    int aK = 0, fx = -1;
+    for (int q = 0; q < ng; ++q) {
+        aA += S_of(q, 1);
+        aD += S_of(q, 2);
+        a0 += S_of(q, 3);
+        a1 += S_of(q, 4);
+        a2 += S_of(q, 5);
+        aK += __float_as_int(S_of(q, 6));
+        Tf = S_of(q, 0);
+        fx = __float_as_int(S_of(q, 7));
+        if (fx >= 0 || Tf < p.T_min) break;  // later runs start below T_min: they add nothing
+    }
     const int r = L.k * g.W + L.j;
-    fixA[r] = fa;
-    fixB[r] = fb;
-    if (fix < 0) write_ray(L, g, p, A, SD, SN0, SN1, SN2, T, K, depth, opacity, normal, drop, st0, st1);
+    if (fx >= 0) {
+        fixA[r] = make_float4(Tf, aA, aD, __int_as_float(aK));
+        fixB[r] = make_float4(a0, a1, a2, __int_as_float(fx));
+    } else {
+        fixA[r] = make_float4(0.f, 0.f, 0.f, 0.f);
+        fixB[r] = make_float4(0.f, 0.f, 0.f, __int_as_float(-1));
+        write_ray(L, g, p, aA, aD, a0, a1, a2, Tf, aK, depth, opacity, normal, drop, st0, st1);
+    }
 }
 
 // Re-walk the chunk in which a ray terminates, from its true transmittance, and finish it.
@@ -408,65 +480,84 @@ __global__ __launch_bounds__(256) void raster_fixup_kernel(
 // ---------------------------------------------------------------------------------------
 
 // Per ray: effective upstream gradients and, per chunk, the suffix sum B of later chunks.
-__global__ __launch_bounds__(256) void raster_bwd_prep_kernel(const uint32_t *__restrict__ chunk_base, Grid g,
-                                                              const float4 *__restrict__ st0,
-                                                              const float4 *__restrict__ st1,
-                                                              const float *__restrict__ gDp,
-                                                              const float *__restrict__ gAp,
-                                                              const float *__restrict__ gNp,
-                                                              float *__restrict__ slots, float4 *__restrict__ gb0,
-                                                              float *__restrict__ gb1)
+// The tile's chunks are split into the same kMergeGroups runs as in the merge: each run sums
+// its chunks' contributions, then walks its chunks backwards from the sum of the later runs.
+__global__ __launch_bounds__(kMergeThreads) void raster_bwd_prep_kernel(const uint32_t *__restrict__ chunk_base, Grid g,
+                                                                        const float4 *__restrict__ st0,
+                                                                        const float4 *__restrict__ st1,
+                                                                        const float *__restrict__ gDp,
+                                                                        const float *__restrict__ gAp,
+                                                                        const float *__restrict__ gNp,
+                                                                        float *__restrict__ slots,
+                                                                        float4 *__restrict__ gb0,
+                                                                        float *__restrict__ gb1)
 {
+    __shared__ float S[kMergeGroups][256];
+    const int ng = (int)(blockDim.x >> 8);
     const int tile = blockIdx.x;
-    const Lane L = lane_of(tile, g);
-    if (!L.valid) return;
-    const int r = L.k * g.W + L.j;
-    const float4 a = st0[r], b = st1[r];
-    const int K = __float_as_int(b.w);
+    const int t = (int)(threadIdx.x & 255u), grp = (int)(threadIdx.x >> 8);
+    const Lane L = lane_of(tile, g, t);
+    const int r = L.valid ? L.k * g.W + L.j : 0;
+    int K = 0;
     float gbD = 0.f, gbN0 = 0.f, gbN1 = 0.f, gbN2 = 0.f, gbA = 0.f;
-    if (K > 0) {
-        const float iA = 1.f / a.x, D = a.y;
-        const float gd = gDp[r], ga = gAp[r];
-        const float gn0 = gNp[3 * r], gn1 = gNp[3 * r + 1], gn2 = gNp[3 * r + 2];
-        gbD = gd * iA;
-        gbN0 = gn0 * iA;
-        gbN1 = gn1 * iA;
-        gbN2 = gn2 * iA;
-        gbA = ga - (gd * D + gn0 * b.x + gn1 * b.y + gn2 * b.z) * iA;
+    if (L.valid) {
+        const float4 a = st0[r], b = st1[r];
+        K = __float_as_int(b.w);
+        if (K > 0) {
+            const float iA = 1.f / a.x, D = a.y;
+            const float gd = gDp[r], ga = gAp[r];
+            const float gn0 = gNp[3 * r], gn1 = gNp[3 * r + 1], gn2 = gNp[3 * r + 2];
+            gbD = gd * iA;
+            gbN0 = gn0 * iA;
+            gbN1 = gn1 * iA;
+            gbN2 = gn2 * iA;
+            gbA = ga - (gd * D + gn0 * b.x + gn1 * b.y + gn2 * b.z) * iA;
+        }
+        if (grp == 0) {
+            gb0[r] = make_float4(gbD, gbN0, gbN1, gbN2);
+            gb1[r] = gbA;
+        }
     }
-    gb0[r] = make_float4(gbD, gbN0, gbN1, gbN2);
-    gb1[r] = gbA;
     const uint32_t c0 = chunk_base[tile], c1 = chunk_base[tile + 1];
+    uint32_t r0, r1;
+    run_bounds(c0, c1, grp, ng, r0, r1);
+    constexpr int kB = 8;  // chunks whose slots are loaded together (one memory latency per batch)
+    const bool live = L.valid && K > 0;
+    // the run's contributions, last chunk first (pass 0); then B from the later runs' sums (pass 1)
     float B = 0.f;
-    if (K == 0) {
-        for (uint32_t it = c0; it < c1; ++it) slots[slot(it, F_B, L.rt)] = 0.f;
-        return;
-    }
-    constexpr int kB = 16;  // chunks whose slots are loaded together (one memory latency per batch)
-    for (uint32_t top = c1; top > c0;) {
-        const uint32_t lo = top - c0 > (uint32_t)kB ? top - kB : c0;
-        float v[kB][6];
+    for (int pass = 0; pass < 2; ++pass) {
+        if (pass == 0 && grp == 0) continue;  // the first run's sum is read by no other run
+        if (pass == 1) {
+            if (ng > 1) __syncthreads();
+            B = 0.f;
+            for (int q = ng - 1; q > grp; --q) B += S[q][t];
+        }
+        for (uint32_t top = r1; top > r0;) {
+            const uint32_t lo = top - r0 > (uint32_t)kB ? top - kB : r0;
+            float v[kB][6];
 #pragma unroll
-        for (int q = 0; q < kB; ++q) {
-            const uint32_t it = top - 1 - q;
-            if (it >= lo && it < top) {
-                v[q][0] = slots[slot(it, F_LAST, L.rt)];
-                v[q][1] = slots[slot(it, F_SA, L.rt)];
-                v[q][2] = slots[slot(it, F_SD, L.rt)];
-                v[q][3] = slots[slot(it, F_SN0, L.rt)];
-                v[q][4] = slots[slot(it, F_SN1, L.rt)];
-                v[q][5] = slots[slot(it, F_SN2, L.rt)];
+            for (int q = 0; q < kB; ++q) {
+                const uint32_t it = top - 1 - q;
+                if (live && it >= lo && it < top) {
+                    v[q][0] = slots[slot(it, F_LAST, L.rt)];
+                    v[q][1] = slots[slot(it, F_SA, L.rt)];
+                    v[q][2] = slots[slot(it, F_SD, L.rt)];
+                    v[q][3] = slots[slot(it, F_SN0, L.rt)];
+                    v[q][4] = slots[slot(it, F_SN1, L.rt)];
+                    v[q][5] = slots[slot(it, F_SN2, L.rt)];
+                }
             }
-        }
 #pragma unroll
-        for (int q = 0; q < kB; ++q) {
-            const uint32_t it = top - 1 - q;
-            if (it < lo || it >= top) break;
-            slots[slot(it, F_B, L.rt)] = B;
-            if (__float_as_int(v[q][0]) < 0) continue;
-            B = fmaf(gbD, v[q][2], fmaf(gbN0, v[q][3], fmaf(gbN1, v[q][4], fmaf(gbN2, v[q][5], fmaf(gbA, v[q][1], B)))));
+            for (int q = 0; q < kB; ++q) {
+                const uint32_t it = top - 1 - q;
+                if (it < lo || it >= top) break;
+                if (pass == 1 && L.valid) slots[slot(it, F_B, L.rt)] = live ? B : 0.f;
+                if (!live || __float_as_int(v[q][0]) < 0) continue;
+                B = fmaf(gbD, v[q][2], fmaf(gbN0, v[q][3], fmaf(gbN1, v[q][4], fmaf(gbN2, v[q][5], fmaf(gbA, v[q][1], B)))));
+            }
+            top = lo;
         }
-        top = lo;
+        if (pass == 0) S[grp][t] = B;
     }
 }
 
@@ -682,8 +773,9 @@ hipError_t launch_raster_fwd(const RasterBufs &R, const Grid &g, const RasterPar
     if (im > 0)
         raster_fwd_chunk_kernel<<<im, 256, 0, s>>>(R.chunks, R.n_items, im, R.ids, R.recs, R.rects, R.rows, R.cols, g,
                                                    p, R.slots);
-    raster_merge_kernel<<<g.T, 256, 0, s>>>(R.chunk_base, g, p, R.slots, depth, opacity, normal, drop, R.st0, R.st1,
-                                           R.fixA, R.fixB);
+    const int ng = merge_groups(g.T);
+    raster_merge_kernel<<<g.T, 256 * ng, (size_t)ng * kMergeRunFloats * sizeof(float), s>>>(
+        R.chunk_base, g, p, R.slots, depth, opacity, normal, drop, R.st0, R.st1, R.fixA, R.fixB);
     if (im > 0)
         raster_fixup_kernel<<<im, 256, 0, s>>>(R.chunks, R.n_items, im, R.ids, R.recs, R.rects, R.rows, R.cols, g, p,
                                                R.fixA, R.fixB, R.slots, depth, opacity, normal, drop, R.st0, R.st1);
@@ -694,7 +786,8 @@ hipError_t launch_raster_bwd_prep(const RasterBufs &R, const Grid &g, const floa
                                   const float *gN, float4 *gb0, float *gb1, hipStream_t s)
 {
     if (g.T <= 0) return hipSuccess;
-    raster_bwd_prep_kernel<<<g.T, 256, 0, s>>>(R.chunk_base, g, R.st0, R.st1, gD, gA, gN, R.slots, gb0, gb1);
+    raster_bwd_prep_kernel<<<g.T, 256 * merge_groups(g.T), 0, s>>>(R.chunk_base, g, R.st0, R.st1, gD, gA, gN, R.slots,
+                                                                  gb0, gb1);
     return hipGetLastError();
 }
 
