@@ -80,6 +80,8 @@ struct lgsr_state {
     DevBuf recs, rects, pk, pv, ranges, long_tiles, st0, st1, pose, chunks, chunk_base, slots, fixA, fixB;
     // per-forward scratch: range keys, per-(tile, shard) counts and cursors, read-back words
     DevBuf keys, cnt, offs, counters;
+    bool cnt_clean = false;      // every word of cnt is zero (the tile scan leaves it so)
+    void *cnt_seen = nullptr;    // the cnt allocation cnt_clean refers to
     uint32_t *pinned = nullptr;  // host-pinned copy of counters[0..2]
     hipEvent_t rb = nullptr;     // recorded after the read-back copy
     int chunk_req = 0;           // requested chunk size (0: automatic)
@@ -373,7 +375,9 @@ lgsr_status forward_begin(lgsr_ctx *ctx, lgsr_state *S, const lgsr_surfels *surf
     uint32_t *counters = as<uint32_t>(S->counters);
     {
     Stage st_(ctx, LGSR_STAGE_PROJECT, s);
-    HIP_TRY(launch_fill_u32(as<uint32_t>(S->cnt), 0u, (int64_t)g.T * kShards, s), "clear tile counts");
+    if (!(S->cnt_clean && S->cnt_seen == S->cnt.p))
+        HIP_TRY(launch_fill_u32(as<uint32_t>(S->cnt), 0u, (int64_t)(S->cnt.cap / 4), s), "clear tile counts");
+    S->cnt_clean = false;  // until the scan below has run
     HIP_TRY(launch_project(S->S, pose_val, pose_dev, as<float>(S->pose), beams->row_sincos, g, S->prm,
                            as<float>(S->recs), as<uint2>(S->rects), as<uint32_t>(S->keys), as<uint32_t>(S->cnt), s),
             "project");
@@ -383,6 +387,8 @@ lgsr_status forward_begin(lgsr_ctx *ctx, lgsr_state *S, const lgsr_surfels *surf
     HIP_TRY(launch_tile_scan(as<uint32_t>(S->cnt), g.T, as<uint2>(S->ranges), as<uint32_t>(S->offs), counters,
                              as<uint32_t>(S->long_tiles), s),
             "tile scan");
+    S->cnt_clean = true;
+    S->cnt_seen = S->cnt.p;
     }
     Stage st_(ctx, LGSR_STAGE_READBACK, s);
     HIP_TRY(hipMemcpyAsync(S->pinned, counters, 4 * sizeof(uint32_t), hipMemcpyDeviceToHost, s), "readback");
@@ -411,17 +417,6 @@ lgsr_status forward_end(lgsr_ctx *ctx, lgsr_state *S, const lgsr_frame *out, hip
         HIP_TRY(ensure(S->pk, pp * 8), "alloc sort workspace");
     }
     S->ids = as<uint32_t>(S->pv);
-    if (P > 0) {
-        {
-        Stage st_(ctx, LGSR_STAGE_EMIT, s);
-        HIP_TRY(launch_emit(as<uint2>(S->rects), n, g, as<uint32_t>(S->offs), S->ids, P, s), "emit");
-        }
-        Stage st_(ctx, LGSR_STAGE_TILE_SORT, s);
-        HIP_TRY(launch_tile_sort(as<uint2>(S->ranges), g.T, as<uint32_t>(S->keys), n, S->ids,
-                                 as<uint32_t>(S->long_tiles), n_long, nch,
-                                 n_long > 0 ? as<unsigned long long>(S->pk) : nullptr, s),
-                "tile sort");
-    }
     const int seg = chunk_size(P, S->chunk_req);
     const int64_t items_max = chunk_items_max(P, g.T, seg);
     if (items_max > 0x7FFFFFFF) return fail(ctx, LGSR_ECAPACITY, "too many list chunks");
@@ -430,6 +425,17 @@ lgsr_status forward_end(lgsr_ctx *ctx, lgsr_state *S, const lgsr_frame *out, hip
     HIP_TRY(ensure(S->slots, chunk_slot_floats(items_max > 0 ? items_max : 1) * sizeof(float)), "alloc slots");
     HIP_TRY(ensure(S->fixA, (size_t)rays * sizeof(float4)), "alloc ray state");
     HIP_TRY(ensure(S->fixB, (size_t)rays * sizeof(float4)), "alloc ray state");
+    if (P > 0) {
+        Stage st_(ctx, LGSR_STAGE_EMIT, s);
+        HIP_TRY(launch_emit(as<uint2>(S->rects), n, g, as<uint32_t>(S->offs), S->ids, P, s), "emit");
+    }
+    {
+    Stage st_(ctx, LGSR_STAGE_TILE_SORT, s);
+    const ChunkList cl{seg, as<uint4>(S->chunks), as<uint32_t>(S->chunk_base), as<uint32_t>(S->pose) + 12};
+    HIP_TRY(launch_tile_sort(as<uint2>(S->ranges), g.T, as<uint32_t>(S->keys), n, S->ids, as<uint32_t>(S->long_tiles),
+                             n_long, nch, n_long > 0 ? as<unsigned long long>(S->pk) : nullptr, cl, s),
+            "tile sort");
+    }
     RasterBufs &R = S->R;
     R.ids = S->ids;
     R.recs = as<float>(S->recs);

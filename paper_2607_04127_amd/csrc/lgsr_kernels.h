@@ -16,17 +16,26 @@ int tile_sort_capacity();
 int tile_sort_chunks(int64_t longest);
 // cnt, cursor: T x kShards.  ranges[t] = [first, end) of tile t's list and cursor[t kShards
 // + s] = first slot of its shard s, from the exclusive prefix sum of cnt in (tile, shard)
-// order; out (device, 4 words) receives the total as two 32-bit words (low, high), the
+// order; cnt is left zero; out (device, 4 words) receives the total as two 32-bit words (low, high), the
 // largest tile count and the number of tiles longer than tile_sort_capacity(), whose ids go
 // to long_tiles (T words).
-hipError_t launch_tile_scan(const uint32_t *cnt, int T, uint2 *ranges, uint32_t *cursor, uint32_t *out,
+hipError_t launch_tile_scan(uint32_t *cnt, int T, uint2 *ranges, uint32_t *cursor, uint32_t *out,
                             uint32_t *long_tiles, hipStream_t s);
+// The raster's chunk list, built alongside the tile sort: chunks of seg list entries
+// (items_max x uint4), chunk_base (T + 1), n_items (device word).
+struct ChunkList {
+    int seg;
+    uint4 *chunks;
+    uint32_t *chunk_base;
+    uint32_t *n_items;
+};
 // Orders every tile's list ids[ranges[t].x .. ranges[t].y) by (keys[id], id) ascending
 // (keys has n entries).  Tiles longer than tile_sort_capacity(): the n_long of them in
 // long_tiles, nch = tile_sort_chunks(longest), tmp (P x 8 bytes); tmp may be null when
 // n_long is 0.
 hipError_t launch_tile_sort(const uint2 *ranges, int T, const uint32_t *keys, int64_t n, uint32_t *ids,
-                            const uint32_t *long_tiles, int n_long, int nch, unsigned long long *tmp, hipStream_t s);
+                            const uint32_t *long_tiles, int n_long, int nch, unsigned long long *tmp,
+                            const ChunkList &cl, hipStream_t s);
 
 // ---- project.hip ----
 struct SurfelPtrs {

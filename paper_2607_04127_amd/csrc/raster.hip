@@ -65,59 +65,7 @@ __device__ __forceinline__ Lane lane_of(int tile, const Grid &g, int t = (int)th
 }
 
 // ---------------------------------------------------------------------------------------
-// chunk list
-// ---------------------------------------------------------------------------------------
-
-__global__ __launch_bounds__(1024) void build_chunks_kernel(const uint2 *__restrict__ ranges, int T, int seg,
-                                                            uint4 *__restrict__ chunks,
-                                                            uint32_t *__restrict__ chunk_base,
-                                                            uint32_t *__restrict__ n_items)
-{
-    __shared__ uint32_t wsum[16];
-    const int t0 = threadIdx.x, w = t0 >> 6, l = t0 & 63;
-    uint32_t carry = 0;
-    for (int base = 0; base < T; base += 1024) {
-        const int t = base + t0;
-        uint2 r = make_uint2(0u, 0u);
-        uint32_t c = 0;
-        if (t < T) {
-            r = ranges[t];
-            c = (r.y - r.x + (uint32_t)seg - 1u) / (uint32_t)seg;
-        }
-        uint32_t inc = c;
-#pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-            uint32_t y = __shfl_up(inc, o, 64);
-            if (l >= o) inc += y;
-        }
-        if (l == 63) wsum[w] = inc;
-        __syncthreads();
-        uint32_t off = 0, tot = 0;
-        for (int q = 0; q < 16; ++q) {
-            uint32_t s = wsum[q];
-            if (q < w) off += s;
-            tot += s;
-        }
-        const uint32_t first = carry + off + inc - c;
-        if (t < T) {
-            chunk_base[t] = first;
-            for (uint32_t q = 0; q < c; ++q) {
-                uint32_t a = r.x + q * (uint32_t)seg;
-                uint32_t b = min(r.y, a + (uint32_t)seg);
-                chunks[first + q] = make_uint4((uint32_t)t, a, b, 0u);
-            }
-        }
-        carry += tot;
-        __syncthreads();
-    }
-    if (t0 == 0) {
-        chunk_base[T] = carry;
-        *n_items = carry;
-    }
-}
-
-// ---------------------------------------------------------------------------------------
-// forward
+// forward (the chunk list comes from the tile sort launch)
 // ---------------------------------------------------------------------------------------
 
 struct Acc {
@@ -768,7 +716,6 @@ hipError_t launch_raster_fwd(const RasterBufs &R, const Grid &g, const RasterPar
                              float *opacity, float *normal, uint8_t *drop, hipStream_t s)
 {
     if (g.T <= 0) return hipSuccess;
-    build_chunks_kernel<<<1, 1024, 0, s>>>(R.ranges, g.T, R.seg, R.chunks, R.chunk_base, R.n_items);
     const int im = (int)R.items_max;
     if (im > 0)
         raster_fwd_chunk_kernel<<<im, 256, 0, s>>>(R.chunks, R.n_items, im, R.ids, R.recs, R.rects, R.rows, R.cols, g,

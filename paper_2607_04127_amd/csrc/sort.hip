@@ -297,14 +297,69 @@ __device__ void sort_resident(TileSortSmem &sm, const uint32_t *__restrict__ key
     }
 }
 
-// One workgroup per tile; lists longer than kTsCap are left to the chunk kernels below.
+// The raster's work list (one workgroup): every tile's list cut into chunks of seg entries,
+// chunk q of tile t = (t, first, end); chunk_base[t] = index of the tile's first chunk,
+// chunk_base[T] = *n_items = the number of chunks.
+__device__ void build_chunks_block(const uint2 *__restrict__ ranges, int T, int seg, uint4 *__restrict__ chunks,
+                                   uint32_t *__restrict__ chunk_base, uint32_t *__restrict__ n_items)
+{
+    static_assert(kTsThreads == 1024, "16 waves");
+    __shared__ uint32_t wsum[16];
+    const int t0 = threadIdx.x, w = t0 >> 6, l = t0 & 63;
+    uint32_t carry = 0;
+    for (int base = 0; base < T; base += 1024) {
+        const int t = base + t0;
+        uint2 r = make_uint2(0u, 0u);
+        uint32_t c = 0;
+        if (t < T) {
+            r = ranges[t];
+            c = (r.y - r.x + (uint32_t)seg - 1u) / (uint32_t)seg;
+        }
+        uint32_t inc = c;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            uint32_t y = __shfl_up(inc, o, 64);
+            if (l >= o) inc += y;
+        }
+        if (l == 63) wsum[w] = inc;
+        __syncthreads();
+        uint32_t off = 0, tot = 0;
+        for (int q = 0; q < 16; ++q) {
+            uint32_t v = wsum[q];
+            if (q < w) off += v;
+            tot += v;
+        }
+        const uint32_t first = carry + off + inc - c;
+        if (t < T) {
+            chunk_base[t] = first;
+            for (uint32_t q = 0; q < c; ++q) {
+                uint32_t a = r.x + q * (uint32_t)seg;
+                uint32_t b = min(r.y, a + (uint32_t)seg);
+                chunks[first + q] = make_uint4((uint32_t)t, a, b, 0u);
+            }
+        }
+        carry += tot;
+        __syncthreads();
+    }
+    if (t0 == 0) {
+        chunk_base[T] = carry;
+        *n_items = carry;
+    }
+}
+
+// One workgroup per tile, and one more that builds the raster's chunk list; lists longer than
+// kTsCap are left to the chunk kernels below.
 __global__ __launch_bounds__(kTsThreads) void tile_sort_kernel(const uint2 *__restrict__ ranges, int T,
                                                                const uint32_t *__restrict__ keys, int64_t n,
-                                                               uint32_t *ids)
+                                                               uint32_t *ids, ChunkList cl)
 {
     __shared__ TileSortSmem sm;
     const int tile = blockIdx.x;
-    if (tile >= T) return;
+    if (tile == T) {
+        build_chunks_block(ranges, T, cl.seg, cl.chunks, cl.chunk_base, cl.n_items);
+        return;
+    }
+    if (tile > T) return;
     const uint2 rg = ranges[tile];
     const int m = (int)(rg.y - rg.x);
     if (m <= 1 || m > kTsCap) return;
@@ -381,10 +436,11 @@ __global__ __launch_bounds__(kTsThreads) void tile_chunk_merge_kernel(const uint
 
 // One workgroup.  cnt holds kShards counts per tile; with o the exclusive prefix sum of all
 // counts in (tile, shard) order: cursor[t kShards + s] = o at that entry, ranges[t] = (o at
-// (t, 0), o at (t + 1, 0)); out[0..1] = total (64-bit), out[2] = largest tile count, out[3] =
+// (t, 0), o at (t + 1, 0)); the counts are left zero; out[0..1] = total (64-bit), out[2] =
+// largest tile count, out[3] =
 // number of tiles with more than kTsCap entries, listed (in no particular order) in
 // long_tiles.
-__global__ __launch_bounds__(1024) void tile_scan_kernel(const uint32_t *__restrict__ cnt, int T,
+__global__ __launch_bounds__(1024) void tile_scan_kernel(uint32_t *__restrict__ cnt, int T,
                                                          uint2 *__restrict__ ranges, uint32_t *__restrict__ cursor,
                                                          uint32_t *__restrict__ out, uint32_t *__restrict__ long_tiles)
 {
@@ -401,9 +457,12 @@ __global__ __launch_bounds__(1024) void tile_scan_kernel(const uint32_t *__restr
         const int tile = first + t;
         uint4 a = make_uint4(0u, 0u, 0u, 0u), b = a;
         if (tile < T) {
-            const uint4 *p = reinterpret_cast<const uint4 *>(cnt + (size_t)tile * kShards);
+            uint4 *p = reinterpret_cast<uint4 *>(cnt + (size_t)tile * kShards);
             a = p[0];
             b = p[1];
+            // leave the counts zero for the next projection
+            p[0] = make_uint4(0u, 0u, 0u, 0u);
+            p[1] = make_uint4(0u, 0u, 0u, 0u);
         }
         const uint32_t x[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
         uint64_t s = 0;
@@ -462,7 +521,7 @@ __global__ __launch_bounds__(1024) void tile_scan_kernel(const uint32_t *__restr
 
 int tile_sort_capacity() { return kTsCap; }
 
-hipError_t launch_tile_scan(const uint32_t *cnt, int T, uint2 *ranges, uint32_t *cursor, uint32_t *out,
+hipError_t launch_tile_scan(uint32_t *cnt, int T, uint2 *ranges, uint32_t *cursor, uint32_t *out,
                             uint32_t *long_tiles, hipStream_t s)
 {
     tile_scan_kernel<<<1, 1024, 0, s>>>(cnt, T, ranges, cursor, out, long_tiles);
@@ -472,10 +531,11 @@ hipError_t launch_tile_scan(const uint32_t *cnt, int T, uint2 *ranges, uint32_t 
 int tile_sort_chunks(int64_t longest) { return (int)((longest + kTsCap - 1) / kTsCap); }
 
 hipError_t launch_tile_sort(const uint2 *ranges, int T, const uint32_t *keys, int64_t n, uint32_t *ids,
-                            const uint32_t *long_tiles, int n_long, int nch, unsigned long long *tmp, hipStream_t s)
+                            const uint32_t *long_tiles, int n_long, int nch, unsigned long long *tmp,
+                            const ChunkList &cl, hipStream_t s)
 {
     if (T <= 0) return hipSuccess;
-    tile_sort_kernel<<<T, kTsThreads, 0, s>>>(ranges, T, keys, n, ids);
+    tile_sort_kernel<<<T + 1, kTsThreads, 0, s>>>(ranges, T, keys, n, ids, cl);
     if (n_long > 0 && nch > 1) {
         const unsigned grid = (unsigned)((int64_t)n_long * nch);
         tile_chunk_sort_kernel<<<grid, kTsThreads, 0, s>>>(ranges, long_tiles, nch, keys, n, ids, tmp);
