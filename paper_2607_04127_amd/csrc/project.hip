@@ -179,16 +179,18 @@ __device__ __forceinline__ uint2 project_one(const SurfelPtrs &S, const Pose &P,
     return make_uint2((uint32_t)r0 | ((uint32_t)r1 << 16), (uint32_t)c0 | ((uint32_t)cw << 16));
 }
 
-// Surfels per projection / emission workgroup (kPerThread per thread, strided by 256): one
-// reservation per (workgroup, tile) then covers four times as many pairs.
-constexpr int kPerThread = 4;
-constexpr int kPerBlock = 256 * kPerThread;
+// Surfels per projection / emission workgroup, one per thread: one reservation per
+// (workgroup, tile) covers the pairs of 1024 surfels, and 16 waves per workgroup keep the
+// CU busy while each works through its surfel's arithmetic.
+constexpr int kProjThreads = 1024;
+constexpr int kPerThread = 1;
+constexpr int kPerBlock = kProjThreads * kPerThread;
 static_assert(kPerBlock == 1 << kShardShift, "the shard of a surfel is its workgroup's");
 
 // Projection plus the per-tile pair counts, tile_cnt[t * kShards + shard_of(i)] (zero on
 // entry).  A workgroup's surfels share one shard.  Dynamic LDS: T words when T <= kLdsBins,
 // else none (counts then go straight to tile_cnt).
-__global__ __launch_bounds__(256) void project_kernel(SurfelPtrs S, Pose pose_val, const float *__restrict__ pose_dev,
+__global__ __launch_bounds__(kProjThreads) void project_kernel(SurfelPtrs S, Pose pose_val, const float *__restrict__ pose_dev,
                                                       float *__restrict__ pose_out,
                                                       const float *__restrict__ rows, Grid g, RasterParams p,
                                                       float *__restrict__ recs, uint2 *__restrict__ rects,
@@ -197,21 +199,21 @@ __global__ __launch_bounds__(256) void project_kernel(SurfelPtrs S, Pose pose_va
     extern __shared__ uint32_t bins[];
     const bool lds_bins = g.T <= kLdsBins;
     if (lds_bins)
-        for (int b = threadIdx.x; b < g.T; b += 256) bins[b] = 0u;
+        for (int b = threadIdx.x; b < g.T; b += kProjThreads) bins[b] = 0u;
     Pose P = pose_val;
     if (pose_dev) {
         for (int c = 0; c < 9; ++c) P.r[c] = pose_dev[(c / 3) * 4 + (c % 3)];
         for (int c = 0; c < 3; ++c) P.t[c] = pose_dev[4 * c + 3];
     }
-    if (blockIdx.x == 0 && threadIdx.x < 12) {
-        int c = threadIdx.x, row = c >> 2, col = c & 3;
-        pose_out[c] = col < 3 ? P.r[3 * row + col] : P.t[row];
+    if (blockIdx.x == 0 && threadIdx.x == 0) {  // constant indices: the pose stays in registers
+#pragma unroll
+        for (int c = 0; c < 12; ++c) pose_out[c] = (c & 3) < 3 ? P.r[3 * (c >> 2) + (c & 3)] : P.t[c >> 2];
     }
     const int64_t first = (int64_t)blockIdx.x * kPerBlock;
     const int sh = shard_of(first);
     if (lds_bins) __syncthreads();
     for (int k = 0; k < kPerThread; ++k) {
-        const int64_t i = first + k * 256 + threadIdx.x;
+        const int64_t i = first + k * kProjThreads + threadIdx.x;
         if (i >= S.n) break;
         const uint2 rc = project_one(S, P, rows, g, p, recs, keys, i);
         rects[i] = rc;
@@ -220,7 +222,7 @@ __global__ __launch_bounds__(256) void project_kernel(SurfelPtrs S, Pose pose_va
     }
     if (lds_bins) {
         __syncthreads();
-        for (int b = threadIdx.x; b < g.T; b += 256) {
+        for (int b = threadIdx.x; b < g.T; b += kProjThreads) {
             const uint32_t c = bins[b];
             if (c) atomicAdd(&tile_cnt[b * kShards + sh], c);
         }
@@ -232,7 +234,7 @@ __global__ __launch_bounds__(256) void project_kernel(SurfelPtrs S, Pose pose_va
 // Per workgroup, pairs are counted per tile in LDS, one range per tile is reserved with a
 // single atomic, and the workgroup's pairs fill it.  Positions at or beyond P are dropped
 // (they cannot occur when the counts came from project_kernel over the same rectangles).
-__global__ __launch_bounds__(256) void emit_kernel(const uint2 *__restrict__ rects, int64_t n, Grid g,
+__global__ __launch_bounds__(kProjThreads) void emit_kernel(const uint2 *__restrict__ rects, int64_t n, Grid g,
                                                    uint32_t *__restrict__ cursor, uint32_t *__restrict__ pv,
                                                    int64_t P)
 {
@@ -242,12 +244,12 @@ __global__ __launch_bounds__(256) void emit_kernel(const uint2 *__restrict__ rec
     uint2 rc[kPerThread];
 #pragma unroll
     for (int k = 0; k < kPerThread; ++k) {
-        const int64_t i = first + k * 256 + threadIdx.x;
+        const int64_t i = first + k * kProjThreads + threadIdx.x;
         rc[k] = i < n ? rects[i] : make_uint2(0u, 0u);
     }
     if (g.T > kLdsBins) {
         for (int k = 0; k < kPerThread; ++k) {
-            const uint32_t id = (uint32_t)(first + k * 256 + threadIdx.x);
+            const uint32_t id = (uint32_t)(first + k * kProjThreads + threadIdx.x);
             for_each_tile(rc[k], g, [&](int t) {
                 const uint32_t pos = atomicAdd(&cursor[t * kShards + sh], 1u);
                 if ((int64_t)pos < P) pv[pos] = id;
@@ -256,18 +258,18 @@ __global__ __launch_bounds__(256) void emit_kernel(const uint2 *__restrict__ rec
         return;
     }
     uint32_t *cnt = bins, *base = bins + g.T;
-    for (int b = threadIdx.x; b < g.T; b += 256) cnt[b] = 0u;
+    for (int b = threadIdx.x; b < g.T; b += kProjThreads) cnt[b] = 0u;
     __syncthreads();
     for (int k = 0; k < kPerThread; ++k) for_each_tile(rc[k], g, [&](int t) { atomicAdd(&cnt[t], 1u); });
     __syncthreads();
-    for (int b = threadIdx.x; b < g.T; b += 256) {
+    for (int b = threadIdx.x; b < g.T; b += kProjThreads) {
         const uint32_t c = cnt[b];
         if (c) base[b] = atomicAdd(&cursor[b * kShards + sh], c);
         cnt[b] = 0u;
     }
     __syncthreads();
     for (int k = 0; k < kPerThread; ++k) {
-        const uint32_t id = (uint32_t)(first + k * 256 + threadIdx.x);
+        const uint32_t id = (uint32_t)(first + k * kProjThreads + threadIdx.x);
         for_each_tile(rc[k], g, [&](int t) {
             const uint32_t pos = base[t] + atomicAdd(&cnt[t], 1u);
             if ((int64_t)pos < P) pv[pos] = id;
@@ -375,7 +377,8 @@ hipError_t launch_project(const SurfelPtrs &S, const Pose &pose_val, const float
 {
     unsigned nb = S.n > 0 ? blocks_for(S.n, kPerBlock) : 1u;  // one block still writes the pose
     size_t lds = g.T <= kLdsBins ? (size_t)g.T * sizeof(uint32_t) : 0;
-    project_kernel<<<nb, 256, lds, s>>>(S, pose_val, pose_dev, pose_out, rows, g, p, recs, rects, keys, tile_cnt);
+    project_kernel<<<nb, kProjThreads, lds, s>>>(S, pose_val, pose_dev, pose_out, rows, g, p, recs, rects, keys,
+                                                 tile_cnt);
     return hipGetLastError();
 }
 
@@ -384,7 +387,7 @@ hipError_t launch_emit(const uint2 *rects, int64_t n, const Grid &g, uint32_t *c
 {
     if (n <= 0 || P <= 0) return hipSuccess;
     size_t lds = g.T <= kLdsBins ? 2 * (size_t)g.T * sizeof(uint32_t) : 0;
-    emit_kernel<<<blocks_for(n, kPerBlock), 256, lds, s>>>(rects, n, g, cursor, pv, P);
+    emit_kernel<<<blocks_for(n, kPerBlock), kProjThreads, lds, s>>>(rects, n, g, cursor, pv, P);
     return hipGetLastError();
 }
 
