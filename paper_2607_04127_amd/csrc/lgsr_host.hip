@@ -77,7 +77,9 @@ struct lgsr_state {
     lgsr_ctx *ctx = nullptr;
     bool live = false;
     // forward products kept for the backward
-    DevBuf recs, rects, pk, pv, ranges, long_tiles, st0, st1, pose, chunks, chunk_base, slots, fixA, fixB;
+    DevBuf recs, rects, pk, pv, ranges, long_tiles, st0, st1, pose, chunks, chunk_base, slots, fixA, fixB, fixflag;
+    bool fixflag_clean = false;  // every word of fixflag is zero (the fix-up clears what the merge sets)
+    void *fixflag_seen = nullptr;
     // per-forward scratch: range keys, per-(tile, shard) counts and cursors, read-back words
     DevBuf keys, cnt, offs, counters;
     bool cnt_clean = false;      // every word of cnt is zero (the tile scan leaves it so)
@@ -207,6 +209,7 @@ void free_state_buffers(lgsr_state *s)
     release(s->recs); release(s->rects); release(s->pk); release(s->pv); release(s->long_tiles);
     release(s->ranges); release(s->st0); release(s->st1); release(s->pose);
     release(s->chunks); release(s->chunk_base); release(s->slots); release(s->fixA); release(s->fixB);
+    release(s->fixflag);
     release(s->keys); release(s->cnt); release(s->offs); release(s->counters);
     if (s->pinned) (void)hipHostFree(s->pinned);
     s->pinned = nullptr;
@@ -268,7 +271,7 @@ size_t state_bytes(const lgsr_state *s)
 {
     return s->recs.cap + s->rects.cap + s->pk.cap + s->pv.cap + s->long_tiles.cap + s->ranges.cap +
            s->st0.cap + s->st1.cap + s->pose.cap + s->chunks.cap + s->chunk_base.cap + s->slots.cap + s->fixA.cap +
-           s->fixB.cap + s->keys.cap + s->cnt.cap + s->offs.cap + s->counters.cap;
+           s->fixB.cap + s->fixflag.cap + s->keys.cap + s->cnt.cap + s->offs.cap + s->counters.cap;
 }
 
 size_t ctx_bytes(const lgsr_ctx *c)
@@ -425,6 +428,10 @@ lgsr_status forward_end(lgsr_ctx *ctx, lgsr_state *S, const lgsr_frame *out, hip
     HIP_TRY(ensure(S->slots, chunk_slot_floats(items_max > 0 ? items_max : 1) * sizeof(float)), "alloc slots");
     HIP_TRY(ensure(S->fixA, (size_t)rays * sizeof(float4)), "alloc ray state");
     HIP_TRY(ensure(S->fixB, (size_t)rays * sizeof(float4)), "alloc ray state");
+    HIP_TRY(ensure(S->fixflag, (size_t)(items_max > 0 ? items_max : 1) * sizeof(uint32_t)), "alloc chunk flags");
+    if (!(S->fixflag_clean && S->fixflag_seen == S->fixflag.p))
+        HIP_TRY(launch_fill_u32(as<uint32_t>(S->fixflag), 0u, (int64_t)(S->fixflag.cap / 4), s), "clear chunk flags");
+    S->fixflag_clean = false;  // until the raster below has run
     if (P > 0) {
         Stage st_(ctx, LGSR_STAGE_EMIT, s);
         HIP_TRY(launch_emit(as<uint2>(S->rects), n, g, as<uint32_t>(S->offs), S->ids, P, s), "emit");
@@ -451,10 +458,13 @@ lgsr_status forward_end(lgsr_ctx *ctx, lgsr_state *S, const lgsr_frame *out, hip
     R.st1 = as<float4>(S->st1);
     R.fixA = as<float4>(S->fixA);
     R.fixB = as<float4>(S->fixB);
+    R.fixflag = as<uint32_t>(S->fixflag);
     R.seg = seg;
     R.items_max = items_max;
     Stage st_(ctx, LGSR_STAGE_RASTER_FWD, s);
     HIP_TRY(launch_raster_fwd(R, g, S->prm, out->depth, out->opacity, out->normal, out->drop, s), "raster forward");
+    S->fixflag_clean = true;
+    S->fixflag_seen = S->fixflag.p;
     S->P = P;
     return LGSR_OK;
 }

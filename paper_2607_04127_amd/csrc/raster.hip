@@ -270,7 +270,8 @@ __global__ __launch_bounds__(kMergeThreads) void raster_merge_kernel(const uint3
                                                                      float *__restrict__ normal,
                                                                      uint8_t *__restrict__ drop,
                                                                      float4 *__restrict__ st0, float4 *__restrict__ st1,
-                                                                     float4 *__restrict__ fixA, float4 *__restrict__ fixB)
+                                                                     float4 *__restrict__ fixA, float4 *__restrict__ fixB,
+                                                                     uint32_t *__restrict__ fixflag)
 {
     extern __shared__ float msm[];  // ng runs x kMergeRunFloats
     const int ng = (int)(blockDim.x >> 8);
@@ -378,6 +379,7 @@ __global__ __launch_bounds__(kMergeThreads) void raster_merge_kernel(const uint3
     if (fx >= 0) {
         fixA[r] = make_float4(Tf, aA, aD, __int_as_float(aK));
         fixB[r] = make_float4(a0, a1, a2, __int_as_float(fx));
+        fixflag[fx] = 1u;  // the chunk has a ray to re-walk
     } else {
         fixA[r] = make_float4(0.f, 0.f, 0.f, 0.f);
         fixB[r] = make_float4(0.f, 0.f, 0.f, __int_as_float(-1));
@@ -392,11 +394,14 @@ __global__ __launch_bounds__(256) void raster_fixup_kernel(
     const float *__restrict__ rows, const float *__restrict__ cols, Grid g, RasterParams p,
     const float4 *__restrict__ fixA, const float4 *__restrict__ fixB, float *__restrict__ slots,
     float *__restrict__ depth, float *__restrict__ opacity, float *__restrict__ normal, uint8_t *__restrict__ drop,
-    float4 *__restrict__ st0, float4 *__restrict__ st1)
+    float4 *__restrict__ st0, float4 *__restrict__ st1, uint32_t *__restrict__ fixflag)
 {
     __shared__ Staged sm;
     const uint32_t item = (uint32_t)xcd_tile(blockIdx.x, items_max);
     if (item >= *n_items) return;  // whole workgroup
+    if (__builtin_amdgcn_readfirstlane(fixflag[item]) == 0u) return;  // whole workgroup: no ray to re-walk here
+    __syncthreads();                                                  // every wave has read the flag
+    if (threadIdx.x == 0) fixflag[item] = 0u;                         // zero for the next forward
     const uint4 ch = uniform_chunk(chunks, item);
     const Lane L = lane_of((int)ch.x, g);
     const int r = L.valid ? L.k * g.W + L.j : 0;
@@ -722,10 +727,11 @@ hipError_t launch_raster_fwd(const RasterBufs &R, const Grid &g, const RasterPar
                                                    p, R.slots);
     const int ng = merge_groups(g.T);
     raster_merge_kernel<<<g.T, 256 * ng, (size_t)ng * kMergeRunFloats * sizeof(float), s>>>(
-        R.chunk_base, g, p, R.slots, depth, opacity, normal, drop, R.st0, R.st1, R.fixA, R.fixB);
+        R.chunk_base, g, p, R.slots, depth, opacity, normal, drop, R.st0, R.st1, R.fixA, R.fixB, R.fixflag);
     if (im > 0)
         raster_fixup_kernel<<<im, 256, 0, s>>>(R.chunks, R.n_items, im, R.ids, R.recs, R.rects, R.rows, R.cols, g, p,
-                                               R.fixA, R.fixB, R.slots, depth, opacity, normal, drop, R.st0, R.st1);
+                                               R.fixA, R.fixB, R.slots, depth, opacity, normal, drop, R.st0, R.st1,
+                                               R.fixflag);
     return hipGetLastError();
 }
 
