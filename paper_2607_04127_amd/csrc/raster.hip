@@ -552,7 +552,11 @@ __device__ __forceinline__ float wave_sum16(const float (&g)[16], int lane)
         b[i] = v;
     }
     const int k = lane & 15;
-    return k == 0 ? b[0] : (k == 1 ? b[1] : (k == 2 ? b[2] : b[3]));
+    float r = b[0];
+    r = k == 1 ? b[1] : r;
+    r = k == 2 ? b[2] : r;
+    r = k == 3 ? b[3] : r;
+    return r;
 }
 
 __device__ __forceinline__ int wave_max_i(int v)
@@ -608,53 +612,51 @@ __global__ __launch_bounds__(256) void raster_bwd_chunk_kernel(
             const int pos = (int)(base + e);
             if (pos > wmax) continue;
             const Rec s = staged_rec(sm, e);
+            // every lane tests; the wave goes on only if some lane composites this entry, and
+            // then runs the composite arithmetic on full waves, keeping its results (the
+            // recurrence of T and B, the 13 gradient values) on the contributing lanes only
+            const Hit h = hit_test(s, ray, p);
+            const bool contrib = pos <= last && h.pass;
+            if (!__any(contrib)) continue;
+            const float one_m = 1.f - h.ah;
+            const float r1m = __builtin_amdgcn_rcpf(one_m);
+            const float Tj = T * r1m;
+            const float w = Tj * h.ah;
+            const float cj = fmaf(gbD, h.t, fmaf(gbN0, s.nt0, fmaf(gbN1, s.nt1, fmaf(gbN2, s.nt2, gbA))));
+            const float dah = fmaf(Tj, cj, -B * r1m);
+            const float Bn = fmaf(w, cj, B);
+            T = contrib ? Tj : T;
+            B = contrib ? Bn : B;
+            const float dt = gbD * w;
+            // a clamped alpha_hat passes no gradient to alpha and G
+            const float dahc = h.aG < p.alpha_max ? dah : 0.f;
+            const float dalpha = dahc * h.G, dG = dahc * s.alpha;
+            const float dq2 = -0.5f * h.G * dG;
+            const float u = h.nu * h.inv, v = h.nv * h.inv;
+            const float du = 2.f * u * dq2, dv = 2.f * v * dq2;
+            const float dnu = du * h.inv, dnv = dv * h.inv;
+            const float dden = -fmaf(du, u, fmaf(dv, v, dt * h.t)) * h.inv;
             float gv[16];
+            gv[G_NT + 0] = fmaf(gbN0, w, dden * ray.dh[0]);
+            gv[G_NT + 1] = fmaf(gbN1, w, dden * ray.dh[1]);
+            gv[G_NT + 2] = fmaf(gbN2, w, dden * ray.dh[2]);
+            gv[G_C] = dt * h.inv;
+            gv[G_CU] = dnu;
+            gv[G_U + 0] = dnu * h.e[0];
+            gv[G_U + 1] = dnu * h.e[1];
+            gv[G_U + 2] = dnu * h.e[2];
+            gv[G_CV] = dnv;
+            gv[G_V + 0] = dnv * h.e[0];
+            gv[G_V + 1] = dnv * h.e[1];
+            gv[G_V + 2] = dnv * h.e[2];
+            gv[G_ALPHA] = dalpha;
 #pragma unroll
-            for (int c = 0; c < 16; ++c) gv[c] = 0.f;
-            bool contrib = false;
-            if (pos <= last) {
-                const Hit h = hit_test(s, ray, p);
-                if (h.pass) {
-                    contrib = true;
-                    const float one_m = 1.f - h.ah;
-                    const float r1m = __builtin_amdgcn_rcpf(one_m);
-                    const float Tj = T * r1m;
-                    const float w = Tj * h.ah;
-                    const float cj = fmaf(gbD, h.t, fmaf(gbN0, s.nt0, fmaf(gbN1, s.nt1, fmaf(gbN2, s.nt2, gbA))));
-                    const float dah = fmaf(Tj, cj, -B * r1m);
-                    B = fmaf(w, cj, B);
-                    T = Tj;
-                    const float dt = gbD * w;
-                    float dalpha = 0.f, dG = 0.f;
-                    if (h.aG < p.alpha_max) {
-                        dalpha = dah * h.G;
-                        dG = dah * s.alpha;
-                    }
-                    const float dq2 = -0.5f * h.G * dG;
-                    const float u = h.nu * h.inv, v = h.nv * h.inv;
-                    const float du = 2.f * u * dq2, dv = 2.f * v * dq2;
-                    const float dnu = du * h.inv, dnv = dv * h.inv;
-                    const float dden = -fmaf(du, u, fmaf(dv, v, dt * h.t)) * h.inv;
-                    gv[G_NT + 0] = fmaf(gbN0, w, dden * ray.dh[0]);
-                    gv[G_NT + 1] = fmaf(gbN1, w, dden * ray.dh[1]);
-                    gv[G_NT + 2] = fmaf(gbN2, w, dden * ray.dh[2]);
-                    gv[G_C] = dt * h.inv;
-                    gv[G_CU] = dnu;
-                    gv[G_U + 0] = dnu * h.e[0];
-                    gv[G_U + 1] = dnu * h.e[1];
-                    gv[G_U + 2] = dnu * h.e[2];
-                    gv[G_CV] = dnv;
-                    gv[G_V + 0] = dnv * h.e[0];
-                    gv[G_V + 1] = dnv * h.e[1];
-                    gv[G_V + 2] = dnv * h.e[2];
-                    gv[G_ALPHA] = dalpha;
-                }
-            }
-            if (__any(contrib)) {
-                const float mine = wave_sum16(gv, L.lane);
-                const int k = L.lane & 15, c = 4 * (L.lane >> 4) + k;
-                if (k < 4 && c < kGradUsed) unsafeAtomicAdd(recgrad + (size_t)sm.id[e] * kGrad + c, mine);
-            }
+            for (int c = 0; c < kGradUsed; ++c) gv[c] = contrib ? gv[c] : 0.f;
+#pragma unroll
+            for (int c = kGradUsed; c < 16; ++c) gv[c] = 0.f;
+            const float mine = wave_sum16(gv, L.lane);
+            const int k = L.lane & 15, c = 4 * (L.lane >> 4) + k;
+            if (k < 4 && c < kGradUsed) unsafeAtomicAdd(recgrad + (size_t)sm.id[e] * kGrad + c, mine);
         }
     }
 }
