@@ -428,7 +428,7 @@ lgsr_status forward_end(lgsr_ctx *ctx, lgsr_state *S, const lgsr_frame *out, hip
     HIP_TRY(ensure(S->slots, chunk_slot_floats(items_max > 0 ? items_max : 1) * sizeof(float)), "alloc slots");
     HIP_TRY(ensure(S->fixA, (size_t)rays * sizeof(float4)), "alloc ray state");
     HIP_TRY(ensure(S->fixB, (size_t)rays * sizeof(float4)), "alloc ray state");
-    HIP_TRY(ensure(S->fixflag, (size_t)(items_max > 0 ? items_max : 1) * sizeof(uint32_t)), "alloc chunk flags");
+    HIP_TRY(ensure(S->fixflag, (size_t)(items_max > 0 ? 4 * items_max : 1) * sizeof(uint32_t)), "alloc chunk flags");
     if (!(S->fixflag_clean && S->fixflag_seen == S->fixflag.p))
         HIP_TRY(launch_fill_u32(as<uint32_t>(S->fixflag), 0u, (int64_t)(S->fixflag.cap / 4), s), "clear chunk flags");
     S->fixflag_clean = false;  // until the raster below has run

@@ -70,8 +70,9 @@ struct RasterBufs {
     float *slots;          // chunk_slot_floats(items_max)
     float4 *st0, *st1;     // per ray
     float4 *fixA, *fixB;   // per ray
-    uint32_t *fixflag;     // items_max: nonzero when a ray's fix-up falls in the chunk; zero
-                           // between forwards (the fix-up clears what the merge set)
+    uint32_t *fixflag;     // 4 x items_max, per (chunk, sub-tile): nonzero when a ray's fix-up
+                           // falls there; zero between forwards (the fix-up clears what the
+                           // merge set)
     int seg;
     int64_t items_max;
 };

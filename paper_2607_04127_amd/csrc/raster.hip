@@ -1,13 +1,12 @@
 // raster.hip -- chunk-parallel front-to-back compositing and its reverse-order backward.
 //
 // Each tile (16 x 16 rays) owns a range-sorted list of surfels.  The lists are cut into
-// chunks of `seg` entries; a chunk is one workgroup whose four wavefronts own the tile's
-// four 8 x 8 sub-tiles (one ray per lane).  The workgroup first stages the chunk's surfel
-// ids, ray rectangles and 64-byte records in LDS with coalesced vector loads; each wave
-// then walks the staged entries on its own, skipping (scalar branch) entries whose
-// rectangle misses its sub-tile and broadcasting the others' records from LDS.  Chunking
-// spreads long lists over many workgroups (load balance) and keeps several waves per SIMD
-// resident (latency hiding).
+// chunks of `seg` entries.  A task is one (chunk, 8 x 8 sub-tile) pair and runs as a
+// workgroup of one wavefront (one ray per lane): it stages, 64 list entries at a time, the
+// ids and 64-byte records of the entries whose ray rectangle meets its sub-tile in LDS with
+// coalesced vector loads, then walks them broadcasting each record from LDS.  Chunking
+// spreads long lists over many workgroups (load balance); one-wave workgroups keep the
+// SIMDs filled when sub-tiles of one chunk differ widely in cost.
 //
 // Compositing (Sec. 3.1 / 3.4 rendering with the 2DGS surfel), per ray and hit:
 //   w = T alpha_hat, A += w, S_D += w t, S_N += w nt, T *= 1 - alpha_hat, stop once T < T_min.
@@ -81,97 +80,85 @@ __device__ __forceinline__ uint4 uniform_chunk(const uint4 *__restrict__ chunks,
                       __builtin_amdgcn_readfirstlane(c.z), 0u);
 }
 
-// A chunk's list entries staged in LDS by the whole workgroup: surfel ids, the 64-byte
-// records (coalesced vector loads, one memory latency per stage) and, for each of the four
-// waves, the compacted in-order list of entries whose ray rectangle meets the wave's
-// sub-tile (one packed block-wide prefix count), so that a wave walks only its own entries
-// with no per-entry test and records no wave needs are never loaded.
-constexpr int kStage = 256;
-struct Staged {
-    float4 rec[kStage][4];
-    uint32_t id[kStage];
-    uint16_t list[4][kStage];
-    uint8_t mask[kStage];
-    uint64_t wtot[4];
-    uint32_t cnt[4];
+// One wavefront per task (chunk item, sub-tile wave): a workgroup of one wave, so that a
+// slot frees as soon as its sub-tile is done and sub-tiles of very different cost do not
+// hold each other's LDS.  Blocks are dealt to the 8 XCDs round-robin; the task of block b
+// keeps an item's four waves on one XCD (they read the same list entries) while consecutive
+// items go to different XCDs (dense and sparse azimuth sectors are spread evenly).  The
+// grid is a multiple of 32 blocks.
+__device__ __forceinline__ uint32_t task_of(uint32_t b) { return (b >> 5) * 32u + (b & 7u) * 4u + ((b >> 3) & 3u); }
+
+constexpr int kTaskGroup = 32;
+static unsigned task_blocks(int items) { return (unsigned)(((int64_t)4 * items + kTaskGroup - 1) / kTaskGroup * kTaskGroup); }
+
+// Up to 64 list entries staged in LDS by one wave: of the entries whose ray rectangle meets
+// the wave's sub-tile, in list order, the surfel ids, list positions and 64-byte records
+// (coalesced vector loads, one memory latency per stage).  Entries the sub-tile does not
+// meet are never loaded.
+constexpr int kWStage = 64;
+constexpr int kChunkMax = 256;  // longest chunk the automatic choice makes
+struct WaveStage {
+    float4 rec[kWStage][4];
+    uint32_t id[kWStage];
+    uint32_t pos[kWStage];
 };
 
-// All 256 threads; n <= kStage entries from list position a; (r16, c16) is the tile origin.
-// Ends with a barrier.
-__device__ __forceinline__ void stage_entries(Staged &sm, const uint32_t *__restrict__ ids,
-                                              const float *__restrict__ recs, const uint2 *__restrict__ rects,
-                                              uint32_t a, uint32_t n, int r16, int c16, int H, int W)
+// Stages list entries [a, a + n), n <= 64; returns how many meet the sub-tile (uniform).
+__device__ __forceinline__ uint32_t stage_wave(WaveStage &ws, const uint32_t *__restrict__ ids,
+                                               const float *__restrict__ recs, const uint2 *__restrict__ rects,
+                                               uint32_t a, uint32_t n, const Lane &L, int W)
 {
-    const int t = threadIdx.x, wv = t >> 6, l = t & 63;
-    uint32_t m = 0;
-    if ((uint32_t)t < n) {
-        const uint32_t id = ids[a + t];
-        const uint2 rc = rects[id];
-        sm.id[t] = id;
-#pragma unroll
-        for (int w = 0; w < 4; ++w) {
-            const int sr = r16 + (w >> 1) * kSub, sc = c16 + (w & 1) * kSub;
-            if (sr < H && sc < W && sub_overlap(rc, sr, sc, W)) m |= 1u << w;
-        }
+    const uint32_t l = (uint32_t)L.lane;
+    bool meet = false;
+    uint32_t id = 0;
+    if (l < n) {
+        id = ids[a + l];
+        meet = sub_overlap(rects[id], L.sr0, L.sc0, W);
     }
-    sm.mask[t] = (uint8_t)m;
-    // exclusive prefix counts of the four membership flags, 16-bit fields of one u64
-    const uint64_t packed = (uint64_t)(m & 1u) | ((uint64_t)((m >> 1) & 1u) << 16) |
-                            ((uint64_t)((m >> 2) & 1u) << 32) | ((uint64_t)((m >> 3) & 1u) << 48);
-    uint64_t inc = packed;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const uint64_t y = __shfl_up(inc, o, 64);
-        if (l >= o) inc += y;
+    const uint64_t bal = __ballot(meet);
+    const uint32_t m = __builtin_amdgcn_readfirstlane((uint32_t)__popcll(bal));
+    const uint32_t k = __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+    if (meet) {
+        ws.id[k] = id;
+        ws.pos[k] = a + l;
     }
-    if (l == 63) sm.wtot[wv] = inc;
     __syncthreads();
-    uint64_t off = 0, tot = 0;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const uint64_t s = sm.wtot[k];
-        off += k < wv ? s : 0ull;
-        tot += s;
-    }
-    const uint64_t excl = off + inc - packed;
-#pragma unroll
-    for (int w = 0; w < 4; ++w)
-        if ((m >> w) & 1u) sm.list[w][(excl >> (16 * w)) & 0xFFFFu] = (uint16_t)t;
-    if (t < 4) sm.cnt[t] = (uint32_t)((tot >> (16 * t)) & 0xFFFFu);
-    __syncthreads();
+    // record quarter q = l + 64 j of entry q / 4: all loads issued before the first store
     const float4 *r4 = reinterpret_cast<const float4 *>(recs);
-    for (uint32_t k = t; k < 4u * n; k += 256u) {
-        const uint32_t e = k >> 2, q = k & 3u;
-        if (sm.mask[e]) sm.rec[e][q] = r4[(size_t)sm.id[e] * 4 + q];
-    }
+    const uint32_t lim = 4u * m;
+    auto ld = [&](uint32_t q) { return q < lim ? r4[(size_t)ws.id[q >> 2] * 4 + (q & 3u)] : make_float4(0.f, 0.f, 0.f, 0.f); };
+    auto st = [&](uint32_t q, float4 v) {
+        if (q < lim) ws.rec[q >> 2][q & 3u] = v;
+    };
+    const float4 v0 = ld(l), v1 = ld(l + 64u), v2 = ld(l + 128u), v3 = ld(l + 192u);
+    st(l, v0);
+    st(l + 64u, v1);
+    st(l + 128u, v2);
+    st(l + 192u, v3);
     __syncthreads();
+    return m;
 }
 
-__device__ __forceinline__ Rec staged_rec(const Staged &sm, uint32_t e)
+__device__ __forceinline__ Rec staged_rec(const WaveStage &ws, uint32_t i)
 {
-    const float4 x = sm.rec[e][0], y = sm.rec[e][1], z = sm.rec[e][2], w = sm.rec[e][3];
+    const float4 x = ws.rec[i][0], y = ws.rec[i][1], z = ws.rec[i][2], w = ws.rec[i][3];
     return Rec{x.x, x.y, x.z, x.w, y.x, y.y, y.z, y.w, z.x, z.y, z.z, z.w, w.x, w.y, w.z, w.w};
 }
 
 // Composite list entries [a, b) for this wave's rays, starting from acc (transmittance
-// acc.T); lanes with `active` false only follow along.  A lane stops once T < T_min.
-// Every thread of the workgroup must call this (it stages through LDS with barriers).
-__device__ __forceinline__ void composite(Staged &sm, const uint32_t *__restrict__ ids,
+// acc.T); lanes with `active` false only follow along.  A lane stops once T < T_min; the
+// wave stops, and stages nothing more, once all of its lanes have.
+__device__ __forceinline__ void composite(WaveStage &ws, const uint32_t *__restrict__ ids,
                                           const float *__restrict__ recs, const uint2 *__restrict__ rects,
                                           uint32_t a, uint32_t b, const Lane &L, const Ray &ray,
-                                          const RasterParams &p, int H, int W, bool active, Acc &acc)
+                                          const RasterParams &p, int W, bool active, Acc &acc)
 {
     bool done = !active || !L.wave_in;
-    const int r16 = L.sr0 - (L.wave >> 1) * kSub, c16 = L.sc0 - (L.wave & 1) * kSub;
-    for (uint32_t base = a; base < b; base += kStage) {
-        const uint32_t n = min((uint32_t)kStage, b - base);
-        if (base != a) __syncthreads();  // the previous stage is no longer read
-        stage_entries(sm, ids, recs, rects, base, n, r16, c16, H, W);
-        if (__all(done)) continue;
-        const uint32_t cnt = __builtin_amdgcn_readfirstlane(sm.cnt[L.wave]);
-        for (uint32_t i = 0; i < cnt; ++i) {
-            const uint32_t e = __builtin_amdgcn_readfirstlane(sm.list[L.wave][i]);
-            const Rec s = staged_rec(sm, e);
+    for (uint32_t base = a; base < b; base += kWStage) {
+        if (__all(done)) return;
+        const uint32_t m = stage_wave(ws, ids, recs, rects, base, min((uint32_t)kWStage, b - base), L, W);
+        for (uint32_t i = 0; i < m; ++i) {
+            const Rec s = staged_rec(ws, i);
             const Hit h = hit_test(s, ray, p);
             if (h.pass && !done) {
                 float w = acc.T * h.ah;
@@ -182,27 +169,29 @@ __device__ __forceinline__ void composite(Staged &sm, const uint32_t *__restrict
                 acc.SN2 = fmaf(w, s.nt2, acc.SN2);
                 acc.T = acc.T * (1.f - h.ah);
                 ++acc.K;
-                acc.last = (int)(base + e);
+                acc.last = (int)ws.pos[i];
                 done = acc.T < p.T_min;
             }
             if (__all(done)) break;
         }
+        __syncthreads();  // the stage is no longer read
     }
 }
 
-__global__ __launch_bounds__(256) void raster_fwd_chunk_kernel(
-    const uint4 *__restrict__ chunks, const uint32_t *__restrict__ n_items, int items_max,
-    const uint32_t *__restrict__ ids, const float *__restrict__ recs, const uint2 *__restrict__ rects,
-    const float *__restrict__ rows, const float *__restrict__ cols, Grid g, RasterParams p, float *__restrict__ slots)
+__global__ __launch_bounds__(64) void raster_fwd_chunk_kernel(
+    const uint4 *__restrict__ chunks, const uint32_t *__restrict__ n_items, const uint32_t *__restrict__ ids,
+    const float *__restrict__ recs, const uint2 *__restrict__ rects, const float *__restrict__ rows,
+    const float *__restrict__ cols, Grid g, RasterParams p, float *__restrict__ slots)
 {
-    __shared__ Staged sm;
-    const uint32_t item = (uint32_t)xcd_tile(blockIdx.x, items_max);
-    if (item >= *n_items) return;  // whole workgroup
+    __shared__ WaveStage ws;
+    const uint32_t task = task_of(blockIdx.x), item = task >> 2;
+    if (item >= *n_items) return;
     const uint4 ch = uniform_chunk(chunks, item);
-    const Lane L = lane_of((int)ch.x, g);
+    const Lane L = lane_of((int)ch.x, g, (int)((task & 3u) * 64u + threadIdx.x));
+    if (!L.wave_in) return;  // the sub-tile lies outside the image
     Ray ray = make_ray(rows, cols, L.valid ? L.k : 0, L.valid ? L.j : 0);
     Acc acc{1.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0, -1};
-    composite(sm, ids, recs, rects, ch.y, ch.z, L, ray, p, g.H, g.W, L.valid, acc);
+    composite(ws, ids, recs, rects, ch.y, ch.z, L, ray, p, g.W, L.valid, acc);
     if (!L.valid) return;
     slots[slot(item, F_TEND, L.rt)] = acc.T;
     slots[slot(item, F_SA, L.rt)] = acc.A;
@@ -379,7 +368,7 @@ __global__ __launch_bounds__(kMergeThreads) void raster_merge_kernel(const uint3
     if (fx >= 0) {
         fixA[r] = make_float4(Tf, aA, aD, __int_as_float(aK));
         fixB[r] = make_float4(a0, a1, a2, __int_as_float(fx));
-        fixflag[fx] = 1u;  // the chunk has a ray to re-walk
+        fixflag[fx * 4 + L.wave] = 1u;  // the chunk has a ray of this sub-tile to re-walk
     } else {
         fixA[r] = make_float4(0.f, 0.f, 0.f, 0.f);
         fixB[r] = make_float4(0.f, 0.f, 0.f, __int_as_float(-1));
@@ -388,22 +377,22 @@ __global__ __launch_bounds__(kMergeThreads) void raster_merge_kernel(const uint3
 }
 
 // Re-walk the chunk in which a ray terminates, from its true transmittance, and finish it.
-__global__ __launch_bounds__(256) void raster_fixup_kernel(
-    const uint4 *__restrict__ chunks, const uint32_t *__restrict__ n_items, int items_max,
-    const uint32_t *__restrict__ ids, const float *__restrict__ recs, const uint2 *__restrict__ rects,
-    const float *__restrict__ rows, const float *__restrict__ cols, Grid g, RasterParams p,
-    const float4 *__restrict__ fixA, const float4 *__restrict__ fixB, float *__restrict__ slots,
-    float *__restrict__ depth, float *__restrict__ opacity, float *__restrict__ normal, uint8_t *__restrict__ drop,
-    float4 *__restrict__ st0, float4 *__restrict__ st1, uint32_t *__restrict__ fixflag)
+// One wave per (chunk, sub-tile) task, flagged by the merge.
+__global__ __launch_bounds__(64) void raster_fixup_kernel(
+    const uint4 *__restrict__ chunks, const uint32_t *__restrict__ n_items, const uint32_t *__restrict__ ids,
+    const float *__restrict__ recs, const uint2 *__restrict__ rects, const float *__restrict__ rows,
+    const float *__restrict__ cols, Grid g, RasterParams p, const float4 *__restrict__ fixA,
+    const float4 *__restrict__ fixB, float *__restrict__ slots, float *__restrict__ depth, float *__restrict__ opacity,
+    float *__restrict__ normal, uint8_t *__restrict__ drop, float4 *__restrict__ st0, float4 *__restrict__ st1,
+    uint32_t *__restrict__ fixflag)
 {
-    __shared__ Staged sm;
-    const uint32_t item = (uint32_t)xcd_tile(blockIdx.x, items_max);
-    if (item >= *n_items) return;  // whole workgroup
-    if (__builtin_amdgcn_readfirstlane(fixflag[item]) == 0u) return;  // whole workgroup: no ray to re-walk here
-    __syncthreads();                                                  // every wave has read the flag
-    if (threadIdx.x == 0) fixflag[item] = 0u;                         // zero for the next forward
+    __shared__ WaveStage ws;
+    const uint32_t task = task_of(blockIdx.x), item = task >> 2;
+    if (item >= *n_items) return;
+    if (__builtin_amdgcn_readfirstlane(fixflag[task]) == 0u) return;  // no ray of this sub-tile re-walks here
+    if (threadIdx.x == 0) fixflag[task] = 0u;                         // zero for the next forward
     const uint4 ch = uniform_chunk(chunks, item);
-    const Lane L = lane_of((int)ch.x, g);
+    const Lane L = lane_of((int)ch.x, g, (int)((task & 3u) * 64u + threadIdx.x));
     const int r = L.valid ? L.k * g.W + L.j : 0;
     float4 fa = make_float4(0.f, 0.f, 0.f, 0.f), fb = make_float4(0.f, 0.f, 0.f, __int_as_float(-1));
     if (L.valid) {
@@ -411,10 +400,10 @@ __global__ __launch_bounds__(256) void raster_fixup_kernel(
         fa = fixA[r];
     }
     const bool pend = L.valid && __float_as_int(fb.w) == (int)item;
-    if (!__syncthreads_or(pend)) return;  // whole workgroup
+    if (!__any(pend)) return;
     Ray ray = make_ray(rows, cols, L.valid ? L.k : 0, L.valid ? L.j : 0);
     Acc acc{pend ? fa.x : 1.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0, -1};
-    composite(sm, ids, recs, rects, ch.y, ch.z, L, ray, p, g.H, g.W, pend, acc);
+    composite(ws, ids, recs, rects, ch.y, ch.z, L, ray, p, g.W, pend, acc);
     if (!pend) return;
     slots[slot(item, F_TEND, L.rt)] = acc.T;
     slots[slot(item, F_SA, L.rt)] = acc.A;
@@ -566,18 +555,17 @@ __device__ __forceinline__ int wave_max_i(int v)
     return v;
 }
 
-__global__ __launch_bounds__(256) void raster_bwd_chunk_kernel(
-    const uint4 *__restrict__ chunks, const uint32_t *__restrict__ n_items, int items_max,
-    const uint32_t *__restrict__ ids, const float *__restrict__ recs, const uint2 *__restrict__ rects,
-    const float *__restrict__ rows, const float *__restrict__ cols, Grid g, RasterParams p,
-    const float *__restrict__ slots, const float4 *__restrict__ gb0, const float *__restrict__ gb1,
-    float *__restrict__ recgrad)
+__global__ __launch_bounds__(64) void raster_bwd_chunk_kernel(
+    const uint4 *__restrict__ chunks, const uint32_t *__restrict__ n_items, const uint32_t *__restrict__ ids,
+    const float *__restrict__ recs, const uint2 *__restrict__ rects, const float *__restrict__ rows,
+    const float *__restrict__ cols, Grid g, RasterParams p, const float *__restrict__ slots,
+    const float4 *__restrict__ gb0, const float *__restrict__ gb1, float *__restrict__ recgrad)
 {
-    __shared__ Staged sm;
-    const uint32_t item = (uint32_t)xcd_tile(blockIdx.x, items_max);
-    if (item >= *n_items) return;  // whole workgroup
+    __shared__ WaveStage ws;
+    const uint32_t task = task_of(blockIdx.x), item = task >> 2;
+    if (item >= *n_items) return;
     const uint4 ch = uniform_chunk(chunks, item);
-    const Lane L = lane_of((int)ch.x, g);
+    const Lane L = lane_of((int)ch.x, g, (int)((task & 3u) * 64u + threadIdx.x));
     Ray ray = make_ray(rows, cols, L.valid ? L.k : 0, L.valid ? L.j : 0);
     int last = -1;
     float T = 1.f, B = 0.f, gbD = 0.f, gbN0 = 0.f, gbN1 = 0.f, gbN2 = 0.f, gbA = 0.f;
@@ -596,22 +584,17 @@ __global__ __launch_bounds__(256) void raster_bwd_chunk_kernel(
         }
     }
     const int wmax = wave_max_i(last);
-    if (!__syncthreads_or(last >= 0)) return;  // whole workgroup: nothing to propagate
+    if (wmax < 0) return;  // nothing to propagate
     const uint32_t a = ch.y, b = ch.z;
-    const int r16 = L.sr0 - (L.wave >> 1) * kSub, c16 = L.sc0 - (L.wave & 1) * kSub;
-    const uint32_t nstages = (b - a + kStage - 1) / kStage;
+    const uint32_t nstages = (b - a + kWStage - 1) / kWStage;
     for (uint32_t sidx = nstages; sidx-- > 0;) {
-        const uint32_t base = a + sidx * kStage;
-        const uint32_t n = min((uint32_t)kStage, b - base);
-        if (sidx + 1 != nstages) __syncthreads();  // the previous stage is no longer read
-        stage_entries(sm, ids, recs, rects, base, n, r16, c16, g.H, g.W);
+        const uint32_t base = a + sidx * kWStage;
         if (wmax < (int)base) continue;
-        const uint32_t cnt = __builtin_amdgcn_readfirstlane(sm.cnt[L.wave]);
-        for (uint32_t i = cnt; i-- > 0;) {
-            const uint32_t e = __builtin_amdgcn_readfirstlane(sm.list[L.wave][i]);
-            const int pos = (int)(base + e);
+        const uint32_t m = stage_wave(ws, ids, recs, rects, base, min((uint32_t)kWStage, b - base), L, g.W);
+        for (uint32_t i = m; i-- > 0;) {
+            const int pos = (int)__builtin_amdgcn_readfirstlane(ws.pos[i]);
             if (pos > wmax) continue;
-            const Rec s = staged_rec(sm, e);
+            const Rec s = staged_rec(ws, i);
             // every lane tests; the wave goes on only if some lane composites this entry, and
             // then runs the composite arithmetic on full waves, keeping its results (the
             // recurrence of T and B, the 13 gradient values) on the contributing lanes only
@@ -656,8 +639,9 @@ __global__ __launch_bounds__(256) void raster_bwd_chunk_kernel(
             for (int c = kGradUsed; c < 16; ++c) gv[c] = 0.f;
             const float mine = wave_sum16(gv, L.lane);
             const int k = L.lane & 15, c = 4 * (L.lane >> 4) + k;
-            if (k < 4 && c < kGradUsed) unsafeAtomicAdd(recgrad + (size_t)sm.id[e] * kGrad + c, mine);
+            if (k < 4 && c < kGradUsed) unsafeAtomicAdd(recgrad + (size_t)ws.id[i] * kGrad + c, mine);
         }
+        __syncthreads();  // the stage is no longer read
     }
 }
 
@@ -707,11 +691,11 @@ int chunk_size(int64_t P, int requested)
 {
     if (requested > 0) return requested;
     // about 4096 chunks (several rounds of 8 resident waves on each of 1024 SIMDs; short
-    // chunks also keep the re-walk of a terminating ray short), at most one LDS stage each
+    // chunks also keep the re-walk of a terminating ray short), at most kChunkMax entries
     int64_t s = (P + 4095) / 4096;
     s = (s + 15) / 16 * 16;
     if (s < 32) s = 32;
-    if (s > kStage) s = kStage;
+    if (s > kChunkMax) s = kChunkMax;
     return (int)s;
 }
 
@@ -725,15 +709,15 @@ hipError_t launch_raster_fwd(const RasterBufs &R, const Grid &g, const RasterPar
     if (g.T <= 0) return hipSuccess;
     const int im = (int)R.items_max;
     if (im > 0)
-        raster_fwd_chunk_kernel<<<im, 256, 0, s>>>(R.chunks, R.n_items, im, R.ids, R.recs, R.rects, R.rows, R.cols, g,
-                                                   p, R.slots);
+        raster_fwd_chunk_kernel<<<task_blocks(im), 64, 0, s>>>(R.chunks, R.n_items, R.ids, R.recs, R.rects, R.rows,
+                                                               R.cols, g, p, R.slots);
     const int ng = merge_groups(g.T);
     raster_merge_kernel<<<g.T, 256 * ng, (size_t)ng * kMergeRunFloats * sizeof(float), s>>>(
         R.chunk_base, g, p, R.slots, depth, opacity, normal, drop, R.st0, R.st1, R.fixA, R.fixB, R.fixflag);
     if (im > 0)
-        raster_fixup_kernel<<<im, 256, 0, s>>>(R.chunks, R.n_items, im, R.ids, R.recs, R.rects, R.rows, R.cols, g, p,
-                                               R.fixA, R.fixB, R.slots, depth, opacity, normal, drop, R.st0, R.st1,
-                                               R.fixflag);
+        raster_fixup_kernel<<<task_blocks(im), 64, 0, s>>>(R.chunks, R.n_items, R.ids, R.recs, R.rects, R.rows,
+                                                           R.cols, g, p, R.fixA, R.fixB, R.slots, depth, opacity,
+                                                           normal, drop, R.st0, R.st1, R.fixflag);
     return hipGetLastError();
 }
 
@@ -758,8 +742,8 @@ hipError_t launch_raster_bwd(const RasterBufs &R, const Grid &g, const RasterPar
 {
     const int im = (int)R.items_max;
     if (g.T <= 0 || im <= 0) return hipSuccess;
-    raster_bwd_chunk_kernel<<<im, 256, 0, s>>>(R.chunks, R.n_items, im, R.ids, R.recs, R.rects, R.rows, R.cols, g, p,
-                                               R.slots, gb0, gb1, recgrad);
+    raster_bwd_chunk_kernel<<<task_blocks(im), 64, 0, s>>>(R.chunks, R.n_items, R.ids, R.recs, R.rects, R.rows,
+                                                           R.cols, g, p, R.slots, gb0, gb1, recgrad);
     return hipGetLastError();
 }
 
