@@ -4,9 +4,9 @@
 //   L = w_depth / |Omega_D| sum M_D |D^ - D| + lambda_n lambda_ng / |Omega_N| sum M_N (1 - N^.N / |N^|)
 //   M_D = [D > 0], M_N = M_D [|N| > 0]
 //
-// Three launches: per-block partial sums (two float sums, two integer counts), one block
-// that folds the partials in a fixed order (deterministic) into loss_out[5], and the
-// per-ray gradient, which needs the global counts.
+// Two launches: per-block partial sums (two float sums, two integer counts), then the
+// per-ray gradient, whose workgroups each fold the partials in a fixed order
+// (deterministic) for the global counts, the first one also writing loss_out[5].
 #include "lgsr_internal.h"
 #include "lgsr_kernels.h"
 
@@ -81,63 +81,59 @@ __global__ __launch_bounds__(kLossThreads) void loss_partials(int64_t n, const f
     }
 }
 
-// One workgroup: thread t adds partials t, t + 256, ... in order, then a fixed tree folds
-// the 256 sums (deterministic); counts are exact integers.
-__global__ __launch_bounds__(kLossThreads) void loss_finalize(int nb, const float *__restrict__ partials,
-                                                              float w_depth, float lambda_n, float lambda_ng,
-                                                              float *__restrict__ loss_out)
-{
-    __shared__ float s1[kLossThreads], s2[kLossThreads];
-    __shared__ uint32_t k1[kLossThreads], k2[kLossThreads];
-    const int t = threadIdx.x;
-    float l1 = 0.f, cs = 0.f;
-    uint32_t cD = 0, cN = 0;
-    for (int b = t; b < nb; b += kLossThreads) {
-        l1 += partials[4 * b];
-        cs += partials[4 * b + 1];
-        cD += __float_as_uint(partials[4 * b + 2]);
-        cN += __float_as_uint(partials[4 * b + 3]);
-    }
-    s1[t] = l1;
-    s2[t] = cs;
-    k1[t] = cD;
-    k2[t] = cN;
-    __syncthreads();
-    for (int o = kLossThreads / 2; o > 0; o >>= 1) {
-        if (t < o) {
-            s1[t] += s1[t + o];
-            s2[t] += s2[t + o];
-            k1[t] += k1[t + o];
-            k2[t] += k2[t + o];
-        }
-        __syncthreads();
-    }
-    if (t != 0) return;
-    l1 = s1[0];
-    cs = s2[0];
-    cD = k1[0];
-    cN = k2[0];
-    float td = cD ? w_depth * l1 / (float)cD : 0.f;
-    float tn = cN ? lambda_n * lambda_ng * cs / (float)cN : 0.f;
-    loss_out[0] = td + tn;
-    loss_out[1] = td;
-    loss_out[2] = tn;
-    loss_out[3] = (float)cD;
-    loss_out[4] = (float)cN;
-}
-
+// Per-ray gradient.  It needs the global counts: every workgroup first folds the partials
+// (thread t adds partials t, t + 256, ... in order, then a fixed tree folds the 256 sums;
+// counts are exact integers, the float sums come out the same in every workgroup), and
+// workgroup 0 writes loss_out.  This saves a separate one-workgroup launch.
 __global__ __launch_bounds__(kLossThreads) void loss_grad(int64_t n, const float *__restrict__ depth,
                                                           const float *__restrict__ normal,
                                                           const float *__restrict__ td,
                                                           const float *__restrict__ tn, float w_depth,
-                                                          float lambda_n, float lambda_ng,
-                                                          const float *__restrict__ loss_out,
-                                                          float *__restrict__ gD, float *__restrict__ gA,
-                                                          float *__restrict__ gN)
+                                                          float lambda_n, float lambda_ng, int nb,
+                                                          const float *__restrict__ partials,
+                                                          float *__restrict__ loss_out, float *__restrict__ gD,
+                                                          float *__restrict__ gA, float *__restrict__ gN)
 {
-    int64_t r = (int64_t)blockIdx.x * kLossThreads + threadIdx.x;
+    __shared__ float s1[kLossThreads], s2[kLossThreads];
+    __shared__ uint32_t k1[kLossThreads], k2[kLossThreads];
+    const int t = threadIdx.x;
+    {
+        float l1 = 0.f, cs = 0.f;
+        uint32_t cD = 0, cN = 0;
+        for (int b = t; b < nb; b += kLossThreads) {
+            l1 += partials[4 * b];
+            cs += partials[4 * b + 1];
+            cD += __float_as_uint(partials[4 * b + 2]);
+            cN += __float_as_uint(partials[4 * b + 3]);
+        }
+        s1[t] = l1;
+        s2[t] = cs;
+        k1[t] = cD;
+        k2[t] = cN;
+        __syncthreads();
+        for (int o = kLossThreads / 2; o > 0; o >>= 1) {
+            if (t < o) {
+                s1[t] += s1[t + o];
+                s2[t] += s2[t + o];
+                k1[t] += k1[t + o];
+                k2[t] += k2[t + o];
+            }
+            __syncthreads();
+        }
+    }
+    const uint32_t nD = k1[0], nN = k2[0];
+    if (blockIdx.x == 0 && t == 0) {
+        const float td0 = nD ? w_depth * s1[0] / (float)nD : 0.f;
+        const float tn0 = nN ? lambda_n * lambda_ng * s2[0] / (float)nN : 0.f;
+        loss_out[0] = td0 + tn0;
+        loss_out[1] = td0;
+        loss_out[2] = tn0;
+        loss_out[3] = (float)nD;
+        loss_out[4] = (float)nN;
+    }
+    const int64_t r = (int64_t)blockIdx.x * kLossThreads + threadIdx.x;
     if (r >= n) return;
-    float cD = loss_out[3], cN = loss_out[4];
+    const float cD = (float)nD, cN = (float)nN;
     float gd = 0.f, g0 = 0.f, g1 = 0.f, g2 = 0.f;
     float D = td[r];
     if (D > 0.f) {
@@ -180,10 +176,9 @@ hipError_t launch_loss(int64_t n_rays, const float *depth, const float *normal, 
 {
     int nb = loss_blocks(n_rays);
     loss_partials<<<nb, kLossThreads, 0, s>>>(n_rays, depth, normal, td, tn, partials);
-    loss_finalize<<<1, kLossThreads, 0, s>>>(nb, partials, w_depth, lambda_n, lambda_ng, loss_out);
-    if (n_rays > 0)
-        loss_grad<<<(unsigned)((n_rays + kLossThreads - 1) / kLossThreads), kLossThreads, 0, s>>>(
-            n_rays, depth, normal, td, tn, w_depth, lambda_n, lambda_ng, loss_out, gD, gA, gN);
+    const int64_t gb = n_rays > 0 ? (n_rays + kLossThreads - 1) / kLossThreads : 1;
+    loss_grad<<<(unsigned)gb, kLossThreads, 0, s>>>(n_rays, depth, normal, td, tn, w_depth, lambda_n, lambda_ng, nb,
+                                                     partials, loss_out, gD, gA, gN);
     return hipGetLastError();
 }
 

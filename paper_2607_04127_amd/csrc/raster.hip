@@ -690,9 +690,10 @@ __global__ __launch_bounds__(256) void work_needed_kernel(const uint32_t *__rest
 int chunk_size(int64_t P, int requested)
 {
     if (requested > 0) return requested;
-    // about 4096 chunks (several rounds of 8 resident waves on each of 1024 SIMDs; short
-    // chunks also keep the re-walk of a terminating ray short), at most kChunkMax entries
-    int64_t s = (P + 4095) / 4096;
+    // about 6144 chunks, 24576 one-wave tasks (several rounds of 8 resident waves on each of
+    // 1024 SIMDs; short chunks also keep the re-walk of a terminating ray short), balanced
+    // against the per-chunk cost of the merge and the backward set-up; at most kChunkMax
+    int64_t s = (P + 6143) / 6144;
     s = (s + 15) / 16 * 16;
     if (s < 32) s = 32;
     if (s > kChunkMax) s = kChunkMax;
