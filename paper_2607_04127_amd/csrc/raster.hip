@@ -92,9 +92,7 @@ constexpr int kTaskGroup = 32;
 static unsigned task_blocks(int items) { return (unsigned)(((int64_t)4 * items + kTaskGroup - 1) / kTaskGroup * kTaskGroup); }
 
 // Up to 64 list entries staged in LDS by one wave: of the entries whose ray rectangle meets
-// the wave's sub-tile, in list order, the surfel ids, list positions and 64-byte records
-// (coalesced vector loads, one memory latency per stage).  Entries the sub-tile does not
-// meet are never loaded.
+// the wave's sub-tile, in list order, the surfel ids, list positions and 64-byte records.
 constexpr int kWStage = 64;
 constexpr int kChunkMax = 256;  // longest chunk the automatic choice makes
 struct WaveStage {
@@ -104,37 +102,37 @@ struct WaveStage {
 };
 
 // Stages list entries [a, a + n), n <= 64; returns how many meet the sub-tile (uniform).
+// Lane l loads entry l's ray rectangle and whole record together (two memory latencies in
+// all: the id, then both), and the entries that meet the sub-tile are written compacted.
 __device__ __forceinline__ uint32_t stage_wave(WaveStage &ws, const uint32_t *__restrict__ ids,
                                                const float *__restrict__ recs, const uint2 *__restrict__ rects,
                                                uint32_t a, uint32_t n, const Lane &L, int W)
 {
     const uint32_t l = (uint32_t)L.lane;
-    bool meet = false;
-    uint32_t id = 0;
-    if (l < n) {
-        id = ids[a + l];
-        meet = sub_overlap(rects[id], L.sr0, L.sc0, W);
+    const bool in = l < n;
+    const uint32_t id = in ? ids[a + l] : 0u;
+    const float4 *r4 = reinterpret_cast<const float4 *>(recs) + (size_t)id * 4;
+    float4 q0 = make_float4(0.f, 0.f, 0.f, 0.f), q1 = q0, q2 = q0, q3 = q0;
+    uint2 rc = make_uint2(0u, 0u);
+    if (in) {
+        rc = rects[id];
+        q0 = r4[0];
+        q1 = r4[1];
+        q2 = r4[2];
+        q3 = r4[3];
     }
+    const bool meet = in && sub_overlap(rc, L.sr0, L.sc0, W);
     const uint64_t bal = __ballot(meet);
     const uint32_t m = __builtin_amdgcn_readfirstlane((uint32_t)__popcll(bal));
     const uint32_t k = __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
     if (meet) {
         ws.id[k] = id;
         ws.pos[k] = a + l;
+        ws.rec[k][0] = q0;
+        ws.rec[k][1] = q1;
+        ws.rec[k][2] = q2;
+        ws.rec[k][3] = q3;
     }
-    __syncthreads();
-    // record quarter q = l + 64 j of entry q / 4: all loads issued before the first store
-    const float4 *r4 = reinterpret_cast<const float4 *>(recs);
-    const uint32_t lim = 4u * m;
-    auto ld = [&](uint32_t q) { return q < lim ? r4[(size_t)ws.id[q >> 2] * 4 + (q & 3u)] : make_float4(0.f, 0.f, 0.f, 0.f); };
-    auto st = [&](uint32_t q, float4 v) {
-        if (q < lim) ws.rec[q >> 2][q & 3u] = v;
-    };
-    const float4 v0 = ld(l), v1 = ld(l + 64u), v2 = ld(l + 128u), v3 = ld(l + 192u);
-    st(l, v0);
-    st(l + 64u, v1);
-    st(l + 128u, v2);
-    st(l + 192u, v3);
     __syncthreads();
     return m;
 }
