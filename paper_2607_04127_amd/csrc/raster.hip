@@ -104,9 +104,12 @@ struct WaveStage {
 // Stages list entries [a, a + n), n <= 64; returns how many meet the sub-tile (uniform).
 // Lane l loads entry l's ray rectangle and whole record together (two memory latencies in
 // all: the id, then both), and the entries that meet the sub-tile are written compacted.
+// Afterwards lane k holds staged slot k's list position and surfel id (slot_pos, slot_id),
+// which the walk reads with readlane instead of LDS.
 __device__ __forceinline__ uint32_t stage_wave(WaveStage &ws, const uint32_t *__restrict__ ids,
                                                const float *__restrict__ recs, const uint2 *__restrict__ rects,
-                                               uint32_t a, uint32_t n, const Lane &L, int W)
+                                               uint32_t a, uint32_t n, const Lane &L, int W, uint32_t &slot_pos,
+                                               uint32_t &slot_id)
 {
     const uint32_t l = (uint32_t)L.lane;
     const bool in = l < n;
@@ -134,6 +137,8 @@ __device__ __forceinline__ uint32_t stage_wave(WaveStage &ws, const uint32_t *__
         ws.rec[k][3] = q3;
     }
     __syncthreads();
+    slot_pos = ws.pos[l];  // meaningful for l < m
+    slot_id = ws.id[l];
     return m;
 }
 
@@ -154,7 +159,9 @@ __device__ __forceinline__ void composite(WaveStage &ws, const uint32_t *__restr
     bool done = !active || !L.wave_in;
     for (uint32_t base = a; base < b; base += kWStage) {
         if (__all(done)) return;
-        const uint32_t m = stage_wave(ws, ids, recs, rects, base, min((uint32_t)kWStage, b - base), L, W);
+        uint32_t slot_pos, slot_id;
+        const uint32_t m = stage_wave(ws, ids, recs, rects, base, min((uint32_t)kWStage, b - base), L, W, slot_pos,
+                                      slot_id);
         for (uint32_t i = 0; i < m; ++i) {
             const Rec s = staged_rec(ws, i);
             const Hit h = hit_test(s, ray, p);
@@ -167,7 +174,7 @@ __device__ __forceinline__ void composite(WaveStage &ws, const uint32_t *__restr
                 acc.SN2 = fmaf(w, s.nt2, acc.SN2);
                 acc.T = acc.T * (1.f - h.ah);
                 ++acc.K;
-                acc.last = (int)ws.pos[i];
+                acc.last = (int)__builtin_amdgcn_readlane((int)slot_pos, (int)i);
                 done = acc.T < p.T_min;
             }
             if (__all(done)) break;
@@ -588,10 +595,13 @@ __global__ __launch_bounds__(64) void raster_bwd_chunk_kernel(
     for (uint32_t sidx = nstages; sidx-- > 0;) {
         const uint32_t base = a + sidx * kWStage;
         if (wmax < (int)base) continue;
-        const uint32_t m = stage_wave(ws, ids, recs, rects, base, min((uint32_t)kWStage, b - base), L, g.W);
-        for (uint32_t i = m; i-- > 0;) {
-            const int pos = (int)__builtin_amdgcn_readfirstlane(ws.pos[i]);
-            if (pos > wmax) continue;
+        uint32_t slot_pos, slot_id;
+        const uint32_t m = stage_wave(ws, ids, recs, rects, base, min((uint32_t)kWStage, b - base), L, g.W,
+                                      slot_pos, slot_id);
+        // staged slots up to the wave's last contributor (slots are in list order)
+        const uint32_t top = (uint32_t)__popcll(__ballot((uint32_t)L.lane < m && (int)slot_pos <= wmax));
+        for (uint32_t i = top; i-- > 0;) {
+            const int pos = __builtin_amdgcn_readlane((int)slot_pos, (int)i);
             const Rec s = staged_rec(ws, i);
             // every lane tests; the wave goes on only if some lane composites this entry, and
             // then runs the composite arithmetic on full waves, keeping its results (the
@@ -637,7 +647,8 @@ __global__ __launch_bounds__(64) void raster_bwd_chunk_kernel(
             for (int c = kGradUsed; c < 16; ++c) gv[c] = 0.f;
             const float mine = wave_sum16(gv, L.lane);
             const int k = L.lane & 15, c = 4 * (L.lane >> 4) + k;
-            if (k < 4 && c < kGradUsed) unsafeAtomicAdd(recgrad + (size_t)ws.id[i] * kGrad + c, mine);
+            const uint32_t sid = (uint32_t)__builtin_amdgcn_readlane((int)slot_id, (int)i);
+            if (k < 4 && c < kGradUsed) unsafeAtomicAdd(recgrad + (size_t)sid * kGrad + c, mine);
         }
         __syncthreads();  // the stage is no longer read
     }
