@@ -40,8 +40,8 @@ PEAK_HBM_GBS = 8000.0
 # WRITE_SIZE per dispatch, each scaled by what the counter reads for a plain 256 MiB device
 # copy (profiles/pmc_traffic_raster_bwd_block64x1024_300k.md).  Valid only for the kernel
 # sources they were taken with (digest below); reported as null once those change.
-TRAFFIC_RASTER_BWD = dict(bytes=38255685,
-                          sources_sha256="8b5d206f426cd6946554a9c94f8a92af2a3dd39713d310b218189468d16c4bb2")
+TRAFFIC_RASTER_BWD = dict(bytes=57558162,
+                          sources_sha256="964927bfc11668831d3654ff153a47b6c3261bee21da6595049ddd429f01af2d")
 
 
 def _sources_digest() -> str:
