@@ -84,8 +84,14 @@ struct lgsr_state {
     DevBuf keys, cnt, offs, counters;
     bool cnt_clean = false;      // every word of cnt is zero (the tile scan leaves it so)
     void *cnt_seen = nullptr;    // the cnt allocation cnt_clean refers to
-    uint32_t *pinned = nullptr;  // host-pinned copy of counters[0..2]
-    hipEvent_t rb = nullptr;     // recorded after the read-back copy
+    uint32_t *pinned = nullptr;      // host copy of counters[0..3], written by the tile scan
+    uint32_t *pinned_dev = nullptr;  // its device address
+    hipEvent_t rb = nullptr;         // recorded after the tile scan
+    // lists emitted and sorted ahead of the read-back, on buffers sized from earlier frames
+    bool spec = false;
+    int spec_seg = 0;
+    int64_t spec_cap_pairs = 0, spec_cap_items = 0;
+    int64_t last_P = -1;  // pairs of this state's previous forward
     int chunk_req = 0;           // requested chunk size (0: automatic)
     uint32_t *ids = nullptr;  // per-tile lists of surfel ids, front to back (pv)
     SurfelPtrs S{};
@@ -373,7 +379,10 @@ lgsr_status forward_begin(lgsr_ctx *ctx, lgsr_state *S, const lgsr_surfels *surf
     HIP_TRY(ensure(S->offs, (size_t)g.T * kShards * 4), "alloc tile cursors");
     HIP_TRY(ensure(S->long_tiles, (size_t)g.T * 4), "alloc long tile list");
     HIP_TRY(ensure(S->counters, 16), "alloc counters");
-    if (!S->pinned) HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&S->pinned), 16, hipHostMallocDefault), "pinned");
+    if (!S->pinned) {
+        HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&S->pinned), 16, hipHostMallocCoherent), "pinned");
+        HIP_TRY(hipHostGetDevicePointer(reinterpret_cast<void **>(&S->pinned_dev), S->pinned, 0), "pinned");
+    }
     if (!S->rb) HIP_TRY(hipEventCreateWithFlags(&S->rb, hipEventDisableTiming), "event");
     uint32_t *counters = as<uint32_t>(S->counters);
     {
@@ -387,15 +396,47 @@ lgsr_status forward_begin(lgsr_ctx *ctx, lgsr_state *S, const lgsr_surfels *surf
     }
     {
     Stage st_(ctx, LGSR_STAGE_SCAN, s);
+    // a value the scan cannot write (P would be 2^64 - 1): seen after the wait, the words did
+    // not arrive and forward_end copies them from the device instead
+    for (int k = 0; k < 4; ++k) S->pinned[k] = 0xFFFFFFFFu;
     HIP_TRY(launch_tile_scan(as<uint32_t>(S->cnt), g.T, as<uint2>(S->ranges), as<uint32_t>(S->offs), counters,
-                             as<uint32_t>(S->long_tiles), s),
+                             as<uint32_t>(S->long_tiles), S->pinned_dev, s),
             "tile scan");
     S->cnt_clean = true;
     S->cnt_seen = S->cnt.p;
-    }
-    Stage st_(ctx, LGSR_STAGE_READBACK, s);
-    HIP_TRY(hipMemcpyAsync(S->pinned, counters, 4 * sizeof(uint32_t), hipMemcpyDeviceToHost, s), "readback");
     HIP_TRY(hipEventRecord(S->rb, s), "readback event");
+    }
+    // Emission and the per-tile sorts go out before the host waits for the pair count, on
+    // buffers sized from this state's previous frame with a margin; forward_end checks the
+    // count and redoes them when a buffer was short or the chunk length differs.
+    S->spec = false;
+    S->ids = as<uint32_t>(S->pv);
+    if (S->last_P >= 0 && g.T > 0) {
+        const int64_t want = S->last_P + S->last_P / 4 + 4096;
+        const int seg = chunk_size(S->last_P, S->chunk_req);
+        const int64_t items = chunk_items_max(want, g.T, seg);
+        if (want <= (int64_t)0x7FFFFFFF && items <= (int64_t)0x7FFFFFFF) {
+            HIP_TRY(ensure(S->pv, (size_t)want * 4), "alloc pairs");
+            HIP_TRY(ensure(S->chunks, (size_t)items * sizeof(uint4)), "alloc chunks");
+            HIP_TRY(ensure(S->chunk_base, (size_t)(g.T + 1) * sizeof(uint32_t)), "alloc chunks");
+            S->ids = as<uint32_t>(S->pv);
+            S->spec_cap_pairs = (int64_t)(S->pv.cap / 4);
+            S->spec_cap_items = (int64_t)(S->chunks.cap / sizeof(uint4));
+            S->spec_seg = seg;
+            {
+            Stage st_(ctx, LGSR_STAGE_EMIT, s);
+            HIP_TRY(launch_emit(as<uint2>(S->rects), n, g, as<uint32_t>(S->offs), S->ids, S->spec_cap_pairs, s),
+                    "emit");
+            }
+            Stage st_(ctx, LGSR_STAGE_TILE_SORT, s);
+            const ChunkList cl{seg, as<uint4>(S->chunks), as<uint32_t>(S->chunk_base), as<uint32_t>(S->pose) + 12,
+                               S->spec_cap_items};
+            HIP_TRY(launch_tile_sort(as<uint2>(S->ranges), g.T, as<uint32_t>(S->keys), n, S->ids, S->spec_cap_pairs,
+                                     true, cl, s),
+                    "tile sort");
+            S->spec = true;
+        }
+    }
     return LGSR_OK;
 }
 
@@ -403,7 +444,12 @@ lgsr_status forward_begin(lgsr_ctx *ctx, lgsr_state *S, const lgsr_surfels *surf
 // compositing into `out`.
 lgsr_status forward_end(lgsr_ctx *ctx, lgsr_state *S, const lgsr_frame *out, hipStream_t s)
 {
+    {
+    Stage st_(ctx, LGSR_STAGE_READBACK, s);
     HIP_TRY(hipEventSynchronize(S->rb), "readback wait");
+    if (S->pinned[0] == 0xFFFFFFFFu && S->pinned[1] == 0xFFFFFFFFu)
+        HIP_TRY(hipMemcpy(S->pinned, S->counters.p, 4 * sizeof(uint32_t), hipMemcpyDeviceToHost), "readback");
+    }
     const int64_t P = (int64_t)((uint64_t)S->pinned[0] | ((uint64_t)S->pinned[1] << 32));
     const int64_t longest = (int64_t)S->pinned[2];
     const Grid g = S->g;
@@ -412,17 +458,19 @@ lgsr_status forward_end(lgsr_ctx *ctx, lgsr_state *S, const lgsr_frame *out, hip
     // lists are addressed with 32-bit offsets
     if (P > (int64_t)0x7FFFFFFF) return fail(ctx, LGSR_ECAPACITY, "too many (surfel, tile) pairs");
     const size_t pp = (size_t)(P > 0 ? P : 1);
-    HIP_TRY(ensure(S->pv, pp * 4), "alloc pairs");
     const int n_long = (int)S->pinned[3];
     const int nch = tile_sort_chunks(longest);
     if (n_long > 0) {
         if ((int64_t)n_long * nch > (int64_t)0x7FFFFFFF) return fail(ctx, LGSR_ECAPACITY, "tile lists too long");
         HIP_TRY(ensure(S->pk, pp * 8), "alloc sort workspace");
     }
-    S->ids = as<uint32_t>(S->pv);
     const int seg = chunk_size(P, S->chunk_req);
     const int64_t items_max = chunk_items_max(P, g.T, seg);
     if (items_max > 0x7FFFFFFF) return fail(ctx, LGSR_ECAPACITY, "too many list chunks");
+    // the lists emitted ahead hold when their buffers were large enough; the chunk list also
+    // needs this frame's chunk length
+    const bool lists_ok = S->spec && P <= S->spec_cap_pairs;
+    const bool chunks_ok = lists_ok && seg == S->spec_seg && items_max <= S->spec_cap_items;
     HIP_TRY(ensure(S->chunks, (size_t)(items_max > 0 ? items_max : 1) * sizeof(uint4)), "alloc chunks");
     HIP_TRY(ensure(S->chunk_base, (size_t)(g.T + 1) * sizeof(uint32_t)), "alloc chunks");
     HIP_TRY(ensure(S->slots, chunk_slot_floats(items_max > 0 ? items_max : 1) * sizeof(float)), "alloc slots");
@@ -432,17 +480,32 @@ lgsr_status forward_end(lgsr_ctx *ctx, lgsr_state *S, const lgsr_frame *out, hip
     if (!(S->fixflag_clean && S->fixflag_seen == S->fixflag.p))
         HIP_TRY(launch_fill_u32(as<uint32_t>(S->fixflag), 0u, (int64_t)(S->fixflag.cap / 4), s), "clear chunk flags");
     S->fixflag_clean = false;  // until the raster below has run
-    if (P > 0) {
-        Stage st_(ctx, LGSR_STAGE_EMIT, s);
-        HIP_TRY(launch_emit(as<uint2>(S->rects), n, g, as<uint32_t>(S->offs), S->ids, P, s), "emit");
+    const ChunkList cl{seg, as<uint4>(S->chunks), as<uint32_t>(S->chunk_base), as<uint32_t>(S->pose) + 12,
+                       (int64_t)(S->chunks.cap / sizeof(uint4))};
+    if (!lists_ok) {
+        HIP_TRY(ensure(S->pv, pp * 4), "alloc pairs");
+        S->ids = as<uint32_t>(S->pv);
+        if (S->spec) HIP_TRY(launch_restore_cursors(as<uint2>(S->ranges), g.T, as<uint32_t>(S->offs), s), "emit");
+        if (P > 0) {
+            Stage st_(ctx, LGSR_STAGE_EMIT, s);
+            HIP_TRY(launch_emit(as<uint2>(S->rects), n, g, as<uint32_t>(S->offs), S->ids, P, s), "emit");
+        }
+        Stage st_(ctx, LGSR_STAGE_TILE_SORT, s);
+        HIP_TRY(launch_tile_sort(as<uint2>(S->ranges), g.T, as<uint32_t>(S->keys), n, S->ids, P, true, cl, s),
+                "tile sort");
+    } else if (!chunks_ok) {
+        Stage st_(ctx, LGSR_STAGE_TILE_SORT, s);
+        HIP_TRY(launch_tile_sort(as<uint2>(S->ranges), g.T, as<uint32_t>(S->keys), n, S->ids, P, false, cl, s),
+                "chunk list");
     }
-    {
-    Stage st_(ctx, LGSR_STAGE_TILE_SORT, s);
-    const ChunkList cl{seg, as<uint4>(S->chunks), as<uint32_t>(S->chunk_base), as<uint32_t>(S->pose) + 12};
-    HIP_TRY(launch_tile_sort(as<uint2>(S->ranges), g.T, as<uint32_t>(S->keys), n, S->ids, as<uint32_t>(S->long_tiles),
-                             n_long, nch, n_long > 0 ? as<unsigned long long>(S->pk) : nullptr, cl, s),
-            "tile sort");
+    if (n_long > 0) {
+        Stage st_(ctx, LGSR_STAGE_TILE_SORT, s);
+        HIP_TRY(launch_tile_sort_long(as<uint2>(S->ranges), as<uint32_t>(S->keys), n, S->ids,
+                                      as<uint32_t>(S->long_tiles), n_long, nch, as<unsigned long long>(S->pk), s),
+                "tile sort");
     }
+    S->spec = false;
+    S->last_P = P;
     RasterBufs &R = S->R;
     R.ids = S->ids;
     R.recs = as<float>(S->recs);

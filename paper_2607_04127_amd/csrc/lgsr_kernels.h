@@ -18,9 +18,12 @@ int tile_sort_chunks(int64_t longest);
 // + s] = first slot of its shard s, from the exclusive prefix sum of cnt in (tile, shard)
 // order; cnt is left zero; out (device, 4 words) receives the total as two 32-bit words (low, high), the
 // largest tile count and the number of tiles longer than tile_sort_capacity(), whose ids go
-// to long_tiles (T words).
+// to long_tiles (T words).  host_out, when not null, is the device address of 4 words of
+// host memory that receive the same words.
 hipError_t launch_tile_scan(uint32_t *cnt, int T, uint2 *ranges, uint32_t *cursor, uint32_t *out,
-                            uint32_t *long_tiles, hipStream_t s);
+                            uint32_t *long_tiles, uint32_t *host_out, hipStream_t s);
+// Puts the cursors of launch_tile_scan back after an emission advanced them.
+hipError_t launch_restore_cursors(const uint2 *ranges, int T, uint32_t *cursor, hipStream_t s);
 // The raster's chunk list, built alongside the tile sort: chunks of seg list entries
 // (items_max x uint4), chunk_base (T + 1), n_items (device word).
 struct ChunkList {
@@ -28,14 +31,19 @@ struct ChunkList {
     uint4 *chunks;
     uint32_t *chunk_base;
     uint32_t *n_items;
+    int64_t cap_items;  // chunks the buffer holds
 };
 // Orders every tile's list ids[ranges[t].x .. ranges[t].y) by (keys[id], id) ascending
-// (keys has n entries).  Tiles longer than tile_sort_capacity(): the n_long of them in
-// long_tiles, nch = tile_sort_chunks(longest), tmp (P x 8 bytes); tmp may be null when
-// n_long is 0.
+// (keys has n entries) and builds the chunk list.  Lists longer than tile_sort_capacity()
+// are left to launch_tile_sort_long; lists reaching past cap_pairs (the ids buffer) are
+// skipped; sort_lists = false builds the chunk list only.
 hipError_t launch_tile_sort(const uint2 *ranges, int T, const uint32_t *keys, int64_t n, uint32_t *ids,
-                            const uint32_t *long_tiles, int n_long, int nch, unsigned long long *tmp,
-                            const ChunkList &cl, hipStream_t s);
+                            int64_t cap_pairs, bool sort_lists, const ChunkList &cl, hipStream_t s);
+// The lists longer than tile_sort_capacity(): the n_long of them in long_tiles,
+// nch = tile_sort_chunks(longest), tmp (P x 8 bytes).
+hipError_t launch_tile_sort_long(const uint2 *ranges, const uint32_t *keys, int64_t n, uint32_t *ids,
+                                 const uint32_t *long_tiles, int n_long, int nch, unsigned long long *tmp,
+                                 hipStream_t s);
 
 // ---- project.hip ----
 struct SurfelPtrs {

@@ -300,8 +300,11 @@ __device__ void sort_resident(TileSortSmem &sm, const uint32_t *__restrict__ key
 // The raster's work list (one workgroup): every tile's list cut into chunks of seg entries,
 // chunk q of tile t = (t, first, end); chunk_base[t] = index of the tile's first chunk,
 // chunk_base[T] = *n_items = the number of chunks.
+// Chunks at or beyond cap_items are not written (the host sizes the buffer before it uses
+// the list; a list built on too small a buffer is built again).
 __device__ void build_chunks_block(const uint2 *__restrict__ ranges, int T, int seg, uint4 *__restrict__ chunks,
-                                   uint32_t *__restrict__ chunk_base, uint32_t *__restrict__ n_items)
+                                   uint32_t *__restrict__ chunk_base, uint32_t *__restrict__ n_items,
+                                   int64_t cap_items)
 {
     static_assert(kTsThreads == 1024, "16 waves");
     __shared__ uint32_t wsum[16];
@@ -335,7 +338,7 @@ __device__ void build_chunks_block(const uint2 *__restrict__ ranges, int T, int 
             for (uint32_t q = 0; q < c; ++q) {
                 uint32_t a = r.x + q * (uint32_t)seg;
                 uint32_t b = min(r.y, a + (uint32_t)seg);
-                chunks[first + q] = make_uint4((uint32_t)t, a, b, 0u);
+                if ((int64_t)first + q < cap_items) chunks[first + q] = make_uint4((uint32_t)t, a, b, 0u);
             }
         }
         carry += tot;
@@ -348,21 +351,24 @@ __device__ void build_chunks_block(const uint2 *__restrict__ ranges, int T, int 
 }
 
 // One workgroup per tile, and one more that builds the raster's chunk list; lists longer than
-// kTsCap are left to the chunk kernels below.
+// kTsCap are left to the chunk kernels below.  Lists reaching past cap_pairs (a buffer too
+// small for this frame, sorted again once it has grown) are skipped; sort_lists = 0 builds
+// the chunk list only.
 __global__ __launch_bounds__(kTsThreads) void tile_sort_kernel(const uint2 *__restrict__ ranges, int T,
                                                                const uint32_t *__restrict__ keys, int64_t n,
-                                                               uint32_t *ids, ChunkList cl)
+                                                               uint32_t *ids, ChunkList cl, int64_t cap_pairs,
+                                                               int sort_lists)
 {
     __shared__ TileSortSmem sm;
     const int tile = blockIdx.x;
     if (tile == T) {
-        build_chunks_block(ranges, T, cl.seg, cl.chunks, cl.chunk_base, cl.n_items);
+        build_chunks_block(ranges, T, cl.seg, cl.chunks, cl.chunk_base, cl.n_items, cl.cap_items);
         return;
     }
-    if (tile > T) return;
+    if (tile > T || !sort_lists) return;
     const uint2 rg = ranges[tile];
     const int m = (int)(rg.y - rg.x);
-    if (m <= 1 || m > kTsCap) return;
+    if (m <= 1 || m > kTsCap || (int64_t)rg.y > cap_pairs) return;
     sort_resident<false>(sm, keys, n, ids + rg.x, m, nullptr);
 }
 
@@ -442,7 +448,8 @@ __global__ __launch_bounds__(kTsThreads) void tile_chunk_merge_kernel(const uint
 // long_tiles.
 __global__ __launch_bounds__(1024) void tile_scan_kernel(uint32_t *__restrict__ cnt, int T,
                                                          uint2 *__restrict__ ranges, uint32_t *__restrict__ cursor,
-                                                         uint32_t *__restrict__ out, uint32_t *__restrict__ long_tiles)
+                                                         uint32_t *__restrict__ out, uint32_t *__restrict__ long_tiles,
+                                                         uint32_t *__restrict__ host_out)
 {
     static_assert(kShards == 8, "two uint4 loads per tile");
     __shared__ uint64_t wsum[16];
@@ -512,7 +519,26 @@ __global__ __launch_bounds__(1024) void tile_scan_kernel(uint32_t *__restrict__ 
         out[1] = (uint32_t)(carry >> 32);
         out[2] = mx;
         out[3] = nlong;
+        if (host_out) {  // the same four words straight into host memory (no copy launch)
+            host_out[0] = (uint32_t)carry;
+            host_out[1] = (uint32_t)(carry >> 32);
+            host_out[2] = mx;
+            host_out[3] = nlong;
+        }
     }
+}
+
+// Emission advances every cursor by its (tile, shard) count, so afterwards cursor[t, s]
+// holds the first slot of shard s + 1; this puts the first slots back for another emission.
+__global__ __launch_bounds__(256) void restore_cursors_kernel(const uint2 *__restrict__ ranges, int T,
+                                                              uint32_t *__restrict__ cursor)
+{
+    const int t = blockIdx.x * 256 + threadIdx.x;
+    if (t >= T) return;
+    uint4 *q = reinterpret_cast<uint4 *>(cursor + (size_t)t * kShards);
+    const uint4 a = q[0], b = q[1];
+    q[0] = make_uint4(ranges[t].x, a.x, a.y, a.z);
+    q[1] = make_uint4(a.w, b.x, b.y, b.z);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -522,20 +548,32 @@ __global__ __launch_bounds__(1024) void tile_scan_kernel(uint32_t *__restrict__ 
 int tile_sort_capacity() { return kTsCap; }
 
 hipError_t launch_tile_scan(uint32_t *cnt, int T, uint2 *ranges, uint32_t *cursor, uint32_t *out,
-                            uint32_t *long_tiles, hipStream_t s)
+                            uint32_t *long_tiles, uint32_t *host_out, hipStream_t s)
 {
-    tile_scan_kernel<<<1, 1024, 0, s>>>(cnt, T, ranges, cursor, out, long_tiles);
+    tile_scan_kernel<<<1, 1024, 0, s>>>(cnt, T, ranges, cursor, out, long_tiles, host_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_restore_cursors(const uint2 *ranges, int T, uint32_t *cursor, hipStream_t s)
+{
+    if (T > 0) restore_cursors_kernel<<<(T + 255) / 256, 256, 0, s>>>(ranges, T, cursor);
     return hipGetLastError();
 }
 
 int tile_sort_chunks(int64_t longest) { return (int)((longest + kTsCap - 1) / kTsCap); }
 
 hipError_t launch_tile_sort(const uint2 *ranges, int T, const uint32_t *keys, int64_t n, uint32_t *ids,
-                            const uint32_t *long_tiles, int n_long, int nch, unsigned long long *tmp,
-                            const ChunkList &cl, hipStream_t s)
+                            int64_t cap_pairs, bool sort_lists, const ChunkList &cl, hipStream_t s)
 {
     if (T <= 0) return hipSuccess;
-    tile_sort_kernel<<<T + 1, kTsThreads, 0, s>>>(ranges, T, keys, n, ids, cl);
+    tile_sort_kernel<<<T + 1, kTsThreads, 0, s>>>(ranges, T, keys, n, ids, cl, cap_pairs, sort_lists ? 1 : 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_tile_sort_long(const uint2 *ranges, const uint32_t *keys, int64_t n, uint32_t *ids,
+                                 const uint32_t *long_tiles, int n_long, int nch, unsigned long long *tmp,
+                                 hipStream_t s)
+{
     if (n_long > 0 && nch > 1) {
         const unsigned grid = (unsigned)((int64_t)n_long * nch);
         tile_chunk_sort_kernel<<<grid, kTsThreads, 0, s>>>(ranges, long_tiles, nch, keys, n, ids, tmp);
