@@ -472,6 +472,24 @@ __global__ __launch_bounds__(kMergeThreads) void raster_bwd_prep_kernel(const ui
     const bool live = L.valid && K > 0;
     // the run's contributions, last chunk first (pass 0); then B from the later runs' sums (pass 1)
     float B = 0.f;
+    float v[kB][6];
+    // a run of at most kB chunks is loaded once and kept in registers for both passes
+    const bool one_batch = r1 - r0 <= (uint32_t)kB;
+    auto load_batch = [&](uint32_t top, uint32_t lo) {
+#pragma unroll
+        for (int q = 0; q < kB; ++q) {
+            const uint32_t it = top - 1 - q;
+            if (live && it >= lo && it < top) {
+                v[q][0] = slots[slot(it, F_LAST, L.rt)];
+                v[q][1] = slots[slot(it, F_SA, L.rt)];
+                v[q][2] = slots[slot(it, F_SD, L.rt)];
+                v[q][3] = slots[slot(it, F_SN0, L.rt)];
+                v[q][4] = slots[slot(it, F_SN1, L.rt)];
+                v[q][5] = slots[slot(it, F_SN2, L.rt)];
+            }
+        }
+    };
+    if (one_batch) load_batch(r1, r0);
     for (int pass = 0; pass < 2; ++pass) {
         if (pass == 0 && grp == 0) continue;  // the first run's sum is read by no other run
         if (pass == 1) {
@@ -481,19 +499,7 @@ __global__ __launch_bounds__(kMergeThreads) void raster_bwd_prep_kernel(const ui
         }
         for (uint32_t top = r1; top > r0;) {
             const uint32_t lo = top - r0 > (uint32_t)kB ? top - kB : r0;
-            float v[kB][6];
-#pragma unroll
-            for (int q = 0; q < kB; ++q) {
-                const uint32_t it = top - 1 - q;
-                if (live && it >= lo && it < top) {
-                    v[q][0] = slots[slot(it, F_LAST, L.rt)];
-                    v[q][1] = slots[slot(it, F_SA, L.rt)];
-                    v[q][2] = slots[slot(it, F_SD, L.rt)];
-                    v[q][3] = slots[slot(it, F_SN0, L.rt)];
-                    v[q][4] = slots[slot(it, F_SN1, L.rt)];
-                    v[q][5] = slots[slot(it, F_SN2, L.rt)];
-                }
-            }
+            if (!one_batch) load_batch(top, lo);
 #pragma unroll
             for (int q = 0; q < kB; ++q) {
                 const uint32_t it = top - 1 - q;
