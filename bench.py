@@ -40,8 +40,8 @@ PEAK_HBM_GBS = 8000.0
 # WRITE_SIZE per dispatch, each scaled by what the counter reads for a plain 256 MiB device
 # copy (profiles/pmc_traffic_raster_bwd_block64x1024_300k.md).  Valid only for the kernel
 # sources they were taken with (digest below); reported as null once those change.
-TRAFFIC_RASTER_BWD = dict(bytes=57558162,
-                          sources_sha256="964927bfc11668831d3654ff153a47b6c3261bee21da6595049ddd429f01af2d")
+TRAFFIC_RASTER_BWD = dict(bytes=57554560,
+                          sources_sha256="7121799734c545eb8493351578a85769e834702563647061e56e5a85c26da958")
 
 
 def _sources_digest() -> str:
