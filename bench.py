@@ -41,7 +41,7 @@ PEAK_HBM_GBS = 8000.0
 # copy (profiles/pmc_traffic_raster_bwd_block64x1024_300k.md).  Valid only for the kernel
 # sources they were taken with (digest below); reported as null once those change.
 TRAFFIC_RASTER_BWD = dict(bytes=57554560,
-                          sources_sha256="7121799734c545eb8493351578a85769e834702563647061e56e5a85c26da958")
+                          sources_sha256="a2dfe77bb504db42acd6a49e3ce57ee83e6b35816a6da82626c0883db0c5e64e")
 
 
 def _sources_digest() -> str:

@@ -20,7 +20,7 @@
 
 namespace lgsr {
 
-constexpr int kTile = 16;      // tile edge in rays: a tile is 16 x 16 rays, one workgroup
+constexpr int kTile = 16;      // tile edge in rays: a tile is 16 x 16 rays with one surfel list
 constexpr int kSub = 8;        // wave sub-tile edge: 8 x 8 rays, one wavefront of 64 lanes
 constexpr int kRec = 16;       // floats per surfel record
 // Per-tile pair counters are split into kShards by surfel index ((i >> kShardShift) mod
@@ -296,16 +296,6 @@ __device__ __forceinline__ bool sub_overlap(uint2 rc, int sr0, int sc0, int W)
     int d2 = c0 - sc0;
     if (d2 < 0) d2 += W;
     return d1 < cw || d2 < kSub;
-}
-
-// XCD-aware block -> tile map: workgroups are dealt to the 8 XCDs round-robin, so give
-// each XCD a contiguous run of tiles (an azimuth sector that shares surfels in its L2).
-__device__ __forceinline__ int xcd_tile(int b, int T)
-{
-    int x = b & 7, i = b >> 3;
-    int per = T >> 3, rem = T & 7;
-    int start = x * per + (x < rem ? x : rem);
-    return start + i;
 }
 
 }  // namespace lgsr
