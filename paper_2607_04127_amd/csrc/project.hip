@@ -49,24 +49,24 @@ __device__ __forceinline__ void col_segments(int c0, int cw, int W, int TW, int 
 }
 
 // first k in [0, H) with rows_sin[k] <= x (rows strictly decreasing); H if none
-__device__ __forceinline__ int first_row_le(const float *__restrict__ rows, int H, float x)
+__device__ __forceinline__ int first_row_le(const float *__restrict__ rows, int stride, int H, float x)
 {
     int lo = 0, hi = H;
     while (lo < hi) {
         int mid = (lo + hi) >> 1;
-        if (rows[2 * mid] <= x) hi = mid;
+        if (rows[stride * mid] <= x) hi = mid;
         else lo = mid + 1;
     }
     return lo;
 }
 
 // first k in [0, H) with rows_sin[k] < x; H if none
-__device__ __forceinline__ int first_row_lt(const float *__restrict__ rows, int H, float x)
+__device__ __forceinline__ int first_row_lt(const float *__restrict__ rows, int stride, int H, float x)
 {
     int lo = 0, hi = H;
     while (lo < hi) {
         int mid = (lo + hi) >> 1;
-        if (rows[2 * mid] < x) hi = mid;
+        if (rows[stride * mid] < x) hi = mid;
         else lo = mid + 1;
     }
     return lo;
@@ -90,11 +90,12 @@ __device__ __forceinline__ void for_each_tile(uint2 rc, const Grid &g, F &&f)
 
 // Grids with at most this many tiles count and reserve pairs in LDS per workgroup.
 constexpr int kLdsBins = 4096;
+constexpr int kLdsRows = 4096;  // row tables up to this many rows are searched in LDS
 
 // Record, range key and ray rectangle of surfel i; (0, 0) when it cannot be hit.
 __device__ __forceinline__ uint2 project_one(const SurfelPtrs &S, const Pose &P, const float *__restrict__ rows,
-                                             const Grid &g, const RasterParams &p, float *__restrict__ recs,
-                                             uint32_t *__restrict__ keys, int64_t i)
+                                             int rstride, const Grid &g, const RasterParams &p,
+                                             float *__restrict__ recs, uint32_t *__restrict__ keys, int64_t i)
 {
     Geom gm = project_geom(S.means, S.quats, S.log_scales, S.logits, i, P, p.near);
     if (!gm.valid) {
@@ -152,8 +153,8 @@ __device__ __forceinline__ uint2 project_one(const SurfelPtrs &S, const Pose &P,
         const bool pole = hi >= kHalfPi || lo <= -kHalfPi;
         const float s_hi = hi >= kHalfPi ? 2.f : sinf(hi);
         const float s_lo = lo <= -kHalfPi ? -2.f : sinf(lo);
-        r0 = first_row_le(rows, H, s_hi);
-        r1 = first_row_lt(rows, H, s_lo) - 1;
+        r0 = first_row_le(rows, rstride, H, s_hi);
+        r1 = first_row_lt(rows, rstride, H, s_lo) - 1;
         const float hmin = rmin * ch - ext_el * fabsf(mz);
         if (pole || hmin <= 0.f) {
             c0 = 0; cw = W;
@@ -200,6 +201,11 @@ __global__ __launch_bounds__(kProjThreads) void project_kernel(SurfelPtrs S, Pos
     const bool lds_bins = g.T <= kLdsBins;
     if (lds_bins)
         for (int b = threadIdx.x; b < g.T; b += kProjThreads) bins[b] = 0u;
+    // the row sines, searched twice per surfel, from LDS rather than memory
+    const bool lds_rows = g.H <= kLdsRows;
+    float *rsin = reinterpret_cast<float *>(bins + (lds_bins ? g.T : 0));
+    if (lds_rows)
+        for (int k = threadIdx.x; k < g.H; k += kProjThreads) rsin[k] = rows[2 * k];
     Pose P = pose_val;
     if (pose_dev) {
         for (int c = 0; c < 9; ++c) P.r[c] = pose_dev[(c / 3) * 4 + (c % 3)];
@@ -211,11 +217,11 @@ __global__ __launch_bounds__(kProjThreads) void project_kernel(SurfelPtrs S, Pos
     }
     const int64_t first = (int64_t)blockIdx.x * kPerBlock;
     const int sh = shard_of(first);
-    if (lds_bins) __syncthreads();
+    if (lds_bins || lds_rows) __syncthreads();
     for (int k = 0; k < kPerThread; ++k) {
         const int64_t i = first + k * kProjThreads + threadIdx.x;
         if (i >= S.n) break;
-        const uint2 rc = project_one(S, P, rows, g, p, recs, keys, i);
+        const uint2 rc = project_one(S, P, lds_rows ? rsin : rows, lds_rows ? 1 : 2, g, p, recs, keys, i);
         rects[i] = rc;
         if (lds_bins) for_each_tile(rc, g, [&](int t) { atomicAdd(&bins[t], 1u); });
         else for_each_tile(rc, g, [&](int t) { atomicAdd(&tile_cnt[t * kShards + sh], 1u); });
@@ -376,7 +382,7 @@ hipError_t launch_project(const SurfelPtrs &S, const Pose &pose_val, const float
                           uint32_t *keys, uint32_t *tile_cnt, hipStream_t s)
 {
     unsigned nb = S.n > 0 ? blocks_for(S.n, kPerBlock) : 1u;  // one block still writes the pose
-    size_t lds = g.T <= kLdsBins ? (size_t)g.T * sizeof(uint32_t) : 0;
+    size_t lds = (g.T <= kLdsBins ? (size_t)g.T * sizeof(uint32_t) : 0) + (g.H <= kLdsRows ? (size_t)g.H * sizeof(float) : 0);
     project_kernel<<<nb, kProjThreads, lds, s>>>(S, pose_val, pose_dev, pose_out, rows, g, p, recs, rects, keys,
                                                  tile_cnt);
     return hipGetLastError();
