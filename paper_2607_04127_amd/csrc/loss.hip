@@ -164,7 +164,7 @@ __global__ __launch_bounds__(kLossThreads) void loss_grad(int64_t n, const float
 
 int loss_blocks(int64_t n_rays)
 {
-    int64_t b = (n_rays + kLossThreads * 4 - 1) / (kLossThreads * 4);
+    int64_t b = (n_rays + kLossThreads - 1) / kLossThreads;  // one ray per thread up to kLossMaxBlocks
     if (b < 1) b = 1;
     if (b > kLossMaxBlocks) b = kLossMaxBlocks;
     return (int)b;
