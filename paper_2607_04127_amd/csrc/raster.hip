@@ -199,13 +199,14 @@ __global__ __launch_bounds__(64) void raster_fwd_chunk_kernel(
     composite(ws, ids, recs, rects, ch.y, ch.z, L, ray, p, g.W, L.valid, acc);
     if (!L.valid) return;
     slots[slot(item, F_TEND, L.rt)] = acc.T;
+    slots[slot(item, F_LAST, L.rt)] = __int_as_float(acc.last);
+    slots[slot(item, F_K, L.rt)] = __int_as_float(acc.K);
+    if (acc.K == 0) return;  // the sums of a chunk without composites are read by no one
     slots[slot(item, F_SA, L.rt)] = acc.A;
     slots[slot(item, F_SD, L.rt)] = acc.SD;
     slots[slot(item, F_SN0, L.rt)] = acc.SN0;
     slots[slot(item, F_SN1, L.rt)] = acc.SN1;
     slots[slot(item, F_SN2, L.rt)] = acc.SN2;
-    slots[slot(item, F_LAST, L.rt)] = __int_as_float(acc.last);
-    slots[slot(item, F_K, L.rt)] = __int_as_float(acc.K);
 }
 
 __device__ __forceinline__ void write_ray(const Lane &L, const Grid &g, const RasterParams &p, float A, float SD,
