@@ -40,8 +40,8 @@ PEAK_HBM_GBS = 8000.0
 # WRITE_SIZE per dispatch, each scaled by what the counter reads for a plain 256 MiB device
 # copy (profiles/pmc_traffic_raster_bwd_block64x1024_300k.md).  Valid only for the kernel
 # sources they were taken with (digest below); reported as null once those change.
-TRAFFIC_RASTER_BWD = dict(bytes=57926329,
-                          sources_sha256="a2dfe77bb504db42acd6a49e3ce57ee83e6b35816a6da82626c0883db0c5e64e")
+TRAFFIC_RASTER_BWD = dict(bytes=57939156,
+                          sources_sha256="946be063aec7e327b6c7608f2244c778d4ac6a357fea636de57ff0a2ef402eff")
 
 
 def _sources_digest() -> str:
