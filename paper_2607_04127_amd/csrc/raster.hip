@@ -320,10 +320,7 @@ __global__ __launch_bounds__(kMergeThreads) void raster_merge_kernel(const uint3
                 continue;
             }
             const int Kl = __float_as_int(v[q][0]);
-            if (Kl == 0) {
-                slots[slot(it, F_TEND, L.rt)] = T;
-                continue;
-            }
+            if (Kl == 0) continue;  // no contributor: its slots are read by no later kernel
             const float Tn = T * v[q][1];
             if (it > c0 && Tn < p.T_min) {  // the ray terminates inside this chunk: re-walk it
                 fix = (int)it;              // the run's end state is then the state before it
@@ -505,8 +502,8 @@ __global__ __launch_bounds__(kMergeThreads) void raster_bwd_prep_kernel(const ui
             for (int q = 0; q < kB; ++q) {
                 const uint32_t it = top - 1 - q;
                 if (it < lo || it >= top) break;
-                if (pass == 1 && L.valid) slots[slot(it, F_B, L.rt)] = live ? B : 0.f;
-                if (!live || __float_as_int(v[q][0]) < 0) continue;
+                if (!live || __float_as_int(v[q][0]) < 0) continue;  // B is read only with a contributor
+                if (pass == 1) slots[slot(it, F_B, L.rt)] = B;
                 B = fmaf(gbD, v[q][2], fmaf(gbN0, v[q][3], fmaf(gbN1, v[q][4], fmaf(gbN2, v[q][5], fmaf(gbA, v[q][1], B)))));
             }
             top = lo;
