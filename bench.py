@@ -40,8 +40,8 @@ PEAK_HBM_GBS = 8000.0
 # WRITE_SIZE per dispatch, each scaled by what the counter reads for a plain 256 MiB device
 # copy (profiles/pmc_traffic_raster_bwd_block64x1024_300k.md).  Valid only for the kernel
 # sources they were taken with (digest below); reported as null once those change.
-TRAFFIC_RASTER_BWD = dict(bytes=57939156,
-                          sources_sha256="946be063aec7e327b6c7608f2244c778d4ac6a357fea636de57ff0a2ef402eff")
+TRAFFIC_RASTER_BWD = dict(bytes=57538829,
+                          sources_sha256="fb81f771d41e898ea1d6cc0e7c4dc898c81c12a627a920db6ba91a00fac2ba27")
 
 
 def _sources_digest() -> str:
