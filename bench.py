@@ -41,7 +41,7 @@ PEAK_HBM_GBS = 8000.0
 # copy (profiles/pmc_traffic_raster_bwd_block64x1024_300k.md).  Valid only for the kernel
 # sources they were taken with (digest below); reported as null once those change.
 TRAFFIC_RASTER_BWD = dict(bytes=57538829,
-                          sources_sha256="fb81f771d41e898ea1d6cc0e7c4dc898c81c12a627a920db6ba91a00fac2ba27")
+                          sources_sha256="6d58e84aaacbf321e84e7e3db46e8447d3b40160f82dd79dd92be0722e4ac37d")
 
 
 def _sources_digest() -> str:

@@ -33,7 +33,10 @@
 
 namespace lgsr {
 
-// Per (chunk, ray) slot fields; slot(item, f, rt) with rt = wave * 64 + lane.
+// Per (chunk, ray) slot fields; slot(item, f, rt) with rt = wave * 64 + lane.  The forward
+// writes F_TEND, F_LAST and F_K for every chunk and ray; the sums, their merged (global)
+// values and B are written only where the chunk has a contributor for the ray (F_K > 0),
+// since nothing reads them otherwise.
 enum : int { F_TEND = 0, F_SA, F_SD, F_SN0, F_SN1, F_SN2, F_LAST, F_K, F_B, kSlotFields };
 
 __device__ __forceinline__ size_t slot(uint32_t item, int f, int rt)
