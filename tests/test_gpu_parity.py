@@ -254,7 +254,9 @@ def test_ragged_grids(ctx, H, W):
 
 def test_wrap_and_near_surfels(ctx):
     """Surfels straddling azimuth 0, one near the sensor whose footprint covers every tile,
-    one nearer than `near` (dropped), a zero quaternion (dropped) and an edge-on surfel."""
+    one nearer than `near` (dropped), a zero quaternion (dropped), an edge-on surfel, and one
+    whose centre lies beyond `near` while its plane is met nearer than `near` by the ray it
+    faces (that hit is skipped; rays meeting it farther out hit it)."""
     from tests import _util as U
     row, col = scenegen.beam_tables(32, 256, -15, 15)
     D = scenegen.ray_dirs_f64(row, col).reshape(-1, 3)
@@ -279,6 +281,13 @@ def test_wrap_and_near_surfels(ctx):
     frames.append(U.frame_facing(np.cross(D[3000], [0.0, 0.0, 1.0])))
     sc.append([1.0, 1.0])
     al.append(0.9)
+    i_near = 5 * 256 + 100  # upper half, away from the surfels above
+    e = np.cross(D[i_near], [0.0, 0.0, 1.0])
+    e /= np.linalg.norm(e)
+    cen.append(0.15 * D[i_near] + 0.25 * e)  # centre 0.29 m away; met at t = 0.15 m, 1.25 sigma off centre
+    frames.append(U.frame_facing(-D[i_near]))
+    sc.append([0.2, 0.2])
+    al.append(0.9)
     S = {k: v.astype(np.float32) for k, v in U.surfels(cen, frames, sc, al).items()}
     S["quats"][3] = 0.0  # zero quaternion: renders nothing
     wl = dict(S, row_sincos=row, col_sincos=col, pose=np.hstack([np.eye(3), np.zeros((3, 1))]).astype(np.float32))
@@ -289,4 +298,5 @@ def test_wrap_and_near_surfels(ctx):
     _print("wrap/near", stats)
     seam = of["K"].reshape(32, 256)
     assert seam[:, 0].sum() > 0 and seam[:, 255].sum() > 0
+    assert of["K"][i_near] == 0 and float(fr["opacity"].reshape(-1)[i_near]) == 0.0
     st.free()

@@ -26,6 +26,14 @@ MUTATIONS = {
     "quaternion_sign": ("a[1] = 2 * (x * y + w * z);", "a[1] = 2 * (x * y - w * z);"),
     "pose_transposed": ("o[j] = pose[j] * v[0] + pose[4 + j] * v[1] + pose[8 + j] * v[2];",
                         "o[j] = pose[4 * j] * v[0] + pose[4 * j + 1] * v[1] + pose[4 * j + 2] * v[2];"),
+    "alpha_not_clamped": ("double ahat = aG < p->alpha_max ? aG : p->alpha_max;", "double ahat = aG;"),
+    "faint_hits_kept": ("if (ahat < p->alpha_thr) continue;", "if (ahat < 0) continue;"),
+    "no_early_stop": ("if (T < p->T_min) {\n            stopped = 1;", "if (0) {\n            stopped = 1;"),
+    "gaussian_without_half": ("double G = exp(-0.5 * q2);", "double G = exp(-q2);"),
+    "no_support_cutoff": ("if (q2 > k2) continue;", "if (0) continue;"),
+    "hits_behind_near_kept": ("if (t < p->near) continue;", "if (t < 0) continue;"),
+    "depth_not_normalised": ("depth[i] = r.SD / r.A;", "depth[i] = r.SD;"),
+    "drop_inverted": ("drop[i] = r.A < prm->drop_tau;", "drop[i] = r.A >= prm->drop_tau;"),
     # loss
     "normal_loss_gradient_unprojected": (
         "for (int c = 0; c < 3; ++c) g_normal[3 * i + c] = f * (N[c] - cosv * Nh[c] / nn);",

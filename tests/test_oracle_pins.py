@@ -283,6 +283,17 @@ def test_edge_cases(ref, beams):
     # nearer than 0.2 m: dropped even though its footprint covers the ray
     S = U.surfels([0.15 * d0], [U.frame_facing(-d0)], [(1.0, 1.0)], [0.9])
     assert ref.forward(S, U.identity_pose(), rows, cols, PRM, ray_ids=[i0])["K"][0] == 0
+    # the near rule applies per hit: a surfel facing the ray with its centre 0.29 m away
+    # (beyond 0.2 m) but its plane met by the ray at t = 0.15 m gives no hit; moved back so
+    # the ray meets it at 0.30 m, it gives one hit at exactly that depth
+    e = np.cross(d0, [0.0, 0.0, 1.0])
+    e /= np.linalg.norm(e)
+    for t_hit, want_k in ((0.15, 0), (0.30, 1)):
+        S = U.surfels([t_hit * d0 + 0.25 * e], [U.frame_facing(-d0)], [(1.0, 1.0)], [0.9])
+        out = ref.forward(S, U.identity_pose(), rows, cols, PRM, ray_ids=[i0])
+        assert out["K"][0] == want_k, t_hit
+        if want_k:
+            assert out["depth"][0] == pytest.approx(t_hit, rel=1e-12)
     # edge-on: normal orthogonal to the ray through its centre
     F = U.frame_facing(np.cross(d0, [0.0, 0.0, 1.0]))
     S = U.surfels([10 * d0], [F], [(1.0, 1.0)], [0.9])
