@@ -38,10 +38,26 @@ MUTATIONS = {
     "normal_loss_gradient_unprojected": (
         "for (int c = 0; c < 3; ++c) g_normal[3 * i + c] = f * (N[c] - cosv * Nh[c] / nn);",
         "for (int c = 0; c < 3; ++c) g_normal[3 * i + c] = f * N[c];"),
+    "normal_term_over_depth_mask": ("cntN += mN;", "cntN += mD;"),
+    "depth_term_over_all_rays": ("cntD += mD;", "cntD += 1;"),
+    "depth_gradient_unmasked": ("if (g_depth) g_depth[i] = cntD > 0 ? w_depth * mD * sgn / cntD : 0.0;",
+                                "if (g_depth) g_depth[i] = cntD > 0 ? w_depth * sgn / cntD : 0.0;"),
+    "zero_normal_costs_nothing": ("sumN += mN * (nn > 0 ? 1.0 - dot3(Nh, N) / nn : 1.0);",
+                                  "sumN += mN * (nn > 0 ? 1.0 - dot3(Nh, N) / nn : 0.0);"),
     # backward
     "backward_drops_later_hits": ("double d_ahat = h->T * cj - B / (1 - h->ahat);", "double d_ahat = h->T * cj;"),
     "clamp_passes_gradient": ("if (h->aG < prm->alpha_max) { d_alpha = d_ahat * h->G; d_G = d_ahat * s->alpha; }",
                               "{ d_alpha = d_ahat * h->G; d_G = d_ahat * s->alpha; }"),
+    "opacity_gradient_without_mean_terms": (
+        "double gbA = g_opacity[i] - (g_depth[i] * Dh + dot3(gN, Nh)) / A;", "double gbA = g_opacity[i];"),
+    "later_sum_unweighted": ("B += w * cj;", "B += cj;"),
+    "gaussian_gradient_sign": ("double d_q2 = -0.5 * h->G * d_G;", "double d_q2 = 0.5 * h->G * d_G;"),
+    "footprint_gradient_unscaled": ("gDelta[c] = d_u * s->a[c] / s->s0 + d_v * s->b[c] / s->s1;",
+                                    "gDelta[c] = d_u * s->a[c] + d_v * s->b[c];"),
+    "range_gradient_misses_ray": ("double g_t = d_t + dot3(gDelta, d);", "double g_t = d_t;"),
+    "centre_gradient_misses_plane": ("g_mu[c] = -gDelta[c] + g_t * s->n[c] / h->den;", "g_mu[c] = -gDelta[c];"),
+    "v_gradient_uses_u": ("double d_u = 2 * h->u * d_q2, d_v = 2 * h->v * d_q2;",
+                          "double d_u = 2 * h->u * d_q2, d_v = 2 * h->u * d_q2;"),
     "scale_gradient_sign": ("atomic_add(&g->s0, -d_u * h->u / s->s0);", "atomic_add(&g->s0, d_u * h->u / s->s0);"),
     "normal_gradient_sign": ("g_n[c] = -g_t * h->delta[c] / h->den + s->sigma * d_nt[c];",
                              "g_n[c] = g_t * h->delta[c] / h->den + s->sigma * d_nt[c];"),
