@@ -64,6 +64,15 @@ MUTATIONS = {
     "quaternion_gradient_unprojected": (
         "for (int c = 0; c < 4; ++c) dq[c] = (dqh[c] - radial * s->qhat[c]) / s->qnorm;",
         "for (int c = 0; c < 4; ++c) dq[c] = dqh[c] / s->qnorm;"),
+    "logit_gradient_missing_factor": ("*dlog = s->alpha * (1 - s->alpha) * g->alpha;\n    double c1[3]",
+                                      "*dlog = s->alpha * g->alpha;\n    double c1[3]"),
+    "log_scale_gradient_unscaled": ("s->qhat[c]) / s->qnorm;\n    dl[0] = s->s0 * g->s0;",
+                                    "s->qhat[c]) / s->qnorm;\n    dl[0] = g->s0;"),
+    "pose_translation_sign": ("dpose[c] = -g->mu[c];", "dpose[c] = g->mu[c];"),
+    "quaternion_term_sign": ("Gb[0] * 2 * y - Gb[1] * 4 * x + Gb[2] * 2 * w", "Gb[0] * 2 * y - Gb[1] * 4 * x - Gb[2] * 2 * w"),
+    "centre_gradient_not_rotated": ("sensor_to_world_dir(pose, g->mu, dm);",
+                                    "for (int c = 0; c < 3; ++c) dm[c] = g->mu[c];"),
+    "pose_rotation_misses_normal": ("cross3(s->n, g->n, c4);", "c4[0] = c4[1] = c4[2] = 0;"),
     "pose_rotation_sign": ("dpose[3 + c] = -(c1[c] + c2[c] + c3[c] + c4[c]);",
                            "dpose[3 + c] = (c1[c] + c2[c] + c3[c] + c4[c]);"),
     # full objective

@@ -406,6 +406,29 @@ def test_render_backward_matches_finite_differences(ref):
     _fd_check(S, pose, g, func)
 
 
+def test_render_backward_finite_differences_under_a_rotated_pose(ref):
+    """The same check after moving the scene and the pose by one rigid transform: the image
+    does not change, but every surfel and pose gradient now passes through a sensor-to-world
+    rotation that is not the identity (the scene's own pose is)."""
+    S, pose, rows, cols, _, _ = _fd_scene()
+    M = Rotation.from_rotvec([0.4, -0.9, 0.6]).as_matrix()
+    tv = np.array([2.0, -5.0, 0.75])
+    S2 = dict(S)
+    S2["means"] = S["means"] @ M.T + tv
+    S2["quats"] = U.quat_wxyz(M[None] @ U.rot_of_wxyz(S["quats"]))
+    P2 = U.pose_from(M @ pose[:, :3], M @ pose[:, 3] + tv)
+    n = rows.shape[0] * cols.shape[0]
+    rng = np.random.default_rng(6)
+    gD, gA, gN = rng.normal(size=n), rng.normal(size=n), rng.normal(size=(n, 3))
+
+    def func(S_, P_):
+        f = ref.forward(S_, P_, rows, cols, PRM)
+        return (gD * f["depth"]).sum() + (gA * f["opacity"]).sum() + (gN * f["normal"]).sum()
+
+    g = ref.backward(S2, P2, rows, cols, gD, gA, gN, PRM)
+    _fd_check(S2, P2, g, func)
+
+
 def test_loss_gradients_match_finite_differences(ref):
     """Forward + Eqs. 8-9 loss + backward.  Surfels sit on the scanned surfaces, so many
     rendered depths equal their raycast targets exactly, at the corner of |x|; the targets
