@@ -86,12 +86,30 @@ MUTATIONS = {
     "stencil_row_sign": ("g_depth[nb.u] += dot3(du, gb);", "g_depth[nb.u] -= dot3(du, gb);"),
     "stencil_cross_transposed": ("cross3(b, gv, ga);", "cross3(gv, b, ga);"),
     "surf_gradient_unprojected": ("gv[c] = sgn * (gN[c] - gu * u[c]) / vn;", "gv[c] = sgn * gN[c] / vn;"),
+    "bce_sign": ("double tA = cntD > 0 ? -lambda_alpha * sumA / cntD : 0.0;",
+                 "double tA = cntD > 0 ? lambda_alpha * sumA / cntD : 0.0;"),
+    "bce_gradient_without_eps": ("g_opacity[i] = -lambda_alpha / (cntD * (opacity[i] + eps));",
+                                 "g_opacity[i] = -lambda_alpha / (cntD * opacity[i]);"),
+    "surf_normal_unnormalised": ("double Ns[3] = {sgn * v[0] / vn, sgn * v[1] / vn, sgn * v[2] / vn};",
+                                 "double Ns[3] = {sgn * v[0], sgn * v[1], sgn * v[2]};"),
+    "scale_reg_squared": ("if (smax > s_max) sum += smax - s_max;",
+                          "if (smax > s_max) sum += (smax - s_max) * (smax - s_max);"),
+    "scale_reg_gradient_not_chained": ("g_log_scales[2 * i + k] = lambda_s * smax;",
+                                       "g_log_scales[2 * i + k] = lambda_s;"),
     "scale_reg_first_axis_only": ("int k = sy > sx ? 1 : 0;", "int k = 0;"),
     # scan projection and target covariance
     "scan_rows_bottom_up": ("double f = (el_max - el) / step;", "double f = (el - el_min) / step;"),
     "scan_farthest_wins": ("if (index[pix] < 0 || r < depth[pix]) {", "if (index[pix] < 0 || r > depth[pix]) {"),
     "scan_seam_clamped": ("if (j < 0) j += W;", "if (j < 0) j = 0;"),
     "scan_normal_not_turned": ("double sgn = dot3(nv, p) > 0 ? -1.0 : 1.0;", "double sgn = 1.0;"),
+    "scan_range_limits_ignored": ("if (!(r >= r_min && r <= r_max) || kf < 0 || kf > H - 1) continue;",
+                                  "if (kf < 0 || kf > H - 1) continue;"),
+    "scan_columns_truncated": ("double kf = floor(f + 0.5), jf = floor(g + 0.5);",
+                               "double kf = floor(f + 0.5), jf = floor(g);"),
+    "scan_elevation_over_range": ("double el = atan2(p[2], rxy);", "double el = atan2(p[2], r);"),
+    "scan_ties_to_later_point": ("if (index[pix] < 0 || r < depth[pix]) {",
+                                 "if (index[pix] < 0 || r <= depth[pix]) {"),
+    "cov_eps_not_squared": ("eps * eps};", "eps};"),
     "cov_axes_transposed": (
         "S[r][c] = R[r][0] * d[0] * R[c][0] + R[r][1] * d[1] * R[c][1] + R[r][2] * d[2] * R[c][2];",
         "S[r][c] = R[0][r] * d[0] * R[0][c] + R[1][r] * d[1] * R[1][c] + R[2][r] * d[2] * R[2][c];"),
