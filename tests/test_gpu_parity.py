@@ -143,6 +143,34 @@ def test_backward_room(ctx, room, chunk):
     st.free()
 
 
+def test_backward_room_general_rotation(ctx, room):
+    """The room and its pose moved by one rigid transform about a general axis: the image
+    (and so the sensor-frame targets) stays the same, while every entry of the pose rotation
+    is far from zero, so a mixed-up row or column of it in the chain cannot hide."""
+    from scipy.spatial.transform import Rotation
+    from tests import _util as U
+    M = Rotation.from_rotvec([0.4, -0.9, 0.6]).as_matrix()
+    tv = np.array([2.0, -5.0, 0.75])
+    P = np.asarray(room["pose"], np.float64)
+    w = dict(room)
+    w["means"] = (np.asarray(room["means"], np.float64) @ M.T + tv).astype(np.float32)
+    w["quats"] = U.quat_wxyz(M[None] @ U.rot_of_wxyz(np.asarray(room["quats"], np.float64))).astype(np.float32)
+    w["pose"] = U.pose_from(M @ P[:, :3], M @ P[:, 3] + tv).astype(np.float32)
+    assert np.abs(w["pose"][:, :3]).min() > 0.05
+    H, W = w["H"], w["W"]
+    dw = G.to_dev(w)
+    _, st = G.gpu_forward(ctx, dw)
+    of = G.oracle_forward(w)
+    mask = (~G.tie_mask(of)).astype(np.float64)
+    gd, go, gn = _loss_upstream(w, of, mask=mask)
+    rng = np.random.default_rng(4)
+    go = (rng.normal(size=go.shape) * 1e-4 * mask).astype(np.float32)
+    g_gpu, gp = _gpu_backward(ctx, dw, st, H, W, gd, go, gn)
+    g_ref = ref.backward(w, w["pose"], w["row_sincos"], w["col_sincos"], gd, go, gn, with_mass=True)
+    _check_grads("backward room32x256_1k general rotation", g_gpu, gp, g_ref)
+    st.free()
+
+
 def test_end_to_end_loss_and_grad(ctx, room):
     """forward -> loss -> backward entirely on the GPU vs the oracle's loss_and_grad.  The
     surfels sit on the raycast surfaces, so many rendered depths equal their targets
