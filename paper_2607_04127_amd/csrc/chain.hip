@@ -4,11 +4,12 @@
 // (the slots of surfels with a ray rectangle, the only ones the raster writes, are cleared
 // here after they are read, so the next backward finds every slot zero),
 // where the hit test evaluates u = (cu + U.(d - m)) / den with cu = U.m (likewise v).  With
-//   nt = sigma n',  c = nt . mu',  U = sigma (b' x mu') / s0,  V = sigma (mu' x a') / s1
+//   nt = sigma n',  c = nt . mu',  U = sigma (na x mu') / s0,  V = sigma (mu' x bn) / s1,
+//   na = n' x a',  bn = b' x n'
 // (sigma piecewise constant) the total U gradient is gU + gcu m, and with w = mu' x m
-//   dmu' = gc nt + (sigma/s0) (gU + gcu m) x b' + (sigma/s1) a' x (gV + gcv m)
-//   da'  = (sigma/s1) (gV x mu' - gcv w),   db' = (sigma/s0) (mu' x gU + gcu w)
-//   dn'  = sigma (gnt + gc mu')
+//   dmu' = gc nt + (sigma/s0) (gU + gcu m) x na + (sigma/s1) bn x (gV + gcv m)
+//   dbn  = (sigma/s1) (gV x mu' - gcv w),   dna = (sigma/s0) (mu' x gU + gcu w)
+//   da'  = dna x n',   db' = n' x dbn,   dn' = sigma (gnt + gc mu') + a' x dna + dbn x b'
 //   ds0  = -(gU.U + gcu cu) / s0,   ds1 = -(gV.V + gcv cv) / s1
 // (U is nearly perpendicular to m, so these forms avoid the cancellation that products with
 // the unsplit gradient would suffer), then world frame (multiply by R), the rotation columns
@@ -82,17 +83,23 @@ __global__ __launch_bounds__(kChainThreads) void chain_kernel(SurfelPtrs S, cons
                 gVt[c] = fmaf(gcv, q.m[c], gV[c]);
             }
             float t1[3], t2[3];
-            cross(gUt, g.b, t1);
-            cross(g.a, gVt, t2);
-            float gmu[3], gav[3], gbv[3], gnv[3];
+            cross(gUt, q.na, t1);
+            cross(q.bn, gVt, t2);
+            float gmu[3], gna[3], gbn[3], gav[3], gbv[3], gnv[3];
             for (int c = 0; c < 3; ++c) gmu[c] = gc * q.nt[c] + k0 * t1[c] + k1 * t2[c];
             cross(gV, mu, t1);
             cross(mu, gU, t2);
             for (int c = 0; c < 3; ++c) {
-                gav[c] = k1 * fmaf(-gcv, q.w[c], t1[c]);
-                gbv[c] = k0 * fmaf(gcu, q.w[c], t2[c]);
-                gnv[c] = g.sigma * (gnt[c] + gc * mu[c]);
+                gbn[c] = k1 * fmaf(-gcv, q.w[c], t1[c]);
+                gna[c] = k0 * fmaf(gcu, q.w[c], t2[c]);
             }
+            // na = n' x a', bn = b' x n'
+            float t3[3], t4[3];
+            cross(gna, g.n, gav);
+            cross(g.n, gbn, gbv);
+            cross(g.a, gna, t3);
+            cross(gbn, g.b, t4);
+            for (int c = 0; c < 3; ++c) gnv[c] = g.sigma * (gnt[c] + gc * mu[c]) + t3[c] + t4[c];
             const float gs0 = -fmaf(gcu, q.cu, gU[0] * q.U[0] + gU[1] * q.U[1] + gU[2] * q.U[2]) / g.s0;
             const float gs1 = -fmaf(gcv, q.cv, gV[0] * q.V[0] + gV[1] * q.V[1] + gV[2] * q.V[2]) / g.s1;
             // world frame

@@ -6,8 +6,16 @@
 //   sigma = +1 if n'.mu' <= 0 else -1, nt = sigma n' (the normal facing the sensor);
 //   ray d: den = nt.d, hit range t = c / den with c = nt.mu' (<= 0),
 //          u = nu / den, v = nv / den  with nu = U.d, nv = V.d,
-//          U = sigma (b' x mu') / s0,  V = sigma (mu' x a') / s1
-//   (homogeneous form of the ray/plane hit: (t d - mu') . a' / s0 = U.d / den).
+//          U = sigma ((n' x a') x mu') / s0,  V = sigma (mu' x (b' x n')) / s1
+//   (homogeneous form of the ray/plane hit: by the vector triple product,
+//   (t d - mu') . a' / s0 = U.d / den for any three vectors a', b', n'; for an exactly
+//   orthonormal frame n' x a' = b' and b' x n' = a').  The frame itself is only as
+//   orthonormal as float32 allows (the pose rotation is a float32 input), so the record is
+//   built from n' x a' and b' x n' rather than from b' and a': u and v then follow the
+//   definition for the frame the kernels hold.
+// At grazing incidence den is small and t, u, v are sensitive to the plane normal in
+// proportion to 1/den, so the frame is formed from the quaternion and the pose in float
+// pairs and rounded once (sensor_frame below).
 // U.d nearly cancels for rays near the surfel centre (|U| ~ r / s), so it is evaluated as
 //   nu = cu + U . ((d_hi - m) + d_lo),   cu = U . m computed from an error-compensated mu',
 // where m is the float32 unit direction of the centre and d = d_hi + d_lo the exact ray
@@ -97,9 +105,82 @@ __device__ __forceinline__ float diff_prod(float a, float b, float c, float d)
     return f + e;
 }
 
+// Unevaluated float pair h + l.  Sums are not renormalised after every step: the pairs
+// below combine a handful of terms and are rounded once at the end.
+struct F2 {
+    float h, l;
+};
+
+__device__ __forceinline__ F2 f2_mul(float a, float b)
+{
+    F2 r;
+    two_prod(a, b, r.h, r.l);
+    return r;
+}
+
+__device__ __forceinline__ F2 f2_add(F2 x, F2 y)
+{
+    F2 r;
+    two_sum(x.h, y.h, r.h, r.l);
+    r.l += x.l + y.l;
+    return r;
+}
+
+__device__ __forceinline__ F2 f2_neg(F2 x) { return F2{-x.h, -x.l}; }
+__device__ __forceinline__ F2 f2_twice(F2 x) { return F2{2.f * x.h, 2.f * x.l}; }
+
 // ----------------------------------------------------------------------------------------
 // per-surfel projection (shared by the projection and the chain-rule kernels)
 // ----------------------------------------------------------------------------------------
+
+// Sensor-frame rotation columns a' = R^T a, b' = R^T b, n' = R^T n of the normalised
+// quaternion q / |q|, each component rounded once.  With qq = |q|^2 the columns of R(q/|q|)
+// are the columns of the homogeneous quaternion matrix divided by qq:
+//   a = (w2+x2-y2-z2, 2(xy+wz), 2(xz-wy)) / qq,  b = (2(xy-wz), w2-x2+y2-z2, 2(yz+wx)) / qq,
+//   n = (2(xz+wy), 2(yz-wx), w2-x2-y2+z2) / qq.
+// Every product of two inputs is exact as a float pair, so the numerators, the rotation by
+// the pose and the division carry errors of order 2^-44, far below one float32 rounding.
+__device__ __forceinline__ void sensor_frame(const float *q, const Pose &P, float *a, float *b, float *n)
+{
+    const float w = q[0], x = q[1], y = q[2], z = q[3];
+    const F2 ww = f2_mul(w, w), xx = f2_mul(x, x), yy = f2_mul(y, y), zz = f2_mul(z, z);
+    const F2 xy = f2_mul(x, y), wz = f2_mul(w, z), xz = f2_mul(x, z), wy = f2_mul(w, y);
+    const F2 yz = f2_mul(y, z), wx = f2_mul(w, x);
+    const F2 wwxx = f2_add(ww, xx), yyzz = f2_add(yy, zz), wwyy = f2_add(ww, yy), xxzz = f2_add(xx, zz);
+    const F2 wwzz = f2_add(ww, zz), xxyy = f2_add(xx, yy);
+    F2 col[3][3];  // world columns times qq: col[c][k], c = a, b, n
+    col[0][0] = f2_add(wwxx, f2_neg(yyzz));
+    col[0][1] = f2_twice(f2_add(xy, wz));
+    col[0][2] = f2_twice(f2_add(xz, f2_neg(wy)));
+    col[1][0] = f2_twice(f2_add(xy, f2_neg(wz)));
+    col[1][1] = f2_add(wwyy, f2_neg(xxzz));
+    col[1][2] = f2_twice(f2_add(yz, wx));
+    col[2][0] = f2_twice(f2_add(xz, wy));
+    col[2][1] = f2_twice(f2_add(yz, f2_neg(wx)));
+    col[2][2] = f2_add(wwzz, f2_neg(xxyy));
+    const F2 qq = f2_add(wwxx, yyzz);
+    const float iq = 1.f / qq.h;
+    float *out[3] = {a, b, n};
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            // (R^T col)_j = sum_k R[k][j] col[k]
+            F2 acc = f2_mul(P.r[j], col[c][0].h);
+            acc.l = fmaf(P.r[j], col[c][0].l, acc.l);
+#pragma unroll
+            for (int k = 1; k < 3; ++k) {
+                F2 t = f2_mul(P.r[3 * k + j], col[c][k].h);
+                t.l = fmaf(P.r[3 * k + j], col[c][k].l, t.l);
+                acc = f2_add(acc, t);
+            }
+            // (acc.h + acc.l) / (qq.h + qq.l): one correction of the rounded quotient
+            const float q0 = acc.h * iq;
+            const float rem = fmaf(-q0, qq.h, acc.h) + fmaf(-q0, qq.l, acc.l);
+            out[c][j] = fmaf(rem, iq, q0);
+        }
+    }
+}
 
 struct Geom {
     float mh[3], ml[3];  // mu' = mh + ml (compensated)
@@ -108,20 +189,6 @@ struct Geom {
     float s0, s1, alpha, r, sigma;
     bool valid;
 };
-
-__device__ __forceinline__ void quat_columns(const float *q, float *a, float *b, float *n)
-{
-    float w = q[0], x = q[1], y = q[2], z = q[3];
-    a[0] = 1.f - 2.f * (y * y + z * z); a[1] = 2.f * (x * y + w * z);       a[2] = 2.f * (x * z - w * y);
-    b[0] = 2.f * (x * y - w * z);       b[1] = 1.f - 2.f * (x * x + z * z); b[2] = 2.f * (y * z + w * x);
-    n[0] = 2.f * (x * z + w * y);       n[1] = 2.f * (y * z - w * x);       n[2] = 1.f - 2.f * (x * x + y * y);
-}
-
-// v' = R^T v
-__device__ __forceinline__ void rot_t(const Pose &P, const float *v, float *o)
-{
-    for (int j = 0; j < 3; ++j) o[j] = fmaf(P.r[j], v[0], fmaf(P.r[3 + j], v[1], P.r[6 + j] * v[2]));
-}
 
 // v = R v'
 __device__ __forceinline__ void rot(const Pose &P, const float *v, float *o)
@@ -141,11 +208,11 @@ __device__ __forceinline__ Geom project_geom(const float *__restrict__ means, co
     g.valid = g.qn > 0.f && isfinite(g.qn);
     float inv = g.valid ? 1.f / g.qn : 0.f;
     for (int c = 0; c < 4; ++c) g.qh[c] = q[c] * inv;
-    float aw[3], bw[3], nw[3];
-    quat_columns(g.qh, aw, bw, nw);
-    rot_t(P, aw, g.a);
-    rot_t(P, bw, g.b);
-    rot_t(P, nw, g.n);
+    if (g.valid) {
+        sensor_frame(q, P, g.a, g.b, g.n);
+    } else {
+        for (int c = 0; c < 3; ++c) g.a[c] = g.b[c] = g.n[c] = 0.f;
+    }
     // mu - t exactly as a float pair, then R^T (.) with compensated sums
     float dh[3], dl[3];
     for (int c = 0; c < 3; ++c) two_sum(means[3 * i + c], -P.t[c], dh[c], dl[c]);
@@ -178,7 +245,7 @@ __device__ __forceinline__ Geom project_geom(const float *__restrict__ means, co
 // The record quantities of a projected surfel.  The chain rule calls this too, so both see
 // bit-identical values.
 struct RecParts {
-    float nt[3], c, m[3], w[3], U[3], cu, V[3], cv;
+    float nt[3], c, m[3], w[3], na[3], bn[3], U[3], cu, V[3], cv;
 };
 
 __device__ __forceinline__ RecParts record_parts(const Geom &g)
@@ -194,16 +261,23 @@ __device__ __forceinline__ RecParts record_parts(const Geom &g)
     q.w[1] = diff_prod(g.mh[2], q.m[0], g.mh[0], q.m[2]) + (g.ml[2] * q.m[0] - g.ml[0] * q.m[2]);
     q.w[2] = diff_prod(g.mh[0], q.m[1], g.mh[1], q.m[0]) + (g.ml[0] * q.m[1] - g.ml[1] * q.m[0]);
     float i0 = g.sigma / g.s0, i1 = g.sigma / g.s1;
-    // U = sigma (b' x mu') / s0, V = sigma (mu' x a') / s1
-    q.U[0] = (g.b[1] * g.mh[2] - g.b[2] * g.mh[1]) * i0;
-    q.U[1] = (g.b[2] * g.mh[0] - g.b[0] * g.mh[2]) * i0;
-    q.U[2] = (g.b[0] * g.mh[1] - g.b[1] * g.mh[0]) * i0;
-    q.V[0] = (g.mh[1] * g.a[2] - g.mh[2] * g.a[1]) * i1;
-    q.V[1] = (g.mh[2] * g.a[0] - g.mh[0] * g.a[2]) * i1;
-    q.V[2] = (g.mh[0] * g.a[1] - g.mh[1] * g.a[0]) * i1;
-    // U . m = sigma b'.(mu' x m) / s0,   V . m = -sigma a'.(mu' x m) / s1
-    q.cu = fmaf(g.b[0], q.w[0], fmaf(g.b[1], q.w[1], g.b[2] * q.w[2])) * i0;
-    q.cv = -fmaf(g.a[0], q.w[0], fmaf(g.a[1], q.w[1], g.a[2] * q.w[2])) * i1;
+    // na = n' x a' (b' for an orthonormal frame), bn = b' x n' (a')
+    q.na[0] = g.n[1] * g.a[2] - g.n[2] * g.a[1];
+    q.na[1] = g.n[2] * g.a[0] - g.n[0] * g.a[2];
+    q.na[2] = g.n[0] * g.a[1] - g.n[1] * g.a[0];
+    q.bn[0] = g.b[1] * g.n[2] - g.b[2] * g.n[1];
+    q.bn[1] = g.b[2] * g.n[0] - g.b[0] * g.n[2];
+    q.bn[2] = g.b[0] * g.n[1] - g.b[1] * g.n[0];
+    // U = sigma (na x mu') / s0, V = sigma (mu' x bn) / s1
+    q.U[0] = (q.na[1] * g.mh[2] - q.na[2] * g.mh[1]) * i0;
+    q.U[1] = (q.na[2] * g.mh[0] - q.na[0] * g.mh[2]) * i0;
+    q.U[2] = (q.na[0] * g.mh[1] - q.na[1] * g.mh[0]) * i0;
+    q.V[0] = (g.mh[1] * q.bn[2] - g.mh[2] * q.bn[1]) * i1;
+    q.V[1] = (g.mh[2] * q.bn[0] - g.mh[0] * q.bn[2]) * i1;
+    q.V[2] = (g.mh[0] * q.bn[1] - g.mh[1] * q.bn[0]) * i1;
+    // U . m = sigma na.(mu' x m) / s0,   V . m = -sigma bn.(mu' x m) / s1
+    q.cu = fmaf(q.na[0], q.w[0], fmaf(q.na[1], q.w[1], q.na[2] * q.w[2])) * i0;
+    q.cv = -fmaf(q.bn[0], q.w[0], fmaf(q.bn[1], q.w[1], q.bn[2] * q.w[2])) * i1;
     return q;
 }
 

@@ -143,19 +143,42 @@ def test_backward_room(ctx, room, chunk):
     st.free()
 
 
+def _moved(w0, rotvec, tv):
+    """The workload's surfels and pose moved by one rigid transform (M, tv): the image, and
+    so the sensor-frame targets, stay the same in exact arithmetic."""
+    from scipy.spatial.transform import Rotation
+    from tests import _util as U
+    M = Rotation.from_rotvec(rotvec).as_matrix()
+    tv = np.asarray(tv, np.float64)
+    P = np.asarray(w0["pose"], np.float64)
+    w = dict(w0)
+    w["means"] = (np.asarray(w0["means"], np.float64) @ M.T + tv).astype(np.float32)
+    w["quats"] = U.quat_wxyz(M[None] @ U.rot_of_wxyz(np.asarray(w0["quats"], np.float64))).astype(np.float32)
+    w["pose"] = U.pose_from(M @ P[:, :3], M @ P[:, 3] + tv).astype(np.float32)
+    return w
+
+
+def test_forward_room_general_rotation(ctx, room):
+    """Forward parity at a general rigid pose: every entry of the pose rotation is far from
+    zero, and the float32 pose is not exactly orthonormal.  Rays that meet the ground at
+    grazing incidence are sensitive to the plane normal in proportion to 1/(n.d), which the
+    sensor frame formed in float pairs keeps within the 1e-5 bar."""
+    w = _moved(room, [0.4, -0.9, 0.6], [2.0, -5.0, 0.75])
+    assert np.abs(w["pose"][:, :3]).min() > 0.05
+    fr, st = G.gpu_forward(ctx, G.to_dev(w))
+    torch.cuda.synchronize()
+    of = G.oracle_forward(w)
+    stats = G.compare_forward(fr, of)
+    _print("forward room32x256_1k general rotation", stats)
+    assert stats["tie"] < 0.01 * stats["rays"]
+    st.free()
+
+
 def test_backward_room_general_rotation(ctx, room):
     """The room and its pose moved by one rigid transform about a general axis: the image
     (and so the sensor-frame targets) stays the same, while every entry of the pose rotation
     is far from zero, so a mixed-up row or column of it in the chain cannot hide."""
-    from scipy.spatial.transform import Rotation
-    from tests import _util as U
-    M = Rotation.from_rotvec([0.4, -0.9, 0.6]).as_matrix()
-    tv = np.array([2.0, -5.0, 0.75])
-    P = np.asarray(room["pose"], np.float64)
-    w = dict(room)
-    w["means"] = (np.asarray(room["means"], np.float64) @ M.T + tv).astype(np.float32)
-    w["quats"] = U.quat_wxyz(M[None] @ U.rot_of_wxyz(np.asarray(room["quats"], np.float64))).astype(np.float32)
-    w["pose"] = U.pose_from(M @ P[:, :3], M @ P[:, 3] + tv).astype(np.float32)
+    w = _moved(room, [0.4, -0.9, 0.6], [2.0, -5.0, 0.75])
     assert np.abs(w["pose"][:, :3]).min() > 0.05
     H, W = w["H"], w["W"]
     dw = G.to_dev(w)
