@@ -274,6 +274,17 @@ void lgsr_state_free(lgsr_state *state);
  *          below T_min). */
 lgsr_status lgsr_query(lgsr_ctx *ctx, const lgsr_state *state, int64_t out[8]);
 
+/* The sorted list of one 16 x 16-ray tile (tile row tile_row covers ray rows 16 tile_row ..
+ * 16 tile_row + 15, likewise columns) of the forward that produced `state`: the ids of the
+ * surfels whose conservative ray rectangle meets the tile, in compositing order (ascending
+ * sensor-frame centre range, ties by lower index; Sec. 3.1 rendering order as read above).
+ * Every surfel that contributes to a ray of the tile must be in it.  Copies
+ * min(*count, cap) ids into ids (HOST) and sets *count to the list length; waits for the
+ * stream.  Errors: EINVAL (tile outside the grid, NULL count, ids NULL with cap > 0),
+ * ESTATE, EDEVICE. */
+lgsr_status lgsr_tile_list(lgsr_ctx *ctx, const lgsr_state *state, int32_t tile_row, int32_t tile_col,
+                           uint32_t *ids, int64_t cap, int64_t *count);
+
 /* Stage timers.  lgsr_profile selects stages by bit mask (bit k = stage k, 0 = off, -1 =
  * all); each selected stage is then bracketed by HIP events on the context's stream (a
  * stage may span several kernel launches; every event costs a little stream time).

@@ -44,6 +44,7 @@ typedef struct {
     double s0, s1, alpha, r;
     double qhat[4], qnorm;
     int valid;
+    int near_cut; /* a valid rotation, but the centre is nearer than `near` (R11): not rendered */
 } surf_t;
 
 typedef struct {
@@ -52,7 +53,7 @@ typedef struct {
 } hit_t;
 
 typedef struct {
-    double A, SD, SN[3], T, margin, order_gap;
+    double A, SD, SN[3], T, margin, order_gap, den_min;
     int32_t K, n_hits;
 } ray_t;
 
@@ -111,6 +112,7 @@ static void setup_surfels(const lgsr_ref_map *map, const double *pose, const lgs
         s->sigma = dot3(s->n, s->mu) <= 0 ? 1.0 : -1.0;
         for (int c = 0; c < 3; ++c) s->nt[c] = s->sigma * s->n[c];
         s->valid = s->r >= p->near;
+        s->near_cut = !s->valid;
     }
 }
 
@@ -125,15 +127,36 @@ static int cmp_range(const void *x, const void *y)
     return (i > j) - (i < j);
 }
 
-/* Valid surfels in compositing order (R3); returns their count. */
-static int64_t sort_surfels(const surf_t *S, int64_t n, int64_t *order)
+/* Valid surfels in compositing order (R3); returns their count.  When cut != NULL the
+ * surfels dropped only for their centre range (near_cut) are listed there, count in *n_cut. */
+static int64_t sort_surfels(const surf_t *S, int64_t n, int64_t *order, int64_t *cut, int64_t *n_cut)
 {
-    int64_t m = 0;
-    for (int64_t i = 0; i < n; ++i)
+    int64_t m = 0, mc = 0;
+    for (int64_t i = 0; i < n; ++i) {
         if (S[i].valid) order[m++] = i;
+        else if (cut && S[i].near_cut) cut[mc++] = i;
+    }
+    if (n_cut) *n_cut = mc;
     g_sort_S = S;
     qsort(order, (size_t)m, sizeof(int64_t), cmp_range);
     return m;
+}
+
+/* Whether ray d passes every per-hit test of surfel s (R1, R4, R11), ignoring the centre
+ * range; used only for the margin of the centre-range decision. */
+static int passes_hit_tests(const surf_t *s, const double *d, const lgsr_ref_params *p)
+{
+    double den = dot3(s->n, d);
+    if (fabs(den) < p->den_eps) return 0;
+    double t = dot3(s->n, s->mu) / den;
+    if (t < p->near) return 0;
+    double delta[3];
+    for (int c = 0; c < 3; ++c) delta[c] = t * d[c] - s->mu[c];
+    double u = dot3(s->a, delta) / s->s0, v = dot3(s->b, delta) / s->s1;
+    double q2 = u * u + v * v;
+    if (q2 > p->cutoff_sigma * p->cutoff_sigma) return 0;
+    double aG = s->alpha * exp(-0.5 * q2);
+    return (aG < p->alpha_max ? aG : p->alpha_max) >= p->alpha_thr;
 }
 
 static void ray_dir(const lgsr_ref_beams *B, int64_t rid, double *d)
@@ -152,13 +175,20 @@ static double rel_gap(double x, double thr) { return fabs(x - thr) / fabs(thr); 
  * composited hits are recorded in order (capacity: the number of valid surfels).
  * margin: the smallest relative gap between a quantity and the threshold it was tested
  * against (|n'.d| vs den_eps, t vs near, q2 vs k^2, alpha G vs alpha_thr and alpha_max,
- * transmittance vs T_min); order_gap: the smallest relative gap between the centre ranges
- * of consecutive composited surfels.  A small value flags a ray whose result may
- * legitimately differ when computed in lower precision. */
-static void render_ray(const surf_t *S, const int64_t *order, int64_t m, const double *d,
-                       const lgsr_ref_params *p, int want_extra, ray_t *out, hit_t *hits)
+ * transmittance vs T_min, and the centre range vs near of every surfel the ray composites
+ * or, among those cut for their centre range, every one whose hit tests it passes, listed
+ * in cut[0 .. n_cut)); order_gap: the smallest relative gap between the centre ranges of
+ * consecutive composited surfels.  A small value flags a ray whose result may legitimately
+ * differ when computed in lower precision.  den_min: the smallest |n'.d| over the composited
+ * hits (the ray/plane intersection amplifies errors of the plane normal by 1 / |n'.d|). */
+static void render_ray(const surf_t *S, const int64_t *order, int64_t m, const int64_t *cut, int64_t n_cut,
+                       const double *d, const lgsr_ref_params *p, int want_extra, ray_t *out, hit_t *hits)
 {
     double T = 1, A = 0, SD = 0, SN[3] = {0, 0, 0}, margin = INFINITY, order_gap = INFINITY;
+    double den_min = INFINITY;
+    if (want_extra)
+        for (int64_t ci = 0; ci < n_cut; ++ci)
+            if (passes_hit_tests(&S[cut[ci]], d, p)) margin = fmin(margin, rel_gap(S[cut[ci]].r, p->near));
     int32_t K = 0, nh = 0;
     int stopped = 0;
     double k2 = p->cutoff_sigma * p->cutoff_sigma, prev_r = -1;
@@ -198,6 +228,10 @@ static void render_ray(const surf_t *S, const int64_t *order, int64_t m, const d
         }
         if (want_extra && prev_r >= 0) order_gap = fmin(order_gap, rel_gap(s->r, prev_r));
         prev_r = s->r;
+        if (want_extra) {
+            margin = fmin(margin, rel_gap(s->r, p->near));
+            den_min = fmin(den_min, fabs(den));
+        }
         double w = T * ahat;
         A += w;
         SD += w * t;
@@ -212,6 +246,7 @@ static void render_ray(const surf_t *S, const int64_t *order, int64_t m, const d
     }
     out->A = A; out->SD = SD; out->T = T; out->K = K; out->n_hits = nh; out->margin = margin;
     out->order_gap = order_gap;
+    out->den_min = den_min;
     for (int c = 0; c < 3; ++c) out->SN[c] = SN[c];
 }
 
@@ -233,23 +268,25 @@ int lgsr_ref_forward(const lgsr_ref_map *map, const double pose[12], const lgsr_
                      const lgsr_ref_params *prm, int64_t n_rays, const int64_t *ray_ids,
                      double *depth, double *opacity, double *normal, uint8_t *drop,
                      double *t_final, int32_t *n_contrib, double *margin, double *order_gap,
-                     int32_t *n_hits)
+                     int32_t *n_hits, double *den_min)
 {
     if (check_args(map, pose, beams, prm, n_rays, ray_ids)) return -1;
     if (n_rays > 0 && (!depth || !opacity || !normal || !drop)) return -1;
     surf_t *S = (surf_t *)calloc((size_t)(map->n > 0 ? map->n : 1), sizeof(surf_t));
     int64_t *order = (int64_t *)malloc(sizeof(int64_t) * (size_t)(map->n > 0 ? map->n : 1));
-    if (!S || !order) { free(S); free(order); return -1; }
+    int64_t *cut = (int64_t *)malloc(sizeof(int64_t) * (size_t)(map->n > 0 ? map->n : 1));
+    if (!S || !order || !cut) { free(S); free(order); free(cut); return -1; }
     setup_surfels(map, pose, prm, S);
-    int64_t m = sort_surfels(S, map->n, order);
-    int want_extra = (margin != NULL) || (n_hits != NULL) || (order_gap != NULL);
+    int64_t n_cut = 0;
+    int64_t m = sort_surfels(S, map->n, order, cut, &n_cut);
+    int want_extra = (margin != NULL) || (n_hits != NULL) || (order_gap != NULL) || (den_min != NULL);
 #pragma omp parallel for schedule(dynamic, 16)
     for (int64_t i = 0; i < n_rays; ++i) {
         int64_t rid = ray_ids ? ray_ids[i] : i;
         double d[3];
         ray_dir(beams, rid, d);
         ray_t r;
-        render_ray(S, order, m, d, prm, want_extra, &r, NULL);
+        render_ray(S, order, m, cut, n_cut, d, prm, want_extra, &r, NULL);
         if (r.K == 0) {
             depth[i] = 0; opacity[i] = 0;
             normal[3 * i] = normal[3 * i + 1] = normal[3 * i + 2] = 0;
@@ -265,9 +302,11 @@ int lgsr_ref_forward(const lgsr_ref_map *map, const double pose[12], const lgsr_
         if (margin) margin[i] = r.margin;
         if (order_gap) order_gap[i] = r.order_gap;
         if (n_hits) n_hits[i] = r.n_hits;
+        if (den_min) den_min[i] = r.den_min;
     }
     free(S);
     free(order);
+    free(cut);
     return 0;
 }
 
@@ -434,7 +473,7 @@ int lgsr_ref_backward(const lgsr_ref_map *map, const double pose[12], const lgsr
     if (pose_mass)
         for (int c = 0; c < 6; ++c) pose_mass[c] = 0;
     setup_surfels(map, pose, prm, S);
-    int64_t m = sort_surfels(S, n, order);
+    int64_t m = sort_surfels(S, n, order, NULL, NULL);
 
 #pragma omp parallel
     {
@@ -445,7 +484,7 @@ int lgsr_ref_backward(const lgsr_ref_map *map, const double pose[12], const lgsr
             double d[3];
             ray_dir(beams, rid, d);
             ray_t r;
-            render_ray(S, order, m, d, prm, 0, &r, hits);
+            render_ray(S, order, m, NULL, 0, d, prm, 0, &r, hits);
             if (r.K == 0) continue;
             /* dL = gD dDhat + gA dA + gN.dNhat with Dhat = SD/A, Nhat = SN/A:
              * dL = (gD/A) dSD + (gN/A).dSN + (gA - (gD Dhat + gN.Nhat)/A) dA. */
@@ -837,6 +876,61 @@ int lgsr_ref_target_cov(int64_t n, const double *quats, const double *log_scales
         o[5] = S[2][2];
     }
     return 0;
+}
+
+/* The valid surfels in compositing order (R3) with their sensor-frame centre ranges. */
+int lgsr_ref_order(const lgsr_ref_map *map, const double pose[12], const lgsr_ref_params *prm, int64_t *order,
+                   double *range, int64_t *m_out)
+{
+    if (!map || !pose || !prm || !m_out || map->n < 0) return -1;
+    if (map->n > 0 && (!order || !range || !map->means || !map->quats || !map->log_scales || !map->opacity_logits))
+        return -1;
+    surf_t *S = (surf_t *)calloc((size_t)(map->n > 0 ? map->n : 1), sizeof(surf_t));
+    if (!S) return -1;
+    setup_surfels(map, pose, prm, S);
+    int64_t m = sort_surfels(S, map->n, order, NULL, NULL);
+    for (int64_t k = 0; k < m; ++k) range[k] = S[order[k]].r;
+    *m_out = m;
+    free(S);
+    return 0;
+}
+
+/* The composited surfels of each of n_rays rays, front to back: ray i's ids in
+ * ids[i * cap .. i * cap + min(count[i], cap)), count[i] its hit count K. */
+int lgsr_ref_contributors(const lgsr_ref_map *map, const double pose[12], const lgsr_ref_beams *beams,
+                          const lgsr_ref_params *prm, int64_t n_rays, const int64_t *ray_ids, int64_t *ids,
+                          int64_t cap, int32_t *count)
+{
+    if (check_args(map, pose, beams, prm, n_rays, ray_ids) || cap < 0 || (n_rays > 0 && (!count || (cap && !ids))))
+        return -1;
+    surf_t *S = (surf_t *)calloc((size_t)(map->n > 0 ? map->n : 1), sizeof(surf_t));
+    int64_t *order = (int64_t *)malloc(sizeof(int64_t) * (size_t)(map->n > 0 ? map->n : 1));
+    if (!S || !order) { free(S); free(order); return -1; }
+    setup_surfels(map, pose, prm, S);
+    int64_t m = sort_surfels(S, map->n, order, NULL, NULL);
+    int fail = 0;
+#pragma omp parallel
+    {
+        hit_t *hits = (hit_t *)malloc(sizeof(hit_t) * (size_t)(m > 0 ? m : 1));
+        if (!hits) {
+#pragma omp atomic write
+            fail = 1;
+        }
+#pragma omp for schedule(dynamic, 4)
+        for (int64_t i = 0; i < n_rays; ++i) {
+            if (!hits) continue;
+            double d[3];
+            ray_dir(beams, ray_ids ? ray_ids[i] : i, d);
+            ray_t r;
+            render_ray(S, order, m, NULL, 0, d, prm, 0, &r, hits);
+            count[i] = r.K;
+            for (int64_t k = 0; k < r.K && k < cap; ++k) ids[i * cap + k] = hits[k].i;
+        }
+        free(hits);
+    }
+    free(S);
+    free(order);
+    return fail ? -1 : 0;
 }
 
 int lgsr_ref_threads(void)

@@ -58,12 +58,13 @@ typedef struct {
  * t_final (transmittance after the last hit), n_contrib (hits composited), margin (smallest
  * relative distance of any threshold decision to its threshold, see lgsr_ref.c), order_gap
  * (smallest relative centre-range gap between consecutive composited surfels), n_hits
- * (hits passing every test when early termination is ignored). */
+ * (hits passing every test when early termination is ignored), den_min (smallest |n'.d| over
+ * the composited hits, infinity without one). */
 int lgsr_ref_forward(const lgsr_ref_map *map, const double pose[12], const lgsr_ref_beams *beams,
                      const lgsr_ref_params *prm, int64_t n_rays, const int64_t *ray_ids,
                      double *depth, double *opacity, double *normal, uint8_t *drop,
                      double *t_final, int32_t *n_contrib, double *margin, double *order_gap,
-                     int32_t *n_hits);
+                     int32_t *n_hits, double *den_min);
 
 /* Loss over n_rays rays and its gradient with respect to the rendered depth, opacity and
  * normal.  ray_weight (NULL = all ones) multiplies the valid masks; it restricts the loss to
@@ -119,6 +120,18 @@ int lgsr_ref_scan_to_range(int64_t n, const double *points, const double *normal
 
 /* Target covariances of surfels (n x 6: xx, xy, xz, yy, yz, zz), thickness eps. */
 int lgsr_ref_target_cov(int64_t n, const double *quats, const double *log_scales, double eps, double *cov);
+
+/* The surfels that render (valid rotation, centre range >= near) in compositing order:
+ * ascending sensor-frame centre range, equal ranges by ascending index (R3); order[k] the
+ * surfel index, range[k] its range (both capacity n), *m the count. */
+int lgsr_ref_order(const lgsr_ref_map *map, const double pose[12], const lgsr_ref_params *prm, int64_t *order,
+                   double *range, int64_t *m);
+
+/* The composited surfels of each ray, front to back: ray i's ids in ids[i cap ..], at most
+ * cap of them; count[i] = its number of composited hits K. */
+int lgsr_ref_contributors(const lgsr_ref_map *map, const double pose[12], const lgsr_ref_beams *beams,
+                          const lgsr_ref_params *prm, int64_t n_rays, const int64_t *ray_ids, int64_t *ids,
+                          int64_t cap, int32_t *count);
 
 /* Number of OpenMP threads the oracle runs with. */
 int lgsr_ref_threads(void);

@@ -48,7 +48,7 @@ def lib():
             _build.build()
         L = ctypes.CDLL(path)
         vp, i64 = ctypes.c_void_p, ctypes.c_int64
-        L.lgsr_ref_forward.argtypes = [vp, vp, vp, vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.lgsr_ref_forward.argtypes = [vp, vp, vp, vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
         L.lgsr_ref_forward.restype = ctypes.c_int
         L.lgsr_ref_loss.argtypes = [i64, vp, vp, vp, vp, vp, vp, ctypes.c_double, ctypes.c_double,
                                     ctypes.c_double, vp, vp, vp, vp]
@@ -67,6 +67,10 @@ def lib():
         L.lgsr_ref_scan_to_range.restype = ctypes.c_int
         L.lgsr_ref_target_cov.argtypes = [i64, vp, vp, d, vp]
         L.lgsr_ref_target_cov.restype = ctypes.c_int
+        L.lgsr_ref_order.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.lgsr_ref_order.restype = ctypes.c_int
+        L.lgsr_ref_contributors.argtypes = [vp, vp, vp, vp, i64, vp, vp, i64, vp]
+        L.lgsr_ref_contributors.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -118,7 +122,8 @@ def _rays(inp, ray_ids):
 
 def forward(surfels, pose, row_sincos, col_sincos, prm=None, ray_ids=None, extra=False):
     """Render (all rays, or ``ray_ids`` = k * W + j).  Returns float64 arrays: depth, opacity,
-    normal (n,3), drop (uint8), t_final, K; with ``extra`` also margin, order_gap and n_hits."""
+    normal (n,3), drop (uint8), t_final, K; with ``extra`` also margin, order_gap, n_hits and
+    den_min."""
     inp = _Inputs(surfels, pose, row_sincos, col_sincos, prm)
     n_rays, ids = _rays(inp, ray_ids)
     out = dict(depth=np.zeros(n_rays), opacity=np.zeros(n_rays), normal=np.zeros((n_rays, 3)),
@@ -127,14 +132,45 @@ def forward(surfels, pose, row_sincos, col_sincos, prm=None, ray_ids=None, extra
         out["margin"] = np.zeros(n_rays)
         out["order_gap"] = np.zeros(n_rays)
         out["n_hits"] = np.zeros(n_rays, np.int32)
+        out["den_min"] = np.zeros(n_rays)
     rc = lib().lgsr_ref_forward(ctypes.byref(inp.map), _ptr(inp.pose), ctypes.byref(inp.beams),
                                 ctypes.byref(inp.prm), n_rays, _ptr(ids), _ptr(out["depth"]),
                                 _ptr(out["opacity"]), _ptr(out["normal"]), _ptr(out["drop"]),
                                 _ptr(out["t_final"]), _ptr(out["K"]), _ptr(out.get("margin")),
-                                _ptr(out.get("order_gap")), _ptr(out.get("n_hits")))
+                                _ptr(out.get("order_gap")), _ptr(out.get("n_hits")), _ptr(out.get("den_min")))
     if rc != 0:
         raise ValueError("lgsr_ref_forward rejected its arguments")
     return out
+
+
+def order(surfels, pose, prm=None):
+    """(order, range): the rendering surfels in compositing order and their FP64 centre
+    ranges."""
+    row = np.zeros((1, 2))
+    inp = _Inputs(surfels, pose, row, row, prm)
+    o = np.zeros(max(1, inp.n), np.int64)
+    r = np.zeros(max(1, inp.n))
+    m = ctypes.c_int64(0)
+    rc = lib().lgsr_ref_order(ctypes.byref(inp.map), _ptr(inp.pose), ctypes.byref(inp.prm), _ptr(o), _ptr(r),
+                              ctypes.byref(m))
+    if rc != 0:
+        raise ValueError("lgsr_ref_order rejected its arguments")
+    return o[:m.value], r[:m.value]
+
+
+def contributors(surfels, pose, row_sincos, col_sincos, ray_ids, prm=None, cap=256):
+    """Per ray of ray_ids: the composited surfel ids front to back (list of int64 arrays)."""
+    inp = _Inputs(surfels, pose, row_sincos, col_sincos, prm)
+    n_rays, ids = _rays(inp, ray_ids)
+    out = np.zeros((max(1, n_rays), cap), np.int64)
+    cnt = np.zeros(max(1, n_rays), np.int32)
+    rc = lib().lgsr_ref_contributors(ctypes.byref(inp.map), _ptr(inp.pose), ctypes.byref(inp.beams),
+                                     ctypes.byref(inp.prm), n_rays, _ptr(ids), _ptr(out), cap, _ptr(cnt))
+    if rc != 0:
+        raise ValueError("lgsr_ref_contributors rejected its arguments")
+    if np.any(cnt[:n_rays] > cap):
+        raise ValueError("more contributors than cap")
+    return [out[i, :cnt[i]].copy() for i in range(n_rays)]
 
 
 def loss(pred, target_depth, target_normal, weights=None, ray_weight=None):

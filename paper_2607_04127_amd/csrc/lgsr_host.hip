@@ -992,6 +992,36 @@ lgsr_status lgsr_query(lgsr_ctx *ctx, const lgsr_state *S, int64_t out[8])
     return LGSR_OK;
 }
 
+lgsr_status lgsr_tile_list(lgsr_ctx *ctx, const lgsr_state *S, int32_t tile_row, int32_t tile_col, uint32_t *ids,
+                           int64_t cap, int64_t *count)
+{
+    if (!ctx) return LGSR_EINVAL;
+    if (!S || !count || (cap > 0 && !ids) || cap < 0) return fail(ctx, LGSR_EINVAL, "state, ids or count invalid");
+    if (S->ctx != ctx || !S->live) return fail(ctx, LGSR_ESTATE, "state does not belong to this context");
+    if (tile_row < 0 || tile_row >= S->g.TH || tile_col < 0 || tile_col >= S->g.TW)
+        return fail(ctx, LGSR_EINVAL, "tile (%d, %d) outside the %d x %d tile grid", tile_row, tile_col, S->g.TH,
+                    S->g.TW);
+    HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
+    hipStream_t s = ctx->stream;
+    const int t = tile_id(tile_row, tile_col, S->g.TH);
+    uint2 rg{0u, 0u};
+    if (S->P > 0) {
+        HIP_TRY(hipMemcpyAsync(&rg, as<uint2>(const_cast<lgsr_state *>(S)->ranges) + t, sizeof(uint2),
+                               hipMemcpyDeviceToHost, s),
+                "tile range");
+        HIP_TRY(hipStreamSynchronize(s), "tile range sync");
+    }
+    const int64_t len = (int64_t)rg.y - (int64_t)rg.x;
+    *count = len;
+    if (len > 0 && cap > 0) {
+        HIP_TRY(hipMemcpyAsync(ids, S->ids + rg.x, (size_t)std::min(len, cap) * sizeof(uint32_t),
+                               hipMemcpyDeviceToHost, s),
+                "tile list");
+        HIP_TRY(hipStreamSynchronize(s), "tile list sync");
+    }
+    return LGSR_OK;
+}
+
 lgsr_status lgsr_profile(lgsr_ctx *ctx, int32_t stage_mask)
 {
     if (!ctx) return LGSR_EINVAL;

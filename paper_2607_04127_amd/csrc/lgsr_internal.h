@@ -129,6 +129,31 @@ __device__ __forceinline__ F2 f2_add(F2 x, F2 y)
 __device__ __forceinline__ F2 f2_neg(F2 x) { return F2{-x.h, -x.l}; }
 __device__ __forceinline__ F2 f2_twice(F2 x) { return F2{2.f * x.h, 2.f * x.l}; }
 
+// x y for pairs, to about 2^-46 relative: the low-order cross terms are added to the exact
+// product of the high parts
+__device__ __forceinline__ F2 f2_mul2(F2 x, F2 y)
+{
+    F2 r = f2_mul(x.h, y.h);
+    r.l = fmaf(x.h, y.l, fmaf(x.l, y.h, r.l));
+    return r;
+}
+
+// o = x cross y, float32 inputs, exact as float pairs
+__device__ __forceinline__ void cross_f2(const float *x, const float *y, F2 *o)
+{
+    o[0] = f2_add(f2_mul(x[1], y[2]), f2_neg(f2_mul(x[2], y[1])));
+    o[1] = f2_add(f2_mul(x[2], y[0]), f2_neg(f2_mul(x[0], y[2])));
+    o[2] = f2_add(f2_mul(x[0], y[1]), f2_neg(f2_mul(x[1], y[0])));
+}
+
+// o = x cross y for pair vectors
+__device__ __forceinline__ void cross_f2f2(const F2 *x, const F2 *y, F2 *o)
+{
+    o[0] = f2_add(f2_mul2(x[1], y[2]), f2_neg(f2_mul2(x[2], y[1])));
+    o[1] = f2_add(f2_mul2(x[2], y[0]), f2_neg(f2_mul2(x[0], y[2])));
+    o[2] = f2_add(f2_mul2(x[0], y[1]), f2_neg(f2_mul2(x[1], y[0])));
+}
+
 // ----------------------------------------------------------------------------------------
 // per-surfel projection (shared by the projection and the chain-rule kernels)
 // ----------------------------------------------------------------------------------------
@@ -232,7 +257,17 @@ __device__ __forceinline__ Geom project_geom(const float *__restrict__ means, co
     g.s0 = expf(log_scales[2 * i]);
     g.s1 = expf(log_scales[2 * i + 1]);
     g.alpha = 1.f / (1.f + expf(-logits[i]));
-    g.r = sqrtf(fmaf(g.mh[0], g.mh[0], fmaf(g.mh[1], g.mh[1], g.mh[2] * g.mh[2])));
+    // r = |mu'| from the compensated centre: r^2 as a pair (exact squares of the high parts,
+    // cross terms 2 mh ml), then one Newton correction of the float32 square root.  The range
+    // key orders the lists, so r is within about half an ulp of |mu'|: two centres can only
+    // compare in the wrong order when their ranges differ by less than 2^-22 relative.
+    {
+        F2 rr = f2_add(f2_add(f2_mul(g.mh[0], g.mh[0]), f2_mul(g.mh[1], g.mh[1])), f2_mul(g.mh[2], g.mh[2]));
+        rr.l = fmaf(2.f * g.mh[0], g.ml[0], fmaf(2.f * g.mh[1], g.ml[1], fmaf(2.f * g.mh[2], g.ml[2], rr.l)));
+        const float r0 = sqrtf(rr.h);
+        const float res = fmaf(-r0, r0, rr.h) + rr.l;
+        g.r = r0 > 0.f ? fmaf(res, 0.5f / r0, r0) : r0;
+    }
     float nm = fmaf(g.n[0], g.mh[0], fmaf(g.n[1], g.mh[1], g.n[2] * g.mh[2]))
              + fmaf(g.n[0], g.ml[0], fmaf(g.n[1], g.ml[1], g.n[2] * g.ml[2]));
     g.sigma = nm <= 0.f ? 1.f : -1.f;
@@ -261,20 +296,24 @@ __device__ __forceinline__ RecParts record_parts(const Geom &g)
     q.w[1] = diff_prod(g.mh[2], q.m[0], g.mh[0], q.m[2]) + (g.ml[2] * q.m[0] - g.ml[0] * q.m[2]);
     q.w[2] = diff_prod(g.mh[0], q.m[1], g.mh[1], q.m[0]) + (g.ml[0] * q.m[1] - g.ml[1] * q.m[0]);
     float i0 = g.sigma / g.s0, i1 = g.sigma / g.s1;
-    // na = n' x a' (b' for an orthonormal frame), bn = b' x n' (a')
-    q.na[0] = g.n[1] * g.a[2] - g.n[2] * g.a[1];
-    q.na[1] = g.n[2] * g.a[0] - g.n[0] * g.a[2];
-    q.na[2] = g.n[0] * g.a[1] - g.n[1] * g.a[0];
-    q.bn[0] = g.b[1] * g.n[2] - g.b[2] * g.n[1];
-    q.bn[1] = g.b[2] * g.n[0] - g.b[0] * g.n[2];
-    q.bn[2] = g.b[0] * g.n[1] - g.b[1] * g.n[0];
-    // U = sigma (na x mu') / s0, V = sigma (mu' x bn) / s1
-    q.U[0] = (q.na[1] * g.mh[2] - q.na[2] * g.mh[1]) * i0;
-    q.U[1] = (q.na[2] * g.mh[0] - q.na[0] * g.mh[2]) * i0;
-    q.U[2] = (q.na[0] * g.mh[1] - q.na[1] * g.mh[0]) * i0;
-    q.V[0] = (g.mh[1] * q.bn[2] - g.mh[2] * q.bn[1]) * i1;
-    q.V[1] = (g.mh[2] * q.bn[0] - g.mh[0] * q.bn[2]) * i1;
-    q.V[2] = (g.mh[0] * q.bn[1] - g.mh[1] * q.bn[0]) * i1;
+    // na = n' x a' (b' for an orthonormal frame), bn = b' x n' (a'), exact as float pairs
+    F2 na[3], bn[3];
+    cross_f2(g.n, g.a, na);
+    cross_f2(g.b, g.n, bn);
+    // U = sigma (na x mu') / s0, V = sigma (mu' x bn) / s1 from the pairs and the compensated
+    // centre, rounded once.  A grazing ray (small n'.d) would amplify any rounding of na, bn
+    // or mu' inside U, V by 1 / |n'.d|: U.d / den changes by (delta x mu').d / den for an
+    // error delta in na; only errors of the form R^T(delta a) cancel against den.
+    const F2 mu[3] = {{g.mh[0], g.ml[0]}, {g.mh[1], g.ml[1]}, {g.mh[2], g.ml[2]}};
+    F2 Uc[3], Vc[3];
+    cross_f2f2(na, mu, Uc);
+    cross_f2f2(mu, bn, Vc);
+    for (int k = 0; k < 3; ++k) {
+        q.na[k] = na[k].h + na[k].l;
+        q.bn[k] = bn[k].h + bn[k].l;
+        q.U[k] = fmaf(Uc[k].h, i0, Uc[k].l * i0);
+        q.V[k] = fmaf(Vc[k].h, i1, Vc[k].l * i1);
+    }
     // U . m = sigma na.(mu' x m) / s0,   V . m = -sigma bn.(mu' x m) / s1
     q.cu = fmaf(q.na[0], q.w[0], fmaf(q.na[1], q.w[1], q.na[2] * q.w[2])) * i0;
     q.cv = -fmaf(q.bn[0], q.w[0], fmaf(q.bn[1], q.w[1], q.bn[2] * q.w[2])) * i1;

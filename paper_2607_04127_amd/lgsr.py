@@ -23,7 +23,7 @@ EXPORTS = ("lgsr_default_opts", "lgsr_default_loss_weights", "lgsr_create", "lgs
            "lgsr_last_error", "lgsr_forward", "lgsr_loss", "lgsr_backward", "lgsr_state_free", "lgsr_query",
            "lgsr_profile", "lgsr_profile_read", "lgsr_sync", "lgsr_state_bytes", "lgsr_adam_step",
            "lgsr_render_batch", "lgsr_default_objective_weights", "lgsr_objective", "lgsr_scale_reg",
-           "lgsr_scan_to_range", "lgsr_target_cov")
+           "lgsr_scan_to_range", "lgsr_target_cov", "lgsr_tile_list")
 STAGES = ("project", "scan", "readback", "emit", "tile_sort", "raster_fwd", "loss", "bwd_prep", "raster_bwd",
           "chain")
 
@@ -126,10 +126,12 @@ def lib():
         L.lgsr_scale_reg.argtypes = [vp, ctypes.c_int64, vp, ctypes.c_float, ctypes.c_float, vp, vp]
         L.lgsr_scan_to_range.argtypes = [vp, ctypes.c_int64, vp, vp, P(ScanGrid), vp, vp, vp]
         L.lgsr_target_cov.argtypes = [vp, ctypes.c_int64, vp, vp, ctypes.c_float, vp]
+        L.lgsr_tile_list.argtypes = [vp, vp, ctypes.c_int32, ctypes.c_int32, vp, ctypes.c_int64,
+                                     P(ctypes.c_int64)]
         for name in ("lgsr_create", "lgsr_set_stream", "lgsr_forward", "lgsr_loss", "lgsr_backward", "lgsr_query",
                      "lgsr_profile", "lgsr_profile_read", "lgsr_sync", "lgsr_state_bytes", "lgsr_adam_step",
                      "lgsr_render_batch", "lgsr_objective", "lgsr_scale_reg", "lgsr_scan_to_range",
-                     "lgsr_target_cov"):
+                     "lgsr_target_cov", "lgsr_tile_list"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -430,6 +432,18 @@ def lgsr_query(ctx: Context, state: State) -> dict:
     ctx._check(lib().lgsr_query(ctx.handle, state.handle, o))
     return dict(pairs=o[0], visible=o[1], workspace_bytes=o[2], max_list=o[3], ray_tests=o[4], composites=o[5],
                 rays_hit=o[6], ray_tests_needed=o[7])
+
+
+def lgsr_tile_list(ctx: Context, state: State, tile_row: int, tile_col: int):
+    """The sorted surfel ids (numpy uint32) of one 16 x 16-ray tile's list; waits."""
+    import numpy as np
+    n = ctypes.c_int64(0)
+    ctx._stream()
+    ctx._check(lib().lgsr_tile_list(ctx.handle, state.handle, tile_row, tile_col, None, 0, ctypes.byref(n)))
+    out = np.zeros(max(1, n.value), np.uint32)
+    ctx._check(lib().lgsr_tile_list(ctx.handle, state.handle, tile_row, tile_col,
+                                    out.ctypes.data_as(ctypes.c_void_p), n.value, ctypes.byref(n)))
+    return out[:n.value]
 
 
 def lgsr_render_batch(ctx: Context, requests, opts: RasterOpts | None = None, weights: LossWeights | None = None):

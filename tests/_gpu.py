@@ -13,10 +13,11 @@ Tolerances (float32 renderer against the float64 oracle):
                   contributors render depth = t exactly, so moving one along the plane
                   changes nothing) and carry float32 noise of about eps32 x mass.
 Tie rays -- a threshold decision within 1e-4 relative of its threshold, or two
-consecutive contributors whose centre ranges differ by less than 5e-7 relative (about four
-float32 rounding errors of the range, which decides the compositing order), where a float32
-evaluation may legitimately decide differently -- are excluded from value parity and
-reported; their upstream gradient is zeroed on both sides in gradient parity.
+consecutive contributors whose centre ranges differ by less than 2.4e-7 = 2^-22 relative
+(the renderer's float32 range key is within about half an ulp of the range, so two keys can
+only order two centres against their true order when the ranges are within two ulps),
+where a float32 evaluation may legitimately decide differently -- are excluded from value
+parity and reported; their upstream gradient is zeroed on both sides in gradient parity.
 """
 from __future__ import annotations
 
@@ -26,7 +27,7 @@ import torch
 from oracle import ref
 
 TIE_MARGIN = 1e-4
-TIE_ORDER = 5e-7
+TIE_ORDER = 2.4e-7
 SURF_KEYS = ("means", "quats", "log_scales", "opacity_logits")
 
 
@@ -56,8 +57,17 @@ def tie_mask(of):
     return (of["margin"] < TIE_MARGIN) | (of["order_gap"] < TIE_ORDER)
 
 
-def compare_forward(fr, of, ray_ids=None, rel=1e-5, natol=1e-4):
-    """Returns a dict of statistics; raises AssertionError on a parity failure."""
+def compare_forward(fr, of, ray_ids=None, rel=1e-5, natol=1e-4, conditioned=False):
+    """Returns a dict of statistics; raises AssertionError on a parity failure.
+
+    conditioned: the bars of a ray grow with 1 / den_min, the smallest |n'.d| among its
+    contributors.  The renderer evaluates den = n'.d in float32 from a rounded normal and
+    rounded ray components: |error| <= 3 * 2^-24 (half an ulp of each of the normal's and
+    the direction's components, one ulp of the sum).  t, u and v all carry den as a divisor,
+    so q^2 = u^2 + v^2 moves by 2 q^2 |error| / den and G = exp(-q^2 / 2) by a relative
+    q^2 |error| / den <= 9 * 1.8e-7 / den = 1.6e-6 / den.  The bars are therefore
+    max(rel, 1.6e-6 / den_min) and max(natol, 1.6e-5 / den_min): unchanged for
+    |n'.d| >= 0.16."""
     dep = fr["depth"].detach().cpu().numpy().reshape(-1).astype(np.float64)
     opa = fr["opacity"].detach().cpu().numpy().reshape(-1).astype(np.float64)
     nrm = fr["normal"].detach().cpu().numpy().reshape(-1, 3).astype(np.float64)
@@ -79,6 +89,13 @@ def compare_forward(fr, of, ray_ids=None, rel=1e-5, natol=1e-4):
                  tie_threshold=int((of["margin"] < TIE_MARGIN).sum()), tie_order=int((of["order_gap"] < TIE_ORDER).sum()),
                  max_rel_depth=float(e_d.max(initial=0)), max_rel_opacity=float(e_a.max(initial=0)),
                  max_abs_normal=float(e_n.max(initial=0)))
+    if conditioned:
+        dmin = of["den_min"][m]
+        rel = np.maximum(rel, 1.6e-6 / dmin)
+        natol = np.maximum(natol, 1.6e-5 / dmin)
+        stats.update(conditioned_rays=int((dmin < 0.16).sum()), min_den=float(dmin.min(initial=1.0)),
+                     worst_of_bar=float(max((e_d / rel).max(initial=0), (e_a / rel).max(initial=0),
+                                            (e_n / natol).max(initial=0))))
     bad_d, bad_a, bad_n = (e_d > rel).sum(), (e_a > rel).sum(), (e_n > natol).sum()
     assert bad_d == 0 and bad_a == 0 and bad_n == 0, (bad_d, bad_a, bad_n, stats)
     drop_ok = (drp[ok] == of["drop"][ok]) | (np.abs(of["opacity"][ok] - 0.5) < 1e-5)
@@ -90,6 +107,30 @@ def grad_check(g, g_ref, mass=None, rel=1e-3, floor=3e-2, per_row=True):
     """(failures, cosine, worst error / bound).  per_row: rows of a 2-D array are one
     surfel's vector; otherwise every element is judged on its own.  mass: per row (or per
     element) sum of contribution magnitudes; without it the floor is relative to the rms."""
+    r = grad_report(g, g_ref, mass, rel, floor, per_row)
+    return r["bad"], r["cos"], r["worst"]
+
+
+def grad_report(g, g_ref, mass=None, rel=1e-3, floor=3e-2, per_row=True):
+    """grad_check's verdict plus two diagnostics:
+      floor_only -- rows within the bound only because of the mass floor (their error
+                    exceeds rel * |g_ref row|);
+      elem_bad   -- elements failing the plain element-wise rule
+                    |g - g_ref| <= rel * max(|g_ref|, 1e-3 * rms(g_ref)),
+      elem_bad_nonfloor -- of those, elements in rows that pass without the floor."""
+    r = _grad_rows(g, g_ref, mass, rel, floor, per_row)
+    g = np.asarray(g, np.float64).reshape(-1)
+    gr = np.asarray(g_ref, np.float64).reshape(-1)
+    rms = float(np.sqrt(np.mean(gr ** 2))) if gr.size else 0.0
+    ebad = np.abs(g - gr) > rel * np.maximum(np.abs(gr), 1e-3 * rms) + 1e-30
+    per = ebad.reshape(r["nrows"], -1).any(axis=1)
+    r.update(elem_bad=int(ebad.sum()), elem_bad_rows=int(per.sum()),
+             elem_bad_nonfloor=int((per & ~r["floor_rows"]).sum()), elems=int(gr.size))
+    del r["floor_rows"]
+    return r
+
+
+def _grad_rows(g, g_ref, mass, rel, floor, per_row):
     g = np.asarray(g, np.float64)
     g_ref = np.asarray(g_ref, np.float64)
     if not per_row or g_ref.ndim == 1:
@@ -99,8 +140,12 @@ def grad_check(g, g_ref, mass=None, rel=1e-3, floor=3e-2, per_row=True):
     else:
         scale = np.asarray(mass, np.float64).reshape(-1)
     err = np.abs(g - g_ref).max(axis=1)
-    bound = rel * np.maximum(np.linalg.norm(g_ref, axis=1), floor * scale)
+    norm = np.linalg.norm(g_ref, axis=1)
+    bound = rel * np.maximum(norm, floor * scale)
     bad = err > bound + 1e-30
+    floor_rows = ~bad & (err > rel * norm + 1e-30)
     gf, rf = g.reshape(-1), g_ref.reshape(-1)
     cos = float(gf @ rf / (np.linalg.norm(gf) * np.linalg.norm(rf) + 1e-300))
-    return int(bad.sum()), cos, float((err / np.maximum(bound, 1e-300)).max(initial=0))
+    return dict(bad=int(bad.sum()), cos=cos, worst=float((err / np.maximum(bound, 1e-300)).max(initial=0)),
+                floor_only=int(floor_rows.sum()), rows=int(g_ref.shape[0]), nrows=int(g_ref.shape[0]),
+                floor_rows=floor_rows)

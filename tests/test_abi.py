@@ -50,6 +50,7 @@ def test_null_and_bad_arguments_rejected(L):
     assert lib.lgsr_loss(None, 0, None, None, None, None, None, None) == L.LGSR_EINVAL
     assert lib.lgsr_backward(None, None, None, None, None) == L.LGSR_EINVAL
     assert lib.lgsr_query(None, None, None) == L.LGSR_EINVAL
+    assert lib.lgsr_tile_list(None, None, 0, 0, None, 0, None) == L.LGSR_EINVAL
     assert lib.lgsr_sync(None) == L.LGSR_EINVAL
     lib.lgsr_destroy(None)
     lib.lgsr_state_free(None)

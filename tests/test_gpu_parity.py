@@ -66,13 +66,20 @@ def _gpu_backward(ctx, dw, state, H, W, gd, go, gn, ray_ids=None):
 
 
 def _check_grads(name, g_gpu, gp_gpu, g_ref):
-    report = {}
+    """Per parameter kind: (failures, cosine, worst error / bound); the diagnostics line
+    gives, per kind, the rows that pass only through the mass floor and the elements that
+    miss the plain element-wise rule (all of them / those in rows passing without the floor)."""
+    report, diag = {}, {}
     for k, key in enumerate(G.SURF_KEYS):
-        nbad, cos, worst = G.grad_check(g_gpu[key], g_ref[key], mass=g_ref["mass"][:, k])
-        report[key] = (nbad, round(cos, 9), round(worst, 3))
-    nbad_p, cos_p, worst_p = G.grad_check(gp_gpu, g_ref["pose"], mass=g_ref["pose_mass"], per_row=False)
-    report["pose"] = (nbad_p, round(cos_p, 9), round(worst_p, 3))
+        r = G.grad_report(g_gpu[key], g_ref[key], mass=g_ref["mass"][:, k])
+        report[key] = (r["bad"], round(r["cos"], 9), round(r["worst"], 3))
+        diag[key] = f"floor_only={r['floor_only']}/{r['rows']} elem={r['elem_bad']}/{r['elems']} " \
+                    f"elem_nonfloor={r['elem_bad_nonfloor']}"
+    r = G.grad_report(gp_gpu, g_ref["pose"], mass=g_ref["pose_mass"], per_row=False)
+    report["pose"] = (r["bad"], round(r["cos"], 9), round(r["worst"], 3))
+    diag["pose"] = f"floor_only={r['floor_only']}/6 elem={r['elem_bad']}/6"
     _print(name, report)
+    _print(name + " diagnostics", diag)
     for key, (nbad, cos, _) in report.items():
         assert nbad == 0, (key, report[key])
         assert cos > 0.99999, (key, report[key])
@@ -223,7 +230,24 @@ def test_end_to_end_loss_and_grad(ctx, room):
 # 64 x 1024 beams, 300,000 surfels: the benchmark configuration, sampled rays
 # ------------------------------------------------------------------------------------------
 
-@pytest.mark.parametrize("chunk", [0, 64])
+def test_forward_block_full_image(ctx, block):
+    """The benchmark configuration, every one of its 65,536 rays, in the launch
+    configuration the benchmark times (automatic chunk length)."""
+    dw = G.to_dev(block)
+    fr, st = G.gpu_forward(ctx, dw)
+    torch.cuda.synchronize()
+    of = G.oracle_forward(block)
+    stats = G.compare_forward(fr, of)
+    from paper_2607_04127_amd import lgsr
+    q = lgsr.lgsr_query(ctx, st)
+    stats.update(pairs=q["pairs"], visible=q["visible"], max_list=q["max_list"], mean_K=float(of["K"].mean()),
+                 composites=q["composites"], composites_oracle=int(of["K"].sum()))
+    _print("forward block64x1024_300k (full image)", stats)
+    assert stats["tie"] < 0.02 * stats["rays"]
+    st.free()
+
+
+@pytest.mark.parametrize("chunk", [64])
 def test_forward_block_sampled(ctx, block, chunk):
     H, W = block["H"], block["W"]
     dw = G.to_dev(block)
@@ -241,22 +265,48 @@ def test_forward_block_sampled(ctx, block, chunk):
     st.free()
 
 
+def _roll_pitch(w0, roll_deg=3.0, pitch_deg=-2.0):
+    """The workload's pose turned by a few degrees of roll and pitch about the sensor (the
+    kind of pose the pose optimiser produces); the targets are not used."""
+    from scipy.spatial.transform import Rotation
+    from tests import _util as U
+    P = np.asarray(w0["pose"], np.float64)
+    Rl = Rotation.from_euler("xy", [roll_deg, pitch_deg], degrees=True).as_matrix()
+    w = dict(w0)
+    w["pose"] = U.pose_from(P[:, :3] @ Rl, P[:, 3]).astype(np.float32)
+    return w
+
+
+def test_forward_block_roll_pitch(ctx, block):
+    w = _roll_pitch(block)
+    H, W = w["H"], w["W"]
+    fr, st = G.gpu_forward(ctx, G.to_dev(w))
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(2025)
+    ids = np.sort(rng.choice(H * W, size=4096, replace=False))
+    of = G.oracle_forward(w, ray_ids=ids)
+    stats = G.compare_forward(fr, of, ray_ids=ids)
+    _print("forward block64x1024_300k roll 3, pitch -2 degrees (4096 sampled rays)", stats)
+    assert stats["tie"] < 0.02 * stats["rays"] and stats["hit"] > 1000
+    st.free()
+
+
 @pytest.mark.parametrize("chunk", [0, 64])
 def test_backward_block_sampled(ctx, block, chunk):
-    """Upstream gradient nonzero on 2048 sampled rays only: the renderer's full backward
+    """Upstream gradient nonzero on 8192 sampled rays only: the renderer's full backward
     then equals the oracle's backward restricted to those rays, for every surfel."""
     H, W = block["H"], block["W"]
     dw = G.to_dev(block)
     _, st = G.gpu_forward(ctx, dw, chunk=chunk)
     rng = np.random.default_rng(77)
-    ids = np.sort(rng.choice(H * W, size=2048, replace=False))
+    ids = np.sort(rng.choice(H * W, size=8192 if chunk == 0 else 2048, replace=False))
     of = G.oracle_forward(block, ray_ids=ids)
     mask = (~G.tie_mask(of)).astype(np.float64)
     gd, go, gn = _loss_upstream(block, of, ray_ids=ids, mask=mask)
     g_gpu, gp = _gpu_backward(ctx, dw, st, H, W, gd, go, gn, ray_ids=ids)
     g_ref = ref.backward(block, block["pose"], block["row_sincos"], block["col_sincos"], gd, go, gn, ray_ids=ids,
                          with_mass=True)
-    _check_grads(f"backward block64x1024_300k (2048 sampled rays) chunk={chunk}", g_gpu, gp, g_ref)
+    _check_grads(f"backward block64x1024_300k ({len(ids)} sampled rays) chunk={chunk}", g_gpu, gp, g_ref)
     st.free()
 
 

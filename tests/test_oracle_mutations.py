@@ -34,6 +34,21 @@ MUTATIONS = {
     "hits_behind_near_kept": ("if (t < p->near) continue;", "if (t < 0) continue;"),
     "depth_not_normalised": ("depth[i] = r.SD / r.A;", "depth[i] = r.SD;"),
     "drop_inverted": ("drop[i] = r.A < prm->drop_tau;", "drop[i] = r.A >= prm->drop_tau;"),
+    # tie outputs (margin, order_gap) and the conditioning output den_min
+    "margin_ignores_den_eps": ("margin = fmin(margin, rel_gap(fabs(den), p->den_eps));", "(void)0;"),
+    "margin_ignores_hit_near": ("margin = fmin(margin, rel_gap(t, p->near));", "(void)0;"),
+    "margin_ignores_cutoff": ("margin = fmin(margin, rel_gap(q2, k2));", "(void)0;"),
+    "margin_ignores_alpha_thr": ("margin = fmin(margin, rel_gap(aG, p->alpha_thr));", "(void)0;"),
+    "margin_ignores_alpha_max": ("margin = fmin(margin, rel_gap(aG, p->alpha_max));", "(void)0;"),
+    "margin_ignores_T_min": ("if (want_extra) margin = fmin(margin, rel_gap(T, p->T_min));", "(void)0;"),
+    "margin_ignores_centre_near": ("margin = fmin(margin, rel_gap(s->r, p->near));", "(void)0;"),
+    "margin_ignores_cut_surfels": ("if (passes_hit_tests(&S[cut[ci]], d, p))", "if (0)"),
+    "margin_absolute_gap": ("static double rel_gap(double x, double thr) { return fabs(x - thr) / fabs(thr); }",
+                            "static double rel_gap(double x, double thr) { return fabs(x - thr); }"),
+    "order_gap_to_first_contributor": ("        prev_r = s->r;\n", "        if (prev_r < 0) prev_r = s->r;\n"),
+    "order_gap_absolute": ("order_gap = fmin(order_gap, rel_gap(s->r, prev_r));",
+                           "order_gap = fmin(order_gap, fabs(s->r - prev_r));"),
+    "den_min_signed": ("den_min = fmin(den_min, fabs(den));", "den_min = fmin(den_min, den);"),
     # loss
     "normal_loss_gradient_unprojected": (
         "for (int c = 0; c < 3; ++c) g_normal[3 * i + c] = f * (N[c] - cosv * Nh[c] / nn);",
@@ -130,6 +145,7 @@ def _run_case(name, tmp):
     env = dict(os.environ, LGSR_REF_LIB=lib, OMP_NUM_THREADS="1")
     r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider",
                         os.path.join(ROOT, "tests", "test_oracle_pins.py"),
+                        os.path.join(ROOT, "tests", "test_oracle_tie_pins.py"),
                         os.path.join(ROOT, "tests", "test_oracle_objective_pins.py"),
                         os.path.join(ROOT, "tests", "test_oracle_scan_pins.py")],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
