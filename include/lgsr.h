@@ -184,6 +184,19 @@ lgsr_status lgsr_loss(lgsr_ctx *ctx, int64_t n_rays, const lgsr_frame *pred,
                       const float *target_depth, const float *target_normal,
                       const lgsr_loss_weights *weights, float *loss_out, lgsr_frame_grad *grad_out);
 
+/* lgsr_loss without any device allocation, for callers that cannot allocate: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.  Same arguments,
+ * result and errors as lgsr_loss, on the context's stream.  The loss's partial sums go to a
+ * static device array of 4096 floats (16 KiB, one per device, held until the process ends)
+ * instead of the context's workspace; the loss needs at most 4 per workgroup and at most
+ * 1024 workgroups for any n_rays, and a larger need is refused with ECAPACITY.  Every call on
+ * one device shares that array: calls that overlap on one device (several streams or host
+ * threads) race and must be serialised by the caller.  Nothing in the array has to start at
+ * zero.  ESTATE if the array's address could not be taken when the context was created. */
+lgsr_status lgsr_loss_noalloc(lgsr_ctx *ctx, int64_t n_rays, const lgsr_frame *pred,
+                              const float *target_depth, const float *target_normal,
+                              const lgsr_loss_weights *weights, float *loss_out, lgsr_frame_grad *grad_out);
+
 /* Frame terms of the full mapping objective (Sec. 3.4: Eq. 10, Eq. 11, weighted as in
  * Eq. 13) and their gradient:
  *   L = w_depth / |Omega_D| sum_{Omega_D} |D^ - D|

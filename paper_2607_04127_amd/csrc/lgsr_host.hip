@@ -19,6 +19,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -606,6 +607,42 @@ void lgsr_default_loss_weights(lgsr_loss_weights *w)
     w->lambda_ng = 0.05f;
 }
 
+// ---- static scratch of lgsr_loss_noalloc ----
+// The loss's per-workgroup partial sums (4 floats for each of at most 1024 workgroups) live
+// in a file-scope device array, so that lgsr_loss_noalloc allocates nothing.  Every device
+// the library runs on holds its own copy until the process ends.  In host code `scratch`
+// names a host-side stand-in, not device memory: its device address is taken once per
+// device (scratch_setup, from lgsr_create with the device current) and only that address is
+// passed to kernels.
+constexpr int kNoAllocScratchFloats = 4096;
+static __device__ __align__(256) float scratch[kNoAllocScratchFloats];
+constexpr int kMaxDevices = 64;
+static float *g_scratch_dev[kMaxDevices] = {};
+static std::mutex g_scratch_mu;
+
+namespace {
+
+hipError_t scratch_setup(int device)
+{
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_dev[device]) return hipSuccess;
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_dev[device] = static_cast<float *>(p);
+    return hipSuccess;
+}
+
+float *scratch_of(int device)
+{
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    return g_scratch_dev[device];
+}
+
+}  // namespace
+
 lgsr_status lgsr_create(lgsr_ctx **out, int device, void *hip_stream)
 {
     if (!out) return LGSR_EINVAL;
@@ -617,6 +654,10 @@ lgsr_status lgsr_create(lgsr_ctx **out, int device, void *hip_stream)
     }
     if (device < 0 || device >= ndev) return LGSR_EDEVICE;
     if (hipSetDevice(device) != hipSuccess) return LGSR_EDEVICE;
+    if (scratch_setup(device) != hipSuccess) {
+        (void)hipGetLastError();
+        return LGSR_EDEVICE;
+    }
     lgsr_ctx *ctx = new (std::nothrow) lgsr_ctx;
     if (!ctx) return LGSR_ENOMEM;
     ctx->device = device;
@@ -730,6 +771,36 @@ lgsr_status lgsr_loss(lgsr_ctx *ctx, int64_t n_rays, const lgsr_frame *pred, con
     }
     HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
     return loss_impl(ctx, ctx->lanes[0], n_rays, pred, target_depth, target_normal, w, loss_out, grad_out);
+}
+
+lgsr_status lgsr_loss_noalloc(lgsr_ctx *ctx, int64_t n_rays, const lgsr_frame *pred, const float *target_depth,
+                              const float *target_normal, const lgsr_loss_weights *w, float *loss_out,
+                              lgsr_frame_grad *grad_out)
+{
+    if (!ctx) return LGSR_EINVAL;
+    if (n_rays < 0) return fail(ctx, LGSR_EINVAL, "n_rays must be >= 0");
+    lgsr_status st = check_weights(ctx, w);
+    if (st != LGSR_OK) return st;
+    if (!loss_out) return fail(ctx, LGSR_EINVAL, "loss_out is NULL");
+    if (n_rays > 0) {
+        if (!pred || !pred->depth || !pred->normal) return fail(ctx, LGSR_EINVAL, "prediction is NULL");
+        if (!target_depth || !target_normal) return fail(ctx, LGSR_EINVAL, "targets are NULL");
+        if (!grad_out || !grad_out->d_depth || !grad_out->d_opacity || !grad_out->d_normal)
+            return fail(ctx, LGSR_EINVAL, "gradient outputs are NULL");
+    }
+    const int64_t need = (int64_t)loss_blocks(n_rays) * 4;
+    if (need > kNoAllocScratchFloats)
+        return fail(ctx, LGSR_ECAPACITY, "the loss needs %lld partial sums, the static scratch holds %d",
+                    (long long)need, kNoAllocScratchFloats);
+    float *part = scratch_of(ctx->device);
+    if (!part) return fail(ctx, LGSR_ESTATE, "no static scratch address for device %d", ctx->device);
+    HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
+    HIP_TRY(launch_loss(n_rays, pred ? pred->depth : nullptr, pred ? pred->normal : nullptr, target_depth,
+                        target_normal, w->w_depth, w->lambda_n, w->lambda_ng, part, loss_out,
+                        grad_out ? grad_out->d_depth : nullptr, grad_out ? grad_out->d_opacity : nullptr,
+                        grad_out ? grad_out->d_normal : nullptr, ctx->stream),
+            "loss");
+    return LGSR_OK;
 }
 
 void lgsr_default_objective_weights(lgsr_objective_weights *w)

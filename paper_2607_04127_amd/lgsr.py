@@ -23,7 +23,7 @@ EXPORTS = ("lgsr_default_opts", "lgsr_default_loss_weights", "lgsr_create", "lgs
            "lgsr_last_error", "lgsr_forward", "lgsr_loss", "lgsr_backward", "lgsr_state_free", "lgsr_query",
            "lgsr_profile", "lgsr_profile_read", "lgsr_sync", "lgsr_state_bytes", "lgsr_adam_step",
            "lgsr_render_batch", "lgsr_default_objective_weights", "lgsr_objective", "lgsr_scale_reg",
-           "lgsr_scan_to_range", "lgsr_target_cov", "lgsr_tile_list")
+           "lgsr_scan_to_range", "lgsr_target_cov", "lgsr_tile_list", "lgsr_loss_noalloc")
 STAGES = ("project", "scan", "readback", "emit", "tile_sort", "raster_fwd", "loss", "bwd_prep", "raster_bwd",
           "chain")
 
@@ -109,6 +109,7 @@ def lib():
         L.lgsr_last_error.restype = ctypes.c_char_p
         L.lgsr_forward.argtypes = [vp, P(Surfels), vp, ctypes.c_int32, P(Beams), P(RasterOpts), P(Frame), P(vp)]
         L.lgsr_loss.argtypes = [vp, ctypes.c_int64, P(Frame), vp, vp, P(LossWeights), vp, P(FrameGrad)]
+        L.lgsr_loss_noalloc.argtypes = [vp, ctypes.c_int64, P(Frame), vp, vp, P(LossWeights), vp, P(FrameGrad)]
         L.lgsr_backward.argtypes = [vp, vp, P(FrameGrad), P(SurfelGrads), vp]
         L.lgsr_state_free.argtypes = [vp]
         L.lgsr_state_free.restype = None
@@ -131,7 +132,7 @@ def lib():
         for name in ("lgsr_create", "lgsr_set_stream", "lgsr_forward", "lgsr_loss", "lgsr_backward", "lgsr_query",
                      "lgsr_profile", "lgsr_profile_read", "lgsr_sync", "lgsr_state_bytes", "lgsr_adam_step",
                      "lgsr_render_batch", "lgsr_objective", "lgsr_scale_reg", "lgsr_scan_to_range",
-                     "lgsr_target_cov", "lgsr_tile_list"):
+                     "lgsr_target_cov", "lgsr_tile_list", "lgsr_loss_noalloc"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -300,6 +301,26 @@ def lgsr_loss(ctx: Context, frame: dict, target_depth: torch.Tensor, target_norm
     ctx._stream()
     ctx._check(lib().lgsr_loss(ctx.handle, n, ctypes.byref(fr), _ptr(target_depth), _ptr(target_normal),
                                ctypes.byref(w), _ptr(loss_out), ctypes.byref(fg)))
+    return loss_out, grad_out
+
+
+def lgsr_loss_noalloc(ctx: Context, frame: dict, target_depth: torch.Tensor, target_normal: torch.Tensor,
+                      loss_out: torch.Tensor, grad_out: dict, weights: LossWeights | None = None):
+    """lgsr_loss into caller-provided outputs, with no device allocation by the library (its
+    partial sums use a static device array shared by every call on the device)."""
+    d = ctx.device
+    H, W = frame["depth"].shape
+    _dev(frame["depth"], "depth", (H, W), d)
+    _dev(frame["normal"], "normal", (H, W, 3), d)
+    _dev(target_depth, "target_depth", (H, W), d)
+    _dev(target_normal, "target_normal", (H, W, 3), d)
+    _dev(loss_out, "loss_out", (5,), d)
+    fr = Frame(_ptr(frame["depth"]), _ptr(frame.get("opacity")), _ptr(frame["normal"]), None)
+    fg = FrameGrad(_ptr(grad_out["depth"]), _ptr(grad_out["opacity"]), _ptr(grad_out["normal"]))
+    w = weights if weights is not None else default_loss_weights()
+    ctx._stream()
+    ctx._check(lib().lgsr_loss_noalloc(ctx.handle, H * W, ctypes.byref(fr), _ptr(target_depth), _ptr(target_normal),
+                                       ctypes.byref(w), _ptr(loss_out), ctypes.byref(fg)))
     return loss_out, grad_out
 
 
