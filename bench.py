@@ -22,11 +22,12 @@ if ROOT not in sys.path:
 METRIC = "rendered rays/s fwd+bwd @64×1024, 300k surfels; p50/p99 batched render latency"
 
 # Algorithmic float32 operations of the raster (FMA = 2): per ray-surfel test (ray direction
-# offsets, plane denominator, two homogeneous tangent coordinates, reciprocal, range,
-# squared radius, Gaussian, opacity clamp and the four threshold tests), per composited hit
-# forward (weight, the four sums, transmittance, stop test) and backward (transmittance
-# recovery, dL/dalpha_hat, the clamp, and the gradients w.r.t. the 13 record quantities).
-FLOPS_TEST = 37
+# offsets, plane denominator with the exact ray direction, two homogeneous tangent
+# coordinates, reciprocal, range, squared radius, Gaussian, opacity clamp and the four
+# threshold tests), per composited hit forward (weight, the four sums, transmittance, stop
+# test) and backward (transmittance recovery, dL/dalpha_hat, the clamp, and the gradients
+# w.r.t. the 13 record quantities).
+FLOPS_TEST = 41
 FLOPS_COMPOSITE_BWD = 53
 FLOPS_COMPOSITE_FWD = 13
 # MI355X float32 vector peak without packed (dual) float32 math: 256 CUs x 64 lanes x
@@ -42,6 +43,12 @@ PEAK_HBM_GBS = 8000.0
 # sources they were taken with (digest below); reported as null once those change.
 TRAFFIC_RASTER_BWD = dict(bytes=57538829,
                           sources_sha256="6d58e84aaacbf321e84e7e3db46e8447d3b40160f82dd79dd92be0722e4ac37d")
+
+
+# rocprofv3 SQ counters of one raster_bwd launch on the benchmark workload (per dispatch) and
+# the kernel's mean duration in the same profiled run; same validity rule as the traffic.
+SQ_RASTER_BWD = dict(SQ_INSTS_VALU=23640643, SQ_INSTS_LDS=1002479, SQ_LDS_BANK_CONFLICT=312440, ms=0.0719,
+                     sources_sha256="6d58e84aaacbf321e84e7e3db46e8447d3b40160f82dd79dd92be0722e4ac37d")
 
 
 def _sources_digest() -> str:
@@ -77,8 +84,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="block64x1024_300k")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--service-requests", type=int, default=2000,
-                    help="requests of the batched-service latency phase (0 = skip)")
+    ap.add_argument("--service-requests", type=int, default=10000,
+                    help="requests per rate of the batched-service phase (0 = skip)")
+    ap.add_argument("--no-growth", action="store_true", help="skip the sliding-window and deep-list workloads")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU oracle sample time")
     ap.add_argument("--chunk", type=int, default=0, help="list entries per raster chunk (0 = automatic)")
     ap.add_argument("--calib-copy", type=int, default=0,
@@ -182,11 +190,16 @@ def main():
     p50 = float(np.percentile(step_ms, 50))
     p99 = float(np.percentile(step_ms, 99))
 
+    cold = cache_cold_phase(ctx, step, args.steps)
+    hbm = hbm_probe(ctx)
+
     aux = aux_kernels(ctx, w, S, rows, cols, pose, frame, td, tn, args.steps)
 
     svc = None
     if args.service_requests > 0:
-        svc = service_phase(ctx, w, S, rows, cols, args.service_requests)
+        svc = service_phase(ctx, args.service_requests)
+
+    growth = None if args.no_growth else growth_phase(ctx)
 
     cpu = None
     if not args.no_cpu:
@@ -211,9 +224,11 @@ def main():
                    "composites": q["composites"], "rays_hit": q["rays_hit"],
                    "loss": "depth L1 + G-ICP normal cosine", "step_latency_ms_p50": round(p50, 4),
                    "step_latency_ms_p99": round(p99, 4),
-                   "batched_latency_ms_p50": svc["batched"]["p50_ms"] if svc else None,
-                   "batched_latency_ms_p99": svc["batched"]["p99_ms"] if svc else None},
+                   "batched_latency_ms_p50": svc["at_0.5x"]["batched"]["p50_ms"] if svc else None,
+                   "batched_latency_ms_p99": svc["at_0.5x"]["batched"]["p99_ms"] if svc else None,
+                   "latency_config": "rendering service at 0.5x single-request capacity (see service)"},
         "service": svc,
+        "growth": growth,
         "aux_kernels": aux,
         "roofline": {"kernel": "raster_bwd", "bound": "alu", "achieved": round(achieved, 3),
                      "peak": round(PEAK_FP32_TFLOPS, 1), "unit": "TFLOP/s",
@@ -227,10 +242,116 @@ def main():
                        "achieved_tflops": round(flops_fwd / (fwd_ms * 1e-3) / 1e12, 3) if fwd_ms > 0 else 0.0},
         "hbm_model": {"bytes_per_step": bytes_step, "achieved_GBps": round(bytes_step / (ms_per_step * 1e-3) / 1e9, 1),
                       "frac_of_8TBps": round(bytes_step / (ms_per_step * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)},
+        "hbm": hbm_fractions(hbm, n, q["pairs"], rays, bytes_step, ms_per_step, cold, bwd_ms),
+        "cache_cold": cold,
+        "counters": counter_figures(bwd_ms),
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
     ctx.close()
+
+
+def hbm_probe(ctx):
+    """The HBM bandwidth a plain streaming kernel reaches on this device: a copy over 2 x 2 GiB
+    and a triad over 3 x 1.5 GiB (working sets far beyond the 256 MB last-level cache), HIP
+    events on the library's stream, best of 10 repetitions after one warm-up."""
+    import torch
+
+    from paper_2607_04127_amd import lgsr
+
+    dev = torch.device("cuda:0")
+    out = {}
+    for kind, arrays, nbytes_per in (("copy", 2, 8), ("triad", 3, 12)):
+        n = (2 if kind == "copy" else 1.5) * 2 ** 30 / 4
+        n = int(n) // 4 * 4
+        A = [torch.empty(n, device=dev) for _ in range(arrays)]
+        for t in A:
+            t.fill_(1.0)
+        call = (lambda: lgsr.lgsr_stream_probe(ctx, "copy", A[0], A[1])) if kind == "copy" else \
+            (lambda: lgsr.lgsr_stream_probe(ctx, "triad", A[0], A[1], A[2]))
+        call()
+        torch.cuda.synchronize()
+        best = None
+        for _ in range(10):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            call()
+            b.record()
+            torch.cuda.synchronize()
+            ms = a.elapsed_time(b)
+            best = ms if best is None else min(best, ms)
+        out[f"{kind}_GBps"] = round(nbytes_per * n / (best * 1e-3) / 1e9, 1)
+        out[f"{kind}_working_set_GiB"] = round(arrays * 4 * n / 2 ** 30, 2)
+        del A
+        torch.cuda.empty_cache()
+    out["achievable_GBps"] = max(out["copy_GBps"], out["triad_GBps"])
+    print(f"# hbm probe: copy {out['copy_GBps']:.0f} GB/s, triad {out['triad_GBps']:.0f} GB/s", file=sys.stderr,
+          flush=True)
+    return out
+
+
+def cache_cold_phase(ctx, step, steps):
+    """Step time with the caches flushed before every step: a 1 GiB streaming copy (512 MiB
+    read, 512 MiB written) runs first, then HIP events bracket the step alone."""
+    import numpy as np
+    import torch
+
+    from paper_2607_04127_amd import lgsr
+
+    dev = torch.device("cuda:0")
+    n = 2 ** 27  # 512 MiB of float32
+    src, dst = torch.ones(n, device=dev), torch.empty(n, device=dev)
+    times = []
+    for _ in range(steps):
+        lgsr.lgsr_stream_probe(ctx, "copy", dst, src)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        step()
+        b.record()
+        torch.cuda.synchronize()
+        times.append(a.elapsed_time(b))
+    del src, dst
+    torch.cuda.empty_cache()
+    p50 = float(np.percentile(times, 50))
+    print(f"# cache-cold step: p50 {p50:.3f} ms", file=sys.stderr, flush=True)
+    return {"ms_per_step_p50": round(p50, 4), "ms_per_step_p90": round(float(np.percentile(times, 90)), 4),
+            "flush_bytes": 2 * 4 * n, "steps": steps}
+
+
+def hbm_fractions(hbm, n, P, rays, bytes_step, ms_per_step, cold, bwd_ms):
+    """The step's and raster_bwd's HBM use against the measured achievable bandwidth."""
+    bw = hbm["achievable_GBps"]
+    # algorithmic bytes of tile-binned splatting at 56 B records (288 N + 156 P + 113 rays)
+    b_method = 288 * n + 156 * P + 113 * rays
+    compulsory = 80 * n + 37 * rays  # parameters in, targets in, image out, gradients out
+
+    def frac(nbytes, ms):
+        return round(nbytes / (ms * 1e-3) / 1e9 / bw, 4) if ms > 0 else None
+
+    out = dict(hbm, b_method_bytes=b_method, compulsory_bytes=compulsory, implementation_model_bytes=bytes_step,
+               step_frac_of_achievable=frac(b_method, ms_per_step),
+               step_frac_of_achievable_cache_cold=frac(b_method, cold["ms_per_step_p50"]),
+               implementation_model_frac_of_achievable=frac(bytes_step, ms_per_step),
+               compulsory_frac_of_achievable=frac(compulsory, ms_per_step))
+    traffic = TRAFFIC_RASTER_BWD["bytes"] if TRAFFIC_RASTER_BWD["sources_sha256"] == _sources_digest() else None
+    out["raster_bwd_traffic_frac_of_achievable"] = frac(traffic, bwd_ms) if traffic else None
+    return out
+
+
+def counter_figures(bwd_ms):
+    """VALU issue and LDS bank-conflict figures of raster_bwd from the rocprofv3 SQ counters
+    (profiles/sq_counters_block64x1024_300k.md), against the chip's issue capacity: 1024 SIMDs
+    at 2.4 GHz, a wave64 VALU instruction holding its SIMD for 4 cycles.  Null once the kernel
+    sources differ from those the counters were taken with."""
+    if SQ_RASTER_BWD["sources_sha256"] != _sources_digest():
+        return None
+    c = SQ_RASTER_BWD
+    simd_cycles = 1024 * 2.4e9 * c["ms"] * 1e-3
+    cu_cycles = 256 * 2.4e9 * c["ms"] * 1e-3
+    return {"kernel": "raster_bwd", "counters_ms_per_launch": c["ms"],
+            "valu_busy_frac": round(4 * c["SQ_INSTS_VALU"] / simd_cycles, 4),
+            "lds_instructions": c["SQ_INSTS_LDS"], "lds_bank_conflict_cycles": c["SQ_LDS_BANK_CONFLICT"],
+            "lds_bank_conflict_frac_of_cu_cycles": round(c["SQ_LDS_BANK_CONFLICT"] / cu_cycles, 4)}
 
 
 def _time_us(fn, reps):
@@ -300,37 +421,139 @@ def aux_kernels(ctx, w, S, rows, cols, pose, frame, td, tn, reps):
     return out
 
 
-def service_phase(ctx, w, S, rows, cols, n_requests, n_poses=4, seed=45):
-    """Batched render latency on the benchmark map: n_requests Poisson arrivals (70% render,
-    30% render + gradient) over n_poses poses (random yaw, +-5 m), at 0.7 times the measured
-    one-request-per-call capacity, served batched (up to 16 per call) and one by one."""
+def service_phase(ctx, n_requests):
+    """The batched-service configuration: four resident street-block maps of 100k, 400k, 1M and
+    2M surfels, request templates at 32 x 1024 and 64 x 1024 beams (+-22.5 deg) and 128 x 2048
+    beams (+-45 deg) with two random poses each and exact raycast targets, Poisson arrivals
+    (70% render, 30% render + gradient) at 0.25, 0.5 and 0.9 times the measured
+    one-request-per-call capacity and at a fixed 3000 requests/s; n_requests per rate, served
+    batched (up to 16 per call, each request's latency taken when its results are ready) and
+    one by one, with p50 / p99 latency and rays/s for each."""
+    import torch
+
+    from paper_2607_04127_amd import service as SV
+
+    t = time.perf_counter()
+    maps = SV.make_maps([100_000, 400_000, 1_000_000, 2_000_000], seed=41)
+    pool = SV.make_pool(maps, poses_per=2, seed=45)
+    SV.measure_pairs(ctx, pool)
+    torch.cuda.synchronize()
+    print(f"# service: {len(maps)} maps, {len(pool)} templates ({time.perf_counter() - t:.1f} s)", file=sys.stderr,
+          flush=True)
+    cap = SV.capacity(ctx, pool, n=200)
+    out = dict(maps=[m["n"] for m in maps], templates=len(pool), requests_per_rate=n_requests, grad_fraction=0.3,
+               max_batch=16, single_capacity_rps=round(cap, 1))
+    for label, rate in (("at_0.25x", 0.25 * cap), ("at_0.5x", 0.5 * cap), ("at_0.9x", 0.9 * cap),
+                        ("fixed_3000rps", 3000.0)):
+        stream = SV.poisson_stream(pool, n_requests, rate, grad_fraction=0.3, seed=45)
+        entry = dict(rate_rps=round(rate, 1))
+        for mode in ("batched", "single"):
+            SV.Service(ctx, pool, mode, max_batch=16).run(stream[:50])  # warm the per-request states
+            rep = SV.Service(ctx, pool, mode, max_batch=16).run(stream)
+            entry[mode] = dict(p50_ms=round(rep["p50_ms"], 4), p99_ms=round(rep["p99_ms"], 4),
+                               rays_per_s=round(rep["rays_per_s"], 1), mean_batch=round(rep["mean_batch"], 2))
+            print(f"# service {label} {mode}: p50 {rep['p50_ms']:.3f} ms p99 {rep['p99_ms']:.3f} ms "
+                  f"({rep['rays_per_s'] / 1e6:.1f} Mrays/s, mean batch {rep['mean_batch']:.1f})",
+                  file=sys.stderr, flush=True)
+        out[label] = entry
+    del maps, pool
+    torch.cuda.empty_cache()
+    return out
+
+
+def growth_phase(ctx):
+    """The growth workloads: the sliding window (64 x 2048 beams, 1M surfels, 8 keyframes, 10
+    Adam iterations through the autograd layer with the lists recomputed in the backward) and
+    the deep-list stress (128 x 2048 beams, 4M surfels with 30% in 0.5 m blobs: forward +
+    backward of a fixed random functional of the frame with the pose gradient, lists kept,
+    then recomputed)."""
     import numpy as np
     import torch
 
     import scenegen
-    from paper_2607_04127_amd import service as SV
+    from paper_2607_04127_amd import autograd as AG
+    from paper_2607_04127_amd import lgsr
+    from paper_2607_04127_amd import window as WN
 
-    rng = np.random.Generator(np.random.PCG64(seed))
-    rows_np, cols_np = w["row_sincos"], w["col_sincos"]
-    pool = []
-    for k in range(n_poses):
-        pose = scenegen.make_pose(rng.uniform(0, 2 * np.pi), *rng.uniform(-5, 5, 2))
-        td, tn = scenegen.targets_for_pose(w["scene"], pose, rows_np, cols_np, 0.1, 300 + k)
-        pool.append(SV.template(S, w["means"].shape[0], rows, cols, pose, torch.from_numpy(td).to(rows.device),
-                                torch.from_numpy(tn).to(rows.device)))
-    cap = SV.capacity(ctx, pool, n=200)
-    rate = 0.7 * cap
-    stream = SV.poisson_stream(pool, n_requests, rate, grad_fraction=0.3, seed=seed)
-    out = dict(requests=n_requests, rate_rps=round(rate, 1), single_capacity_rps=round(cap, 1),
-               grad_fraction=0.3, max_batch=16)
-    for mode in ("batched", "single"):
-        SV.Service(ctx, pool, mode, max_batch=16).run(stream[:50])  # warm the per-request states
-        rep = SV.Service(ctx, pool, mode, max_batch=16).run(stream)
-        out[mode] = dict(p50_ms=round(rep["p50_ms"], 4), p99_ms=round(rep["p99_ms"], 4),
-                         rays_per_s=round(rep["rays_per_s"], 1), mean_batch=round(rep["mean_batch"], 2))
-        print(f"# service {mode}: p50 {rep['p50_ms']:.3f} ms p99 {rep['p99_ms']:.3f} ms "
-              f"({rep['rays_per_s'] / 1e6:.1f} Mrays/s, mean batch {rep['mean_batch']:.1f})",
-              file=sys.stderr, flush=True)
+    out = {}
+    t = time.perf_counter()
+    w = scenegen.make_workload("window64x2048_1m")
+    print(f"# window workload ({time.perf_counter() - t:.1f} s)", file=sys.stderr, flush=True)
+    poses, means = WN.perturb(w)
+    win = WN.Window(ctx, w, poses, means=means, keep_lists="recompute")
+    err0 = WN.pose_errors(win.pose_opt.T0, w["poses"])
+    curve, times = [], []
+    for _ in range(10):
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        curve.append(win.step())
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - a)
+    err1 = WN.pose_errors(win.pose_opt.T0, w["poses"])
+    rays = w["H"] * w["W"] * len(w["poses"])
+    out["window64x2048_1m"] = dict(
+        surfels=int(w["means"].shape[0]), keyframes=len(w["poses"]), iterations=10, keep_lists="recompute",
+        s_per_iter=round(float(np.median(times)), 5), rays_per_s=round(rays / float(np.median(times)), 1),
+        loss=[round(x, 6) for x in curve], recomputed_backwards=win.renderer.recomputed,
+        pose_err_before_m_deg=[round(float(np.mean([e[0] for e in err0])), 5),
+                               round(float(np.degrees(np.mean([e[1] for e in err0]))), 4)],
+        pose_err_after_m_deg=[round(float(np.mean([e[0] for e in err1])), 5),
+                              round(float(np.degrees(np.mean([e[1] for e in err1]))), 4)])
+    print(f"# window: {np.median(times) * 1e3:.2f} ms/iteration, loss {curve[0]:.4f} -> {curve[-1]:.4f}",
+          file=sys.stderr, flush=True)
+    del win, w
+    torch.cuda.empty_cache()
+
+    t = time.perf_counter()
+    w = scenegen.make_workload("deep128x2048_4m", with_targets=False)
+    print(f"# deep workload ({time.perf_counter() - t:.1f} s)", file=sys.stderr, flush=True)
+    dev = torch.device("cuda:0")
+    H, W = w["H"], w["W"]
+    S = {k: torch.from_numpy(np.ascontiguousarray(w[k])).to(dev) for k in AG.SURF_KEYS}
+    rows = torch.from_numpy(w["row_sincos"]).to(dev)
+    cols = torch.from_numpy(w["col_sincos"]).to(dev)
+    pose = torch.from_numpy(w["pose"])
+    rng = np.random.default_rng(2024)
+    up = dict(depth=torch.from_numpy(rng.uniform(-1, 1, (H, W)).astype(np.float32)).to(dev),
+              opacity=torch.from_numpy(rng.uniform(-1, 1, (H, W)).astype(np.float32)).to(dev),
+              normal=torch.from_numpy(rng.uniform(-1, 1, (H, W, 3)).astype(np.float32)).to(dev))
+
+    def kept():
+        _, st = lgsr.lgsr_forward(ctx, S, pose, rows, cols)
+        lgsr.lgsr_backward(ctx, st, up)
+        st.free()
+
+    def recomputed():
+        lgsr.lgsr_forward(ctx, S, pose, rows, cols, want_state=False)
+        _, st = lgsr.lgsr_forward(ctx, S, pose, rows, cols)
+        lgsr.lgsr_backward(ctx, st, up)
+        st.free()
+
+    res = {}
+    for name, fn in (("kept", kept), ("recomputed", recomputed)):
+        for _ in range(2):
+            fn()
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        for _ in range(10):
+            fn()
+        torch.cuda.synchronize()
+        res[name] = round((time.perf_counter() - a) * 1e3 / 10, 4)
+    _, st = lgsr.lgsr_forward(ctx, S, pose, rows, cols)
+    q = lgsr.lgsr_query(ctx, st)
+    ch = lgsr.lgsr_count_hits(ctx, st)
+    st.free()
+    out["deep128x2048_4m"] = dict(
+        surfels=int(w["means"].shape[0]), rays=H * W, ms_fwd_bwd_lists_kept=res["kept"],
+        ms_fwd_bwd_lists_recomputed=res["recomputed"], rays_per_s=round(H * W / (res["kept"] * 1e-3), 1),
+        pairs=q["pairs"], max_tile_list=q["max_list"], composites_per_hit_ray=round(q["composites"] / max(q["rays_hit"], 1), 2),
+        intersections_per_hit_ray_before_termination=round(ch["hits_all"] / max(ch["rays_with_hits"], 1), 2),
+        intersections_per_ray_before_termination=round(ch["hits_all"] / (H * W), 2))
+    print(f"# deep: {res['kept']:.3f} ms fwd+bwd (lists kept), {res['recomputed']:.3f} ms (recomputed), "
+          f"{out['deep128x2048_4m']['intersections_per_hit_ray_before_termination']} intersections per hit ray",
+          file=sys.stderr, flush=True)
+    del S, w
+    torch.cuda.empty_cache()
     return out
 
 

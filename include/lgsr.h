@@ -287,6 +287,14 @@ void lgsr_state_free(lgsr_state *state);
  *          below T_min). */
 lgsr_status lgsr_query(lgsr_ctx *ctx, const lgsr_state *state, int64_t out[8]);
 
+/* Depth of the per-ray lists of the forward that produced `state` (waits for it), HOST
+ * int64[2]: out[0] the (ray, surfel) hits that pass every per-hit test (cut-off, alpha_thr,
+ * near, den_eps) summed over rays, counting the hits behind the point where the ray's
+ * transmittance fell below T_min as well; out[1] the rays with at least one such hit.  The
+ * beam tables and the surfel arrays of that forward must still hold their values.
+ * Errors: EINVAL, ESTATE, EDEVICE. */
+lgsr_status lgsr_count_hits(lgsr_ctx *ctx, const lgsr_state *state, int64_t out[2]);
+
 /* The sorted list of one 16 x 16-ray tile (tile row tile_row covers ray rows 16 tile_row ..
  * 16 tile_row + 15, likewise columns) of the forward that produced `state`: the ids of the
  * surfels whose conservative ray rectangle meets the tile, in compositing order (ascending
@@ -297,6 +305,14 @@ lgsr_status lgsr_query(lgsr_ctx *ctx, const lgsr_state *state, int64_t out[8]);
  * ESTATE, EDEVICE. */
 lgsr_status lgsr_tile_list(lgsr_ctx *ctx, const lgsr_state *state, int32_t tile_row, int32_t tile_col,
                            uint32_t *ids, int64_t cap, int64_t *count);
+
+/* Streaming probe, outside the rendering path: the HBM bandwidth a plain streaming kernel
+ * reaches on this device, the denominator of the path's HBM fraction, and a cache flush
+ * between timed steps.  kind 0 (copy): a[i] = b[i] (8 bytes per float); kind 1 (triad):
+ * a[i] = b[i] + 3 c[i] (12 bytes per float).  n floats, a multiple of 4; a, b, c DEVICE,
+ * 16-byte aligned, not overlapping.  Asynchronous on the context's stream.  Errors: EINVAL,
+ * EDEVICE. */
+lgsr_status lgsr_stream_probe(lgsr_ctx *ctx, int32_t kind, const float *b, const float *c, float *a, int64_t n);
 
 /* Stage timers.  lgsr_profile selects stages by bit mask (bit k = stage k, 0 = off, -1 =
  * all); each selected stage is then bracketed by HIP events on the context's stream (a
@@ -353,9 +369,26 @@ typedef struct {
 lgsr_status lgsr_render_batch(lgsr_ctx *ctx, int32_t n, const lgsr_request *requests /* HOST */,
                               const lgsr_raster_opts *opts, const lgsr_loss_weights *weights);
 
+/* Device bytes one request holds beyond its inputs and outputs (host computation, no
+ * device needed): the buffers of its state (records, rectangles, keys, pair lists and sort
+ * workspace, chunk list and per-chunk summaries, per-ray state) for a map of n surfels, an
+ * H x W beam model and P (surfel, tile) pairs at the automatic chunk length, and, when
+ * with_grad, the loss and backward scratch, each sized as the library allocates it.  A
+ * service admits requests against an HBM budget with it.  Errors: EINVAL. */
+lgsr_status lgsr_request_bytes(int64_t n, int32_t H, int32_t W, int64_t P, int32_t with_grad, int64_t *bytes);
+
+/* Completion of the requests of the most recent lgsr_render_batch on the context, without
+ * waiting: done[i] (HOST int32, n entries) = 1 once request i's kernels have finished and its
+ * outputs hold their values, else 0.  A service can hand each result on as soon as it is
+ * ready instead of at the end of the whole batch.  n must not exceed the number of requests
+ * that batch issued.  Errors: EINVAL, EDEVICE (a kernel of the batch faulted). */
+lgsr_status lgsr_batch_poll(lgsr_ctx *ctx, int32_t n, int32_t *done);
+
 /* Device bytes held by `state` (HOST int64 out); no GPU work, no wait.  A caller that keeps
  * states from forward to backward can budget HBM with it, and recompute (run the forward
- * again, which is deterministic) instead of keeping a state when the budget is spent. */
+ * again, which is deterministic) instead of keeping a state when the budget is spent.
+ * state == NULL: the bytes the context itself retains (its workspace, the scratch of the
+ * loss and backward, the states of earlier batches kept for reuse). */
 lgsr_status lgsr_state_bytes(lgsr_ctx *ctx, const lgsr_state *state, int64_t *bytes);
 
 /* One Adam step (Kingma and Ba; the map optimisation of Sec. 3.4 does not name its

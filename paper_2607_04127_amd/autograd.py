@@ -21,6 +21,7 @@ library's fused Adam kernel) and for poses (Adam in the tangent, retracted every
 from __future__ import annotations
 
 import math
+import weakref
 
 import numpy as np
 import torch
@@ -128,6 +129,22 @@ def _pose32(T: np.ndarray) -> torch.Tensor:
     return torch.from_numpy(np.ascontiguousarray(T, dtype=np.float32))
 
 
+def _release(renderer: Renderer, state: lgsr.State, nbytes: int):
+    renderer.held -= nbytes
+    state.free()
+
+
+class _Held:
+    """A state kept for a pending backward.  Its bytes return to the renderer's budget and the
+    state is freed once the backward has used it, or when the autograd graph that holds it is
+    dropped without a backward."""
+
+    def __init__(self, renderer: Renderer, state: lgsr.State, nbytes: int):
+        renderer.held += nbytes
+        self.state = state
+        self.release = weakref.finalize(self, _release, renderer, state, nbytes)
+
+
 class _Render(torch.autograd.Function):
     @staticmethod
     def forward(fctx, renderer: Renderer, T0: np.ndarray, xi: torch.Tensor, means, quats, log_scales, logits):
@@ -135,16 +152,18 @@ class _Render(torch.autograd.Function):
         pose = _pose32(compose(T0, xi64))
         S = dict(means=means.detach(), quats=quats.detach(), log_scales=log_scales.detach(),
                  opacity_logits=logits.detach())
+        # a backward can only follow when some input asks for a gradient
+        wants_grad = any(fctx.needs_input_grad[2:])
         frame, st = lgsr.lgsr_forward(renderer.ctx, S, pose, renderer.rows, renderer.cols, opts=renderer.opts,
-                                      want_state=True)
-        nbytes = lgsr.lgsr_state_bytes(renderer.ctx, st)
-        if renderer._keep(nbytes):
-            renderer.held += nbytes
-            fctx.nbytes = nbytes
-        else:
-            st.free()
-            st, fctx.nbytes = None, 0
-        fctx.renderer, fctx.state, fctx.pose, fctx.xi64 = renderer, st, pose, xi64
+                                      want_state=wants_grad)
+        fctx.held = None
+        if wants_grad:
+            nbytes = lgsr.lgsr_state_bytes(renderer.ctx, st)
+            if renderer._keep(nbytes):
+                fctx.held = _Held(renderer, st, nbytes)
+            else:
+                st.free()
+        fctx.renderer, fctx.pose, fctx.xi64 = renderer, pose, xi64
         fctx.xi_meta = (xi.device, xi.dtype)
         fctx.save_for_backward(means, quats, log_scales, logits)
         fctx.mark_non_differentiable(frame["drop"])
@@ -156,22 +175,24 @@ class _Render(torch.autograd.Function):
         means, quats, log_scales, logits = fctx.saved_tensors
         H, W = r.shape
         dev = r.ctx.device
-        st = fctx.state
-        if st is None:
+        held, fctx.held = fctx.held, None
+        if held is None:
             S = dict(means=means.detach(), quats=quats.detach(), log_scales=log_scales.detach(),
                      opacity_logits=logits.detach())
             _, st = lgsr.lgsr_forward(r.ctx, S, fctx.pose, r.rows, r.cols, opts=r.opts, want_state=True)
             r.recomputed += 1
         else:
-            r.held -= fctx.nbytes
-        fctx.state = None
+            st = held.state
 
         def full(g, shape):
             return torch.zeros(shape, device=dev) if g is None else g.contiguous().to(torch.float32)
 
         grad = dict(depth=full(g_depth, (H, W)), opacity=full(g_opacity, (H, W)), normal=full(g_normal, (H, W, 3)))
         out, gp = lgsr.lgsr_backward(r.ctx, st, grad)
-        st.free()
+        if held is None:
+            st.free()
+        else:
+            held.release()
         Jr = torch.from_numpy(se3_right_jacobian(fctx.xi64).T.astype(np.float32)).to(dev)
         g_xi = (Jr @ gp).to(device=fctx.xi_meta[0], dtype=fctx.xi_meta[1])
         return (None, None, g_xi, out["means"], out["quats"], out["log_scales"], out["opacity_logits"])

@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblgsr.so")
-SOURCES = ["lgsr_host.hip", "project.hip", "sort.hip", "raster.hip", "loss.hip", "objective.hip", "scan.hip", "chain.hip", "adam.hip"]
+SOURCES = ["lgsr_host.hip", "project.hip", "sort.hip", "raster.hip", "loss.hip", "objective.hip", "scan.hip", "chain.hip", "adam.hip", "probe.hip"]
 ARCH = os.environ.get("LGSR_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

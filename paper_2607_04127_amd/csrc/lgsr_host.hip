@@ -121,6 +121,8 @@ struct lgsr_ctx {
     std::string err;
     Lane lanes[kLanes];
     hipEvent_t batch_start = nullptr;
+    std::vector<hipEvent_t> req_done;  // per request of the latest batch: recorded after its last kernel
+    int32_t batch_n = 0;               // requests of the latest batch
     DevBuf counters;             // lgsr_query's counters
     DevBuf scan_slots;           // lgsr_scan_to_range's per-pixel keys
     uint32_t *pinned = nullptr;  // host-pinned read-back of lgsr_query
@@ -695,6 +697,7 @@ void lgsr_destroy(lgsr_ctx *ctx)
     release(ctx->counters);
     release(ctx->scan_slots);
     if (ctx->batch_start) (void)hipEventDestroy(ctx->batch_start);
+    for (hipEvent_t e : ctx->req_done) (void)hipEventDestroy(e);
     for (auto &pe : ctx->ev_pending) {
         (void)hipEventDestroy(pe.second.first);
         (void)hipEventDestroy(pe.second.second);
@@ -969,6 +972,12 @@ lgsr_status lgsr_render_batch(lgsr_ctx *ctx, int32_t n, const lgsr_request *reqs
     for (Lane &L : ctx->lanes)
         if (!L.done) HIP_TRY(hipEventCreateWithFlags(&L.done, hipEventDisableTiming), "lane event");
     if (!ctx->batch_start) HIP_TRY(hipEventCreateWithFlags(&ctx->batch_start, hipEventDisableTiming), "event");
+    while ((int32_t)ctx->req_done.size() < n) {
+        hipEvent_t e = nullptr;
+        HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming), "request event");
+        ctx->req_done.push_back(e);
+    }
+    ctx->batch_n = 0;
     // The lanes start after the work already on the context's stream, and the context's
     // stream continues after the lanes (also when returning early with an error).
     HIP_TRY(hipEventRecord(ctx->batch_start, ctx->stream), "batch start");
@@ -1011,12 +1020,58 @@ lgsr_status lgsr_render_batch(lgsr_ctx *ctx, int32_t n, const lgsr_request *reqs
         Lane &L = ctx->lanes[i % kLanes];
         lgsr_state *S = states[(size_t)i];
         if ((st = forward_end(ctx, S, &q.out, L.stream)) != LGSR_OK) return st;
-        if (!q.target_depth) continue;
-        const int64_t rays = (int64_t)q.beams.H * q.beams.W;
-        if ((st = loss_impl(ctx, L, rays, &q.out, q.target_depth, q.target_normal, w, q.loss_out, &q.frame_grad)) !=
-            LGSR_OK)
-            return st;
-        if ((st = backward_impl(ctx, L, S, &q.frame_grad, &q.grads, q.grad_pose)) != LGSR_OK) return st;
+        if (q.target_depth) {
+            const int64_t rays = (int64_t)q.beams.H * q.beams.W;
+            if ((st = loss_impl(ctx, L, rays, &q.out, q.target_depth, q.target_normal, w, q.loss_out,
+                                &q.frame_grad)) != LGSR_OK)
+                return st;
+            if ((st = backward_impl(ctx, L, S, &q.frame_grad, &q.grads, q.grad_pose)) != LGSR_OK) return st;
+        }
+        HIP_TRY(hipEventRecord(ctx->req_done[(size_t)i], L.stream), "request done");
+        ctx->batch_n = i + 1;
+    }
+    return LGSR_OK;
+}
+
+lgsr_status lgsr_request_bytes(int64_t n, int32_t H, int32_t W, int64_t P, int32_t with_grad, int64_t *bytes)
+{
+    if (!bytes || n < 0 || P < 0 || H < 1 || W < 1 || H > 32768 || W > 32768) return LGSR_EINVAL;
+    // every buffer as ensure() sizes it: the request plus a quarter, whole 4 KiB pages
+    auto buf = [](size_t b) -> size_t {
+        if (b == 0) b = 256;
+        return ((b + b / 4) + 4095) & ~(size_t)4095;
+    };
+    const size_t nn = (size_t)(n > 0 ? n : 1);
+    const int TH = (H + kTile - 1) / kTile, TW = (W + kTile - 1) / kTile;
+    const int64_t T = (int64_t)TH * TW, rays = (int64_t)H * W;
+    const int seg = chunk_size(P, 0);
+    const int64_t items = chunk_items_max(P, (int)T, seg);
+    const size_t pp = (size_t)(P > 0 ? P : 1);
+    size_t b = buf(nn * kRec * sizeof(float)) + buf(nn * sizeof(uint2)) + buf(nn * 4) + buf((size_t)T * sizeof(uint2)) +
+               4 * buf((size_t)rays * sizeof(float4)) + buf(16 * sizeof(float)) + 2 * buf((size_t)T * kShards * 4) +
+               buf((size_t)T * 4) + buf(16) + buf(pp * 4 + pp) + buf(pp * 8) +
+               buf((size_t)(items > 0 ? items : 1) * sizeof(uint4)) + buf((size_t)(T + 1) * sizeof(uint32_t)) +
+               buf(chunk_slot_floats(items > 0 ? items : 1) * sizeof(float)) +
+               buf((size_t)(items > 0 ? 4 * items : 1) * sizeof(uint32_t));
+    if (with_grad)
+        b += buf((size_t)loss_blocks(rays) * 4 * sizeof(float)) + buf(nn * kGrad * sizeof(float)) +
+             buf((size_t)chain_blocks(n) * 6 * sizeof(float)) + buf((size_t)rays * sizeof(float4)) +
+             buf((size_t)rays * sizeof(float));
+    *bytes = (int64_t)b;
+    return LGSR_OK;
+}
+
+lgsr_status lgsr_batch_poll(lgsr_ctx *ctx, int32_t n, int32_t *done)
+{
+    if (!ctx) return LGSR_EINVAL;
+    if (n < 0 || (n > 0 && !done)) return fail(ctx, LGSR_EINVAL, "n < 0 or done is NULL");
+    if (n > ctx->batch_n) return fail(ctx, LGSR_EINVAL, "the latest batch issued %d requests", ctx->batch_n);
+    HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
+    for (int32_t i = 0; i < n; ++i) {
+        const hipError_t e = hipEventQuery(ctx->req_done[(size_t)i]);
+        if (e == hipSuccess) done[i] = 1;
+        else if (e == hipErrorNotReady) done[i] = 0;
+        else return hip_fail(ctx, e, "request event");
     }
     return LGSR_OK;
 }
@@ -1063,6 +1118,28 @@ lgsr_status lgsr_query(lgsr_ctx *ctx, const lgsr_state *S, int64_t out[8])
     return LGSR_OK;
 }
 
+lgsr_status lgsr_count_hits(lgsr_ctx *ctx, const lgsr_state *S, int64_t out[2])
+{
+    if (!ctx) return LGSR_EINVAL;
+    if (!S || !out) return fail(ctx, LGSR_EINVAL, "state or out is NULL");
+    if (S->ctx != ctx || !S->live) return fail(ctx, LGSR_ESTATE, "state does not belong to this context");
+    HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
+    hipStream_t s = ctx->stream;
+    unsigned long long *wc = reinterpret_cast<unsigned long long *>(as<uint32_t>(ctx->counters) + 8);
+    if (S->P > 0) {
+        HIP_TRY(launch_count_hits(S->R, S->g, S->prm, wc, s), "count hits");
+        HIP_TRY(hipMemcpyAsync(ctx->pinned + 4, wc, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s),
+                "readback");
+        HIP_TRY(hipStreamSynchronize(s), "count hits sync");
+        const unsigned long long *hw = reinterpret_cast<const unsigned long long *>(ctx->pinned + 4);
+        out[0] = (int64_t)hw[0];
+        out[1] = (int64_t)hw[1];
+    } else {
+        out[0] = out[1] = 0;
+    }
+    return LGSR_OK;
+}
+
 lgsr_status lgsr_tile_list(lgsr_ctx *ctx, const lgsr_state *S, int32_t tile_row, int32_t tile_col, uint32_t *ids,
                            int64_t cap, int64_t *count)
 {
@@ -1090,6 +1167,20 @@ lgsr_status lgsr_tile_list(lgsr_ctx *ctx, const lgsr_state *S, int32_t tile_row,
                 "tile list");
         HIP_TRY(hipStreamSynchronize(s), "tile list sync");
     }
+    return LGSR_OK;
+}
+
+lgsr_status lgsr_stream_probe(lgsr_ctx *ctx, int32_t kind, const float *b, const float *c, float *a, int64_t n)
+{
+    if (!ctx) return LGSR_EINVAL;
+    if (n < 0 || (n % 4) != 0) return fail(ctx, LGSR_EINVAL, "n must be a non-negative multiple of 4");
+    if (kind != 0 && kind != 1) return fail(ctx, LGSR_EINVAL, "kind must be 0 (copy) or 1 (triad)");
+    if (n > 0 && (!b || !a || (kind == 1 && !c))) return fail(ctx, LGSR_EINVAL, "NULL array");
+    if (((reinterpret_cast<uintptr_t>(a) | reinterpret_cast<uintptr_t>(b) | reinterpret_cast<uintptr_t>(c)) & 15u) != 0)
+        return fail(ctx, LGSR_EINVAL, "arrays must be 16-byte aligned");
+    HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
+    if (kind == 0) HIP_TRY(launch_stream_copy(b, a, n, ctx->stream), "stream copy");
+    else HIP_TRY(launch_stream_triad(b, c, a, 3.f, n, ctx->stream), "stream triad");
     return LGSR_OK;
 }
 
@@ -1138,7 +1229,11 @@ lgsr_status lgsr_sync(lgsr_ctx *ctx)
 lgsr_status lgsr_state_bytes(lgsr_ctx *ctx, const lgsr_state *S, int64_t *bytes)
 {
     if (!ctx) return LGSR_EINVAL;
-    if (!S || !bytes) return fail(ctx, LGSR_EINVAL, "state or bytes is NULL");
+    if (!bytes) return fail(ctx, LGSR_EINVAL, "bytes is NULL");
+    if (!S) {
+        *bytes = (int64_t)ctx_bytes(ctx);
+        return LGSR_OK;
+    }
     if (S->ctx != ctx || !S->live) return fail(ctx, LGSR_ESTATE, "state does not belong to this context");
     *bytes = (int64_t)state_bytes(S);
     return LGSR_OK;

@@ -382,7 +382,9 @@ __device__ __forceinline__ Hit hit_test(const Rec &s, const Ray &ray, const Rast
     h.e[0] = (ray.dh[0] - s.m0) + ray.dl[0];
     h.e[1] = (ray.dh[1] - s.m1) + ray.dl[1];
     h.e[2] = ray.dh[2] - s.m2;
-    h.den = fmaf(s.nt0, ray.dh[0], fmaf(s.nt1, ray.dh[1], s.nt2 * ray.dh[2]));
+    // den with the exact ray direction (the residuals of its two rounded products): at
+    // grazing incidence t, u and v inherit the relative error of den multiplied by 1 / |den|
+    h.den = fmaf(s.nt0, ray.dl[0], fmaf(s.nt1, ray.dl[1], fmaf(s.nt0, ray.dh[0], fmaf(s.nt1, ray.dh[1], s.nt2 * ray.dh[2]))));
     h.nu = fmaf(s.U0, h.e[0], fmaf(s.U1, h.e[1], fmaf(s.U2, h.e[2], s.cu)));
     h.nv = fmaf(s.V0, h.e[0], fmaf(s.V1, h.e[1], fmaf(s.V2, h.e[2], s.cv)));
     h.inv = __builtin_amdgcn_rcpf(h.den);

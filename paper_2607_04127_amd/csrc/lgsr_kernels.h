@@ -94,6 +94,10 @@ hipError_t launch_raster_bwd_prep(const RasterBufs &R, const Grid &g, const floa
 // out (u64, device) += ray tests needed up to each wave's last contributor (query only)
 hipError_t launch_work_needed(const RasterBufs &R, const Grid &g, const RasterParams &p, unsigned long long *out,
                               hipStream_t s);
+// out[0] (u64) = list entries passing every per-hit test summed over rays, ignoring early
+// termination; out[1] = rays with at least one (query only)
+hipError_t launch_count_hits(const RasterBufs &R, const Grid &g, const RasterParams &p, unsigned long long *out,
+                             hipStream_t s);
 hipError_t launch_raster_bwd(const RasterBufs &R, const Grid &g, const RasterParams &p, const float4 *gb0,
                              const float *gb1, float *recgrad, hipStream_t s);
 
@@ -148,5 +152,9 @@ struct AdamBatch {
     int count;
 };
 hipError_t launch_adam(AdamBatch B, float beta1, float beta2, float eps, int step, hipStream_t s);
+
+// ---- probe.hip ----
+hipError_t launch_stream_copy(const float *src, float *dst, int64_t n, hipStream_t s);
+hipError_t launch_stream_triad(const float *b, const float *c, float *a, float scale, int64_t n, hipStream_t s);
 
 }  // namespace lgsr

@@ -699,6 +699,42 @@ __global__ __launch_bounds__(256) void work_needed_kernel(const uint32_t *__rest
     if (L.lane == 0 && c) atomicAdd(out, c);
 }
 
+// out[0] += per ray, the list entries that pass every per-hit test (cut-off, alpha_thr, near,
+// den_eps) whether or not the ray has stopped compositing before them; out[1] += rays with at
+// least one.  One workgroup per tile, one ray per thread, records read straight from memory
+// (query only, not on the rendering path).
+__global__ __launch_bounds__(256) void count_hits_kernel(const uint32_t *__restrict__ ids,
+                                                         const float *__restrict__ recs,
+                                                         const uint2 *__restrict__ rects,
+                                                         const uint2 *__restrict__ ranges,
+                                                         const float *__restrict__ rows,
+                                                         const float *__restrict__ cols, Grid g, RasterParams p,
+                                                         unsigned long long *__restrict__ out)
+{
+    const int tile = blockIdx.x;
+    const Lane L = lane_of(tile, g);
+    const uint2 rg = ranges[tile];
+    unsigned long long c = 0;
+    if (L.wave_in) {
+        const Ray ray = make_ray(rows, cols, L.valid ? L.k : 0, L.valid ? L.j : 0);
+        for (uint32_t pos = rg.x; pos < rg.y; ++pos) {
+            const uint32_t id = ids[pos];
+            if (!sub_overlap(rects[id], L.sr0, L.sc0, g.W)) continue;
+            const Hit h = hit_test(load_rec(recs, id), ray, p);
+            c += (L.valid && h.pass) ? 1ull : 0ull;
+        }
+    }
+    unsigned long long hit = c > 0 ? 1ull : 0ull;
+    for (int o = 32; o >= 1; o >>= 1) {
+        c += __shfl_xor(c, o, 64);
+        hit += __shfl_xor(hit, o, 64);
+    }
+    if (L.lane == 0) {
+        if (c) atomicAdd(out, c);
+        if (hit) atomicAdd(out + 1, hit);
+    }
+}
+
 // ---------------------------------------------------------------------------------------
 // host launchers
 // ---------------------------------------------------------------------------------------
@@ -751,6 +787,15 @@ hipError_t launch_work_needed(const RasterBufs &R, const Grid &g, const RasterPa
                               hipStream_t s)
 {
     work_needed_kernel<<<g.T, 256, 0, s>>>(R.chunk_base, R.ids, R.rects, R.ranges, g, p, R.slots, R.st0, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_count_hits(const RasterBufs &R, const Grid &g, const RasterParams &p, unsigned long long *out,
+                             hipStream_t s)
+{
+    hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t *>(out), 0u, 4, s);
+    if (e != hipSuccess || g.T <= 0) return e;
+    count_hits_kernel<<<g.T, 256, 0, s>>>(R.ids, R.recs, R.rects, R.ranges, R.rows, R.cols, g, p, out);
     return hipGetLastError();
 }
 

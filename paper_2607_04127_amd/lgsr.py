@@ -23,7 +23,8 @@ EXPORTS = ("lgsr_default_opts", "lgsr_default_loss_weights", "lgsr_create", "lgs
            "lgsr_last_error", "lgsr_forward", "lgsr_loss", "lgsr_backward", "lgsr_state_free", "lgsr_query",
            "lgsr_profile", "lgsr_profile_read", "lgsr_sync", "lgsr_state_bytes", "lgsr_adam_step",
            "lgsr_render_batch", "lgsr_default_objective_weights", "lgsr_objective", "lgsr_scale_reg",
-           "lgsr_scan_to_range", "lgsr_target_cov", "lgsr_tile_list", "lgsr_loss_noalloc")
+           "lgsr_scan_to_range", "lgsr_target_cov", "lgsr_tile_list", "lgsr_loss_noalloc",
+           "lgsr_stream_probe", "lgsr_count_hits", "lgsr_batch_poll", "lgsr_request_bytes")
 STAGES = ("project", "scan", "readback", "emit", "tile_sort", "raster_fwd", "loss", "bwd_prep", "raster_bwd",
           "chain")
 
@@ -110,6 +111,11 @@ def lib():
         L.lgsr_forward.argtypes = [vp, P(Surfels), vp, ctypes.c_int32, P(Beams), P(RasterOpts), P(Frame), P(vp)]
         L.lgsr_loss.argtypes = [vp, ctypes.c_int64, P(Frame), vp, vp, P(LossWeights), vp, P(FrameGrad)]
         L.lgsr_loss_noalloc.argtypes = [vp, ctypes.c_int64, P(Frame), vp, vp, P(LossWeights), vp, P(FrameGrad)]
+        L.lgsr_stream_probe.argtypes = [vp, ctypes.c_int32, vp, vp, vp, ctypes.c_int64]
+        L.lgsr_count_hits.argtypes = [vp, vp, P(ctypes.c_int64)]
+        L.lgsr_batch_poll.argtypes = [vp, ctypes.c_int32, P(ctypes.c_int32)]
+        L.lgsr_request_bytes.argtypes = [ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64,
+                                         ctypes.c_int32, P(ctypes.c_int64)]
         L.lgsr_backward.argtypes = [vp, vp, P(FrameGrad), P(SurfelGrads), vp]
         L.lgsr_state_free.argtypes = [vp]
         L.lgsr_state_free.restype = None
@@ -132,7 +138,8 @@ def lib():
         for name in ("lgsr_create", "lgsr_set_stream", "lgsr_forward", "lgsr_loss", "lgsr_backward", "lgsr_query",
                      "lgsr_profile", "lgsr_profile_read", "lgsr_sync", "lgsr_state_bytes", "lgsr_adam_step",
                      "lgsr_render_batch", "lgsr_objective", "lgsr_scale_reg", "lgsr_scan_to_range",
-                     "lgsr_target_cov", "lgsr_tile_list", "lgsr_loss_noalloc"):
+                     "lgsr_target_cov", "lgsr_tile_list", "lgsr_loss_noalloc", "lgsr_stream_probe",
+                     "lgsr_count_hits", "lgsr_batch_poll", "lgsr_request_bytes"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -455,6 +462,15 @@ def lgsr_query(ctx: Context, state: State) -> dict:
                 rays_hit=o[6], ray_tests_needed=o[7])
 
 
+def lgsr_count_hits(ctx: Context, state: State) -> dict:
+    """Hits passing every per-hit test summed over rays, ignoring early termination, and the
+    rays with one; waits."""
+    o = (ctypes.c_int64 * 2)()
+    ctx._stream()
+    ctx._check(lib().lgsr_count_hits(ctx.handle, state.handle, o))
+    return dict(hits_all=o[0], rays_with_hits=o[1])
+
+
 def lgsr_tile_list(ctx: Context, state: State, tile_row: int, tile_col: int):
     """The sorted surfel ids (numpy uint32) of one 16 x 16-ray tile's list; waits."""
     import numpy as np
@@ -465,6 +481,32 @@ def lgsr_tile_list(ctx: Context, state: State, tile_row: int, tile_col: int):
     ctx._check(lib().lgsr_tile_list(ctx.handle, state.handle, tile_row, tile_col,
                                     out.ctypes.data_as(ctypes.c_void_p), n.value, ctypes.byref(n)))
     return out[:n.value]
+
+
+def lgsr_stream_probe(ctx: Context, kind: str, a: torch.Tensor, b: torch.Tensor, c: torch.Tensor | None = None):
+    """Streaming probe (not part of the path): kind "copy" a = b, "triad" a = b + 3 c."""
+    for t in (a, b) + ((c,) if c is not None else ()):
+        if t.dtype != torch.float32 or not t.is_contiguous() or t.device != ctx.device:
+            raise ValueError("probe arrays must be contiguous float32 on the context's device")
+    ctx._stream()
+    ctx._check(lib().lgsr_stream_probe(ctx.handle, 0 if kind == "copy" else 1, _ptr(b), _ptr(c), _ptr(a),
+                                       a.numel()))
+
+
+def lgsr_request_bytes(n: int, H: int, W: int, pairs: int, with_grad: bool) -> int:
+    """Device bytes a request holds beyond its inputs and outputs (no device needed)."""
+    b = ctypes.c_int64(0)
+    rc = lib().lgsr_request_bytes(n, H, W, pairs, 1 if with_grad else 0, ctypes.byref(b))
+    if rc != LGSR_OK:
+        raise ValueError(f"lgsr_request_bytes: {_STATUS.get(rc, rc)}")
+    return b.value
+
+
+def lgsr_batch_poll(ctx: Context, n: int):
+    """Per request of the latest batch, whether its kernels have finished (list of bool)."""
+    d = (ctypes.c_int32 * max(1, n))()
+    ctx._check(lib().lgsr_batch_poll(ctx.handle, n, d))
+    return [bool(d[i]) for i in range(n)]
 
 
 def lgsr_render_batch(ctx: Context, requests, opts: RasterOpts | None = None, weights: LossWeights | None = None):
@@ -527,10 +569,11 @@ def lgsr_render_batch(ctx: Context, requests, opts: RasterOpts | None = None, we
     return results
 
 
-def lgsr_state_bytes(ctx: Context, state: State) -> int:
-    """Device bytes held by a state (host-side bookkeeping, no GPU work)."""
+def lgsr_state_bytes(ctx: Context, state: State | None) -> int:
+    """Device bytes held by a state, or by the context itself when state is None (host-side
+    bookkeeping, no GPU work)."""
     b = ctypes.c_int64()
-    ctx._check(lib().lgsr_state_bytes(ctx.handle, state.handle, ctypes.byref(b)))
+    ctx._check(lib().lgsr_state_bytes(ctx.handle, state.handle if state is not None else None, ctypes.byref(b)))
     return int(b.value)
 
 

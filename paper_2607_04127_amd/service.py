@@ -7,8 +7,8 @@ stream, each for a random map, pose and beam model.  The service admits the requ
 have arrived, in arrival order, into a batch until the batch is full or its estimated HBM
 working set would exceed the budget, runs the batch with ``lgsr_render_batch`` (one host
 wait per request instead of a wait inside every forward, kernels of different requests
-overlapping on four streams), and records each request's latency from arrival to the end
-of its batch.  ``mode="single"`` serves one request per call through lgsr_forward /
+overlapping on four streams), and records each request's latency from arrival to the moment
+the host sees that request's results ready (``lgsr_batch_poll``).  ``mode="single"`` serves one request per call through lgsr_forward /
 lgsr_loss / lgsr_backward, the reference point.
 
 The command-line run builds four maps (100k, 400k, 1M and 2M surfels of the seeded
@@ -75,10 +75,19 @@ def make_pool(maps, resolutions=RESOLUTIONS, poses_per=2, seed=45, device="cuda:
 
 def template(surfels, n, rows, cols, pose, target_depth, target_normal, map_index=0, res_index=0):
     """One request template: a resident map (device tensors, n surfels), device beam tables,
-    a host 3 x 4 pose and device targets for render + gradient requests."""
+    a host 3 x 4 pose and device targets for render + gradient requests.  `pairs` (the
+    (surfel, tile) pairs of its forward) is filled in by measure_pairs."""
     H, W = rows.shape[0], cols.shape[0]
     return dict(map=map_index, res=res_index, rows=rows, cols=cols, pose=np.asarray(pose, np.float32),
-                td=target_depth, tn=target_normal, rays=H * W, surfels=surfels, n=int(n))
+                td=target_depth, tn=target_normal, rays=H * W, H=H, W=W, surfels=surfels, n=int(n), pairs=None)
+
+
+def measure_pairs(ctx, pool):
+    """Fill each template's `pairs` from one forward (the admission model's P)."""
+    for tp in pool:
+        _, st = lgsr.lgsr_forward(ctx, tp["surfels"], torch.from_numpy(tp["pose"]), tp["rows"], tp["cols"])
+        tp["pairs"] = int(lgsr.lgsr_query(ctx, st)["pairs"])
+        st.free()
 
 
 Request = collections.namedtuple("Request", "id t template grad")
@@ -94,14 +103,24 @@ def poisson_stream(pool, n, rate, grad_fraction=0.3, seed=45):
     return [Request(i, float(t[i]), int(tpl[i]), bool(grad[i])) for i in range(n)]
 
 
+# (surfel, tile) pairs per surfel assumed for a template whose forward has not been
+# measured: above what the street-block maps reach at every beam model of the service
+PAIRS_PER_SURFEL_BOUND = 3
+
+
 def working_bytes(tpl, grad):
-    """Estimated device bytes a request needs beyond its resident map: per surfel the
-    record, rectangle, key and (with a gradient) the record-gradient slot and parameter
-    gradients; per ray the frame, ray state and chunk summaries."""
+    """Device bytes a request holds beyond its resident map: the library's own account of its
+    state and (with a gradient) its loss and backward scratch (lgsr_request_bytes), at the
+    template's measured pair count or PAIRS_PER_SURFEL_BOUND per surfel, plus the frame
+    outputs (21 B per ray) and, with a gradient, the per-ray loss gradient (20 B) and the
+    parameter gradients (40 B per surfel)."""
     n, rays = tpl["n"], tpl["rays"]
-    b = n * (64 + 8 + 4) + rays * (21 + 64 + 200)
+    pairs = tpl.get("pairs")
+    if pairs is None:
+        pairs = PAIRS_PER_SURFEL_BOUND * n
+    b = lgsr.lgsr_request_bytes(n, tpl["H"], tpl["W"], pairs, grad) + 21 * rays
     if grad:
-        b += n * (64 + 40) + rays * (40 + 20)
+        b += 20 * rays + 40 * n
     return b
 
 
@@ -112,11 +131,14 @@ def working_bytes(tpl, grad):
 
 class Service:
     def __init__(self, ctx: lgsr.Context, pool, mode="batched", max_batch=16, hbm_budget=32 << 30):
+        """hbm_budget: device bytes the service may use for requests in flight; what the
+        context already retains (workspace and earlier batch states) is taken off it."""
         if mode not in ("batched", "single"):
             raise ValueError("mode must be 'batched' or 'single'")
         self.ctx, self.pool, self.mode = ctx, pool, mode
         self.max_batch = max(1, int(max_batch)) if mode == "batched" else 1
-        self.hbm_budget = int(hbm_budget)
+        retained = lgsr.lgsr_state_bytes(ctx, None) if ctx is not None else 0
+        self.hbm_budget = max(0, int(hbm_budget) - retained)
 
     def _admit(self, pending):
         """Requests from the head of the queue while the batch fits (at least one)."""
@@ -130,8 +152,10 @@ class Service:
             total += b
         return batch
 
-    def _execute(self, batch):
-        if self.mode == "batched":
+    def _execute(self, batch, t0):
+        """Runs a batch; returns each request's completion time (seconds since t0), taken
+        when the host sees that request's results ready."""
+        if self.mode == "batched" and len(batch) > 1:
             reqs = []
             for r in batch:
                 tp = self.pool[r.template]
@@ -140,16 +164,32 @@ class Service:
                     q["target_depth"], q["target_normal"] = tp["td"], tp["tn"]
                 reqs.append(q)
             lgsr.lgsr_render_batch(self.ctx, reqs)
-        else:
-            for r in batch:
-                tp = self.pool[r.template]
-                fr, st = lgsr.lgsr_forward(self.ctx, tp["surfels"], torch.from_numpy(tp["pose"]), tp["rows"],
-                                           tp["cols"], want_state=r.grad)
-                if r.grad:
-                    _, g = lgsr.lgsr_loss(self.ctx, fr, tp["td"], tp["tn"])
-                    lgsr.lgsr_backward(self.ctx, st, g)
-                    st.free()
-        torch.cuda.synchronize()
+            n = len(batch)
+            done_at = [None] * n
+            left = n
+            while left:
+                ready = lgsr.lgsr_batch_poll(self.ctx, n)
+                now = time.perf_counter() - t0
+                for k in range(n):
+                    if ready[k] and done_at[k] is None:
+                        done_at[k] = now
+                        left -= 1
+            torch.cuda.synchronize()
+            return done_at
+        # one request per call (and a batch of one in batched mode: the batch path's stream
+        # joins and per-request events only pay off when requests overlap)
+        done_at = []
+        for r in batch:
+            tp = self.pool[r.template]
+            fr, st = lgsr.lgsr_forward(self.ctx, tp["surfels"], torch.from_numpy(tp["pose"]), tp["rows"],
+                                       tp["cols"], want_state=r.grad)
+            if r.grad:
+                _, g = lgsr.lgsr_loss(self.ctx, fr, tp["td"], tp["tn"])
+                lgsr.lgsr_backward(self.ctx, st, g)
+                st.free()
+            torch.cuda.synchronize()
+            done_at.append(time.perf_counter() - t0)
+        return done_at
 
     def run(self, stream):
         """Serve a stream in real time; returns latency percentiles and throughput."""
@@ -170,9 +210,7 @@ class Service:
                     time.sleep(wait - 1e-4)
                 continue
             batch = self._admit(pending)
-            self._execute(batch)
-            done = time.perf_counter() - t0
-            for r in batch:
+            for r, done in zip(batch, self._execute(batch, t0)):
                 lat.append(done - r.t)
                 ids.append(r.id)
                 rays += self.pool[r.template]["rays"]
@@ -207,6 +245,7 @@ def main():
     pool = make_pool(maps, poses_per=args.poses)
     print(f"# {len(maps)} maps, {len(pool)} templates ({time.perf_counter() - t:.1f} s)", file=sys.stderr, flush=True)
     ctx = lgsr.Context(0)
+    measure_pairs(ctx, pool)
     cap = capacity(ctx, pool)
     print(f"# single-request capacity {cap:.1f} requests/s", file=sys.stderr, flush=True)
     runs = []

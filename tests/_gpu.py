@@ -61,9 +61,9 @@ def compare_forward(fr, of, ray_ids=None, rel=1e-5, natol=1e-4, conditioned=Fals
     """Returns a dict of statistics; raises AssertionError on a parity failure.
 
     conditioned: the bars of a ray grow with 1 / den_min, the smallest |n'.d| among its
-    contributors.  The renderer evaluates den = n'.d in float32 from a rounded normal and
-    rounded ray components: |error| <= 3 * 2^-24 (half an ulp of each of the normal's and
-    the direction's components, one ulp of the sum).  t, u and v all carry den as a divisor,
+    contributors.  The renderer evaluates den = n'.d in float32 from the rounded normal (the
+    ray direction enters exactly, as a float pair): |error| <= 3 * 2^-24 (half an ulp of each
+    of the normal's three components, and the rounding of the sum).  t, u and v all carry den as a divisor,
     so q^2 = u^2 + v^2 moves by 2 q^2 |error| / den and G = exp(-q^2 / 2) by a relative
     q^2 |error| / den <= 9 * 1.8e-7 / den = 1.6e-6 / den.  The bars are therefore
     max(rel, 1.6e-6 / den_min) and max(natol, 1.6e-5 / den_min): unchanged for

@@ -96,6 +96,31 @@ def test_autograd_equals_direct_calls_and_keep_modes(ctx, room_off):
     _close(P["means"].grad.cpu().numpy(), direct["means"], "auto, recomputed")
 
 
+def test_kept_states_return_their_budget(ctx, room_off):
+    """A render that no backward can follow keeps no state, and a kept state whose graph is
+    dropped without a backward gives its bytes back to the renderer's budget."""
+    import gc
+
+    from paper_2607_04127_amd import autograd as AG
+    w = room_off
+    r = _renderer(ctx, w, keep_lists="store")
+    P = _leaf(w)
+    with torch.no_grad():
+        AG.render(r, P, w["pose"])
+    assert r.held == 0
+    frozen = {k: v.detach() for k, v in P.items()}
+    AG.render(r, frozen, w["pose"])  # no input asks for a gradient
+    assert r.held == 0
+    fr = AG.render(r, P, w["pose"])
+    assert r.held > 0
+    del fr
+    gc.collect()
+    assert r.held == 0
+    fr = AG.render(r, P, w["pose"])
+    AG.loss(r, fr, torch.from_numpy(w["target_depth"]).cuda(), torch.from_numpy(w["target_normal"]).cuda())[0].backward()
+    assert r.held == 0 and r.recomputed == 0
+
+
 def test_pose_tangent_gradient_at_nonzero_xi(ctx, room_off):
     """d loss / d xi at T0 Exp(xi), xi != 0: against J_r(xi)^T applied to the oracle's
     right-perturbation gradient at T (tolerance of the gradient parity), and against central

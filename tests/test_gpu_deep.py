@@ -119,7 +119,14 @@ def test_deep_lists_gradients_match_finite_differences(ctx, deep):
     # work counters of the forward: list depth; the state is kept for the masked backwards
     fr0, st0 = G.gpu_forward(ctx, dw)
     q = lgsr.lgsr_query(ctx, st0)
+    ch = lgsr.lgsr_count_hits(ctx, st0)
     torch.cuda.synchronize()
+    # deep lists: hits per ray before early termination (counted over the whole image)
+    a19 = ch["hits_all"] / max(ch["rays_with_hits"], 1)
+    print(f"\n[deep 128x2048 4M] intersections per hit ray before termination {a19:.1f} "
+          f"(per ray {ch['hits_all'] / (H * W):.1f}), composited per hit ray "
+          f"{q['composites'] / max(q['rays_hit'], 1):.1f}", flush=True)
+    assert a19 > 64
     gD_t = torch.from_numpy(gD).float().cuda()
     gA_t = torch.from_numpy(gA).float().cuda()
     gN_t = torch.from_numpy(gN).float().cuda()

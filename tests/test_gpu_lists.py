@@ -263,3 +263,41 @@ def test_tile_lists_complete_and_ordered(ctx, name):
     assert missing == 0
     assert checked_rays > 0.9 * 256 * len(tiles) * (0.5 if name.startswith("room") else 0.9)
     st.free()
+
+
+@pytest.mark.parametrize("name", ["room32x256_1k", "grazing"])
+def test_count_hits_matches_oracle(ctx, name):
+    """lgsr_count_hits (hits passing every per-hit test, early termination ignored) against
+    the oracle's per-ray n_hits summed over the image; rays with a threshold tie may count
+    a hit differently and bound the difference."""
+    from paper_2607_04127_amd import lgsr
+    if name == "grazing":
+        from tests import _util as U
+        rng = np.random.default_rng(31)
+        row, col = scenegen.beam_tables(32, 256, -15, 15)
+        cen, frames, sc, al = [], [], [], []
+        for _ in range(600):
+            d = np.array([rng.normal(), rng.normal(), 0.3 * rng.normal()])
+            d /= np.linalg.norm(d)
+            r = rng.uniform(1.0, 25.0)
+            nrm = -d + rng.normal(scale=1.5, size=3)
+            cen.append(r * d)
+            frames.append(U.frame_facing(nrm, spin=rng.uniform(0, 6.28)))
+            sc.append(rng.uniform(0.02, 0.1, 2) * r)
+            al.append(rng.uniform(0.2, 0.95))
+        S = {k: v.astype(np.float32) for k, v in U.surfels(cen, frames, sc, al).items()}
+        w = dict(S, row_sincos=row, col_sincos=col, pose=U.identity_pose().astype(np.float32))
+    else:
+        w = scenegen.make_workload(name)
+    fr, st = G.gpu_forward(ctx, G.to_dev(w))
+    c = lgsr.lgsr_count_hits(ctx, st)
+    q = lgsr.lgsr_query(ctx, st)
+    of = G.oracle_forward(w)
+    ties = int((of["margin"] < G.TIE_MARGIN).sum())
+    want, want_rays = int(of["n_hits"].sum()), int((of["n_hits"] > 0).sum())
+    print(f"\n[count hits {name}] gpu={c['hits_all']} oracle={want} rays gpu={c['rays_with_hits']} oracle={want_rays} "
+          f"composited={q['composites']} threshold ties={ties}", flush=True)
+    assert abs(c["hits_all"] - want) <= 3 * ties
+    assert abs(c["rays_with_hits"] - want_rays) <= ties
+    assert c["hits_all"] >= q["composites"]
+    st.free()

@@ -9,8 +9,10 @@ from paper_2607_04127_amd import service as SV
 
 
 def _pool():
-    # templates by size only: admission reads n (surfels) and rays
-    return [dict(n=100_000, rays=32 * 1024), dict(n=2_000_000, rays=128 * 2048), dict(n=400_000, rays=64 * 1024)]
+    # templates by size only: admission reads n (surfels), the beam model and the pair count
+    return [dict(n=100_000, rays=32 * 1024, H=32, W=1024, pairs=None),
+            dict(n=2_000_000, rays=128 * 2048, H=128, W=2048, pairs=None),
+            dict(n=400_000, rays=64 * 1024, H=64, W=1024, pairs=300_000)]
 
 
 def test_poisson_stream_statistics():
@@ -32,6 +34,23 @@ def test_working_set_grows_with_gradients_and_size():
     a, b = _pool()[0], _pool()[1]
     assert SV.working_bytes(a, True) > SV.working_bytes(a, False) > 0
     assert SV.working_bytes(b, False) > SV.working_bytes(a, False)
+
+
+def test_working_set_covers_the_library_account():
+    """The admission model is at least the library's own account of a request's buffers
+    (lgsr_request_bytes, sized as the library allocates them, slots of the chunk summaries,
+    pair lists and sort workspace included) for the benchmark shape and the service's
+    shapes, at the measured or the assumed pair count; an unmeasured template is budgeted
+    with more pairs than the measured one of the same shape."""
+    from paper_2607_04127_amd import lgsr
+    cfg2 = dict(n=300_000, rays=64 * 1024, H=64, W=1024, pairs=229_247)
+    for tp in [cfg2] + _pool():
+        P = tp["pairs"] if tp["pairs"] is not None else SV.PAIRS_PER_SURFEL_BOUND * tp["n"]
+        for g in (False, True):
+            assert SV.working_bytes(tp, g) >= lgsr.lgsr_request_bytes(tp["n"], tp["H"], tp["W"], P, g)
+    # per-chunk summaries dominate at 64 x 1024 / 300k: 9 x 256 floats per chunk
+    assert lgsr.lgsr_request_bytes(300_000, 64, 1024, 229_247, False) > 9 * 256 * 4 * (256 + 229_247 // 48)
+    assert SV.working_bytes(dict(cfg2, pairs=None), False) > SV.working_bytes(cfg2, False)
 
 
 def _queue(pool, spec):
