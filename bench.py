@@ -427,8 +427,9 @@ def service_phase(ctx, n_requests):
     beams (+-45 deg) with two random poses each and exact raycast targets, Poisson arrivals
     (70% render, 30% render + gradient) at 0.25, 0.5 and 0.9 times the measured
     one-request-per-call capacity and at a fixed 3000 requests/s; n_requests per rate, served
-    batched (up to 16 per call, each request's latency taken when its results are ready) and
-    one by one, with p50 / p99 latency and rays/s for each."""
+    batched (up to 16 per call, each request's latency taken when its results are ready; at
+    0.9x and 3000/s also with one launch per compositing stage for the whole batch) and one
+    by one, with p50 / p99 latency and rays/s for each."""
     import torch
 
     from paper_2607_04127_amd import service as SV
@@ -447,7 +448,10 @@ def service_phase(ctx, n_requests):
                         ("fixed_3000rps", 3000.0)):
         stream = SV.poisson_stream(pool, n_requests, rate, grad_fraction=0.3, seed=45)
         entry = dict(rate_rps=round(rate, 1))
-        for mode in ("batched", "single"):
+        # the fused batch mode (one launch per compositing stage for the whole batch) only
+        # differs from the per-stream one where batches hold several requests
+        modes = ("batched", "single") if label in ("at_0.25x", "at_0.5x") else ("batched", "fused", "single")
+        for mode in modes:
             SV.Service(ctx, pool, mode, max_batch=16).run(stream[:50])  # warm the per-request states
             rep = SV.Service(ctx, pool, mode, max_batch=16).run(stream)
             entry[mode] = dict(p50_ms=round(rep["p50_ms"], 4), p99_ms=round(rep["p99_ms"], 4),

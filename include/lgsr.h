@@ -91,8 +91,13 @@ typedef struct {
     float drop_tau;     /* rendered drop = [A < drop_tau]                      (default 0.5)    */
     int32_t chunk;      /* list entries per parallel chunk; 0 = chosen from the pair count, else
                            16..65536.  Results do not depend on it beyond float32 rounding.     */
-    int32_t flags;      /* reserved, must be 0 */
+    int32_t flags;      /* 0, or LGSR_FLAG_BATCH_FUSED (lgsr_render_batch only; others ignore it) */
 } lgsr_raster_opts;
+
+/* lgsr_render_batch: composite all requests of the batch with one launch per stage (chunks,
+ * merge, fix-up) after every request's lists are built, instead of each request on its own
+ * stream as soon as its lists are ready.  Same results. */
+#define LGSR_FLAG_BATCH_FUSED 1
 
 typedef struct {
     float *depth;   /* H x W   */

@@ -180,7 +180,7 @@ lgsr_status check_opts(lgsr_ctx *ctx, const lgsr_raster_opts *o)
     if (!std::isfinite(o->drop_tau)) return fail(ctx, LGSR_EINVAL, "drop_tau must be finite");
     if (o->chunk != 0 && (o->chunk < 16 || o->chunk > 65536))
         return fail(ctx, LGSR_EINVAL, "chunk must be 0 or lie in [16, 65536]");
-    if (o->flags != 0) return fail(ctx, LGSR_EINVAL, "flags must be 0");
+    if ((o->flags & ~LGSR_FLAG_BATCH_FUSED) != 0) return fail(ctx, LGSR_EINVAL, "unknown flags");
     return LGSR_OK;
 }
 
@@ -443,9 +443,9 @@ lgsr_status forward_begin(lgsr_ctx *ctx, lgsr_state *S, const lgsr_surfels *surf
     return LGSR_OK;
 }
 
-// Forward, second half: waits for the read-back, then emission, per-tile order and
-// compositing into `out`.
-lgsr_status forward_end(lgsr_ctx *ctx, lgsr_state *S, const lgsr_frame *out, hipStream_t s)
+// Forward, second half, up to the compositing: waits for the read-back, then emission,
+// per-tile order and the chunk list; S->R then describes the raster buffers.
+lgsr_status forward_lists(lgsr_ctx *ctx, lgsr_state *S, hipStream_t s)
 {
     {
     Stage st_(ctx, LGSR_STAGE_READBACK, s);
@@ -527,11 +527,26 @@ lgsr_status forward_end(lgsr_ctx *ctx, lgsr_state *S, const lgsr_frame *out, hip
     R.fixflag = as<uint32_t>(S->fixflag);
     R.seg = seg;
     R.items_max = items_max;
-    Stage st_(ctx, LGSR_STAGE_RASTER_FWD, s);
-    HIP_TRY(launch_raster_fwd(R, g, S->prm, out->depth, out->opacity, out->normal, out->drop, s), "raster forward");
+    S->P = P;
+    return LGSR_OK;
+}
+
+// After the raster forward of S has been issued: the fix-up leaves every chunk flag zero.
+void raster_issued(lgsr_state *S)
+{
     S->fixflag_clean = true;
     S->fixflag_seen = S->fixflag.p;
-    S->P = P;
+}
+
+// Forward, second half: lists (forward_lists), then compositing into `out`.
+lgsr_status forward_end(lgsr_ctx *ctx, lgsr_state *S, const lgsr_frame *out, hipStream_t s)
+{
+    lgsr_status st = forward_lists(ctx, S, s);
+    if (st != LGSR_OK) return st;
+    Stage st_(ctx, LGSR_STAGE_RASTER_FWD, s);
+    HIP_TRY(launch_raster_fwd(S->R, S->g, S->prm, out->depth, out->opacity, out->normal, out->drop, s),
+            "raster forward");
+    raster_issued(S);
     return LGSR_OK;
 }
 
@@ -1015,19 +1030,69 @@ lgsr_status lgsr_render_batch(lgsr_ctx *ctx, int32_t n, const lgsr_request *reqs
                            ctx->lanes[i % kLanes].stream);
         if (st != LGSR_OK) return st;
     }
+    if (!(opts->flags & LGSR_FLAG_BATCH_FUSED)) {
+        // each request's lists, compositing, loss and backward on its lane as soon as its
+        // pair count arrives, overlapping with the other lanes and with the host's waits
+        for (int32_t i = 0; i < n; ++i) {
+            const lgsr_request &q = reqs[i];
+            Lane &L = ctx->lanes[i % kLanes];
+            lgsr_state *S = states[(size_t)i];
+            if ((st = forward_end(ctx, S, &q.out, L.stream)) != LGSR_OK) return st;
+            if (q.target_depth) {
+                const int64_t rays = (int64_t)q.beams.H * q.beams.W;
+                if ((st = loss_impl(ctx, L, rays, &q.out, q.target_depth, q.target_normal, w, q.loss_out,
+                                    &q.frame_grad)) != LGSR_OK)
+                    return st;
+                if ((st = backward_impl(ctx, L, S, &q.frame_grad, &q.grads, q.grad_pose)) != LGSR_OK) return st;
+            }
+            HIP_TRY(hipEventRecord(ctx->req_done[(size_t)i], L.stream), "request done");
+            ctx->batch_n = i + 1;
+        }
+        return LGSR_OK;
+    }
+    // LGSR_FLAG_BATCH_FUSED: lists of every request, on its lane, as its pair count arrives
+    for (int32_t i = 0; i < n; ++i)
+        if ((st = forward_lists(ctx, states[(size_t)i], ctx->lanes[i % kLanes].stream)) != LGSR_OK) return st;
+    // the compositing of all requests: one launch per stage (chunks, merge, fix-up) on the
+    // context's stream once every lane has its lists
+    for (int k = 1; k < kLanes; ++k) {
+        HIP_TRY(hipEventRecord(ctx->lanes[k].done, ctx->lanes[k].stream), "lists done");
+        HIP_TRY(hipStreamWaitEvent(ctx->stream, ctx->lanes[k].done, 0), "join lists");
+    }
+    const RasterParams prm = to_params(opts);
+    for (int32_t i0 = 0; i0 < n; i0 += kMaxFwdJobs) {
+        FwdJobs J{};
+        J.n = std::min<int32_t>(kMaxFwdJobs, n - i0);
+        for (int k = 0; k < J.n; ++k) {
+            const lgsr_request &q = reqs[i0 + k];
+            lgsr_state *S = states[(size_t)(i0 + k)];
+            J.j[k].R = S->R;
+            J.j[k].g = S->g;
+            J.j[k].depth = q.out.depth;
+            J.j[k].opacity = q.out.opacity;
+            J.j[k].normal = q.out.normal;
+            J.j[k].drop = q.out.drop;
+        }
+        HIP_TRY(launch_raster_fwd_multi(J, prm, ctx->stream), "raster forward (batch)");
+        for (int k = 0; k < J.n; ++k) raster_issued(states[(size_t)(i0 + k)]);
+    }
+    HIP_TRY(hipEventRecord(ctx->batch_start, ctx->stream), "frames done");
+    for (int k = 1; k < kLanes; ++k) HIP_TRY(hipStreamWaitEvent(ctx->lanes[k].stream, ctx->batch_start, 0), "fork");
+    // render-only requests are done with the frames; loss and backward of the others on lanes
     for (int32_t i = 0; i < n; ++i) {
         const lgsr_request &q = reqs[i];
         Lane &L = ctx->lanes[i % kLanes];
         lgsr_state *S = states[(size_t)i];
-        if ((st = forward_end(ctx, S, &q.out, L.stream)) != LGSR_OK) return st;
         if (q.target_depth) {
             const int64_t rays = (int64_t)q.beams.H * q.beams.W;
             if ((st = loss_impl(ctx, L, rays, &q.out, q.target_depth, q.target_normal, w, q.loss_out,
                                 &q.frame_grad)) != LGSR_OK)
                 return st;
             if ((st = backward_impl(ctx, L, S, &q.frame_grad, &q.grads, q.grad_pose)) != LGSR_OK) return st;
+            HIP_TRY(hipEventRecord(ctx->req_done[(size_t)i], L.stream), "request done");
+        } else {
+            HIP_TRY(hipEventRecord(ctx->req_done[(size_t)i], ctx->stream), "request done");
         }
-        HIP_TRY(hipEventRecord(ctx->req_done[(size_t)i], L.stream), "request done");
         ctx->batch_n = i + 1;
     }
     return LGSR_OK;

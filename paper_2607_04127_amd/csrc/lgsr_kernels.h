@@ -84,6 +84,25 @@ struct RasterBufs {
     int seg;
     int64_t items_max;
 };
+// One request of a batched forward raster: its buffers, grid and outputs; block0 and tile0
+// (its first block in the chunk-task launches and in the merge launch) are filled by the
+// launcher.
+struct FwdJob {
+    RasterBufs R;
+    Grid g;
+    float *depth, *opacity, *normal;
+    uint8_t *drop;
+    uint32_t block0, tile0;
+};
+constexpr int kMaxFwdJobs = 16;
+struct FwdJobs {
+    FwdJob j[kMaxFwdJobs];
+    int n;
+};
+static_assert(sizeof(FwdJobs) <= 4096, "the job table travels as a kernel argument");
+// The forward raster (chunks, merge, fix-up) of up to kMaxFwdJobs requests, one launch per
+// stage for all of them.
+hipError_t launch_raster_fwd_multi(FwdJobs &J, const RasterParams &p, hipStream_t s);
 int chunk_size(int64_t P, int requested);
 int64_t chunk_items_max(int64_t P, int T, int seg);
 size_t chunk_slot_floats(int64_t items_max);

@@ -186,13 +186,14 @@ __device__ __forceinline__ void composite(WaveStage &ws, const uint32_t *__restr
     }
 }
 
-__global__ __launch_bounds__(64) void raster_fwd_chunk_kernel(
+// Block b of a request's forward chunk launch (b = blockIdx.x for a single request).
+__device__ __forceinline__ void fwd_chunk_task(
     const uint4 *__restrict__ chunks, const uint32_t *__restrict__ n_items, const uint32_t *__restrict__ ids,
     const float *__restrict__ recs, const uint2 *__restrict__ rects, const float *__restrict__ rows,
-    const float *__restrict__ cols, Grid g, RasterParams p, float *__restrict__ slots)
+    const float *__restrict__ cols, const Grid &g, const RasterParams &p, float *__restrict__ slots, uint32_t b)
 {
     __shared__ WaveStage ws;
-    const uint32_t task = task_of(blockIdx.x), item = task >> 2;
+    const uint32_t task = task_of(b), item = task >> 2;
     if (item >= *n_items) return;
     const uint4 ch = uniform_chunk(chunks, item);
     const Lane L = lane_of((int)ch.x, g, (int)((task & 3u) * 64u + threadIdx.x));
@@ -210,6 +211,14 @@ __global__ __launch_bounds__(64) void raster_fwd_chunk_kernel(
     slots[slot(item, F_SN0, L.rt)] = acc.SN0;
     slots[slot(item, F_SN1, L.rt)] = acc.SN1;
     slots[slot(item, F_SN2, L.rt)] = acc.SN2;
+}
+
+__global__ __launch_bounds__(64) void raster_fwd_chunk_kernel(
+    const uint4 *__restrict__ chunks, const uint32_t *__restrict__ n_items, const uint32_t *__restrict__ ids,
+    const float *__restrict__ recs, const uint2 *__restrict__ rects, const float *__restrict__ rows,
+    const float *__restrict__ cols, Grid g, RasterParams p, float *__restrict__ slots)
+{
+    fwd_chunk_task(chunks, n_items, ids, recs, rects, rows, cols, g, p, slots, blockIdx.x);
 }
 
 __device__ __forceinline__ void write_ray(const Lane &L, const Grid &g, const RasterParams &p, float A, float SD,
@@ -261,19 +270,17 @@ __device__ __forceinline__ void run_bounds(uint32_t c0, uint32_t c1, int grp, in
 // Runs per tile: enough workgroups to fill the machine first, then shorter chains.
 int merge_groups(int T) { return T <= 512 ? 4 : 1; }
 
-__global__ __launch_bounds__(kMergeThreads) void raster_merge_kernel(const uint32_t *__restrict__ chunk_base, Grid g,
-                                                                     RasterParams p, float *__restrict__ slots,
-                                                                     float *__restrict__ depth,
-                                                                     float *__restrict__ opacity,
-                                                                     float *__restrict__ normal,
-                                                                     uint8_t *__restrict__ drop,
-                                                                     float4 *__restrict__ st0, float4 *__restrict__ st1,
-                                                                     float4 *__restrict__ fixA, float4 *__restrict__ fixB,
-                                                                     uint32_t *__restrict__ fixflag)
+// Tile `tile` of a request's merge launch.
+__device__ __forceinline__ void merge_tile(const uint32_t *__restrict__ chunk_base, const Grid &g,
+                                           const RasterParams &p, float *__restrict__ slots,
+                                           float *__restrict__ depth, float *__restrict__ opacity,
+                                           float *__restrict__ normal, uint8_t *__restrict__ drop,
+                                           float4 *__restrict__ st0, float4 *__restrict__ st1,
+                                           float4 *__restrict__ fixA, float4 *__restrict__ fixB,
+                                           uint32_t *__restrict__ fixflag, int tile)
 {
     extern __shared__ float msm[];  // ng runs x kMergeRunFloats
     const int ng = (int)(blockDim.x >> 8);
-    const int tile = blockIdx.x;
     const int t = (int)(threadIdx.x & 255u), grp = (int)(threadIdx.x >> 8);
     const Lane L = lane_of(tile, g, t);
     const uint32_t c0 = chunk_base[tile], c1 = chunk_base[tile + 1];
@@ -382,18 +389,31 @@ __global__ __launch_bounds__(kMergeThreads) void raster_merge_kernel(const uint3
     }
 }
 
+__global__ __launch_bounds__(kMergeThreads) void raster_merge_kernel(const uint32_t *__restrict__ chunk_base, Grid g,
+                                                                     RasterParams p, float *__restrict__ slots,
+                                                                     float *__restrict__ depth,
+                                                                     float *__restrict__ opacity,
+                                                                     float *__restrict__ normal,
+                                                                     uint8_t *__restrict__ drop,
+                                                                     float4 *__restrict__ st0, float4 *__restrict__ st1,
+                                                                     float4 *__restrict__ fixA, float4 *__restrict__ fixB,
+                                                                     uint32_t *__restrict__ fixflag)
+{
+    merge_tile(chunk_base, g, p, slots, depth, opacity, normal, drop, st0, st1, fixA, fixB, fixflag, blockIdx.x);
+}
+
 // Re-walk the chunk in which a ray terminates, from its true transmittance, and finish it.
 // One wave per (chunk, sub-tile) task, flagged by the merge.
-__global__ __launch_bounds__(64) void raster_fixup_kernel(
+__device__ __forceinline__ void fixup_task(
     const uint4 *__restrict__ chunks, const uint32_t *__restrict__ n_items, const uint32_t *__restrict__ ids,
     const float *__restrict__ recs, const uint2 *__restrict__ rects, const float *__restrict__ rows,
-    const float *__restrict__ cols, Grid g, RasterParams p, const float4 *__restrict__ fixA,
+    const float *__restrict__ cols, const Grid &g, const RasterParams &p, const float4 *__restrict__ fixA,
     const float4 *__restrict__ fixB, float *__restrict__ slots, float *__restrict__ depth, float *__restrict__ opacity,
     float *__restrict__ normal, uint8_t *__restrict__ drop, float4 *__restrict__ st0, float4 *__restrict__ st1,
-    uint32_t *__restrict__ fixflag)
+    uint32_t *__restrict__ fixflag, uint32_t b)
 {
     __shared__ WaveStage ws;
-    const uint32_t task = task_of(blockIdx.x), item = task >> 2;
+    const uint32_t task = task_of(b), item = task >> 2;
     if (item >= *n_items) return;
     if (__builtin_amdgcn_readfirstlane(fixflag[task]) == 0u) return;  // no ray of this sub-tile re-walks here
     if (threadIdx.x == 0) fixflag[task] = 0u;                         // zero for the next forward
@@ -421,6 +441,55 @@ __global__ __launch_bounds__(64) void raster_fixup_kernel(
     slots[slot(item, F_K, L.rt)] = __int_as_float(acc.K);
     write_ray(L, g, p, fa.y + acc.A, fa.z + acc.SD, fb.x + acc.SN0, fb.y + acc.SN1, fb.z + acc.SN2, acc.T,
               __float_as_int(fa.w) + acc.K, depth, opacity, normal, drop, st0, st1);
+}
+
+__global__ __launch_bounds__(64) void raster_fixup_kernel(
+    const uint4 *__restrict__ chunks, const uint32_t *__restrict__ n_items, const uint32_t *__restrict__ ids,
+    const float *__restrict__ recs, const uint2 *__restrict__ rects, const float *__restrict__ rows,
+    const float *__restrict__ cols, Grid g, RasterParams p, const float4 *__restrict__ fixA,
+    const float4 *__restrict__ fixB, float *__restrict__ slots, float *__restrict__ depth, float *__restrict__ opacity,
+    float *__restrict__ normal, uint8_t *__restrict__ drop, float4 *__restrict__ st0, float4 *__restrict__ st1,
+    uint32_t *__restrict__ fixflag)
+{
+    fixup_task(chunks, n_items, ids, recs, rects, rows, cols, g, p, fixA, fixB, slots, depth, opacity, normal, drop,
+               st0, st1, fixflag, blockIdx.x);
+}
+
+// ---------------------------------------------------------------------------------------
+// forward over a batch of requests: one launch per stage for all of them
+// ---------------------------------------------------------------------------------------
+
+// The job of block b (jobs sorted by first block; at most kMaxFwdJobs, a uniform scan).
+__device__ __forceinline__ int job_of(const FwdJobs &J, uint32_t b, bool merge)
+{
+    int j = 0;
+    for (int k = 1; k < J.n; ++k)
+        if (b >= (merge ? J.j[k].tile0 : J.j[k].block0)) j = k;
+    return j;
+}
+
+__global__ __launch_bounds__(64) void raster_fwd_chunk_multi(FwdJobs J, RasterParams p)
+{
+    const int j = job_of(J, blockIdx.x, false);
+    const FwdJob &q = J.j[j];
+    fwd_chunk_task(q.R.chunks, q.R.n_items, q.R.ids, q.R.recs, q.R.rects, q.R.rows, q.R.cols, q.g, p, q.R.slots,
+                   blockIdx.x - q.block0);
+}
+
+__global__ __launch_bounds__(kMergeThreads) void raster_merge_multi(FwdJobs J, RasterParams p)
+{
+    const int j = job_of(J, blockIdx.x, true);
+    const FwdJob &q = J.j[j];
+    merge_tile(q.R.chunk_base, q.g, p, q.R.slots, q.depth, q.opacity, q.normal, q.drop, q.R.st0, q.R.st1, q.R.fixA,
+               q.R.fixB, q.R.fixflag, (int)(blockIdx.x - q.tile0));
+}
+
+__global__ __launch_bounds__(64) void raster_fixup_multi(FwdJobs J, RasterParams p)
+{
+    const int j = job_of(J, blockIdx.x, false);
+    const FwdJob &q = J.j[j];
+    fixup_task(q.R.chunks, q.R.n_items, q.R.ids, q.R.recs, q.R.rects, q.R.rows, q.R.cols, q.g, p, q.R.fixA, q.R.fixB,
+               q.R.slots, q.depth, q.opacity, q.normal, q.drop, q.R.st0, q.R.st1, q.R.fixflag, blockIdx.x - q.block0);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -771,6 +840,25 @@ hipError_t launch_raster_fwd(const RasterBufs &R, const Grid &g, const RasterPar
         raster_fixup_kernel<<<task_blocks(im), 64, 0, s>>>(R.chunks, R.n_items, R.ids, R.recs, R.rects, R.rows,
                                                            R.cols, g, p, R.fixA, R.fixB, R.slots, depth, opacity,
                                                            normal, drop, R.st0, R.st1, R.fixflag);
+    return hipGetLastError();
+}
+
+hipError_t launch_raster_fwd_multi(FwdJobs &J, const RasterParams &p, hipStream_t s)
+{
+    if (J.n <= 0) return hipSuccess;
+    uint32_t blocks = 0, tiles = 0;
+    for (int k = 0; k < J.n; ++k) {
+        J.j[k].block0 = blocks;
+        J.j[k].tile0 = tiles;
+        blocks += J.j[k].R.items_max > 0 && J.j[k].g.T > 0 ? task_blocks((int)J.j[k].R.items_max) : 0u;
+        tiles += (uint32_t)(J.j[k].g.T > 0 ? J.j[k].g.T : 0);
+    }
+    if (blocks > 0) raster_fwd_chunk_multi<<<blocks, 64, 0, s>>>(J, p);
+    if (tiles > 0) {
+        const int ng = kMergeGroups;
+        raster_merge_multi<<<tiles, 256 * ng, (size_t)ng * kMergeRunFloats * sizeof(float), s>>>(J, p);
+    }
+    if (blocks > 0) raster_fixup_multi<<<blocks, 64, 0, s>>>(J, p);
     return hipGetLastError();
 }
 

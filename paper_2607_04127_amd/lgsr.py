@@ -16,6 +16,7 @@ import torch
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liblgsr.so")
 
+LGSR_FLAG_BATCH_FUSED = 1
 LGSR_OK, LGSR_EINVAL, LGSR_ENOMEM, LGSR_EDEVICE, LGSR_ECAPACITY, LGSR_ESTATE, LGSR_EINTERNAL = 0, -1, -2, -3, -4, -5, -6
 _STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ECAPACITY", -5: "ESTATE", -6: "EINTERNAL"}
 

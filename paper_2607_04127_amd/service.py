@@ -131,12 +131,17 @@ def working_bytes(tpl, grad):
 
 class Service:
     def __init__(self, ctx: lgsr.Context, pool, mode="batched", max_batch=16, hbm_budget=32 << 30):
-        """hbm_budget: device bytes the service may use for requests in flight; what the
-        context already retains (workspace and earlier batch states) is taken off it."""
-        if mode not in ("batched", "single"):
-            raise ValueError("mode must be 'batched' or 'single'")
+        """mode: "batched" (lgsr_render_batch, each request on one of four streams),
+        "fused" (lgsr_render_batch with one launch per compositing stage for the whole batch)
+        or "single" (one request per call).  hbm_budget: device bytes the service may use for
+        requests in flight; what the context already retains (workspace and earlier batch
+        states) is taken off it."""
+        if mode not in ("batched", "fused", "single"):
+            raise ValueError("mode must be 'batched', 'fused' or 'single'")
         self.ctx, self.pool, self.mode = ctx, pool, mode
-        self.max_batch = max(1, int(max_batch)) if mode == "batched" else 1
+        self.max_batch = max(1, int(max_batch)) if mode != "single" else 1
+        self.opts = lgsr.default_opts(flags=lgsr.LGSR_FLAG_BATCH_FUSED if mode == "fused" else 0) \
+            if ctx is not None else None
         retained = lgsr.lgsr_state_bytes(ctx, None) if ctx is not None else 0
         self.hbm_budget = max(0, int(hbm_budget) - retained)
 
@@ -155,7 +160,7 @@ class Service:
     def _execute(self, batch, t0):
         """Runs a batch; returns each request's completion time (seconds since t0), taken
         when the host sees that request's results ready."""
-        if self.mode == "batched" and len(batch) > 1:
+        if self.mode != "single" and len(batch) > 1:
             reqs = []
             for r in batch:
                 tp = self.pool[r.template]
@@ -163,7 +168,7 @@ class Service:
                 if r.grad:
                     q["target_depth"], q["target_normal"] = tp["td"], tp["tn"]
                 reqs.append(q)
-            lgsr.lgsr_render_batch(self.ctx, reqs)
+            lgsr.lgsr_render_batch(self.ctx, reqs, opts=self.opts)
             n = len(batch)
             done_at = [None] * n
             left = n

@@ -63,11 +63,15 @@ def _close(a, b, what):
     assert np.abs(a - b).max(initial=0.0) <= 1e-5 * scale + 1e-30, what
 
 
-def test_batch_matches_single_calls(ctx):
+@pytest.mark.parametrize("fused", [False, True])
+def test_batch_matches_single_calls(ctx, fused):
+    """Both batch modes: requests on four streams, and one launch per compositing stage for
+    the whole batch (LGSR_FLAG_BATCH_FUSED)."""
     from paper_2607_04127_amd import lgsr
     reqs = _requests(3)
+    opts = lgsr.default_opts(flags=lgsr.LGSR_FLAG_BATCH_FUSED if fused else 0)
     for rep in range(2):  # the second batch reuses the internal per-request states
-        res = lgsr.lgsr_render_batch(ctx, reqs)
+        res = lgsr.lgsr_render_batch(ctx, reqs, opts=opts)
         torch.cuda.synchronize()
         for k, (q, r) in enumerate(zip(reqs, res)):
             fr, st = lgsr.lgsr_forward(ctx, q["surfels"], torch.from_numpy(np.asarray(q["pose"])), q["row_sincos"],
@@ -106,7 +110,8 @@ def test_service_serves_a_poisson_stream(ctx):
         assert 0 < rep["p50_ms"] <= rep["p99_ms"], rep
 
 
-def test_batch_matches_oracle(ctx):
+@pytest.mark.parametrize("fused", [False, True])
+def test_batch_matches_oracle(ctx, fused):
     """One batch mixing two maps (the 1k-surfel room and a 20k-surfel street block), four beam
     models and render / render + gradient requests, every request against the FP64 oracle:
     frames at the parity bars on every ray (the 64 x 1024 one on 4096 sampled rays), the
@@ -145,7 +150,7 @@ def test_batch_matches_oracle(ctx):
             q["target_normal"] = torch.from_numpy(w["target_normal"]).cuda()
         reqs.append(q)
         meta.append((w, of, ids, grad))
-    res = lgsr.lgsr_render_batch(ctx, reqs)
+    res = lgsr.lgsr_render_batch(ctx, reqs, opts=lgsr.default_opts(flags=lgsr.LGSR_FLAG_BATCH_FUSED if fused else 0))
     torch.cuda.synchronize()
     assert all(lgsr.lgsr_batch_poll(ctx, len(reqs)))
     for k, (r, (w, of, ids, grad)) in enumerate(zip(res, meta)):
