@@ -253,8 +253,10 @@ def main():
 
 def hbm_probe(ctx):
     """The HBM bandwidth a plain streaming kernel reaches on this device: a copy over 2 x 2 GiB
-    and a triad over 3 x 1.5 GiB (working sets far beyond the 256 MB last-level cache), HIP
-    events on the library's stream, best of 10 repetitions after one warm-up."""
+    and a triad over 3 x 1.5 GiB (working sets far beyond the 256 MB last-level cache), each
+    in two access forms (non-temporal 4-vector, plain 1-vector) at 1024, 4096 and 65536
+    workgroups, HIP events on the library's stream, the best of 5 repetitions per form after
+    one warm-up, then the best form."""
     import torch
 
     from paper_2607_04127_amd import lgsr
@@ -267,20 +269,25 @@ def hbm_probe(ctx):
         A = [torch.empty(n, device=dev) for _ in range(arrays)]
         for t in A:
             t.fill_(1.0)
-        call = (lambda: lgsr.lgsr_stream_probe(ctx, "copy", A[0], A[1])) if kind == "copy" else \
-            (lambda: lgsr.lgsr_stream_probe(ctx, "triad", A[0], A[1], A[2]))
-        call()
-        torch.cuda.synchronize()
-        best = None
-        for _ in range(10):
-            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            a.record()
-            call()
-            b.record()
-            torch.cuda.synchronize()
-            ms = a.elapsed_time(b)
-            best = ms if best is None else min(best, ms)
+        best, form = None, None
+        for plain in (False, True):
+            for blocks in (1024, 4096, 65536):
+                def call():
+                    lgsr.lgsr_stream_probe(ctx, kind, A[0], A[1], A[2] if kind == "triad" else None, plain=plain,
+                                           blocks=blocks)
+                call()
+                torch.cuda.synchronize()
+                for _ in range(5):
+                    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    a.record()
+                    call()
+                    b.record()
+                    torch.cuda.synchronize()
+                    ms = a.elapsed_time(b)
+                    if best is None or ms < best:
+                        best, form = ms, f"{'plain 1-vector' if plain else 'non-temporal 4-vector'}, {blocks} workgroups"
         out[f"{kind}_GBps"] = round(nbytes_per * n / (best * 1e-3) / 1e9, 1)
+        out[f"{kind}_form"] = form
         out[f"{kind}_working_set_GiB"] = round(arrays * 4 * n / 2 ** 30, 2)
         del A
         torch.cuda.empty_cache()
@@ -583,10 +590,23 @@ def cpu_baseline(w, target_s):
     dt = run(m)
     m2 = int(min(H * W, max(m, m * target_s / max(dt, 1e-3))))
     dt2 = run(m2)
-    print(f"# cpu oracle: {m2} rays in {dt2:.1f} s", file=sys.stderr, flush=True)
-    return {"value": round(m2 / dt2, 1), "unit": "rays/s", "cores": ref.threads(), "kind": "oracle",
+    cores = ref.threads()
+    print(f"# cpu oracle: {m2} rays in {dt2:.1f} s on {cores} threads", file=sys.stderr, flush=True)
+    # one thread, on a sample about a fifth as long
+    ref.set_threads(1)
+    m1 = max(16, int(m2 / cores / 5))
+    dt1 = run(m1)
+    ref.set_threads(cores)
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
+    except OSError:
+        pass
+    return {"value": round(m2 / dt2, 1), "unit": "rays/s", "cores": cores, "kind": "oracle",
+            "cpu_model": model, "one_thread_rays_per_s": round(m1 / dt1, 2),
             "sample": f"{m2} seeded random rays of the {H}x{W} image against all {w['means'].shape[0]} surfels, "
-                      f"forward + loss + backward in float64 ({dt2:.1f} s)"}
+                      f"forward + loss + backward in float64 ({dt2:.1f} s); one thread: {m1} rays ({dt1:.1f} s)"}
 
 
 if __name__ == "__main__":

@@ -314,10 +314,13 @@ lgsr_status lgsr_tile_list(lgsr_ctx *ctx, const lgsr_state *state, int32_t tile_
 /* Streaming probe, outside the rendering path: the HBM bandwidth a plain streaming kernel
  * reaches on this device, the denominator of the path's HBM fraction, and a cache flush
  * between timed steps.  kind 0 (copy): a[i] = b[i] (8 bytes per float); kind 1 (triad):
- * a[i] = b[i] + 3 c[i] (12 bytes per float).  n floats, a multiple of 4; a, b, c DEVICE,
- * 16-byte aligned, not overlapping.  Asynchronous on the context's stream.  Errors: EINVAL,
- * EDEVICE. */
-lgsr_status lgsr_stream_probe(lgsr_ctx *ctx, int32_t kind, const float *b, const float *c, float *a, int64_t n);
+ * a[i] = b[i] + 3 c[i] (12 bytes per float), both with non-temporal 4-vector accesses per
+ * lane; kinds 2 and 3: the same with plain one-vector accesses.  blocks: 256-lane
+ * workgroups striding over the arrays (0 = 4096).  n floats, a multiple of 4; a, b, c
+ * DEVICE, 16-byte aligned, not overlapping.  Asynchronous on the context's stream.
+ * Errors: EINVAL, EDEVICE. */
+lgsr_status lgsr_stream_probe(lgsr_ctx *ctx, int32_t kind, const float *b, const float *c, float *a, int64_t n,
+                              int32_t blocks);
 
 /* Stage timers.  lgsr_profile selects stages by bit mask (bit k = stage k, 0 = off, -1 =
  * all); each selected stage is then bracketed by HIP events on the context's stream (a

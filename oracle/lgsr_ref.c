@@ -933,6 +933,15 @@ int lgsr_ref_contributors(const lgsr_ref_map *map, const double pose[12], const 
     return fail ? -1 : 0;
 }
 
+void lgsr_ref_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 int lgsr_ref_threads(void)
 {
 #ifdef _OPENMP

@@ -133,6 +133,9 @@ int lgsr_ref_contributors(const lgsr_ref_map *map, const double pose[12], const 
                           const lgsr_ref_params *prm, int64_t n_rays, const int64_t *ray_ids, int64_t *ids,
                           int64_t cap, int32_t *count);
 
+/* Set the number of OpenMP threads later calls run with (n > 0). */
+void lgsr_ref_set_threads(int n);
+
 /* Number of OpenMP threads the oracle runs with. */
 int lgsr_ref_threads(void);
 

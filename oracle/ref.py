@@ -67,6 +67,8 @@ def lib():
         L.lgsr_ref_scan_to_range.restype = ctypes.c_int
         L.lgsr_ref_target_cov.argtypes = [i64, vp, vp, d, vp]
         L.lgsr_ref_target_cov.restype = ctypes.c_int
+        L.lgsr_ref_set_threads.argtypes = [ctypes.c_int]
+        L.lgsr_ref_set_threads.restype = None
         L.lgsr_ref_order.argtypes = [vp, vp, vp, vp, vp, vp]
         L.lgsr_ref_order.restype = ctypes.c_int
         L.lgsr_ref_contributors.argtypes = [vp, vp, vp, vp, i64, vp, vp, i64, vp]
@@ -77,6 +79,11 @@ def lib():
 
 def threads() -> int:
     return int(lib().lgsr_ref_threads())
+
+
+def set_threads(n: int) -> None:
+    """Threads of later oracle calls (OpenMP)."""
+    lib().lgsr_ref_set_threads(int(n))
 
 
 def params(**kw) -> dict:

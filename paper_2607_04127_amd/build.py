@@ -24,16 +24,23 @@ FLAGS = [
 ]
 
 
-def build(verbose: bool = False, extra=None) -> str:
+# host code only: AddressSanitizer and UndefinedBehaviorSanitizer for the CPU side of the
+# library (device code is built as always)
+HOST_SANITIZE = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+                 "-Xarch_host", "-fno-omit-frame-pointer"]
+
+
+def build(verbose: bool = False, extra=None, out: str | None = None, host_sanitize: bool = False) -> str:
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    tmp = LIB + ".tmp"
-    cmd = [hipcc, *FLAGS, *(extra or []), "-I", os.path.join(ROOT, "include"), "-I", CSRC,
-           *[os.path.join(CSRC, s) for s in SOURCES], "-o", tmp]
+    out = out or LIB
+    tmp = out + ".tmp"
+    cmd = [hipcc, *FLAGS, *(HOST_SANITIZE if host_sanitize else []), *(extra or []), "-I", os.path.join(ROOT, "include"),
+           "-I", CSRC, *[os.path.join(CSRC, s) for s in SOURCES], "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":

@@ -1235,17 +1235,18 @@ lgsr_status lgsr_tile_list(lgsr_ctx *ctx, const lgsr_state *S, int32_t tile_row,
     return LGSR_OK;
 }
 
-lgsr_status lgsr_stream_probe(lgsr_ctx *ctx, int32_t kind, const float *b, const float *c, float *a, int64_t n)
+lgsr_status lgsr_stream_probe(lgsr_ctx *ctx, int32_t kind, const float *b, const float *c, float *a, int64_t n,
+                              int32_t blocks)
 {
     if (!ctx) return LGSR_EINVAL;
     if (n < 0 || (n % 4) != 0) return fail(ctx, LGSR_EINVAL, "n must be a non-negative multiple of 4");
-    if (kind != 0 && kind != 1) return fail(ctx, LGSR_EINVAL, "kind must be 0 (copy) or 1 (triad)");
-    if (n > 0 && (!b || !a || (kind == 1 && !c))) return fail(ctx, LGSR_EINVAL, "NULL array");
+    if (kind < 0 || kind > 3) return fail(ctx, LGSR_EINVAL, "kind must lie in 0..3");
+    if (blocks < 0 || blocks > (1 << 20)) return fail(ctx, LGSR_EINVAL, "blocks must lie in 0..2^20");
+    if (n > 0 && (!b || !a || ((kind & 1) && !c))) return fail(ctx, LGSR_EINVAL, "NULL array");
     if (((reinterpret_cast<uintptr_t>(a) | reinterpret_cast<uintptr_t>(b) | reinterpret_cast<uintptr_t>(c)) & 15u) != 0)
         return fail(ctx, LGSR_EINVAL, "arrays must be 16-byte aligned");
     HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
-    if (kind == 0) HIP_TRY(launch_stream_copy(b, a, n, ctx->stream), "stream copy");
-    else HIP_TRY(launch_stream_triad(b, c, a, 3.f, n, ctx->stream), "stream triad");
+    HIP_TRY(launch_stream_probe(kind, b, c, a, n, blocks, ctx->stream), "stream probe");
     return LGSR_OK;
 }
 

@@ -173,7 +173,9 @@ struct AdamBatch {
 hipError_t launch_adam(AdamBatch B, float beta1, float beta2, float eps, int step, hipStream_t s);
 
 // ---- probe.hip ----
-hipError_t launch_stream_copy(const float *src, float *dst, int64_t n, hipStream_t s);
-hipError_t launch_stream_triad(const float *b, const float *c, float *a, float scale, int64_t n, hipStream_t s);
+// kind 0 copy a = b (non-temporal, 4 vectors per lane), 1 triad a = b + 3 c (same), 2 copy
+// and 3 triad with plain loads and stores, one vector per lane; blocks <= 0: 4096
+hipError_t launch_stream_probe(int kind, const float *b, const float *c, float *a, int64_t n, int blocks,
+                               hipStream_t s);
 
 }  // namespace lgsr

@@ -14,7 +14,8 @@ import weakref
 import torch
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "liblgsr.so")
+# LGSR_LIB names another build of the library (the sanitizer test loads a host-sanitized one)
+LIB_PATH = os.environ.get("LGSR_LIB") or os.path.join(HERE, "liblgsr.so")
 
 LGSR_FLAG_BATCH_FUSED = 1
 LGSR_OK, LGSR_EINVAL, LGSR_ENOMEM, LGSR_EDEVICE, LGSR_ECAPACITY, LGSR_ESTATE, LGSR_EINTERNAL = 0, -1, -2, -3, -4, -5, -6
@@ -112,7 +113,7 @@ def lib():
         L.lgsr_forward.argtypes = [vp, P(Surfels), vp, ctypes.c_int32, P(Beams), P(RasterOpts), P(Frame), P(vp)]
         L.lgsr_loss.argtypes = [vp, ctypes.c_int64, P(Frame), vp, vp, P(LossWeights), vp, P(FrameGrad)]
         L.lgsr_loss_noalloc.argtypes = [vp, ctypes.c_int64, P(Frame), vp, vp, P(LossWeights), vp, P(FrameGrad)]
-        L.lgsr_stream_probe.argtypes = [vp, ctypes.c_int32, vp, vp, vp, ctypes.c_int64]
+        L.lgsr_stream_probe.argtypes = [vp, ctypes.c_int32, vp, vp, vp, ctypes.c_int64, ctypes.c_int32]
         L.lgsr_count_hits.argtypes = [vp, vp, P(ctypes.c_int64)]
         L.lgsr_batch_poll.argtypes = [vp, ctypes.c_int32, P(ctypes.c_int32)]
         L.lgsr_request_bytes.argtypes = [ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64,
@@ -484,14 +485,16 @@ def lgsr_tile_list(ctx: Context, state: State, tile_row: int, tile_col: int):
     return out[:n.value]
 
 
-def lgsr_stream_probe(ctx: Context, kind: str, a: torch.Tensor, b: torch.Tensor, c: torch.Tensor | None = None):
-    """Streaming probe (not part of the path): kind "copy" a = b, "triad" a = b + 3 c."""
+def lgsr_stream_probe(ctx: Context, kind: str, a: torch.Tensor, b: torch.Tensor, c: torch.Tensor | None = None,
+                      plain: bool = False, blocks: int = 0):
+    """Streaming probe (not part of the path): kind "copy" a = b, "triad" a = b + 3 c;
+    non-temporal 4-vector accesses, or plain one-vector ones; blocks 0 = 4096."""
     for t in (a, b) + ((c,) if c is not None else ()):
         if t.dtype != torch.float32 or not t.is_contiguous() or t.device != ctx.device:
             raise ValueError("probe arrays must be contiguous float32 on the context's device")
     ctx._stream()
-    ctx._check(lib().lgsr_stream_probe(ctx.handle, 0 if kind == "copy" else 1, _ptr(b), _ptr(c), _ptr(a),
-                                       a.numel()))
+    k = (0 if kind == "copy" else 1) + (2 if plain else 0)
+    ctx._check(lib().lgsr_stream_probe(ctx.handle, k, _ptr(b), _ptr(c), _ptr(a), a.numel(), int(blocks)))
 
 
 def lgsr_request_bytes(n: int, H: int, W: int, pairs: int, with_grad: bool) -> int:

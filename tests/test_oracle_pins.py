@@ -4,7 +4,7 @@ routines (scipy rotations, numpy linear solves) and central finite differences.
 
 Paper: arXiv 2607.04127 -- Sec. 3.1 (map of 2D Gaussian primitives rendered under the
 spherical projection into depth/opacity/normals), Sec. 3.4 (masked depth L1 and cosine
-normal loss, Eqs. 8-9), Sec. 4.1 (loss weights).
+normal loss, Eq. 10 left and Eq. 11 first term), Sec. 4.1 (loss weights).
 """
 import math
 
@@ -301,7 +301,7 @@ def test_edge_cases(ref, beams):
 
 
 # ------------------------------------------------------------------------------------------
-# Loss (Eqs. 8-9) on hand-checked numbers
+# Loss (Eq. 10 left, Eq. 11 first term) on hand-checked numbers
 # ------------------------------------------------------------------------------------------
 
 def test_loss_hand_values(ref):
@@ -430,7 +430,7 @@ def test_render_backward_finite_differences_under_a_rotated_pose(ref):
 
 
 def test_loss_gradients_match_finite_differences(ref):
-    """Forward + Eqs. 8-9 loss + backward.  Surfels sit on the scanned surfaces, so many
+    """Forward + loss (Eq. 10 left, Eq. 11 first term) + backward.  Surfels sit on the scanned surfaces, so many
     rendered depths equal their raycast targets exactly, at the corner of |x|; the targets
     are moved off it by a random 5-30 cm so the central differences are derivatives."""
     S, pose, rows, cols, td, tn = _fd_scene()
