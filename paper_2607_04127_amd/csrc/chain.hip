@@ -51,9 +51,9 @@ __global__ __launch_bounds__(kChainThreads) void chain_kernel(SurfelPtrs S, cons
     const int64_t i = (int64_t)blockIdx.x * kChainThreads + threadIdx.x;
     float pr[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     if (i < S.n) {
+        Geom g = project_geom(S.means, S.quats, S.log_scales, S.logits, i, P, p.near);
         float out_m[3] = {0.f, 0.f, 0.f}, out_q[4] = {0.f, 0.f, 0.f, 0.f}, out_s[2] = {0.f, 0.f}, out_o = 0.f;
-        // only surfels with a ray rectangle (from the forward) can have a written slot; the
-        // others get zero gradients without their projection being formed again
+        // only surfels with a ray rectangle (from the forward) can have a written slot
         const bool listed = (rects[i].y >> 16) > 0u;
         float4 x = make_float4(0.f, 0.f, 0.f, 0.f), y = x, z = x, zz = x;
         if (listed) {
@@ -69,9 +69,6 @@ __global__ __launch_bounds__(kChainThreads) void chain_kernel(SurfelPtrs S, cons
             G4[2] = z4;
             G4[3] = z4;
         }
-        Geom g;
-        g.valid = false;
-        if (listed) g = project_geom(S.means, S.quats, S.log_scales, S.logits, i, P, p.near);
         if (g.valid && listed) {
             const RecParts q = record_parts(g);
             const float gnt[3] = {x.x, x.y, x.z}, gc = x.w;
