@@ -41,14 +41,14 @@ PEAK_HBM_GBS = 8000.0
 # WRITE_SIZE per dispatch, each scaled by what the counter reads for a plain 256 MiB device
 # copy (profiles/pmc_traffic_raster_bwd_block64x1024_300k.md).  Valid only for the kernel
 # sources they were taken with (digest below); reported as null once those change.
-TRAFFIC_RASTER_BWD = dict(bytes=57538829,
-                          sources_sha256="6d58e84aaacbf321e84e7e3db46e8447d3b40160f82dd79dd92be0722e4ac37d")
+TRAFFIC_RASTER_BWD = dict(bytes=57592575,
+                          sources_sha256="880d31f60cd5f837ecee0aad0caca4aafa68b10b1a40a941c6769bcd7373f2a3")
 
 
 # rocprofv3 SQ counters of one raster_bwd launch on the benchmark workload (per dispatch) and
 # the kernel's mean duration in the same profiled run; same validity rule as the traffic.
-SQ_RASTER_BWD = dict(SQ_INSTS_VALU=23640643, SQ_INSTS_LDS=1002479, SQ_LDS_BANK_CONFLICT=312440, ms=0.0719,
-                     sources_sha256="6d58e84aaacbf321e84e7e3db46e8447d3b40160f82dd79dd92be0722e4ac37d")
+SQ_RASTER_BWD = dict(SQ_INSTS_VALU=24054991, SQ_INSTS_LDS=1002483, SQ_LDS_BANK_CONFLICT=312440, ms=0.0761,
+                     sources_sha256="880d31f60cd5f837ecee0aad0caca4aafa68b10b1a40a941c6769bcd7373f2a3")
 
 
 def _sources_digest() -> str:
