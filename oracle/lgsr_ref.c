@@ -142,6 +142,17 @@ static int64_t sort_surfels(const surf_t *S, int64_t n, int64_t *order, int64_t 
     return m;
 }
 
+/* Copies of the surfels ids[0 .. m) in that order, so that a ray's walk in compositing order
+ * reads memory front to back (the visit order and the arithmetic are those of the walk over
+ * S[ids[k]]; only the layout differs).  NULL on allocation failure when m > 0. */
+static surf_t *in_order(const surf_t *S, const int64_t *ids, int64_t m)
+{
+    surf_t *Q = (surf_t *)malloc(sizeof(surf_t) * (size_t)(m > 0 ? m : 1));
+    if (Q)
+        for (int64_t k = 0; k < m; ++k) Q[k] = S[ids[k]];
+    return Q;
+}
+
 /* Whether ray d passes every per-hit test of surfel s (R1, R4, R11), ignoring the centre
  * range; used only for the margin of the centre-range decision. */
 static int passes_hit_tests(const surf_t *s, const double *d, const lgsr_ref_params *p)
@@ -171,8 +182,10 @@ static void ray_dir(const lgsr_ref_beams *B, int64_t rid, double *d)
 
 static double rel_gap(double x, double thr) { return fabs(x - thr) / fabs(thr); }
 
-/* Front-to-back compositing of one ray over every surfel (R1-R5).  When hits != NULL the
- * composited hits are recorded in order (capacity: the number of valid surfels).
+/* Front-to-back compositing of one ray over every surfel (R1-R5).  Q[0 .. m) are the valid
+ * surfels in compositing order and order[k] the id of Q[k]; C[0 .. n_cut) the surfels cut for
+ * their centre range only.  When hits != NULL the composited hits are recorded in order
+ * (capacity: the number of valid surfels).
  * margin: the smallest relative gap between a quantity and the threshold it was tested
  * against (|n'.d| vs den_eps, t vs near, q2 vs k^2, alpha G vs alpha_thr and alpha_max,
  * transmittance vs T_min, and the centre range vs near of every surfel the ray composites
@@ -181,19 +194,19 @@ static double rel_gap(double x, double thr) { return fabs(x - thr) / fabs(thr); 
  * consecutive composited surfels.  A small value flags a ray whose result may legitimately
  * differ when computed in lower precision.  den_min: the smallest |n'.d| over the composited
  * hits (the ray/plane intersection amplifies errors of the plane normal by 1 / |n'.d|). */
-static void render_ray(const surf_t *S, const int64_t *order, int64_t m, const int64_t *cut, int64_t n_cut,
+static void render_ray(const surf_t *Q, const int64_t *order, int64_t m, const surf_t *C, int64_t n_cut,
                        const double *d, const lgsr_ref_params *p, int want_extra, ray_t *out, hit_t *hits)
 {
     double T = 1, A = 0, SD = 0, SN[3] = {0, 0, 0}, margin = INFINITY, order_gap = INFINITY;
     double den_min = INFINITY;
     if (want_extra)
         for (int64_t ci = 0; ci < n_cut; ++ci)
-            if (passes_hit_tests(&S[cut[ci]], d, p)) margin = fmin(margin, rel_gap(S[cut[ci]].r, p->near));
+            if (passes_hit_tests(&C[ci], d, p)) margin = fmin(margin, rel_gap(C[ci].r, p->near));
     int32_t K = 0, nh = 0;
     int stopped = 0;
     double k2 = p->cutoff_sigma * p->cutoff_sigma, prev_r = -1;
     for (int64_t oi = 0; oi < m; ++oi) {
-        const surf_t *s = &S[order[oi]];
+        const surf_t *s = &Q[oi];
         double den = dot3(s->n, d);
         if (want_extra && !stopped) margin = fmin(margin, rel_gap(fabs(den), p->den_eps));
         if (fabs(den) < p->den_eps) continue;
@@ -279,6 +292,8 @@ int lgsr_ref_forward(const lgsr_ref_map *map, const double pose[12], const lgsr_
     setup_surfels(map, pose, prm, S);
     int64_t n_cut = 0;
     int64_t m = sort_surfels(S, map->n, order, cut, &n_cut);
+    surf_t *Q = in_order(S, order, m), *C = in_order(S, cut, n_cut);
+    if (!Q || !C) { free(S); free(order); free(cut); free(Q); free(C); return -1; }
     int want_extra = (margin != NULL) || (n_hits != NULL) || (order_gap != NULL) || (den_min != NULL);
 #pragma omp parallel for schedule(dynamic, 16)
     for (int64_t i = 0; i < n_rays; ++i) {
@@ -286,7 +301,7 @@ int lgsr_ref_forward(const lgsr_ref_map *map, const double pose[12], const lgsr_
         double d[3];
         ray_dir(beams, rid, d);
         ray_t r;
-        render_ray(S, order, m, cut, n_cut, d, prm, want_extra, &r, NULL);
+        render_ray(Q, order, m, C, n_cut, d, prm, want_extra, &r, NULL);
         if (r.K == 0) {
             depth[i] = 0; opacity[i] = 0;
             normal[3 * i] = normal[3 * i + 1] = normal[3 * i + 2] = 0;
@@ -307,6 +322,8 @@ int lgsr_ref_forward(const lgsr_ref_map *map, const double pose[12], const lgsr_
     free(S);
     free(order);
     free(cut);
+    free(Q);
+    free(C);
     return 0;
 }
 
@@ -474,6 +491,8 @@ int lgsr_ref_backward(const lgsr_ref_map *map, const double pose[12], const lgsr
         for (int c = 0; c < 6; ++c) pose_mass[c] = 0;
     setup_surfels(map, pose, prm, S);
     int64_t m = sort_surfels(S, n, order, NULL, NULL);
+    surf_t *Q = in_order(S, order, m);
+    if (!Q) { free(S); free(order); free(Gs); return -1; }
 
 #pragma omp parallel
     {
@@ -484,7 +503,7 @@ int lgsr_ref_backward(const lgsr_ref_map *map, const double pose[12], const lgsr
             double d[3];
             ray_dir(beams, rid, d);
             ray_t r;
-            render_ray(S, order, m, NULL, 0, d, prm, 0, &r, hits);
+            render_ray(Q, order, m, NULL, 0, d, prm, 0, &r, hits);
             if (r.K == 0) continue;
             /* dL = gD dDhat + gA dA + gN.dNhat with Dhat = SD/A, Nhat = SN/A:
              * dL = (gD/A) dSD + (gN/A).dSN + (gA - (gD Dhat + gN.Nhat)/A) dA. */
@@ -598,6 +617,7 @@ int lgsr_ref_backward(const lgsr_ref_map *map, const double pose[12], const lgsr
     }
     for (int c = 0; c < 3; ++c) { d_pose[c] = pr[c]; d_pose[3 + c] = pw[c]; }
     free(S);
+    free(Q);
     free(order);
     free(Gs);
     return 0;
@@ -908,6 +928,8 @@ int lgsr_ref_contributors(const lgsr_ref_map *map, const double pose[12], const 
     if (!S || !order) { free(S); free(order); return -1; }
     setup_surfels(map, pose, prm, S);
     int64_t m = sort_surfels(S, map->n, order, NULL, NULL);
+    surf_t *Q = in_order(S, order, m);
+    if (!Q) { free(S); free(order); return -1; }
     int fail = 0;
 #pragma omp parallel
     {
@@ -922,7 +944,7 @@ int lgsr_ref_contributors(const lgsr_ref_map *map, const double pose[12], const 
             double d[3];
             ray_dir(beams, ray_ids ? ray_ids[i] : i, d);
             ray_t r;
-            render_ray(S, order, m, NULL, 0, d, prm, 0, &r, hits);
+            render_ray(Q, order, m, NULL, 0, d, prm, 0, &r, hits);
             count[i] = r.K;
             for (int64_t k = 0; k < r.K && k < cap; ++k) ids[i * cap + k] = hits[k].i;
         }
@@ -930,6 +952,7 @@ int lgsr_ref_contributors(const lgsr_ref_map *map, const double pose[12], const 
     }
     free(S);
     free(order);
+    free(Q);
     return fail ? -1 : 0;
 }
 

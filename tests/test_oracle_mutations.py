@@ -42,7 +42,7 @@ MUTATIONS = {
     "margin_ignores_alpha_max": ("margin = fmin(margin, rel_gap(aG, p->alpha_max));", "(void)0;"),
     "margin_ignores_T_min": ("if (want_extra) margin = fmin(margin, rel_gap(T, p->T_min));", "(void)0;"),
     "margin_ignores_centre_near": ("margin = fmin(margin, rel_gap(s->r, p->near));", "(void)0;"),
-    "margin_ignores_cut_surfels": ("if (passes_hit_tests(&S[cut[ci]], d, p))", "if (0)"),
+    "margin_ignores_cut_surfels": ("if (passes_hit_tests(&C[ci], d, p))", "if (0)"),
     "margin_absolute_gap": ("static double rel_gap(double x, double thr) { return fabs(x - thr) / fabs(thr); }",
                             "static double rel_gap(double x, double thr) { return fabs(x - thr); }"),
     "order_gap_to_first_contributor": ("        prev_r = s->r;\n", "        if (prev_r < 0) prev_r = s->r;\n"),
