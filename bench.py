@@ -28,7 +28,7 @@ METRIC = "rendered rays/s fwd+bwd @64×1024, 300k surfels; p50/p99 batched rende
 # test) and backward (transmittance recovery, dL/dalpha_hat, the clamp, and the gradients
 # w.r.t. the 13 record quantities).
 FLOPS_TEST = 41
-FLOPS_COMPOSITE_BWD = 53
+FLOPS_COMPOSITE_BWD = 65
 FLOPS_COMPOSITE_FWD = 13
 # MI355X float32 vector peak without packed (dual) float32 math: 256 CUs x 64 lanes x
 # 2 flops (FMA) x 2.4 GHz.  The published 157.3 TFLOP/s counts packed float32, which this

@@ -9,10 +9,13 @@
 // (sigma piecewise constant) the total U gradient is gU + gcu m, and with w = mu' x m
 //   dmu' = gc nt + (sigma/s0) (gU + gcu m) x na + (sigma/s1) bn x (gV + gcv m)
 //   dbn  = (sigma/s1) (gV x mu' - gcv w),   dna = (sigma/s0) (mu' x gU + gcu w)
-//   da'  = dna x n',   db' = n' x dbn,   dn' = sigma (gnt + gc mu') + a' x dna + dbn x b'
+//   da'  = dna x n',   db' = n' x dbn,
+//   dn'  = sigma (gnt + (r gcm - (nt.zeta) gci) m + gc zeta) + a' x dna + dbn x b',
+//   zeta = mu' - r m
 //   ds0  = -(gU.U + gcu cu) / s0,   ds1 = -(gV.V + gcv cv) / s1
 // (U is nearly perpendicular to m, so these forms avoid the cancellation that products with
-// the unsplit gradient would suffer), then world frame (multiply by R), the rotation columns
+// the unsplit gradient would suffer; gnt already holds the part of the hit-distance
+// derivative along d - m, and the terms in m and zeta the rest), then world frame (multiply by R), the rotation columns
 // (a, b, n) of the normalised quaternion and its normalisation, s~ = log s (Sec. 3.3) and
 // alpha = sigmoid(o).  Pose, right perturbation T Exp(xi): drho = -sum dmu', domega =
 // -sum(mu' x dmu' + a' x da' + b' x db' + n' x dn'); per-block partials are folded by one
@@ -74,7 +77,7 @@ __global__ __launch_bounds__(kChainThreads) void chain_kernel(SurfelPtrs S, cons
             const float gnt[3] = {x.x, x.y, x.z}, gc = x.w;
             const float gcu = y.x, gU[3] = {y.y, y.z, y.w};
             const float gcv = z.x, gV[3] = {z.y, z.z, z.w};
-            const float ga = zz.x;
+            const float ga = zz.x, gcm = zz.y, gci = zz.z;
             float mu[3] = {g.mh[0] + g.ml[0], g.mh[1] + g.ml[1], g.mh[2] + g.ml[2]};
             const float k0 = g.sigma / g.s0, k1 = g.sigma / g.s1;
             float gUt[3], gVt[3];
@@ -99,7 +102,14 @@ __global__ __launch_bounds__(kChainThreads) void chain_kernel(SurfelPtrs S, cons
             cross(g.n, gbn, gbv);
             cross(g.a, gna, t3);
             cross(gbn, g.b, t4);
-            for (int c = 0; c < 3; ++c) gnv[c] = g.sigma * (gnt[c] + gc * mu[c]) + t3[c] + t4[c];
+            // zeta = mu' - r m: mh - r m rounded once (it is of the order of r times the
+            // roundoff of m), plus the low part of the centre
+            float zeta[3];
+            for (int c = 0; c < 3; ++c) zeta[c] = fmaf(-g.r, q.m[c], g.mh[c]) + g.ml[c];
+            const float ntz = fmaf(q.nt[0], zeta[0], fmaf(q.nt[1], zeta[1], q.nt[2] * zeta[2]));
+            const float cm = fmaf(gcm, g.r, -gci * ntz);
+            for (int c = 0; c < 3; ++c)
+                gnv[c] = g.sigma * fmaf(gc, zeta[c], fmaf(cm, q.m[c], gnt[c])) + t3[c] + t4[c];
             const float gs0 = -fmaf(gcu, q.cu, gU[0] * q.U[0] + gU[1] * q.U[1] + gU[2] * q.U[2]) / g.s0;
             const float gs1 = -fmaf(gcv, q.cv, gV[0] * q.V[0] + gV[1] * q.V[1] + gV[2] * q.V[2]) / g.s1;
             // world frame

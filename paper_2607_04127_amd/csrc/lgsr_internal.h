@@ -38,7 +38,7 @@ constexpr int kShards = 8;
 constexpr int kShardShift = 10;
 __host__ __device__ __forceinline__ int shard_of(int64_t i) { return (int)((i >> kShardShift) & (kShards - 1)); }
 constexpr int kGrad = 16;      // floats per surfel record-gradient slot (kGradUsed used)
-constexpr int kGradUsed = 13;
+constexpr int kGradUsed = 15;
 constexpr uint32_t kCulledKey = 0x7FFFFFFFu;  // depth key of a surfel that renders nothing
 
 // Record layout (float index).
@@ -57,7 +57,17 @@ enum : int {
 // Record gradients.  u = (cu + U.(d - m)) / den is differentiated in that split: G_CU
 // accumulates dL/dnu and G_U the vector dL/dnu (d - m), so that the chain rule meets U only
 // through products that do not cancel (U is nearly perpendicular to m, and the rays near m).
-enum : int { G_NT = 0, G_C = 3, G_CU = 4, G_U = 5, G_CV = 8, G_V = 9, G_ALPHA = 12 };
+// Likewise the hit distance t = c / den: its derivative in nt is -g delta, g = dL/dc =
+// (dL/dt) / den, delta = t d - mu'.  With the record's rounded m, zeta = mu' - r m (about r
+// times the float32 unit roundoff) and e = d - m,
+//   delta = t e + (t - r) m - zeta,   t - r = (nt.zeta - r nt.e) / den,
+// so G_NT takes -g t e per hit, G_CM the sum of g (nt.e) / den and G_CI the sum of g / den,
+// and the chain adds (r G_CM - (nt.zeta) G_CI) m + G_C zeta.  Forming -g t d per hit and
+// adding G_C mu' once per surfel instead would cancel two terms of size r to one of size
+// |delta|, and treating m as exactly mu' / r would leave an error of g |zeta|: both are
+// r / |delta| times the roundoff, large for a far, small surfel hit near its centre.  G_C
+// (dL/dc) also carries the centre gradient.
+enum : int { G_NT = 0, G_C = 3, G_CU = 4, G_U = 5, G_CV = 8, G_V = 9, G_ALPHA = 12, G_CM = 13, G_CI = 14 };
 
 struct Pose {
     float r[9];  // row-major rotation sensor -> world

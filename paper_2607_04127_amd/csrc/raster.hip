@@ -26,8 +26,8 @@
 // + gA~ S_A) set up per ray beforehand, and T_j recovered as T_{j+1} / (1 - alpha_hat_j)
 // from the bit-identical recomputed alpha_hat_j.  The per-(ray, surfel) gradient w.r.t.
 // the record quantities (nt, c, cu, U, cv, V, alpha; U and V split along m as the record
-// splits them) is summed over the wave and added with one vector atomic (13 lanes) per
-// surfel and wave.
+// splits them; and the hit-distance terms along m) is summed over the wave and added with
+// one vector atomic (15 lanes) per surfel and wave.
 #include "lgsr_internal.h"
 #include "lgsr_kernels.h"
 
@@ -681,7 +681,7 @@ __global__ __launch_bounds__(64) void raster_bwd_chunk_kernel(
             const Rec s = staged_rec(ws, i);
             // every lane tests; the wave goes on only if some lane composites this entry, and
             // then runs the composite arithmetic on full waves, keeping its results (the
-            // recurrence of T and B, the 13 gradient values) on the contributing lanes only
+            // recurrence of T and B, the 15 gradient values) on the contributing lanes only
             const Hit h = hit_test(s, ray, p);
             const bool contrib = pos <= last && h.pass;
             if (!__any(contrib)) continue;
@@ -702,12 +702,17 @@ __global__ __launch_bounds__(64) void raster_bwd_chunk_kernel(
             const float u = h.nu * h.inv, v = h.nv * h.inv;
             const float du = 2.f * u * dq2, dv = 2.f * v * dq2;
             const float dnu = du * h.inv, dnv = dv * h.inv;
-            const float dden = -fmaf(du, u, fmaf(dv, v, dt * h.t)) * h.inv;
+            // dL/dden through u and v; the path through t goes along e and into G_CM
+            const float dduv = -fmaf(du, u, dv * v) * h.inv;
+            const float gc = dt * h.inv, gte = gc * h.t, gci = gc * h.inv;
+            const float nte = fmaf(s.nt0, h.e[0], fmaf(s.nt1, h.e[1], s.nt2 * h.e[2]));
             float gv[16];
-            gv[G_NT + 0] = fmaf(gbN0, w, dden * ray.dh[0]);
-            gv[G_NT + 1] = fmaf(gbN1, w, dden * ray.dh[1]);
-            gv[G_NT + 2] = fmaf(gbN2, w, dden * ray.dh[2]);
-            gv[G_C] = dt * h.inv;
+            gv[G_NT + 0] = fmaf(gbN0, w, fmaf(dduv, ray.dh[0], -gte * h.e[0]));
+            gv[G_NT + 1] = fmaf(gbN1, w, fmaf(dduv, ray.dh[1], -gte * h.e[1]));
+            gv[G_NT + 2] = fmaf(gbN2, w, fmaf(dduv, ray.dh[2], -gte * h.e[2]));
+            gv[G_C] = gc;
+            gv[G_CM] = gci * nte;
+            gv[G_CI] = gci;
             gv[G_CU] = dnu;
             gv[G_U + 0] = dnu * h.e[0];
             gv[G_U + 1] = dnu * h.e[1];

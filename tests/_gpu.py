@@ -146,6 +146,10 @@ def _grad_rows(g, g_ref, mass, rel, floor, per_row):
     floor_rows = ~bad & (err > rel * norm + 1e-30)
     gf, rf = g.reshape(-1), g_ref.reshape(-1)
     cos = float(gf @ rf / (np.linalg.norm(gf) * np.linalg.norm(rf) + 1e-300))
-    return dict(bad=int(bad.sum()), cos=cos, worst=float((err / np.maximum(bound, 1e-300)).max(initial=0)),
+    ratio = err / np.maximum(bound, 1e-300)
+    w = int(np.argmax(ratio)) if ratio.size else -1
+    worst_row = None if w < 0 else dict(row=w, g=g[w].tolist(), g_ref=g_ref[w].tolist(), scale=float(scale[w]),
+                                        bound=float(bound[w]))
+    return dict(bad=int(bad.sum()), cos=cos, worst=float(ratio.max(initial=0)),
                 floor_only=int(floor_rows.sum()), rows=int(g_ref.shape[0]), nrows=int(g_ref.shape[0]),
-                floor_rows=floor_rows)
+                floor_rows=floor_rows, worst_row=worst_row, bad_rows=np.flatnonzero(bad)[:8].tolist())
