@@ -153,21 +153,57 @@ static surf_t *in_order(const surf_t *S, const int64_t *ids, int64_t m)
     return Q;
 }
 
-/* Whether ray d passes every per-hit test of surfel s (R1, R4, R11), ignoring the centre
- * range; used only for the margin of the centre-range decision. */
-static int passes_hit_tests(const surf_t *s, const double *d, const lgsr_ref_params *p)
+/* One surfel's per-hit tests on ray d (R1, R4, R11): the hit quantities, whether each test
+ * accepts (|n'.d| >= den_eps, t >= near, q2 <= k^2, alpha_hat >= alpha_thr) and its relative
+ * gap to its threshold.  The Gaussian is evaluated where the support test accepts, or where
+ * its gap is below gap_below (a caller that needs the opacity test's gap of a surfel the
+ * support test rejects only when that gap could matter); otherwise G = 0. */
+typedef struct {
+    double den, t, delta[3], u, v, q2, G, aG, ahat;
+    int ok[4];
+    double gap[4];
+} eval_t;
+
+static double rel_gap(double x, double thr) { return fabs(x - thr) / fabs(thr); }
+
+static void eval_hit(const surf_t *s, const double *d, const lgsr_ref_params *p, double gap_below, eval_t *e)
 {
-    double den = dot3(s->n, d);
-    if (fabs(den) < p->den_eps) return 0;
-    double t = dot3(s->n, s->mu) / den;
-    if (t < p->near) return 0;
-    double delta[3];
-    for (int c = 0; c < 3; ++c) delta[c] = t * d[c] - s->mu[c];
-    double u = dot3(s->a, delta) / s->s0, v = dot3(s->b, delta) / s->s1;
-    double q2 = u * u + v * v;
-    if (q2 > p->cutoff_sigma * p->cutoff_sigma) return 0;
-    double aG = s->alpha * exp(-0.5 * q2);
-    return (aG < p->alpha_max ? aG : p->alpha_max) >= p->alpha_thr;
+    double k2 = p->cutoff_sigma * p->cutoff_sigma;
+    e->den = dot3(s->n, d);
+    e->t = dot3(s->n, s->mu) / e->den;
+    for (int c = 0; c < 3; ++c) e->delta[c] = e->t * d[c] - s->mu[c];
+    e->u = dot3(s->a, e->delta) / s->s0;
+    e->v = dot3(s->b, e->delta) / s->s1;
+    e->q2 = e->u * e->u + e->v * e->v;
+    e->G = (e->q2 <= k2 || rel_gap(e->q2, k2) < gap_below) ? exp(-0.5 * e->q2) : 0.0;
+    e->aG = s->alpha * e->G;
+    e->ahat = e->aG < p->alpha_max ? e->aG : p->alpha_max;
+    e->ok[0] = fabs(e->den) >= p->den_eps;
+    e->ok[1] = e->t >= p->near;
+    e->ok[2] = e->q2 <= k2;
+    e->ok[3] = e->ahat >= p->alpha_thr;
+    e->gap[0] = rel_gap(fabs(e->den), p->den_eps);
+    e->gap[1] = rel_gap(e->t, p->near);
+    e->gap[2] = rel_gap(e->q2, k2);
+    e->gap[3] = rel_gap(e->aG, p->alpha_thr);
+}
+
+static int accepted(const eval_t *e) { return e->ok[0] && e->ok[1] && e->ok[2] && e->ok[3]; }
+
+/* How far the tests' verdict on a surfel is from flipping: for an accepted surfel any one
+ * test crossing its threshold rejects it (the smallest gap); for a rejected one every test
+ * that rejects it has to cross (the largest of their gaps, an undefined gap counting as
+ * infinite). */
+static double flip_gap(const eval_t *e)
+{
+    int acc = accepted(e);
+    double g = acc ? INFINITY : 0.0;
+    for (int k = 0; k < 4; ++k) {
+        double x = isnan(e->gap[k]) ? INFINITY : e->gap[k];
+        if (acc) g = fmin(g, x);
+        else if (!e->ok[k]) g = fmax(g, x);
+    }
+    return g;
 }
 
 static void ray_dir(const lgsr_ref_beams *B, int64_t rid, double *d)
@@ -180,70 +216,61 @@ static void ray_dir(const lgsr_ref_beams *B, int64_t rid, double *d)
     d[2] = sp;
 }
 
-static double rel_gap(double x, double thr) { return fabs(x - thr) / fabs(thr); }
-
 /* Front-to-back compositing of one ray over every surfel (R1-R5).  Q[0 .. m) are the valid
  * surfels in compositing order and order[k] the id of Q[k]; C[0 .. n_cut) the surfels cut for
  * their centre range only.  When hits != NULL the composited hits are recorded in order
  * (capacity: the number of valid surfels).
- * margin: the smallest relative gap between a quantity and the threshold it was tested
- * against (|n'.d| vs den_eps, t vs near, q2 vs k^2, alpha G vs alpha_thr and alpha_max,
- * transmittance vs T_min, and the centre range vs near of every surfel the ray composites
- * or, among those cut for their centre range, every one whose hit tests it passes, listed
- * in cut[0 .. n_cut)); order_gap: the smallest relative gap between the centre ranges of
- * consecutive composited surfels.  A small value flags a ray whose result may legitimately
- * differ when computed in lower precision.  den_min: the smallest |n'.d| over the composited
- * hits (the ray/plane intersection amplifies errors of the plane normal by 1 / |n'.d|). */
+ * margin: the smallest relative distance by which some threshold decision would have to
+ * move to change the ray's result: for every surfel the ray reaches before it stops, how far
+ * the per-hit tests' verdict is from flipping (flip_gap); for a composited surfel also its
+ * alpha G against alpha_max, its centre range against `near` and the transmittance after it
+ * against T_min; for a surfel cut for its centre range, the largest of that range's gap and
+ * the gaps of the hit tests that reject it.  order_gap: the smallest relative gap between
+ * the centre ranges of consecutive composited surfels.  A small value flags a ray whose
+ * result may legitimately differ when computed in lower precision.  den_min: the smallest
+ * |n'.d| over the composited hits (the ray/plane intersection amplifies errors of the plane
+ * normal by 1 / |n'.d|). */
 static void render_ray(const surf_t *Q, const int64_t *order, int64_t m, const surf_t *C, int64_t n_cut,
                        const double *d, const lgsr_ref_params *p, int want_extra, ray_t *out, hit_t *hits)
 {
     double T = 1, A = 0, SD = 0, SN[3] = {0, 0, 0}, margin = INFINITY, order_gap = INFINITY;
     double den_min = INFINITY;
+    eval_t e;
     if (want_extra)
-        for (int64_t ci = 0; ci < n_cut; ++ci)
-            if (passes_hit_tests(&C[ci], d, p)) margin = fmin(margin, rel_gap(C[ci].r, p->near));
+        for (int64_t ci = 0; ci < n_cut; ++ci) {
+            eval_hit(&C[ci], d, p, INFINITY, &e);
+            double need = rel_gap(C[ci].r, p->near);
+            if (!accepted(&e)) need = fmax(need, flip_gap(&e));
+            margin = fmin(margin, need);
+        }
     int32_t K = 0, nh = 0;
     int stopped = 0;
-    double k2 = p->cutoff_sigma * p->cutoff_sigma, prev_r = -1;
+    double prev_r = -1;
     for (int64_t oi = 0; oi < m; ++oi) {
         const surf_t *s = &Q[oi];
-        double den = dot3(s->n, d);
-        if (want_extra && !stopped) margin = fmin(margin, rel_gap(fabs(den), p->den_eps));
-        if (fabs(den) < p->den_eps) continue;
-        double t = dot3(s->n, s->mu) / den;
-        if (want_extra && !stopped) margin = fmin(margin, rel_gap(t, p->near));
-        if (t < p->near) continue;
-        double delta[3];
-        for (int c = 0; c < 3; ++c) delta[c] = t * d[c] - s->mu[c];
-        double u = dot3(s->a, delta) / s->s0;
-        double v = dot3(s->b, delta) / s->s1;
-        double q2 = u * u + v * v;
-        if (want_extra && !stopped) margin = fmin(margin, rel_gap(q2, k2));
-        if (q2 > k2) continue;
-        double G = exp(-0.5 * q2);
-        double aG = s->alpha * G;
-        if (want_extra && !stopped) {
-            margin = fmin(margin, rel_gap(aG, p->alpha_thr));
-            margin = fmin(margin, rel_gap(aG, p->alpha_max));
-        }
-        double ahat = aG < p->alpha_max ? aG : p->alpha_max;
-        if (ahat < p->alpha_thr) continue;
+        /* a surfel the support test rejects with a gap of at least the margin so far cannot
+         * lower the margin, whatever its opacity test's gap: its Gaussian is not needed */
+        eval_hit(s, d, p, want_extra && !stopped ? margin : 0.0, &e);
+        if (want_extra && !stopped) margin = fmin(margin, flip_gap(&e));
+        if (!accepted(&e)) continue;
         nh++;
         if (stopped) {
             if (!want_extra) break;
             continue;
         }
+        double t = e.t, ahat = e.ahat;
         if (hits) {
             hit_t *h = &hits[K];
             h->i = order[oi];
-            h->t = t; h->u = u; h->v = v; h->G = G; h->aG = aG; h->ahat = ahat; h->T = T; h->den = den;
-            for (int c = 0; c < 3; ++c) h->delta[c] = delta[c];
+            h->t = t; h->u = e.u; h->v = e.v; h->G = e.G; h->aG = e.aG; h->ahat = ahat; h->T = T; h->den = e.den;
+            for (int c = 0; c < 3; ++c) h->delta[c] = e.delta[c];
         }
         if (want_extra && prev_r >= 0) order_gap = fmin(order_gap, rel_gap(s->r, prev_r));
         prev_r = s->r;
         if (want_extra) {
+            margin = fmin(margin, rel_gap(e.aG, p->alpha_max));
             margin = fmin(margin, rel_gap(s->r, p->near));
-            den_min = fmin(den_min, fabs(den));
+            den_min = fmin(den_min, fabs(e.den));
         }
         double w = T * ahat;
         A += w;

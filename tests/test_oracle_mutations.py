@@ -15,7 +15,7 @@ SRC = os.path.join(ROOT, "oracle", "lgsr_ref.c")
 # name -> (text in lgsr_ref.c, replacement)
 MUTATIONS = {
     # forward
-    "u_uses_minor_scale": ("double u = dot3(s->a, delta) / s->s0;", "double u = dot3(s->a, delta) / s->s1;"),
+    "u_uses_minor_scale": ("e->u = dot3(s->a, e->delta) / s->s0;", "e->u = dot3(s->a, e->delta) / s->s1;"),
     "transmittance_half_step": ("T *= (1 - ahat);", "T *= (1 - 0.5 * ahat);"),
     "depth_weight_is_T": ("SD += w * t;", "SD += T * t;"),
     "normal_not_normalised": ("for (int c = 0; c < 3; ++c) normal[3 * i + c] = r.SN[c] / r.A;",
@@ -26,29 +26,36 @@ MUTATIONS = {
     "quaternion_sign": ("a[1] = 2 * (x * y + w * z);", "a[1] = 2 * (x * y - w * z);"),
     "pose_transposed": ("o[j] = pose[j] * v[0] + pose[4 + j] * v[1] + pose[8 + j] * v[2];",
                         "o[j] = pose[4 * j] * v[0] + pose[4 * j + 1] * v[1] + pose[4 * j + 2] * v[2];"),
-    "alpha_not_clamped": ("double ahat = aG < p->alpha_max ? aG : p->alpha_max;", "double ahat = aG;"),
-    "faint_hits_kept": ("if (ahat < p->alpha_thr) continue;", "if (ahat < 0) continue;"),
+    "alpha_not_clamped": ("e->ahat = e->aG < p->alpha_max ? e->aG : p->alpha_max;", "e->ahat = e->aG;"),
+    "faint_hits_kept": ("e->ok[3] = e->ahat >= p->alpha_thr;", "e->ok[3] = e->ahat >= 0;"),
     "no_early_stop": ("if (T < p->T_min) {\n            stopped = 1;", "if (0) {\n            stopped = 1;"),
-    "gaussian_without_half": ("double G = exp(-0.5 * q2);", "double G = exp(-q2);"),
-    "no_support_cutoff": ("if (q2 > k2) continue;", "if (0) continue;"),
-    "hits_behind_near_kept": ("if (t < p->near) continue;", "if (t < 0) continue;"),
+    "gaussian_without_half": ("exp(-0.5 * e->q2)", "exp(-e->q2)"),
+    "no_support_cutoff": ("double k2 = p->cutoff_sigma * p->cutoff_sigma;\n    e->den", "double k2 = INFINITY;\n    e->den"),
+    "hits_behind_near_kept": ("e->ok[1] = e->t >= p->near;", "e->ok[1] = e->t >= 0;"),
     "depth_not_normalised": ("depth[i] = r.SD / r.A;", "depth[i] = r.SD;"),
     "drop_inverted": ("drop[i] = r.A < prm->drop_tau;", "drop[i] = r.A >= prm->drop_tau;"),
     # tie outputs (margin, order_gap) and the conditioning output den_min
-    "margin_ignores_den_eps": ("margin = fmin(margin, rel_gap(fabs(den), p->den_eps));", "(void)0;"),
-    "margin_ignores_hit_near": ("margin = fmin(margin, rel_gap(t, p->near));", "(void)0;"),
-    "margin_ignores_cutoff": ("margin = fmin(margin, rel_gap(q2, k2));", "(void)0;"),
-    "margin_ignores_alpha_thr": ("margin = fmin(margin, rel_gap(aG, p->alpha_thr));", "(void)0;"),
-    "margin_ignores_alpha_max": ("margin = fmin(margin, rel_gap(aG, p->alpha_max));", "(void)0;"),
+    "margin_ignores_den_eps": ("e->gap[0] = rel_gap(fabs(e->den), p->den_eps);", "e->gap[0] = INFINITY;"),
+    "margin_ignores_hit_near": ("e->gap[1] = rel_gap(e->t, p->near);", "e->gap[1] = INFINITY;"),
+    "margin_ignores_cutoff": ("e->gap[2] = rel_gap(e->q2, k2);", "e->gap[2] = INFINITY;"),
+    "margin_ignores_alpha_thr": ("e->gap[3] = rel_gap(e->aG, p->alpha_thr);", "e->gap[3] = INFINITY;"),
+    "margin_ignores_alpha_max": ("margin = fmin(margin, rel_gap(e.aG, p->alpha_max));", "(void)0;"),
     "margin_ignores_T_min": ("if (want_extra) margin = fmin(margin, rel_gap(T, p->T_min));", "(void)0;"),
     "margin_ignores_centre_near": ("margin = fmin(margin, rel_gap(s->r, p->near));", "(void)0;"),
-    "margin_ignores_cut_surfels": ("if (passes_hit_tests(&C[ci], d, p))", "if (0)"),
+    "margin_ignores_cut_surfels": ("margin = fmin(margin, need);", "(void)0;"),
+    "margin_cut_surfels_only_when_accepted": ("if (!accepted(&e)) need = fmax(need, flip_gap(&e));",
+                                              "if (!accepted(&e)) need = INFINITY;"),
+    "margin_rejected_surfel_smallest_gap": ("else if (!e->ok[k]) g = fmax(g, x);",
+                                            "else if (!e->ok[k]) g = g == 0.0 ? x : fmin(g, x);"),
+    "margin_every_gap_of_every_surfel": ("else if (!e->ok[k]) g = fmax(g, x);",
+                                         "else g = g == 0.0 ? x : fmin(g, x);"),
+    "margin_rejected_surfels_ignored": ("else if (!e->ok[k]) g = fmax(g, x);", "else g = INFINITY;"),
     "margin_absolute_gap": ("static double rel_gap(double x, double thr) { return fabs(x - thr) / fabs(thr); }",
                             "static double rel_gap(double x, double thr) { return fabs(x - thr); }"),
     "order_gap_to_first_contributor": ("        prev_r = s->r;\n", "        if (prev_r < 0) prev_r = s->r;\n"),
     "order_gap_absolute": ("order_gap = fmin(order_gap, rel_gap(s->r, prev_r));",
                            "order_gap = fmin(order_gap, fabs(s->r - prev_r));"),
-    "den_min_signed": ("den_min = fmin(den_min, fabs(den));", "den_min = fmin(den_min, den);"),
+    "den_min_signed": ("den_min = fmin(den_min, fabs(e.den));", "den_min = fmin(den_min, e.den);"),
     # loss
     "normal_loss_gradient_unprojected": (
         "for (int c = 0; c < 3; ++c) g_normal[3 * i + c] = f * (N[c] - cosv * Nh[c] / nn);",

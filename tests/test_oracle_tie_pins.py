@@ -14,6 +14,12 @@ is known in closed form:
 * |n'.d| at a stated distance from den_eps (normal from scipy's rotation);
 * a hit range t and a centre range r at a stated distance from `near`, each on its own,
   both for a surfel that is rendered and for one cut for its centre range;
+* surfels rejected by several tests, one of them marginally: only a decision that could
+  change which surfels the ray composites counts, so a rejected surfel is as far from
+  flipping as the largest gap among the tests that reject it (a surfel the ray crosses at
+  t = near but 20 sigma from its centre, or at the 3-sigma edge but too faint there, is no
+  tie; a surfel cut for its centre range whose hit tests reject it counts with the larger
+  gap);
 * three contributors at known relative range gaps (order_gap is the smallest gap between
   consecutive contributors in compositing order);
 * den_min, the smallest |n'.d| over a ray's contributors, of a tilted surfel.
@@ -175,6 +181,55 @@ def test_margin_centre_near(ref, delta):
     r = float(np.linalg.norm(S["means"][0]))
     o = _one(ref, S, ray)
     assert o["K"] == (1 if delta > 0 else 0)
+    assert o["margin"] == pytest.approx(_rel(r, F32["near"]), rel=1e-6)
+
+
+@pytest.mark.parametrize("delta", [4e-6, -4e-6])
+def test_margin_rejected_surfel_takes_largest_gap(ref, delta):
+    """A neighbouring ray meets a head-on surfel of opacity 0.2 at q^2 = 9 (1 + delta): at the
+    3-sigma edge alpha G is about 0.0022, well under alpha_thr, so the surfel is rejected on
+    either side of the support threshold and the margin is the opacity test's gap (0.43)."""
+    ray = I0 + 2
+    F = U.frame_facing(-D0, spin=0.3)
+    _, q2_unit = _q2_on_ray(10 * D0, F, (1.0, 1.0), D[ray])
+    s = math.sqrt(q2_unit / (9 * (1 + delta)))
+    S = U.surfels([10 * D0], [F], [(s, s)], [0.2])
+    frame = U.rot_of_wxyz(S["quats"][0])
+    _, q2 = _q2_on_ray(S["means"][0], frame, np.exp(S["log_scales"][0]), D[ray])
+    assert _rel(q2, 9.0) < 1e-5
+    aG = _sigmoid(float(S["opacity_logits"][0])) * math.exp(-0.5 * q2)
+    o = _one(ref, S, ray)
+    assert o["K"] == 0
+    assert o["margin"] == pytest.approx(_rel(aG, F32["alpha_thr"]), rel=1e-6)
+    assert o["margin"] > 0.4
+
+
+@pytest.mark.parametrize("delta", [1e-6, -1e-6])
+def test_margin_far_surfel_crossed_near_the_sensor(ref, delta):
+    """A surfel 3 m out whose plane a ray ten columns over crosses at t = 0.2 (1 + delta),
+    20 sigma from its centre (q^2 = 400): the support test rejects it by a wide margin, so
+    the hit-range decision next to `near` does not count and the margin is the largest gap
+    of the rejecting tests, that of q^2 against 9."""
+    ray = I0 + 10
+    S = _plane_through(3.0 * D0, F32["near"] * (1 + delta) * D[ray], scale_factor=0.05)
+    frame = U.rot_of_wxyz(S["quats"][0])
+    t, q2 = _q2_on_ray(S["means"][0], frame, np.exp(S["log_scales"][0]), D[ray])
+    assert _rel(t, F32["near"]) < 2e-6 and q2 == pytest.approx(400.0, rel=1e-9)
+    o = _one(ref, S, ray)
+    assert o["K"] == 0
+    assert o["margin"] == pytest.approx(_rel(q2, 9.0), rel=1e-6)
+
+
+def test_margin_cut_surfel_rejected_by_its_hit_tests(ref):
+    """A surfel with its centre at 0.1 m (cut: 0.5 from `near`) whose plane a ray meets at
+    q^2 = 4 with alpha G 1e-5 under alpha_thr: to render it both decisions would have to
+    flip, so the margin is the larger gap, the centre range's."""
+    ray = I0 + 10
+    S = _plane_through(0.1 * D0, 0.3 * D[ray])
+    S["opacity_logits"][:] = _logit(F32["alpha_thr"] * (1 - 1e-5) * math.exp(2.0))
+    r = float(np.linalg.norm(S["means"][0]))
+    o = _one(ref, S, ray)
+    assert o["K"] == 0
     assert o["margin"] == pytest.approx(_rel(r, F32["near"]), rel=1e-6)
 
 
