@@ -336,7 +336,7 @@ enum {
     LGSR_STAGE_TILE_SORT = 4,  /* each tile list by (range, index) */
     LGSR_STAGE_RASTER_FWD = 5, /* forward compositing: chunk list, chunks, merge, fix-up */
     LGSR_STAGE_LOSS = 6,       /* loss and its per-ray gradient */
-    LGSR_STAGE_BWD_PREP = 7,   /* clearing the record gradients, per-ray backward set-up */
+    LGSR_STAGE_BWD_PREP = 7,   /* clearing the record gradients (after a new allocation only) */
     LGSR_STAGE_RASTER_BWD = 8, /* backward compositing */
     LGSR_STAGE_CHAIN = 9,      /* parameter and pose gradients */
     LGSR_NUM_STAGES = 10

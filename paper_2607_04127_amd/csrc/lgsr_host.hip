@@ -107,7 +107,7 @@ struct lgsr_state {
 struct Lane {
     hipStream_t stream = nullptr;  // lane 0: the context's stream
     bool own = false;              // created by the context (lanes 1..)
-    DevBuf recgrad, partials, pose_partials, gb0, gb1;
+    DevBuf recgrad, partials, pose_partials;
     bool recgrad_zero = false;  // every record-gradient slot is zero (the chain clears what it reads)
     hipEvent_t done = nullptr;  // joins a batch back into the context's stream
     std::vector<lgsr_state *> batch_states;  // per-request states of batches on this lane
@@ -228,7 +228,7 @@ void free_state_buffers(lgsr_state *s)
 
 void free_lane(Lane &L)
 {
-    release(L.recgrad); release(L.partials); release(L.pose_partials); release(L.gb0); release(L.gb1);
+    release(L.recgrad); release(L.partials); release(L.pose_partials);
     if (L.done) (void)hipEventDestroy(L.done);
     L.done = nullptr;
     if (L.own && L.stream) (void)hipStreamDestroy(L.stream);
@@ -287,7 +287,7 @@ size_t ctx_bytes(const lgsr_ctx *c)
 {
     size_t b = c->counters.cap + c->scan_slots.cap + state_bytes(&c->scratch_state);
     for (const Lane &L : c->lanes) {
-        b += L.recgrad.cap + L.partials.cap + L.pose_partials.cap + L.gb0.cap + L.gb1.cap;
+        b += L.recgrad.cap + L.partials.cap + L.pose_partials.cap;
         for (const lgsr_state *st : L.batch_states) b += state_bytes(st);
     }
     return b;
@@ -572,22 +572,19 @@ lgsr_status backward_impl(lgsr_ctx *ctx, Lane &L, lgsr_state *S, const lgsr_fram
     if (L.recgrad.cap < nn * kGrad * sizeof(float)) L.recgrad_zero = false;
     HIP_TRY(ensure(L.recgrad, nn * kGrad * sizeof(float)), "alloc record gradients");
     HIP_TRY(ensure(L.pose_partials, (size_t)chain_blocks(S->S.n) * 6 * sizeof(float)), "alloc pose partials");
-    const int64_t rays = (int64_t)S->g.H * S->g.W;
-    HIP_TRY(ensure(L.gb0, (size_t)rays * sizeof(float4)), "alloc backward state");
-    HIP_TRY(ensure(L.gb1, (size_t)rays * sizeof(float)), "alloc backward state");
     {
+    // only after a new allocation or a backward that did not finish: the chain clears the
+    // slots it reads
     Stage st_(ctx, LGSR_STAGE_BWD_PREP, s);
     if (!L.recgrad_zero)
         HIP_TRY(launch_fill_u32(as<uint32_t>(L.recgrad), 0u, (int64_t)(L.recgrad.cap / sizeof(uint32_t)), s),
                 "zero record gradients");
     L.recgrad_zero = false;
-    HIP_TRY(launch_raster_bwd_prep(S->R, S->g, gin->d_depth, gin->d_opacity, gin->d_normal, as<float4>(L.gb0),
-                                   as<float>(L.gb1), s),
-            "backward set-up");
     }
     {
     Stage st_(ctx, LGSR_STAGE_RASTER_BWD, s);
-    HIP_TRY(launch_raster_bwd(S->R, S->g, S->prm, as<float4>(L.gb0), as<float>(L.gb1), as<float>(L.recgrad), s),
+    HIP_TRY(launch_raster_bwd(S->R, S->g, S->prm, gin->d_depth, gin->d_opacity, gin->d_normal,
+                              as<float>(L.recgrad), s),
             "raster backward");
     }
     Stage st_(ctx, LGSR_STAGE_CHAIN, s);
@@ -1120,8 +1117,7 @@ lgsr_status lgsr_request_bytes(int64_t n, int32_t H, int32_t W, int64_t P, int32
                buf((size_t)(items > 0 ? 4 * items : 1) * sizeof(uint32_t));
     if (with_grad)
         b += buf((size_t)loss_blocks(rays) * 4 * sizeof(float)) + buf(nn * kGrad * sizeof(float)) +
-             buf((size_t)chain_blocks(n) * 6 * sizeof(float)) + buf((size_t)rays * sizeof(float4)) +
-             buf((size_t)rays * sizeof(float));
+             buf((size_t)chain_blocks(n) * 6 * sizeof(float));
     *bytes = (int64_t)b;
     return LGSR_OK;
 }

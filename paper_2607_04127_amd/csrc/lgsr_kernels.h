@@ -77,7 +77,8 @@ struct RasterBufs {
     uint32_t *n_items;     // device counter
     float *slots;          // chunk_slot_floats(items_max)
     float4 *st0, *st1;     // per ray
-    float4 *fixA, *fixB;   // per ray
+    float4 *fixA, *fixB;   // per ray: the merge's fix-up record; after the fix-up, the
+                           // sums of the chunk it re-walked (fixB.w: that chunk, or -1)
     uint32_t *fixflag;     // 4 x items_max, per (chunk, sub-tile): nonzero when a ray's fix-up
                            // falls there; zero between forwards (the fix-up clears what the
                            // merge set)
@@ -108,8 +109,6 @@ int64_t chunk_items_max(int64_t P, int T, int seg);
 size_t chunk_slot_floats(int64_t items_max);
 hipError_t launch_raster_fwd(const RasterBufs &R, const Grid &g, const RasterParams &p, float *depth,
                              float *opacity, float *normal, uint8_t *drop, hipStream_t s);
-hipError_t launch_raster_bwd_prep(const RasterBufs &R, const Grid &g, const float *gD, const float *gA,
-                                  const float *gN, float4 *gb0, float *gb1, hipStream_t s);
 // out (u64, device) += ray tests needed up to each wave's last contributor (query only)
 hipError_t launch_work_needed(const RasterBufs &R, const Grid &g, const RasterParams &p, unsigned long long *out,
                               hipStream_t s);
@@ -117,8 +116,10 @@ hipError_t launch_work_needed(const RasterBufs &R, const Grid &g, const RasterPa
 // termination; out[1] = rays with at least one (query only)
 hipError_t launch_count_hits(const RasterBufs &R, const Grid &g, const RasterParams &p, unsigned long long *out,
                              hipStream_t s);
-hipError_t launch_raster_bwd(const RasterBufs &R, const Grid &g, const RasterParams &p, const float4 *gb0,
-                             const float *gb1, float *recgrad, hipStream_t s);
+// record gradients += the backward of the raster for per-ray upstream gradients gD, gA (per
+// ray) and gN (3 per ray)
+hipError_t launch_raster_bwd(const RasterBufs &R, const Grid &g, const RasterParams &p, const float *gD,
+                             const float *gA, const float *gN, float *recgrad, hipStream_t s);
 
 // ---- loss.hip ----
 int loss_blocks(int64_t n_rays);

@@ -21,10 +21,13 @@
 // aligned on list position, each lane acting only on its own contributors):
 //   gD~ = gD / A, gN~ = gN / A, gA~ = gA - (gD depth + gN . normal) / A,
 //   c_j = gD~ t_j + gN~ . nt_j + gA~,  B_j = sum_{i > j} w_i c_i (global weights),
-//   dL/dalpha_hat_j = T_j c_j - B_j / (1 - alpha_hat_j),
-// with the chunk's end transmittance and its B (the later chunks' sums gD~ S_D + gN~ . S_N
-// + gA~ S_A) set up per ray beforehand, and T_j recovered as T_{j+1} / (1 - alpha_hat_j)
-// from the bit-identical recomputed alpha_hat_j.  The per-(ray, surfel) gradient w.r.t.
+//   dL/dalpha_hat_j = T_j c_j - B_j / (1 - alpha_hat_j).
+// B at the end of a chunk is gD~ S_D + gN~ . S_N + gA~ S_A over the later chunks' sums: the
+// merge leaves those suffix sums per (chunk, ray) (all but the sums of the chunk a fix-up
+// re-walks, which the fix-up leaves per ray), so each backward task forms its B from the
+// upstream gradient directly and no set-up pass runs between the loss and the backward.
+// T_j is recovered as T_{j+1} / (1 - alpha_hat_j) from the bit-identical recomputed
+// alpha_hat_j.  The per-(ray, surfel) gradient w.r.t.
 // the record quantities (nt, c, cu, U, cv, V, alpha; U and V split along m as the record
 // splits them; and the hit-distance terms along m) is summed over the wave and added with
 // one vector atomic (15 lanes) per surfel and wave.
@@ -34,10 +37,12 @@
 namespace lgsr {
 
 // Per (chunk, ray) slot fields; slot(item, f, rt) with rt = wave * 64 + lane.  The forward
-// writes F_TEND, F_LAST and F_K for every chunk and ray; the sums, their merged (global)
-// values and B are written only where the chunk has a contributor for the ray (F_K > 0),
-// since nothing reads them otherwise.
-enum : int { F_TEND = 0, F_SA, F_SD, F_SN0, F_SN1, F_SN2, F_LAST, F_K, F_B, kSlotFields };
+// writes F_TEND, F_LAST and F_K for every chunk and ray, and the chunk's local sums F_SA ..
+// F_SN2 only where the chunk has a contributor for the ray (F_K > 0), since nothing reads
+// them otherwise.  The merge turns F_TEND into the global transmittance and, where the
+// chunk keeps a contributor (F_LAST >= 0), F_SA .. F_SN2 into the sums of all later chunks
+// of the tile in global weights (the fix-up chunk's aside).
+enum : int { F_TEND = 0, F_SA, F_SD, F_SN0, F_SN1, F_SN2, F_LAST, F_K, kSlotFields };
 
 __device__ __forceinline__ size_t slot(uint32_t item, int f, int rt)
 {
@@ -246,13 +251,15 @@ __device__ __forceinline__ void write_ray(const Lane &L, const Grid &g, const Ra
 }
 
 // One workgroup per tile: combine the chunks of every ray in list order (slots become
-// global: end transmittance and sums in global weights), detect termination in a later
-// chunk (-> fix-up record) and write the frame for rays that need no fix-up.  The tile's
-// chunks are split into kMergeGroups runs handled side by side, 256 threads (one per ray)
-// each: first the product of each run's chunk transmittances (a chunk's transmittance is
-// exactly 1 for a ray it does not touch), which gives every run its exact incoming
-// transmittance; then each run walks its chunks from there; then one pass per ray joins
-// the runs' sums in order up to the first run in which the ray terminates.
+// global: end transmittance, and the sums of the later chunks in global weights), detect
+// termination in a later chunk (-> fix-up record) and write the frame for rays that need
+// no fix-up.  The tile's chunks are split into kMergeGroups runs handled side by side, 256
+// threads (one per ray) each: first the product of each run's chunk transmittances (a
+// chunk's transmittance is exactly 1 for a ray it does not touch), which gives every run
+// its exact incoming transmittance; then each run walks its chunks from there; then each
+// run walks its chunks back from the later runs' sums, leaving every contributing chunk the
+// sums behind it, and one pass per ray joins the runs' sums in order up to the first run in
+// which the ray terminates.
 constexpr int kMergeGroups = 4;  // at most; the launch picks 1 or 4 (blockDim.x / 256)
 constexpr int kMergeThreads = 256 * kMergeGroups;
 
@@ -306,8 +313,12 @@ __device__ __forceinline__ void merge_tile(const uint32_t *__restrict__ chunk_ba
     float T = 1.f, A = 0.f, SD = 0.f, SN0 = 0.f, SN1 = 0.f, SN2 = 0.f;
     int K = 0, fix = -1;
     for (int q = 0; q < grp; ++q) T *= P_of(q);
+    // a run of at most kB chunks keeps its chunks' global sums in v for step 4, with bit q of
+    // `kept` set where chunk r0 + q keeps a contributor
+    const bool one_batch = r1 - r0 <= (uint32_t)kB;
+    uint32_t kept = 0u;
+    float v[kB][7];
     for (uint32_t it0 = r0; it0 < r1 && L.valid; it0 += kB) {
-        float v[kB][7];
 #pragma unroll
         for (int q = 0; q < kB; ++q) {
             const uint32_t it = it0 + q;
@@ -339,11 +350,20 @@ __device__ __forceinline__ void merge_tile(const uint32_t *__restrict__ chunk_ba
             }
             const float gA = T * v[q][2], gD = T * v[q][3], g0 = T * v[q][4], g1 = T * v[q][5], g2 = T * v[q][6];
             slots[slot(it, F_TEND, L.rt)] = Tn;
-            slots[slot(it, F_SA, L.rt)] = gA;
-            slots[slot(it, F_SD, L.rt)] = gD;
-            slots[slot(it, F_SN0, L.rt)] = g0;
-            slots[slot(it, F_SN1, L.rt)] = g1;
-            slots[slot(it, F_SN2, L.rt)] = g2;
+            if (one_batch) {
+                v[q][2] = gA;
+                v[q][3] = gD;
+                v[q][4] = g0;
+                v[q][5] = g1;
+                v[q][6] = g2;
+                kept |= 1u << q;
+            } else {
+                slots[slot(it, F_SA, L.rt)] = gA;
+                slots[slot(it, F_SD, L.rt)] = gD;
+                slots[slot(it, F_SN0, L.rt)] = g0;
+                slots[slot(it, F_SN1, L.rt)] = g1;
+                slots[slot(it, F_SN2, L.rt)] = g2;
+            }
             A += gA;
             SD += gD;
             SN0 += g0;
@@ -362,8 +382,61 @@ __device__ __forceinline__ void merge_tile(const uint32_t *__restrict__ chunk_ba
     S_of(grp, 6) = __int_as_float(K);
     S_of(grp, 7) = __int_as_float(fix);
     __syncthreads();
-    // 3. join the runs in order
-    if (grp != 0 || !L.valid) return;
+    if (!L.valid) return;
+    // 3. every contributing chunk of the run gets the sums of all later chunks: the later runs'
+    // sums (zero past termination), then the run's own chunks walked backwards
+    {
+        float bA = 0.f, bD = 0.f, b0 = 0.f, b1 = 0.f, b2 = 0.f;
+        for (int q = grp + 1; q < ng; ++q) {
+            bA += S_of(q, 1);
+            bD += S_of(q, 2);
+            b0 += S_of(q, 3);
+            b1 += S_of(q, 4);
+            b2 += S_of(q, 5);
+        }
+        auto emit = [&](uint32_t it, const float (&c)[7]) {
+            slots[slot(it, F_SA, L.rt)] = bA;
+            slots[slot(it, F_SD, L.rt)] = bD;
+            slots[slot(it, F_SN0, L.rt)] = b0;
+            slots[slot(it, F_SN1, L.rt)] = b1;
+            slots[slot(it, F_SN2, L.rt)] = b2;
+            bA += c[2];
+            bD += c[3];
+            b0 += c[4];
+            b1 += c[5];
+            b2 += c[6];
+        };
+        if (one_batch) {
+#pragma unroll
+            for (int q = kB - 1; q >= 0; --q)
+                if (kept >> q & 1u) emit(r0 + q, v[q]);
+        } else {
+            for (uint32_t top = r1; top > r0;) {
+                const uint32_t lo = top - r0 > (uint32_t)kB ? top - kB : r0;
+#pragma unroll
+                for (int q = 0; q < kB; ++q) {
+                    const uint32_t it = top - 1 - q;
+                    if (it >= lo && it < top) {
+                        v[q][0] = slots[slot(it, F_LAST, L.rt)];
+                        v[q][2] = slots[slot(it, F_SA, L.rt)];
+                        v[q][3] = slots[slot(it, F_SD, L.rt)];
+                        v[q][4] = slots[slot(it, F_SN0, L.rt)];
+                        v[q][5] = slots[slot(it, F_SN1, L.rt)];
+                        v[q][6] = slots[slot(it, F_SN2, L.rt)];
+                    }
+                }
+#pragma unroll
+                for (int q = 0; q < kB; ++q) {
+                    const uint32_t it = top - 1 - q;
+                    if (it < lo || it >= top) break;
+                    if (__float_as_int(v[q][0]) >= 0) emit(it, v[q]);
+                }
+                top = lo;
+            }
+        }
+    }
+    // 4. join the runs in order
+    if (grp != 0) return;
     float aA = 0.f, aD = 0.f, a0 = 0.f, a1 = 0.f, a2 = 0.f, Tf = 1.f;
     int aK = 0, fx = -1;
     for (int q = 0; q < ng; ++q) {
@@ -407,8 +480,8 @@ __global__ __launch_bounds__(kMergeThreads) void raster_merge_kernel(const uint3
 __device__ __forceinline__ void fixup_task(
     const uint4 *__restrict__ chunks, const uint32_t *__restrict__ n_items, const uint32_t *__restrict__ ids,
     const float *__restrict__ recs, const uint2 *__restrict__ rects, const float *__restrict__ rows,
-    const float *__restrict__ cols, const Grid &g, const RasterParams &p, const float4 *__restrict__ fixA,
-    const float4 *__restrict__ fixB, float *__restrict__ slots, float *__restrict__ depth, float *__restrict__ opacity,
+    const float *__restrict__ cols, const Grid &g, const RasterParams &p, float4 *__restrict__ fixA,
+    float4 *__restrict__ fixB, float *__restrict__ slots, float *__restrict__ depth, float *__restrict__ opacity,
     float *__restrict__ normal, uint8_t *__restrict__ drop, float4 *__restrict__ st0, float4 *__restrict__ st1,
     uint32_t *__restrict__ fixflag, uint32_t b)
 {
@@ -432,22 +505,21 @@ __device__ __forceinline__ void fixup_task(
     composite(ws, ids, recs, rects, ch.y, ch.z, L, ray, p, g.W, pend, acc);
     if (!pend) return;
     slots[slot(item, F_TEND, L.rt)] = acc.T;
-    slots[slot(item, F_SA, L.rt)] = acc.A;
-    slots[slot(item, F_SD, L.rt)] = acc.SD;
-    slots[slot(item, F_SN0, L.rt)] = acc.SN0;
-    slots[slot(item, F_SN1, L.rt)] = acc.SN1;
-    slots[slot(item, F_SN2, L.rt)] = acc.SN2;
     slots[slot(item, F_LAST, L.rt)] = __int_as_float(acc.last);
     slots[slot(item, F_K, L.rt)] = __int_as_float(acc.K);
     write_ray(L, g, p, fa.y + acc.A, fa.z + acc.SD, fb.x + acc.SN0, fb.y + acc.SN1, fb.z + acc.SN2, acc.T,
               __float_as_int(fa.w) + acc.K, depth, opacity, normal, drop, st0, st1);
+    // the chunk's sums for the backward of the earlier chunks (nothing after it contributes);
+    // the chunk index stays in fixB.w
+    fixA[r] = make_float4(acc.A, acc.SD, acc.SN0, acc.SN1);
+    fixB[r] = make_float4(acc.SN2, 0.f, 0.f, __int_as_float((int)item));
 }
 
 __global__ __launch_bounds__(64) void raster_fixup_kernel(
     const uint4 *__restrict__ chunks, const uint32_t *__restrict__ n_items, const uint32_t *__restrict__ ids,
     const float *__restrict__ recs, const uint2 *__restrict__ rects, const float *__restrict__ rows,
-    const float *__restrict__ cols, Grid g, RasterParams p, const float4 *__restrict__ fixA,
-    const float4 *__restrict__ fixB, float *__restrict__ slots, float *__restrict__ depth, float *__restrict__ opacity,
+    const float *__restrict__ cols, Grid g, RasterParams p, float4 *__restrict__ fixA,
+    float4 *__restrict__ fixB, float *__restrict__ slots, float *__restrict__ depth, float *__restrict__ opacity,
     float *__restrict__ normal, uint8_t *__restrict__ drop, float4 *__restrict__ st0, float4 *__restrict__ st1,
     uint32_t *__restrict__ fixflag)
 {
@@ -495,94 +567,6 @@ __global__ __launch_bounds__(64) void raster_fixup_multi(FwdJobs J, RasterParams
 // ---------------------------------------------------------------------------------------
 // backward
 // ---------------------------------------------------------------------------------------
-
-// Per ray: effective upstream gradients and, per chunk, the suffix sum B of later chunks.
-// The tile's chunks are split into the same kMergeGroups runs as in the merge: each run sums
-// its chunks' contributions, then walks its chunks backwards from the sum of the later runs.
-__global__ __launch_bounds__(kMergeThreads) void raster_bwd_prep_kernel(const uint32_t *__restrict__ chunk_base, Grid g,
-                                                                        const float4 *__restrict__ st0,
-                                                                        const float4 *__restrict__ st1,
-                                                                        const float *__restrict__ gDp,
-                                                                        const float *__restrict__ gAp,
-                                                                        const float *__restrict__ gNp,
-                                                                        float *__restrict__ slots,
-                                                                        float4 *__restrict__ gb0,
-                                                                        float *__restrict__ gb1)
-{
-    __shared__ float S[kMergeGroups][256];
-    const int ng = (int)(blockDim.x >> 8);
-    const int tile = blockIdx.x;
-    const int t = (int)(threadIdx.x & 255u), grp = (int)(threadIdx.x >> 8);
-    const Lane L = lane_of(tile, g, t);
-    const int r = L.valid ? L.k * g.W + L.j : 0;
-    int K = 0;
-    float gbD = 0.f, gbN0 = 0.f, gbN1 = 0.f, gbN2 = 0.f, gbA = 0.f;
-    if (L.valid) {
-        const float4 a = st0[r], b = st1[r];
-        K = __float_as_int(b.w);
-        if (K > 0) {
-            const float iA = 1.f / a.x, D = a.y;
-            const float gd = gDp[r], ga = gAp[r];
-            const float gn0 = gNp[3 * r], gn1 = gNp[3 * r + 1], gn2 = gNp[3 * r + 2];
-            gbD = gd * iA;
-            gbN0 = gn0 * iA;
-            gbN1 = gn1 * iA;
-            gbN2 = gn2 * iA;
-            gbA = ga - (gd * D + gn0 * b.x + gn1 * b.y + gn2 * b.z) * iA;
-        }
-        if (grp == 0) {
-            gb0[r] = make_float4(gbD, gbN0, gbN1, gbN2);
-            gb1[r] = gbA;
-        }
-    }
-    const uint32_t c0 = chunk_base[tile], c1 = chunk_base[tile + 1];
-    uint32_t r0, r1;
-    run_bounds(c0, c1, grp, ng, r0, r1);
-    constexpr int kB = 8;  // chunks whose slots are loaded together (one memory latency per batch)
-    const bool live = L.valid && K > 0;
-    // the run's contributions, last chunk first (pass 0); then B from the later runs' sums (pass 1)
-    float B = 0.f;
-    float v[kB][6];
-    // a run of at most kB chunks is loaded once and kept in registers for both passes
-    const bool one_batch = r1 - r0 <= (uint32_t)kB;
-    auto load_batch = [&](uint32_t top, uint32_t lo) {
-#pragma unroll
-        for (int q = 0; q < kB; ++q) {
-            const uint32_t it = top - 1 - q;
-            if (live && it >= lo && it < top) {
-                v[q][0] = slots[slot(it, F_LAST, L.rt)];
-                v[q][1] = slots[slot(it, F_SA, L.rt)];
-                v[q][2] = slots[slot(it, F_SD, L.rt)];
-                v[q][3] = slots[slot(it, F_SN0, L.rt)];
-                v[q][4] = slots[slot(it, F_SN1, L.rt)];
-                v[q][5] = slots[slot(it, F_SN2, L.rt)];
-            }
-        }
-    };
-    if (one_batch) load_batch(r1, r0);
-    for (int pass = 0; pass < 2; ++pass) {
-        if (pass == 0 && grp == 0) continue;  // the first run's sum is read by no other run
-        if (pass == 1) {
-            if (ng > 1) __syncthreads();
-            B = 0.f;
-            for (int q = ng - 1; q > grp; --q) B += S[q][t];
-        }
-        for (uint32_t top = r1; top > r0;) {
-            const uint32_t lo = top - r0 > (uint32_t)kB ? top - kB : r0;
-            if (!one_batch) load_batch(top, lo);
-#pragma unroll
-            for (int q = 0; q < kB; ++q) {
-                const uint32_t it = top - 1 - q;
-                if (it < lo || it >= top) break;
-                if (!live || __float_as_int(v[q][0]) < 0) continue;  // B is read only with a contributor
-                if (pass == 1) slots[slot(it, F_B, L.rt)] = B;
-                B = fmaf(gbD, v[q][2], fmaf(gbN0, v[q][3], fmaf(gbN1, v[q][4], fmaf(gbN2, v[q][5], fmaf(gbA, v[q][1], B)))));
-            }
-            top = lo;
-        }
-        if (pass == 0) S[grp][t] = B;
-    }
-}
 
 // Wave-wide sums of 16 per-lane values by transposition: v_permlane32_swap folds lanes
 // 32-63 onto 0-31 for eight pairs (i, i + 8), v_permlane16_swap folds odd rows onto even rows
@@ -640,7 +624,9 @@ __global__ __launch_bounds__(64) void raster_bwd_chunk_kernel(
     const uint4 *__restrict__ chunks, const uint32_t *__restrict__ n_items, const uint32_t *__restrict__ ids,
     const float *__restrict__ recs, const uint2 *__restrict__ rects, const float *__restrict__ rows,
     const float *__restrict__ cols, Grid g, RasterParams p, const float *__restrict__ slots,
-    const float4 *__restrict__ gb0, const float *__restrict__ gb1, float *__restrict__ recgrad)
+    const float4 *__restrict__ st0, const float4 *__restrict__ st1, const float *__restrict__ gDp,
+    const float *__restrict__ gAp, const float *__restrict__ gNp, const float4 *__restrict__ fixA,
+    const float4 *__restrict__ fixB, float *__restrict__ recgrad)
 {
     __shared__ WaveStage ws;
     const uint32_t task = task_of(blockIdx.x), item = task >> 2;
@@ -653,15 +639,33 @@ __global__ __launch_bounds__(64) void raster_bwd_chunk_kernel(
     if (L.valid) {
         last = __float_as_int(slots[slot(item, F_LAST, L.rt)]);
         if (last >= 0) {
+            // effective upstream gradients of the ray, and B at the end of the chunk from the
+            // sums of the later chunks: the merge's suffix, plus the sums of a later chunk that
+            // a fix-up re-walked; the fix-up chunk itself is the ray's last (B = 0)
             const int r = L.k * g.W + L.j;
             T = slots[slot(item, F_TEND, L.rt)];
-            B = slots[slot(item, F_B, L.rt)];
-            const float4 q = gb0[r];
-            gbD = q.x;
-            gbN0 = q.y;
-            gbN1 = q.z;
-            gbN2 = q.w;
-            gbA = gb1[r];
+            float sA = slots[slot(item, F_SA, L.rt)], sD = slots[slot(item, F_SD, L.rt)];
+            float s0 = slots[slot(item, F_SN0, L.rt)], s1 = slots[slot(item, F_SN1, L.rt)];
+            float s2 = slots[slot(item, F_SN2, L.rt)];
+            const float4 a = st0[r], b = st1[r], fa = fixA[r], fb = fixB[r];
+            const float gd = gDp[r], ga = gAp[r];
+            const float gn0 = gNp[3 * r], gn1 = gNp[3 * r + 1], gn2 = gNp[3 * r + 2];
+            const float iA = 1.f / a.x;
+            gbD = gd * iA;
+            gbN0 = gn0 * iA;
+            gbN1 = gn1 * iA;
+            gbN2 = gn2 * iA;
+            gbA = ga - (gd * a.y + gn0 * b.x + gn1 * b.y + gn2 * b.z) * iA;
+            const int fx = __float_as_int(fb.w);
+            if ((int)item < fx) {
+                sA += fa.x;
+                sD += fa.y;
+                s0 += fa.z;
+                s1 += fa.w;
+                s2 += fb.x;
+            }
+            if ((int)item != fx)
+                B = fmaf(gbD, sD, fmaf(gbN0, s0, fmaf(gbN1, s1, fmaf(gbN2, s2, gbA * sA))));
         }
     }
     const int wmax = wave_max_i(last);
@@ -867,15 +871,6 @@ hipError_t launch_raster_fwd_multi(FwdJobs &J, const RasterParams &p, hipStream_
     return hipGetLastError();
 }
 
-hipError_t launch_raster_bwd_prep(const RasterBufs &R, const Grid &g, const float *gD, const float *gA,
-                                  const float *gN, float4 *gb0, float *gb1, hipStream_t s)
-{
-    if (g.T <= 0) return hipSuccess;
-    raster_bwd_prep_kernel<<<g.T, 256 * merge_groups(g.T), 0, s>>>(R.chunk_base, g, R.st0, R.st1, gD, gA, gN, R.slots,
-                                                                  gb0, gb1);
-    return hipGetLastError();
-}
-
 hipError_t launch_work_needed(const RasterBufs &R, const Grid &g, const RasterParams &p, unsigned long long *out,
                               hipStream_t s)
 {
@@ -892,13 +887,14 @@ hipError_t launch_count_hits(const RasterBufs &R, const Grid &g, const RasterPar
     return hipGetLastError();
 }
 
-hipError_t launch_raster_bwd(const RasterBufs &R, const Grid &g, const RasterParams &p, const float4 *gb0,
-                             const float *gb1, float *recgrad, hipStream_t s)
+hipError_t launch_raster_bwd(const RasterBufs &R, const Grid &g, const RasterParams &p, const float *gD,
+                             const float *gA, const float *gN, float *recgrad, hipStream_t s)
 {
     const int im = (int)R.items_max;
     if (g.T <= 0 || im <= 0) return hipSuccess;
     raster_bwd_chunk_kernel<<<task_blocks(im), 64, 0, s>>>(R.chunks, R.n_items, R.ids, R.recs, R.rects, R.rows,
-                                                           R.cols, g, p, R.slots, gb0, gb1, recgrad);
+                                                           R.cols, g, p, R.slots, R.st0, R.st1, gD, gA, gN, R.fixA,
+                                                           R.fixB, recgrad);
     return hipGetLastError();
 }
 
