@@ -386,9 +386,11 @@ __device__ __forceinline__ Rec load_rec(const float *__restrict__ recs, uint32_t
 // -log2(e) / 2: G = exp(-q2 / 2) = exp2(q2 * kNegHalfLog2e)
 constexpr float kNegHalfLog2e = -0.72134752044448170f;
 
-__device__ __forceinline__ Hit hit_test(const Rec &s, const Ray &ray, const RasterParams &p)
+// The hit test in two parts: the geometry (hit distance, footprint coordinates, and the
+// tests that need no Gaussian), then the opacity; a wave in which no lane passes the first
+// part can skip the second.  hit_test runs both, bit for bit as the two parts.
+__device__ __forceinline__ float hit_geom(Hit &h, const Rec &s, const Ray &ray, const RasterParams &p)
 {
-    Hit h;
     h.e[0] = (ray.dh[0] - s.m0) + ray.dl[0];
     h.e[1] = (ray.dh[1] - s.m1) + ray.dl[1];
     h.e[2] = ray.dh[2] - s.m2;
@@ -401,11 +403,25 @@ __device__ __forceinline__ Hit hit_test(const Rec &s, const Ray &ray, const Rast
     h.t = s.c * h.inv;
     float u = h.nu * h.inv, v = h.nv * h.inv;
     float q2 = fmaf(u, u, v * v);
+    // |den| >= den_eps, t >= near, q2 <= k^2
+    h.pass = (fabsf(h.den) >= p.den_eps) && (h.t >= p.near) && (q2 <= p.k2);
+    return q2;
+}
+
+// alpha_hat >= alpha_thr completes h.pass
+__device__ __forceinline__ void hit_opacity(Hit &h, float q2, const Rec &s, const RasterParams &p)
+{
     h.G = __builtin_amdgcn_exp2f(q2 * kNegHalfLog2e);
     h.aG = s.alpha * h.G;
     h.ah = fminf(h.aG, p.alpha_max);
-    // |den| >= den_eps, t >= near, q2 <= k^2, alpha_hat >= alpha_thr
-    h.pass = (fabsf(h.den) >= p.den_eps) && (h.t >= p.near) && (q2 <= p.k2) && (h.ah >= p.alpha_thr);
+    h.pass = h.pass && (h.ah >= p.alpha_thr);
+}
+
+__device__ __forceinline__ Hit hit_test(const Rec &s, const Ray &ray, const RasterParams &p)
+{
+    Hit h;
+    const float q2 = hit_geom(h, s, ray, p);
+    hit_opacity(h, q2, s, p);
     return h;
 }
 

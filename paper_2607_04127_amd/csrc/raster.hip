@@ -172,7 +172,10 @@ __device__ __forceinline__ void composite(WaveStage &ws, const uint32_t *__restr
                                       slot_id);
         for (uint32_t i = 0; i < m; ++i) {
             const Rec s = staged_rec(ws, i);
-            const Hit h = hit_test(s, ray, p);
+            Hit h;
+            const float q2 = hit_geom(h, s, ray, p);
+            if (!__any(h.pass && !done)) continue;  // no lane reaches the opacity test
+            hit_opacity(h, q2, s, p);
             if (h.pass && !done) {
                 float w = acc.T * h.ah;
                 acc.A += w;
@@ -686,7 +689,10 @@ __global__ __launch_bounds__(64) void raster_bwd_chunk_kernel(
             // every lane tests; the wave goes on only if some lane composites this entry, and
             // then runs the composite arithmetic on full waves, keeping its results (the
             // recurrence of T and B, the 15 gradient values) on the contributing lanes only
-            const Hit h = hit_test(s, ray, p);
+            Hit h;
+            const float q2 = hit_geom(h, s, ray, p);
+            if (!__any(pos <= last && h.pass)) continue;  // no lane reaches the opacity test
+            hit_opacity(h, q2, s, p);
             const bool contrib = pos <= last && h.pass;
             if (!__any(contrib)) continue;
             const float one_m = 1.f - h.ah;
@@ -698,22 +704,27 @@ __global__ __launch_bounds__(64) void raster_bwd_chunk_kernel(
             const float Bn = fmaf(w, cj, B);
             T = contrib ? Tj : T;
             B = contrib ? Bn : B;
-            const float dt = gbD * w;
-            // a clamped alpha_hat passes no gradient to alpha and G
-            const float dahc = h.aG < p.alpha_max ? dah : 0.f;
-            const float dalpha = dahc * h.G, dG = dahc * s.alpha;
-            const float dq2 = -0.5f * h.G * dG;
-            const float u = h.nu * h.inv, v = h.nv * h.inv;
+            // Lanes that do not composite this entry get zero weight, dL/dalpha_hat, G and 1/den,
+            // so every gradient value below is zero there (the other factors, the direction
+            // residual e, nu, nv and the record, are finite on every lane), without masking
+            // each of them.  A clamped alpha_hat passes no gradient to alpha and G.
+            const float wc = contrib ? w : 0.f;
+            const float dahc = contrib && h.aG < p.alpha_max ? dah : 0.f;
+            const float inv = contrib ? h.inv : 0.f, G = contrib ? h.G : 0.f;
+            const float dt = gbD * wc;
+            const float dalpha = dahc * G, dG = dahc * s.alpha;
+            const float dq2 = -0.5f * G * dG;
+            const float u = h.nu * inv, v = h.nv * inv, t = s.c * inv;
             const float du = 2.f * u * dq2, dv = 2.f * v * dq2;
-            const float dnu = du * h.inv, dnv = dv * h.inv;
+            const float dnu = du * inv, dnv = dv * inv;
             // dL/dden through u and v; the path through t goes along e and into G_CM
-            const float dduv = -fmaf(du, u, dv * v) * h.inv;
-            const float gc = dt * h.inv, gte = gc * h.t, gci = gc * h.inv;
+            const float dduv = -fmaf(du, u, dv * v) * inv;
+            const float gc = dt * inv, gte = gc * t, gci = gc * inv;
             const float nte = fmaf(s.nt0, h.e[0], fmaf(s.nt1, h.e[1], s.nt2 * h.e[2]));
             float gv[16];
-            gv[G_NT + 0] = fmaf(gbN0, w, fmaf(dduv, ray.dh[0], -gte * h.e[0]));
-            gv[G_NT + 1] = fmaf(gbN1, w, fmaf(dduv, ray.dh[1], -gte * h.e[1]));
-            gv[G_NT + 2] = fmaf(gbN2, w, fmaf(dduv, ray.dh[2], -gte * h.e[2]));
+            gv[G_NT + 0] = fmaf(gbN0, wc, fmaf(dduv, ray.dh[0], -gte * h.e[0]));
+            gv[G_NT + 1] = fmaf(gbN1, wc, fmaf(dduv, ray.dh[1], -gte * h.e[1]));
+            gv[G_NT + 2] = fmaf(gbN2, wc, fmaf(dduv, ray.dh[2], -gte * h.e[2]));
             gv[G_C] = gc;
             gv[G_CM] = gci * nte;
             gv[G_CI] = gci;
@@ -726,8 +737,6 @@ __global__ __launch_bounds__(64) void raster_bwd_chunk_kernel(
             gv[G_V + 1] = dnv * h.e[1];
             gv[G_V + 2] = dnv * h.e[2];
             gv[G_ALPHA] = dalpha;
-#pragma unroll
-            for (int c = 0; c < kGradUsed; ++c) gv[c] = contrib ? gv[c] : 0.f;
 #pragma unroll
             for (int c = kGradUsed; c < 16; ++c) gv[c] = 0.f;
             const float mine = wave_sum16(gv, L.lane);
@@ -820,10 +829,10 @@ __global__ __launch_bounds__(256) void count_hits_kernel(const uint32_t *__restr
 int chunk_size(int64_t P, int requested)
 {
     if (requested > 0) return requested;
-    // about 6144 chunks, 24576 one-wave tasks (several rounds of 8 resident waves on each of
+    // about 8192 chunks, 32768 one-wave tasks (several rounds of 8 resident waves on each of
     // 1024 SIMDs; short chunks also keep the re-walk of a terminating ray short), balanced
-    // against the per-chunk cost of the merge and the backward set-up; at most kChunkMax
-    int64_t s = (P + 6143) / 6144;
+    // against the per-chunk cost of the merge; at most kChunkMax
+    int64_t s = (P + 8191) / 8192;
     s = (s + 15) / 16 * 16;
     if (s < 32) s = 32;
     if (s > kChunkMax) s = kChunkMax;

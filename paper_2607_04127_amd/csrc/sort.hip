@@ -20,6 +20,7 @@ constexpr int kTsThreads = 1024;
 constexpr int kTsWaves = kTsThreads / 64;
 constexpr int kTsItems = 8;
 constexpr int kTsCap = kTsThreads * kTsItems;  // entries sorted without leaving the CU
+constexpr int kTileChunks = 64;  // most chunks of one tile's list in the raster
 constexpr int kDigitBits = 9;
 constexpr int kDigits = 1 << kDigitBits;
 constexpr int kRunMax = 16;  // longest run of equal range keys ordered in place
@@ -297,8 +298,10 @@ __device__ void sort_resident(TileSortSmem &sm, const uint32_t *__restrict__ key
     }
 }
 
-// The raster's work list (one workgroup): every tile's list cut into chunks of seg entries,
-// chunk q of tile t = (t, first, end); chunk_base[t] = index of the tile's first chunk,
+// The raster's work list (one workgroup): every tile's list cut into c = ceil(len / seg)
+// chunks of nearly equal length, at most kTileChunks (a longer list gets longer chunks:
+// the merge walks a tile's chunks in sequence, so its longest tile sets its time); chunk q
+// of tile t = (t, first, end); chunk_base[t] = index of the tile's first chunk,
 // chunk_base[T] = *n_items = the number of chunks.
 // Chunks at or beyond cap_items are not written (the host sizes the buffer before it uses
 // the list; a list built on too small a buffer is built again).
@@ -316,7 +319,7 @@ __device__ void build_chunks_block(const uint2 *__restrict__ ranges, int T, int 
         uint32_t c = 0;
         if (t < T) {
             r = ranges[t];
-            c = (r.y - r.x + (uint32_t)seg - 1u) / (uint32_t)seg;
+            c = min((r.y - r.x + (uint32_t)seg - 1u) / (uint32_t)seg, (uint32_t)kTileChunks);
         }
         uint32_t inc = c;
 #pragma unroll
@@ -335,9 +338,9 @@ __device__ void build_chunks_block(const uint2 *__restrict__ ranges, int T, int 
         const uint32_t first = carry + off + inc - c;
         if (t < T) {
             chunk_base[t] = first;
+            const uint64_t len = r.y - r.x;
             for (uint32_t q = 0; q < c; ++q) {
-                uint32_t a = r.x + q * (uint32_t)seg;
-                uint32_t b = min(r.y, a + (uint32_t)seg);
+                const uint32_t a = r.x + (uint32_t)(q * len / c), b = r.x + (uint32_t)((q + 1) * len / c);
                 if ((int64_t)first + q < cap_items) chunks[first + q] = make_uint4((uint32_t)t, a, b, 0u);
             }
         }
