@@ -78,7 +78,8 @@ struct lgsr_state {
     lgsr_ctx *ctx = nullptr;
     bool live = false;
     // forward products kept for the backward
-    DevBuf recs, rects, pk, pv, ranges, long_tiles, st0, st1, pose, chunks, chunk_base, slots, fixA, fixB, fixflag;
+    DevBuf recs, rects, pk, pv, ranges, long_tiles, st0, st1, pose, chunks, chunk_base, slots, fixA, fixB, fixflag,
+        kmask;
     bool fixflag_clean = false;  // every word of fixflag is zero (the fix-up clears what the merge sets)
     void *fixflag_seen = nullptr;
     // per-forward scratch: range keys, per-(tile, shard) counts and cursors, read-back words
@@ -219,6 +220,7 @@ void free_state_buffers(lgsr_state *s)
     release(s->ranges); release(s->st0); release(s->st1); release(s->pose);
     release(s->chunks); release(s->chunk_base); release(s->slots); release(s->fixA); release(s->fixB);
     release(s->fixflag);
+    release(s->kmask);
     release(s->keys); release(s->cnt); release(s->offs); release(s->counters);
     if (s->pinned) (void)hipHostFree(s->pinned);
     s->pinned = nullptr;
@@ -280,7 +282,7 @@ size_t state_bytes(const lgsr_state *s)
 {
     return s->recs.cap + s->rects.cap + s->pk.cap + s->pv.cap + s->long_tiles.cap + s->ranges.cap +
            s->st0.cap + s->st1.cap + s->pose.cap + s->chunks.cap + s->chunk_base.cap + s->slots.cap + s->fixA.cap +
-           s->fixB.cap + s->fixflag.cap + s->keys.cap + s->cnt.cap + s->offs.cap + s->counters.cap;
+           s->fixB.cap + s->fixflag.cap + s->kmask.cap + s->keys.cap + s->cnt.cap + s->offs.cap + s->counters.cap;
 }
 
 size_t ctx_bytes(const lgsr_ctx *c)
@@ -480,6 +482,7 @@ lgsr_status forward_lists(lgsr_ctx *ctx, lgsr_state *S, hipStream_t s)
     HIP_TRY(ensure(S->fixA, (size_t)rays * sizeof(float4)), "alloc ray state");
     HIP_TRY(ensure(S->fixB, (size_t)rays * sizeof(float4)), "alloc ray state");
     HIP_TRY(ensure(S->fixflag, (size_t)(items_max > 0 ? 4 * items_max : 1) * sizeof(uint32_t)), "alloc chunk flags");
+    HIP_TRY(ensure(S->kmask, (size_t)(items_max > 0 ? 4 * items_max : 1) * sizeof(uint64_t)), "alloc chunk masks");
     if (!(S->fixflag_clean && S->fixflag_seen == S->fixflag.p))
         HIP_TRY(launch_fill_u32(as<uint32_t>(S->fixflag), 0u, (int64_t)(S->fixflag.cap / 4), s), "clear chunk flags");
     S->fixflag_clean = false;  // until the raster below has run
@@ -525,6 +528,7 @@ lgsr_status forward_lists(lgsr_ctx *ctx, lgsr_state *S, hipStream_t s)
     R.fixA = as<float4>(S->fixA);
     R.fixB = as<float4>(S->fixB);
     R.fixflag = as<uint32_t>(S->fixflag);
+    R.kmask = as<uint64_t>(S->kmask);
     R.seg = seg;
     R.items_max = items_max;
     S->P = P;
@@ -1114,7 +1118,8 @@ lgsr_status lgsr_request_bytes(int64_t n, int32_t H, int32_t W, int64_t P, int32
                buf((size_t)T * 4) + buf(16) + buf(pp * 4 + pp) + buf(pp * 8) +
                buf((size_t)(items > 0 ? items : 1) * sizeof(uint4)) + buf((size_t)(T + 1) * sizeof(uint32_t)) +
                buf(chunk_slot_floats(items > 0 ? items : 1) * sizeof(float)) +
-               buf((size_t)(items > 0 ? 4 * items : 1) * sizeof(uint32_t));
+               buf((size_t)(items > 0 ? 4 * items : 1) * sizeof(uint32_t)) +
+               buf((size_t)(items > 0 ? 4 * items : 1) * sizeof(uint64_t));
     if (with_grad)
         b += buf((size_t)loss_blocks(rays) * 4 * sizeof(float)) + buf(nn * kGrad * sizeof(float)) +
              buf((size_t)chain_blocks(n) * 6 * sizeof(float));

@@ -67,6 +67,8 @@ hipError_t launch_work_counts(const uint2 *ranges, const uint32_t *ids, const ui
                               const float4 *st1, const Grid &g, unsigned long long *out, hipStream_t s);
 
 // ---- raster.hip ----
+// Most chunks one tile's list is cut into (the merge keeps a 64-bit set of chunks per ray).
+constexpr int kTileChunks = 64;
 struct RasterBufs {
     const uint32_t *ids;  // sorted pair surfel ids
     const float *recs;
@@ -82,6 +84,8 @@ struct RasterBufs {
     uint32_t *fixflag;     // 4 x items_max, per (chunk, sub-tile): nonzero when a ray's fix-up
                            // falls there; zero between forwards (the fix-up clears what the
                            // merge set)
+    uint64_t *kmask;       // 4 x items_max, per (chunk, sub-tile): the lanes whose ray has a
+                           // composite in the chunk (written by the forward chunk tasks)
     int seg;
     int64_t items_max;
 };

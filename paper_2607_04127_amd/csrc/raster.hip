@@ -96,6 +96,8 @@ __device__ __forceinline__ uint4 uniform_chunk(const uint4 *__restrict__ chunks,
 // grid is a multiple of 32 blocks.
 __device__ __forceinline__ uint32_t task_of(uint32_t b) { return (b >> 5) * 32u + (b & 7u) * 4u + ((b >> 3) & 3u); }
 
+static_assert(kTileChunks <= 64, "the merge keeps a run's chunks as the bits of a 64-bit word");
+
 constexpr int kTaskGroup = 32;
 static unsigned task_blocks(int items) { return (unsigned)(((int64_t)4 * items + kTaskGroup - 1) / kTaskGroup * kTaskGroup); }
 
@@ -198,17 +200,23 @@ __device__ __forceinline__ void composite(WaveStage &ws, const uint32_t *__restr
 __device__ __forceinline__ void fwd_chunk_task(
     const uint4 *__restrict__ chunks, const uint32_t *__restrict__ n_items, const uint32_t *__restrict__ ids,
     const float *__restrict__ recs, const uint2 *__restrict__ rects, const float *__restrict__ rows,
-    const float *__restrict__ cols, const Grid &g, const RasterParams &p, float *__restrict__ slots, uint32_t b)
+    const float *__restrict__ cols, const Grid &g, const RasterParams &p, float *__restrict__ slots,
+    uint64_t *__restrict__ kmask, uint32_t b)
 {
     __shared__ WaveStage ws;
     const uint32_t task = task_of(b), item = task >> 2;
     if (item >= *n_items) return;
     const uint4 ch = uniform_chunk(chunks, item);
     const Lane L = lane_of((int)ch.x, g, (int)((task & 3u) * 64u + threadIdx.x));
-    if (!L.wave_in) return;  // the sub-tile lies outside the image
+    if (!L.wave_in) {  // the sub-tile lies outside the image
+        if (threadIdx.x == 0) kmask[task] = 0ull;
+        return;
+    }
     Ray ray = make_ray(rows, cols, L.valid ? L.k : 0, L.valid ? L.j : 0);
     Acc acc{1.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0, -1};
     composite(ws, ids, recs, rects, ch.y, ch.z, L, ray, p, g.W, L.valid, acc);
+    const uint64_t km = __ballot(L.valid && acc.K > 0);
+    if (threadIdx.x == 0) kmask[task] = km;
     if (!L.valid) return;
     slots[slot(item, F_TEND, L.rt)] = acc.T;
     slots[slot(item, F_LAST, L.rt)] = __int_as_float(acc.last);
@@ -224,9 +232,9 @@ __device__ __forceinline__ void fwd_chunk_task(
 __global__ __launch_bounds__(64) void raster_fwd_chunk_kernel(
     const uint4 *__restrict__ chunks, const uint32_t *__restrict__ n_items, const uint32_t *__restrict__ ids,
     const float *__restrict__ recs, const uint2 *__restrict__ rects, const float *__restrict__ rows,
-    const float *__restrict__ cols, Grid g, RasterParams p, float *__restrict__ slots)
+    const float *__restrict__ cols, Grid g, RasterParams p, float *__restrict__ slots, uint64_t *__restrict__ kmask)
 {
-    fwd_chunk_task(chunks, n_items, ids, recs, rects, rows, cols, g, p, slots, blockIdx.x);
+    fwd_chunk_task(chunks, n_items, ids, recs, rects, rows, cols, g, p, slots, kmask, blockIdx.x);
 }
 
 __device__ __forceinline__ void write_ray(const Lane &L, const Grid &g, const RasterParams &p, float A, float SD,
@@ -287,11 +295,14 @@ __device__ __forceinline__ void merge_tile(const uint32_t *__restrict__ chunk_ba
                                            float *__restrict__ normal, uint8_t *__restrict__ drop,
                                            float4 *__restrict__ st0, float4 *__restrict__ st1,
                                            float4 *__restrict__ fixA, float4 *__restrict__ fixB,
-                                           uint32_t *__restrict__ fixflag, int tile)
+                                           uint32_t *__restrict__ fixflag, const uint64_t *__restrict__ kmask,
+                                           int tile)
 {
     extern __shared__ float msm[];  // ng runs x kMergeRunFloats
     const int ng = (int)(blockDim.x >> 8);
-    const int t = (int)(threadIdx.x & 255u), grp = (int)(threadIdx.x >> 8);
+    // a run is four whole waves, so its index is uniform in a wave (chunk loops and mask loads
+    // become scalar)
+    const int t = (int)(threadIdx.x & 255u), grp = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 8));
     const Lane L = lane_of(tile, g, t);
     const uint32_t c0 = chunk_base[tile], c1 = chunk_base[tile + 1];
     uint32_t r0, r1;
@@ -299,13 +310,29 @@ __device__ __forceinline__ void merge_tile(const uint32_t *__restrict__ chunk_ba
     auto P_of = [&](int q) -> float & { return msm[q * kMergeRunFloats + t]; };
     auto S_of = [&](int q, int f) -> float & { return msm[q * kMergeRunFloats + (1 + f) * 256 + t]; };
     constexpr int kB = 8;  // chunks whose slots are loaded together (one memory latency per batch)
+    // kmask[4 item + wave]: the lanes of this wave's sub-tile with a composite in chunk item
+    // (the forward's); a slot of any other lane holds T_end = 1 and no sums, so only these
+    // lanes load, and a batch of chunks in which no lane has a composite is skipped
+    const int wv = L.wave;
+    auto masks = [&](uint32_t it0, uint64_t (&mk)[kB]) -> uint64_t {
+        uint64_t any = 0ull;
+#pragma unroll
+        for (int q = 0; q < kB; ++q) {
+            mk[q] = it0 + q < r1 ? kmask[(size_t)(it0 + q) * 4 + wv] : 0ull;
+            any |= mk[q];
+        }
+        return any;
+    };
+    const int ln = L.lane;
     // 1. the run's transmittance product (read by the later runs only)
     if (grp + 1 < ng) {
         float P = 1.f;
-        for (uint32_t it0 = r0; it0 < r1 && L.valid; it0 += kB) {
+        for (uint32_t it0 = r0; it0 < r1; it0 += kB) {
+            uint64_t mk[kB];
+            if (masks(it0, mk) == 0ull) continue;
             float v[kB];
 #pragma unroll
-            for (int q = 0; q < kB; ++q) v[q] = it0 + q < r1 ? slots[slot(it0 + q, F_TEND, L.rt)] : 1.f;
+            for (int q = 0; q < kB; ++q) v[q] = (mk[q] >> ln & 1ull) ? slots[slot(it0 + q, F_TEND, L.rt)] : 1.f;
 #pragma unroll
             for (int q = 0; q < kB; ++q) P *= v[q];
         }
@@ -316,16 +343,19 @@ __device__ __forceinline__ void merge_tile(const uint32_t *__restrict__ chunk_ba
     float T = 1.f, A = 0.f, SD = 0.f, SN0 = 0.f, SN1 = 0.f, SN2 = 0.f;
     int K = 0, fix = -1;
     for (int q = 0; q < grp; ++q) T *= P_of(q);
-    // a run of at most kB chunks keeps its chunks' global sums in v for step 4, with bit q of
-    // `kept` set where chunk r0 + q keeps a contributor
+    // bit (it - r0) of `kept`: chunk it keeps a contributor for this lane's ray (a run has at
+    // most kTileChunks <= 64 chunks); a run of at most kB chunks also keeps those chunks'
+    // global sums in v for step 3
     const bool one_batch = r1 - r0 <= (uint32_t)kB;
-    uint32_t kept = 0u;
+    uint64_t kept = 0ull;
     float v[kB][7];
-    for (uint32_t it0 = r0; it0 < r1 && L.valid; it0 += kB) {
+    for (uint32_t it0 = r0; it0 < r1; it0 += kB) {
+        uint64_t mk[kB];
+        if (masks(it0, mk) == 0ull) continue;
 #pragma unroll
         for (int q = 0; q < kB; ++q) {
-            const uint32_t it = it0 + q;
-            if (it < r1) {
+            if (mk[q] >> ln & 1ull) {
+                const uint32_t it = it0 + q;
                 v[q][0] = slots[slot(it, F_K, L.rt)];
                 v[q][1] = slots[slot(it, F_TEND, L.rt)];
                 v[q][2] = slots[slot(it, F_SA, L.rt)];
@@ -339,12 +369,12 @@ __device__ __forceinline__ void merge_tile(const uint32_t *__restrict__ chunk_ba
         for (int q = 0; q < kB; ++q) {
             const uint32_t it = it0 + q;
             if (it >= r1) break;
+            if (!(mk[q] >> ln & 1ull)) continue;  // no composite: F_LAST is -1, nothing to add
             if (fix >= 0 || T < p.T_min) {  // after termination: the chunk contributes nothing
                 slots[slot(it, F_LAST, L.rt)] = __int_as_float(-1);
                 continue;
             }
             const int Kl = __float_as_int(v[q][0]);
-            if (Kl == 0) continue;  // no contributor: its slots are read by no later kernel
             const float Tn = T * v[q][1];
             if (it > c0 && Tn < p.T_min) {  // the ray terminates inside this chunk: re-walk it
                 fix = (int)it;              // the run's end state is then the state before it
@@ -353,13 +383,13 @@ __device__ __forceinline__ void merge_tile(const uint32_t *__restrict__ chunk_ba
             }
             const float gA = T * v[q][2], gD = T * v[q][3], g0 = T * v[q][4], g1 = T * v[q][5], g2 = T * v[q][6];
             slots[slot(it, F_TEND, L.rt)] = Tn;
+            kept |= 1ull << (it - r0);
             if (one_batch) {
                 v[q][2] = gA;
                 v[q][3] = gD;
                 v[q][4] = g0;
                 v[q][5] = g1;
                 v[q][6] = g2;
-                kept |= 1u << q;
             } else {
                 slots[slot(it, F_SA, L.rt)] = gA;
                 slots[slot(it, F_SD, L.rt)] = gD;
@@ -412,27 +442,29 @@ __device__ __forceinline__ void merge_tile(const uint32_t *__restrict__ chunk_ba
         if (one_batch) {
 #pragma unroll
             for (int q = kB - 1; q >= 0; --q)
-                if (kept >> q & 1u) emit(r0 + q, v[q]);
+                if (kept >> q & 1ull) emit(r0 + q, v[q]);
         } else {
             for (uint32_t top = r1; top > r0;) {
                 const uint32_t lo = top - r0 > (uint32_t)kB ? top - kB : r0;
+                const uint64_t kb = (kept >> (lo - r0)) & ((1ull << (top - lo)) - 1ull);
+                if (__any(kb != 0ull)) {
 #pragma unroll
-                for (int q = 0; q < kB; ++q) {
-                    const uint32_t it = top - 1 - q;
-                    if (it >= lo && it < top) {
-                        v[q][0] = slots[slot(it, F_LAST, L.rt)];
-                        v[q][2] = slots[slot(it, F_SA, L.rt)];
-                        v[q][3] = slots[slot(it, F_SD, L.rt)];
-                        v[q][4] = slots[slot(it, F_SN0, L.rt)];
-                        v[q][5] = slots[slot(it, F_SN1, L.rt)];
-                        v[q][6] = slots[slot(it, F_SN2, L.rt)];
+                    for (int q = 0; q < kB; ++q) {
+                        const uint32_t it = top - 1 - q;
+                        if (it >= lo && it < top && (kb >> (it - lo) & 1ull)) {
+                            v[q][2] = slots[slot(it, F_SA, L.rt)];
+                            v[q][3] = slots[slot(it, F_SD, L.rt)];
+                            v[q][4] = slots[slot(it, F_SN0, L.rt)];
+                            v[q][5] = slots[slot(it, F_SN1, L.rt)];
+                            v[q][6] = slots[slot(it, F_SN2, L.rt)];
+                        }
                     }
-                }
 #pragma unroll
-                for (int q = 0; q < kB; ++q) {
-                    const uint32_t it = top - 1 - q;
-                    if (it < lo || it >= top) break;
-                    if (__float_as_int(v[q][0]) >= 0) emit(it, v[q]);
+                    for (int q = 0; q < kB; ++q) {
+                        const uint32_t it = top - 1 - q;
+                        if (it < lo || it >= top) break;
+                        if (kb >> (it - lo) & 1ull) emit(it, v[q]);
+                    }
                 }
                 top = lo;
             }
@@ -473,9 +505,11 @@ __global__ __launch_bounds__(kMergeThreads) void raster_merge_kernel(const uint3
                                                                      uint8_t *__restrict__ drop,
                                                                      float4 *__restrict__ st0, float4 *__restrict__ st1,
                                                                      float4 *__restrict__ fixA, float4 *__restrict__ fixB,
-                                                                     uint32_t *__restrict__ fixflag)
+                                                                     uint32_t *__restrict__ fixflag,
+                                                                     const uint64_t *__restrict__ kmask)
 {
-    merge_tile(chunk_base, g, p, slots, depth, opacity, normal, drop, st0, st1, fixA, fixB, fixflag, blockIdx.x);
+    merge_tile(chunk_base, g, p, slots, depth, opacity, normal, drop, st0, st1, fixA, fixB, fixflag, kmask,
+               blockIdx.x);
 }
 
 // Re-walk the chunk in which a ray terminates, from its true transmittance, and finish it.
@@ -548,7 +582,7 @@ __global__ __launch_bounds__(64) void raster_fwd_chunk_multi(FwdJobs J, RasterPa
     const int j = job_of(J, blockIdx.x, false);
     const FwdJob &q = J.j[j];
     fwd_chunk_task(q.R.chunks, q.R.n_items, q.R.ids, q.R.recs, q.R.rects, q.R.rows, q.R.cols, q.g, p, q.R.slots,
-                   blockIdx.x - q.block0);
+                   q.R.kmask, blockIdx.x - q.block0);
 }
 
 __global__ __launch_bounds__(kMergeThreads) void raster_merge_multi(FwdJobs J, RasterParams p)
@@ -556,7 +590,7 @@ __global__ __launch_bounds__(kMergeThreads) void raster_merge_multi(FwdJobs J, R
     const int j = job_of(J, blockIdx.x, true);
     const FwdJob &q = J.j[j];
     merge_tile(q.R.chunk_base, q.g, p, q.R.slots, q.depth, q.opacity, q.normal, q.drop, q.R.st0, q.R.st1, q.R.fixA,
-               q.R.fixB, q.R.fixflag, (int)(blockIdx.x - q.tile0));
+               q.R.fixB, q.R.fixflag, q.R.kmask, (int)(blockIdx.x - q.tile0));
 }
 
 __global__ __launch_bounds__(64) void raster_fixup_multi(FwdJobs J, RasterParams p)
@@ -629,17 +663,20 @@ __global__ __launch_bounds__(64) void raster_bwd_chunk_kernel(
     const float *__restrict__ cols, Grid g, RasterParams p, const float *__restrict__ slots,
     const float4 *__restrict__ st0, const float4 *__restrict__ st1, const float *__restrict__ gDp,
     const float *__restrict__ gAp, const float *__restrict__ gNp, const float4 *__restrict__ fixA,
-    const float4 *__restrict__ fixB, float *__restrict__ recgrad)
+    const float4 *__restrict__ fixB, const uint64_t *__restrict__ kmask, float *__restrict__ recgrad)
 {
     __shared__ WaveStage ws;
     const uint32_t task = task_of(blockIdx.x), item = task >> 2;
     if (item >= *n_items) return;
+    // lanes without a composite in this chunk have nothing to propagate
+    const uint64_t km = kmask[task];
+    if (km == 0ull) return;
     const uint4 ch = uniform_chunk(chunks, item);
     const Lane L = lane_of((int)ch.x, g, (int)((task & 3u) * 64u + threadIdx.x));
     Ray ray = make_ray(rows, cols, L.valid ? L.k : 0, L.valid ? L.j : 0);
     int last = -1;
     float T = 1.f, B = 0.f, gbD = 0.f, gbN0 = 0.f, gbN1 = 0.f, gbN2 = 0.f, gbA = 0.f;
-    if (L.valid) {
+    if (km >> L.lane & 1ull) {
         last = __float_as_int(slots[slot(item, F_LAST, L.rt)]);
         if (last >= 0) {
             // effective upstream gradients of the ray, and B at the end of the chunk from the
@@ -850,10 +887,10 @@ hipError_t launch_raster_fwd(const RasterBufs &R, const Grid &g, const RasterPar
     const int im = (int)R.items_max;
     if (im > 0)
         raster_fwd_chunk_kernel<<<task_blocks(im), 64, 0, s>>>(R.chunks, R.n_items, R.ids, R.recs, R.rects, R.rows,
-                                                               R.cols, g, p, R.slots);
+                                                               R.cols, g, p, R.slots, R.kmask);
     const int ng = merge_groups(g.T);
     raster_merge_kernel<<<g.T, 256 * ng, (size_t)ng * kMergeRunFloats * sizeof(float), s>>>(
-        R.chunk_base, g, p, R.slots, depth, opacity, normal, drop, R.st0, R.st1, R.fixA, R.fixB, R.fixflag);
+        R.chunk_base, g, p, R.slots, depth, opacity, normal, drop, R.st0, R.st1, R.fixA, R.fixB, R.fixflag, R.kmask);
     if (im > 0)
         raster_fixup_kernel<<<task_blocks(im), 64, 0, s>>>(R.chunks, R.n_items, R.ids, R.recs, R.rects, R.rows,
                                                            R.cols, g, p, R.fixA, R.fixB, R.slots, depth, opacity,
@@ -903,7 +940,7 @@ hipError_t launch_raster_bwd(const RasterBufs &R, const Grid &g, const RasterPar
     if (g.T <= 0 || im <= 0) return hipSuccess;
     raster_bwd_chunk_kernel<<<task_blocks(im), 64, 0, s>>>(R.chunks, R.n_items, R.ids, R.recs, R.rects, R.rows,
                                                            R.cols, g, p, R.slots, R.st0, R.st1, gD, gA, gN, R.fixA,
-                                                           R.fixB, recgrad);
+                                                           R.fixB, R.kmask, recgrad);
     return hipGetLastError();
 }
 

@@ -20,7 +20,6 @@ constexpr int kTsThreads = 1024;
 constexpr int kTsWaves = kTsThreads / 64;
 constexpr int kTsItems = 8;
 constexpr int kTsCap = kTsThreads * kTsItems;  // entries sorted without leaving the CU
-constexpr int kTileChunks = 64;  // most chunks of one tile's list in the raster
 constexpr int kDigitBits = 9;
 constexpr int kDigits = 1 << kDigitBits;
 constexpr int kRunMax = 16;  // longest run of equal range keys ordered in place
