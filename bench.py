@@ -41,14 +41,14 @@ PEAK_HBM_GBS = 8000.0
 # WRITE_SIZE per dispatch, each scaled by what the counter reads for a plain 256 MiB device
 # copy (profiles/pmc_traffic_raster_bwd_block64x1024_300k.md).  Valid only for the kernel
 # sources they were taken with (digest below); reported as null once those change.
-TRAFFIC_RASTER_BWD = dict(bytes=57592575,
-                          sources_sha256="880d31f60cd5f837ecee0aad0caca4aafa68b10b1a40a941c6769bcd7373f2a3")
+TRAFFIC_RASTER_BWD = dict(bytes=77663840,
+                          sources_sha256="ae403d2afe7ec7dce0d40943d284ff6968f2e2ba54e3ae1aa25a6af1cd44f1b6")
 
 
 # rocprofv3 SQ counters of one raster_bwd launch on the benchmark workload (per dispatch) and
 # the kernel's mean duration in the same profiled run; same validity rule as the traffic.
-SQ_RASTER_BWD = dict(SQ_INSTS_VALU=24054991, SQ_INSTS_LDS=1002483, SQ_LDS_BANK_CONFLICT=312440, ms=0.0761,
-                     sources_sha256="880d31f60cd5f837ecee0aad0caca4aafa68b10b1a40a941c6769bcd7373f2a3")
+SQ_RASTER_BWD = dict(SQ_INSTS_VALU=24001224, SQ_INSTS_LDS=974394, SQ_LDS_BANK_CONFLICT=305332, ms=0.0694,
+                     sources_sha256="ae403d2afe7ec7dce0d40943d284ff6968f2e2ba54e3ae1aa25a6af1cd44f1b6")
 
 
 def _sources_digest() -> str:
@@ -586,9 +586,12 @@ def cpu_baseline(w, target_s):
                           ray_ids=ids)
         return time.perf_counter() - t
 
-    m = 256
-    dt = run(m)
-    m2 = int(min(H * W, max(m, m * target_s / max(dt, 1e-3))))
+    # the oracle's time is a fixed set-up (projection and ordering of every surfel) plus a
+    # per-ray cost: measure both from two short runs, then size the sample
+    dt_a, dt_b = run(256), run(1024)
+    per_ray = max((dt_b - dt_a) / 768, 1e-7)
+    fixed = max(dt_a - 256 * per_ray, 0.0)
+    m2 = int(min(H * W, max(1024, (target_s - fixed) / per_ray)))
     dt2 = run(m2)
     cores = ref.threads()
     print(f"# cpu oracle: {m2} rays in {dt2:.1f} s on {cores} threads", file=sys.stderr, flush=True)
