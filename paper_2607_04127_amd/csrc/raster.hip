@@ -37,9 +37,9 @@
 namespace lgsr {
 
 // Per (chunk, ray) slot fields; slot(item, f, rt) with rt = wave * 64 + lane.  The forward
-// writes F_TEND, F_LAST and F_K for every chunk and ray, and the chunk's local sums F_SA ..
-// F_SN2 only where the chunk has a contributor for the ray (F_K > 0), since nothing reads
-// them otherwise.  The merge turns F_TEND into the global transmittance and, where the
+// writes a slot only where the chunk has a contributor for the ray (its bit in the task's
+// composite mask, kmask), and every reader looks at the mask first: F_TEND, F_LAST, F_K and
+// the chunk's local sums F_SA .. F_SN2.  The merge turns F_TEND into the global transmittance and, where the
 // chunk keeps a contributor (F_LAST >= 0), F_SA .. F_SN2 into the sums of all later chunks
 // of the tile in global weights (the fix-up chunk's aside).
 enum : int { F_TEND = 0, F_SA, F_SD, F_SN0, F_SN1, F_SN2, F_LAST, F_K, kSlotFields };
@@ -217,11 +217,11 @@ __device__ __forceinline__ void fwd_chunk_task(
     composite(ws, ids, recs, rects, ch.y, ch.z, L, ray, p, g.W, L.valid, acc);
     const uint64_t km = __ballot(L.valid && acc.K > 0);
     if (threadIdx.x == 0) kmask[task] = km;
-    if (!L.valid) return;
+    // the slot of a ray without a composite here is read by no one: its mask bit is clear
+    if (!L.valid || acc.K == 0) return;
     slots[slot(item, F_TEND, L.rt)] = acc.T;
     slots[slot(item, F_LAST, L.rt)] = __int_as_float(acc.last);
     slots[slot(item, F_K, L.rt)] = __int_as_float(acc.K);
-    if (acc.K == 0) return;  // the sums of a chunk without composites are read by no one
     slots[slot(item, F_SA, L.rt)] = acc.A;
     slots[slot(item, F_SD, L.rt)] = acc.SD;
     slots[slot(item, F_SN0, L.rt)] = acc.SN0;
@@ -797,6 +797,7 @@ __global__ __launch_bounds__(256) void work_needed_kernel(const uint32_t *__rest
                                                           const uint2 *__restrict__ rects,
                                                           const uint2 *__restrict__ ranges, Grid g, RasterParams p,
                                                           const float *__restrict__ slots,
+                                                          const uint64_t *__restrict__ kmask,
                                                           const float4 *__restrict__ st0,
                                                           unsigned long long *__restrict__ out)
 {
@@ -807,7 +808,9 @@ __global__ __launch_bounds__(256) void work_needed_kernel(const uint32_t *__rest
     if (L.valid) {
         const uint32_t c0 = chunk_base[tile], c1 = chunk_base[tile + 1];
         int last = -1;
-        for (uint32_t it = c0; it < c1; ++it) last = max(last, __float_as_int(slots[slot(it, F_LAST, L.rt)]));
+        for (uint32_t it = c0; it < c1; ++it)
+            if (kmask[(size_t)it * 4 + L.wave] >> L.lane & 1ull)
+                last = max(last, __float_as_int(slots[slot(it, F_LAST, L.rt)]));
         const bool dead = st0[L.k * g.W + L.j].z < p.T_min;
         need = dead ? last : (int)rg.y - 1;
     }
@@ -920,7 +923,8 @@ hipError_t launch_raster_fwd_multi(FwdJobs &J, const RasterParams &p, hipStream_
 hipError_t launch_work_needed(const RasterBufs &R, const Grid &g, const RasterParams &p, unsigned long long *out,
                               hipStream_t s)
 {
-    work_needed_kernel<<<g.T, 256, 0, s>>>(R.chunk_base, R.ids, R.rects, R.ranges, g, p, R.slots, R.st0, out);
+    work_needed_kernel<<<g.T, 256, 0, s>>>(R.chunk_base, R.ids, R.rects, R.ranges, g, p, R.slots, R.kmask, R.st0,
+                                           out);
     return hipGetLastError();
 }
 
