@@ -41,14 +41,14 @@ PEAK_HBM_GBS = 8000.0
 # WRITE_SIZE per dispatch, each scaled by what the counter reads for a plain 256 MiB device
 # copy (profiles/pmc_traffic_raster_bwd_block64x1024_300k.md).  Valid only for the kernel
 # sources they were taken with (digest below); reported as null once those change.
-TRAFFIC_RASTER_BWD = dict(bytes=77663840,
-                          sources_sha256="ae403d2afe7ec7dce0d40943d284ff6968f2e2ba54e3ae1aa25a6af1cd44f1b6")
+TRAFFIC_RASTER_BWD = dict(bytes=77662577,
+                          sources_sha256="693a91c1a211a62155b93cf95919a1863be6291c0cc4afc6d0fa89fe68bdacb4")
 
 
 # rocprofv3 SQ counters of one raster_bwd launch on the benchmark workload (per dispatch) and
 # the kernel's mean duration in the same profiled run; same validity rule as the traffic.
-SQ_RASTER_BWD = dict(SQ_INSTS_VALU=24001224, SQ_INSTS_LDS=974394, SQ_LDS_BANK_CONFLICT=305332, ms=0.0694,
-                     sources_sha256="ae403d2afe7ec7dce0d40943d284ff6968f2e2ba54e3ae1aa25a6af1cd44f1b6")
+SQ_RASTER_BWD = dict(SQ_INSTS_VALU=24001224, SQ_INSTS_LDS=974394, SQ_LDS_BANK_CONFLICT=305332, ms=0.0701,
+                     sources_sha256="693a91c1a211a62155b93cf95919a1863be6291c0cc4afc6d0fa89fe68bdacb4")
 
 
 def _sources_digest() -> str:
