@@ -776,10 +776,23 @@ __global__ __launch_bounds__(64) void raster_bwd_chunk_kernel(
             gv[G_ALPHA] = dalpha;
 #pragma unroll
             for (int c = kGradUsed; c < 16; ++c) gv[c] = 0.f;
-            const float mine = wave_sum16(gv, L.lane);
-            const int k = L.lane & 15, c = 4 * (L.lane >> 4) + k;
             const uint32_t sid = (uint32_t)__builtin_amdgcn_readlane((int)slot_id, (int)i);
-            if (k < 4 && c < kGradUsed) unsafeAtomicAdd(recgrad + (size_t)sid * kGrad + c, mine);
+            const uint64_t cm = __builtin_amdgcn_ballot_w64(contrib);
+            if ((cm & (cm - 1ull)) == 0ull) {
+                // one contributing lane: its values are the sums; lane c takes value c
+                const int src = (int)__builtin_ctzll(cm);
+                float mine = 0.f;
+#pragma unroll
+                for (int c = 0; c < kGradUsed; ++c) {
+                    const float x = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(gv[c]), src));
+                    mine = L.lane == c ? x : mine;
+                }
+                if (L.lane < kGradUsed) unsafeAtomicAdd(recgrad + (size_t)sid * kGrad + L.lane, mine);
+            } else {
+                const float mine = wave_sum16(gv, L.lane);
+                const int k = L.lane & 15, c = 4 * (L.lane >> 4) + k;
+                if (k < 4 && c < kGradUsed) unsafeAtomicAdd(recgrad + (size_t)sid * kGrad + c, mine);
+            }
         }
         __syncthreads();  // the stage is no longer read
     }
