@@ -190,7 +190,7 @@ static void eval_hit(const surf_t *s, const double *d, const lgsr_ref_params *p,
 
 static int accepted(const eval_t *e) { return e->ok[0] && e->ok[1] && e->ok[2] && e->ok[3]; }
 
-/* How far the tests' verdict on a surfel is from flipping: for an accepted surfel any one
+/* How far the tests' decision on a surfel is from flipping: for an accepted surfel any one
  * test crossing its threshold rejects it (the smallest gap); for a rejected one every test
  * that rejects it has to cross (the largest of their gaps, an undefined gap counting as
  * infinite). */
@@ -222,7 +222,7 @@ static void ray_dir(const lgsr_ref_beams *B, int64_t rid, double *d)
  * (capacity: the number of valid surfels).
  * margin: the smallest relative distance by which some threshold decision would have to
  * move to change the ray's result: for every surfel the ray reaches before it stops, how far
- * the per-hit tests' verdict is from flipping (flip_gap); for a composited surfel also its
+ * the per-hit tests' decision is from flipping (flip_gap); for a composited surfel also its
  * alpha G against alpha_max, its centre range against `near` and the transmittance after it
  * against T_min; for a surfel cut for its centre range, the largest of that range's gap and
  * the gaps of the hit tests that reject it.  order_gap: the smallest relative gap between

@@ -105,14 +105,14 @@ def compare_forward(fr, of, ray_ids=None, rel=1e-5, natol=1e-4, conditioned=Fals
 
 def grad_check(g, g_ref, mass=None, rel=1e-3, floor=3e-2, per_row=True):
     """(failures, cosine, worst error / bound).  per_row: rows of a 2-D array are one
-    surfel's vector; otherwise every element is judged on its own.  mass: per row (or per
+    surfel's vector; otherwise every element is checked on its own.  mass: per row (or per
     element) sum of contribution magnitudes; without it the floor is relative to the rms."""
     r = grad_report(g, g_ref, mass, rel, floor, per_row)
     return r["bad"], r["cos"], r["worst"]
 
 
 def grad_report(g, g_ref, mass=None, rel=1e-3, floor=3e-2, per_row=True):
-    """grad_check's verdict plus two diagnostics:
+    """grad_check's outcome plus two diagnostics:
       floor_only -- rows within the bound only because of the mass floor (their error
                     exceeds rel * |g_ref row|);
       elem_bad   -- elements failing the plain element-wise rule
