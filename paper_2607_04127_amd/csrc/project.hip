@@ -72,19 +72,74 @@ __device__ __forceinline__ int first_row_lt(const float *__restrict__ rows, int 
     return lo;
 }
 
-// Calls f(tile) for every tile met by the ray rectangle rc (rows r0..r1, columns c0 ..
-// c0 + cw - 1 modulo W); projection (counting) and emission (writing) both enumerate with it.
-template <class F>
-__device__ __forceinline__ void for_each_tile(uint2 rc, const Grid &g, F &&f)
+// Tiles met by a ray rectangle (rows r0..r1, columns c0 .. c0 + cw - 1 modulo W): tile rows
+// tr0 .. tr0 + rows - 1, and in each the tile columns a0 .. a0 + na - 1 followed by
+// b0 .. b0 + nb - 1; n tiles in all.
+struct TileSpan {
+    int tr0, a0, na, b0, nb, n;
+};
+
+__device__ __forceinline__ TileSpan tile_span(uint2 rc, const Grid &g)
 {
+    TileSpan s{0, 0, 0, 0, 0, 0};
     const int r0 = (int)(rc.x & 0xFFFFu), r1 = (int)(rc.x >> 16);
     const int c0 = (int)(rc.y & 0xFFFFu), cw = (int)(rc.y >> 16);
-    if (cw <= 0) return;
+    if (cw <= 0 || r1 < r0) return s;
     int a0, a1, b0, b1;
     col_segments(c0, cw, g.W, g.TW, a0, a1, b0, b1);
-    for (int tr = r0 / kTile; tr <= r1 / kTile; ++tr) {
-        for (int tc = a0; tc <= a1; ++tc) f(tile_id(tr, tc, g.TH));
-        for (int tc = b0; tc <= b1; ++tc) f(tile_id(tr, tc, g.TH));
+    s.tr0 = r0 / kTile;
+    s.a0 = a0;
+    s.na = a1 - a0 + 1;
+    s.b0 = b0;
+    s.nb = b1 >= b0 ? b1 - b0 + 1 : 0;
+    s.n = (r1 / kTile - s.tr0 + 1) * (s.na + s.nb);
+    return s;
+}
+
+__device__ __forceinline__ int span_tile(const TileSpan &s, int k, int TH)
+{
+    const int w = s.na + s.nb;
+    const int row = k / w, j = k - row * w;
+    return tile_id(s.tr0 + row, j < s.na ? s.a0 + j : s.b0 + (j - s.na), TH);
+}
+
+// A lane walks the tiles of its own rectangle when there are at most this many; the tiles
+// of a larger rectangle are shared out over the wave's 64 lanes.
+constexpr int kOwnTiles = 8;
+
+// Calls f(tile, v) for every tile met by each lane's ray rectangle rc, v being the value
+// the rectangle's lane passed.  Every lane of the wavefront must call it (lanes with
+// nothing to enumerate pass an empty rectangle).  A rectangle around the sensor meets every
+// tile of the grid; walked by its own lane alone it would hold the whole wave for hundreds
+// of serial steps, so rectangles of more than kOwnTiles tiles are taken one at a time by
+// the whole wave, a tile per lane.  Projection (counting) and emission (writing) both
+// enumerate with it; the order of the calls is of no consequence to either.
+template <class F>
+__device__ __forceinline__ void for_each_tile(uint2 rc, uint32_t v, const Grid &g, F &&f)
+{
+    const TileSpan s = tile_span(rc, g);
+    const bool wide = s.n > kOwnTiles;
+    if (!wide && s.n > 0) {
+        const int rows = s.n / (s.na + s.nb);
+        for (int r = 0; r < rows; ++r) {
+            for (int j = 0; j < s.na; ++j) f(tile_id(s.tr0 + r, s.a0 + j, g.TH), v);
+            for (int j = 0; j < s.nb; ++j) f(tile_id(s.tr0 + r, s.b0 + j, g.TH), v);
+        }
+    }
+    uint64_t wm = __ballot(wide);
+    const int lane = (int)(threadIdx.x & 63u);
+    while (wm) {
+        const int src = __builtin_ctzll(wm);
+        wm &= wm - 1ull;
+        TileSpan w;
+        w.tr0 = __builtin_amdgcn_readlane(s.tr0, src);
+        w.a0 = __builtin_amdgcn_readlane(s.a0, src);
+        w.na = __builtin_amdgcn_readlane(s.na, src);
+        w.b0 = __builtin_amdgcn_readlane(s.b0, src);
+        w.nb = __builtin_amdgcn_readlane(s.nb, src);
+        w.n = __builtin_amdgcn_readlane(s.n, src);
+        const uint32_t wv = (uint32_t)__builtin_amdgcn_readlane((int)v, src);
+        for (int k = lane; k < w.n; k += 64) f(span_tile(w, k, g.TH), wv);
     }
 }
 
@@ -180,13 +235,13 @@ __device__ __forceinline__ uint2 project_one(const SurfelPtrs &S, const Pose &P,
     return make_uint2((uint32_t)r0 | ((uint32_t)r1 << 16), (uint32_t)c0 | ((uint32_t)cw << 16));
 }
 
-// Surfels per projection / emission workgroup, one per thread: one reservation per
-// (workgroup, tile) covers the pairs of 1024 surfels, and 16 waves per workgroup keep the
-// CU busy while each works through its surfel's arithmetic.
+// Surfels per projection / emission workgroup, one per thread.  One count flush and one
+// reservation per (workgroup, tile) cover the pairs of 1024 surfels; smaller workgroups
+// measured slower for both kernels.
 constexpr int kProjThreads = 1024;
-constexpr int kPerThread = 1;
-constexpr int kPerBlock = kProjThreads * kPerThread;
-static_assert(kPerBlock == 1 << kShardShift, "the shard of a surfel is its workgroup's");
+constexpr int kEmitThreads = 1024;
+static_assert((1 << kShardShift) % kProjThreads == 0 && (1 << kShardShift) % kEmitThreads == 0,
+              "a workgroup's surfels share one shard");
 
 // Projection plus the per-tile pair counts, tile_cnt[t * kShards + shard_of(i)] (zero on
 // entry).  A workgroup's surfels share one shard.  Dynamic LDS: T words when T <= kLdsBins,
@@ -215,17 +270,18 @@ __global__ __launch_bounds__(kProjThreads) void project_kernel(SurfelPtrs S, Pos
 #pragma unroll
         for (int c = 0; c < 12; ++c) pose_out[c] = (c & 3) < 3 ? P.r[3 * (c >> 2) + (c & 3)] : P.t[c >> 2];
     }
-    const int64_t first = (int64_t)blockIdx.x * kPerBlock;
+    const int64_t first = (int64_t)blockIdx.x * kProjThreads;
+    const int64_t i = first + threadIdx.x;
     const int sh = shard_of(first);
     if (lds_bins || lds_rows) __syncthreads();
-    for (int k = 0; k < kPerThread; ++k) {
-        const int64_t i = first + k * kProjThreads + threadIdx.x;
-        if (i >= S.n) break;
-        const uint2 rc = project_one(S, P, lds_rows ? rsin : rows, lds_rows ? 1 : 2, g, p, recs, keys, i);
+    uint2 rc = make_uint2(0u, 0u);
+    if (i < S.n) {
+        rc = project_one(S, P, lds_rows ? rsin : rows, lds_rows ? 1 : 2, g, p, recs, keys, i);
         rects[i] = rc;
-        if (lds_bins) for_each_tile(rc, g, [&](int t) { atomicAdd(&bins[t], 1u); });
-        else for_each_tile(rc, g, [&](int t) { atomicAdd(&tile_cnt[t * kShards + sh], 1u); });
     }
+    // the whole wave enumerates (lanes past the end with an empty rectangle)
+    if (lds_bins) for_each_tile(rc, 0u, g, [&](int t, uint32_t) { atomicAdd(&bins[t], 1u); });
+    else for_each_tile(rc, 0u, g, [&](int t, uint32_t) { atomicAdd(&tile_cnt[t * kShards + sh], 1u); });
     if (lds_bins) {
         __syncthreads();
         for (int b = threadIdx.x; b < g.T; b += kProjThreads) {
@@ -240,47 +296,38 @@ __global__ __launch_bounds__(kProjThreads) void project_kernel(SurfelPtrs S, Pos
 // Per workgroup, pairs are counted per tile in LDS, one range per tile is reserved with a
 // single atomic, and the workgroup's pairs fill it.  Positions at or beyond P are dropped
 // (they cannot occur when the counts came from project_kernel over the same rectangles).
-__global__ __launch_bounds__(kProjThreads) void emit_kernel(const uint2 *__restrict__ rects, int64_t n, Grid g,
+__global__ __launch_bounds__(kEmitThreads) void emit_kernel(const uint2 *__restrict__ rects, int64_t n, Grid g,
                                                    uint32_t *__restrict__ cursor, uint32_t *__restrict__ pv,
                                                    int64_t P)
 {
     extern __shared__ uint32_t bins[];  // count, then reserved base, per tile
-    const int64_t first = (int64_t)blockIdx.x * kPerBlock;
+    const int64_t first = (int64_t)blockIdx.x * kEmitThreads;
     const int sh = shard_of(first);
-    uint2 rc[kPerThread];
-#pragma unroll
-    for (int k = 0; k < kPerThread; ++k) {
-        const int64_t i = first + k * kProjThreads + threadIdx.x;
-        rc[k] = i < n ? rects[i] : make_uint2(0u, 0u);
-    }
+    const int64_t i = first + threadIdx.x;
+    const uint2 rc = i < n ? rects[i] : make_uint2(0u, 0u);
+    const uint32_t id = (uint32_t)i;
     if (g.T > kLdsBins) {
-        for (int k = 0; k < kPerThread; ++k) {
-            const uint32_t id = (uint32_t)(first + k * kProjThreads + threadIdx.x);
-            for_each_tile(rc[k], g, [&](int t) {
-                const uint32_t pos = atomicAdd(&cursor[t * kShards + sh], 1u);
-                if ((int64_t)pos < P) pv[pos] = id;
-            });
-        }
+        for_each_tile(rc, id, g, [&](int t, uint32_t sid) {
+            const uint32_t pos = atomicAdd(&cursor[t * kShards + sh], 1u);
+            if ((int64_t)pos < P) pv[pos] = sid;
+        });
         return;
     }
     uint32_t *cnt = bins, *base = bins + g.T;
-    for (int b = threadIdx.x; b < g.T; b += kProjThreads) cnt[b] = 0u;
+    for (int b = threadIdx.x; b < g.T; b += kEmitThreads) cnt[b] = 0u;
     __syncthreads();
-    for (int k = 0; k < kPerThread; ++k) for_each_tile(rc[k], g, [&](int t) { atomicAdd(&cnt[t], 1u); });
+    for_each_tile(rc, 0u, g, [&](int t, uint32_t) { atomicAdd(&cnt[t], 1u); });
     __syncthreads();
-    for (int b = threadIdx.x; b < g.T; b += kProjThreads) {
+    for (int b = threadIdx.x; b < g.T; b += kEmitThreads) {
         const uint32_t c = cnt[b];
         if (c) base[b] = atomicAdd(&cursor[b * kShards + sh], c);
         cnt[b] = 0u;
     }
     __syncthreads();
-    for (int k = 0; k < kPerThread; ++k) {
-        const uint32_t id = (uint32_t)(first + k * kProjThreads + threadIdx.x);
-        for_each_tile(rc[k], g, [&](int t) {
-            const uint32_t pos = base[t] + atomicAdd(&cnt[t], 1u);
-            if ((int64_t)pos < P) pv[pos] = id;
-        });
-    }
+    for_each_tile(rc, id, g, [&](int t, uint32_t sid) {
+        const uint32_t pos = base[t] + atomicAdd(&cnt[t], 1u);
+        if ((int64_t)pos < P) pv[pos] = sid;
+    });
 }
 
 __global__ __launch_bounds__(256) void fill_u32_kernel(uint32_t *__restrict__ p, uint32_t v, int64_t n)
@@ -381,7 +428,7 @@ hipError_t launch_project(const SurfelPtrs &S, const Pose &pose_val, const float
                           const float *rows, const Grid &g, const RasterParams &p, float *recs, uint2 *rects,
                           uint32_t *keys, uint32_t *tile_cnt, hipStream_t s)
 {
-    unsigned nb = S.n > 0 ? blocks_for(S.n, kPerBlock) : 1u;  // one block still writes the pose
+    unsigned nb = S.n > 0 ? blocks_for(S.n, kProjThreads) : 1u;  // one block still writes the pose
     size_t lds = (g.T <= kLdsBins ? (size_t)g.T * sizeof(uint32_t) : 0) + (g.H <= kLdsRows ? (size_t)g.H * sizeof(float) : 0);
     project_kernel<<<nb, kProjThreads, lds, s>>>(S, pose_val, pose_dev, pose_out, rows, g, p, recs, rects, keys,
                                                  tile_cnt);
@@ -393,7 +440,7 @@ hipError_t launch_emit(const uint2 *rects, int64_t n, const Grid &g, uint32_t *c
 {
     if (n <= 0 || P <= 0) return hipSuccess;
     size_t lds = g.T <= kLdsBins ? 2 * (size_t)g.T * sizeof(uint32_t) : 0;
-    emit_kernel<<<blocks_for(n, kPerBlock), kProjThreads, lds, s>>>(rects, n, g, cursor, pv, P);
+    emit_kernel<<<blocks_for(n, kEmitThreads), kEmitThreads, lds, s>>>(rects, n, g, cursor, pv, P);
     return hipGetLastError();
 }
 
