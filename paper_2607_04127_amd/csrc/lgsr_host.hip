@@ -118,6 +118,7 @@ constexpr int kLanes = 4;
 
 struct lgsr_ctx {
     int device = 0;
+    int n_cu = 1;  // compute units of the device: projection and emission run one workgroup per CU at most
     hipStream_t stream = nullptr;
     std::string err;
     Lane lanes[kLanes];
@@ -396,7 +397,8 @@ lgsr_status forward_begin(lgsr_ctx *ctx, lgsr_state *S, const lgsr_surfels *surf
         HIP_TRY(launch_fill_u32(as<uint32_t>(S->cnt), 0u, (int64_t)(S->cnt.cap / 4), s), "clear tile counts");
     S->cnt_clean = false;  // until the scan below has run
     HIP_TRY(launch_project(S->S, pose_val, pose_dev, as<float>(S->pose), beams->row_sincos, g, S->prm,
-                           as<float>(S->recs), as<uint2>(S->rects), as<uint32_t>(S->keys), as<uint32_t>(S->cnt), s),
+                           as<float>(S->recs), as<uint2>(S->rects), as<uint32_t>(S->keys), as<uint32_t>(S->cnt),
+                           surfel_blocks(S->S.n, ctx->n_cu), s),
             "project");
     }
     {
@@ -430,7 +432,8 @@ lgsr_status forward_begin(lgsr_ctx *ctx, lgsr_state *S, const lgsr_surfels *surf
             S->spec_seg = seg;
             {
             Stage st_(ctx, LGSR_STAGE_EMIT, s);
-            HIP_TRY(launch_emit(as<uint2>(S->rects), n, g, as<uint32_t>(S->offs), S->ids, S->spec_cap_pairs, s),
+            HIP_TRY(launch_emit(as<uint2>(S->rects), n, g, as<uint32_t>(S->offs), S->ids, S->spec_cap_pairs,
+                                surfel_blocks(n, ctx->n_cu), s),
                     "emit");
             }
             Stage st_(ctx, LGSR_STAGE_TILE_SORT, s);
@@ -494,7 +497,9 @@ lgsr_status forward_lists(lgsr_ctx *ctx, lgsr_state *S, hipStream_t s)
         if (S->spec) HIP_TRY(launch_restore_cursors(as<uint2>(S->ranges), g.T, as<uint32_t>(S->offs), s), "emit");
         if (P > 0) {
             Stage st_(ctx, LGSR_STAGE_EMIT, s);
-            HIP_TRY(launch_emit(as<uint2>(S->rects), n, g, as<uint32_t>(S->offs), S->ids, P, s), "emit");
+            HIP_TRY(launch_emit(as<uint2>(S->rects), n, g, as<uint32_t>(S->offs), S->ids, P, surfel_blocks(n, ctx->n_cu),
+                                s),
+                    "emit");
         }
         Stage st_(ctx, LGSR_STAGE_TILE_SORT, s);
         HIP_TRY(launch_tile_sort(as<uint2>(S->ranges), g.T, as<uint32_t>(S->keys), n, S->ids, P, true, cl, s),
@@ -679,6 +684,12 @@ lgsr_status lgsr_create(lgsr_ctx **out, int device, void *hip_stream)
     lgsr_ctx *ctx = new (std::nothrow) lgsr_ctx;
     if (!ctx) return LGSR_ENOMEM;
     ctx->device = device;
+    if (hipDeviceGetAttribute(&ctx->n_cu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess ||
+        ctx->n_cu < 1) {
+        (void)hipGetLastError();
+        delete ctx;
+        return LGSR_EDEVICE;
+    }
     ctx->stream = static_cast<hipStream_t>(hip_stream);
     ctx->lanes[0].stream = ctx->stream;
     ctx->scratch_state.ctx = ctx;

@@ -31,12 +31,10 @@ namespace lgsr {
 constexpr int kTile = 16;      // tile edge in rays: a tile is 16 x 16 rays with one surfel list
 constexpr int kSub = 8;        // wave sub-tile edge: 8 x 8 rays, one wavefront of 64 lanes
 constexpr int kRec = 16;       // floats per surfel record
-// Per-tile pair counters are split into kShards by surfel index ((i >> kShardShift) mod
-// kShards, the projection workgroup of the surfel) so that no single counter takes an atomic
-// from every workgroup; a tile's list is the concatenation of its shards.
+// Per-tile pair counters are split into kShards by the projection workgroup of the surfel
+// (workgroup index mod kShards) so that no single counter takes an atomic from every
+// workgroup; a tile's list is the concatenation of its shards.
 constexpr int kShards = 8;
-constexpr int kShardShift = 10;
-__host__ __device__ __forceinline__ int shard_of(int64_t i) { return (int)((i >> kShardShift) & (kShards - 1)); }
 constexpr int kGrad = 16;      // floats per surfel record-gradient slot (kGradUsed used)
 constexpr int kGradUsed = 15;
 constexpr uint32_t kCulledKey = 0x7FFFFFFFu;  // depth key of a surfel that renders nothing

@@ -51,14 +51,18 @@ struct SurfelPtrs {
     int64_t n;
 };
 
+// Workgroups of the projection and of the emission for n surfels on a device of n_cu compute
+// units: one per CU at most (workgroup b takes surfels [b n / B, (b + 1) n / B)); both
+// launches of one frame must use the same count.
+int surfel_blocks(int64_t n, int n_cu);
 // records, range keys (float bits of the sensor range), ray rectangles, and per-(tile,
 // shard) pair counts added to tile_cnt (T x kShards, zero it first)
 hipError_t launch_project(const SurfelPtrs &S, const Pose &pose_val, const float *pose_dev, float *pose_out,
                           const float *rows, const Grid &g, const RasterParams &p, float *recs, uint2 *rects,
-                          uint32_t *keys, uint32_t *tile_cnt, hipStream_t s);
+                          uint32_t *keys, uint32_t *tile_cnt, int blocks, hipStream_t s);
 // surfel ids into the tile lists; cursor (T x kShards) from launch_tile_scan, pv holds P words
 hipError_t launch_emit(const uint2 *rects, int64_t n, const Grid &g, uint32_t *cursor, uint32_t *pv, int64_t P,
-                       hipStream_t s);
+                       int blocks, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
 hipError_t launch_count_visible(const uint2 *rects, int64_t n, uint32_t *out, hipStream_t s);
 hipError_t launch_max_range(const uint2 *ranges, int T, uint32_t *out, hipStream_t s);

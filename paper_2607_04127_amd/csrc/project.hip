@@ -235,17 +235,26 @@ __device__ __forceinline__ uint2 project_one(const SurfelPtrs &S, const Pose &P,
     return make_uint2((uint32_t)r0 | ((uint32_t)r1 << 16), (uint32_t)c0 | ((uint32_t)cw << 16));
 }
 
-// Surfels per projection / emission workgroup, one per thread.  One count flush and one
-// reservation per (workgroup, tile) cover the pairs of 1024 surfels; smaller workgroups
-// measured slower for both kernels.
+// Projection and emission run one 1024-thread workgroup per CU at most, each on a contiguous
+// range of nearly equal length (a thread takes surfels lo + t, lo + t + 1024, ...).  The
+// projection is bound by its VALU work per CU: with one surfel per thread a 300k-surfel map
+// made 293 workgroups, and the 37 CUs that took two set the kernel's time.  Smaller
+// workgroups do not fix that, as the dispatcher packs several onto one CU.  One count flush
+// and one reservation per (workgroup, tile) cover the workgroup's range.
 constexpr int kProjThreads = 1024;
-constexpr int kEmitThreads = 1024;
-static_assert((1 << kShardShift) % kProjThreads == 0 && (1 << kShardShift) % kEmitThreads == 0,
-              "a workgroup's surfels share one shard");
 
-// Projection plus the per-tile pair counts, tile_cnt[t * kShards + shard_of(i)] (zero on
-// entry).  A workgroup's surfels share one shard.  Dynamic LDS: T words when T <= kLdsBins,
-// else none (counts then go straight to tile_cnt).
+int surfel_blocks(int64_t n, int n_cu)
+{
+    if (n <= 0) return 1;  // one workgroup still writes the pose
+    const int64_t b = (n + kProjThreads - 1) / kProjThreads;
+    return (int)(b < n_cu ? b : (n_cu > 0 ? n_cu : 1));
+}
+
+__device__ __forceinline__ int64_t range_lo(int64_t n, int b) { return n * b / (int64_t)gridDim.x; }
+
+// Projection plus the per-tile pair counts, tile_cnt[t * kShards + b mod kShards] for the
+// surfels of workgroup b (zero on entry).  Dynamic LDS: T words when T <= kLdsBins, else none
+// (counts then go straight to tile_cnt).
 __global__ __launch_bounds__(kProjThreads) void project_kernel(SurfelPtrs S, Pose pose_val, const float *__restrict__ pose_dev,
                                                       float *__restrict__ pose_out,
                                                       const float *__restrict__ rows, Grid g, RasterParams p,
@@ -270,18 +279,20 @@ __global__ __launch_bounds__(kProjThreads) void project_kernel(SurfelPtrs S, Pos
 #pragma unroll
         for (int c = 0; c < 12; ++c) pose_out[c] = (c & 3) < 3 ? P.r[3 * (c >> 2) + (c & 3)] : P.t[c >> 2];
     }
-    const int64_t first = (int64_t)blockIdx.x * kProjThreads;
-    const int64_t i = first + threadIdx.x;
-    const int sh = shard_of(first);
+    const int64_t lo = range_lo(S.n, blockIdx.x), hi = range_lo(S.n, blockIdx.x + 1);
+    const int sh = (int)(blockIdx.x & (kShards - 1));
     if (lds_bins || lds_rows) __syncthreads();
-    uint2 rc = make_uint2(0u, 0u);
-    if (i < S.n) {
-        rc = project_one(S, P, lds_rows ? rsin : rows, lds_rows ? 1 : 2, g, p, recs, keys, i);
-        rects[i] = rc;
+    for (int64_t i0 = lo; i0 < hi; i0 += kProjThreads) {  // the same trip count for every thread
+        const int64_t i = i0 + threadIdx.x;
+        uint2 rc = make_uint2(0u, 0u);
+        if (i < hi) {
+            rc = project_one(S, P, lds_rows ? rsin : rows, lds_rows ? 1 : 2, g, p, recs, keys, i);
+            rects[i] = rc;
+        }
+        // the whole wave enumerates (lanes past the end with an empty rectangle)
+        if (lds_bins) for_each_tile(rc, 0u, g, [&](int t, uint32_t) { atomicAdd(&bins[t], 1u); });
+        else for_each_tile(rc, 0u, g, [&](int t, uint32_t) { atomicAdd(&tile_cnt[t * kShards + sh], 1u); });
     }
-    // the whole wave enumerates (lanes past the end with an empty rectangle)
-    if (lds_bins) for_each_tile(rc, 0u, g, [&](int t, uint32_t) { atomicAdd(&bins[t], 1u); });
-    else for_each_tile(rc, 0u, g, [&](int t, uint32_t) { atomicAdd(&tile_cnt[t * kShards + sh], 1u); });
     if (lds_bins) {
         __syncthreads();
         for (int b = threadIdx.x; b < g.T; b += kProjThreads) {
@@ -296,38 +307,43 @@ __global__ __launch_bounds__(kProjThreads) void project_kernel(SurfelPtrs S, Pos
 // Per workgroup, pairs are counted per tile in LDS, one range per tile is reserved with a
 // single atomic, and the workgroup's pairs fill it.  Positions at or beyond P are dropped
 // (they cannot occur when the counts came from project_kernel over the same rectangles).
-__global__ __launch_bounds__(kEmitThreads) void emit_kernel(const uint2 *__restrict__ rects, int64_t n, Grid g,
-                                                   uint32_t *__restrict__ cursor, uint32_t *__restrict__ pv,
-                                                   int64_t P)
+__global__ __launch_bounds__(kProjThreads) void emit_kernel(const uint2 *__restrict__ rects, int64_t n, Grid g,
+                                                            uint32_t *__restrict__ cursor, uint32_t *__restrict__ pv,
+                                                            int64_t P)
 {
     extern __shared__ uint32_t bins[];  // count, then reserved base, per tile
-    const int64_t first = (int64_t)blockIdx.x * kEmitThreads;
-    const int sh = shard_of(first);
-    const int64_t i = first + threadIdx.x;
-    const uint2 rc = i < n ? rects[i] : make_uint2(0u, 0u);
-    const uint32_t id = (uint32_t)i;
+    const int64_t lo = range_lo(n, blockIdx.x), hi = range_lo(n, blockIdx.x + 1);
+    const int sh = (int)(blockIdx.x & (kShards - 1));
+    auto rect_of = [&](int64_t i) { return i < hi ? rects[i] : make_uint2(0u, 0u); };
     if (g.T > kLdsBins) {
-        for_each_tile(rc, id, g, [&](int t, uint32_t sid) {
-            const uint32_t pos = atomicAdd(&cursor[t * kShards + sh], 1u);
-            if ((int64_t)pos < P) pv[pos] = sid;
-        });
+        for (int64_t i0 = lo; i0 < hi; i0 += kProjThreads) {
+            const int64_t i = i0 + threadIdx.x;
+            for_each_tile(rect_of(i), (uint32_t)i, g, [&](int t, uint32_t sid) {
+                const uint32_t pos = atomicAdd(&cursor[t * kShards + sh], 1u);
+                if ((int64_t)pos < P) pv[pos] = sid;
+            });
+        }
         return;
     }
     uint32_t *cnt = bins, *base = bins + g.T;
-    for (int b = threadIdx.x; b < g.T; b += kEmitThreads) cnt[b] = 0u;
+    for (int b = threadIdx.x; b < g.T; b += kProjThreads) cnt[b] = 0u;
     __syncthreads();
-    for_each_tile(rc, 0u, g, [&](int t, uint32_t) { atomicAdd(&cnt[t], 1u); });
+    for (int64_t i0 = lo; i0 < hi; i0 += kProjThreads)
+        for_each_tile(rect_of(i0 + threadIdx.x), 0u, g, [&](int t, uint32_t) { atomicAdd(&cnt[t], 1u); });
     __syncthreads();
-    for (int b = threadIdx.x; b < g.T; b += kEmitThreads) {
+    for (int b = threadIdx.x; b < g.T; b += kProjThreads) {
         const uint32_t c = cnt[b];
         if (c) base[b] = atomicAdd(&cursor[b * kShards + sh], c);
         cnt[b] = 0u;
     }
     __syncthreads();
-    for_each_tile(rc, id, g, [&](int t, uint32_t sid) {
-        const uint32_t pos = base[t] + atomicAdd(&cnt[t], 1u);
-        if ((int64_t)pos < P) pv[pos] = sid;
-    });
+    for (int64_t i0 = lo; i0 < hi; i0 += kProjThreads) {
+        const int64_t i = i0 + threadIdx.x;
+        for_each_tile(rect_of(i), (uint32_t)i, g, [&](int t, uint32_t sid) {
+            const uint32_t pos = base[t] + atomicAdd(&cnt[t], 1u);
+            if ((int64_t)pos < P) pv[pos] = sid;
+        });
+    }
 }
 
 __global__ __launch_bounds__(256) void fill_u32_kernel(uint32_t *__restrict__ p, uint32_t v, int64_t n)
@@ -426,9 +442,9 @@ hipError_t launch_work_counts(const uint2 *ranges, const uint32_t *ids, const ui
 
 hipError_t launch_project(const SurfelPtrs &S, const Pose &pose_val, const float *pose_dev, float *pose_out,
                           const float *rows, const Grid &g, const RasterParams &p, float *recs, uint2 *rects,
-                          uint32_t *keys, uint32_t *tile_cnt, hipStream_t s)
+                          uint32_t *keys, uint32_t *tile_cnt, int blocks, hipStream_t s)
 {
-    unsigned nb = S.n > 0 ? blocks_for(S.n, kProjThreads) : 1u;  // one block still writes the pose
+    const unsigned nb = (unsigned)(blocks > 0 ? blocks : 1);
     size_t lds = (g.T <= kLdsBins ? (size_t)g.T * sizeof(uint32_t) : 0) + (g.H <= kLdsRows ? (size_t)g.H * sizeof(float) : 0);
     project_kernel<<<nb, kProjThreads, lds, s>>>(S, pose_val, pose_dev, pose_out, rows, g, p, recs, rects, keys,
                                                  tile_cnt);
@@ -436,11 +452,11 @@ hipError_t launch_project(const SurfelPtrs &S, const Pose &pose_val, const float
 }
 
 hipError_t launch_emit(const uint2 *rects, int64_t n, const Grid &g, uint32_t *cursor, uint32_t *pv, int64_t P,
-                       hipStream_t s)
+                       int blocks, hipStream_t s)
 {
     if (n <= 0 || P <= 0) return hipSuccess;
     size_t lds = g.T <= kLdsBins ? 2 * (size_t)g.T * sizeof(uint32_t) : 0;
-    emit_kernel<<<blocks_for(n, kEmitThreads), kEmitThreads, lds, s>>>(rects, n, g, cursor, pv, P);
+    emit_kernel<<<(unsigned)(blocks > 0 ? blocks : 1), kProjThreads, lds, s>>>(rects, n, g, cursor, pv, P);
     return hipGetLastError();
 }
 
