@@ -41,14 +41,14 @@ PEAK_HBM_GBS = 8000.0
 # WRITE_SIZE per dispatch, each scaled by what the counter reads for a plain 256 MiB device
 # copy (profiles/pmc_traffic_raster_bwd_block64x1024_300k.md).  Valid only for the kernel
 # sources they were taken with (digest below); reported as null once those change.
-TRAFFIC_RASTER_BWD = dict(bytes=77668312,
-                          sources_sha256="32e0dcd52deae25df5b286f5194e343869794294d8eddf1278e6ccfe17c684f0")
+TRAFFIC_RASTER_BWD = dict(bytes=77697685,
+                          sources_sha256="6b92dda8f3365b3d0851953468d7caa32537a131fe2c99a70da36d262e3f3520")
 
 
 # rocprofv3 SQ counters of one raster_bwd launch on the benchmark workload (per dispatch) and
 # the kernel's mean duration in the same profiled run; same validity rule as the traffic.
-SQ_RASTER_BWD = dict(SQ_INSTS_VALU=25741302, SQ_INSTS_LDS=974394, SQ_LDS_BANK_CONFLICT=305332, ms=0.0684,
-                     sources_sha256="32e0dcd52deae25df5b286f5194e343869794294d8eddf1278e6ccfe17c684f0")
+SQ_RASTER_BWD = dict(SQ_INSTS_VALU=25741302, SQ_INSTS_LDS=974394, SQ_LDS_BANK_CONFLICT=305332, ms=0.0686,
+                     sources_sha256="6b92dda8f3365b3d0851953468d7caa32537a131fe2c99a70da36d262e3f3520")
 
 
 def _sources_digest() -> str:
