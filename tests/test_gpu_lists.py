@@ -265,6 +265,87 @@ def test_tile_lists_complete_and_ordered(ctx, name):
     st.free()
 
 
+def _around_sensor_map(seed):
+    """The room's 1000 surfels with 12 large surfels at 1.6-2.7 m inserted among them (three
+    in the first wavefront's lanes 3, 5 and 7, one in the last lane of the second, the rest
+    spread): each has its long axis, 1 m, nearly along its centre direction and its plane
+    tilted so that it is hit at a few tenths of a metre, so its hit disk reaches around the
+    sensor."""
+    w = scenegen.make_workload("room32x256_1k")
+    base = {k: np.asarray(w[k], np.float64) for k in G.SURF_KEYS}
+    rng = np.random.default_rng(seed)
+    cen, frames = [], []
+    for k in range(12):
+        d0 = rng.normal(size=3)
+        d0[2] *= 0.2
+        d0 /= np.linalg.norm(d0)
+        n0 = np.cross(d0, [0.0, 0.0, 1.0])
+        n0 /= np.linalg.norm(n0)
+        n = n0 + 0.2 * d0
+        n /= np.linalg.norm(n)
+        a = d0 - (d0 @ n) * n
+        a /= np.linalg.norm(a)
+        frames.append(np.stack([a, np.cross(n, a), n], axis=1))
+        cen.append((1.6 + 0.1 * k) * d0)
+    wide = U.surfels(np.asarray(cen), frames, np.tile([1.0, 0.5], (12, 1)), np.full(12, 0.3))
+    at = np.array([3, 5, 7, 127, 200, 333, 334, 512, 640, 777, 900, 1011])
+    n = base["means"].shape[0] + len(at)
+    keep = np.setdiff1d(np.arange(n), at)
+    S = {}
+    for k in G.SURF_KEYS:
+        shape = (n,) + base[k].shape[1:]
+        v = np.zeros(shape, np.float64)
+        v[keep] = base[k]
+        v[at] = wide[k]
+        S[k] = v.astype(np.float32)
+    return S, at
+
+
+@pytest.mark.parametrize("H,W", [(64, 1024), (80, 13120)])
+def test_around_sensor_surfels_listed_in_every_tile(ctx, H, W):
+    """Rectangles of more than 8 tiles are enumerated by the whole wavefront, one tile per
+    lane, one rectangle at a time, in both the count (projection) and the fill (emission);
+    80 x 13120 beams (4100 tiles) take the global-atomic path of both.  Checks, per tile list:
+    every surfel whose disk reaches around the sensor (its ray rectangle is the whole grid) is
+    listed in every tile, no list repeats an id, and every surfel the oracle composites on a
+    sampled ray (threshold ties excepted) is in that ray's tile list."""
+    from paper_2607_04127_amd import lgsr
+    S, at = _around_sensor_map(17)
+    row, col = scenegen.beam_tables(H, W, -15, 15)
+    w = dict(S, row_sincos=row, col_sincos=col, pose=U.identity_pose().astype(np.float32))
+    fr, st = G.gpu_forward(ctx, G.to_dev(w))
+    torch.cuda.synchronize()
+    TH, TW = (H + 15) // 16, (W + 15) // 16
+    lists = {}
+    for tr in range(TH):
+        for tc in range(TW):
+            ids = lgsr.lgsr_tile_list(ctx, st, tr, tc).astype(np.int64)
+            assert len(np.unique(ids)) == len(ids), ("repeated id", tr, tc)
+            assert np.all(np.isin(at, ids)), ("around-sensor surfel missing", tr, tc, np.setdiff1d(at, ids))
+            lists[(tr, tc)] = set(ids.tolist())
+    rng = np.random.default_rng(23)
+    rays = np.sort(rng.choice(H * W, size=2048, replace=False))
+    of = G.oracle_forward(w, ray_ids=rays)
+    ok = ~G.tie_mask(of)
+    contrib = ref.contributors(w, w["pose"], row, col, rays, cap=512)
+    checked = missing = wide_hits = 0
+    wide_set = set(at.tolist())
+    for ray, c, good in zip(rays.tolist(), contrib, ok):
+        if not good:
+            continue
+        checked += 1
+        lst = lists[((ray // W) // 16, (ray % W) // 16)]
+        missing += sum(1 for x in c.tolist() if x not in lst)
+        wide_hits += sum(1 for x in c.tolist() if x in wide_set)
+    listed = sum(len(v) for v in lists.values())
+    print(f"\n[around sensor {H}x{W}] tiles={TH * TW} listed={listed} rays={checked} missing={missing} "
+          f"composites of around-sensor surfels={wide_hits}", flush=True)
+    assert missing == 0
+    assert checked > 0.9 * len(rays)
+    assert wide_hits > 0
+    st.free()
+
+
 @pytest.mark.parametrize("name", ["room32x256_1k", "grazing"])
 def test_count_hits_matches_oracle(ctx, name):
     """lgsr_count_hits (hits passing every per-hit test, early termination ignored) against
