@@ -172,11 +172,12 @@ __device__ __forceinline__ void composite(WaveStage &ws, const uint32_t *__restr
         uint32_t slot_pos, slot_id;
         const uint32_t m = stage_wave(ws, ids, recs, rects, base, min((uint32_t)kWStage, b - base), L, W, slot_pos,
                                       slot_id);
-        for (uint32_t i = 0; i < m; ++i) {
-            const Rec s = staged_rec(ws, i);
+        // Entry i: the hit test, and the composite on lanes that pass; true once every lane
+        // is done (only a composite can change that).
+        auto step = [&](const Rec &s, uint32_t i) -> bool {
             Hit h;
             const float q2 = hit_geom(h, s, ray, p);
-            if (!__any(h.pass && !done)) continue;  // no lane reaches the opacity test
+            if (!__any(h.pass && !done)) return false;  // no lane reaches the opacity test
             hit_opacity(h, q2, s, p);
             if (h.pass && !done) {
                 float w = acc.T * h.ah;
@@ -190,7 +191,16 @@ __device__ __forceinline__ void composite(WaveStage &ws, const uint32_t *__restr
                 acc.last = (int)__builtin_amdgcn_readlane((int)slot_pos, (int)i);
                 done = acc.T < p.T_min;
             }
-            if (__all(done)) break;
+            return __all(done);
+        };
+        // Two record buffers in turn: the next entry's record is read from LDS while this one
+        // is tested, with no register copies between them.
+        Rec ra = staged_rec(ws, 0), rb;
+        for (uint32_t i = 0; i < m; i += 2) {
+            rb = staged_rec(ws, i + 1 < m ? i + 1 : i);
+            if (step(ra, i) || i + 1 >= m) break;
+            ra = staged_rec(ws, i + 2 < m ? i + 2 : i);
+            if (step(rb, i + 1)) break;
         }
         __syncthreads();  // the stage is no longer read
     }
