@@ -16,7 +16,6 @@ namespace lgsr {
 constexpr float kAngMargin = 2e-4f;
 // Relative inflation of the disk's extents: covers float32 rounding of the frame and scales.
 constexpr float kExtSlack = 1e-4f;
-constexpr float kHalfPi = 1.57079632679489662f;
 constexpr float kTwoPi = 6.28318530717958648f;
 
 // Tile-column segments [a0, a1] and [b0, b1] (b1 < b0: empty) covered by columns
@@ -176,6 +175,10 @@ __device__ __forceinline__ uint2 project_one(const SurfelPtrs &S, const Pose &P,
     //   elevation toward the equator, by at most the factor c = 1/sqrt(1 + (ext_az / (r -
     //   ext_m))^2) on its sine;
     //   azimuth: atan2(d_az, h) with h >= (r - ext_m) cos phi_c - ext_el |sin phi_c|.
+    // The rows are searched by the sines of their elevations, so the elevation bounds are kept
+    // as sines: sin(phi_c +- A) from sin phi_c = m_z, cos phi_c = |m_xy| and cos A, sin A, with
+    // a bound past +-90 degrees told by the sign of cos(phi_c +- A).  As |d sin| <= |d angle|,
+    // the angular margin added to a sine keeps the bound conservative.
     // Tilted (foreshortened) and elongated surfels get a footprint much tighter than the
     // bounding cone of radius k max(s0, s1).
     const int H = g.H, W = g.W;
@@ -196,18 +199,21 @@ __device__ __forceinline__ uint2 project_one(const SurfelPtrs &S, const Pose &P,
     if (rmin <= 0.05f * gm.r) {  // the disk reaches around the sensor: every ray
         r0 = 0; r1 = H - 1; c0 = 0; cw = W;
     } else {
-        const float phic = asinf(mz);
-        const float A = atanf(ext_el / rmin);
+        const float rho = sqrtf(fmaf(rmin, rmin, ext_el * ext_el));
+        const float cA = rmin / rho, sA = ext_el / rho;
         const float q = ext_az / rmin;
         const float c = 1.f / sqrtf(1.f + q * q);
-        float hi = phic + A, lo = phic - A;
-        if (hi < 0.f) hi = asinf(sinf(hi) * c);
-        if (lo > 0.f) lo = asinf(sinf(lo) * c);
-        hi += kAngMargin;
-        lo -= kAngMargin;
-        const bool pole = hi >= kHalfPi || lo <= -kHalfPi;
-        const float s_hi = hi >= kHalfPi ? 2.f : sinf(hi);
-        const float s_lo = lo <= -kHalfPi ? -2.f : sinf(lo);
+        float s_hi = fmaf(mz, cA, ch * sA), s_lo = fmaf(mz, cA, -ch * sA);
+        const bool over_hi = fmaf(ch, cA, -mz * sA) <= 0.f;  // phi_c + A reaches +90 degrees
+        const bool over_lo = fmaf(ch, cA, mz * sA) <= 0.f;   // phi_c - A reaches -90 degrees
+        if (s_hi < 0.f) s_hi *= c;
+        if (s_lo > 0.f) s_lo *= c;
+        s_hi += kAngMargin;
+        s_lo -= kAngMargin;
+        const bool top = over_hi || s_hi >= 1.f, bottom = over_lo || s_lo <= -1.f;
+        const bool pole = top || bottom;
+        if (top) s_hi = 2.f;
+        if (bottom) s_lo = -2.f;
         r0 = first_row_le(rows, rstride, H, s_hi);
         r1 = first_row_lt(rows, rstride, H, s_lo) - 1;
         const float hmin = rmin * ch - ext_el * fabsf(mz);
