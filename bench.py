@@ -41,13 +41,13 @@ PEAK_HBM_GBS = 8000.0
 # WRITE_SIZE per dispatch, each scaled by what the counter reads for a plain 256 MiB device
 # copy (profiles/pmc_traffic_raster_bwd_block64x1024_300k.md).  Valid only for the kernel
 # sources they were taken with (digest below); reported as null once those change.
-TRAFFIC_RASTER_BWD = dict(bytes=77673726,
+TRAFFIC_RASTER_BWD = dict(bytes=77672111,
                           sources_sha256="311327d7e9c240845593e710ae7e44d355accb59b856b7870bf0425f5ea563ec")
 
 
 # rocprofv3 SQ counters of one raster_bwd launch on the benchmark workload (per dispatch) and
 # the kernel's mean duration in the same profiled run; same validity rule as the traffic.
-SQ_RASTER_BWD = dict(SQ_INSTS_VALU=25741302, SQ_INSTS_LDS=974394, SQ_LDS_BANK_CONFLICT=305332, ms=0.0678,
+SQ_RASTER_BWD = dict(SQ_INSTS_VALU=25740091, SQ_INSTS_LDS=974275, SQ_LDS_BANK_CONFLICT=305352, ms=0.0678,
                      sources_sha256="311327d7e9c240845593e710ae7e44d355accb59b856b7870bf0425f5ea563ec")
 
 
