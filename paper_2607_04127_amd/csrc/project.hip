@@ -2,10 +2,11 @@
 //
 // Projection (per surfel; a workgroup per CU over a range of surfels): activations
 // (normalised q, s = exp(s~) per Sec. 3.3, alpha = sigmoid), world -> sensor transform, the
-// 64-byte record of lgsr_internal.h, and a conservative ray rectangle of the hit disk u^2 + v^2 <= k^2 (bounds along the centre,
-// elevation and azimuth directions; see project_one): an elevation interval (rows, by
-// binary search of the monotone row table) and an azimuth interval (columns, uniform,
-// wrapping at 360 degrees), or whole rows of azimuth when a pole may lie inside.
+// 64-byte record of lgsr_internal.h, and a conservative ray rectangle of the hit disk
+// u^2 + v^2 <= k^2 (bounds along the centre, elevation and azimuth directions; see
+// project_one): an elevation interval (rows, by binary search of the monotone row table) and
+// an azimuth interval (columns, uniform, wrapping at 360 degrees), or whole rows of azimuth
+// when a pole may lie inside.
 #include "lgsr_internal.h"
 #include "lgsr_kernels.h"
 
